@@ -1,0 +1,209 @@
+/*
+ * tsvdm.h -- C ABI of the MI355X (gfx950) t-SVDM library.
+ *
+ * The library computes, on one GPU, the data-parallel core of the tensor-based
+ * structured matrix approximation of Kilmer & Saibaba ("Structured matrix
+ * approximations via tensor decompositions"), Algorithm alg:strategy (Sec. 3.1)
+ * with a transform-domain truncated tensor SVD as the tensor compression of
+ * step 3 (the paper admits any tensor approximation there, remarks of Sec. 3):
+ *
+ *   A  --T_E-->  X = T_E[A]  --x3 M-->  Xhat  --facewise truncated SVD-->
+ *   (Uhat_f, S_f, Vhat_f)_f  --apply-->  y = M_E[T] x.
+ *
+ * Conventions shared by every entry point
+ *  - Every data pointer is a DEVICE pointer owned by the caller; the library
+ *    never allocates or frees device memory.  Scratch space is the caller's
+ *    `workspace` of the size the matching *_workspace_size call returns.
+ *  - Work is enqueued on `stream` (a hipStream_t passed as void*, NULL = the
+ *    null stream) and is asynchronous; results are valid after the caller
+ *    synchronises the stream.
+ *  - Column-major storage.  A third-order tensor of dims (m, p, n3) stores
+ *    element (a, b, t) at a*s_a + b*s_b + t*s_t (dense: 1, m, m*p).  Frontal
+ *    slices (faces) are the m x p matrices X(:, :, t) (Sec. 2.1).
+ *  - Complex values (C64, C128) are interleaved (re, im) pairs.
+ *  - Status: argument errors (null pointers, shapes, strides, dtypes, sizes,
+ *    workspace) are detected on the host before anything is launched and are
+ *    returned synchronously; tsvdm_last_error() then holds a message.  Errors
+ *    found on the device (non-convergence, breakdown, non-finite input) are
+ *    reported per face in tsvdm_factors.info after the stream is synchronised.
+ *  - No C++ exception crosses this interface.  Calls are thread-safe as long
+ *    as concurrent calls use distinct outputs and workspaces.
+ */
+#ifndef TSVDM_H
+#define TSVDM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t tsvdm_status;
+enum {
+    TSVDM_OK = 0,
+    TSVDM_EINVAL = 1,        /* bad argument (null pointer, shape, stride, size) */
+    TSVDM_EUNSUPPORTED = 2,  /* valid but not implemented combination */
+    TSVDM_EWORKSPACE = 3,    /* workspace missing or smaller than required */
+    TSVDM_EDEVICE = 4        /* a HIP runtime call failed (launch, device query) */
+};
+
+/* element types */
+enum {
+    TSVDM_F64 = 0,
+    TSVDM_F32 = 1,
+    TSVDM_BF16 = 2,
+    TSVDM_C64 = 3,   /* complex float  */
+    TSVDM_C128 = 4   /* complex double */
+};
+
+/* the transform M applied along mode 3 (every tube) */
+enum {
+    TSVDM_M_DCT2 = 0,   /* orthonormal DCT-II: M[f,t] = a_f cos(pi (2t+1) f / (2 n3)) */
+    TSVDM_M_DFT = 1,    /* unitary DFT: M[f,t] = n3^{-1/2} exp(-2 pi i f t / n3)      */
+    TSVDM_M_DENSE = 2   /* caller-supplied real orthogonal n3 x n3 matrix             */
+};
+
+typedef struct {
+    int32_t kind;      /* TSVDM_M_* */
+    int32_t reserved;
+    int64_t n3;        /* transform length (tube length in the original domain) */
+    const double *M;   /* TSVDM_M_DENSE only: device pointer, n3 x n3, column major,
+                          FP64.  Must be orthogonal (inverse = transpose); see
+                          tsvdm_check_orthogonal. Ignored otherwise. */
+} tsvdm_mdesc;
+
+/* A strided third-order tensor.  The lateral index b may be split as
+ * b = j + bsplit * k (0 <= j < bsplit): its address term is then
+ * j*s_b + k*s_bk.  bsplit = 0 means no split (address term b*s_b).
+ * The split expresses the zero-copy view T_E[A] of a block matrix. */
+typedef struct {
+    int64_t m, p, n3;
+    int64_t s_a, s_b, s_t;
+    int64_t bsplit, s_bk;
+    int32_t dtype;     /* TSVDM_F32/F64/C64/C128 */
+    int32_t reserved;
+    void *data;        /* device pointer */
+} tsvdm_tensor;
+
+/* Rank selection for the facewise truncation */
+enum {
+    TSVDM_RANK_FIXED = 0,   /* k_f = min(k, min(m,p))                                  */
+    TSVDM_RANK_ENERGY = 1   /* k_f = smallest k <= kcap with
+                               sum_{j>k} s_{f,j}^2 <= tau^2 ||Xhat_f||_F^2            */
+};
+
+/* Arithmetic of the facewise truncation */
+enum {
+    TSVDM_PREC_F64 = 0,     /* plain: full facewise SVD by one-sided Jacobi in FP64     */
+    TSVDM_PREC_MIXED = 1    /* randomized range finder: BF16 sketch and first power
+                               half-step, split-BF16 (FP32-accurate) final half-step
+                               and projection, FP64 orthogonalisation and core SVD    */
+};
+
+typedef struct {
+    int32_t rank_mode;     /* TSVDM_RANK_* */
+    int32_t k;             /* FIXED: the rank.  ENERGY: cap on the rank (<= kmax)   */
+    double tau;            /* ENERGY: relative tolerance per face                   */
+    int32_t precision;     /* TSVDM_PREC_* */
+    int32_t oversample;    /* MIXED: sketch width ell = k + oversample (ell <= 64)  */
+    int32_t power_iters;   /* MIXED: 0 or 1 power iterations                        */
+    int32_t max_sweeps;    /* Jacobi sweep cap, 0 = default (60 plain, 30 core)     */
+    int32_t certify;       /* MIXED: 1 = compute cert by an explicit residual pass  */
+    int32_t reserved;
+    const float *omega;    /* MIXED: device, p x ell Gaussian test matrix, column
+                              major FP32 (the random draws of the range finder)     */
+} tsvdm_truncate_opts;
+
+/* Transform-domain factors: face f holds Uhat_f (m x kmax), S_f (kmax),
+ * Vhat_f (p x kmax); only the leading ranks[f] columns are meaningful, the
+ * rest are zero.  nf = n3 for real transforms, n3/2+1 for the DFT of a real
+ * tensor (the other faces are the conjugates). */
+typedef struct {
+    int64_t m, p, nf, kmax;
+    int32_t dtype;     /* of U and V: F32 or F64 (real M); C64 or C128 (DFT) */
+    int32_t reserved;
+    void *U;           /* m x kmax x nf  */
+    double *S;         /* kmax x nf, singular values, decreasing per face       */
+    void *V;           /* p x kmax x nf  */
+    int32_t *ranks;    /* nf */
+    double *cert;      /* nf or NULL: ||Xhat_f - Uhat_f S_f Vhat_f^H||_F         */
+    double *fro;       /* nf or NULL: ||Xhat_f||_F                               */
+    int32_t *info;     /* nf or NULL: 0 ok, 1 Jacobi sweep cap reached,
+                          2 Cholesky breakdown in the range finder, 3 non-finite */
+} tsvdm_factors;
+
+/* Library version, (major << 16) | minor. */
+int32_t tsvdm_version(void);
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *tsvdm_last_error(void);
+
+/* Zero-copy view X = T_E[A] of a column-major block matrix A ((ell*m) x (q*n),
+ * leading dimension lda >= ell*m) for the generic placement of the remark
+ * after Lemma lem:tenapprox (Sec. 3): p = ell*q distinct blocks, E_b = e_j e_k^T
+ * with b = j + ell*k, eta = 1, so X(a, b, t) = A(j*m + a, k*n + t).
+ * Fills *out; copies nothing.  dtype is TSVDM_F32 or TSVDM_F64. */
+tsvdm_status tsvdm_tensor_from_blockmat(const void *A, int64_t lda, int32_t dtype, int64_t ell,
+                                        int64_t q, int64_t m, int64_t n, tsvdm_tensor *out);
+
+/* Host-side check that the n3 x n3 column-major HOST matrix M is orthogonal:
+ * max |M^T M - I| <= tol.  Returns TSVDM_OK or TSVDM_EINVAL. */
+tsvdm_status tsvdm_check_orthogonal(const double *M_host, int64_t n3, double tol);
+
+/* Mode-3 transform of every tube (Sec. 2.1: X x_3 M multiplies each tube by M).
+ *   direction = +1: out = in x_3 M;   direction = -1: out = in x_3 M^{-1}.
+ * DCT2 / DENSE: in and out are real (F32 or F64, same type), n3 faces each.
+ * DFT, direction +1: real in (n3 faces) -> complex out (C64/C128) holding
+ *   faces 0..n3/2 (out->n3 = n3/2 + 1).
+ * DFT, direction -1: complex in holding faces 0..n3/2 -> real out (n3 faces);
+ *   the remaining faces are taken as conjugates, imaginary parts of faces 0
+ *   and n3/2 are ignored.
+ * `in` may be any strided view (e.g. from tsvdm_tensor_from_blockmat); `out`
+ * must be dense (strides 1, m, m*p) and must not overlap `in`.
+ * Power-of-two n3 (2..1024) uses an FFT in LDS; other lengths and DENSE use
+ * a direct per-tube product. */
+tsvdm_status tsvdm_transform(const tsvdm_mdesc *M, int32_t direction, const tsvdm_tensor *in,
+                             tsvdm_tensor *out, void *stream);
+
+/* Workspace bytes tsvdm_truncate needs for this input and options. */
+size_t tsvdm_truncate_workspace_size(const tsvdm_tensor *Xhat, const tsvdm_truncate_opts *opts);
+
+/* Facewise truncated SVD of a dense transform-domain tensor Xhat (the output
+ * of tsvdm_transform): for every face f, Xhat_f ~ Uhat_f diag(S_f) Vhat_f^H
+ * with rank ranks[f] chosen by opts->rank_mode.  Together with the inverse
+ * transform this is the truncated t-SVDM, step 3 of Algorithm alg:strategy.
+ *   PREC_F64:   Xhat FP64 or C128; factors F64 / C128; full SVD per face.
+ *   PREC_MIXED: Xhat FP32 (real M); factors F32; randomized range finder
+ *               with the caller's Gaussian omega, power iteration, FP64
+ *               shifted Cholesky-QR, FP64 core SVD; cert from an explicit
+ *               residual pass when opts->certify is set (else cert = -1).
+ * out->kmax >= the largest rank that can be returned (k for FIXED, the cap
+ * for ENERGY).  The error of the approximation in the original domain is
+ * sqrt(sum_f w_f cert_f^2) (w_f = 1, or 2 for DFT faces 0 < f < n3/2). */
+tsvdm_status tsvdm_truncate(const tsvdm_tensor *Xhat, const tsvdm_truncate_opts *opts,
+                            tsvdm_factors *out, void *workspace, size_t workspace_bytes,
+                            void *stream);
+
+/* Workspace bytes tsvdm_apply needs. */
+size_t tsvdm_apply_workspace_size(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell,
+                                  int64_t q, int64_t nrhs, int32_t compute);
+
+/* y = A_hat x with A_hat = M_E[T] (Sec. 3, map M_E, generic placement with
+ * p = ell*q) and T = That x_3 M^{-1}, That_f = Uhat_f diag(S_f) Vhat_f^H from
+ * the factors F (only the leading ranks[f] triplets).  A_hat is never formed:
+ *   xt_k = tube transform of the k-th block row of x by conj(M),
+ *   Z_f[r, j, c] = sum_k conj(Vhat_f[j + ell*k, r]) xt_k[f, c],
+ *   y_j[:, c] = sum_f Uhat_f diag(S_f) Z_f[:, j, c].
+ * x: (q*n3) x nrhs, column major (ldx), y: (ell*m) x nrhs (ldy), both real of
+ * the compute type's precision: FP32 for compute = F32 (or BF16), FP64 for
+ * compute = F64.  Factor precision must match (F32/C64 or F64/C128). */
+tsvdm_status tsvdm_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell, int64_t q,
+                         int64_t nrhs, const void *x, int64_t ldx, void *y, int64_t ldy,
+                         int32_t compute, void *workspace, size_t workspace_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSVDM_H */

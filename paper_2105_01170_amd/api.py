@@ -1,0 +1,143 @@
+"""PyTorch-facing helpers around the C ABI.
+
+PyTorch supplies device memory and the stream; every computation is a call
+into libtsvdm.so through :mod:`.tsvdm`.  Tensors are flat device buffers in
+the column-major layout of the C interface: a third-order (m, p, n3) tensor
+has element (a, b, t) at a + m*b + m*p*t.  Complex data uses torch's complex
+dtypes (interleaved re/im, as the C interface expects).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import tsvdm as C
+
+_TORCH_DT = {C.F64: torch.float64, C.F32: torch.float32, C.C64: torch.complex64,
+             C.C128: torch.complex128}
+_CODE = {v: k for k, v in _TORCH_DT.items()}
+
+
+def dtype_code(t: torch.Tensor) -> int:
+    return _CODE[t.dtype]
+
+
+def _stream(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _mdesc(kind: int, n3: int, M: torch.Tensor | None):
+    if kind == C.M_DENSE:
+        if M is None or M.dtype != torch.float64 or not M.is_cuda:
+            raise ValueError("dense M must be a float64 CUDA tensor (n3 x n3, column major)")
+        return C.mdesc(kind, n3, M.data_ptr())
+    return C.mdesc(kind, n3)
+
+
+def transform(x: torch.Tensor, m: int, p: int, n3: int, kind: int, direction: int = 1,
+              M: torch.Tensor | None = None, out: torch.Tensor | None = None, view=None,
+              stream=None) -> torch.Tensor:
+    """x (dense (m, p, nf_in) or the strided `view` descriptor over x) x_3 M^{+-1}."""
+    real_in = not x.is_complex()
+    if kind == C.M_DFT:
+        nf_out = n3 // 2 + 1 if direction > 0 else n3
+        if direction > 0:
+            odt = torch.complex64 if x.dtype == torch.float32 else torch.complex128
+        else:
+            odt = torch.float32 if x.dtype == torch.complex64 else torch.float64
+    else:
+        nf_out = n3
+        odt = x.dtype
+    nf_in = n3 if (kind != C.M_DFT or direction > 0) else n3 // 2 + 1
+    if out is None:
+        out = torch.empty(m * p * nf_out, dtype=odt, device=x.device)
+    tin = view if view is not None else C.dense_tensor(x.data_ptr(), m, p, nf_in, dtype_code(x))
+    tout = C.dense_tensor(out.data_ptr(), m, p, nf_out, dtype_code(out))
+    C.tsvdm_transform(_mdesc(kind, n3, M), direction, tin, tout, _stream(stream))
+    del real_in
+    return out
+
+
+@dataclass
+class Factors:
+    m: int
+    p: int
+    nf: int
+    kmax: int
+    U: torch.Tensor
+    S: torch.Tensor
+    V: torch.Tensor
+    ranks: torch.Tensor
+    cert: torch.Tensor
+    fro: torch.Tensor
+    info: torch.Tensor
+
+    def desc(self) -> C.TsvdmFactors:
+        return C.factors(self.m, self.p, self.nf, self.kmax, dtype_code(self.U),
+                         self.U.data_ptr(), self.S.data_ptr(), self.V.data_ptr(),
+                         self.ranks.data_ptr(), self.cert.data_ptr(), self.fro.data_ptr(),
+                         self.info.data_ptr())
+
+
+def empty_factors(m, p, nf, kmax, dtype, device="cuda") -> Factors:
+    return Factors(m, p, nf, kmax,
+                   torch.zeros(m * kmax * nf, dtype=dtype, device=device),
+                   torch.zeros(kmax * nf, dtype=torch.float64, device=device),
+                   torch.zeros(p * kmax * nf, dtype=dtype, device=device),
+                   torch.zeros(nf, dtype=torch.int32, device=device),
+                   torch.zeros(nf, dtype=torch.float64, device=device),
+                   torch.zeros(nf, dtype=torch.float64, device=device),
+                   torch.zeros(nf, dtype=torch.int32, device=device))
+
+
+class Truncator:
+    """Holds the options, the workspace and the output factors of repeated
+    tsvdm_truncate calls on tensors of one shape."""
+
+    def __init__(self, m, p, nf, dtype, *, rank_mode=C.RANK_FIXED, k=1, tau=0.0,
+                 precision=C.PREC_F64, oversample=0, power_iters=0, max_sweeps=0, certify=1,
+                 omega: torch.Tensor | None = None, kmax=None, device="cuda"):
+        self.omega = omega
+        self.opts = C.truncate_opts(rank_mode, k, tau, precision, oversample, power_iters,
+                                    max_sweeps, certify, omega.data_ptr() if omega is not None else 0)
+        self.m, self.p, self.nf, self.dtype = m, p, nf, dtype
+        probe = C.dense_tensor(0, m, p, nf, _CODE[dtype])
+        self.ws_bytes = C.tsvdm_truncate_workspace_size(probe, self.opts)
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+        if kmax is None:
+            ns = min(m, p)
+            kmax = min(k if k > 0 else ns, ns)
+            if precision == C.PREC_MIXED:
+                kmax = min(kmax, k + oversample)
+        fdt = dtype if precision == C.PREC_F64 else torch.float32
+        self.F = empty_factors(m, p, nf, max(kmax, 1), fdt, device)
+
+    def __call__(self, xhat: torch.Tensor, stream=None) -> Factors:
+        X = C.dense_tensor(xhat.data_ptr(), self.m, self.p, self.nf, dtype_code(xhat))
+        C.tsvdm_truncate(X, self.opts, self.F.desc(), self.ws.data_ptr(), self.ws_bytes,
+                         _stream(stream))
+        return self.F
+
+
+def apply(F: Factors, kind: int, n3: int, ell: int, q: int, x: torch.Tensor, ldx: int | None = None,
+          compute: int | None = None, M: torch.Tensor | None = None, y: torch.Tensor | None = None,
+          ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """y = M_E[T] x for the factors F; x is (q*n3) x nrhs column major (flat)."""
+    if compute is None:
+        compute = C.F64 if F.U.dtype in (torch.float64, torch.complex128) else C.F32
+    rdt = torch.float64 if compute == C.F64 else torch.float32
+    rows_x = q * n3
+    ldx = ldx or rows_x
+    nrhs = x.numel() // ldx
+    md = _mdesc(kind, n3, M)
+    desc = F.desc()
+    need = C.tsvdm_apply_workspace_size(md, desc, ell, q, nrhs, compute)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    if y is None:
+        y = torch.empty(ell * F.m * nrhs, dtype=rdt, device=x.device)
+    C.tsvdm_apply(md, desc, ell, q, nrhs, x.data_ptr(), ldx, y.data_ptr(), ell * F.m, compute,
+                  ws.data_ptr(), need, _stream(stream))
+    return y

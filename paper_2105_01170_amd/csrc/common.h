@@ -1,0 +1,92 @@
+// Internal helpers shared by the HIP sources of the t-SVDM library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/tsvdm.h"
+
+namespace tsvdm {
+
+// ---------------------------------------------------------------- complex
+template <typename T>
+struct cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cadd(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> csub(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cconj(cx<T> a) { return {a.re, -a.im}; }
+
+// ---------------------------------------------------------------- bf16
+// Round-to-nearest-even float -> bf16 bit pattern (finite inputs).
+__device__ __forceinline__ uint16_t f2bf(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// ---------------------------------------------------------------- views
+// Strided third-order tensor view with an optionally split lateral index
+// (b = j + bsplit*k), the zero-copy form of T_E[A].
+struct View {
+    int64_t m, p, n3, s_a, s_b, s_t, bsplit, s_bk;
+    __host__ __device__ __forceinline__ int64_t tube_base(int64_t i) const {
+        int64_t a = i % m, b = i / m;
+        if (bsplit > 0) return a * s_a + (b % bsplit) * s_b + (b / bsplit) * s_bk;
+        return a * s_a + b * s_b;
+    }
+};
+
+inline View make_view(const tsvdm_tensor &t) {
+    View v;
+    v.m = t.m; v.p = t.p; v.n3 = t.n3;
+    v.s_a = t.s_a; v.s_b = t.s_b; v.s_t = t.s_t;
+    v.bsplit = t.bsplit; v.s_bk = t.s_bk;
+    return v;
+}
+
+// Wave-level sum (64 lanes) via cross-lane shuffles.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+}  // namespace tsvdm
+
+// ---------------------------------------------------------------- host side
+namespace tsvdm {
+void set_error(const char *fmt, ...);
+tsvdm_status hip_check(hipError_t e, const char *what);
+
+// launchers implemented in the .hip files
+tsvdm_status launch_transform(const tsvdm_mdesc *M, int direction, const tsvdm_tensor *in,
+                              tsvdm_tensor *out, hipStream_t s);
+size_t jacobi_workspace(int64_t m, int64_t p, int64_t nf, bool cplx);
+tsvdm_status launch_jacobi_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
+                                    tsvdm_factors *F, void *ws, hipStream_t s);
+size_t mixed_workspace(int64_t m, int64_t p, int64_t nf, int ell);
+tsvdm_status launch_mixed_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
+                                   tsvdm_factors *F, void *ws, hipStream_t s);
+size_t apply_workspace(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell, int64_t q,
+                       int64_t nrhs, int32_t compute);
+tsvdm_status launch_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell, int64_t q,
+                          int64_t nrhs, const void *x, int64_t ldx, void *y, int64_t ldy,
+                          int32_t compute, void *ws, hipStream_t s);
+}  // namespace tsvdm
+
+#define TSVDM_LAUNCH_CHECK(what)                                      \
+    do {                                                              \
+        hipError_t e_ = hipGetLastError();                            \
+        if (e_ != hipSuccess) return ::tsvdm::hip_check(e_, what);    \
+    } while (0)

@@ -1,0 +1,244 @@
+// Host side of the C ABI: argument validation, workspace sizing, dispatch.
+// Every check runs before anything is enqueued; a failed check returns a
+// status and leaves a message for tsvdm_last_error().
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <cmath>
+
+#include "common.h"
+
+namespace tsvdm {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+tsvdm_status hip_check(hipError_t e, const char *what) {
+    if (e == hipSuccess) return TSVDM_OK;
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return TSVDM_EDEVICE;
+}
+
+}  // namespace tsvdm
+
+using namespace tsvdm;
+
+#define FAIL(code, ...)            \
+    do {                           \
+        set_error(__VA_ARGS__);    \
+        return (code);             \
+    } while (0)
+
+static bool is_real(int32_t d) { return d == TSVDM_F32 || d == TSVDM_F64; }
+static bool is_cplx(int32_t d) { return d == TSVDM_C64 || d == TSVDM_C128; }
+static bool is_double(int32_t d) { return d == TSVDM_F64 || d == TSVDM_C128; }
+static bool is_dense(const tsvdm_tensor &t) {
+    return t.s_a == 1 && t.s_b == t.m && t.s_t == t.m * t.p && t.bsplit == 0;
+}
+
+static tsvdm_status check_tensor(const tsvdm_tensor *t, const char *name) {
+    if (!t) FAIL(TSVDM_EINVAL, "%s is NULL", name);
+    if (t->m < 0 || t->p < 0 || t->n3 < 0) FAIL(TSVDM_EINVAL, "%s has a negative dimension", name);
+    if (t->dtype < TSVDM_F64 || t->dtype > TSVDM_C128 || t->dtype == TSVDM_BF16)
+        FAIL(TSVDM_EINVAL, "%s has unsupported dtype %d", name, t->dtype);
+    if (t->m * t->p * t->n3 > 0 && !t->data) FAIL(TSVDM_EINVAL, "%s->data is NULL", name);
+    if (t->bsplit < 0) FAIL(TSVDM_EINVAL, "%s->bsplit is negative", name);
+    if (t->bsplit > 0 && t->p % t->bsplit != 0)
+        FAIL(TSVDM_EINVAL, "%s->bsplit (%lld) does not divide p (%lld)", name, (long long)t->bsplit,
+             (long long)t->p);
+    return TSVDM_OK;
+}
+
+extern "C" {
+
+int32_t tsvdm_version(void) { return (1 << 16) | 0; }
+
+const char *tsvdm_last_error(void) { return g_err; }
+
+tsvdm_status tsvdm_tensor_from_blockmat(const void *A, int64_t lda, int32_t dtype, int64_t ell,
+                                        int64_t q, int64_t m, int64_t n, tsvdm_tensor *out) {
+    if (!out) FAIL(TSVDM_EINVAL, "out is NULL");
+    if (ell <= 0 || q <= 0 || m <= 0 || n <= 0) FAIL(TSVDM_EINVAL, "block sizes must be positive");
+    if (lda < ell * m) FAIL(TSVDM_EINVAL, "lda (%lld) < ell*m (%lld)", (long long)lda, (long long)(ell * m));
+    if (!is_real(dtype)) FAIL(TSVDM_EINVAL, "block matrix dtype must be F32 or F64");
+    if (!A) FAIL(TSVDM_EINVAL, "A is NULL");
+    // X(a, j + ell*k, t) = A(j*m + a, k*n + t) = A[a + m*j + lda*n*k + lda*t]
+    out->m = m;
+    out->p = ell * q;
+    out->n3 = n;
+    out->s_a = 1;
+    out->s_b = m;
+    out->s_t = lda;
+    out->bsplit = ell;
+    out->s_bk = lda * n;
+    out->dtype = dtype;
+    out->reserved = 0;
+    out->data = const_cast<void *>(A);
+    return TSVDM_OK;
+}
+
+tsvdm_status tsvdm_check_orthogonal(const double *M, int64_t n3, double tol) {
+    if (!M || n3 <= 0) FAIL(TSVDM_EINVAL, "M is NULL or n3 <= 0");
+    for (int64_t i = 0; i < n3; ++i)
+        for (int64_t j = 0; j < n3; ++j) {
+            double acc = 0.0;
+            for (int64_t t = 0; t < n3; ++t) acc += M[t + n3 * i] * M[t + n3 * j];
+            double d = std::fabs(acc - (i == j ? 1.0 : 0.0));
+            if (!(d <= tol))
+                FAIL(TSVDM_EINVAL, "M is not orthogonal: |M^T M - I|(%lld,%lld) = %g", (long long)i,
+                     (long long)j, d);
+        }
+    return TSVDM_OK;
+}
+
+tsvdm_status tsvdm_transform(const tsvdm_mdesc *M, int32_t direction, const tsvdm_tensor *in,
+                             tsvdm_tensor *out, void *stream) {
+    if (!M) FAIL(TSVDM_EINVAL, "M is NULL");
+    if (M->kind < TSVDM_M_DCT2 || M->kind > TSVDM_M_DENSE) FAIL(TSVDM_EINVAL, "unknown M kind %d", M->kind);
+    if (M->n3 < 1) FAIL(TSVDM_EINVAL, "M->n3 must be >= 1");
+    if (M->n3 > 1024) FAIL(TSVDM_EUNSUPPORTED, "transform length %lld > 1024", (long long)M->n3);
+    if (M->kind == TSVDM_M_DENSE && !M->M) FAIL(TSVDM_EINVAL, "dense M requires M->M");
+    if (direction != 1 && direction != -1) FAIL(TSVDM_EINVAL, "direction must be +1 or -1");
+    tsvdm_status st;
+    if ((st = check_tensor(in, "in")) != TSVDM_OK) return st;
+    if ((st = check_tensor(out, "out")) != TSVDM_OK) return st;
+    if (!is_dense(*out)) FAIL(TSVDM_EINVAL, "out must be dense (strides 1, m, m*p)");
+    if (in->m != out->m || in->p != out->p) FAIL(TSVDM_EINVAL, "in and out differ in m or p");
+    if (is_double(in->dtype) != is_double(out->dtype)) FAIL(TSVDM_EINVAL, "in and out differ in precision");
+    const int64_t n3 = M->n3, half = n3 / 2 + 1;
+    if (M->kind == TSVDM_M_DFT) {
+        if (direction > 0) {
+            if (!is_real(in->dtype) || !is_cplx(out->dtype))
+                FAIL(TSVDM_EINVAL, "forward DFT maps a real tensor to a complex one");
+            if (in->n3 != n3 || out->n3 != half)
+                FAIL(TSVDM_EINVAL, "forward DFT: in->n3 must be %lld and out->n3 %lld", (long long)n3,
+                     (long long)half);
+        } else {
+            if (!is_cplx(in->dtype) || !is_real(out->dtype))
+                FAIL(TSVDM_EINVAL, "inverse DFT maps a complex half spectrum to a real tensor");
+            if (in->n3 != half || out->n3 != n3)
+                FAIL(TSVDM_EINVAL, "inverse DFT: in->n3 must be %lld and out->n3 %lld", (long long)half,
+                     (long long)n3);
+        }
+    } else {
+        if (!is_real(in->dtype) || in->dtype != out->dtype)
+            FAIL(TSVDM_EINVAL, "DCT-II / dense M map real tensors to real tensors of the same type");
+        if (in->n3 != n3 || out->n3 != n3) FAIL(TSVDM_EINVAL, "tube length differs from M->n3");
+    }
+    if (in->data == out->data && in->m * in->p > 0) FAIL(TSVDM_EINVAL, "in and out must not alias");
+    if (in->m * in->p == 0) return TSVDM_OK;
+    return launch_transform(M, direction, in, out, (hipStream_t)stream);
+}
+
+static tsvdm_status check_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o) {
+    tsvdm_status st;
+    if ((st = check_tensor(X, "Xhat")) != TSVDM_OK) return st;
+    if (!is_dense(*X)) FAIL(TSVDM_EINVAL, "Xhat must be dense (strides 1, m, m*p)");
+    if (!o) FAIL(TSVDM_EINVAL, "opts is NULL");
+    if (o->rank_mode != TSVDM_RANK_FIXED && o->rank_mode != TSVDM_RANK_ENERGY)
+        FAIL(TSVDM_EUNSUPPORTED, "rank mode %d", o->rank_mode);
+    if (o->k < 0) FAIL(TSVDM_EINVAL, "k must be >= 0");
+    if (o->rank_mode == TSVDM_RANK_ENERGY && !(o->tau >= 0.0)) FAIL(TSVDM_EINVAL, "tau must be >= 0");
+    if (o->max_sweeps < 0) FAIL(TSVDM_EINVAL, "max_sweeps must be >= 0");
+    if (o->precision == TSVDM_PREC_F64) {
+        if (!is_double(X->dtype)) FAIL(TSVDM_EINVAL, "PREC_F64 needs an F64 or C128 Xhat");
+    } else if (o->precision == TSVDM_PREC_MIXED) {
+        if (X->dtype != TSVDM_F32) FAIL(TSVDM_EUNSUPPORTED, "PREC_MIXED needs a real F32 Xhat");
+        if (o->oversample < 0) FAIL(TSVDM_EINVAL, "oversample must be >= 0");
+        if (o->power_iters < 0 || o->power_iters > 1) FAIL(TSVDM_EUNSUPPORTED, "power_iters must be 0 or 1");
+        int ell = o->k + o->oversample;
+        if (ell < 1 || ell > 64) FAIL(TSVDM_EUNSUPPORTED, "sketch width k+oversample = %d not in 1..64", ell);
+        if (ell > X->m || ell > X->p)
+            FAIL(TSVDM_EINVAL, "sketch width %d exceeds min(m, p) = %lld", ell,
+                 (long long)(X->m < X->p ? X->m : X->p));
+        if (!o->omega) FAIL(TSVDM_EINVAL, "PREC_MIXED needs the test matrix omega");
+    } else {
+        FAIL(TSVDM_EINVAL, "unknown precision %d", o->precision);
+    }
+    return TSVDM_OK;
+}
+
+size_t tsvdm_truncate_workspace_size(const tsvdm_tensor *X, const tsvdm_truncate_opts *o) {
+    if (check_truncate(X, o) != TSVDM_OK) return 0;
+    if (o->precision == TSVDM_PREC_F64) return jacobi_workspace(X->m, X->p, X->n3, is_cplx(X->dtype));
+    return mixed_workspace(X->m, X->p, X->n3, o->k + o->oversample);
+}
+
+tsvdm_status tsvdm_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
+                            void *ws, size_t ws_bytes, void *stream) {
+    tsvdm_status st;
+    if ((st = check_truncate(X, o)) != TSVDM_OK) return st;
+    if (!F) FAIL(TSVDM_EINVAL, "out is NULL");
+    if (F->m != X->m || F->p != X->p || F->nf != X->n3)
+        FAIL(TSVDM_EINVAL, "factor dims (%lld, %lld, %lld) differ from Xhat (%lld, %lld, %lld)",
+             (long long)F->m, (long long)F->p, (long long)F->nf, (long long)X->m, (long long)X->p,
+             (long long)X->n3);
+    const int64_t ns = X->m < X->p ? X->m : X->p;
+    int64_t need = o->k;
+    if (o->rank_mode == TSVDM_RANK_ENERGY && o->k == 0) need = ns;
+    if (need > ns) need = ns;
+    if (o->precision == TSVDM_PREC_MIXED && need > o->k + o->oversample) need = o->k + o->oversample;
+    if (F->kmax < need || F->kmax < 1)
+        FAIL(TSVDM_EINVAL, "out->kmax (%lld) < largest possible rank (%lld)", (long long)F->kmax, (long long)need);
+    const int32_t want = o->precision == TSVDM_PREC_F64 ? X->dtype : TSVDM_F32;
+    if (F->dtype != want) FAIL(TSVDM_EINVAL, "factor dtype %d, expected %d", F->dtype, want);
+    if (X->m * X->p * X->n3 > 0 && (!F->U || !F->S || !F->V || !F->ranks))
+        FAIL(TSVDM_EINVAL, "factor pointers U, S, V, ranks must be set");
+    size_t need_ws = tsvdm_truncate_workspace_size(X, o);
+    if (need_ws > 0 && (!ws || ws_bytes < need_ws))
+        FAIL(TSVDM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need_ws, ws_bytes);
+    if (X->n3 == 0) return TSVDM_OK;
+    if (o->precision == TSVDM_PREC_F64) return launch_jacobi_truncate(X, o, F, ws, (hipStream_t)stream);
+    return launch_mixed_truncate(X, o, F, ws, (hipStream_t)stream);
+}
+
+static tsvdm_status check_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell, int64_t q,
+                                int64_t nrhs, int32_t compute) {
+    if (!M || !F) FAIL(TSVDM_EINVAL, "M or F is NULL");
+    if (M->kind < TSVDM_M_DCT2 || M->kind > TSVDM_M_DENSE) FAIL(TSVDM_EINVAL, "unknown M kind");
+    if (M->n3 < 1 || M->n3 > 1024) FAIL(TSVDM_EUNSUPPORTED, "transform length must be in 1..1024");
+    if (M->kind == TSVDM_M_DENSE && !M->M) FAIL(TSVDM_EINVAL, "dense M requires M->M");
+    if (ell <= 0 || q <= 0 || nrhs < 0) FAIL(TSVDM_EINVAL, "ell, q must be > 0 and nrhs >= 0");
+    if (F->p != ell * q) FAIL(TSVDM_EINVAL, "factor p (%lld) != ell*q (%lld)", (long long)F->p, (long long)(ell * q));
+    const int64_t nf = M->kind == TSVDM_M_DFT ? M->n3 / 2 + 1 : M->n3;
+    if (F->nf != nf) FAIL(TSVDM_EINVAL, "factor nf (%lld) != %lld", (long long)F->nf, (long long)nf);
+    if (F->kmax < 1 || F->m < 1) FAIL(TSVDM_EINVAL, "factor m and kmax must be >= 1");
+    if (M->kind == TSVDM_M_DFT ? !is_cplx(F->dtype) : !is_real(F->dtype))
+        FAIL(TSVDM_EINVAL, "factor dtype does not match the transform (complex iff DFT)");
+    if (compute != TSVDM_F32 && compute != TSVDM_F64 && compute != TSVDM_BF16)
+        FAIL(TSVDM_EINVAL, "compute must be F32, F64 or BF16");
+    if ((compute == TSVDM_F64) != is_double(F->dtype))
+        FAIL(TSVDM_EINVAL, "compute precision must match the factor precision");
+    if (!F->U || !F->S || !F->V || !F->ranks) FAIL(TSVDM_EINVAL, "factor pointers must be set");
+    return TSVDM_OK;
+}
+
+size_t tsvdm_apply_workspace_size(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell, int64_t q,
+                                  int64_t nrhs, int32_t compute) {
+    if (check_apply(M, F, ell, q, nrhs, compute) != TSVDM_OK) return 0;
+    return apply_workspace(M, F, ell, q, nrhs, compute);
+}
+
+tsvdm_status tsvdm_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell, int64_t q,
+                         int64_t nrhs, const void *x, int64_t ldx, void *y, int64_t ldy,
+                         int32_t compute, void *ws, size_t ws_bytes, void *stream) {
+    tsvdm_status st;
+    if ((st = check_apply(M, F, ell, q, nrhs, compute)) != TSVDM_OK) return st;
+    if (nrhs == 0) return TSVDM_OK;
+    if (!x || !y) FAIL(TSVDM_EINVAL, "x or y is NULL");
+    if (ldx < q * M->n3) FAIL(TSVDM_EINVAL, "ldx < q*n3");
+    if (ldy < ell * F->m) FAIL(TSVDM_EINVAL, "ldy < ell*m");
+    size_t need = apply_workspace(M, F, ell, q, nrhs, compute);
+    if (need > 0 && (!ws || ws_bytes < need))
+        FAIL(TSVDM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    return launch_apply(M, F, ell, q, nrhs, x, ldx, y, ldy, compute, ws, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,357 @@
+// Mode-3 transform of every tube: Xhat = X x_3 M (or x_3 M^{-1}).
+//
+// The mode-3 product multiplies each tube X(a, b, :) by M (mode-i product and
+// mode-3 unfolding, Sec. 2.1).  Two implementations:
+//
+//  * k_fft_tubes: power-of-two tube length N (2..1024).  A tile of 2*TP
+//    consecutive tubes (consecutive linear index i = a + m*b, so every load
+//    and store of one time step is a contiguous run) is staged in LDS, two
+//    real tubes packed into one complex sequence, and transformed by an
+//    in-place radix-4/radix-2 decimation-in-time FFT.  The orthonormal DCT-II
+//    uses Makhoul's reordering (even samples ascending, odd samples
+//    descending) and a quarter-wave post-twiddle; its inverse runs the same
+//    steps backwards.  The unitary DFT of real tubes keeps the Hermitian half
+//    (faces 0..N/2).  Bound: HBM (about 2.5 log2 N flop per element).
+//
+//  * k_dense_tubes: any length up to 1024 and caller-supplied dense M.  The
+//    tile is staged in LDS and every output is a direct sum over the tube;
+//    DCT/DFT coefficients come from an LDS cosine table.
+#include "common.h"
+
+#include <math.h>
+
+using namespace tsvdm;
+
+namespace {
+
+constexpr int NT = 256;
+
+enum { KIND_DCT = 0, KIND_DFT = 1 };
+
+__device__ __forceinline__ int bitrev(int x, int bits) {
+    return (int)(__brev((unsigned)x) >> (32 - bits));
+}
+
+// position of sample t in Makhoul's reordered sequence
+__device__ __forceinline__ int makhoul(int t, int N) { return (t & 1) ? (N - 1 - (t >> 1)) : (t >> 1); }
+
+template <typename T>
+__device__ __forceinline__ T dct_alpha(int f, int N) {
+    return f == 0 ? (T)sqrt(1.0 / N) : (T)sqrt(2.0 / N);
+}
+
+template <typename T, int KIND, int DIR>
+__global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, View iv,
+                                                  void *__restrict__ out, int64_t ntubes,
+                                                  int64_t mp, int logn, int TP) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int N = 1 << logn, H = N >> 1, TT = 2 * TP;
+    cx<T> *buf = reinterpret_cast<cx<T> *>(smem);  // [N][TP]
+    cx<T> *tw = buf + N * TP;                        // [N/2]  exp(-+2 pi i j / N)
+    cx<T> *wq = tw + H;                              // [N]    exp(-i pi f / (2N))
+    int64_t *base = reinterpret_cast<int64_t *>(wq + N);  // [2TP]
+    const int tid = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * TT;
+
+    for (int j = tid; j < H; j += NT) {
+        double s, c;
+        sincospi(2.0 * j / N, &s, &c);
+        tw[j] = {(T)c, (T)(DIR > 0 ? -s : s)};
+    }
+    if (KIND == KIND_DCT) {
+        for (int f = tid; f < N; f += NT) {
+            double s, c;
+            sincospi((double)f / (2.0 * N), &s, &c);
+            wq[f] = {(T)c, (T)(-s)};
+        }
+    }
+    for (int u = tid; u < TT; u += NT) base[u] = (i0 + u < ntubes) ? iv.tube_base(i0 + u) : -1;
+    __syncthreads();
+
+    // ---------------------------------------------------------------- load
+    if (DIR > 0) {  // real tubes in; tube u < TP -> real part, u >= TP -> imaginary part
+        const T *X = reinterpret_cast<const T *>(in);
+        for (int w = tid; w < TT * N; w += NT) {
+            int u = w % TT, t = w / TT;
+            int64_t b = base[u];
+            T v = b >= 0 ? X[b + (int64_t)t * iv.s_t] : T(0);
+            int n = KIND == KIND_DCT ? makhoul(t, N) : t;
+            T *slot = reinterpret_cast<T *>(&buf[bitrev(n, logn) * TP + (u % TP)]);
+            slot[u / TP] = v;
+        }
+    } else if (KIND == KIND_DFT) {  // Hermitian half spectra in (faces 0..N/2)
+        const cx<T> *X = reinterpret_cast<const cx<T> *>(in);
+        for (int w = tid; w < TP * (H + 1); w += NT) {
+            int c = w % TP, f = w / TP;
+            int64_t bx = base[c], by = base[c + TP];
+            cx<T> a = bx >= 0 ? X[bx + (int64_t)f * iv.s_t] : cx<T>{0, 0};
+            cx<T> b = by >= 0 ? X[by + (int64_t)f * iv.s_t] : cx<T>{0, 0};
+            if (f == 0 || f == H) { a.im = 0; b.im = 0; }
+            // Z = Sx + i Sy over the full spectrum, with S[N-f] = conj(S[f])
+            buf[bitrev(f, logn) * TP + c] = {a.re - b.im, a.im + b.re};
+            if (f > 0 && f < H) buf[bitrev(N - f, logn) * TP + c] = {a.re + b.im, b.re - a.im};
+        }
+    } else {  // inverse DCT-II: rebuild the FFT of Makhoul's sequence
+        const T *X = reinterpret_cast<const T *>(in);
+        const T rs0 = (T)sqrt((double)N), rs1 = (T)sqrt(N / 2.0);  // 1 / alpha_f
+        for (int w = tid; w < TP * (H + 1); w += NT) {
+            int c = w % TP, f = w / TP, g = N - f;
+            int64_t bx = base[c], by = base[c + TP];
+            T sf = f == 0 ? rs0 : rs1;
+            T ax = bx >= 0 ? X[bx + (int64_t)f * iv.s_t] * sf : T(0);
+            T ay = by >= 0 ? X[by + (int64_t)f * iv.s_t] * sf : T(0);
+            T bxv = (f > 0 && bx >= 0) ? X[bx + (int64_t)g * iv.s_t] * rs1 : T(0);
+            T byv = (f > 0 && by >= 0) ? X[by + (int64_t)g * iv.s_t] * rs1 : T(0);
+            // V[f] = exp(i pi f/(2N)) (C[f] - i C[N-f]),  Z = Vx + i Vy
+            cx<T> wc = cconj(wq[f]);
+            cx<T> vx = cmul(wc, cx<T>{ax, -bxv}), vy = cmul(wc, cx<T>{ay, -byv});
+            buf[bitrev(f, logn) * TP + c] = {vx.re - vy.im, vx.im + vy.re};
+            if (f > 0 && f < H) {
+                cx<T> wg = cconj(wq[g]);
+                cx<T> ux = cmul(wg, cx<T>{bxv, -ax}), uy = cmul(wg, cx<T>{byv, -ay});
+                buf[bitrev(g, logn) * TP + c] = {ux.re - uy.im, ux.im + uy.re};
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---------------------------------------------------------------- FFT
+    int s = 0;
+    if (logn & 1) {  // one radix-2 stage (h = 1)
+        for (int w = tid; w < TP * H; w += NT) {
+            int c = w % TP, qi = w / TP;
+            int i0r = qi << 1, i1r = i0r + 1;
+            cx<T> a = buf[i0r * TP + c], b = buf[i1r * TP + c];
+            buf[i0r * TP + c] = cadd(a, b);
+            buf[i1r * TP + c] = csub(a, b);
+        }
+        s = 1;
+        __syncthreads();
+    }
+    for (; s < logn; s += 2) {  // radix-4: stages s and s+1 together
+        const int h = 1 << s;
+        for (int w = tid; w < TP * (N >> 2); w += NT) {
+            int c = w % TP, qi = w / TP;
+            int pos = qi & (h - 1), grp = qi >> s;
+            int r0 = (grp << (s + 2)) + pos;
+            cx<T> x0 = buf[r0 * TP + c], x1 = buf[(r0 + h) * TP + c];
+            cx<T> x2 = buf[(r0 + 2 * h) * TP + c], x3 = buf[(r0 + 3 * h) * TP + c];
+            cx<T> wa = tw[pos << (logn - s - 1)];
+            cx<T> wb = tw[pos << (logn - s - 2)];
+            cx<T> wc = tw[(pos + h) << (logn - s - 2)];
+            cx<T> t1 = cmul(x1, wa), t3 = cmul(x3, wa);
+            cx<T> a0 = cadd(x0, t1), a1 = csub(x0, t1), a2 = cadd(x2, t3), a3 = csub(x2, t3);
+            cx<T> u2 = cmul(a2, wb), u3 = cmul(a3, wc);
+            buf[r0 * TP + c] = cadd(a0, u2);
+            buf[(r0 + 2 * h) * TP + c] = csub(a0, u2);
+            buf[(r0 + h) * TP + c] = cadd(a1, u3);
+            buf[(r0 + 3 * h) * TP + c] = csub(a1, u3);
+        }
+        __syncthreads();
+    }
+
+    // ---------------------------------------------------------------- store
+    if (DIR > 0 && KIND == KIND_DCT) {
+        T *Y = reinterpret_cast<T *>(out);
+        for (int w = tid; w < TT * N; w += NT) {
+            int u = w % TT, f = w / TT, c = u % TP;
+            cx<T> Z = buf[f * TP + c], Zr = buf[((N - f) & (N - 1)) * TP + c];
+            cx<T> V = u < TP ? cx<T>{(Z.re + Zr.re) * T(0.5), (Z.im - Zr.im) * T(0.5)}
+                             : cx<T>{(Z.im + Zr.im) * T(0.5), (Zr.re - Z.re) * T(0.5)};
+            cx<T> W = wq[f];
+            T val = (W.re * V.re - W.im * V.im) * dct_alpha<T>(f, N);
+            if (i0 + u < ntubes) Y[(i0 + u) + mp * f] = val;
+        }
+    } else if (DIR > 0) {  // DFT, faces 0..N/2
+        cx<T> *Y = reinterpret_cast<cx<T> *>(out);
+        const T sc = (T)(0.5 / sqrt((double)N));
+        for (int w = tid; w < TT * (H + 1); w += NT) {
+            int u = w % TT, f = w / TT, c = u % TP;
+            cx<T> Z = buf[f * TP + c], Zr = buf[((N - f) & (N - 1)) * TP + c];
+            cx<T> V = u < TP ? cx<T>{(Z.re + Zr.re) * sc, (Z.im - Zr.im) * sc}
+                             : cx<T>{(Z.im + Zr.im) * sc, (Zr.re - Z.re) * sc};
+            if (i0 + u < ntubes) Y[(i0 + u) + mp * f] = V;
+        }
+    } else {
+        T *Y = reinterpret_cast<T *>(out);
+        const T sc = KIND == KIND_DFT ? (T)(1.0 / sqrt((double)N)) : (T)(1.0 / N);
+        for (int w = tid; w < TT * N; w += NT) {
+            int u = w % TT, t = w / TT, c = u % TP;
+            int n = KIND == KIND_DCT ? makhoul(t, N) : t;
+            cx<T> Z = buf[n * TP + c];
+            T val = (u < TP ? Z.re : Z.im) * sc;
+            if (i0 + u < ntubes) Y[(i0 + u) + mp * t] = val;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- dense
+enum { DENSE_DCT_FWD = 0, DENSE_DCT_INV, DENSE_M_FWD, DENSE_M_INV, DENSE_DFT_FWD, DENSE_DFT_INV };
+
+template <typename T, int CASE>
+__global__ __launch_bounds__(NT) void k_dense_tubes(const void *__restrict__ in, View iv,
+                                                    void *__restrict__ out, int64_t ntubes,
+                                                    int64_t mp, int N, int nf_in, int nf_out,
+                                                    int TB, const double *__restrict__ Md) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr bool CIN = CASE == DENSE_DFT_INV;
+    constexpr bool COUT = CASE == DENSE_DFT_FWD;
+    constexpr bool TAB = CASE == DENSE_DCT_FWD || CASE == DENSE_DCT_INV || CASE == DENSE_DFT_FWD ||
+                         CASE == DENSE_DFT_INV;
+    double *ctab = reinterpret_cast<double *>(smem);  // [4N] cos(pi j / (2N))
+    T *xs = reinterpret_cast<T *>(smem + (TAB ? sizeof(double) * 4 * N : 0));  // [nf_in][TB](x2)
+    const int tid = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * TB;
+    if (TAB)
+        for (int j = tid; j < 4 * N; j += NT) ctab[j] = cospi((double)j / (2.0 * N));
+    const int E = CIN ? 2 : 1;
+    for (int w = tid; w < TB * nf_in; w += NT) {
+        int u = w % TB, t = w / TB;
+        bool ok = i0 + u < ntubes;
+        int64_t b = ok ? iv.tube_base(i0 + u) + (int64_t)t * iv.s_t : 0;
+        if (CIN) {
+            const T *X = reinterpret_cast<const T *>(in);
+            xs[(t * TB + u) * 2 + 0] = ok ? X[2 * b] : T(0);
+            xs[(t * TB + u) * 2 + 1] = ok ? X[2 * b + 1] : T(0);
+        } else {
+            const T *X = reinterpret_cast<const T *>(in);
+            xs[t * TB + u] = ok ? X[b] : T(0);
+        }
+    }
+    __syncthreads();
+    const int u = tid % TB, ng = NT / TB;
+    const int fourN = 4 * N;
+    const double rsn = 1.0 / sqrt((double)N);
+    for (int o = tid / TB; o < nf_out; o += ng) {
+        double acc = 0.0, acci = 0.0;
+        for (int j = 0; j < nf_in; ++j) {
+            if (CASE == DENSE_DCT_FWD || CASE == DENSE_DCT_INV) {
+                int f = CASE == DENSE_DCT_FWD ? o : j, t = CASE == DENSE_DCT_FWD ? j : o;
+                double a = f == 0 ? sqrt(1.0 / N) : sqrt(2.0 / N);
+                acc += a * ctab[((2 * t + 1) * f) % fourN] * (double)xs[j * TB + u];
+            } else if (CASE == DENSE_M_FWD) {
+                acc += Md[o + (int64_t)N * j] * (double)xs[j * TB + u];
+            } else if (CASE == DENSE_M_INV) {
+                acc += Md[j + (int64_t)N * o] * (double)xs[j * TB + u];
+            } else if (CASE == DENSE_DFT_FWD) {
+                int r = (int)(((int64_t)o * j) % N);
+                double c = ctab[4 * r], sn = ctab[(4 * r - N + fourN) % fourN];
+                double x = (double)xs[j * TB + u];
+                acc += c * x;
+                acci -= sn * x;
+            } else {  // DENSE_DFT_INV: faces j = 0..nf_in-1 of a Hermitian spectrum
+                int r = (int)(((int64_t)j * o) % N);
+                double c = ctab[4 * r], sn = ctab[(4 * r - N + fourN) % fourN];
+                double wgt = (j == 0 || 2 * j == N) ? 1.0 : 2.0;
+                acc += wgt * (c * (double)xs[(j * TB + u) * 2] - sn * (double)xs[(j * TB + u) * 2 + 1]);
+            }
+        }
+        if (i0 + u < ntubes) {
+            if (COUT) {
+                T *Y = reinterpret_cast<T *>(out);
+                Y[2 * ((i0 + u) + mp * o)] = (T)(acc * rsn);
+                Y[2 * ((i0 + u) + mp * o) + 1] = (T)(acci * rsn);
+            } else {
+                T *Y = reinterpret_cast<T *>(out);
+                Y[(i0 + u) + mp * o] = (T)(CASE == DENSE_DFT_INV ? acc * rsn : acc);
+            }
+        }
+    }
+    (void)E;
+}
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <typename T>
+tsvdm_status run_fft(int kind, int dir, const tsvdm_tensor *in, tsvdm_tensor *out, int N,
+                     hipStream_t s) {
+    int logn = 0;
+    while ((1 << logn) < N) ++logn;
+    const int64_t ntubes = in->m * in->p, mp = ntubes;
+    int TP = 64;
+    while (TP > 1 && (size_t)N * TP * sizeof(cx<T>) > 65536) TP >>= 1;
+    const size_t lds = sizeof(cx<T>) * ((size_t)N * TP + N / 2 + N) + sizeof(int64_t) * 2 * TP;
+    const int64_t grid = (ntubes + 2 * TP - 1) / (2 * TP);
+    if (grid == 0) return TSVDM_OK;
+    View iv = make_view(*in);
+    hipError_t e = hipSuccess;
+#define TSVDM_FFT_LAUNCH(KD, DR)                                                                \
+    do {                                                                                         \
+        auto kern = k_fft_tubes<T, KD, DR>;                                                      \
+        e = allow_lds(kern, lds);                                                                \
+        if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute(fft)");                   \
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), lds, s, in->data, iv, out->data, \
+                           ntubes, mp, logn, TP);                                                \
+    } while (0)
+    if (kind == KIND_DCT && dir > 0) TSVDM_FFT_LAUNCH(KIND_DCT, 1);
+    else if (kind == KIND_DCT) TSVDM_FFT_LAUNCH(KIND_DCT, -1);
+    else if (dir > 0) TSVDM_FFT_LAUNCH(KIND_DFT, 1);
+    else TSVDM_FFT_LAUNCH(KIND_DFT, -1);
+#undef TSVDM_FFT_LAUNCH
+    TSVDM_LAUNCH_CHECK("k_fft_tubes");
+    return TSVDM_OK;
+}
+
+template <typename T>
+tsvdm_status run_dense(int kind, int dir, const tsvdm_mdesc *M, const tsvdm_tensor *in,
+                       tsvdm_tensor *out, int N, hipStream_t s) {
+    const int64_t ntubes = in->m * in->p, mp = ntubes;
+    const int nf_in = (int)in->n3, nf_out = (int)out->n3;
+    const bool tab = kind != TSVDM_M_DENSE;
+    const bool cin = kind == TSVDM_M_DFT && dir < 0;
+    const size_t esz = sizeof(T) * (cin ? 2 : 1);
+    const size_t tabb = tab ? sizeof(double) * 4 * N : 0;
+    int TB = 64;
+    while (TB > 1 && tabb + (size_t)nf_in * TB * esz > 96 * 1024) TB >>= 1;
+    const size_t lds = tabb + (size_t)nf_in * TB * esz;
+    const int64_t grid = (ntubes + TB - 1) / TB;
+    if (grid == 0) return TSVDM_OK;
+    View iv = make_view(*in);
+    hipError_t e = hipSuccess;
+#define TSVDM_DENSE_LAUNCH(CS)                                                                  \
+    do {                                                                                         \
+        auto kern = k_dense_tubes<T, CS>;                                                        \
+        e = allow_lds(kern, lds);                                                                \
+        if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute(dense)");                 \
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), lds, s, in->data, iv, out->data, \
+                           ntubes, mp, N, nf_in, nf_out, TB, M->M);                             \
+    } while (0)
+    if (kind == TSVDM_M_DCT2) {
+        if (dir > 0) TSVDM_DENSE_LAUNCH(DENSE_DCT_FWD);
+        else TSVDM_DENSE_LAUNCH(DENSE_DCT_INV);
+    } else if (kind == TSVDM_M_DENSE) {
+        if (dir > 0) TSVDM_DENSE_LAUNCH(DENSE_M_FWD);
+        else TSVDM_DENSE_LAUNCH(DENSE_M_INV);
+    } else {
+        if (dir > 0) TSVDM_DENSE_LAUNCH(DENSE_DFT_FWD);
+        else TSVDM_DENSE_LAUNCH(DENSE_DFT_INV);
+    }
+#undef TSVDM_DENSE_LAUNCH
+    TSVDM_LAUNCH_CHECK("k_dense_tubes");
+    return TSVDM_OK;
+}
+
+}  // namespace
+
+namespace tsvdm {
+
+tsvdm_status launch_transform(const tsvdm_mdesc *M, int direction, const tsvdm_tensor *in,
+                              tsvdm_tensor *out, hipStream_t s) {
+    const int N = (int)M->n3;
+    const bool pow2 = N >= 2 && (N & (N - 1)) == 0;
+    const bool dbl = in->dtype == TSVDM_F64 || in->dtype == TSVDM_C128;
+    if (M->kind != TSVDM_M_DENSE && pow2) {
+        int kind = M->kind == TSVDM_M_DCT2 ? KIND_DCT : KIND_DFT;
+        return dbl ? run_fft<double>(kind, direction, in, out, N, s)
+                   : run_fft<float>(kind, direction, in, out, N, s);
+    }
+    return dbl ? run_dense<double>(M->kind, direction, M, in, out, N, s)
+               : run_dense<float>(M->kind, direction, M, in, out, N, s);
+}
+
+}  // namespace tsvdm

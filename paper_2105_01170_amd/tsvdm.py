@@ -1,0 +1,170 @@
+"""Thin ctypes binding of the t-SVDM C ABI (include/tsvdm.h).
+
+The functions here carry the C entry points' names and only marshal
+arguments: every step of the computation runs in the HIP library
+``libtsvdm.so``.  Device memory and streams come from the caller (PyTorch
+tensors in the helpers below).  If the library is not built, loading it
+raises; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtsvdm.so")
+
+# status / dtype / transform / rank / precision codes (tsvdm.h)
+OK, EINVAL, EUNSUPPORTED, EWORKSPACE, EDEVICE = 0, 1, 2, 3, 4
+F64, F32, BF16, C64, C128 = 0, 1, 2, 3, 4
+M_DCT2, M_DFT, M_DENSE = 0, 1, 2
+RANK_FIXED, RANK_ENERGY = 0, 1
+PREC_F64, PREC_MIXED = 0, 1
+
+
+class TsvdmMdesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n3", ctypes.c_int64),
+                ("M", ctypes.c_void_p)]
+
+
+class TsvdmTensor(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("p", ctypes.c_int64), ("n3", ctypes.c_int64),
+                ("s_a", ctypes.c_int64), ("s_b", ctypes.c_int64), ("s_t", ctypes.c_int64),
+                ("bsplit", ctypes.c_int64), ("s_bk", ctypes.c_int64),
+                ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32), ("data", ctypes.c_void_p)]
+
+
+class TsvdmTruncateOpts(ctypes.Structure):
+    _fields_ = [("rank_mode", ctypes.c_int32), ("k", ctypes.c_int32), ("tau", ctypes.c_double),
+                ("precision", ctypes.c_int32), ("oversample", ctypes.c_int32),
+                ("power_iters", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("certify", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("omega", ctypes.c_void_p)]
+
+
+class TsvdmFactors(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("p", ctypes.c_int64), ("nf", ctypes.c_int64),
+                ("kmax", ctypes.c_int64), ("dtype", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("U", ctypes.c_void_p), ("S", ctypes.c_void_p), ("V", ctypes.c_void_p),
+                ("ranks", ctypes.c_void_p), ("cert", ctypes.c_void_p), ("fro", ctypes.c_void_p),
+                ("info", ctypes.c_void_p)]
+
+
+EXPORTS = ["tsvdm_version", "tsvdm_last_error", "tsvdm_tensor_from_blockmat",
+           "tsvdm_check_orthogonal", "tsvdm_transform", "tsvdm_truncate_workspace_size",
+           "tsvdm_truncate", "tsvdm_apply_workspace_size", "tsvdm_apply"]
+
+_LIB = None
+
+
+def lib():
+    """Load libtsvdm.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER
+        vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+        L.tsvdm_version.restype = i32
+        L.tsvdm_version.argtypes = []
+        L.tsvdm_last_error.restype = ctypes.c_char_p
+        L.tsvdm_last_error.argtypes = []
+        L.tsvdm_tensor_from_blockmat.restype = i32
+        L.tsvdm_tensor_from_blockmat.argtypes = [vp, i64, i32, i64, i64, i64, i64, P(TsvdmTensor)]
+        L.tsvdm_check_orthogonal.restype = i32
+        L.tsvdm_check_orthogonal.argtypes = [vp, i64, ctypes.c_double]
+        L.tsvdm_transform.restype = i32
+        L.tsvdm_transform.argtypes = [P(TsvdmMdesc), i32, P(TsvdmTensor), P(TsvdmTensor), vp]
+        L.tsvdm_truncate_workspace_size.restype = sz
+        L.tsvdm_truncate_workspace_size.argtypes = [P(TsvdmTensor), P(TsvdmTruncateOpts)]
+        L.tsvdm_truncate.restype = i32
+        L.tsvdm_truncate.argtypes = [P(TsvdmTensor), P(TsvdmTruncateOpts), P(TsvdmFactors), vp, sz, vp]
+        L.tsvdm_apply_workspace_size.restype = sz
+        L.tsvdm_apply_workspace_size.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, i32]
+        L.tsvdm_apply.restype = i32
+        L.tsvdm_apply.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, vp, i64, vp, i64,
+                                  i32, vp, sz, vp]
+        _LIB = L
+    return _LIB
+
+
+class TsvdmError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"tsvdm status {status}: {msg}")
+        self.status = status
+
+
+def _check(st):
+    if st != OK:
+        raise TsvdmError(st, lib().tsvdm_last_error().decode())
+    return st
+
+
+# ------------------------------------------------------------ C entry points
+def tsvdm_version() -> int:
+    return lib().tsvdm_version()
+
+
+def tsvdm_last_error() -> str:
+    return lib().tsvdm_last_error().decode()
+
+
+def tsvdm_tensor_from_blockmat(A_ptr: int, lda: int, dtype: int, ell: int, q: int, m: int,
+                               n: int) -> TsvdmTensor:
+    out = TsvdmTensor()
+    _check(lib().tsvdm_tensor_from_blockmat(A_ptr, lda, dtype, ell, q, m, n, ctypes.byref(out)))
+    return out
+
+
+def tsvdm_check_orthogonal(M_host_ptr: int, n3: int, tol: float) -> int:
+    return lib().tsvdm_check_orthogonal(M_host_ptr, n3, tol)
+
+
+def tsvdm_transform(M: TsvdmMdesc, direction: int, inp: TsvdmTensor, out: TsvdmTensor,
+                    stream: int = 0):
+    _check(lib().tsvdm_transform(ctypes.byref(M), direction, ctypes.byref(inp), ctypes.byref(out),
+                                 stream))
+
+
+def tsvdm_truncate_workspace_size(X: TsvdmTensor, opts: TsvdmTruncateOpts) -> int:
+    return lib().tsvdm_truncate_workspace_size(ctypes.byref(X), ctypes.byref(opts))
+
+
+def tsvdm_truncate(X: TsvdmTensor, opts: TsvdmTruncateOpts, F: TsvdmFactors, ws_ptr: int,
+                   ws_bytes: int, stream: int = 0):
+    _check(lib().tsvdm_truncate(ctypes.byref(X), ctypes.byref(opts), ctypes.byref(F), ws_ptr,
+                                ws_bytes, stream))
+
+
+def tsvdm_apply_workspace_size(M: TsvdmMdesc, F: TsvdmFactors, ell: int, q: int, nrhs: int,
+                               compute: int) -> int:
+    return lib().tsvdm_apply_workspace_size(ctypes.byref(M), ctypes.byref(F), ell, q, nrhs, compute)
+
+
+def tsvdm_apply(M: TsvdmMdesc, F: TsvdmFactors, ell: int, q: int, nrhs: int, x_ptr: int, ldx: int,
+                y_ptr: int, ldy: int, compute: int, ws_ptr: int, ws_bytes: int, stream: int = 0):
+    _check(lib().tsvdm_apply(ctypes.byref(M), ctypes.byref(F), ell, q, nrhs, x_ptr, ldx, y_ptr,
+                             ldy, compute, ws_ptr, ws_bytes, stream))
+
+
+# ------------------------------------------------------------ descriptors
+def mdesc(kind: int, n3: int, M_ptr: int = 0) -> TsvdmMdesc:
+    return TsvdmMdesc(kind, 0, n3, M_ptr or None)
+
+
+def dense_tensor(ptr: int, m: int, p: int, n3: int, dtype: int) -> TsvdmTensor:
+    """Descriptor of a dense column-major (m, p, n3) tensor at device address ptr."""
+    return TsvdmTensor(m, p, n3, 1, m, m * p, 0, 0, dtype, 0, ptr)
+
+
+def truncate_opts(rank_mode=RANK_FIXED, k=1, tau=0.0, precision=PREC_F64, oversample=0,
+                  power_iters=0, max_sweeps=0, certify=1, omega_ptr=0) -> TsvdmTruncateOpts:
+    return TsvdmTruncateOpts(rank_mode, k, tau, precision, oversample, power_iters, max_sweeps,
+                             certify, 0, omega_ptr or None)
+
+
+def factors(m, p, nf, kmax, dtype, U, S, V, ranks, cert=0, fro=0, info=0) -> TsvdmFactors:
+    return TsvdmFactors(m, p, nf, kmax, dtype, 0, U, S, V, ranks, cert or None, fro or None,
+                        info or None)

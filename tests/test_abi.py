@@ -1,0 +1,180 @@
+"""C-ABI checks that need no GPU: symbols, struct layouts, host-side validation."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_2105_01170_amd import tsvdm as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsvdm.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(tsvdm_[a-z_]+)\s*\(", text)))
+
+
+def test_library_loads_and_exports_every_declared_symbol():
+    lib = C.lib()
+    declared = _declared_functions()
+    assert set(declared) == set(C.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert C.tsvdm_version() >> 16 == 1
+
+
+def test_struct_layout_matches_c_compiler(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "tsvdm.h"
+#define P(T, f) printf(#T "." #f " %zu\n", offsetof(T, f))
+int main(void) {
+  printf("sizeof tsvdm_mdesc %zu\n", sizeof(tsvdm_mdesc));
+  printf("sizeof tsvdm_tensor %zu\n", sizeof(tsvdm_tensor));
+  printf("sizeof tsvdm_truncate_opts %zu\n", sizeof(tsvdm_truncate_opts));
+  printf("sizeof tsvdm_factors %zu\n", sizeof(tsvdm_factors));
+  P(tsvdm_mdesc, M); P(tsvdm_tensor, bsplit); P(tsvdm_tensor, dtype); P(tsvdm_tensor, data);
+  P(tsvdm_truncate_opts, tau); P(tsvdm_truncate_opts, certify); P(tsvdm_truncate_opts, omega);
+  P(tsvdm_factors, dtype); P(tsvdm_factors, U); P(tsvdm_factors, info);
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)],
+                   check=True)
+    out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True,
+                                                              text=True, check=True).stdout.split("\n") if line)
+    out = {k: int(v) for k, v in out.items()}
+    assert out["sizeof tsvdm_mdesc"] == ctypes.sizeof(C.TsvdmMdesc)
+    assert out["sizeof tsvdm_tensor"] == ctypes.sizeof(C.TsvdmTensor)
+    assert out["sizeof tsvdm_truncate_opts"] == ctypes.sizeof(C.TsvdmTruncateOpts)
+    assert out["sizeof tsvdm_factors"] == ctypes.sizeof(C.TsvdmFactors)
+    for key, val in out.items():
+        if key.startswith("sizeof"):
+            continue
+        struct, field = key.split(".")
+        cls = {"tsvdm_mdesc": C.TsvdmMdesc, "tsvdm_tensor": C.TsvdmTensor,
+               "tsvdm_truncate_opts": C.TsvdmTruncateOpts, "tsvdm_factors": C.TsvdmFactors}[struct]
+        assert getattr(cls, field).offset == val, key
+
+
+def test_blockmat_view_strides():
+    """T_E[A] view: X(a, j + ell*k, t) = A(j*m + a, k*n + t) with lda."""
+    v = C.tsvdm_tensor_from_blockmat(0x1000, 50, C.F64, 3, 4, 7, 5)
+    assert (v.m, v.p, v.n3) == (7, 12, 5)
+    ell, lda, m, n = 3, 50, 7, 5
+    for a, j, k, t in [(0, 0, 0, 0), (6, 2, 3, 4), (3, 1, 2, 0)]:
+        b = j + ell * k
+        addr = a * v.s_a + (b % v.bsplit) * v.s_b + (b // v.bsplit) * v.s_bk + t * v.s_t
+        assert addr == (j * m + a) + lda * (k * n + t)
+
+
+def test_blockmat_view_rejects_bad_arguments():
+    with pytest.raises(C.TsvdmError) as e:
+        C.tsvdm_tensor_from_blockmat(0x1000, 10, C.F64, 3, 4, 7, 5)  # lda < ell*m
+    assert e.value.status == C.EINVAL
+    with pytest.raises(C.TsvdmError):
+        C.tsvdm_tensor_from_blockmat(0x1000, 50, C.C64, 3, 4, 7, 5)
+    with pytest.raises(C.TsvdmError):
+        C.tsvdm_tensor_from_blockmat(0, 50, C.F64, 3, 4, 7, 5)
+
+
+def test_check_orthogonal_host():
+    Q, _ = np.linalg.qr(np.random.default_rng(0).standard_normal((9, 9)))
+    Qf = np.asfortranarray(Q)
+    assert C.tsvdm_check_orthogonal(Qf.ctypes.data, 9, 1e-12) == C.OK
+    Qf[0, 0] += 1e-6
+    assert C.tsvdm_check_orthogonal(Qf.ctypes.data, 9, 1e-12) == C.EINVAL
+    assert "not orthogonal" in C.tsvdm_last_error()
+
+
+def _t(m, p, n3, dt, ptr=0x1000):
+    return C.dense_tensor(ptr, m, p, n3, dt)
+
+
+@pytest.mark.parametrize("case", [
+    dict(M=(C.M_DFT, 8), d=1, i=(4, 5, 8, C.F32), o=(4, 5, 8, C.C64)),      # out must have 5 faces
+    dict(M=(C.M_DFT, 8), d=1, i=(4, 5, 8, C.F32), o=(4, 5, 5, C.F32)),      # out must be complex
+    dict(M=(C.M_DCT2, 8), d=1, i=(4, 5, 8, C.F32), o=(4, 5, 8, C.F64)),     # precision mismatch
+    dict(M=(C.M_DCT2, 8), d=2, i=(4, 5, 8, C.F32), o=(4, 5, 8, C.F32)),     # direction
+    dict(M=(C.M_DCT2, 8), d=1, i=(4, 5, 8, C.F32), o=(4, 6, 8, C.F32)),     # p mismatch
+    dict(M=(C.M_DENSE, 8), d=1, i=(4, 5, 8, C.F32), o=(4, 5, 8, C.F32)),    # dense without M
+    dict(M=(C.M_DCT2, 4096), d=1, i=(4, 5, 4096, C.F32), o=(4, 5, 4096, C.F32)),  # too long
+])
+def test_transform_validation(case):
+    M = C.mdesc(*case["M"])
+    tin = _t(*case["i"], ptr=0x1000)
+    tout = _t(*case["o"], ptr=0x9000)
+    with pytest.raises(C.TsvdmError) as e:
+        C.tsvdm_transform(M, case["d"], tin, tout, 0)
+    assert e.value.status in (C.EINVAL, C.EUNSUPPORTED)
+    assert C.tsvdm_last_error()
+
+
+def test_transform_rejects_strided_output_and_aliasing():
+    M = C.mdesc(C.M_DCT2, 8)
+    tin = _t(4, 5, 8, C.F32, 0x1000)
+    tout = _t(4, 5, 8, C.F32, 0x9000)
+    tout.s_t = 999
+    with pytest.raises(C.TsvdmError):
+        C.tsvdm_transform(M, 1, tin, tout, 0)
+    with pytest.raises(C.TsvdmError):
+        C.tsvdm_transform(M, 1, tin, _t(4, 5, 8, C.F32, 0x1000), 0)
+
+
+def test_truncate_validation_and_workspace():
+    X = _t(64, 48, 4, C.F32)
+    o = C.truncate_opts(C.RANK_FIXED, 8, 0.0, C.PREC_MIXED, 8, 1, 0, 1, 0x2000)
+    ws = C.tsvdm_truncate_workspace_size(X, o)
+    assert ws > 0
+    F = C.factors(64, 48, 4, 8, C.F32, 0x3000, 0x4000, 0x5000, 0x6000)
+    with pytest.raises(C.TsvdmError) as e:       # workspace too small
+        C.tsvdm_truncate(X, o, F, 0x7000, ws - 1, 0)
+    assert e.value.status == C.EWORKSPACE
+    bad = [
+        C.truncate_opts(C.RANK_FIXED, 8, 0.0, C.PREC_MIXED, 8, 1, 0, 1, 0),        # no omega
+        C.truncate_opts(C.RANK_FIXED, 60, 0.0, C.PREC_MIXED, 8, 1, 0, 1, 0x2000),  # ell > 64
+        C.truncate_opts(C.RANK_FIXED, 8, 0.0, C.PREC_MIXED, 8, 2, 0, 1, 0x2000),   # power iters
+        C.truncate_opts(C.RANK_FIXED, 8, 0.0, C.PREC_F64, 0, 0, 0, 1, 0),          # F32 data, F64 path
+        C.truncate_opts(7, 8, 0.0, C.PREC_MIXED, 8, 1, 0, 1, 0x2000),              # rank mode
+        C.truncate_opts(C.RANK_ENERGY, 8, -1.0, C.PREC_MIXED, 8, 1, 0, 1, 0x2000),  # tau < 0
+    ]
+    for ob in bad:
+        assert C.tsvdm_truncate_workspace_size(X, ob) == 0
+        with pytest.raises(C.TsvdmError):
+            C.tsvdm_truncate(X, ob, F, 0x7000, ws, 0)
+    # factor shape and kmax checks
+    with pytest.raises(C.TsvdmError):
+        C.tsvdm_truncate(X, o, C.factors(64, 48, 5, 8, C.F32, 1, 2, 3, 4), 0x7000, ws, 0)
+    with pytest.raises(C.TsvdmError):
+        C.tsvdm_truncate(X, o, C.factors(64, 48, 4, 7, C.F32, 1, 2, 3, 4), 0x7000, ws, 0)
+    with pytest.raises(C.TsvdmError):
+        C.tsvdm_truncate(X, o, C.factors(64, 48, 4, 8, C.F64, 1, 2, 3, 4), 0x7000, ws, 0)
+
+
+def test_apply_validation():
+    M = C.mdesc(C.M_DFT, 8)
+    F = C.factors(6, 12, 5, 3, C.C64, 1, 2, 3, 4)
+    assert C.tsvdm_apply_workspace_size(M, F, 3, 4, 10, C.F32) > 0
+    with pytest.raises(C.TsvdmError):  # p != ell*q
+        C.tsvdm_apply(M, F, 3, 5, 10, 0x1000, 32, 0x2000, 18, C.F32, 0x3000, 1 << 20, 0)
+    with pytest.raises(C.TsvdmError):  # real factors with the DFT
+        C.tsvdm_apply(M, C.factors(6, 12, 5, 3, C.F32, 1, 2, 3, 4), 3, 4, 10, 0x1000, 32, 0x2000,
+                      18, C.F32, 0x3000, 1 << 20, 0)
+    with pytest.raises(C.TsvdmError):  # nf must be n3/2+1
+        C.tsvdm_apply(M, C.factors(6, 12, 8, 3, C.C64, 1, 2, 3, 4), 3, 4, 10, 0x1000, 32, 0x2000,
+                      18, C.F32, 0x3000, 1 << 20, 0)
+    with pytest.raises(C.TsvdmError):  # ldx too small
+        C.tsvdm_apply(M, F, 3, 4, 10, 0x1000, 31, 0x2000, 18, C.F32, 0x3000, 1 << 20, 0)
+    with pytest.raises(C.TsvdmError) as e:  # workspace
+        C.tsvdm_apply(M, F, 3, 4, 10, 0x1000, 32, 0x2000, 18, C.F32, 0x3000, 1, 0)
+    assert e.value.status == C.EWORKSPACE
+    with pytest.raises(C.TsvdmError):  # compute precision vs factors
+        C.tsvdm_apply(M, F, 3, 4, 10, 0x1000, 32, 0x2000, 18, C.F64, 0x3000, 1 << 20, 0)

@@ -1,0 +1,63 @@
+"""GPU parity of tsvdm_apply against the dense product A_hat x formed by the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_helpers import from_dev, relerr, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2105_01170_amd import api  # noqa: E402
+from paper_2105_01170_amd import tsvdm as C  # noqa: E402
+
+TOL = {C.F64: 1e-10, C.F32: 2e-5, C.BF16: 3e-2}
+
+
+def _case(kind, m, ell, q, n, k, nrhs, compute, salt=0):
+    w = synth.apply_factors(m=m, ell=ell, q=q, n=n, k=k, nrhs=nrhs, salt=salt)
+    p = ell * q
+    M = oracle.dct2_matrix(n) if kind == C.M_DCT2 else oracle.dft_matrix(n)
+    # oracle: dense A_hat from the spatial factors, every face of the transform domain
+    Uh, Vh = oracle.mode3(w["U"], M), oracle.mode3(w["V"], M)
+    That = np.zeros((m, p, n), dtype=Uh.dtype, order="F")
+    for f in range(n):
+        That[:, :, f] = (Uh[:, :, f] * w["sigma"]) @ np.conj(Vh[:, :, f]).T
+    T = oracle.inverse_mode3(That, M)
+    if kind == C.M_DFT:
+        T = np.real(T)
+    Ahat = oracle.blockmat_from_tensor(T, ell, q)
+    y_ref = oracle.dense_apply(Ahat, w["X"])
+    # GPU: transform the spatial factors with the library, then apply
+    rdt = np.float64 if compute == C.F64 else np.float32
+    tdt = torch.float64 if compute == C.F64 else torch.float32
+    Ud = api.transform(to_dev(w["U"], rdt), m, k, n, kind, +1)
+    Vd = api.transform(to_dev(w["V"], rdt), p, k, n, kind, +1)
+    nf = n // 2 + 1 if kind == C.M_DFT else n
+    S = torch.tensor(np.tile(w["sigma"][:, None], (1, nf)).ravel(order="F"), dtype=torch.float64,
+                     device="cuda")
+    F = api.Factors(m, p, nf, k, Ud, S, Vd, torch.full((nf,), k, dtype=torch.int32, device="cuda"),
+                    torch.zeros(nf, dtype=torch.float64, device="cuda"),
+                    torch.zeros(nf, dtype=torch.float64, device="cuda"),
+                    torch.zeros(nf, dtype=torch.int32, device="cuda"))
+    x = to_dev(w["X"], rdt)
+    y = api.apply(F, kind, n, ell, q, x, compute=compute)
+    assert y.dtype == tdt
+    return from_dev(y, (ell * m, nrhs)), y_ref
+
+
+@pytest.mark.parametrize("compute", [C.F64, C.F32, C.BF16])
+@pytest.mark.parametrize("kind", [C.M_DCT2, C.M_DFT])
+@pytest.mark.parametrize("dims", [(8, 4, 3, 8, 3, 20), (70, 3, 5, 12, 5, 65), (5, 2, 70, 6, 2, 7)])
+def test_apply_small(kind, compute, dims):
+    m, ell, q, n, k, nrhs = dims
+    y, y_ref = _case(kind, m, ell, q, n, k, nrhs, compute)
+    assert relerr(y, y_ref) < TOL[compute], relerr(y, y_ref)
+
+
+def test_apply_full_size_dft_fp32():
+    """4096 x 4096 structured matrix (l = q = m = n = 64, rank 16, DFT) on 1024
+    right-hand sides, FP32, against the dense FP64 product."""
+    y, y_ref = _case(C.M_DFT, 64, 64, 64, 64, 16, 1024, C.F32)
+    assert relerr(y, y_ref) < TOL[C.F32]

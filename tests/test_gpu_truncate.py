@@ -1,0 +1,152 @@
+"""GPU parity of tsvdm_truncate (plain FP64 and mixed precision) against the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_helpers import from_dev, reconstruct, relerr, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2105_01170_amd import api  # noqa: E402
+from paper_2105_01170_amd import tsvdm as C  # noqa: E402
+
+
+def _gpu_factors(F, nf):
+    m, p, k = F.m, F.p, F.kmax
+    U = from_dev(F.U, (m, k, nf))
+    V = from_dev(F.V, (p, k, nf))
+    S = from_dev(F.S, (k, nf))
+    return U, S, V, from_dev(F.ranks, (nf,)), from_dev(F.cert, (nf,)), from_dev(F.fro, (nf,)), \
+        from_dev(F.info, (nf,))
+
+
+# ------------------------------------------------------------------ plain FP64
+@pytest.mark.parametrize("shape", [(12, 7, 4), (7, 12, 5), (16, 16, 3), (1, 9, 2), (9, 1, 2),
+                                   (33, 70, 3), (70, 33, 2)])
+@pytest.mark.parametrize("mode", ["fixed", "energy"])
+def test_plain_f64_real(shape, mode):
+    m, p, nf = shape
+    g = np.random.default_rng(sum(shape))
+    Xh = np.asfortranarray(g.standard_normal(shape))
+    k, tau = (3, 0.0) if mode == "fixed" else (0, 0.35)
+    ref = oracle.tsvdm_truncate_faces(Xh, mode, k, tau)
+    kmax = min(m, p) if mode == "energy" else min(k, m, p)
+    tr = api.Truncator(m, p, nf, torch.float64, rank_mode=C.RANK_FIXED if mode == "fixed" else
+                       C.RANK_ENERGY, k=k, tau=tau, precision=C.PREC_F64, kmax=kmax)
+    F = tr(to_dev(Xh))
+    U, S, V, ranks, cert, fro, info = _gpu_factors(F, nf)
+    assert np.array_equal(ranks, ref["ranks"])
+    assert np.all(info == 0)
+    for f in range(nf):
+        kf = ranks[f]
+        np.testing.assert_allclose(S[:kf, f], ref["s"][:kf, f], rtol=1e-12, atol=1e-13)
+    assert relerr(reconstruct(U, S, V, ranks), ref["That"]) < 1e-10
+    disc = np.array([np.sqrt(np.sum(ref["s"][ranks[f]:, f] ** 2)) for f in range(nf)])
+    np.testing.assert_allclose(cert, disc, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(fro, np.sqrt(ref["fro2"]), rtol=1e-13)
+
+
+@pytest.mark.parametrize("shape", [(6, 9, 8), (10, 4, 7)])
+def test_plain_f64_complex_dft_half(shape):
+    m, p, n = shape
+    g = np.random.default_rng(n)
+    X = np.asfortranarray(g.standard_normal(shape))
+    res = oracle.tsvdm(X, oracle.dft_matrix(n), "fixed", 2)
+    half = n // 2 + 1
+    Xh = np.asfortranarray(res["Xh"][:, :, :half])
+    tr = api.Truncator(m, p, half, torch.complex128, k=2, precision=C.PREC_F64, kmax=2)
+    F = tr(to_dev(Xh))
+    U, S, V, ranks, cert, fro, info = _gpu_factors(F, half)
+    assert np.array_equal(ranks, res["ranks"][:half])
+    assert relerr(reconstruct(U, S, V, ranks), res["That"][:, :, :half]) < 1e-10
+    # the real result in the original domain from the half faces
+    Uf, Sf, Vf, Rf = oracle.expand_hermitian(U, S, V, ranks, n)
+    T = np.real(oracle.approx_from_factors(Uf, Sf, Vf, Rf, oracle.dft_matrix(n)))
+    assert relerr(T, res["T"]) < 1e-10
+
+
+def test_plain_f64_kronecker_sum_workload_full_size():
+    """The 1024 x 1024 Kronecker-sum matrix (4 terms + 1e-8 noise), DCT-II,
+    rank 4: full pipeline on the GPU (zero-copy view, transform, truncate,
+    inverse transform of the truncated faces) against the oracle."""
+    w = synth.kronecker_sum_matrix(terms=4, size=32, noise=1e-8)
+    A, ell, q, m, n = w["A"], w["ell"], w["q"], w["m"], w["n"]
+    Ad = to_dev(A)
+    view = C.tsvdm_tensor_from_blockmat(Ad.data_ptr(), ell * m, C.F64, ell, q, m, n)
+    p = ell * q
+    xh = api.transform(Ad, m, p, n, C.M_DCT2, +1, view=view)
+    tr = api.Truncator(m, p, n, torch.float64, k=4, precision=C.PREC_F64)
+    F = tr(xh)
+    U, S, V, ranks, cert, fro, info = _gpu_factors(F, n)
+    X = oracle.tensor_from_blockmat(A, ell, q, m, n)
+    ref = oracle.tsvdm(X, oracle.dct2_matrix(n), "fixed", 4)
+    assert np.all(ranks == 4) and np.all(info == 0)
+    That = reconstruct(U, S, V, ranks)
+    assert relerr(That, ref["That"]) < 1e-10
+    T = oracle.inverse_mode3(That, oracle.dct2_matrix(n))
+    Ahat = oracle.blockmat_from_tensor(T, ell, q)
+    rec = relerr(Ahat, A)
+    assert 1e-10 < rec < 1e-8   # recovery to the 1e-8 noise level
+    # Lemma lem:tenapprox on the GPU result: matrix error = tensor error
+    assert np.linalg.norm(A - Ahat) == pytest.approx(np.linalg.norm(X - T), rel=1e-9)
+
+
+# ------------------------------------------------------------------ mixed
+def _known_rank_input(m, p, n3, k, decay, seed_salt):
+    fac = synth.known_rank_factors(m=m, p=p, n3=n3, k=k, decay=decay, oversample=8, salt=seed_salt)
+    Xh = np.zeros((m, p, n3), order="F")
+    for f in range(n3):
+        Xh[:, :, f] = (fac["U"][:, :, f] * fac["sigma"]) @ fac["V"][:, :, f].T
+    X = oracle.inverse_mode3(Xh, oracle.dct2_matrix(n3)).astype(np.float32)
+    return X, fac
+
+
+@pytest.mark.parametrize("shape", [(128, 96, 16), (100, 70, 8), (64, 200, 4)])
+def test_mixed_known_rank_matches_oracle(shape):
+    m, p, n3 = shape
+    k, os_ = 12, 8
+    X, fac = _known_rank_input(m, p, n3, k, 1.0 / 8.0, 1)
+    Xd = to_dev(X)
+    xh = api.transform(Xd, m, p, n3, C.M_DCT2, +1)
+    omega = to_dev(fac["Omega"], np.float32)
+    tr = api.Truncator(m, p, n3, torch.float32, k=k, precision=C.PREC_MIXED, oversample=os_,
+                       power_iters=1, omega=omega)
+    F = tr(xh)
+    U, S, V, ranks, cert, fro, info = _gpu_factors(F, n3)
+    Xh64 = oracle.mode3(X.astype(np.float64), oracle.dct2_matrix(n3))
+    ref = oracle.tsvdm_truncate_faces(Xh64, "fixed", k)
+    assert np.all(ranks == k) and np.all(info == 0)
+    That = reconstruct(U.astype(np.float64), S, V.astype(np.float64), ranks)
+    assert relerr(That, ref["That"]) < 1e-4
+    np.testing.assert_allclose(S[:k], ref["s"][:k], rtol=1e-4)
+    # certificate: the error of the returned factors against the transform-domain data
+    true = np.array([np.linalg.norm(Xh64[:, :, f] - That[:, :, f]) for f in range(n3)])
+    assert np.all(cert >= 0)
+    np.testing.assert_allclose(cert, true, rtol=0.05, atol=2e-6 * np.max(fro))
+    np.testing.assert_allclose(fro, np.sqrt(ref["fro2"]), rtol=1e-5)
+
+
+def test_mixed_truncation_below_rank():
+    """k below the true rank: the kept triplets match the oracle's and the
+    certificate equals the discarded energy."""
+    m, p, n3, r = 96, 80, 6, 20
+    X, fac = _known_rank_input(m, p, n3, r, 1.0 / 8.0, 2)
+    k, os_ = 10, 8
+    g = np.random.default_rng(9)
+    omega = to_dev(g.standard_normal((p, k + os_)), np.float32)
+    xh = api.transform(to_dev(X), m, p, n3, C.M_DCT2, +1)
+    tr = api.Truncator(m, p, n3, torch.float32, k=k, precision=C.PREC_MIXED, oversample=os_,
+                       power_iters=1, omega=omega)
+    F = tr(xh)
+    U, S, V, ranks, cert, fro, info = _gpu_factors(F, n3)
+    Xh64 = oracle.mode3(X.astype(np.float64), oracle.dct2_matrix(n3))
+    ref = oracle.tsvdm_truncate_faces(Xh64, "fixed", k)
+    That = reconstruct(U.astype(np.float64), S, V.astype(np.float64), ranks)
+    # randomized: close to, not equal to, the optimal rank-k truncation
+    err_gpu = np.linalg.norm(Xh64 - That)
+    err_opt = np.linalg.norm(Xh64 - ref["That"])
+    assert err_opt <= err_gpu <= 1.05 * err_opt
+    true = np.array([np.linalg.norm(Xh64[:, :, f] - That[:, :, f]) for f in range(n3)])
+    np.testing.assert_allclose(cert, true, rtol=1e-3)
