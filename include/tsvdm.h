@@ -166,7 +166,8 @@ tsvdm_status tsvdm_check_orthogonal(const double *M_host, int64_t n3, double tol
 tsvdm_status tsvdm_transform(const tsvdm_mdesc *M, int32_t direction, const tsvdm_tensor *in,
                              tsvdm_tensor *out, void *stream);
 
-/* Workspace bytes tsvdm_truncate needs for this input and options. */
+/* Workspace bytes tsvdm_truncate needs for this input and options (only the
+ * shapes are read: data and omega may be NULL).  0 if the arguments are invalid. */
 size_t tsvdm_truncate_workspace_size(const tsvdm_tensor *Xhat, const tsvdm_truncate_opts *opts);
 
 /* Facewise truncated SVD of a dense transform-domain tensor Xhat (the output

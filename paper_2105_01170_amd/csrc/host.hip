@@ -43,12 +43,12 @@ static bool is_dense(const tsvdm_tensor &t) {
     return t.s_a == 1 && t.s_b == t.m && t.s_t == t.m * t.p && t.bsplit == 0;
 }
 
-static tsvdm_status check_tensor(const tsvdm_tensor *t, const char *name) {
+static tsvdm_status check_tensor(const tsvdm_tensor *t, const char *name, bool need_data = true) {
     if (!t) FAIL(TSVDM_EINVAL, "%s is NULL", name);
     if (t->m < 0 || t->p < 0 || t->n3 < 0) FAIL(TSVDM_EINVAL, "%s has a negative dimension", name);
     if (t->dtype < TSVDM_F64 || t->dtype > TSVDM_C128 || t->dtype == TSVDM_BF16)
         FAIL(TSVDM_EINVAL, "%s has unsupported dtype %d", name, t->dtype);
-    if (t->m * t->p * t->n3 > 0 && !t->data) FAIL(TSVDM_EINVAL, "%s->data is NULL", name);
+    if (need_data && t->m * t->p * t->n3 > 0 && !t->data) FAIL(TSVDM_EINVAL, "%s->data is NULL", name);
     if (t->bsplit < 0) FAIL(TSVDM_EINVAL, "%s->bsplit is negative", name);
     if (t->bsplit > 0 && t->p % t->bsplit != 0)
         FAIL(TSVDM_EINVAL, "%s->bsplit (%lld) does not divide p (%lld)", name, (long long)t->bsplit,
@@ -137,9 +137,11 @@ tsvdm_status tsvdm_transform(const tsvdm_mdesc *M, int32_t direction, const tsvd
     return launch_transform(M, direction, in, out, (hipStream_t)stream);
 }
 
-static tsvdm_status check_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o) {
+// need_data = false for the workspace query, which looks at shapes only
+static tsvdm_status check_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
+                                   bool need_data = true) {
     tsvdm_status st;
-    if ((st = check_tensor(X, "Xhat")) != TSVDM_OK) return st;
+    if ((st = check_tensor(X, "Xhat", need_data)) != TSVDM_OK) return st;
     if (!is_dense(*X)) FAIL(TSVDM_EINVAL, "Xhat must be dense (strides 1, m, m*p)");
     if (!o) FAIL(TSVDM_EINVAL, "opts is NULL");
     if (o->rank_mode != TSVDM_RANK_FIXED && o->rank_mode != TSVDM_RANK_ENERGY)
@@ -158,7 +160,7 @@ static tsvdm_status check_truncate(const tsvdm_tensor *X, const tsvdm_truncate_o
         if (ell > X->m || ell > X->p)
             FAIL(TSVDM_EINVAL, "sketch width %d exceeds min(m, p) = %lld", ell,
                  (long long)(X->m < X->p ? X->m : X->p));
-        if (!o->omega) FAIL(TSVDM_EINVAL, "PREC_MIXED needs the test matrix omega");
+        if (need_data && !o->omega) FAIL(TSVDM_EINVAL, "PREC_MIXED needs the test matrix omega");
     } else {
         FAIL(TSVDM_EINVAL, "unknown precision %d", o->precision);
     }
@@ -166,7 +168,7 @@ static tsvdm_status check_truncate(const tsvdm_tensor *X, const tsvdm_truncate_o
 }
 
 size_t tsvdm_truncate_workspace_size(const tsvdm_tensor *X, const tsvdm_truncate_opts *o) {
-    if (check_truncate(X, o) != TSVDM_OK) return 0;
+    if (check_truncate(X, o, false) != TSVDM_OK) return 0;
     if (o->precision == TSVDM_PREC_F64) return jacobi_workspace(X->m, X->p, X->n3, is_cplx(X->dtype));
     return mixed_workspace(X->m, X->p, X->n3, o->k + o->oversample);
 }

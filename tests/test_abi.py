@@ -146,8 +146,13 @@ def test_truncate_validation_and_workspace():
         C.truncate_opts(7, 8, 0.0, C.PREC_MIXED, 8, 1, 0, 1, 0x2000),              # rank mode
         C.truncate_opts(C.RANK_ENERGY, 8, -1.0, C.PREC_MIXED, 8, 1, 0, 1, 0x2000),  # tau < 0
     ]
-    for ob in bad:
-        assert C.tsvdm_truncate_workspace_size(X, ob) == 0
+    # the size query reads shapes only: a missing omega is an error of the call,
+    # not of the query
+    assert C.tsvdm_truncate_workspace_size(X, bad[0]) == ws
+    assert C.tsvdm_truncate_workspace_size(C.dense_tensor(0, 64, 48, 4, C.F32), o) == ws
+    for i, ob in enumerate(bad):
+        if i > 0:
+            assert C.tsvdm_truncate_workspace_size(X, ob) == 0
         with pytest.raises(C.TsvdmError):
             C.tsvdm_truncate(X, ob, F, 0x7000, ws, 0)
     # factor shape and kmax checks
