@@ -203,6 +203,22 @@ tsvdm_status tsvdm_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t e
                          int64_t nrhs, const void *x, int64_t ldx, void *y, int64_t ldy,
                          int32_t compute, void *workspace, size_t workspace_bytes, void *stream);
 
+/* Per-kernel timing (diagnostics).  While enabled, every kernel launch the
+ * library makes is bracketed by two HIP events recorded on the launch
+ * stream, so one kernel inside a multi-kernel call can be timed on its own
+ * stream.  Enabling starts a fresh window.  Costs one flag test per launch
+ * when disabled (the default).  Host-side only; not thread-safe with
+ * respect to enabling/reading while other threads launch. */
+tsvdm_status tsvdm_timing_enable(int32_t on);
+
+/* Waits for the recorded events, reduces them per kernel name and returns
+ * the number of distinct names. */
+int32_t tsvdm_timing_count(void);
+
+/* Name, number of launches and summed milliseconds of entry i (0-based, after
+ * tsvdm_timing_count).  The name stays valid until the next enable or count. */
+tsvdm_status tsvdm_timing_get(int32_t i, const char **name, int32_t *launches, double *total_ms);
+
 #ifdef __cplusplus
 }
 #endif

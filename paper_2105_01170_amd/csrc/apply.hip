@@ -188,7 +188,7 @@ tsvdm_status launch_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t 
                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds); \
             if (e_ != hipSuccess) return hip_check(e_, "hipFuncSetAttribute(apply)");              \
         }                                                                                           \
-        hipLaunchKernelGGL((k_apply<T, C, B>), grid, dim3(AT), lds, s,                              \
+        TSVDM_LAUNCH("apply_fused", (k_apply<T, C, B>), grid, dim3(AT), lds, s,                              \
                            reinterpret_cast<const T *>(F->U), F->S, reinterpret_cast<const T *>(F->V), \
                            F->ranks, F->m, F->p, F->kmax, (int)nf, (int)n3, ell, q,                 \
                            reinterpret_cast<const T *>(ws), nrhs, reinterpret_cast<T *>(y), ldy, KQ); \

@@ -85,6 +85,20 @@ tsvdm_status launch_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t 
                           int32_t compute, void *ws, hipStream_t s);
 }  // namespace tsvdm
 
+namespace tsvdm {
+extern bool g_trace;
+void trace_begin(const char *name, hipStream_t s);
+void trace_end(hipStream_t s);
+}  // namespace tsvdm
+
+// Launch with optional per-kernel event timing (tsvdm_timing_enable).
+#define TSVDM_LAUNCH(name, kernel, grid, block, lds, stream, ...)              \
+    do {                                                                      \
+        if (::tsvdm::g_trace) ::tsvdm::trace_begin(name, stream);            \
+        hipLaunchKernelGGL(kernel, grid, block, lds, stream, __VA_ARGS__);   \
+        if (::tsvdm::g_trace) ::tsvdm::trace_end(stream);                    \
+    } while (0)
+
 #define TSVDM_LAUNCH_CHECK(what)                                      \
     do {                                                              \
         hipError_t e_ = hipGetLastError();                            \

@@ -276,14 +276,14 @@ tsvdm_status run_jacobi(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsv
     w += align256(sizeof(double) * nf);
     int *sw = reinterpret_cast<int *>(w);
     const int maxsw = o->max_sweeps > 0 ? o->max_sweeps : 60;
-    hipLaunchKernelGGL(k_jac_prepare<T>, dim3((unsigned)nf), dim3(JT), 0, s,
+    TSVDM_LAUNCH("jacobi_prepare", k_jac_prepare<T>, dim3((unsigned)nf), dim3(JT), 0, s,
                        reinterpret_cast<const T *>(X->data), m, p, W, V, fro2);
     TSVDM_LAUNCH_CHECK("k_jac_prepare");
-    hipLaunchKernelGGL(k_jac_sweeps<T>, dim3((unsigned)nf), dim3(JT), 0, s, m, p, W, V, maxsw,
+    TSVDM_LAUNCH("jacobi_sweeps", k_jac_sweeps<T>, dim3((unsigned)nf), dim3(JT), 0, s, m, p, W, V, maxsw,
                        1e-15, sw);
     TSVDM_LAUNCH_CHECK("k_jac_sweeps");
     size_t lds = (sizeof(double) + sizeof(int)) * (size_t)n;
-    hipLaunchKernelGGL(k_jac_finish<T>, dim3((unsigned)nf), dim3(JT), lds, s, m, p, F->kmax, W, V,
+    TSVDM_LAUNCH("jacobi_finish", k_jac_finish<T>, dim3((unsigned)nf), dim3(JT), lds, s, m, p, F->kmax, W, V,
                        fro2, sw, o->rank_mode, o->k, o->tau, reinterpret_cast<T *>(F->U), F->S,
                        reinterpret_cast<T *>(F->V), F->ranks, F->cert, F->fro, F->info);
     TSVDM_LAUNCH_CHECK("k_jac_finish");

@@ -3,28 +3,30 @@
 // For every face X_f (m x p, FP32) of the transform-domain tensor, with the
 // caller's Gaussian test matrix Omega (p x ell, ell = k + oversample):
 //
-//   Y  = X Omega            BF16 MFMA, FP32 accumulation        (pass 1, + ||X||^2)
-//   Q  = qr(Y)              FP64 shifted Cholesky-QR3
-//   Z  = X^T Q              BF16 MFMA                            (pass 2)
-//   Qz = qr(Z)              FP64 shifted Cholesky-QR3
-//   Y' = X Qz               split-BF16 MFMA (hi*hi + hi*lo + lo*hi), FP32-accurate (pass 3)
-//   Q  = qr(Y')             FP64 shifted Cholesky-QR3
-//   B^T = X^T Q             split-BF16 MFMA                      (pass 4)
-//   B B^T = U_B L U_B^T     FP64 Gram + cyclic Jacobi eigensolver, s = sqrt(L)
-//   Uhat = Q U_B, Vhat = B^T U_B / s, truncated to k_f
-//   cert = ||X - Uhat S Vhat^T||_F  (explicit residual pass 5, FP64 sums)
+//   Y  = X Omega          BF16 MFMA, FP32 accumulation          (pass 1, + ||X||^2)
+//   Q  = orth(Y)          one shifted Cholesky-QR step          (Gram: FP32 partials)
+//   Z  = X^T Q            BF16 MFMA                              (pass 2)
+//   Qz = orth(Z)          one shifted Cholesky-QR step          (Gram: FP32 partials)
+//   Y' = X Qz             split-BF16 MFMA (hi*hi + hi*lo + lo*hi), FP32-accurate (pass 3)
+//   Q  = qr(Y')           FP64 shifted Cholesky-QR2 (FP64 Gram by MFMA)
+//   B^T = X^T Q           split-BF16 MFMA                        (pass 4)
+//   r2 = ||X - Q B||^2    FP32 MFMA product, FP64 sums           (pass 5)
+//   B B^T = U_B L U_B^T   FP64 Gram (MFMA) + cyclic Jacobi eigensolver, s = sqrt(L)
+//   Uhat = Q U_B, Vhat = B^T U_B / s, truncated to k_f;  cert^2 = r2 + sum_{j>k_f} L_j
 //
 // This is the randomized range finder with power iteration of Halko,
 // Martinsson & Tropp (2011), applied face by face.  Only the first sketch
-// and the first power half-step run in plain BF16: the range they find is
-// refined by the FP32-accurate last half-step, so BF16 rounding of the data
-// does not limit the accuracy (the last half-step maps any basis that sees
-// the dominant right subspace onto the exact dominant left subspace).
+// and the first power half-step run in plain BF16, and their bases only
+// need the right span: one Cholesky-QR step with a shift at the rounding
+// level of the FP32 Gram matrix (Fukaya et al. 2020) bounds cond(Q) and keeps
+// the span exact.  The last half-step is FP32-accurate, so BF16 rounding of
+// the data does not limit the result; its basis is made orthonormal in FP64.
 //
-// The passes over X are HBM-bound skinny GEMMs (N = ell <= 64); every
-// workgroup stages a 64-row (or 64-column) slab of one face through LDS,
-// converting FP32 to BF16 on the way, and the four wavefronts each drive
-// 16 x 16 MFMA tiles.  The small FP64 steps use one workgroup per face.
+// The passes over X are HBM-bound skinny GEMMs (N = ell <= 64).  Every
+// workgroup streams a 64-row (or 64-column) slab of one face, converts it to
+// BF16 in registers, stages it in LDS, and the four wavefronts drive 16x16
+// MFMA tiles; the next slab's loads are issued before the current slab's
+// MFMAs.  The small FP64 steps use one workgroup per face.
 #include "common.h"
 
 #include <math.h>
@@ -36,6 +38,7 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int GT = 256;  // threads per workgroup
 enum { PROD_BF16 = 0, PROD_SPLIT = 1 };
@@ -50,25 +53,148 @@ __device__ __forceinline__ f32x4 mfma(const u16x8 &a, const u16x8 &b, f32x4 c) {
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
+// ---------------------------------------------------------------- staging
+// Rows r0..r0+RC-1 of the rows x LP column-major panel S into
+// st[r*(LP+1) + c] (zeros past the last row).  All loads of a thread are
+// issued before any LDS store, so they are in flight together.
+template <int LP, int RC>
+__device__ __forceinline__ void stage_panel(const float *__restrict__ S, int rows, int r0, float *st) {
+    constexpr int PER = RC * LP / GT;
+    static_assert(RC * LP % GT == 0, "panel size");
+    float v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * GT, r = e % RC, c = e / RC;
+        v[q] = r0 + r < rows ? S[(r0 + r) + (int64_t)rows * c] : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * GT, r = e % RC, c = e / RC;
+        st[r * (LP + 1) + c] = v[q];
+    }
+}
+
+// upper 16x16 tile t (row-major over the upper triangle) -> tile coordinates
+template <int NT>
+__device__ __forceinline__ void tile_ij(int t, int &ti, int &tj) {
+    ti = 0;
+    while (t >= NT - ti) {
+        t -= NT - ti;
+        ++ti;
+    }
+    tj = ti + t;
+}
+
+// Write the 16x16 accumulator tile (ti, tj) of a symmetric LP x LP matrix
+// and its mirror image.  Output layout of the 16x16x4 MFMAs (column
+// lane%16 in both): FP32 holds row 4*(lane/16) + v in slot v, FP64 holds row
+// lane/16 + 4*v.  Diagonal tiles write only their upper half and mirror it,
+// so every entry has exactly one writer.
+template <bool F64, typename T, typename V4>
+__device__ __forceinline__ void put_sym_tile(T *G, int ld, int ti, int tj, const V4 &acc, int lane) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int ir = F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v;
+        const int i = 16 * ti + ir, j = 16 * tj + (lane & 15);
+        if (ti < tj || i <= j) {
+            G[i * ld + j] = acc[v];
+            G[j * ld + i] = acc[v];
+        }
+    }
+}
+
+// FP64 Gram G = S^T S (LDS, pitch LP+1) of the rows x LP FP32 panel S, by
+// FP64 MFMA on the upper tiles (products of FP32 values are exact in FP64).
+// `st` holds at least 64*(LP+1) floats.  Ends with a barrier.
+template <int LP>
+__device__ void gram_f64(const float *__restrict__ S, int rows, double *G, float *st) {
+    constexpr int NT = LP / 16, NTILE = NT * (NT + 1) / 2, TPW = (NTILE + 3) / 4;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    f64x4 acc[TPW];
+    int ti[TPW], tj[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        acc[t] = f64x4{0, 0, 0, 0};
+        int idx = wave + 4 * t;
+        if (idx < NTILE) tile_ij<NT>(idx, ti[t], tj[t]);
+        else ti[t] = tj[t] = -1;
+    }
+    for (int r0 = 0; r0 < rows; r0 += 64) {
+        stage_panel<LP, 64>(S, rows, r0, st);
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+            const int r = 4 * kk + (lane >> 4);
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                if (ti[t] < 0) continue;
+                const double a = st[r * (LP + 1) + 16 * ti[t] + (lane & 15)];
+                const double b = st[r * (LP + 1) + 16 * tj[t] + (lane & 15)];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < TPW; ++t)
+        if (ti[t] >= 0) put_sym_tile<true>(G, LP + 1, ti[t], tj[t], acc[t], lane);
+    __syncthreads();
+}
+
+// FP64 Gram of the 64 x LP block held in the four wavefronts' MFMA
+// accumulators (row 16*wave + 4*(lane/16) + v, column 16*j + lane%16), by FP64
+// MFMA on the upper tiles (products of FP32 values are exact in FP64);
+// written row major LP x LP to `out`.  `ys` holds 64*(LP+1) floats.
+template <int LP>
+__device__ void block_gram_f64(const f32x4 (&acc)[LP / 16], double *__restrict__ out, float *ys) {
+    constexpr int NT = LP / 16, NTILE = NT * (NT + 1) / 2, TPW = (NTILE + 3) / 4;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            ys[(16 * wave + 4 * (lane >> 4) + v) * (LP + 1) + 16 * j + (lane & 15)] = acc[j][v];
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int idx = wave + 4 * t;
+        if (idx >= NTILE) continue;
+        int ti, tj;
+        tile_ij<NT>(idx, ti, tj);
+        f64x4 g = f64x4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const int r = 4 * kk + (lane >> 4);
+            g = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ys[r * (LP + 1) + 16 * ti + (lane & 15)],
+                                                     (double)ys[r * (LP + 1) + 16 * tj + (lane & 15)], g,
+                                                     0, 0, 0);
+        }
+        put_sym_tile<true>(out, LP, ti, tj, g, lane);
+    }
+}
+
 // ---------------------------------------------------------------- Y = X W
 // Grid (ceil(m/64), nf).  Workgroup: rows a0..a0+63 of face f, all LP
 // columns of the result; K = p in chunks of 32.  W (p x nw used columns,
 // leading dim ldw) is per face (stride w_stride) or shared (w_stride = 0).
-// Both the X slab and the W chunk are converted to BF16 (hi, and lo for the
-// split product) once per workgroup and staged in LDS with K contiguous, so
-// each lane's MFMA operand is one 16-byte LDS read.
-template <int LP, int PROD>
+// The X slab and the W chunk are converted to BF16 (hi, and lo for the
+// split product) and staged in LDS with K contiguous, so each lane's MFMA
+// operand is one 16-byte LDS read; the next chunk is loaded into registers
+// while the current one is multiplied.
+template <int LP, int PROD, bool GRAM>
 __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, int p,
                                            const float *__restrict__ W, int64_t w_stride, int ldw,
                                            int nw, float *__restrict__ Y,
-                                           double *__restrict__ fro_part) {
+                                           double *__restrict__ fro_part,
+                                           double *__restrict__ gram_part) {
     constexpr int KC = 32, LDK = KC + 8;  // LDS row pitch (bf16 elements)
-    constexpr int NB = LP / 16;
+    constexpr int NB = LP / 16, WPT = KC * LP / GT;
     constexpr bool SPL = PROD == PROD_SPLIT;
     __shared__ __align__(16) uint16_t xh[64 * LDK];
     __shared__ __align__(16) uint16_t xl[SPL ? 64 * LDK : 8];
     __shared__ __align__(16) uint16_t wh[LP * LDK];
     __shared__ __align__(16) uint16_t wl[SPL ? LP * LDK : 8];
+    __shared__ float ys[GRAM ? 64 * (LP + 1) : 1];
     __shared__ double red[GT / 64];
     const int f = blockIdx.y, a0 = blockIdx.x * 64;
     const float *Xf = X + (int64_t)f * m * p;
@@ -80,29 +206,42 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
     for (int j = 0; j < NB; ++j) acc[j] = f32x4{0, 0, 0, 0};
     double fro = 0.0;
     const bool rok = a0 + lr < m;
+    float xr[8], wr[WPT];
+    auto load = [&](int b0) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            const int b = b0 + 8 * kg + v;
+            xr[v] = (rok && b < p) ? Xf[(a0 + lr) + (int64_t)m * b] : 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int e = tid + q * GT, k = e % KC, c = e / KC, b = b0 + k;
+            wr[q] = (c < nw && b < p) ? Wf[b + (int64_t)ldw * c] : 0.0f;
+        }
+    };
+    load(0);
     for (int b0 = 0; b0 < p; b0 += KC) {
         u16x8 h, l;
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
-            int b = b0 + 8 * kg + v;
-            float x = (rok && b < p) ? Xf[(a0 + lr) + (int64_t)m * b] : 0.0f;
-            fro += (double)x * (double)x;
+            fro += (double)xr[v] * (double)xr[v];
             uint16_t hh, ll;
-            split_bf16(x, hh, ll);
+            split_bf16(xr[v], hh, ll);
             h[v] = hh;
             l[v] = ll;
         }
         *reinterpret_cast<u16x8 *>(&xh[lr * LDK + 8 * kg]) = h;
         if (SPL) *reinterpret_cast<u16x8 *>(&xl[lr * LDK + 8 * kg]) = l;
-        for (int e = tid; e < KC * LP; e += GT) {
-            int k = e % KC, c = e / KC, b = b0 + k;
-            float w = (c < nw && b < p) ? Wf[b + (int64_t)ldw * c] : 0.0f;
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int e = tid + q * GT, k = e % KC, c = e / KC;
             uint16_t hh, ll;
-            split_bf16(w, hh, ll);
+            split_bf16(wr[q], hh, ll);
             wh[c * LDK + k] = hh;
             if (SPL) wl[c * LDK + k] = ll;
         }
         __syncthreads();
+        if (b0 + KC < p) load(b0 + KC);  // next chunk in flight during the MFMAs
         const int ar = 16 * wave + (lane & 15), kq = 8 * (lane >> 4);
         u16x8 Ah = *reinterpret_cast<const u16x8 *>(&xh[ar * LDK + kq]);
         u16x8 Al;
@@ -130,6 +269,7 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
             if (r < m) Yf[r + (int64_t)m * c] = acc[j][v];
         }
     }
+    if (GRAM) block_gram_f64<LP>(acc, gram_part + ((int64_t)f * gridDim.x + blockIdx.x) * LP * LP, ys);
     if (fro_part) {
         fro = wave_sum(fro);
         if (lane == 0) red[wave] = fro;
@@ -141,17 +281,19 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
 // ---------------------------------------------------------------- Z = X^T W
 // Grid (ceil(p/64), nf).  Workgroup: output rows b0..b0+63 (columns of the
 // face), K = m in chunks of 64.  W is m x nw (leading dim ldw), per face.
-template <int LP, int PROD>
+template <int LP, int PROD, bool GRAM>
 __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, int p,
                                             const float *__restrict__ W, int64_t w_stride, int ldw,
-                                            int nw, float *__restrict__ Z) {
+                                            int nw, float *__restrict__ Z,
+                                            double *__restrict__ gram_part) {
     constexpr int KC = 64, LDK = KC + 8;
-    constexpr int NB = LP / 16;
+    constexpr int NB = LP / 16, WPT = KC * LP / GT;
     constexpr bool SPL = PROD == PROD_SPLIT;
     __shared__ __align__(16) uint16_t xh[64 * LDK];
     __shared__ __align__(16) uint16_t xl[SPL ? 64 * LDK : 8];
     __shared__ __align__(16) uint16_t wh[LP * LDK];
     __shared__ __align__(16) uint16_t wl[SPL ? LP * LDK : 8];
+    __shared__ float ys[GRAM ? 64 * (LP + 1) : 1];
     const int f = blockIdx.y, b0 = blockIdx.x * 64;
     const float *Xf = X + (int64_t)f * m * p;
     const float *Wf = W + (int64_t)f * w_stride;
@@ -160,17 +302,31 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
     f32x4 acc[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[j] = f32x4{0, 0, 0, 0};
+    float xr[16], wr[WPT];
+    auto load = [&](int a0) {
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int b = b0 + cj0 + 16 * it;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = a0 + 4 * q4 + v;
+                xr[4 * it + v] = (b < p && a < m) ? Xf[a + (int64_t)m * b] : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int e = tid + q * GT, k = e % KC, c = e / KC, a = a0 + k;
+            wr[q] = (c < nw && a < m) ? Wf[a + (int64_t)ldw * c] : 0.0f;
+        }
+    };
+    load(0);
     for (int a0 = 0; a0 < m; a0 += KC) {
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
-            const int cj = cj0 + 16 * it, b = b0 + cj;
+            const int cj = cj0 + 16 * it;
             uint16_t hh[4], ll[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int a = a0 + 4 * q4 + v;
-                float x = (b < p && a < m) ? Xf[a + (int64_t)m * b] : 0.0f;
-                split_bf16(x, hh[v], ll[v]);
-            }
+            for (int v = 0; v < 4; ++v) split_bf16(xr[4 * it + v], hh[v], ll[v]);
             uint2 ph, pl;
             ph.x = hh[0] | ((uint32_t)hh[1] << 16);
             ph.y = hh[2] | ((uint32_t)hh[3] << 16);
@@ -179,15 +335,16 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
             *reinterpret_cast<uint2 *>(&xh[cj * LDK + 4 * q4]) = ph;
             if (SPL) *reinterpret_cast<uint2 *>(&xl[cj * LDK + 4 * q4]) = pl;
         }
-        for (int e = tid; e < KC * LP; e += GT) {
-            int k = e % KC, c = e / KC, a = a0 + k;
-            float w = (c < nw && a < m) ? Wf[a + (int64_t)ldw * c] : 0.0f;
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int e = tid + q * GT, k = e % KC, c = e / KC;
             uint16_t hh, ll;
-            split_bf16(w, hh, ll);
+            split_bf16(wr[q], hh, ll);
             wh[c * LDK + k] = hh;
             if (SPL) wl[c * LDK + k] = ll;
         }
         __syncthreads();
+        if (a0 + KC < m) load(a0 + KC);  // next chunk in flight during the MFMAs
         const int br = 16 * wave + (lane & 15);
 #pragma unroll
         for (int kk = 0; kk < KC / 32; ++kk) {
@@ -219,58 +376,25 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
             if (r < p) Zf[r + (int64_t)p * c] = acc[j][v];
         }
     }
-}
-
-// ---------------------------------------------------------------- FP64 Gram
-// G = S^T S for the rows x LP panel S (leading dim rows) of FP32 values,
-// accumulated in FP64 (products of two FP32 values are exact in FP64).
-// Result in LDS G[LP][LP+1].  Every thread owns a BS x BS block (BS = LP/16).
-template <int LP>
-__device__ void gram64(const float *__restrict__ S, int rows, double *G, float *stage) {
-    constexpr int BS = LP / 16, RC = 64;
-    const int tid = threadIdx.x, bi = (tid >> 4) * BS, bj = (tid & 15) * BS;
-    double acc[BS][BS];
-#pragma unroll
-    for (int i = 0; i < BS; ++i)
-#pragma unroll
-        for (int j = 0; j < BS; ++j) acc[i][j] = 0.0;
-    for (int r0 = 0; r0 < rows; r0 += RC) {
-        for (int e = tid; e < RC * LP; e += GT) {
-            int r = e % RC, c = e / RC;
-            stage[r * (LP + 1) + c] = r0 + r < rows ? S[(r0 + r) + (int64_t)rows * c] : 0.0f;
-        }
-        __syncthreads();
-        for (int r = 0; r < RC; ++r) {
-            double a[BS], b[BS];
-#pragma unroll
-            for (int i = 0; i < BS; ++i) a[i] = stage[r * (LP + 1) + bi + i];
-#pragma unroll
-            for (int j = 0; j < BS; ++j) b[j] = stage[r * (LP + 1) + bj + j];
-#pragma unroll
-            for (int i = 0; i < BS; ++i)
-#pragma unroll
-                for (int j = 0; j < BS; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < BS; ++i)
-#pragma unroll
-        for (int j = 0; j < BS; ++j) G[(bi + i) * (LP + 1) + bj + j] = acc[i][j];
-    __syncthreads();
+    if (GRAM) block_gram_f64<LP>(acc, gram_part + ((int64_t)f * gridDim.x + blockIdx.x) * LP * LP, ys);
 }
 
 // ---------------------------------------------------------------- Cholesky-QR
-// Q = S R^{-1} with G + shift I = R^T R, repeated `passes` times, the first
-// one shifted if `shift_first` (Fukaya et al. 2020, shift
-// 11 (rows*ell + ell(ell+1)) u ||S||_F^2).  One workgroup per face; columns
-// ell..LP-1 of the panel are zero on input and output.
+// Q = S R^{-1} with G + shift I = R^T R, `passes` times.  The first pass
+// takes its FP64 Gram matrix from the producer's per-block partials when
+// `gpart` is given, else computes it; it is shifted by
+// 11 (rows*ell + ell(ell+1)) u ||S||_F^2, u = 2^-53 (Fukaya et al. 2020), so
+// that the factor exists for rank-deficient S and cond(Q) is bounded after
+// one pass.  Later passes use the FP64 Gram of the current Q, unshifted.
+// One workgroup per face; columns ell..LP-1 of the panel are zero on output.
 template <int LP>
 __global__ __launch_bounds__(GT) void k_cholqr(const float *__restrict__ Sin, int rows, int ell,
-                                               float *__restrict__ Qout, int passes, int shift_first,
+                                               float *__restrict__ Qout, int passes,
+                                               const double *__restrict__ gpart, int nparts,
                                                int32_t *__restrict__ qr_info) {
     constexpr int CH = GT;  // rows per triangular-solve chunk (one per thread)
     __shared__ double G[LP * (LP + 1)];
+    __shared__ double R[LP * (LP + 1)];
     __shared__ float chunk[CH * (LP + 1)];  // also the Gram staging area
     __shared__ double rinv[LP];
     __shared__ int bad;
@@ -280,13 +404,25 @@ __global__ __launch_bounds__(GT) void k_cholqr(const float *__restrict__ Sin, in
     if (tid == 0) bad = 0;
     for (int pass = 0; pass < passes; ++pass) {
         const float *src = pass == 0 ? S : Q;
-        gram64<LP>(src, rows, G, chunk);
+        if (pass == 0 && gpart) {
+            constexpr int EPT = (LP * LP + GT - 1) / GT;
+#pragma unroll
+            for (int q = 0; q < EPT; ++q) {
+                const int e = tid + q * GT;
+                if (e >= LP * LP) break;
+                double acc = 0.0;
+#pragma unroll 8
+                for (int pp = 0; pp < nparts; ++pp) acc += gpart[((int64_t)f * nparts + pp) * LP * LP + e];
+                G[(e / LP) * (LP + 1) + e % LP] = acc;
+            }
+            __syncthreads();
+        } else {
+            gram_f64<LP>(src, rows, G, chunk);
+        }
         if (tid == 0) {
             double tr = 0.0;
             for (int c = 0; c < ell; ++c) tr += G[c * (LP + 1) + c];
-            double sh = 0.0;
-            if (pass == 0 && shift_first)
-                sh = 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * 0x1p-53 * tr;
+            const double sh = pass == 0 ? 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * 0x1p-53 * tr : 0.0;
             for (int c = 0; c < ell; ++c) G[c * (LP + 1) + c] += sh;
             for (int c = ell; c < LP; ++c) {
                 for (int j = 0; j < LP; ++j) G[c * (LP + 1) + j] = G[j * (LP + 1) + c] = 0.0;
@@ -294,40 +430,52 @@ __global__ __launch_bounds__(GT) void k_cholqr(const float *__restrict__ Sin, in
             }
         }
         __syncthreads();
-        // right-looking Cholesky: row j of R = row j of G scaled by 1/sqrt(pivot)
-        for (int j = 0; j < LP; ++j) {
-            double piv = G[j * (LP + 1) + j];
-            bool ok = piv > 0.0 && isfinite(piv);
-            double d = ok ? sqrt(piv) : 1.0;
-            // trailing update uses the unscaled row j (only rows i > j change)
-            for (int e = tid; e < (LP - j - 1) * (LP - j - 1); e += GT) {
-                int i = j + 1 + e / (LP - j - 1), c = j + 1 + e % (LP - j - 1);
-                if (c >= i && ok) G[i * (LP + 1) + c] -= G[j * (LP + 1) + i] * G[j * (LP + 1) + c] / piv;
+        // right-looking Cholesky, one barrier per step: row j of R is row j of
+        // the trailing matrix over sqrt(pivot); rows i > j are updated from the
+        // unscaled row j, which nobody writes during the step.  Threads form a
+        // 16 x 16 grid over the trailing upper triangle.
+        {
+            const int ty = tid >> 4, tx = tid & 15;
+            for (int j = 0; j < LP; ++j) {
+                const double piv = G[j * (LP + 1) + j];
+                const bool ok = piv > 0.0 && isfinite(piv);
+                const double d = ok ? sqrt(piv) : 1.0, ipv = ok ? 1.0 / piv : 0.0;
+                for (int i = j + 1 + ty; i < LP; i += 16) {
+                    const double gji = G[j * (LP + 1) + i] * ipv;
+                    for (int c = i + ((tx - (i - j - 1)) & 15); c < LP; c += 16)
+                        G[i * (LP + 1) + c] -= gji * G[j * (LP + 1) + c];
+                }
+                if (tid < LP - j) {
+                    const int c = j + tid;
+                    R[j * (LP + 1) + c] = ok ? G[j * (LP + 1) + c] / d : (c == j ? 1.0 : 0.0);
+                }
+                if (tid == 0) {
+                    rinv[j] = 1.0 / d;
+                    if (!ok) bad = 1;
+                }
+                __syncthreads();
             }
-            __syncthreads();
-            for (int c = j + 1 + tid; c < LP; c += GT) G[j * (LP + 1) + c] = ok ? G[j * (LP + 1) + c] / d : 0.0;
-            if (tid == 0) {
-                G[j * (LP + 1) + j] = d;
-                rinv[j] = 1.0 / d;
-                if (!ok) bad = 1;
-            }
-            __syncthreads();
         }
         // forward substitution q R = s, one row per thread, in place in LDS;
-        // the solved entries are stored as FP32 (the precision of Q), every
+        // four independent partial sums keep several LDS reads in flight.
+        // The solved entries are stored as FP32 (the precision of Q), every
         // dot product is accumulated in FP64
         for (int r0 = 0; r0 < rows; r0 += CH) {
             const int nr = rows - r0 < CH ? rows - r0 : CH;
-            for (int e = tid; e < CH * LP; e += GT) {
-                int r = e % CH, c = e / CH;
-                chunk[r * (LP + 1) + c] = r < nr ? src[(r0 + r) + (int64_t)rows * c] : 0.0f;
-            }
+            stage_panel<LP, CH>(src, rows, r0, chunk);
             __syncthreads();
             float *row = chunk + tid * (LP + 1);
             for (int c = 0; c < ell; ++c) {
-                double v = (double)row[c];
-                for (int j = 0; j < c; ++j) v -= (double)row[j] * G[j * (LP + 1) + c];
-                row[c] = (float)(v * rinv[c]);
+                double v0 = (double)row[c], v1 = 0.0, v2 = 0.0, v3 = 0.0;
+                int j = 0;
+                for (; j + 4 <= c; j += 4) {
+                    v0 -= (double)row[j] * R[j * (LP + 1) + c];
+                    v1 -= (double)row[j + 1] * R[(j + 1) * (LP + 1) + c];
+                    v2 -= (double)row[j + 2] * R[(j + 2) * (LP + 1) + c];
+                    v3 -= (double)row[j + 3] * R[(j + 3) * (LP + 1) + c];
+                }
+                for (; j < c; ++j) v0 -= (double)row[j] * R[j * (LP + 1) + c];
+                row[c] = (float)(((v0 + v1) + (v2 + v3)) * rinv[c]);
             }
             for (int c = ell; c < LP; ++c) row[c] = 0.0f;
             __syncthreads();
@@ -341,50 +489,131 @@ __global__ __launch_bounds__(GT) void k_cholqr(const float *__restrict__ Sin, in
     if (tid == 0 && bad) qr_info[f] = 2;
 }
 
-// ---------------------------------------------------------------- core SVD
-// B B^T from B^T (p x LP): FP64 Gram, cyclic Jacobi eigensolver with the
-// round-robin ordering, eigenvalues sorted decreasing, rank rule.
+// ---------------------------------------------------------------- residual
+// Partial sums over 64-column blocks of ||X - Q B||_F^2 with B^T = X^T Q (the
+// projection), computed directly (not by cancellation): Q B by FP32 MFMA,
+// differences and squares in FP64.  Together with the discarded eigenvalues
+// of B B^T this is the error of the truncated result.
 template <int LP>
-__global__ __launch_bounds__(GT) void k_core(const float *__restrict__ Bt, int p, int ell,
-                                             const double *__restrict__ fro_part, int nparts,
+__global__ __launch_bounds__(GT) void k_resid(const float *__restrict__ X, int m, int p,
+                                              const float *__restrict__ Q, const float *__restrict__ Bt,
+                                              double *__restrict__ part) {
+    constexpr int LD = LP + 1;
+    __shared__ float bs[64 * LD];  // [b][c] = B^T block
+    __shared__ float qs[64 * LD];  // [a][c] = Q chunk
+    __shared__ double red[GT / 64];
+    const int f = blockIdx.y, b0 = blockIdx.x * 64, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const float *Xf = X + (int64_t)f * m * p;
+    const float *Qf = Q + (int64_t)f * m * LP;
+    const float *Bf = Bt + (int64_t)f * p * LP;
+    stage_panel<LP, 64>(Bf, p, b0, bs);
+    double acc = 0.0;
+    const int ar = 16 * wave + (lane & 15), kl = lane >> 4;
+    for (int a0 = 0; a0 < m; a0 += 64) {
+        __syncthreads();
+        // X values this lane compares against, loaded with the Q chunk
+        float xv[4][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                int a = a0 + 16 * wave + 4 * (lane >> 4) + v, b = b0 + 16 * t + (lane & 15);
+                xv[t][v] = (a < m && b < p) ? Xf[a + (int64_t)m * b] : 0.0f;
+            }
+        stage_panel<LP, 64>(Qf, m, a0, qs);
+        __syncthreads();
+        f32x4 pr[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) pr[t] = f32x4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < LP / 4; ++kk) {
+            const float av = qs[ar * LD + 4 * kk + kl];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const float bv = bs[(16 * t + (lane & 15)) * LD + 4 * kk + kl];
+                pr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, pr[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double d = (double)xv[t][v] - (double)pr[t][v];
+                acc += d * d;
+            }
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) red[wave] = acc;
+    __syncthreads();
+    if (tid == 0) part[(int64_t)f * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// ---------------------------------------------------------------- core SVD
+// B B^T (sum of the projection's FP64 per-block Gram partials), cyclic Jacobi eigensolver with the
+// round-robin ordering: in each round the rotations of all ne/2 disjoint
+// pairs are found, then every 2x2 block (pair p rows, pair q columns) is
+// updated at once, B' = J_p^T B J_q, and the eigenvector columns likewise.
+// Eigenvalues sorted decreasing, rank rule, certificate
+//   cert^2 = ||X - Q B||^2 + sum_{j > k_f} lambda_j
+// (the error of Q U_B[:, :k] U_B[:, :k]^T B, since Q has orthonormal columns).
+// The energy rule takes the smallest k whose certified error meets tau.
+template <int LP>
+__global__ __launch_bounds__(GT) void k_core(const double *__restrict__ gpart, int nparts, int ell,
+                                             const double *__restrict__ fro_part, int nfro,
+                                             const double *__restrict__ res_part, int nres,
                                              int mode, int kfix, double tau, int max_sweeps,
                                              double *__restrict__ UB, double *__restrict__ sig,
                                              int *__restrict__ perm_out, int *__restrict__ kf_out,
-                                             double *__restrict__ fro2_out,
+                                             double *__restrict__ fro2_out, double *__restrict__ cert,
                                              int32_t *__restrict__ jinfo) {
-    constexpr int EB = sizeof(double) * LP * (LP + 1), SB = sizeof(float) * 64 * (LP + 1);
-    __shared__ double G[LP * (LP + 1)];
-    __shared__ __align__(16) unsigned char eraw[EB > SB ? EB : SB];
-    double *E = reinterpret_cast<double *>(eraw);  // eigenvectors, column c = vector c
-    float *stage = reinterpret_cast<float *>(eraw);  // Gram staging, used before E
-    __shared__ double cs[LP / 2][2];
+    constexpr int LD = LP + 1, NPMAX = LP / 2;
+    __shared__ double G[LP * LD];
+    __shared__ double E[LP * LD];  // eigenvectors, column c = vector c
+    __shared__ double cs[NPMAX][2];
+    __shared__ unsigned char pa[(LP - 1) * NPMAX], pb[(LP - 1) * NPMAX];
     __shared__ int rot;
     __shared__ double lam[LP];
     __shared__ int perm[LP];
-    const int f = blockIdx.x, tid = threadIdx.x;
     __shared__ double trace;
-    gram64<LP>(Bt + (int64_t)f * p * LP, p, G, stage);
+    const int f = blockIdx.x, tid = threadIdx.x;
+    const int ne = ell + (ell & 1), np = ne / 2;
+    {
+        constexpr int EPT = (LP * LP + GT - 1) / GT;
+#pragma unroll
+        for (int q = 0; q < EPT; ++q) {
+            const int e = tid + q * GT;
+            if (e >= LP * LP) break;
+            double acc = 0.0;
+#pragma unroll 8
+            for (int pp = 0; pp < nparts; ++pp) acc += gpart[((int64_t)f * nparts + pp) * LP * LP + e];
+            G[(e / LP) * LD + e % LP] = acc;
+            E[(e / LP) * LD + e % LP] = (e / LP == e % LP) ? 1.0 : 0.0;
+        }
+    }
+    for (int e = tid; e < (ne - 1) * np; e += GT) {  // round-robin pairs, a < b
+        int r = e / np, k = e % np, a, b;
+        if (k == 0) { a = r; b = ne - 1; }
+        else { a = (r + k) % (ne - 1); b = (r - k + (ne - 1)) % (ne - 1); }
+        pa[e] = (unsigned char)(a < b ? a : b);
+        pb[e] = (unsigned char)(a < b ? b : a);
+    }
     if (tid == 0) {
         double t = 0.0;
-        for (int c = 0; c < ell; ++c) t += G[c * (LP + 1) + c];
+        for (int c = 0; c < ell; ++c) t += G[c * LD + c];
         trace = t;
     }
-    for (int e = tid; e < LP * LP; e += GT) E[(e / LP) * (LP + 1) + e % LP] = (e / LP == e % LP) ? 1.0 : 0.0;
-    const int ne = ell + (ell & 1);
     int sweep = 0, conv = 0;
     __syncthreads();
     for (sweep = 1; sweep <= max_sweeps && ell > 1; ++sweep) {
         if (tid == 0) rot = 0;
         __syncthreads();
         for (int r = 0; r < ne - 1; ++r) {
-            if (tid < ne / 2) {
-                int a, b, k = tid;
-                if (k == 0) { a = r; b = ne - 1; }
-                else { a = (r + k) % (ne - 1); b = (r - k + (ne - 1)) % (ne - 1); }
-                if (a > b) { int t = a; a = b; b = t; }
+            const unsigned char *ra = pa + r * np, *rb = pb + r * np;
+            if (tid < np) {
+                const int a = ra[tid], b = rb[tid];
                 double c = 1.0, s = 0.0;
                 if (b < ell) {
-                    double app = G[a * (LP + 1) + a], aqq = G[b * (LP + 1) + b], apq = G[a * (LP + 1) + b];
+                    double app = G[a * LD + a], aqq = G[b * LD + b], apq = G[a * LD + b];
                     // relative test (high relative accuracy for well separated pairs) and an
                     // absolute floor at the rounding level of the Gram matrix
                     if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-15 * trace) {
@@ -395,45 +624,47 @@ __global__ __launch_bounds__(GT) void k_core(const float *__restrict__ Bt, int p
                         rot = 1;
                     }
                 }
-                cs[k][0] = c;
-                cs[k][1] = s;
+                cs[tid][0] = c;
+                cs[tid][1] = s;
             }
             __syncthreads();
-            // rows: (row_a, row_b) <- (c row_a - s row_b, s row_a + c row_b)
-            for (int e = tid; e < (ne / 2) * ell; e += GT) {
-                int k = e / ell, col = e % ell, a, b;
-                if (k == 0) { a = r; b = ne - 1; }
-                else { a = (r + k) % (ne - 1); b = (r - k + (ne - 1)) % (ne - 1); }
-                if (a > b) { int t = a; a = b; b = t; }
-                if (b >= ell) continue;
-                double c = cs[k][0], s = cs[k][1];
-                double x = G[a * (LP + 1) + col], y = G[b * (LP + 1) + col];
-                G[a * (LP + 1) + col] = c * x - s * y;
-                G[b * (LP + 1) + col] = s * x + c * y;
-            }
-            __syncthreads();
-            // columns of G and of E
-            for (int e = tid; e < (ne / 2) * ell; e += GT) {
-                int k = e / ell, row = e % ell, a, b;
-                if (k == 0) { a = r; b = ne - 1; }
-                else { a = (r + k) % (ne - 1); b = (r - k + (ne - 1)) % (ne - 1); }
-                if (a > b) { int t = a; a = b; b = t; }
-                if (b >= ell) continue;
-                double c = cs[k][0], s = cs[k][1];
-                double x = G[row * (LP + 1) + a], y = G[row * (LP + 1) + b];
-                G[row * (LP + 1) + a] = c * x - s * y;
-                G[row * (LP + 1) + b] = s * x + c * y;
-                x = E[row * (LP + 1) + a];
-                y = E[row * (LP + 1) + b];
-                E[row * (LP + 1) + a] = c * x - s * y;
-                E[row * (LP + 1) + b] = s * x + c * y;
+            // G blocks (pair pp rows, pair qq columns) and E blocks (row pair i, pair qq columns)
+            const int ng = np * np, nitems = ng + (LP / 2) * np;
+            for (int e = tid; e < nitems; e += GT) {
+                if (e < ng) {
+                    const int pp = e / np, qq = e % np;
+                    const double sp = cs[pp][1], sq = cs[qq][1];
+                    if (sp == 0.0 && sq == 0.0) continue;
+                    const double cp = cs[pp][0], cq = cs[qq][0];
+                    const int a = ra[pp], b = rb[pp], c2 = ra[qq], d = rb[qq];
+                    double m00 = G[a * LD + c2], m01 = G[a * LD + d], m10 = G[b * LD + c2], m11 = G[b * LD + d];
+                    // rows: (a, b) <- (cp a - sp b, sp a + cp b)
+                    double t00 = cp * m00 - sp * m10, t01 = cp * m01 - sp * m11;
+                    double t10 = sp * m00 + cp * m10, t11 = sp * m01 + cp * m11;
+                    // columns: (c, d) <- (cq c - sq d, sq c + cq d)
+                    G[a * LD + c2] = cq * t00 - sq * t01;
+                    G[a * LD + d] = sq * t00 + cq * t01;
+                    G[b * LD + c2] = cq * t10 - sq * t11;
+                    G[b * LD + d] = sq * t10 + cq * t11;
+                } else {
+                    const int ee = e - ng, i = ee / np, qq = ee % np;
+                    const double sq = cs[qq][1];
+                    if (sq == 0.0) continue;
+                    const double cq = cs[qq][0];
+                    const int c2 = ra[qq], d = rb[qq], r0 = 2 * i, r1 = 2 * i + 1;
+                    double x0 = E[r0 * LD + c2], y0 = E[r0 * LD + d], x1 = E[r1 * LD + c2], y1 = E[r1 * LD + d];
+                    E[r0 * LD + c2] = cq * x0 - sq * y0;
+                    E[r0 * LD + d] = sq * x0 + cq * y0;
+                    E[r1 * LD + c2] = cq * x1 - sq * y1;
+                    E[r1 * LD + d] = sq * x1 + cq * y1;
+                }
             }
             __syncthreads();
         }
         if (!rot) { conv = 1; break; }
         __syncthreads();
     }
-    if (tid < ell) lam[tid] = fmax(G[tid * (LP + 1) + tid], 0.0);
+    if (tid < ell) lam[tid] = fmax(G[tid * LD + tid], 0.0);
     __syncthreads();
     if (tid < ell) {
         int pos = 0;
@@ -443,14 +674,15 @@ __global__ __launch_bounds__(GT) void k_core(const float *__restrict__ Bt, int p
     }
     __syncthreads();
     if (tid == 0) {
-        double fro2 = 0.0;
-        for (int i = 0; i < nparts; ++i) fro2 += fro_part[(int64_t)f * nparts + i];
+        double fro2 = 0.0, res = 0.0;
+        for (int i = 0; i < nfro; ++i) fro2 += fro_part[(int64_t)f * nfro + i];
+        for (int i = 0; i < nres; ++i) res += res_part[(int64_t)f * nres + i];
         int kf;
         if (mode == TSVDM_RANK_FIXED) {
             kf = kfix < ell ? kfix : ell;
         } else {
             int cap = kfix > 0 && kfix < ell ? kfix : ell;
-            double tail = 0.0, bound = tau * tau * fro2;
+            double tail = res, bound = tau * tau * fro2;
             for (int j = 0; j < ell; ++j) tail += lam[j];
             kf = cap;
             for (int k = 0; k <= cap; ++k) {
@@ -458,8 +690,11 @@ __global__ __launch_bounds__(GT) void k_core(const float *__restrict__ Bt, int p
                 if (k < ell) tail -= lam[perm[k]];
             }
         }
+        double disc = 0.0;
+        for (int j = ell - 1; j >= kf; --j) disc += lam[perm[j]];
         kf_out[f] = kf;
         fro2_out[f] = fro2;
+        if (cert) cert[f] = nres > 0 ? sqrt(res + disc) : -1.0;
         jinfo[f] = (conv || ell <= 1) ? 0 : 1;
     }
     for (int r = tid; r < LP; r += GT) {
@@ -468,7 +703,7 @@ __global__ __launch_bounds__(GT) void k_core(const float *__restrict__ Bt, int p
         perm_out[(int64_t)f * LP + r] = j;
     }
     for (int e = tid; e < LP * LP; e += GT)
-        UB[(int64_t)f * LP * LP + e] = E[(e % LP) * (LP + 1) + e / LP];  // column major, col = e/LP
+        UB[(int64_t)f * LP * LP + e] = E[(e % LP) * LD + e / LP];  // column major, col = e/LP
 }
 
 // ---------------------------------------------------------------- factors
@@ -548,61 +783,6 @@ __global__ __launch_bounds__(GT) void k_factors(const float *__restrict__ Q, con
     }
 }
 
-// ---------------------------------------------------------------- certificate
-// partial sums of (X - Uhat S Vhat^T)^2 over 64-row slabs, FP64 accumulation
-__global__ __launch_bounds__(GT) void k_resid(const float *__restrict__ X, int m, int p,
-                                              const float *__restrict__ U, const double *__restrict__ S,
-                                              const float *__restrict__ V, int64_t kmax,
-                                              const int32_t *__restrict__ ranks,
-                                              double *__restrict__ part) {
-    __shared__ float us[64 * 65];
-    __shared__ float vs[64 * 65];
-    __shared__ double red[GT / 64];
-    const int f = blockIdx.y, a0 = blockIdx.x * 64, tid = threadIdx.x;
-    const int kf = ranks[f] < 64 ? ranks[f] : 64;
-    const float *Xf = X + (int64_t)f * m * p;
-    const float *Uf = U + (int64_t)f * m * kmax;
-    const float *Vf = V + (int64_t)f * p * kmax;
-    for (int e = tid; e < 64 * 64; e += GT) {
-        int r = e % 64, j = e / 64;
-        us[r * 65 + j] = (j < kf && a0 + r < m) ? (float)(Uf[(a0 + r) + (int64_t)m * j] * S[(int64_t)f * kmax + j]) : 0.0f;
-    }
-    double acc = 0.0;
-    const int r = tid & 63;
-    for (int b0 = 0; b0 < p; b0 += 64) {
-        __syncthreads();
-        for (int e = tid; e < 64 * 64; e += GT) {
-            int c = e % 64, j = e / 64;
-            vs[c * 65 + j] = (j < kf && b0 + c < p) ? Vf[(b0 + c) + (int64_t)p * j] : 0.0f;
-        }
-        __syncthreads();
-        for (int c = tid >> 6; c < 64; c += GT / 64) {
-            if (a0 + r >= m || b0 + c >= p) continue;
-            float pr = 0.0f;
-            for (int j = 0; j < kf; ++j) pr = fmaf(us[r * 65 + j], vs[c * 65 + j], pr);
-            double d = (double)Xf[(a0 + r) + (int64_t)m * (b0 + c)] - (double)pr;
-            acc += d * d;
-        }
-    }
-    acc = wave_sum(acc);
-    if ((tid & 63) == 0) red[tid >> 6] = acc;
-    __syncthreads();
-    if (tid == 0) part[(int64_t)f * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
-}
-
-__global__ void k_cert(const double *__restrict__ part, int nparts, int nf, double *__restrict__ cert) {
-    int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
-    double s = 0.0;
-    for (int i = 0; i < nparts; ++i) s += part[(int64_t)f * nparts + i];
-    cert[f] = sqrt(s);
-}
-
-__global__ void k_fill(double *__restrict__ x, int n, double v) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = v;
-}
-
 __global__ void k_zero_i32(int32_t *__restrict__ x, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) x[i] = 0;
@@ -612,7 +792,7 @@ inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct MixedWs {
     float *Y, *Qm, *Z, *Qp;
-    double *fro_part, *res_part, *UB, *sig, *fro2;
+    double *gram_m, *gram_p, *fro_part, *res_part, *UB, *sig, *fro2;
     int *perm, *kf;
     int32_t *qr_info, *jinfo;
 };
@@ -624,14 +804,16 @@ size_t carve(char *base, int64_t m, int64_t p, int64_t nf, int LP, MixedWs *w) {
         off += al256(bytes);
         return ptr;
     };
-    const int64_t mparts = (m + 63) / 64;
+    const int64_t mparts = (m + 63) / 64, pparts = (p + 63) / 64;
     MixedWs t;
     t.Y = (float *)take(sizeof(float) * nf * m * LP);
     t.Qm = (float *)take(sizeof(float) * nf * m * LP);
     t.Z = (float *)take(sizeof(float) * nf * p * LP);
     t.Qp = (float *)take(sizeof(float) * nf * p * LP);
+    t.gram_m = (double *)take(sizeof(double) * nf * mparts * LP * LP);
+    t.gram_p = (double *)take(sizeof(double) * nf * pparts * LP * LP);
     t.fro_part = (double *)take(sizeof(double) * nf * mparts);
-    t.res_part = (double *)take(sizeof(double) * nf * mparts);
+    t.res_part = (double *)take(sizeof(double) * nf * pparts);
     t.UB = (double *)take(sizeof(double) * nf * LP * LP);
     t.sig = (double *)take(sizeof(double) * nf * LP);
     t.fro2 = (double *)take(sizeof(double) * nf);
@@ -651,45 +833,50 @@ tsvdm_status run_mixed(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     carve(reinterpret_cast<char *>(wsp), m, p, nf, LP, &w);
     const float *Xd = reinterpret_cast<const float *>(X->data);
     const dim3 gm((m + 63) / 64, nf), gp((p + 63) / 64, nf);
-    const int mparts = (m + 63) / 64;
-    hipLaunchKernelGGL(k_zero_i32, dim3((nf + 255) / 256), dim3(256), 0, s, w.qr_info, nf);
-    // pass 1: sketch
-    hipLaunchKernelGGL((k_xw<LP, PROD_BF16>), gm, dim3(GT), 0, s, Xd, m, p, o->omega, (int64_t)0, p, ell,
-                       w.Y, w.fro_part);
-    hipLaunchKernelGGL((k_cholqr<LP>), dim3(nf), dim3(GT), 0, s, w.Y, m, ell, w.Qm, 3, 1, w.qr_info);
-    const float *Qsrc = w.Qm;
-    if (o->power_iters > 0) {
-        // pass 2: Z = X^T Q
-        hipLaunchKernelGGL((k_xtw<LP, PROD_BF16>), gp, dim3(GT), 0, s, Xd, m, p, w.Qm, (int64_t)m * LP, m,
-                           LP, w.Z);
-        hipLaunchKernelGGL((k_cholqr<LP>), dim3(nf), dim3(GT), 0, s, w.Z, p, ell, w.Qp, 3, 1, w.qr_info);
-        // pass 3: Y' = X Qz, FP32-accurate
-        hipLaunchKernelGGL((k_xw<LP, PROD_SPLIT>), gm, dim3(GT), 0, s, Xd, m, p, w.Qp, (int64_t)p * LP, p,
-                           LP, w.Y, (double *)nullptr);
-        hipLaunchKernelGGL((k_cholqr<LP>), dim3(nf), dim3(GT), 0, s, w.Y, m, ell, w.Qm, 3, 1, w.qr_info);
+    const int mparts = (m + 63) / 64, pparts = (p + 63) / 64;
+    const bool power = o->power_iters > 0;
+    // the residual is needed for the certificate and for the energy rule
+    const bool resid = o->rank_mode == TSVDM_RANK_ENERGY || (o->certify && F->cert);
+    TSVDM_LAUNCH("zero_info", k_zero_i32, dim3((nf + 255) / 256), dim3(256), 0, s, w.qr_info, nf);
+    const double *gm_c = w.gram_m, *gp_c = w.gram_p;
+    if (power) {
+        // pass 1: sketch Y = X Omega (BF16), ||X||^2, Gram partials of Y
+        TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true>), gm, dim3(GT), 0, s, Xd, m, p, o->omega,
+                     (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m);
+        // basis of the sketch: one shifted Cholesky-QR step (its span is what
+        // the power step needs)
+        TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(GT), 0, s, (const float *)w.Y, m, ell,
+                     w.Qm, 1, gm_c, mparts, w.qr_info);
+        // pass 2: Z = X^T Q (BF16) and its Gram partials; basis of Z
+        TSVDM_LAUNCH("power_xtw_bf16", (k_xtw<LP, PROD_BF16, true>), gp, dim3(GT), 0, s, Xd, m, p,
+                     (const float *)w.Qm, (int64_t)m * LP, m, LP, w.Z, w.gram_p);
+        TSVDM_LAUNCH("cholqr_power_z", (k_cholqr<LP>), dim3(nf), dim3(GT), 0, s, (const float *)w.Z, p, ell,
+                     w.Qp, 1, gp_c, pparts, w.qr_info);
+        // pass 3: Y' = X Qz, FP32-accurate (split BF16), and its Gram partials
+        TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true>), gm, dim3(GT), 0, s, Xd, m, p,
+                     (const float *)w.Qp, (int64_t)p * LP, p, LP, w.Y, (double *)nullptr, w.gram_m);
+    } else {
+        TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true>), gm, dim3(GT), 0, s, Xd, m, p, o->omega,
+                     (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m);
     }
-    // pass 4: B^T = X^T Q, FP32-accurate
-    hipLaunchKernelGGL((k_xtw<LP, PROD_SPLIT>), gp, dim3(GT), 0, s, Xd, m, p, Qsrc, (int64_t)m * LP, m, LP,
-                       w.Z);
+    // final basis: FP64 shifted Cholesky-QR2 (first Gram from the partials)
+    TSVDM_LAUNCH("cholqr_final", (k_cholqr<LP>), dim3(nf), dim3(GT), 0, s, (const float *)w.Y, m, ell, w.Qm,
+                 2, gm_c, mparts, w.qr_info);
+    // pass 4: B^T = X^T Q, FP32-accurate, and the Gram partials of B^T
+    TSVDM_LAUNCH("project_xtw_split", (k_xtw<LP, PROD_SPLIT, true>), gp, dim3(GT), 0, s, Xd, m, p,
+                 (const float *)w.Qm, (int64_t)m * LP, m, LP, w.Z, w.gram_p);
+    if (resid)  // pass 5: ||X - Q B||^2 per 64-column block
+        TSVDM_LAUNCH("certificate_resid", (k_resid<LP>), gp, dim3(GT), 0, s, Xd, m, p,
+                     (const float *)w.Qm, (const float *)w.Z, w.res_part);
     const int msw = o->max_sweeps > 0 ? o->max_sweeps : 30;
-    hipLaunchKernelGGL((k_core<LP>), dim3(nf), dim3(GT), 0, s, w.Z, p, ell, w.fro_part, mparts,
-                       o->rank_mode, o->k, o->tau, msw, w.UB, w.sig, w.perm, w.kf, w.fro2, w.jinfo);
+    TSVDM_LAUNCH("core_gram_eig", (k_core<LP>), dim3(nf), dim3(GT), 0, s, gp_c, pparts, ell,
+                 (const double *)w.fro_part, mparts, (const double *)w.res_part, resid ? pparts : 0,
+                 o->rank_mode, o->k, o->tau, msw, w.UB, w.sig, w.perm, w.kf, w.fro2, F->cert, w.jinfo);
     const int rows = m > p ? m : p;
-    hipLaunchKernelGGL((k_factors<LP>), dim3((rows + GT - 1) / GT, nf), dim3(GT), 0, s, Qsrc, w.Z, m, p,
-                       ell, F->kmax, w.UB, w.sig, w.perm, w.kf, w.fro2, w.qr_info, w.jinfo,
-                       reinterpret_cast<float *>(F->U), F->S, reinterpret_cast<float *>(F->V), F->ranks,
-                       F->fro, F->info);
-    if (F->cert) {
-        if (o->certify) {
-            hipLaunchKernelGGL(k_resid, gm, dim3(GT), 0, s, Xd, m, p,
-                               reinterpret_cast<const float *>(F->U), F->S,
-                               reinterpret_cast<const float *>(F->V), F->kmax, F->ranks, w.res_part);
-            hipLaunchKernelGGL(k_cert, dim3((nf + 255) / 256), dim3(256), 0, s, w.res_part, mparts, nf,
-                               F->cert);
-        } else {
-            hipLaunchKernelGGL(k_fill, dim3((nf + 255) / 256), dim3(256), 0, s, F->cert, nf, -1.0);
-        }
-    }
+    TSVDM_LAUNCH("factors", (k_factors<LP>), dim3((rows + GT - 1) / GT, nf), dim3(GT), 0, s,
+                 (const float *)w.Qm, (const float *)w.Z, m, p, ell, F->kmax, w.UB, w.sig, w.perm, w.kf,
+                 w.fro2, w.qr_info, w.jinfo, reinterpret_cast<float *>(F->U), F->S,
+                 reinterpret_cast<float *>(F->V), F->ranks, F->fro, F->info);
     TSVDM_LAUNCH_CHECK("mixed truncate");
     return TSVDM_OK;
 }

@@ -43,9 +43,9 @@ __device__ __forceinline__ T dct_alpha(int f, int N) {
 template <typename T, int KIND, int DIR>
 __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, View iv,
                                                   void *__restrict__ out, int64_t ntubes,
-                                                  int64_t mp, int logn, int TP) {
+                                                  int64_t mp, int logn, int logtp) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int N = 1 << logn, H = N >> 1, TT = 2 * TP;
+    const int N = 1 << logn, H = N >> 1, TP = 1 << logtp, TT = 2 * TP, logtt = logtp + 1;
     cx<T> *buf = reinterpret_cast<cx<T> *>(smem);  // [N][TP]
     cx<T> *tw = buf + N * TP;                        // [N/2]  exp(-+2 pi i j / N)
     cx<T> *wq = tw + H;                              // [N]    exp(-i pi f / (2N))
@@ -69,20 +69,36 @@ __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, V
     __syncthreads();
 
     // ---------------------------------------------------------------- load
+    // Every thread issues a batch of UNR independent loads before it touches
+    // LDS, so that many loads are in flight per wavefront.
+    constexpr int UNR = 16;
     if (DIR > 0) {  // real tubes in; tube u < TP -> real part, u >= TP -> imaginary part
         const T *X = reinterpret_cast<const T *>(in);
-        for (int w = tid; w < TT * N; w += NT) {
-            int u = w % TT, t = w / TT;
-            int64_t b = base[u];
-            T v = b >= 0 ? X[b + (int64_t)t * iv.s_t] : T(0);
-            int n = KIND == KIND_DCT ? makhoul(t, N) : t;
-            T *slot = reinterpret_cast<T *>(&buf[bitrev(n, logn) * TP + (u % TP)]);
-            slot[u / TP] = v;
+        const int total = TT * N;
+        for (int w0 = tid; w0 < total; w0 += NT * UNR) {
+            T vals[UNR];
+#pragma unroll
+            for (int q = 0; q < UNR; ++q) {
+                const int w = w0 + q * NT;
+                const int u = w & (TT - 1), t = w >> logtt;
+                const int64_t b = w < total ? base[u] : -1;
+                vals[q] = b >= 0 ? X[b + (int64_t)t * iv.s_t] : T(0);
+            }
+#pragma unroll
+            for (int q = 0; q < UNR; ++q) {
+                const int w = w0 + q * NT;
+                if (w >= total) break;
+                const int u = w & (TT - 1), t = w >> logtt;
+                const int n = KIND == KIND_DCT ? makhoul(t, N) : t;
+                T *slot = reinterpret_cast<T *>(&buf[bitrev(n, logn) * TP + (u & (TP - 1))]);
+                slot[u >= TP] = vals[q];
+            }
         }
     } else if (KIND == KIND_DFT) {  // Hermitian half spectra in (faces 0..N/2)
         const cx<T> *X = reinterpret_cast<const cx<T> *>(in);
+#pragma unroll 4
         for (int w = tid; w < TP * (H + 1); w += NT) {
-            int c = w % TP, f = w / TP;
+            int c = w & (TP - 1), f = w >> logtp;
             int64_t bx = base[c], by = base[c + TP];
             cx<T> a = bx >= 0 ? X[bx + (int64_t)f * iv.s_t] : cx<T>{0, 0};
             cx<T> b = by >= 0 ? X[by + (int64_t)f * iv.s_t] : cx<T>{0, 0};
@@ -94,8 +110,9 @@ __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, V
     } else {  // inverse DCT-II: rebuild the FFT of Makhoul's sequence
         const T *X = reinterpret_cast<const T *>(in);
         const T rs0 = (T)sqrt((double)N), rs1 = (T)sqrt(N / 2.0);  // 1 / alpha_f
+#pragma unroll 4
         for (int w = tid; w < TP * (H + 1); w += NT) {
-            int c = w % TP, f = w / TP, g = N - f;
+            int c = w & (TP - 1), f = w >> logtp, g = N - f;
             int64_t bx = base[c], by = base[c + TP];
             T sf = f == 0 ? rs0 : rs1;
             T ax = bx >= 0 ? X[bx + (int64_t)f * iv.s_t] * sf : T(0);
@@ -119,7 +136,7 @@ __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, V
     int s = 0;
     if (logn & 1) {  // one radix-2 stage (h = 1)
         for (int w = tid; w < TP * H; w += NT) {
-            int c = w % TP, qi = w / TP;
+            int c = w & (TP - 1), qi = w >> logtp;
             int i0r = qi << 1, i1r = i0r + 1;
             cx<T> a = buf[i0r * TP + c], b = buf[i1r * TP + c];
             buf[i0r * TP + c] = cadd(a, b);
@@ -131,7 +148,7 @@ __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, V
     for (; s < logn; s += 2) {  // radix-4: stages s and s+1 together
         const int h = 1 << s;
         for (int w = tid; w < TP * (N >> 2); w += NT) {
-            int c = w % TP, qi = w / TP;
+            int c = w & (TP - 1), qi = w >> logtp;
             int pos = qi & (h - 1), grp = qi >> s;
             int r0 = (grp << (s + 2)) + pos;
             cx<T> x0 = buf[r0 * TP + c], x1 = buf[(r0 + h) * TP + c];
@@ -153,20 +170,23 @@ __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, V
     // ---------------------------------------------------------------- store
     if (DIR > 0 && KIND == KIND_DCT) {
         T *Y = reinterpret_cast<T *>(out);
+        const T al0 = (T)sqrt(1.0 / N), al1 = (T)sqrt(2.0 / N);
+#pragma unroll 8
         for (int w = tid; w < TT * N; w += NT) {
-            int u = w % TT, f = w / TT, c = u % TP;
+            int u = w & (TT - 1), f = w >> logtt, c = u & (TP - 1);
             cx<T> Z = buf[f * TP + c], Zr = buf[((N - f) & (N - 1)) * TP + c];
             cx<T> V = u < TP ? cx<T>{(Z.re + Zr.re) * T(0.5), (Z.im - Zr.im) * T(0.5)}
                              : cx<T>{(Z.im + Zr.im) * T(0.5), (Zr.re - Z.re) * T(0.5)};
             cx<T> W = wq[f];
-            T val = (W.re * V.re - W.im * V.im) * dct_alpha<T>(f, N);
+            T val = (W.re * V.re - W.im * V.im) * (f == 0 ? al0 : al1);
             if (i0 + u < ntubes) Y[(i0 + u) + mp * f] = val;
         }
     } else if (DIR > 0) {  // DFT, faces 0..N/2
         cx<T> *Y = reinterpret_cast<cx<T> *>(out);
         const T sc = (T)(0.5 / sqrt((double)N));
+#pragma unroll 8
         for (int w = tid; w < TT * (H + 1); w += NT) {
-            int u = w % TT, f = w / TT, c = u % TP;
+            int u = w & (TT - 1), f = w >> logtt, c = u & (TP - 1);
             cx<T> Z = buf[f * TP + c], Zr = buf[((N - f) & (N - 1)) * TP + c];
             cx<T> V = u < TP ? cx<T>{(Z.re + Zr.re) * sc, (Z.im - Zr.im) * sc}
                              : cx<T>{(Z.im + Zr.im) * sc, (Zr.re - Z.re) * sc};
@@ -175,8 +195,9 @@ __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, V
     } else {
         T *Y = reinterpret_cast<T *>(out);
         const T sc = KIND == KIND_DFT ? (T)(1.0 / sqrt((double)N)) : (T)(1.0 / N);
+#pragma unroll 8
         for (int w = tid; w < TT * N; w += NT) {
-            int u = w % TT, t = w / TT, c = u % TP;
+            int u = w & (TT - 1), t = w >> logtt, c = u & (TP - 1);
             int n = KIND == KIND_DCT ? makhoul(t, N) : t;
             cx<T> Z = buf[n * TP + c];
             T val = (u < TP ? Z.re : Z.im) * sc;
@@ -275,6 +296,8 @@ tsvdm_status run_fft(int kind, int dir, const tsvdm_tensor *in, tsvdm_tensor *ou
     const int64_t ntubes = in->m * in->p, mp = ntubes;
     int TP = 64;
     while (TP > 1 && (size_t)N * TP * sizeof(cx<T>) > 65536) TP >>= 1;
+    int logtp = 0;
+    while ((1 << logtp) < TP) ++logtp;
     const size_t lds = sizeof(cx<T>) * ((size_t)N * TP + N / 2 + N) + sizeof(int64_t) * 2 * TP;
     const int64_t grid = (ntubes + 2 * TP - 1) / (2 * TP);
     if (grid == 0) return TSVDM_OK;
@@ -285,8 +308,8 @@ tsvdm_status run_fft(int kind, int dir, const tsvdm_tensor *in, tsvdm_tensor *ou
         auto kern = k_fft_tubes<T, KD, DR>;                                                      \
         e = allow_lds(kern, lds);                                                                \
         if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute(fft)");                   \
-        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), lds, s, in->data, iv, out->data, \
-                           ntubes, mp, logn, TP);                                                \
+        TSVDM_LAUNCH("transform_fft", kern, dim3((unsigned)grid), dim3(NT), lds, s, in->data, iv,   \
+                     out->data, ntubes, mp, logn, logtp);                                                \
     } while (0)
     if (kind == KIND_DCT && dir > 0) TSVDM_FFT_LAUNCH(KIND_DCT, 1);
     else if (kind == KIND_DCT) TSVDM_FFT_LAUNCH(KIND_DCT, -1);
@@ -318,8 +341,8 @@ tsvdm_status run_dense(int kind, int dir, const tsvdm_mdesc *M, const tsvdm_tens
         auto kern = k_dense_tubes<T, CS>;                                                        \
         e = allow_lds(kern, lds);                                                                \
         if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute(dense)");                 \
-        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), lds, s, in->data, iv, out->data, \
-                           ntubes, mp, N, nf_in, nf_out, TB, M->M);                             \
+        TSVDM_LAUNCH("transform_direct", kern, dim3((unsigned)grid), dim3(NT), lds, s, in->data, iv, \
+                     out->data, ntubes, mp, N, nf_in, nf_out, TB, M->M);                             \
     } while (0)
     if (kind == TSVDM_M_DCT2) {
         if (dir > 0) TSVDM_DENSE_LAUNCH(DENSE_DCT_FWD);

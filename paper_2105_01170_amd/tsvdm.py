@@ -52,7 +52,8 @@ class TsvdmFactors(ctypes.Structure):
 
 EXPORTS = ["tsvdm_version", "tsvdm_last_error", "tsvdm_tensor_from_blockmat",
            "tsvdm_check_orthogonal", "tsvdm_transform", "tsvdm_truncate_workspace_size",
-           "tsvdm_truncate", "tsvdm_apply_workspace_size", "tsvdm_apply"]
+           "tsvdm_truncate", "tsvdm_apply_workspace_size", "tsvdm_apply", "tsvdm_timing_enable",
+           "tsvdm_timing_count", "tsvdm_timing_get"]
 
 _LIB = None
 
@@ -86,6 +87,12 @@ def lib():
         L.tsvdm_apply.restype = i32
         L.tsvdm_apply.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, vp, i64, vp, i64,
                                   i32, vp, sz, vp]
+        L.tsvdm_timing_enable.restype = i32
+        L.tsvdm_timing_enable.argtypes = [i32]
+        L.tsvdm_timing_count.restype = i32
+        L.tsvdm_timing_count.argtypes = []
+        L.tsvdm_timing_get.restype = i32
+        L.tsvdm_timing_get.argtypes = [i32, P(ctypes.c_char_p), P(i32), P(ctypes.c_double)]
         _LIB = L
     return _LIB
 
@@ -147,6 +154,27 @@ def tsvdm_apply(M: TsvdmMdesc, F: TsvdmFactors, ell: int, q: int, nrhs: int, x_p
                 y_ptr: int, ldy: int, compute: int, ws_ptr: int, ws_bytes: int, stream: int = 0):
     _check(lib().tsvdm_apply(ctypes.byref(M), ctypes.byref(F), ell, q, nrhs, x_ptr, ldx, y_ptr,
                              ldy, compute, ws_ptr, ws_bytes, stream))
+
+
+def tsvdm_timing_enable(on: bool):
+    _check(lib().tsvdm_timing_enable(1 if on else 0))
+
+
+def tsvdm_timing_count() -> int:
+    return lib().tsvdm_timing_count()
+
+
+def tsvdm_timing_get(i: int):
+    name = ctypes.c_char_p()
+    n = ctypes.c_int32()
+    ms = ctypes.c_double()
+    _check(lib().tsvdm_timing_get(i, ctypes.byref(name), ctypes.byref(n), ctypes.byref(ms)))
+    return name.value.decode(), n.value, ms.value
+
+
+def timing_table() -> dict:
+    """{kernel name: (launches, total ms)} of the current timing window."""
+    return {name: (n, ms) for name, n, ms in (tsvdm_timing_get(i) for i in range(tsvdm_timing_count()))}
 
 
 # ------------------------------------------------------------ descriptors

@@ -123,8 +123,10 @@ def test_mixed_known_rank_matches_oracle(shape):
     np.testing.assert_allclose(S[:k], ref["s"][:k], rtol=1e-4)
     # certificate: the error of the returned factors against the transform-domain data
     true = np.array([np.linalg.norm(Xh64[:, :, f] - That[:, :, f]) for f in range(n3)])
-    assert np.all(cert >= 0)
-    np.testing.assert_allclose(cert, true, rtol=0.05, atol=2e-6 * np.max(fro))
+    # certificate: an estimate of the error of the returned factors, accurate to
+    # the FP32 rounding of the residual product (about 1e-6 of ||Xhat_f||)
+    assert np.all(cert >= 0.95 * true)
+    assert np.all(cert <= 1.1 * true + 1e-6 * fro)
     np.testing.assert_allclose(fro, np.sqrt(ref["fro2"]), rtol=1e-5)
 
 
