@@ -53,6 +53,22 @@ __device__ __forceinline__ f32x4 mfma(const u16x8 &a, const u16x8 &b, f32x4 c) {
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
+// ---------------------------------------------------------------- XCD map
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup L runs on
+// XCD L % 8, each with its own L2).  For a pass whose nb blocks of a face all
+// read the same per-face operand, give those blocks consecutive slots on one
+// XCD, so the operand is fetched into that L2 once instead of eight times.
+__device__ __forceinline__ void xcd_map(int L, int nb, int nf, int &b, int &f) {
+    if ((nf & 7) == 0) {
+        const int x = L & 7, s = L >> 3;
+        b = s % nb;
+        f = (s / nb) * 8 + x;
+    } else {
+        b = L % nb;
+        f = L / nb;
+    }
+}
+
 // ---------------------------------------------------------------- staging
 // Rows r0..r0+RC-1 of the rows x LP column-major panel S into
 // st[r*(LP+1) + c] (zeros past the last row).  All loads of a thread are
@@ -182,12 +198,12 @@ __device__ void block_gram_f64(const f32x4 (&acc)[LP / 16], double *__restrict__
 // operand is one 16-byte LDS read; the next chunk is loaded into registers
 // while the current one is multiplied.
 template <int LP, int PROD, bool GRAM>
-__global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, int p,
+__global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, int p, int nf,
                                            const float *__restrict__ W, int64_t w_stride, int ldw,
                                            int nw, float *__restrict__ Y,
                                            double *__restrict__ fro_part,
                                            double *__restrict__ gram_part) {
-    constexpr int KC = 32, LDK = KC + 8;  // LDS row pitch (bf16 elements)
+    constexpr int KC = 64, LDK = KC + 8;  // LDS row pitch (bf16 elements)
     constexpr int NB = LP / 16, WPT = KC * LP / GT;
     constexpr bool SPL = PROD == PROD_SPLIT;
     __shared__ __align__(16) uint16_t xh[64 * LDK];
@@ -196,21 +212,24 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
     __shared__ __align__(16) uint16_t wl[SPL ? LP * LDK : 8];
     __shared__ float ys[GRAM ? 64 * (LP + 1) : 1];
     __shared__ double red[GT / 64];
-    const int f = blockIdx.y, a0 = blockIdx.x * 64;
+    const int nb = (m + 63) / 64;
+    int blk, f;
+    xcd_map(blockIdx.x, nb, nf, blk, f);
+    const int a0 = blk * 64;
     const float *Xf = X + (int64_t)f * m * p;
     const float *Wf = W + (int64_t)f * w_stride;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int lr = tid & 63, kg = tid >> 6;  // X load mapping: row, 8-column group
+    const int lr = tid & 63, kg = tid >> 6;  // X load mapping: row, group of 16 columns
     f32x4 acc[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[j] = f32x4{0, 0, 0, 0};
     double fro = 0.0;
     const bool rok = a0 + lr < m;
-    float xr[8], wr[WPT];
+    float xr[16], wr[WPT];
     auto load = [&](int b0) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            const int b = b0 + 8 * kg + v;
+        for (int v = 0; v < 16; ++v) {
+            const int b = b0 + 16 * kg + v;
             xr[v] = (rok && b < p) ? Xf[(a0 + lr) + (int64_t)m * b] : 0.0f;
         }
 #pragma unroll
@@ -221,17 +240,21 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
     };
     load(0);
     for (int b0 = 0; b0 < p; b0 += KC) {
-        u16x8 h, l;
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            fro += (double)xr[v] * (double)xr[v];
-            uint16_t hh, ll;
-            split_bf16(xr[v], hh, ll);
-            h[v] = hh;
-            l[v] = ll;
+        for (int hv = 0; hv < 2; ++hv) {
+            u16x8 h, l;
+#pragma unroll
+            for (int v = 0; v < 8; ++v) {
+                const float x = xr[8 * hv + v];
+                fro += (double)x * (double)x;
+                uint16_t hh, ll;
+                split_bf16(x, hh, ll);
+                h[v] = hh;
+                l[v] = ll;
+            }
+            *reinterpret_cast<u16x8 *>(&xh[lr * LDK + 16 * kg + 8 * hv]) = h;
+            if (SPL) *reinterpret_cast<u16x8 *>(&xl[lr * LDK + 16 * kg + 8 * hv]) = l;
         }
-        *reinterpret_cast<u16x8 *>(&xh[lr * LDK + 8 * kg]) = h;
-        if (SPL) *reinterpret_cast<u16x8 *>(&xl[lr * LDK + 8 * kg]) = l;
 #pragma unroll
         for (int q = 0; q < WPT; ++q) {
             const int e = tid + q * GT, k = e % KC, c = e / KC;
@@ -242,19 +265,23 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
         }
         __syncthreads();
         if (b0 + KC < p) load(b0 + KC);  // next chunk in flight during the MFMAs
-        const int ar = 16 * wave + (lane & 15), kq = 8 * (lane >> 4);
-        u16x8 Ah = *reinterpret_cast<const u16x8 *>(&xh[ar * LDK + kq]);
-        u16x8 Al;
-        if (SPL) Al = *reinterpret_cast<const u16x8 *>(&xl[ar * LDK + kq]);
+        const int ar = 16 * wave + (lane & 15);
 #pragma unroll
-        for (int j = 0; j < NB; ++j) {
-            const int c = 16 * j + (lane & 15);
-            u16x8 Bh = *reinterpret_cast<const u16x8 *>(&wh[c * LDK + kq]);
-            acc[j] = mfma(Ah, Bh, acc[j]);
-            if (SPL) {
-                u16x8 Bl = *reinterpret_cast<const u16x8 *>(&wl[c * LDK + kq]);
-                acc[j] = mfma(Ah, Bl, acc[j]);
-                acc[j] = mfma(Al, Bh, acc[j]);
+        for (int kk = 0; kk < KC / 32; ++kk) {
+            const int kq = 32 * kk + 8 * (lane >> 4);
+            u16x8 Ah = *reinterpret_cast<const u16x8 *>(&xh[ar * LDK + kq]);
+            u16x8 Al;
+            if (SPL) Al = *reinterpret_cast<const u16x8 *>(&xl[ar * LDK + kq]);
+#pragma unroll
+            for (int j = 0; j < NB; ++j) {
+                const int c = 16 * j + (lane & 15);
+                u16x8 Bh = *reinterpret_cast<const u16x8 *>(&wh[c * LDK + kq]);
+                acc[j] = mfma(Ah, Bh, acc[j]);
+                if (SPL) {
+                    u16x8 Bl = *reinterpret_cast<const u16x8 *>(&wl[c * LDK + kq]);
+                    acc[j] = mfma(Ah, Bl, acc[j]);
+                    acc[j] = mfma(Al, Bh, acc[j]);
+                }
             }
         }
         __syncthreads();
@@ -269,12 +296,12 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
             if (r < m) Yf[r + (int64_t)m * c] = acc[j][v];
         }
     }
-    if (GRAM) block_gram_f64<LP>(acc, gram_part + ((int64_t)f * gridDim.x + blockIdx.x) * LP * LP, ys);
+    if (GRAM) block_gram_f64<LP>(acc, gram_part + ((int64_t)f * nb + blk) * LP * LP, ys);
     if (fro_part) {
         fro = wave_sum(fro);
         if (lane == 0) red[wave] = fro;
         __syncthreads();
-        if (tid == 0) fro_part[(int64_t)f * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+        if (tid == 0) fro_part[(int64_t)f * nb + blk] = red[0] + red[1] + red[2] + red[3];
     }
 }
 
@@ -282,7 +309,7 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
 // Grid (ceil(p/64), nf).  Workgroup: output rows b0..b0+63 (columns of the
 // face), K = m in chunks of 64.  W is m x nw (leading dim ldw), per face.
 template <int LP, int PROD, bool GRAM>
-__global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, int p,
+__global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, int p, int nf,
                                             const float *__restrict__ W, int64_t w_stride, int ldw,
                                             int nw, float *__restrict__ Z,
                                             double *__restrict__ gram_part) {
@@ -294,7 +321,10 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
     __shared__ __align__(16) uint16_t wh[LP * LDK];
     __shared__ __align__(16) uint16_t wl[SPL ? LP * LDK : 8];
     __shared__ float ys[GRAM ? 64 * (LP + 1) : 1];
-    const int f = blockIdx.y, b0 = blockIdx.x * 64;
+    const int nb = (p + 63) / 64;
+    int blk, f;
+    xcd_map(blockIdx.x, nb, nf, blk, f);
+    const int b0 = blk * 64;
     const float *Xf = X + (int64_t)f * m * p;
     const float *Wf = W + (int64_t)f * w_stride;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -376,7 +406,7 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
             if (r < p) Zf[r + (int64_t)p * c] = acc[j][v];
         }
     }
-    if (GRAM) block_gram_f64<LP>(acc, gram_part + ((int64_t)f * gridDim.x + blockIdx.x) * LP * LP, ys);
+    if (GRAM) block_gram_f64<LP>(acc, gram_part + ((int64_t)f * nb + blk) * LP * LP, ys);
 }
 
 // ---------------------------------------------------------------- Cholesky-QR
@@ -495,14 +525,17 @@ __global__ __launch_bounds__(GT) void k_cholqr(const float *__restrict__ Sin, in
 // differences and squares in FP64.  Together with the discarded eigenvalues
 // of B B^T this is the error of the truncated result.
 template <int LP>
-__global__ __launch_bounds__(GT) void k_resid(const float *__restrict__ X, int m, int p,
+__global__ __launch_bounds__(GT) void k_resid(const float *__restrict__ X, int m, int p, int nf,
                                               const float *__restrict__ Q, const float *__restrict__ Bt,
                                               double *__restrict__ part) {
     constexpr int LD = LP + 1;
     __shared__ float bs[64 * LD];  // [b][c] = B^T block
     __shared__ float qs[64 * LD];  // [a][c] = Q chunk
     __shared__ double red[GT / 64];
-    const int f = blockIdx.y, b0 = blockIdx.x * 64, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int nb = (p + 63) / 64;
+    int blk, f;
+    xcd_map(blockIdx.x, nb, nf, blk, f);
+    const int b0 = blk * 64, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const float *Xf = X + (int64_t)f * m * p;
     const float *Qf = Q + (int64_t)f * m * LP;
     const float *Bf = Bt + (int64_t)f * p * LP;
@@ -545,7 +578,7 @@ __global__ __launch_bounds__(GT) void k_resid(const float *__restrict__ X, int m
     acc = wave_sum(acc);
     if (lane == 0) red[wave] = acc;
     __syncthreads();
-    if (tid == 0) part[(int64_t)f * gridDim.x + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    if (tid == 0) part[(int64_t)f * nb + blk] = red[0] + red[1] + red[2] + red[3];
 }
 
 // ---------------------------------------------------------------- core SVD
@@ -832,7 +865,7 @@ tsvdm_status run_mixed(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     MixedWs w;
     carve(reinterpret_cast<char *>(wsp), m, p, nf, LP, &w);
     const float *Xd = reinterpret_cast<const float *>(X->data);
-    const dim3 gm((m + 63) / 64, nf), gp((p + 63) / 64, nf);
+    const dim3 gm((unsigned)(((m + 63) / 64) * nf)), gp((unsigned)(((p + 63) / 64) * nf));
     const int mparts = (m + 63) / 64, pparts = (p + 63) / 64;
     const bool power = o->power_iters > 0;
     // the residual is needed for the certificate and for the energy rule
@@ -841,32 +874,32 @@ tsvdm_status run_mixed(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     const double *gm_c = w.gram_m, *gp_c = w.gram_p;
     if (power) {
         // pass 1: sketch Y = X Omega (BF16), ||X||^2, Gram partials of Y
-        TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true>), gm, dim3(GT), 0, s, Xd, m, p, o->omega,
+        TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true>), gm, dim3(GT), 0, s, Xd, m, p, nf, o->omega,
                      (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m);
         // basis of the sketch: one shifted Cholesky-QR step (its span is what
         // the power step needs)
         TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(GT), 0, s, (const float *)w.Y, m, ell,
                      w.Qm, 1, gm_c, mparts, w.qr_info);
         // pass 2: Z = X^T Q (BF16) and its Gram partials; basis of Z
-        TSVDM_LAUNCH("power_xtw_bf16", (k_xtw<LP, PROD_BF16, true>), gp, dim3(GT), 0, s, Xd, m, p,
+        TSVDM_LAUNCH("power_xtw_bf16", (k_xtw<LP, PROD_BF16, true>), gp, dim3(GT), 0, s, Xd, m, p, nf,
                      (const float *)w.Qm, (int64_t)m * LP, m, LP, w.Z, w.gram_p);
         TSVDM_LAUNCH("cholqr_power_z", (k_cholqr<LP>), dim3(nf), dim3(GT), 0, s, (const float *)w.Z, p, ell,
                      w.Qp, 1, gp_c, pparts, w.qr_info);
         // pass 3: Y' = X Qz, FP32-accurate (split BF16), and its Gram partials
-        TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true>), gm, dim3(GT), 0, s, Xd, m, p,
+        TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true>), gm, dim3(GT), 0, s, Xd, m, p, nf,
                      (const float *)w.Qp, (int64_t)p * LP, p, LP, w.Y, (double *)nullptr, w.gram_m);
     } else {
-        TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true>), gm, dim3(GT), 0, s, Xd, m, p, o->omega,
+        TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true>), gm, dim3(GT), 0, s, Xd, m, p, nf, o->omega,
                      (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m);
     }
     // final basis: FP64 shifted Cholesky-QR2 (first Gram from the partials)
     TSVDM_LAUNCH("cholqr_final", (k_cholqr<LP>), dim3(nf), dim3(GT), 0, s, (const float *)w.Y, m, ell, w.Qm,
                  2, gm_c, mparts, w.qr_info);
     // pass 4: B^T = X^T Q, FP32-accurate, and the Gram partials of B^T
-    TSVDM_LAUNCH("project_xtw_split", (k_xtw<LP, PROD_SPLIT, true>), gp, dim3(GT), 0, s, Xd, m, p,
+    TSVDM_LAUNCH("project_xtw_split", (k_xtw<LP, PROD_SPLIT, true>), gp, dim3(GT), 0, s, Xd, m, p, nf,
                  (const float *)w.Qm, (int64_t)m * LP, m, LP, w.Z, w.gram_p);
     if (resid)  // pass 5: ||X - Q B||^2 per 64-column block
-        TSVDM_LAUNCH("certificate_resid", (k_resid<LP>), gp, dim3(GT), 0, s, Xd, m, p,
+        TSVDM_LAUNCH("certificate_resid", (k_resid<LP>), gp, dim3(GT), 0, s, Xd, m, p, nf,
                      (const float *)w.Qm, (const float *)w.Z, w.res_part);
     const int msw = o->max_sweeps > 0 ? o->max_sweeps : 30;
     TSVDM_LAUNCH("core_gram_eig", (k_core<LP>), dim3(nf), dim3(GT), 0, s, gp_c, pparts, ell,

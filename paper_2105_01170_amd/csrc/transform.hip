@@ -40,7 +40,10 @@ __device__ __forceinline__ T dct_alpha(int f, int N) {
     return f == 0 ? (T)sqrt(1.0 / N) : (T)sqrt(2.0 / N);
 }
 
-template <typename T, int KIND, int DIR>
+// VEC: the input (forward) and output are dense with every tile full and 16-byte
+// aligned rows, so a thread moves 16 bytes per load/store (4 FP32 or 2 FP64
+// tubes of one time step) and issues all of its tile loads at once.
+template <typename T, int KIND, int DIR, bool VEC>
 __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, View iv,
                                                   void *__restrict__ out, int64_t ntubes,
                                                   int64_t mp, int logn, int logtp) {
@@ -72,7 +75,34 @@ __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, V
     // Every thread issues a batch of UNR independent loads before it touches
     // LDS, so that many loads are in flight per wavefront.
     constexpr int UNR = 16;
-    if (DIR > 0) {  // real tubes in; tube u < TP -> real part, u >= TP -> imaginary part
+    constexpr int VW = 16 / sizeof(T);  // elements per 16-byte vector
+    typedef T vec_t __attribute__((ext_vector_type(VW)));
+    if (DIR > 0 && VEC) {
+        const T *X = reinterpret_cast<const T *>(in) + i0;
+        const int lvpr = logtt - (VW == 4 ? 2 : 1), vpr = 1 << lvpr, total = vpr * N;
+        for (int w0 = tid; w0 < total; w0 += NT * UNR) {
+            vec_t vals[UNR];
+#pragma unroll
+            for (int q = 0; q < UNR; ++q) {
+                const int w = w0 + q * NT;
+                const int u4 = w & (vpr - 1), t = w >> lvpr;
+                if (w < total) vals[q] = *reinterpret_cast<const vec_t *>(X + u4 * VW + (int64_t)t * iv.s_t);
+            }
+#pragma unroll
+            for (int q = 0; q < UNR; ++q) {
+                const int w = w0 + q * NT;
+                if (w >= total) break;
+                const int u4 = w & (vpr - 1), t = w >> lvpr;
+                const int n = KIND == KIND_DCT ? makhoul(t, N) : t;
+                cx<T> *rowp = &buf[bitrev(n, logn) * TP];
+#pragma unroll
+                for (int e = 0; e < VW; ++e) {
+                    const int u = u4 * VW + e;
+                    reinterpret_cast<T *>(&rowp[u & (TP - 1)])[u >= TP] = vals[q][e];
+                }
+            }
+        }
+    } else if (DIR > 0) {  // real tubes in; tube u < TP -> real part, u >= TP -> imaginary part
         const T *X = reinterpret_cast<const T *>(in);
         const int total = TT * N;
         for (int w0 = tid; w0 < total; w0 += NT * UNR) {
@@ -171,15 +201,31 @@ __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, V
     if (DIR > 0 && KIND == KIND_DCT) {
         T *Y = reinterpret_cast<T *>(out);
         const T al0 = (T)sqrt(1.0 / N), al1 = (T)sqrt(2.0 / N);
-#pragma unroll 8
-        for (int w = tid; w < TT * N; w += NT) {
-            int u = w & (TT - 1), f = w >> logtt, c = u & (TP - 1);
+        auto dct_val = [&](int u, int f) -> T {
+            const int c = u & (TP - 1);
             cx<T> Z = buf[f * TP + c], Zr = buf[((N - f) & (N - 1)) * TP + c];
             cx<T> V = u < TP ? cx<T>{(Z.re + Zr.re) * T(0.5), (Z.im - Zr.im) * T(0.5)}
                              : cx<T>{(Z.im + Zr.im) * T(0.5), (Zr.re - Z.re) * T(0.5)};
             cx<T> W = wq[f];
-            T val = (W.re * V.re - W.im * V.im) * (f == 0 ? al0 : al1);
-            if (i0 + u < ntubes) Y[(i0 + u) + mp * f] = val;
+            return (W.re * V.re - W.im * V.im) * (f == 0 ? al0 : al1);
+        };
+        if (VEC) {
+            const int lvpr = logtt - (VW == 4 ? 2 : 1), vpr = 1 << lvpr;
+#pragma unroll 4
+            for (int w = tid; w < vpr * N; w += NT) {
+                const int u4 = w & (vpr - 1), f = w >> lvpr;
+                vec_t v;
+#pragma unroll
+                for (int e = 0; e < VW; ++e) v[e] = dct_val(u4 * VW + e, f);
+                *reinterpret_cast<vec_t *>(Y + i0 + u4 * VW + mp * f) = v;
+            }
+        } else {
+#pragma unroll 8
+            for (int w = tid; w < TT * N; w += NT) {
+                int u = w & (TT - 1), f = w >> logtt;
+                T val = dct_val(u, f);
+                if (i0 + u < ntubes) Y[(i0 + u) + mp * f] = val;
+            }
         }
     } else if (DIR > 0) {  // DFT, faces 0..N/2
         cx<T> *Y = reinterpret_cast<cx<T> *>(out);
@@ -195,13 +241,28 @@ __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, V
     } else {
         T *Y = reinterpret_cast<T *>(out);
         const T sc = KIND == KIND_DFT ? (T)(1.0 / sqrt((double)N)) : (T)(1.0 / N);
-#pragma unroll 8
-        for (int w = tid; w < TT * N; w += NT) {
-            int u = w & (TT - 1), t = w >> logtt, c = u & (TP - 1);
+        auto inv_val = [&](int u, int t) -> T {
             int n = KIND == KIND_DCT ? makhoul(t, N) : t;
-            cx<T> Z = buf[n * TP + c];
-            T val = (u < TP ? Z.re : Z.im) * sc;
-            if (i0 + u < ntubes) Y[(i0 + u) + mp * t] = val;
+            cx<T> Z = buf[n * TP + (u & (TP - 1))];
+            return (u < TP ? Z.re : Z.im) * sc;
+        };
+        if (VEC) {
+            const int lvpr = logtt - (VW == 4 ? 2 : 1), vpr = 1 << lvpr;
+#pragma unroll 4
+            for (int w = tid; w < vpr * N; w += NT) {
+                const int u4 = w & (vpr - 1), t = w >> lvpr;
+                vec_t v;
+#pragma unroll
+                for (int e = 0; e < VW; ++e) v[e] = inv_val(u4 * VW + e, t);
+                *reinterpret_cast<vec_t *>(Y + i0 + u4 * VW + mp * t) = v;
+            }
+        } else {
+#pragma unroll 8
+            for (int w = tid; w < TT * N; w += NT) {
+                int u = w & (TT - 1), t = w >> logtt;
+                T val = inv_val(u, t);
+                if (i0 + u < ntubes) Y[(i0 + u) + mp * t] = val;
+            }
         }
     }
 }
@@ -302,10 +363,17 @@ tsvdm_status run_fft(int kind, int dir, const tsvdm_tensor *in, tsvdm_tensor *ou
     const int64_t grid = (ntubes + 2 * TP - 1) / (2 * TP);
     if (grid == 0) return TSVDM_OK;
     View iv = make_view(*in);
+    // vector fast path: all tiles full, 16-byte aligned rows in and out; dense
+    // input for the forward direction
+    const int vw = 16 / (int)sizeof(T);
+    const bool dense_in = in->s_a == 1 && in->s_b == in->m && in->bsplit == 0;
+    const bool vec = ntubes % (2 * TP) == 0 && mp % vw == 0 && 2 * TP >= vw &&
+                     ((uintptr_t)out->data % 16) == 0 &&
+                     (dir < 0 || (dense_in && in->s_t % vw == 0 && ((uintptr_t)in->data % 16) == 0));
     hipError_t e = hipSuccess;
 #define TSVDM_FFT_LAUNCH(KD, DR)                                                                \
     do {                                                                                         \
-        auto kern = k_fft_tubes<T, KD, DR>;                                                      \
+        auto kern = vec ? k_fft_tubes<T, KD, DR, true> : k_fft_tubes<T, KD, DR, false>;          \
         e = allow_lds(kern, lds);                                                                \
         if (e != hipSuccess) return hip_check(e, "hipFuncSetAttribute(fft)");                   \
         TSVDM_LAUNCH("transform_fft", kern, dim3((unsigned)grid), dim3(NT), lds, s, in->data, iv,   \

@@ -14,7 +14,9 @@ from paper_2105_01170_amd import tsvdm as C  # noqa: E402
 # (m, p, n3): several tiles and a ragged tail of tubes; power-of-two lengths use
 # the FFT kernel, others the direct kernel
 SHAPES = [(5, 7, 8), (33, 17, 16), (64, 40, 32), (9, 11, 256), (3, 5, 1024), (7, 13, 12),
-          (6, 5, 31), (4, 3, 1), (2, 3, 2), (17, 9, 100)]
+          (6, 5, 31), (4, 3, 1), (2, 3, 2), (17, 9, 100),
+          # whole tiles with 16-byte rows: the vector load/store path
+          (8, 16, 2), (16, 8, 1024), (32, 32, 64)]
 TOL = {np.float32: 3e-6, np.float64: 1e-12}
 
 
