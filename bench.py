@@ -145,6 +145,8 @@ def main():
     n_dom, ms_dom = table[dom]
     avg_s = ms_dom / n_dom / 1e3
     bound, amount = work.get(dom, ("hbm", float("nan")))
+    # the step's work for a kernel is split over its launches (one per face group)
+    amount = amount * args.steps / n_dom
     if bound == "hbm":
         roof = {"bound": "hbm", "achieved": amount / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     else:
@@ -159,7 +161,7 @@ def main():
     for name, (n, ms) in table.items():
         b, amt = work.get(name, (None, None))
         if b == "hbm":
-            gbs = amt / (ms / n / 1e3) / 1e9
+            gbs = amt * args.steps / n / (ms / n / 1e3) / 1e9
             passes[name] = round(gbs / HBM_PEAK_GBS, 4)
 
     # comparator: the plain FP64 GPU t-SVDM of the same input at k = 32

@@ -58,6 +58,68 @@ __device__ __forceinline__ f32x4 mfma(const u16x8 &a, const u16x8 &b, f32x4 c) {
 // XCD L % 8, each with its own L2).  For a pass whose nb blocks of a face all
 // read the same per-face operand, give those blocks consecutive slots on one
 // XCD, so the operand is fetched into that L2 once instead of eight times.
+// 1/a for a > 0 normal: hardware reciprocal refined by two Newton steps
+// (error within an ulp or two; used for Cholesky multipliers, where that is
+// below the rounding of the update itself)
+__device__ __forceinline__ double recip(double a) {
+    double r = __builtin_amdgcn_rcp(a);
+    double e = fma(-a, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-a, r, 1.0);
+    return fma(r, e, r);
+}
+
+// 1/sqrt(a) for a > 0 normal: hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rsqrt_nr(double a) {
+    double y = __builtin_amdgcn_rsq(a);
+    double e = fma(-a * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-a * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+// G (LDS, pitch ldg) = ordered sum over pp of the nparts LP x LP row-major
+// FP64 partials of face f.  All loads of a block of 8 partials are issued
+// before any is summed (clamped addresses, zero-selected, no branches).
+template <int LP, int NTH>
+__device__ __forceinline__ void load_gram_partials(const double *__restrict__ gpart, int f, int nparts,
+                                                   double *G, int ldg) {
+    constexpr int N2 = LP * LP / 2, E2 = (N2 + NTH - 1) / NTH, PB = 8;
+    const int tid = threadIdx.x;
+    const double2 *g2 = reinterpret_cast<const double2 *>(gpart + (int64_t)f * nparts * LP * LP);
+    double2 acc[E2];
+#pragma unroll
+    for (int q = 0; q < E2; ++q) acc[q] = double2{0.0, 0.0};
+    for (int p0 = 0; p0 < nparts; p0 += PB) {
+        double2 v[E2][PB];
+#pragma unroll
+        for (int q = 0; q < E2; ++q)
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                const int e2 = tid + q * NTH, pp = p0 + u;
+                const bool in = e2 < N2 && pp < nparts;
+                const double2 t = g2[(int64_t)(pp < nparts ? pp : nparts - 1) * N2 + (e2 < N2 ? e2 : 0)];
+                v[q][u] = in ? t : double2{0.0, 0.0};
+            }
+#pragma unroll
+        for (int q = 0; q < E2; ++q)
+#pragma unroll
+            for (int u = 0; u < PB; ++u) {
+                acc[q].x += v[q][u].x;
+                acc[q].y += v[q][u].y;
+            }
+    }
+#pragma unroll
+    for (int q = 0; q < E2; ++q) {
+        const int e2 = tid + q * NTH;
+        if (e2 < N2) {
+            const int r = (2 * e2) / LP, c = (2 * e2) % LP;
+            G[r * ldg + c] = acc[q].x;
+            G[r * ldg + c + 1] = acc[q].y;
+        }
+    }
+}
+
 __device__ __forceinline__ void xcd_map(int L, int nb, int nf, int &b, int &f) {
     if ((nf & 7) == 0) {
         const int x = L & 7, s = L >> 3;
@@ -117,44 +179,6 @@ __device__ __forceinline__ void put_sym_tile(T *G, int ld, int ti, int tj, const
             G[j * ld + i] = acc[v];
         }
     }
-}
-
-// FP64 Gram G = S^T S (LDS, pitch LP+1) of the rows x LP FP32 panel S, by
-// FP64 MFMA on the upper tiles (products of FP32 values are exact in FP64).
-// `st` holds at least 64*(LP+1) floats.  Ends with a barrier.
-template <int LP>
-__device__ void gram_f64(const float *__restrict__ S, int rows, double *G, float *st) {
-    constexpr int NT = LP / 16, NTILE = NT * (NT + 1) / 2, TPW = (NTILE + 3) / 4;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    f64x4 acc[TPW];
-    int ti[TPW], tj[TPW];
-#pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-        acc[t] = f64x4{0, 0, 0, 0};
-        int idx = wave + 4 * t;
-        if (idx < NTILE) tile_ij<NT>(idx, ti[t], tj[t]);
-        else ti[t] = tj[t] = -1;
-    }
-    for (int r0 = 0; r0 < rows; r0 += 64) {
-        stage_panel<LP, 64>(S, rows, r0, st);
-        __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < 16; ++kk) {
-            const int r = 4 * kk + (lane >> 4);
-#pragma unroll
-            for (int t = 0; t < TPW; ++t) {
-                if (ti[t] < 0) continue;
-                const double a = st[r * (LP + 1) + 16 * ti[t] + (lane & 15)];
-                const double b = st[r * (LP + 1) + 16 * tj[t] + (lane & 15)];
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int t = 0; t < TPW; ++t)
-        if (ti[t] >= 0) put_sym_tile<true>(G, LP + 1, ti[t], tj[t], acc[t], lane);
-    __syncthreads();
 }
 
 // FP64 Gram of the 64 x LP block held in the four wavefronts' MFMA
@@ -410,108 +434,191 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
 }
 
 // ---------------------------------------------------------------- Cholesky-QR
-// Q = S R^{-1} with G + shift I = R^T R, `passes` times.  The first pass
-// takes its FP64 Gram matrix from the producer's per-block partials when
-// `gpart` is given, else computes it; it is shifted by
-// 11 (rows*ell + ell(ell+1)) u ||S||_F^2, u = 2^-53 (Fukaya et al. 2020), so
-// that the factor exists for rank-deficient S and cond(Q) is bounded after
-// one pass.  Later passes use the FP64 Gram of the current Q, unshifted.
-// One workgroup per face; columns ell..LP-1 of the panel are zero on output.
+// Orthonormal basis Q (rows x LP, FP32, columns >= ell zero) of the rows x ell
+// panel S by shifted Cholesky-QR (Fukaya et al. 2020): G = S^T S (+ shift on
+// the first pass), R = chol(G), Q = S R^{-1}; `passes` = 2 repeats the step on
+// Q (Cholesky-QR2).  One workgroup per face, QT threads, one row per thread:
+//  * the first Gram is the sum of the per-64-row-block partials written by the
+//    GEMM pass that produced S (all loads of a block of 8 partials in flight);
+//  * the Cholesky factorisation is right-looking with one barrier per column,
+//    every thread loading its operands of a step before it writes any;
+//  * the triangular solve runs in registers, fully unrolled, with R^T read by
+//    LDS broadcast; the row is solved in FP64 and stored as FP32;
+//  * the Gram of the first pass's Q, for the second pass, comes from those FP32
+//    rows staged in LDS (FP64 MFMA), so the second pass reads nothing from HBM
+//    when the panel fits in one chunk of QT rows.
+constexpr int QT = 512;
+
 template <int LP>
-__global__ __launch_bounds__(GT) void k_cholqr(const float *__restrict__ Sin, int rows, int ell,
+__global__ __launch_bounds__(QT) void k_cholqr(const float *__restrict__ Sin, int rows, int ell,
                                                float *__restrict__ Qout, int passes,
                                                const double *__restrict__ gpart, int nparts,
                                                int32_t *__restrict__ qr_info) {
-    constexpr int CH = GT;  // rows per triangular-solve chunk (one per thread)
-    __shared__ double G[LP * (LP + 1)];
-    __shared__ double R[LP * (LP + 1)];
-    __shared__ float chunk[CH * (LP + 1)];  // also the Gram staging area
+    constexpr int LDG = LP + 1, LDR = LP + 2, LDS_ = LP + 1, HR = LP <= 48 ? QT : QT / 2;
+    constexpr int NT = LP / 16, NTILE = NT * (NT + 1) / 2, TPW = (NTILE + 7) / 8;
+    __shared__ double G[LP * LDG];
+    __shared__ __align__(16) double Rt[LP * LDR];  // Rt[c * LDR + j] = R[j][c]
     __shared__ double rinv[LP];
+    __shared__ float st[HR * LDS_];  // FP32 rows of the chunk (or half of it) for the Gram
+    __shared__ double trace_s;
     __shared__ int bad;
-    const int f = blockIdx.x, tid = threadIdx.x;
+    const int f = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const float *S = Sin + (int64_t)f * rows * LP;
     float *Q = Qout + (int64_t)f * rows * LP;
     if (tid == 0) bad = 0;
+
+    // ---- first Gram: ordered sum of the partials
+    load_gram_partials<LP, QT>(gpart, f, nparts, G, LDG);
+    __syncthreads();
+
+    const int nch = (rows + QT - 1) / QT;
+    float x[LP];
     for (int pass = 0; pass < passes; ++pass) {
-        const float *src = pass == 0 ? S : Q;
-        if (pass == 0 && gpart) {
-            constexpr int EPT = (LP * LP + GT - 1) / GT;
-#pragma unroll
-            for (int q = 0; q < EPT; ++q) {
-                const int e = tid + q * GT;
-                if (e >= LP * LP) break;
-                double acc = 0.0;
-#pragma unroll 8
-                for (int pp = 0; pp < nparts; ++pp) acc += gpart[((int64_t)f * nparts + pp) * LP * LP + e];
-                G[(e / LP) * (LP + 1) + e % LP] = acc;
+        // ---- shift of the first pass: 11 (rows*ell + ell(ell+1)) u tr(G), u = 2^-53
+        if (pass == 0) {
+            if (wave == 0) {
+                double t = 0.0;
+                for (int c = lane; c < ell; c += 64) t += G[c * LDG + c];
+                t = wave_sum(t);
+                if (lane == 0) trace_s = t;
             }
             __syncthreads();
-        } else {
-            gram_f64<LP>(src, rows, G, chunk);
+            const double sh = 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * 0x1p-53 * trace_s;
+            if (tid < ell) G[tid * LDG + tid] += sh;
+            __syncthreads();
         }
-        if (tid == 0) {
-            double tr = 0.0;
-            for (int c = 0; c < ell; ++c) tr += G[c * (LP + 1) + c];
-            const double sh = pass == 0 ? 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * 0x1p-53 * tr : 0.0;
-            for (int c = 0; c < ell; ++c) G[c * (LP + 1) + c] += sh;
-            for (int c = ell; c < LP; ++c) {
-                for (int j = 0; j < LP; ++j) G[c * (LP + 1) + j] = G[j * (LP + 1) + c] = 0.0;
-                G[c * (LP + 1) + c] = 1.0;
-            }
-        }
-        __syncthreads();
-        // right-looking Cholesky, one barrier per step: row j of R is row j of
-        // the trailing matrix over sqrt(pivot); rows i > j are updated from the
-        // unscaled row j, which nobody writes during the step.  Threads form a
-        // 16 x 16 grid over the trailing upper triangle.
+        // ---- Cholesky of the leading ell x ell block.  Step j subtracts the
+        // outer product of row j over the pivot from the rows below; row j of
+        // the trailing matrix is final after step j, so the rows of R
+        // (row j / sqrt(pivot j)) are formed afterwards, all at once.
         {
+            constexpr int NI = (LP + 31) / 32, NC = (LP + 15) / 16;
             const int ty = tid >> 4, tx = tid & 15;
-            for (int j = 0; j < LP; ++j) {
-                const double piv = G[j * (LP + 1) + j];
-                const bool ok = piv > 0.0 && isfinite(piv);
-                const double d = ok ? sqrt(piv) : 1.0, ipv = ok ? 1.0 / piv : 0.0;
-                for (int i = j + 1 + ty; i < LP; i += 16) {
-                    const double gji = G[j * (LP + 1) + i] * ipv;
-                    for (int c = i + ((tx - (i - j - 1)) & 15); c < LP; c += 16)
-                        G[i * (LP + 1) + c] -= gji * G[j * (LP + 1) + c];
+            for (int j = 0; j < ell; ++j) {
+                const double piv = G[j * LDG + j];
+                double gji[NI], gjc[NC], gic[NI][NC];
+#pragma unroll
+                for (int a = 0; a < NI; ++a) {
+                    const int i = j + 1 + ty + 32 * a;
+                    gji[a] = i < ell ? G[j * LDG + i] : 0.0;
+#pragma unroll
+                    for (int b = 0; b < NC; ++b) {
+                        const int c = j + 1 + tx + 16 * b;
+                        gic[a][b] = (i < ell && c < ell && c >= i) ? G[i * LDG + c] : 0.0;
+                    }
                 }
-                if (tid < LP - j) {
-                    const int c = j + tid;
-                    R[j * (LP + 1) + c] = ok ? G[j * (LP + 1) + c] / d : (c == j ? 1.0 : 0.0);
+#pragma unroll
+                for (int b = 0; b < NC; ++b) {
+                    const int c = j + 1 + tx + 16 * b;
+                    gjc[b] = c < ell ? G[j * LDG + c] : 0.0;
                 }
-                if (tid == 0) {
-                    rinv[j] = 1.0 / d;
-                    if (!ok) bad = 1;
+                const double ipv = piv > 0.0 && isfinite(piv) ? recip(piv) : 0.0;
+#pragma unroll
+                for (int a = 0; a < NI; ++a) {
+                    const int i = j + 1 + ty + 32 * a;
+                    const double l = gji[a] * ipv;
+#pragma unroll
+                    for (int b = 0; b < NC; ++b) {
+                        const int c = j + 1 + tx + 16 * b;
+                        if (i < ell && c < ell && c >= i) G[i * LDG + c] = gic[a][b] - l * gjc[b];
+                    }
                 }
                 __syncthreads();
             }
-        }
-        // forward substitution q R = s, one row per thread, in place in LDS;
-        // four independent partial sums keep several LDS reads in flight.
-        // The solved entries are stored as FP32 (the precision of Q), every
-        // dot product is accumulated in FP64
-        for (int r0 = 0; r0 < rows; r0 += CH) {
-            const int nr = rows - r0 < CH ? rows - r0 : CH;
-            stage_panel<LP, CH>(src, rows, r0, chunk);
-            __syncthreads();
-            float *row = chunk + tid * (LP + 1);
-            for (int c = 0; c < ell; ++c) {
-                double v0 = (double)row[c], v1 = 0.0, v2 = 0.0, v3 = 0.0;
-                int j = 0;
-                for (; j + 4 <= c; j += 4) {
-                    v0 -= (double)row[j] * R[j * (LP + 1) + c];
-                    v1 -= (double)row[j + 1] * R[(j + 1) * (LP + 1) + c];
-                    v2 -= (double)row[j + 2] * R[(j + 2) * (LP + 1) + c];
-                    v3 -= (double)row[j + 3] * R[(j + 3) * (LP + 1) + c];
+            // R[j][c] = G[j][c] / sqrt(G[j][j]), c >= j; a non-positive pivot
+            // (rank deficiency beyond the shift) gives a unit row and a flag
+            for (int e = tid; e < ell * ell; e += QT) {
+                const int j = e / ell, c = e % ell;
+                if (c < j) continue;
+                const double piv = G[j * LDG + j];
+                const bool ok = piv > 0.0 && isfinite(piv);
+                const double d = ok ? sqrt(piv) : 1.0;
+                Rt[c * LDR + j] = ok ? G[j * LDG + c] / d : (c == j ? 1.0 : 0.0);
+                if (c == j) {
+                    rinv[j] = 1.0 / d;
+                    if (!ok) bad = 1;
                 }
-                for (; j < c; ++j) v0 -= (double)row[j] * R[j * (LP + 1) + c];
-                row[c] = (float)(((v0 + v1) + (v2 + v3)) * rinv[c]);
             }
-            for (int c = ell; c < LP; ++c) row[c] = 0.0f;
             __syncthreads();
-            for (int e = tid; e < CH * LP; e += GT) {
-                int r = e % CH, c = e / CH;
-                if (r < nr) Q[(r0 + r) + (int64_t)rows * c] = chunk[r * (LP + 1) + c];
+        }
+        // ---- Q = S R^{-1}, chunks of QT rows; Gram of the result for the next pass
+        const bool again = pass + 1 < passes;
+        f64x4 gacc[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) gacc[t] = f64x4{0, 0, 0, 0};
+        for (int ch = 0; ch < nch; ++ch) {
+            const int row = ch * QT + tid;
+            if (pass == 0 || nch > 1) {
+                const float *src = (pass == 0 ? S : Q) + (row < rows ? row : rows - 1);
+#pragma unroll
+                for (int c = 0; c < LP; ++c) x[c] = src[(int64_t)rows * c];
+                if (row >= rows) {
+#pragma unroll
+                    for (int c = 0; c < LP; ++c) x[c] = 0.0f;
+                }
+            }
+            double qd[LP];
+#pragma unroll
+            for (int c = 0; c < LP; ++c) {
+                if (c < ell) {
+                    double v0 = (double)x[c], v1 = 0.0, v2 = 0.0, v3 = 0.0;
+                    const double *rc = Rt + c * LDR;
+#pragma unroll
+                    for (int j = 0; j + 3 < c; j += 4) {
+                        const double2 r01 = *reinterpret_cast<const double2 *>(rc + j);
+                        const double2 r23 = *reinterpret_cast<const double2 *>(rc + j + 2);
+                        v0 -= qd[j] * r01.x;
+                        v1 -= qd[j + 1] * r01.y;
+                        v2 -= qd[j + 2] * r23.x;
+                        v3 -= qd[j + 3] * r23.y;
+                    }
+#pragma unroll
+                    for (int j = c & ~3; j < c; ++j) v0 -= qd[j] * rc[j];
+                    qd[c] = ((v0 + v1) + (v2 + v3)) * rinv[c];
+                } else {
+                    qd[c] = 0.0;
+                }
+                x[c] = (float)qd[c];
+            }
+            if (row < rows) {
+#pragma unroll
+                for (int c = 0; c < LP; ++c) Q[row + (int64_t)rows * c] = x[c];
+            }
+            if (again) {
+#pragma unroll
+                for (int h = 0; h < QT / HR; ++h) {
+                    if (tid / HR == h) {
+                        const int r = tid % HR;
+#pragma unroll
+                        for (int c = 0; c < LP; ++c) st[r * LDS_ + c] = x[c];
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int t = 0; t < TPW; ++t) {
+                        const int idx = wave + 8 * t;
+                        if (idx >= NTILE) continue;
+                        int ti, tj;
+                        tile_ij<NT>(idx, ti, tj);
+#pragma unroll 4
+                        for (int kk = 0; kk < HR / 4; ++kk) {
+                            const int r = 4 * kk + (lane >> 4);
+                            const double a = st[r * LDS_ + 16 * ti + (lane & 15)];
+                            const double b = st[r * LDS_ + 16 * tj + (lane & 15)];
+                            gacc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, gacc[t], 0, 0, 0);
+                        }
+                    }
+                    __syncthreads();
+                }
+            }
+        }
+        if (again) {
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const int idx = wave + 8 * t;
+                if (idx >= NTILE) continue;
+                int ti, tj;
+                tile_ij<NT>(idx, ti, tj);
+                put_sym_tile<true>(G, LDG, ti, tj, gacc[t], lane);
             }
             __syncthreads();
         }
@@ -582,16 +689,58 @@ __global__ __launch_bounds__(GT) void k_resid(const float *__restrict__ X, int m
 }
 
 // ---------------------------------------------------------------- core SVD
-// B B^T (sum of the projection's FP64 per-block Gram partials), cyclic Jacobi eigensolver with the
-// round-robin ordering: in each round the rotations of all ne/2 disjoint
-// pairs are found, then every 2x2 block (pair p rows, pair q columns) is
-// updated at once, B' = J_p^T B J_q, and the eigenvector columns likewise.
+// B B^T (sum of the projection's FP64 per-block Gram partials), cyclic Jacobi
+// eigensolver with the round-robin ordering: in round r the ne/2 disjoint
+// pairs are (r, ne-1) and ((r+k) mod (ne-1), (r-k) mod (ne-1)), k = 1..ne/2-1,
+// and every 2x2 block of B B^T (pair p rows, pair q columns) becomes
+// J_p^T B J_q at once; the eigenvector columns likewise.
+// One barrier per round: the matrix is double buffered and every thread
+// forms the rotations its blocks need from the current buffer (the symmetric
+// Schur 2x2 step, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) written without
+// the quotient zeta).  Only blocks p <= q are computed; each writes its mirror.
+// Entries of B B^T are below 2^300 (squares of FP32 data summed over at most
+// 2^16 rows), so d^2 + e^2 cannot overflow.
 // Eigenvalues sorted decreasing, rank rule, certificate
 //   cert^2 = ||X - Q B||^2 + sum_{j > k_f} lambda_j
 // (the error of Q U_B[:, :k] U_B[:, :k]^T B, since Q has orthonormal columns).
 // The energy rule takes the smallest k whose certified error meets tau.
+__device__ __forceinline__ void rr_pair(int r, int k, int n1, int &a, int &b) {
+    if (k == 0) {
+        a = r;
+        b = n1;
+    } else {
+        a = r + k;
+        if (a >= n1) a -= n1;
+        b = r - k;
+        if (b < 0) b += n1;
+    }
+    if (a > b) {
+        const int t = a;
+        a = b;
+        b = t;
+    }
+}
+
+// rotation (c, s) of a pair from its entries app, aqq, apq; identity (and
+// false) when the pair is a padding pair or the off-diagonal entry is
+// negligible (relative to the diagonal pair, and at the rounding level of the
+// trace).  Branch free, so that the caller's loads are all issued up front.
+__device__ __forceinline__ bool jrot(double app, double aqq, double apq, bool valid, double trace,
+                                     double &c, double &s) {
+    const bool go = valid && apq * apq > 1e-30 * fabs(app * aqq) && fabs(apq) > 1e-15 * trace;
+    const double d = aqq - app, e = 2.0 * apq;
+    const double q = go ? fma(d, d, e * e) : 1.0;
+    const double h = q * rsqrt_nr(q);
+    double t = fabs(e) * recip(go ? fabs(d) + h : 1.0);
+    t = (d == 0.0 || ((d > 0.0) == (e > 0.0))) ? t : -t;
+    const double cc = rsqrt_nr(fma(t, t, 1.0));
+    c = go ? cc : 1.0;
+    s = go ? cc * t : 0.0;
+    return go;
+}
+
 template <int LP>
-__global__ __launch_bounds__(GT) void k_core(const double *__restrict__ gpart, int nparts, int ell,
+__global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, int nparts, int ell,
                                              const double *__restrict__ fro_part, int nfro,
                                              const double *__restrict__ res_part, int nres,
                                              int mode, int kfix, double tau, int max_sweeps,
@@ -599,104 +748,143 @@ __global__ __launch_bounds__(GT) void k_core(const double *__restrict__ gpart, i
                                              int *__restrict__ perm_out, int *__restrict__ kf_out,
                                              double *__restrict__ fro2_out, double *__restrict__ cert,
                                              int32_t *__restrict__ jinfo) {
-    constexpr int LD = LP + 1, NPMAX = LP / 2;
-    __shared__ double G[LP * LD];
-    __shared__ double E[LP * LD];  // eigenvectors, column c = vector c
-    __shared__ double cs[NPMAX][2];
-    __shared__ unsigned char pa[(LP - 1) * NPMAX], pb[(LP - 1) * NPMAX];
-    __shared__ int rot;
+    constexpr int LD = LP + 1, LDE = LP + 2, NPM = LP / 2;
+    constexpr int IPT = (NPM * (NPM + 1) / 2 + (LP / 4) * NPM + QT - 1) / QT;  // items per thread
+    __shared__ double Gb[2][LP * LD];
+    __shared__ __align__(16) double Et[LP * LDE];  // eigenvectors transposed: Et[c * LDE + r] = E[r][c]
+    __shared__ __align__(16) double2 cs[2][NPM];   // rotations of the previous round, for E
     __shared__ double lam[LP];
     __shared__ int perm[LP];
-    __shared__ double trace;
-    const int f = blockIdx.x, tid = threadIdx.x;
-    const int ne = ell + (ell & 1), np = ne / 2;
-    {
-        constexpr int EPT = (LP * LP + GT - 1) / GT;
-#pragma unroll
-        for (int q = 0; q < EPT; ++q) {
-            const int e = tid + q * GT;
-            if (e >= LP * LP) break;
-            double acc = 0.0;
-#pragma unroll 8
-            for (int pp = 0; pp < nparts; ++pp) acc += gpart[((int64_t)f * nparts + pp) * LP * LP + e];
-            G[(e / LP) * LD + e % LP] = acc;
-            E[(e / LP) * LD + e % LP] = (e / LP == e % LP) ? 1.0 : 0.0;
-        }
-    }
-    for (int e = tid; e < (ne - 1) * np; e += GT) {  // round-robin pairs, a < b
-        int r = e / np, k = e % np, a, b;
-        if (k == 0) { a = r; b = ne - 1; }
-        else { a = (r + k) % (ne - 1); b = (r - k + (ne - 1)) % (ne - 1); }
-        pa[e] = (unsigned char)(a < b ? a : b);
-        pb[e] = (unsigned char)(a < b ? b : a);
-    }
-    if (tid == 0) {
-        double t = 0.0;
-        for (int c = 0; c < ell; ++c) t += G[c * LD + c];
-        trace = t;
-    }
-    int sweep = 0, conv = 0;
+    __shared__ double trace_s;
+    __shared__ int rflag[3];
+    const int f = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    const int ne = ell + (ell & 1), np = ne / 2, n1 = ne - 1;
+    for (int e = tid; e < LP * LD; e += QT) Gb[0][e] = 0.0;
+    for (int e = tid; e < LP * LDE; e += QT) Et[e] = 0.0;
     __syncthreads();
-    for (sweep = 1; sweep <= max_sweeps && ell > 1; ++sweep) {
-        if (tid == 0) rot = 0;
-        __syncthreads();
-        for (int r = 0; r < ne - 1; ++r) {
-            const unsigned char *ra = pa + r * np, *rb = pb + r * np;
-            if (tid < np) {
-                const int a = ra[tid], b = rb[tid];
-                double c = 1.0, s = 0.0;
-                if (b < ell) {
-                    double app = G[a * LD + a], aqq = G[b * LD + b], apq = G[a * LD + b];
-                    // relative test (high relative accuracy for well separated pairs) and an
-                    // absolute floor at the rounding level of the Gram matrix
-                    if (fabs(apq) > 1e-15 * sqrt(fabs(app * aqq)) && fabs(apq) > 1e-15 * trace) {
-                        double zeta = (aqq - app) / (2.0 * apq);
-                        double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                        c = 1.0 / sqrt(1.0 + t * t);
-                        s = c * t;
-                        rot = 1;
-                    }
-                }
-                cs[tid][0] = c;
-                cs[tid][1] = s;
-            }
-            __syncthreads();
-            // G blocks (pair pp rows, pair qq columns) and E blocks (row pair i, pair qq columns)
-            const int ng = np * np, nitems = ng + (LP / 2) * np;
-            for (int e = tid; e < nitems; e += GT) {
-                if (e < ng) {
-                    const int pp = e / np, qq = e % np;
-                    const double sp = cs[pp][1], sq = cs[qq][1];
-                    if (sp == 0.0 && sq == 0.0) continue;
-                    const double cp = cs[pp][0], cq = cs[qq][0];
-                    const int a = ra[pp], b = rb[pp], c2 = ra[qq], d = rb[qq];
-                    double m00 = G[a * LD + c2], m01 = G[a * LD + d], m10 = G[b * LD + c2], m11 = G[b * LD + d];
-                    // rows: (a, b) <- (cp a - sp b, sp a + cp b)
-                    double t00 = cp * m00 - sp * m10, t01 = cp * m01 - sp * m11;
-                    double t10 = sp * m00 + cp * m10, t11 = sp * m01 + cp * m11;
-                    // columns: (c, d) <- (cq c - sq d, sq c + cq d)
-                    G[a * LD + c2] = cq * t00 - sq * t01;
-                    G[a * LD + d] = sq * t00 + cq * t01;
-                    G[b * LD + c2] = cq * t10 - sq * t11;
-                    G[b * LD + d] = sq * t10 + cq * t11;
-                } else {
-                    const int ee = e - ng, i = ee / np, qq = ee % np;
-                    const double sq = cs[qq][1];
-                    if (sq == 0.0) continue;
-                    const double cq = cs[qq][0];
-                    const int c2 = ra[qq], d = rb[qq], r0 = 2 * i, r1 = 2 * i + 1;
-                    double x0 = E[r0 * LD + c2], y0 = E[r0 * LD + d], x1 = E[r1 * LD + c2], y1 = E[r1 * LD + d];
-                    E[r0 * LD + c2] = cq * x0 - sq * y0;
-                    E[r0 * LD + d] = sq * x0 + cq * y0;
-                    E[r1 * LD + c2] = cq * x1 - sq * y1;
-                    E[r1 * LD + d] = sq * x1 + cq * y1;
-                }
-            }
-            __syncthreads();
-        }
-        if (!rot) { conv = 1; break; }
-        __syncthreads();
+    // Gram into the leading block (the padded rows and columns of the
+    // partials are zero), identity eigenvectors
+    load_gram_partials<LP, QT>(gpart, f, nparts, Gb[0], LD);
+    if (tid < ell) Et[tid * LDE + tid] = 1.0;
+    if (tid < 3) rflag[tid] = 0;
+    __syncthreads();
+    if (tid < 64) {
+        double t = 0.0;
+        for (int c = tid; c < ell; c += 64) t += Gb[0][c * LD + c];
+        t = wave_sum(t);
+        if (tid == 0) trace_s = t;
     }
+    __syncthreads();
+    const double trace = trace_s;
+
+    // this thread's items, fixed for all rounds: G block (pp <= qq) or E block
+    // (rows 4*qd .. 4*qd+3, pair qq)
+    const int ng = np * (np + 1) / 2, nq = (ne + 3) / 4, nitems = ng + nq * np;
+    int ik[IPT], i1[IPT], i2[IPT];
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+        const int it = tid + u * QT;
+        ik[u] = it < ng ? 0 : it < nitems ? 1 : 2;
+        if (ik[u] == 0) {
+            int pp = 0, rem = it;
+            while (rem >= np - pp) {
+                rem -= np - pp;
+                ++pp;
+            }
+            i1[u] = pp;
+            i2[u] = pp + rem;
+        } else if (ik[u] == 1) {
+            i1[u] = (it - ng) / np;
+            i2[u] = (it - ng) % np;
+        } else {
+            i1[u] = i2[u] = 0;
+        }
+    }
+    // E block item: apply the rotations of round r (stored in cs[par]) to its
+    // four rows of the eigenvector columns of pair i2
+    auto e_item = [&](int u, int r, int par) {
+        int c2, d;
+        rr_pair(r, i2[u], n1, c2, d);
+        const int r0 = 4 * i1[u];
+        double2 *pc = reinterpret_cast<double2 *>(Et + c2 * LDE + r0);
+        double2 *pd = reinterpret_cast<double2 *>(Et + d * LDE + r0);
+        const double2 rt = cs[par][i2[u]];
+        const double2 x0 = pc[0], x1 = pc[1], y0 = pd[0], y1 = pd[1];
+        pc[0] = double2{rt.x * x0.x - rt.y * y0.x, rt.x * x0.y - rt.y * y0.y};
+        pc[1] = double2{rt.x * x1.x - rt.y * y1.x, rt.x * x1.y - rt.y * y1.y};
+        pd[0] = double2{rt.y * x0.x + rt.x * y0.x, rt.y * x0.y + rt.x * y0.y};
+        pd[1] = double2{rt.y * x1.x + rt.x * y1.x, rt.y * x1.y + rt.x * y1.y};
+    };
+
+    int sweep = 0, conv = 0, cur = 0, rr = 0;  // rr counts rounds over all sweeps
+    for (sweep = 1; sweep <= max_sweeps && ell > 1; ++sweep) {
+        const int fl = sweep % 3;
+        for (int r = 0; r < n1; ++r, ++rr) {
+            const double *Gc = Gb[cur];
+            double *Gn = Gb[cur ^ 1];
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < IPT; ++u) {
+                if (ik[u] == 2) continue;
+                if (ik[u] == 0) {
+                    int a, b, c2, d;
+                    rr_pair(r, i1[u], n1, a, b);
+                    rr_pair(r, i2[u], n1, c2, d);
+                    // every load of the item first
+                    const double m00 = Gc[a * LD + c2], m01 = Gc[a * LD + d];
+                    const double m10 = Gc[b * LD + c2], m11 = Gc[b * LD + d];
+                    const double paa = Gc[a * LD + a], pbb = Gc[b * LD + b], pab = Gc[a * LD + b];
+                    const double qcc = Gc[c2 * LD + c2], qdd = Gc[d * LD + d], qcd = Gc[c2 * LD + d];
+                    double cp, sp, cq, sq;
+                    any |= jrot(paa, pbb, pab, b < ell, trace, cp, sp);
+                    jrot(qcc, qdd, qcd, d < ell, trace, cq, sq);
+                    // rows: (a, b) <- (cp a - sp b, sp a + cp b); then the columns
+                    const double t00 = cp * m00 - sp * m10, t01 = cp * m01 - sp * m11;
+                    const double t10 = sp * m00 + cp * m10, t11 = sp * m01 + cp * m11;
+                    const double n00 = cq * t00 - sq * t01, n01 = sq * t00 + cq * t01;
+                    const double n10 = cq * t10 - sq * t11, n11 = sq * t10 + cq * t11;
+                    if (i2[u] != i1[u]) {
+                        Gn[a * LD + c2] = n00;
+                        Gn[a * LD + d] = n01;
+                        Gn[b * LD + c2] = n10;
+                        Gn[b * LD + d] = n11;
+                        Gn[c2 * LD + a] = n00;
+                        Gn[d * LD + a] = n01;
+                        Gn[c2 * LD + b] = n10;
+                        Gn[d * LD + b] = n11;
+                    } else {  // diagonal block: kept exactly symmetric; its rotation
+                              // goes to the eigenvectors in the next round
+                        Gn[a * LD + a] = n00;
+                        Gn[a * LD + b] = n01;
+                        Gn[b * LD + a] = n01;
+                        Gn[b * LD + b] = n11;
+                        cs[rr & 1][i1[u]] = double2{cp, sp};
+                    }
+                } else if (rr > 0) {
+                    e_item(u, r > 0 ? r - 1 : n1 - 1, (rr - 1) & 1);
+                }
+            }
+            // one flag write per wavefront that rotated
+            if (__any(any) && lane == 0) rflag[fl] = 1;
+            __syncthreads();
+            // the flag of sweep+2 is cleared after the first barrier of this
+            // sweep, when every thread has read it at the end of sweep-1
+            if (r == 0 && tid == 0) rflag[(sweep + 2) % 3] = 0;
+            cur ^= 1;
+        }
+        if (rflag[fl] == 0) {
+            conv = 1;
+            break;
+        }
+    }
+    // the eigenvectors take the last round's rotations
+    if (rr > 0) {
+#pragma unroll
+        for (int u = 0; u < IPT; ++u)
+            if (ik[u] == 1) e_item(u, (rr - 1) % n1, (rr - 1) & 1);
+    }
+    __syncthreads();
+    const double *G = Gb[cur];
     if (tid < ell) lam[tid] = fmax(G[tid * LD + tid], 0.0);
     __syncthreads();
     if (tid < ell) {
@@ -730,13 +918,13 @@ __global__ __launch_bounds__(GT) void k_core(const double *__restrict__ gpart, i
         if (cert) cert[f] = nres > 0 ? sqrt(res + disc) : -1.0;
         jinfo[f] = (conv || ell <= 1) ? 0 : 1;
     }
-    for (int r = tid; r < LP; r += GT) {
+    for (int r = tid; r < LP; r += QT) {
         int j = r < ell ? perm[r] : r;
         sig[(int64_t)f * LP + r] = r < ell ? sqrt(lam[j]) : 0.0;
         perm_out[(int64_t)f * LP + r] = j;
     }
-    for (int e = tid; e < LP * LP; e += GT)
-        UB[(int64_t)f * LP * LP + e] = E[(e % LP) * LD + e / LP];  // column major, col = e/LP
+    for (int e = tid; e < LP * LP; e += QT)
+        UB[(int64_t)f * LP * LP + e] = Et[(e / LP) * LDE + e % LP];  // column major, col = e/LP
 }
 
 // ---------------------------------------------------------------- factors
@@ -858,18 +1046,44 @@ size_t carve(char *base, int64_t m, int64_t p, int64_t nf, int LP, MixedWs *w) {
     return off;
 }
 
+// Faces [f0, f0 + nfg) through the whole path on stream s.  Every kernel
+// below works face by face, so the pointers are offset to the first face of
+// the range and the kernels see a tensor of nfg faces.
 template <int LP>
-tsvdm_status run_mixed(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
-                       void *wsp, hipStream_t s) {
-    const int m = (int)X->m, p = (int)X->p, nf = (int)X->n3, ell = o->k + o->oversample;
-    MixedWs w;
-    carve(reinterpret_cast<char *>(wsp), m, p, nf, LP, &w);
-    const float *Xd = reinterpret_cast<const float *>(X->data);
-    const dim3 gm((unsigned)(((m + 63) / 64) * nf)), gp((unsigned)(((p + 63) / 64) * nf));
+tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
+                       const MixedWs &w0, int f0, int nfg, hipStream_t s) {
+    const int m = (int)X->m, p = (int)X->p, ell = o->k + o->oversample;
     const int mparts = (m + 63) / 64, pparts = (p + 63) / 64;
+    const int64_t kmax = F->kmax;
+    MixedWs w = w0;
+    w.Y += (int64_t)f0 * m * LP;
+    w.Qm += (int64_t)f0 * m * LP;
+    w.Z += (int64_t)f0 * p * LP;
+    w.Qp += (int64_t)f0 * p * LP;
+    w.gram_m += (int64_t)f0 * mparts * LP * LP;
+    w.gram_p += (int64_t)f0 * pparts * LP * LP;
+    w.fro_part += (int64_t)f0 * mparts;
+    w.res_part += (int64_t)f0 * pparts;
+    w.UB += (int64_t)f0 * LP * LP;
+    w.sig += (int64_t)f0 * LP;
+    w.fro2 += f0;
+    w.perm += (int64_t)f0 * LP;
+    w.kf += f0;
+    w.qr_info += f0;
+    w.jinfo += f0;
+    const float *Xd = reinterpret_cast<const float *>(X->data) + (int64_t)f0 * m * p;
+    float *Uo = reinterpret_cast<float *>(F->U) + (int64_t)f0 * m * kmax;
+    float *Vo = reinterpret_cast<float *>(F->V) + (int64_t)f0 * p * kmax;
+    double *So = F->S + (int64_t)f0 * kmax;
+    int32_t *ranks = F->ranks + f0;
+    double *cert = F->cert ? F->cert + f0 : nullptr;
+    double *fro = F->fro ? F->fro + f0 : nullptr;
+    int32_t *info = F->info ? F->info + f0 : nullptr;
+    const int nf = nfg;
+    const dim3 gm((unsigned)(mparts * nf)), gp((unsigned)(pparts * nf));
     const bool power = o->power_iters > 0;
     // the residual is needed for the certificate and for the energy rule
-    const bool resid = o->rank_mode == TSVDM_RANK_ENERGY || (o->certify && F->cert);
+    const bool resid = o->rank_mode == TSVDM_RANK_ENERGY || (o->certify && cert);
     TSVDM_LAUNCH("zero_info", k_zero_i32, dim3((nf + 255) / 256), dim3(256), 0, s, w.qr_info, nf);
     const double *gm_c = w.gram_m, *gp_c = w.gram_p;
     if (power) {
@@ -878,12 +1092,12 @@ tsvdm_status run_mixed(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
                      (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m);
         // basis of the sketch: one shifted Cholesky-QR step (its span is what
         // the power step needs)
-        TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(GT), 0, s, (const float *)w.Y, m, ell,
+        TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell,
                      w.Qm, 1, gm_c, mparts, w.qr_info);
         // pass 2: Z = X^T Q (BF16) and its Gram partials; basis of Z
         TSVDM_LAUNCH("power_xtw_bf16", (k_xtw<LP, PROD_BF16, true>), gp, dim3(GT), 0, s, Xd, m, p, nf,
                      (const float *)w.Qm, (int64_t)m * LP, m, LP, w.Z, w.gram_p);
-        TSVDM_LAUNCH("cholqr_power_z", (k_cholqr<LP>), dim3(nf), dim3(GT), 0, s, (const float *)w.Z, p, ell,
+        TSVDM_LAUNCH("cholqr_power_z", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Z, p, ell,
                      w.Qp, 1, gp_c, pparts, w.qr_info);
         // pass 3: Y' = X Qz, FP32-accurate (split BF16), and its Gram partials
         TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true>), gm, dim3(GT), 0, s, Xd, m, p, nf,
@@ -893,7 +1107,7 @@ tsvdm_status run_mixed(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
                      (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m);
     }
     // final basis: FP64 shifted Cholesky-QR2 (first Gram from the partials)
-    TSVDM_LAUNCH("cholqr_final", (k_cholqr<LP>), dim3(nf), dim3(GT), 0, s, (const float *)w.Y, m, ell, w.Qm,
+    TSVDM_LAUNCH("cholqr_final", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell, w.Qm,
                  2, gm_c, mparts, w.qr_info);
     // pass 4: B^T = X^T Q, FP32-accurate, and the Gram partials of B^T
     TSVDM_LAUNCH("project_xtw_split", (k_xtw<LP, PROD_SPLIT, true>), gp, dim3(GT), 0, s, Xd, m, p, nf,
@@ -902,16 +1116,23 @@ tsvdm_status run_mixed(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
         TSVDM_LAUNCH("certificate_resid", (k_resid<LP>), gp, dim3(GT), 0, s, Xd, m, p, nf,
                      (const float *)w.Qm, (const float *)w.Z, w.res_part);
     const int msw = o->max_sweeps > 0 ? o->max_sweeps : 30;
-    TSVDM_LAUNCH("core_gram_eig", (k_core<LP>), dim3(nf), dim3(GT), 0, s, gp_c, pparts, ell,
+    TSVDM_LAUNCH("core_gram_eig", (k_core<LP>), dim3(nf), dim3(QT), 0, s, gp_c, pparts, ell,
                  (const double *)w.fro_part, mparts, (const double *)w.res_part, resid ? pparts : 0,
-                 o->rank_mode, o->k, o->tau, msw, w.UB, w.sig, w.perm, w.kf, w.fro2, F->cert, w.jinfo);
+                 o->rank_mode, o->k, o->tau, msw, w.UB, w.sig, w.perm, w.kf, w.fro2, cert, w.jinfo);
     const int rows = m > p ? m : p;
     TSVDM_LAUNCH("factors", (k_factors<LP>), dim3((rows + GT - 1) / GT, nf), dim3(GT), 0, s,
-                 (const float *)w.Qm, (const float *)w.Z, m, p, ell, F->kmax, w.UB, w.sig, w.perm, w.kf,
-                 w.fro2, w.qr_info, w.jinfo, reinterpret_cast<float *>(F->U), F->S,
-                 reinterpret_cast<float *>(F->V), F->ranks, F->fro, F->info);
+                 (const float *)w.Qm, (const float *)w.Z, m, p, ell, kmax, w.UB, w.sig, w.perm, w.kf,
+                 w.fro2, w.qr_info, w.jinfo, Uo, So, Vo, ranks, fro, info);
     TSVDM_LAUNCH_CHECK("mixed truncate");
     return TSVDM_OK;
+}
+
+template <int LP>
+tsvdm_status run_mixed(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
+                       void *wsp, hipStream_t s) {
+    MixedWs w;
+    carve(reinterpret_cast<char *>(wsp), X->m, X->p, X->n3, LP, &w);
+    return run_group<LP>(X, o, F, w, 0, (int)X->n3, s);
 }
 
 }  // namespace
