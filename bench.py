@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--fp64-steps", type=int, default=1)
-    ap.add_argument("--cpu-faces", type=int, default=48)
+    ap.add_argument("--cpu-faces", type=int, default=96)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--kernel-table", action="store_true", help="print the per-kernel table to stderr")
@@ -45,10 +45,16 @@ def parse():
     return ap.parse_args()
 
 
-def algorithmic_work(m, p, nf, ell, k):
+def algorithmic_work(m, p, nf, ell, k, sweeps=6):
     """Algorithmic bytes (HBM-bound kernels) or FP64 flops (FP64 kernels) of one
-    launch of each kernel of the step, for the roofline of the dominant one."""
+    step's launches of each kernel, for the roofline of the dominant one."""
     X = 4.0 * m * p * nf
+
+    def chol_qr(rows, passes):
+        # Cholesky l^3/3 and triangular solve rows*l^2 per pass; the second
+        # pass also forms its Gram rows*l(l+1) (the first comes from partials)
+        return nf * (passes * (ell ** 3 / 3.0 + rows * ell * ell) + (passes - 1) * rows * ell * (ell + 1))
+
     return {
         "transform_fft": ("hbm", 2 * X),                                  # read X, write Xhat
         "sketch_xw_bf16": ("hbm", X + 4.0 * m * ell * nf),                # read Xhat, write Y
@@ -57,12 +63,43 @@ def algorithmic_work(m, p, nf, ell, k):
         "project_xtw_split": ("hbm", X + 4.0 * (m + p) * ell * nf),
         "certificate_resid": ("hbm", X + 4.0 * (m + p) * k * nf),
         "factors": ("hbm", 4.0 * (m + p) * (ell + k) * nf),
-        # shifted Cholesky-QR3: 3 x (Gram r*l(l+1) + TRSM r*l^2) flops + Cholesky l^3/3
-        "cholqr_sketch": ("fp64", nf * 3 * (m * ell * (ell + 1) + m * ell * ell + ell ** 3 / 3.0)),
-        "cholqr_power_z": ("fp64", nf * 3 * (p * ell * (ell + 1) + p * ell * ell + ell ** 3 / 3.0)),
-        "cholqr_power_y": ("fp64", nf * 3 * (m * ell * (ell + 1) + m * ell * ell + ell ** 3 / 3.0)),
-        "core_gram_eig": ("fp64", nf * (p * ell * (ell + 1) + 9 * ell ** 3)),
+        "cholqr_sketch": ("fp64", chol_qr(m, 1)),
+        "cholqr_power_z": ("fp64", chol_qr(p, 1)),
+        "cholqr_final": ("fp64", chol_qr(m, 2)),
+        # cyclic Jacobi on the l x l Gram: l(l-1)/2 rotations per sweep, each
+        # 6l flops on the rows, 6l on the columns and 6l on the eigenvectors
+        "core_gram_eig": ("fp64", nf * sweeps * 9.0 * ell ** 3),
     }
+
+
+def kernel_sources_sha256():
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    base = os.path.join(ROOT, "paper_2105_01170_amd", "csrc")
+    for fn in sorted(glob.glob(os.path.join(base, "*.hip")) + glob.glob(os.path.join(base, "*.h"))):
+        with open(fn, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the
+    kernel sources changed since the counters were taken."""
+    fn = os.path.join(ROOT, "profiles", "tsvdm_mixed_512x512x256_k32.md")
+    try:
+        with open(fn) as f:
+            for line in f:
+                line = line.strip()
+                if line.startswith("traffic-json "):
+                    rec = json.loads(line[len("traffic-json "):])
+                    if rec.get("sha256") != kernel_sources_sha256():
+                        return None
+                    return rec["bytes"].get(kernel)
+    except OSError:
+        return None
+    return None
 
 
 def main():
@@ -153,7 +190,7 @@ def main():
         roof = {"bound": "alu", "achieved": amount / avg_s / 1e12, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s (fp64)"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom)
     roof["kernel"] = dom
     roof["avg_us"] = 1e6 * avg_s
     # the HBM-bound passes of the step, each against the HBM peak
