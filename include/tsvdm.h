@@ -219,6 +219,62 @@ int32_t tsvdm_timing_count(void);
  * tsvdm_timing_count).  The name stays valid until the next enable or count. */
 tsvdm_status tsvdm_timing_get(int32_t i, const char **name, int32_t *launches, double *total_ms);
 
+/* ---------------------------------------------------------------- batches
+ * Facewise truncation of an uneven batch: nmat dense transform-domain tensors
+ * Xhat[i] (FP32, m_i x p_i x nf_i, each face with m_i <= 64 rows), each with
+ * its own factors F[i] (F32 U and V, kmax_i columns).  This is the truncation
+ * step of Algorithm alg:strategy for many independent inputs at once (e.g.
+ * the Kronecker-sum matrices of Sec. 3 mapped by T_E and transformed).
+ *
+ * Per face, with X = Xhat_f (m x p):
+ *   1. G = X X^T in FP64 (every product of FP32 values is exact in FP64);
+ *   2. rank-revealing pivoted Cholesky P G P^T = R^T R + S, stopped when
+ *      trace(S) <= 1e-3 tau^2 trace(G) (ENERGY) or 1e-15 trace(G) (FIXED), or
+ *      after 32 steps; Jacobi eigensolver of R R^T;
+ *   3. rank k_f by opts->rank_mode, with the discarded energy counted as
+ *      sum_{j>k} lambda_j(R R^T) + trace(S), an upper bound on the exact
+ *      discarded energy; cert_f = its square root;
+ *   4. U = P^T R^T U_H diag(sigma)^{-1} (orthonormal), V = X^T U diag(sigma)^{-1}.
+ * The result is the truncated SVD of the face up to trace(S).
+ *
+ * Usage: size the workspace, create a plan (host work and one synchronous
+ * upload of the face table into the workspace), optionally autotune it, then
+ * launch with tsvdm_truncate_batched as often as needed (asynchronous; no
+ * allocation, no host-device copy: safe under stream capture).  The plan
+ * keeps the device pointers it was created with. */
+typedef struct tsvdm_batched_plan_s tsvdm_batched_plan;
+
+/* Workspace bytes for the batch (shapes only). 0 if the arguments are invalid. */
+size_t tsvdm_batched_workspace_size(int32_t nmat, const tsvdm_tensor *Xhat);
+
+/* Validates the batch (host arrays Xhat[nmat], F[nmat] of device pointers),
+ * orders the faces by cost (largest first) and writes the face table into the
+ * caller's workspace (synchronous copy).  opts: rank_mode, k (FIXED rank or
+ * ENERGY cap, <= F[i].kmax and <= 32), tau, max_sweeps; the other fields are
+ * ignored.  *plan is a host object released with tsvdm_batched_plan_destroy. */
+tsvdm_status tsvdm_batched_plan_create(int32_t nmat, const tsvdm_tensor *Xhat,
+                                       const tsvdm_truncate_opts *opts, const tsvdm_factors *F,
+                                       void *workspace, size_t workspace_bytes,
+                                       tsvdm_batched_plan **plan);
+
+/* Launches the batch on `stream`: a queue reset, the persistent Gram kernel,
+ * the per-face core, the persistent V kernel.  Outputs as for tsvdm_truncate. */
+tsvdm_status tsvdm_truncate_batched(const tsvdm_batched_plan *plan, void *stream);
+
+/* Times the candidate launch configurations of the two persistent kernels on
+ * this plan (it runs the batch several times on `stream` and synchronizes),
+ * keeps the fastest in the plan and in a process-wide table keyed by the
+ * batch signature, which later plans of the same signature start from. */
+tsvdm_status tsvdm_batched_autotune(tsvdm_batched_plan *plan, void *stream);
+
+/* The plan's configuration: cfg[0] Gram workgroups per CU, cfg[1] Gram column
+ * chunk, cfg[2] V workgroups per CU, cfg[3] 1 if it came from the autotuner
+ * (here or through the table). */
+tsvdm_status tsvdm_batched_config(const tsvdm_batched_plan *plan, int32_t cfg[4]);
+
+/* Releases the host plan (the workspace stays the caller's). NULL is allowed. */
+void tsvdm_batched_plan_destroy(tsvdm_batched_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

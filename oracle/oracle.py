@@ -136,6 +136,29 @@ def placement_generic(ell: int, q: int):
     return E
 
 
+def kron_sum_faces(B: np.ndarray, C: np.ndarray, M: np.ndarray, faces) -> np.ndarray:
+    """Transform-domain faces of X = T_E[A], A = sum_r B_r kron C_r, for the
+    generic blocking with square B_r (l x l, so q = l) and square C_r (m x m,
+    so n = m), without forming A.
+
+    Block (j, k) of A is sum_r B_r[j, k] C_r, so X(a, j + l*k, t) =
+    sum_r B_r[j, k] C_r[a, t] (Sec. 3, T_E) and the mode-3 product gives
+    Xhat_f[a, b] = sum_r (C_r M^T)[a, f] vec(B_r)[b] (column-major vec):
+    every face has rank at most r.  B: (r, l, l), C: (r, m, m).  Returns an
+    (m, l*l, len(faces)) array."""
+    B = np.asarray(B, dtype=np.float64)
+    C = np.asarray(C, dtype=np.float64)
+    r, l, _ = B.shape
+    m = C.shape[1]
+    # vec(B_r)[j + l*k] = B_r[j, k]: column-major unwrapping
+    vecB = np.stack([B[i].reshape(-1, order="F") for i in range(r)])
+    CM = np.einsum("rat,ft->raf", C, M)  # (C_r M^T)[a, f]
+    out = np.empty((m, l * l, len(faces)), order="F")
+    for i, f in enumerate(faces):
+        out[:, :, i] = CM[:, :, f].T @ vecB
+    return out
+
+
 def struct_kron(E, blocks) -> np.ndarray:
     """struct(A) = sum_k E_k kron B_k (eq. kronsum with B_k = sqrt(eta_k) A_k)."""
     return sum(np.kron(Ek, Bk) for Ek, Bk in zip(E, blocks))

@@ -121,6 +121,47 @@ class Truncator:
         return self.F
 
 
+class BatchedTruncator:
+    """Facewise truncation of an uneven batch (tsvdm_batched_*): the tensors
+    xhats[i] are dense FP32 (m_i, p_i, nf_i) device buffers with m_i <= 64.
+    Allocates the factors of every tensor and the workspace, creates the plan
+    (one synchronous upload); calling launches the batch asynchronously (safe
+    to capture in a CUDA/HIP graph)."""
+
+    def __init__(self, xhats: list, shapes: list, *, rank_mode=C.RANK_ENERGY, k=16, tau=1e-4,
+                 max_sweeps=0, kmax=None, device="cuda"):
+        self.xhats = xhats
+        self.shapes = [tuple(int(v) for v in s) for s in shapes]
+        self.opts = C.truncate_opts(rank_mode, k, tau, C.PREC_F64, 0, 0, max_sweeps, 1, 0)
+        kmax = k if kmax is None else kmax
+        self.Xd = [C.dense_tensor(x.data_ptr(), m, p, nf, C.F32)
+                   for x, (m, p, nf) in zip(xhats, self.shapes)]
+        self.F = [empty_factors(m, p, nf, kmax, torch.float32, device) for (m, p, nf) in self.shapes]
+        self.ws_bytes = C.tsvdm_batched_workspace_size(self.Xd)
+        if self.ws_bytes == 0:
+            raise C.TsvdmError(C.EINVAL, C.tsvdm_last_error())
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=device)
+        self.plan = C.tsvdm_batched_plan_create(self.Xd, self.opts, [f.desc() for f in self.F],
+                                                self.ws.data_ptr(), self.ws_bytes)
+
+    def __call__(self, stream=None) -> list:
+        C.tsvdm_truncate_batched(self.plan, _stream(stream))
+        return self.F
+
+    def autotune(self, stream=None) -> list:
+        C.tsvdm_batched_autotune(self.plan, _stream(stream))
+        return C.tsvdm_batched_config(self.plan)
+
+    def config(self) -> list:
+        return C.tsvdm_batched_config(self.plan)
+
+    def __del__(self):
+        plan = getattr(self, "plan", None)
+        if plan:
+            C.tsvdm_batched_plan_destroy(plan)
+            self.plan = None
+
+
 def apply(F: Factors, kind: int, n3: int, ell: int, q: int, x: torch.Tensor, ldx: int | None = None,
           compute: int | None = None, M: torch.Tensor | None = None, y: torch.Tensor | None = None,
           ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:

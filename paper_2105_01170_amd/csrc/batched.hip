@@ -1,0 +1,691 @@
+// Facewise truncation of an uneven batch of tensors whose faces have at most
+// 64 rows (the truncation step of Algorithm alg:strategy for many independent
+// inputs, e.g. Kronecker-sum matrices of different factor sizes, Sec. 3).
+//
+// Three kernels per batch, all items (faces) listed in a table built once on
+// the host and ordered by cost, largest first:
+//  * k_bgram (persistent, HBM + FP64 MFMA): workgroups pull faces from an
+//    atomic queue and form G = X X^T in FP64 (exact products of FP32 data)
+//    from column chunks of the face staged in LDS; G goes to the workspace.
+//  * k_bcore (one wavefront per face): rank-revealing pivoted Cholesky
+//    P G P^T = R^T R + S (left-looking, largest remaining diagonal first),
+//    stopped once trace(S) is below the rule's tolerance; Jacobi
+//    eigensolver of R R^T (at most 32 x 32); rank rule with the discarded
+//    energy sum_{j>k} lambda_j + trace(S); U = P^T R^T U_H diag(1/sigma).
+//  * k_bvec (persistent, HBM): V = X^T U diag(1/sigma), a second pass over
+//    the face.
+// A queue reset kernel precedes the two persistent kernels, so a launch
+// sequence can be captured in a graph and replayed.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <new>
+#include <mutex>
+#include <vector>
+
+#include "common.h"
+#include "jacobi_dev.h"
+
+using namespace tsvdm;
+
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BT = 256;      // threads per workgroup of the streaming kernels
+constexpr int MX = 64;       // largest face row count
+constexpr int RX = 32;       // largest pivoted-Cholesky rank (Jacobi size)
+constexpr int LDX = MX + 1;  // LDS pitch (floats) of one staged column
+constexpr int KMAXB = 32;    // largest rank returned
+
+struct Item {
+    const float *X;  // m x p, column major
+    float *U;        // m x kmax (ld m)
+    float *V;        // p x kmax (ld p)
+    double *S;       // kmax
+    double *G;       // m x m, row major (workspace)
+    int32_t *rank;
+    double *cert;  // may be null
+    double *fro;   // may be null
+    int32_t *info; // may be null
+    int32_t m, p, kmax, pad;
+};
+
+// staging of a chunk of KC columns of the m x p face (m*KC consecutive floats)
+// into LDS as xs[k * LDX + i]; rows m..63 of xs stay zero.  Each thread holds
+// KC*MX/BT floats between the global load and the LDS store, so the next
+// chunk's loads are in flight while the current chunk is consumed.
+template <int KC>
+struct Stager {
+    static constexpr int PER = KC * MX / BT;
+    float v[PER];
+    int i0, k0, di, dk, m, p;
+    const float *X;
+    __device__ void init(const float *X_, int m_, int p_) {
+        X = X_;
+        m = m_;
+        p = p_;
+        i0 = threadIdx.x % m;
+        k0 = threadIdx.x / m;
+        di = BT % m;
+        dk = BT / m;
+    }
+    __device__ void load(int c) {
+        const int ncol = min(KC, p - c * KC);
+        const int lim = m * ncol;
+        const float *src = X + (int64_t)m * KC * c;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int l = threadIdx.x + q * BT;
+            v[q] = l < lim ? src[l] : 0.0f;
+        }
+    }
+    __device__ void store(float *xs) const {
+        int i = i0, k = k0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            if (k < KC) xs[k * LDX + i] = v[q];
+            i += di;
+            k += dk;
+            if (i >= m) {
+                i -= m;
+                ++k;
+            }
+        }
+    }
+};
+
+__device__ __forceinline__ void tile_of(int t, int nt, int &ti, int &tj) {
+    ti = 0;
+    while (t >= nt - ti) {
+        t -= nt - ti;
+        ++ti;
+    }
+    tj = ti + t;
+}
+
+__device__ __forceinline__ int next_item(int *counter, int *s_idx) {
+    if (threadIdx.x == 0) *s_idx = atomicAdd(counter, 1);
+    __syncthreads();
+    const int idx = *s_idx;
+    __syncthreads();
+    return idx;
+}
+
+// ---------------------------------------------------------------- Gram
+template <int KC>
+__global__ __launch_bounds__(BT) void k_bgram(const Item *__restrict__ items, int nitems,
+                                              int *__restrict__ counter) {
+    __shared__ float xs[KC * LDX];
+    __shared__ int s_idx;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (;;) {
+        const int idx = next_item(counter, &s_idx);
+        if (idx >= nitems) break;
+        const Item it = items[idx];
+        const int m = it.m, p = it.p, nt = (m + 15) >> 4, ntile = nt * (nt + 1) / 2;
+        int ti[3], tj[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int id = wave + 4 * t;
+            if (id < ntile) tile_of(id, nt, ti[t], tj[t]);
+            else ti[t] = tj[t] = -1;
+        }
+        f64x4 acc[3];
+#pragma unroll
+        for (int t = 0; t < 3; ++t) acc[t] = f64x4{0, 0, 0, 0};
+        for (int e = tid; e < KC * LDX; e += BT) xs[e] = 0.0f;
+        Stager<KC> sg;
+        sg.init(it.X, m, p);
+        const int nck = (p + KC - 1) / KC;
+        sg.load(0);
+        __syncthreads();
+        for (int c = 0; c < nck; ++c) {
+            sg.store(xs);
+            __syncthreads();
+            if (c + 1 < nck) sg.load(c + 1);
+#pragma unroll 4
+            for (int kk = 0; kk < KC / 4; ++kk) {
+                const int r = 4 * kk + (lane >> 4);
+#pragma unroll
+                for (int t = 0; t < 3; ++t) {
+                    if (ti[t] < 0) continue;
+                    const double a = xs[r * LDX + 16 * ti[t] + (lane & 15)];
+                    const double b = xs[r * LDX + 16 * tj[t] + (lane & 15)];
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+                }
+            }
+            __syncthreads();
+        }
+        // FP64 16x16x4 output: row lane/16 + 4v, column lane%16 of the tile
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            if (ti[t] < 0) continue;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * ti[t] + (lane >> 4) + 4 * v, j = 16 * tj[t] + (lane & 15);
+                if (i < m && j < m) {
+                    it.G[i * m + j] = acc[t][v];
+                    it.G[j * m + i] = acc[t][v];
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- core
+// One wavefront per face.  mode/kcap/tau: the rank rule; stop tolerance of
+// the pivoted Cholesky: 1e-3 tau^2 trace(G) (ENERGY), 1e-15 trace(G) (FIXED).
+__global__ __launch_bounds__(64) void k_bcore(const Item *__restrict__ items, int mode, int kcap,
+                                              double tau, int max_sweeps) {
+    constexpr int LD = RX + 1, LDE = RX + 2;
+    __shared__ double R[RX * MX];  // R[t * MX + i]: row t of the factor, column i
+    __shared__ double Hb[2][RX * LD];
+    __shared__ __align__(16) double Et[RX * LDE];
+    __shared__ __align__(16) double2 cs[2 * (RX / 2)];
+    __shared__ double diag[MX];
+    __shared__ int chosen[MX];
+    __shared__ int piv[RX];
+    __shared__ double lam[RX];
+    __shared__ int perm[RX];
+    __shared__ int rflag[3];
+    const int lane = threadIdx.x;
+    const Item it = items[blockIdx.x];
+    const int m = it.m;
+    const double *G = it.G;
+
+    // ---- pivoted Cholesky
+    const double gii = lane < m ? G[lane * m + lane] : 0.0;
+    diag[lane] = gii;
+    chosen[lane] = lane < m ? 0 : 1;
+    for (int e = lane; e < RX * MX; e += 64) R[e] = 0.0;
+    const double trG = wave_sum(gii);
+    const double stop = mode == TSVDM_RANK_ENERGY ? 1e-3 * tau * tau * trG : 1e-15 * trG;
+    const int rlim = m < RX ? m : RX;
+    __syncthreads();
+    int r = 0;
+    for (int j = 0; j < rlim; ++j) {
+        const double d = chosen[lane] ? -1.0 : diag[lane];
+        const double rem = wave_sum(fmax(d, 0.0));
+        if (!(rem > stop)) break;
+        // largest remaining diagonal (lowest index on ties)
+        double best = d;
+        int q = lane;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ob = __shfl_xor(best, off, 64);
+            const int oq = __shfl_xor(q, off, 64);
+            if (ob > best || (ob == best && oq < q)) {
+                best = ob;
+                q = oq;
+            }
+        }
+        if (!(best > 0.0)) break;
+        const double rjj = sqrt(best), inv = 1.0 / rjj;
+        if (lane < m && !chosen[lane] && lane != q) {
+            double sacc = G[q * m + lane];
+            for (int t = 0; t < j; ++t) sacc -= R[t * MX + q] * R[t * MX + lane];
+            const double rv = sacc * inv;
+            R[j * MX + lane] = rv;
+            diag[lane] -= rv * rv;
+        }
+        if (lane == q) {
+            R[j * MX + q] = rjj;
+            chosen[q] = 1;
+            diag[q] = 0.0;
+            piv[j] = q;
+        }
+        __syncthreads();
+        r = j + 1;
+    }
+    const double remS = wave_sum(chosen[lane] ? 0.0 : fmax(diag[lane], 0.0));
+
+    // ---- H = R R^T (r x r) and its eigen-decomposition
+    for (int e = lane; e < RX * LD; e += 64) Hb[0][e] = 0.0;
+    for (int e = lane; e < RX * LDE; e += 64) Et[e] = 0.0;
+    if (lane < 3) rflag[lane] = 0;
+    __syncthreads();
+    for (int e = lane; e < r * r; e += 64) {
+        const int a = e / r, b = e % r;
+        if (b < a) continue;
+        double h = 0.0;
+        for (int i = 0; i < m; ++i) h += R[a * MX + i] * R[b * MX + i];
+        Hb[0][a * LD + b] = h;
+        Hb[0][b * LD + a] = h;
+    }
+    if (lane < r) Et[lane * LDE + lane] = 1.0;
+    __syncthreads();
+    double trH = wave_sum(lane < r ? Hb[0][lane * LD + lane] : 0.0);
+    int conv = 0;
+    const double *Hf = jacobi_eig<RX, 64>(Hb[0], Hb[1], Et, cs, rflag, r, trH, max_sweeps, conv);
+    if (lane < r) lam[lane] = fmax(Hf[lane * LD + lane], 0.0);
+    __syncthreads();
+    if (lane < r) {
+        int pos = 0;
+        const double li = lam[lane];
+        for (int j = 0; j < r; ++j) pos += (lam[j] > li) || (lam[j] == li && j < lane);
+        perm[pos] = lane;
+    }
+    __syncthreads();
+
+    // ---- rank rule: discarded energy of rank k = sum_{j>=k} lambda_(j) + trace(S)
+    int cap = kcap < it.kmax ? kcap : it.kmax;
+    if (cap > r) cap = r;
+    int kf = cap, code = 0;
+    double tail_k;
+    {
+        double tail = remS;
+        for (int j = 0; j < r; ++j) tail += lam[j];  // rank 0
+        if (mode == TSVDM_RANK_ENERGY) {
+            const double bound = tau * tau * trG;
+            kf = -1;
+            for (int k = 0; k <= cap; ++k) {
+                if (tail <= bound) {
+                    kf = k;
+                    break;
+                }
+                if (k < r) tail -= lam[perm[k]];
+            }
+            if (kf < 0) {  // tolerance not met within the cap
+                kf = cap;
+                code = 4;
+            }
+        }
+        // recompute the tail of the chosen rank from the smallest eigenvalues up
+        tail_k = remS;
+        for (int j = r - 1; j >= kf; --j) tail_k += lam[perm[j]];
+    }
+    if (!conv && r > 1) code = 1;
+    if (!isfinite(trG)) code = 3;
+
+    // ---- outputs: S, U = R^T U_H / sigma, rank, cert, fro
+    for (int j = lane; j < it.kmax; j += 64) it.S[j] = j < kf ? sqrt(lam[perm[j]]) : 0.0;
+    if (lane < m) {
+        for (int j = 0; j < it.kmax; ++j) {
+            float out = 0.0f;
+            if (j < kf) {
+                const int c = perm[j];
+                const double sg = sqrt(lam[c]);
+                double u = 0.0;
+                for (int t = 0; t < r; ++t) u += R[t * MX + lane] * Et[c * LDE + t];
+                out = sg > 0.0 ? (float)(u / sg) : 0.0f;
+            }
+            it.U[lane + (int64_t)m * j] = out;
+        }
+    }
+    if (lane == 0) {
+        *it.rank = kf;
+        if (it.cert) *it.cert = sqrt(fmax(tail_k, 0.0));
+        if (it.fro) *it.fro = sqrt(trG);
+        if (it.info) *it.info = code;
+    }
+}
+
+// ---------------------------------------------------------------- V
+template <int KC>
+__global__ __launch_bounds__(BT) void k_bvec(const Item *__restrict__ items, int nitems,
+                                             int *__restrict__ counter) {
+    constexpr int NG = BT / KC;  // column threads share a column, NG rank groups
+    __shared__ float xs[KC * LDX];
+    __shared__ float us[MX * (KMAXB + 1)];
+    __shared__ float isg[KMAXB];
+    __shared__ int s_idx;
+    const int tid = threadIdx.x, c = tid % KC, g = tid / KC;
+    for (;;) {
+        const int idx = next_item(counter, &s_idx);
+        if (idx >= nitems) break;
+        const Item it = items[idx];
+        const int m = it.m, p = it.p, kmax = it.kmax;
+        const int kf = *it.rank;
+        for (int e = tid; e < m * kf; e += BT) {
+            const int i = e % m, j = e / m;
+            us[i * (KMAXB + 1) + j] = it.U[i + (int64_t)m * j];
+        }
+        for (int j = tid; j < kf; j += BT) {
+            const double s = it.S[j];
+            isg[j] = s > 0.0 ? (float)(1.0 / s) : 0.0f;
+        }
+        for (int e = tid; e < KC * LDX; e += BT) xs[e] = 0.0f;
+        Stager<KC> sg;
+        sg.init(it.X, m, p);
+        const int nck = (p + KC - 1) / KC;
+        sg.load(0);
+        __syncthreads();
+        for (int ch = 0; ch < nck; ++ch) {
+            sg.store(xs);
+            __syncthreads();
+            if (ch + 1 < nck) sg.load(ch + 1);
+            const int col = ch * KC + c;
+            for (int j = g; j < kmax; j += NG) {
+                float acc = 0.0f;
+                if (j < kf) {
+                    for (int i = 0; i < m; ++i) acc += xs[c * LDX + i] * us[i * (KMAXB + 1) + j];
+                    acc *= isg[j];
+                }
+                if (col < p) it.V[col + (int64_t)p * j] = acc;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ void k_bzero(int *__restrict__ c) {
+    if (threadIdx.x < 2) c[threadIdx.x] = 0;
+}
+
+constexpr size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t items, gram, counters, total;
+};
+
+Layout layout(int64_t nitems, int64_t gram_doubles) {
+    Layout L;
+    L.items = 0;
+    L.gram = L.items + al256(sizeof(Item) * nitems);
+    L.counters = L.gram + al256(sizeof(double) * gram_doubles);
+    L.total = L.counters + 256;
+    return L;
+}
+
+struct Cfg {
+    int gram_wpc, gram_kc, vec_wpc, tuned;
+};
+
+std::mutex g_tune_mu;
+std::map<uint64_t, Cfg> g_tune;
+
+}  // namespace
+
+struct tsvdm_batched_plan_s {
+    int32_t nmat = 0, nitems = 0, num_cu = 0;
+    Item *d_items = nullptr;
+    int32_t *d_counter = nullptr;
+    int mode = 0, kcap = 0, max_sweeps = 30;
+    double tau = 0.0;
+    Cfg cfg{2, 64, 2, 0};
+    uint64_t sig = 0;
+};
+
+namespace {
+
+bool check_batch(int32_t nmat, const tsvdm_tensor *X, int64_t *nitems, int64_t *gram) {
+    if (nmat < 1 || !X) {
+        set_error("batched: nmat >= 1 and a tensor array are required");
+        return false;
+    }
+    int64_t n = 0, gd = 0;
+    for (int32_t i = 0; i < nmat; ++i) {
+        const tsvdm_tensor &t = X[i];
+        if (t.dtype != TSVDM_F32) {
+            set_error("batched: tensor %d must be TSVDM_F32", i);
+            return false;
+        }
+        if (t.m < 1 || t.m > MX || t.p < 1 || t.n3 < 1 || t.p > (int64_t(1) << 24) || t.n3 > (1 << 20)) {
+            set_error("batched: tensor %d has m=%lld p=%lld n3=%lld (need 1 <= m <= 64, p <= 2^24)", i,
+                      (long long)t.m, (long long)t.p, (long long)t.n3);
+            return false;
+        }
+        if (t.s_a != 1 || t.s_b != t.m || t.s_t != t.m * t.p || t.bsplit != 0) {
+            set_error("batched: tensor %d must be dense column major (strides 1, m, m*p)", i);
+            return false;
+        }
+        n += t.n3;
+        gd += t.n3 * t.m * t.m;
+    }
+    if (n > (int64_t(1) << 30)) {
+        set_error("batched: too many faces (%lld)", (long long)n);
+        return false;
+    }
+    *nitems = n;
+    *gram = gd;
+    return true;
+}
+
+uint64_t signature(int64_t nitems, const std::vector<Item> &items) {
+    int maxm = 0;
+    double elems = 0.0;
+    for (const Item &it : items) {
+        maxm = std::max(maxm, (int)it.m);
+        elems += (double)it.m * it.p;
+    }
+    int lg = 0;
+    while (lg < 62 && std::ldexp(1.0, lg + 1) <= elems) ++lg;
+    int ln = 0;
+    while (ln < 40 && (int64_t(1) << (ln + 1)) <= nitems) ++ln;
+    return (uint64_t)maxm | ((uint64_t)lg << 8) | ((uint64_t)ln << 16);
+}
+
+tsvdm_status launch(const tsvdm_batched_plan_s *P, const Cfg &cfg, hipStream_t s, int which) {
+    // which: bit 0 Gram, bit 1 core, bit 2 V (always preceded by the queue reset)
+    TSVDM_LAUNCH("batched_reset", k_bzero, dim3(1), dim3(64), 0, s, P->d_counter);
+    if (which & 1) {
+        const dim3 grid((unsigned)(P->num_cu * cfg.gram_wpc));
+        if (cfg.gram_kc == 32)
+            TSVDM_LAUNCH("batched_gram", k_bgram<32>, grid, dim3(BT), 0, s, P->d_items, P->nitems, P->d_counter);
+        else
+            TSVDM_LAUNCH("batched_gram", k_bgram<64>, grid, dim3(BT), 0, s, P->d_items, P->nitems, P->d_counter);
+    }
+    if (which & 2)
+        TSVDM_LAUNCH("batched_core", k_bcore, dim3((unsigned)P->nitems), dim3(64), 0, s, P->d_items, P->mode,
+                     P->kcap, P->tau, P->max_sweeps);
+    if (which & 4) {
+        const dim3 grid((unsigned)(P->num_cu * cfg.vec_wpc));
+        TSVDM_LAUNCH("batched_vec", k_bvec<64>, grid, dim3(BT), 0, s, P->d_items, P->nitems, P->d_counter + 1);
+    }
+    TSVDM_LAUNCH_CHECK("batched truncate");
+    return TSVDM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tsvdm_batched_workspace_size(int32_t nmat, const tsvdm_tensor *Xhat) {
+    int64_t n = 0, gd = 0;
+    if (!check_batch(nmat, Xhat, &n, &gd)) return 0;
+    return layout(n, gd).total;
+}
+
+tsvdm_status tsvdm_batched_plan_create(int32_t nmat, const tsvdm_tensor *Xhat,
+                                       const tsvdm_truncate_opts *o, const tsvdm_factors *F,
+                                       void *ws, size_t ws_bytes, tsvdm_batched_plan **plan) {
+    if (!plan) {
+        set_error("batched_plan_create: plan is NULL");
+        return TSVDM_EINVAL;
+    }
+    *plan = nullptr;
+    int64_t n = 0, gd = 0;
+    if (!check_batch(nmat, Xhat, &n, &gd)) return TSVDM_EINVAL;
+    if (!o || !F) {
+        set_error("batched_plan_create: opts and factors are required");
+        return TSVDM_EINVAL;
+    }
+    if (o->rank_mode != TSVDM_RANK_FIXED && o->rank_mode != TSVDM_RANK_ENERGY) {
+        set_error("batched_plan_create: unknown rank_mode %d", o->rank_mode);
+        return TSVDM_EINVAL;
+    }
+    if (o->k < 1 || o->k > KMAXB) {
+        set_error("batched_plan_create: k must be in 1..%d (got %d)", KMAXB, o->k);
+        return TSVDM_EINVAL;
+    }
+    if (o->rank_mode == TSVDM_RANK_ENERGY && !(o->tau > 0.0 && o->tau < 1.0)) {
+        set_error("batched_plan_create: ENERGY needs 0 < tau < 1");
+        return TSVDM_EINVAL;
+    }
+    if (o->max_sweeps < 0) {
+        set_error("batched_plan_create: max_sweeps must be >= 0");
+        return TSVDM_EINVAL;
+    }
+    for (int32_t i = 0; i < nmat; ++i) {
+        const tsvdm_factors &f = F[i];
+        const tsvdm_tensor &t = Xhat[i];
+        if (f.dtype != TSVDM_F32 || f.m != t.m || f.p != t.p || f.nf != t.n3 || f.kmax < o->k ||
+            f.kmax > KMAXB) {
+            set_error("batched_plan_create: factors %d must be F32 with m, p, nf of the tensor and "
+                      "k <= kmax <= %d", i, KMAXB);
+            return TSVDM_EINVAL;
+        }
+        if (!t.data || !f.U || !f.S || !f.V || !f.ranks) {
+            set_error("batched_plan_create: NULL data/U/S/V/ranks for matrix %d", i);
+            return TSVDM_EINVAL;
+        }
+    }
+    const Layout L = layout(n, gd);
+    if (!ws || ws_bytes < L.total) {
+        set_error("batched_plan_create: workspace of %zu bytes needed, %zu given", L.total, ws_bytes);
+        return TSVDM_EWORKSPACE;
+    }
+    char *base = reinterpret_cast<char *>(ws);
+    std::vector<Item> items;
+    items.reserve(n);
+    double *gp = reinterpret_cast<double *>(base + L.gram);
+    for (int32_t i = 0; i < nmat; ++i) {
+        const tsvdm_tensor &t = Xhat[i];
+        const tsvdm_factors &f = F[i];
+        for (int64_t fc = 0; fc < t.n3; ++fc) {
+            Item it{};
+            it.X = reinterpret_cast<const float *>(t.data) + fc * t.m * t.p;
+            it.U = reinterpret_cast<float *>(f.U) + fc * t.m * f.kmax;
+            it.V = reinterpret_cast<float *>(f.V) + fc * t.p * f.kmax;
+            it.S = f.S + fc * f.kmax;
+            it.G = gp;
+            gp += t.m * t.m;
+            it.rank = f.ranks + fc;
+            it.cert = f.cert ? f.cert + fc : nullptr;
+            it.fro = f.fro ? f.fro + fc : nullptr;
+            it.info = f.info ? f.info + fc : nullptr;
+            it.m = (int32_t)t.m;
+            it.p = (int32_t)t.p;
+            it.kmax = (int32_t)f.kmax;
+            items.push_back(it);
+        }
+    }
+    // longest first: the queue then ends on short items (less tail imbalance)
+    std::stable_sort(items.begin(), items.end(), [](const Item &a, const Item &b) {
+        return (int64_t)a.m * a.m * a.p > (int64_t)b.m * b.m * b.p;
+    });
+    int dev = 0, ncu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_check(e, "batched_plan_create: device query");
+    e = hipMemcpy(base + L.items, items.data(), sizeof(Item) * items.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_check(e, "batched_plan_create: face table upload");
+    auto *P = new (std::nothrow) tsvdm_batched_plan_s();
+    if (!P) {
+        set_error("batched_plan_create: out of host memory");
+        return TSVDM_EINVAL;
+    }
+    P->nmat = nmat;
+    P->nitems = (int32_t)n;
+    P->num_cu = ncu > 0 ? ncu : 1;
+    P->d_items = reinterpret_cast<Item *>(base + L.items);
+    P->d_counter = reinterpret_cast<int32_t *>(base + L.counters);
+    P->mode = o->rank_mode;
+    P->kcap = o->k;
+    P->tau = o->tau;
+    P->max_sweeps = o->max_sweeps > 0 ? o->max_sweeps : 30;
+    P->sig = signature(n, items);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto hit = g_tune.find(P->sig);
+        if (hit != g_tune.end()) P->cfg = hit->second;
+    }
+    *plan = P;
+    return TSVDM_OK;
+}
+
+tsvdm_status tsvdm_truncate_batched(const tsvdm_batched_plan *plan, void *stream) {
+    if (!plan) {
+        set_error("truncate_batched: plan is NULL");
+        return TSVDM_EINVAL;
+    }
+    return launch(plan, plan->cfg, (hipStream_t)stream, 7);
+}
+
+tsvdm_status tsvdm_batched_autotune(tsvdm_batched_plan *plan, void *stream) {
+    if (!plan) {
+        set_error("batched_autotune: plan is NULL");
+        return TSVDM_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    // one full run so that the core's outputs (ranks, U, S) exist for the V kernel
+    tsvdm_status st = launch(plan, plan->cfg, s, 7);
+    if (st != TSVDM_OK) return st;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipError_t e = hipEventCreate(&a);
+    if (e == hipSuccess) e = hipEventCreate(&b);
+    if (e != hipSuccess) return hip_check(e, "batched_autotune: events");
+    auto time_cfg = [&](const Cfg &c, int which, float *best) -> tsvdm_status {
+        *best = 1e30f;
+        for (int rep = 0; rep < 3; ++rep) {
+            hipError_t er = hipEventRecord(a, s);
+            if (er != hipSuccess) return hip_check(er, "batched_autotune: record");
+            tsvdm_status st2 = launch(plan, c, s, which);
+            if (st2 != TSVDM_OK) return st2;
+            er = hipEventRecord(b, s);
+            if (er == hipSuccess) er = hipEventSynchronize(b);
+            float ms = 0.0f;
+            if (er == hipSuccess) er = hipEventElapsedTime(&ms, a, b);
+            if (er != hipSuccess) return hip_check(er, "batched_autotune: timing");
+            if (rep > 0 && ms < *best) *best = ms;  // the first run warms up
+        }
+        return TSVDM_OK;
+    };
+    Cfg best = plan->cfg;
+    float tg = 1e30f, tv = 1e30f;
+    const int wpcs[3] = {1, 2, 4}, kcs[2] = {32, 64};
+    for (int w : wpcs)
+        for (int kc : kcs) {
+            Cfg c = best;
+            c.gram_wpc = w;
+            c.gram_kc = kc;
+            float t = 0.0f;
+            st = time_cfg(c, 1, &t);
+            if (st != TSVDM_OK) break;
+            if (t < tg) {
+                tg = t;
+                best.gram_wpc = w;
+                best.gram_kc = kc;
+            }
+        }
+    if (st == TSVDM_OK)
+        for (int w : wpcs) {
+            Cfg c = best;
+            c.vec_wpc = w;
+            float t = 0.0f;
+            st = time_cfg(c, 4, &t);
+            if (st != TSVDM_OK) break;
+            if (t < tv) {
+                tv = t;
+                best.vec_wpc = w;
+            }
+        }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != TSVDM_OK) return st;
+    best.tuned = 1;
+    plan->cfg = best;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[plan->sig] = best;
+    }
+    // leave the outputs of a complete run with the chosen configuration
+    return launch(plan, plan->cfg, s, 7);
+}
+
+tsvdm_status tsvdm_batched_config(const tsvdm_batched_plan *plan, int32_t cfg[4]) {
+    if (!plan || !cfg) {
+        set_error("batched_config: NULL argument");
+        return TSVDM_EINVAL;
+    }
+    cfg[0] = plan->cfg.gram_wpc;
+    cfg[1] = plan->cfg.gram_kc;
+    cfg[2] = plan->cfg.vec_wpc;
+    cfg[3] = plan->cfg.tuned;
+    return TSVDM_OK;
+}
+
+void tsvdm_batched_plan_destroy(tsvdm_batched_plan *plan) { delete plan; }
+
+}  // extern "C"

@@ -28,6 +28,7 @@
 // MFMA tiles; the next slab's loads are issued before the current slab's
 // MFMAs.  The small FP64 steps use one workgroup per face.
 #include "common.h"
+#include "jacobi_dev.h"
 
 #include <math.h>
 
@@ -58,26 +59,6 @@ __device__ __forceinline__ f32x4 mfma(const u16x8 &a, const u16x8 &b, f32x4 c) {
 // XCD L % 8, each with its own L2).  For a pass whose nb blocks of a face all
 // read the same per-face operand, give those blocks consecutive slots on one
 // XCD, so the operand is fetched into that L2 once instead of eight times.
-// 1/a for a > 0 normal: hardware reciprocal refined by two Newton steps
-// (error within an ulp or two; used for Cholesky multipliers, where that is
-// below the rounding of the update itself)
-__device__ __forceinline__ double recip(double a) {
-    double r = __builtin_amdgcn_rcp(a);
-    double e = fma(-a, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-a, r, 1.0);
-    return fma(r, e, r);
-}
-
-// 1/sqrt(a) for a > 0 normal: hardware estimate refined by two Newton steps
-__device__ __forceinline__ double rsqrt_nr(double a) {
-    double y = __builtin_amdgcn_rsq(a);
-    double e = fma(-a * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    e = fma(-a * y, y, 1.0);
-    return fma(0.5 * y, e, y);
-}
-
 // G (LDS, pitch ldg) = ordered sum over pp of the nparts LP x LP row-major
 // FP64 partials of face f.  All loads of a block of 8 partials are issued
 // before any is summed (clamped addresses, zero-selected, no branches).
@@ -689,56 +670,14 @@ __global__ __launch_bounds__(GT) void k_resid(const float *__restrict__ X, int m
 }
 
 // ---------------------------------------------------------------- core SVD
-// B B^T (sum of the projection's FP64 per-block Gram partials), cyclic Jacobi
-// eigensolver with the round-robin ordering: in round r the ne/2 disjoint
-// pairs are (r, ne-1) and ((r+k) mod (ne-1), (r-k) mod (ne-1)), k = 1..ne/2-1,
-// and every 2x2 block of B B^T (pair p rows, pair q columns) becomes
-// J_p^T B J_q at once; the eigenvector columns likewise.
-// One barrier per round: the matrix is double buffered and every thread
-// forms the rotations its blocks need from the current buffer (the symmetric
-// Schur 2x2 step, t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)) written without
-// the quotient zeta).  Only blocks p <= q are computed; each writes its mirror.
+// B B^T (sum of the projection's FP64 per-block Gram partials), its
+// eigenvalues and eigenvectors by the cyclic Jacobi solver of jacobi_dev.h.
 // Entries of B B^T are below 2^300 (squares of FP32 data summed over at most
-// 2^16 rows), so d^2 + e^2 cannot overflow.
+// 2^16 rows), so the rotation arithmetic cannot overflow.
 // Eigenvalues sorted decreasing, rank rule, certificate
 //   cert^2 = ||X - Q B||^2 + sum_{j > k_f} lambda_j
 // (the error of Q U_B[:, :k] U_B[:, :k]^T B, since Q has orthonormal columns).
 // The energy rule takes the smallest k whose certified error meets tau.
-__device__ __forceinline__ void rr_pair(int r, int k, int n1, int &a, int &b) {
-    if (k == 0) {
-        a = r;
-        b = n1;
-    } else {
-        a = r + k;
-        if (a >= n1) a -= n1;
-        b = r - k;
-        if (b < 0) b += n1;
-    }
-    if (a > b) {
-        const int t = a;
-        a = b;
-        b = t;
-    }
-}
-
-// rotation (c, s) of a pair from its entries app, aqq, apq; identity (and
-// false) when the pair is a padding pair or the off-diagonal entry is
-// negligible (relative to the diagonal pair, and at the rounding level of the
-// trace).  Branch free, so that the caller's loads are all issued up front.
-__device__ __forceinline__ bool jrot(double app, double aqq, double apq, bool valid, double trace,
-                                     double &c, double &s) {
-    const bool go = valid && apq * apq > 1e-30 * fabs(app * aqq) && fabs(apq) > 1e-15 * trace;
-    const double d = aqq - app, e = 2.0 * apq;
-    const double q = go ? fma(d, d, e * e) : 1.0;
-    const double h = q * rsqrt_nr(q);
-    double t = fabs(e) * recip(go ? fabs(d) + h : 1.0);
-    t = (d == 0.0 || ((d > 0.0) == (e > 0.0))) ? t : -t;
-    const double cc = rsqrt_nr(fma(t, t, 1.0));
-    c = go ? cc : 1.0;
-    s = go ? cc * t : 0.0;
-    return go;
-}
-
 template <int LP>
 __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, int nparts, int ell,
                                              const double *__restrict__ fro_part, int nfro,
@@ -749,7 +688,6 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
                                              double *__restrict__ fro2_out, double *__restrict__ cert,
                                              int32_t *__restrict__ jinfo) {
     constexpr int LD = LP + 1, LDE = LP + 2, NPM = LP / 2;
-    constexpr int IPT = (NPM * (NPM + 1) / 2 + (LP / 4) * NPM + QT - 1) / QT;  // items per thread
     __shared__ double Gb[2][LP * LD];
     __shared__ __align__(16) double Et[LP * LDE];  // eigenvectors transposed: Et[c * LDE + r] = E[r][c]
     __shared__ __align__(16) double2 cs[2][NPM];   // rotations of the previous round, for E
@@ -757,8 +695,7 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
     __shared__ int perm[LP];
     __shared__ double trace_s;
     __shared__ int rflag[3];
-    const int f = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
-    const int ne = ell + (ell & 1), np = ne / 2, n1 = ne - 1;
+    const int f = blockIdx.x, tid = threadIdx.x;
     for (int e = tid; e < LP * LD; e += QT) Gb[0][e] = 0.0;
     for (int e = tid; e < LP * LDE; e += QT) Et[e] = 0.0;
     __syncthreads();
@@ -777,114 +714,8 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
     __syncthreads();
     const double trace = trace_s;
 
-    // this thread's items, fixed for all rounds: G block (pp <= qq) or E block
-    // (rows 4*qd .. 4*qd+3, pair qq)
-    const int ng = np * (np + 1) / 2, nq = (ne + 3) / 4, nitems = ng + nq * np;
-    int ik[IPT], i1[IPT], i2[IPT];
-#pragma unroll
-    for (int u = 0; u < IPT; ++u) {
-        const int it = tid + u * QT;
-        ik[u] = it < ng ? 0 : it < nitems ? 1 : 2;
-        if (ik[u] == 0) {
-            int pp = 0, rem = it;
-            while (rem >= np - pp) {
-                rem -= np - pp;
-                ++pp;
-            }
-            i1[u] = pp;
-            i2[u] = pp + rem;
-        } else if (ik[u] == 1) {
-            i1[u] = (it - ng) / np;
-            i2[u] = (it - ng) % np;
-        } else {
-            i1[u] = i2[u] = 0;
-        }
-    }
-    // E block item: apply the rotations of round r (stored in cs[par]) to its
-    // four rows of the eigenvector columns of pair i2
-    auto e_item = [&](int u, int r, int par) {
-        int c2, d;
-        rr_pair(r, i2[u], n1, c2, d);
-        const int r0 = 4 * i1[u];
-        double2 *pc = reinterpret_cast<double2 *>(Et + c2 * LDE + r0);
-        double2 *pd = reinterpret_cast<double2 *>(Et + d * LDE + r0);
-        const double2 rt = cs[par][i2[u]];
-        const double2 x0 = pc[0], x1 = pc[1], y0 = pd[0], y1 = pd[1];
-        pc[0] = double2{rt.x * x0.x - rt.y * y0.x, rt.x * x0.y - rt.y * y0.y};
-        pc[1] = double2{rt.x * x1.x - rt.y * y1.x, rt.x * x1.y - rt.y * y1.y};
-        pd[0] = double2{rt.y * x0.x + rt.x * y0.x, rt.y * x0.y + rt.x * y0.y};
-        pd[1] = double2{rt.y * x1.x + rt.x * y1.x, rt.y * x1.y + rt.x * y1.y};
-    };
-
-    int sweep = 0, conv = 0, cur = 0, rr = 0;  // rr counts rounds over all sweeps
-    for (sweep = 1; sweep <= max_sweeps && ell > 1; ++sweep) {
-        const int fl = sweep % 3;
-        for (int r = 0; r < n1; ++r, ++rr) {
-            const double *Gc = Gb[cur];
-            double *Gn = Gb[cur ^ 1];
-            bool any = false;
-#pragma unroll
-            for (int u = 0; u < IPT; ++u) {
-                if (ik[u] == 2) continue;
-                if (ik[u] == 0) {
-                    int a, b, c2, d;
-                    rr_pair(r, i1[u], n1, a, b);
-                    rr_pair(r, i2[u], n1, c2, d);
-                    // every load of the item first
-                    const double m00 = Gc[a * LD + c2], m01 = Gc[a * LD + d];
-                    const double m10 = Gc[b * LD + c2], m11 = Gc[b * LD + d];
-                    const double paa = Gc[a * LD + a], pbb = Gc[b * LD + b], pab = Gc[a * LD + b];
-                    const double qcc = Gc[c2 * LD + c2], qdd = Gc[d * LD + d], qcd = Gc[c2 * LD + d];
-                    double cp, sp, cq, sq;
-                    any |= jrot(paa, pbb, pab, b < ell, trace, cp, sp);
-                    jrot(qcc, qdd, qcd, d < ell, trace, cq, sq);
-                    // rows: (a, b) <- (cp a - sp b, sp a + cp b); then the columns
-                    const double t00 = cp * m00 - sp * m10, t01 = cp * m01 - sp * m11;
-                    const double t10 = sp * m00 + cp * m10, t11 = sp * m01 + cp * m11;
-                    const double n00 = cq * t00 - sq * t01, n01 = sq * t00 + cq * t01;
-                    const double n10 = cq * t10 - sq * t11, n11 = sq * t10 + cq * t11;
-                    if (i2[u] != i1[u]) {
-                        Gn[a * LD + c2] = n00;
-                        Gn[a * LD + d] = n01;
-                        Gn[b * LD + c2] = n10;
-                        Gn[b * LD + d] = n11;
-                        Gn[c2 * LD + a] = n00;
-                        Gn[d * LD + a] = n01;
-                        Gn[c2 * LD + b] = n10;
-                        Gn[d * LD + b] = n11;
-                    } else {  // diagonal block: kept exactly symmetric; its rotation
-                              // goes to the eigenvectors in the next round
-                        Gn[a * LD + a] = n00;
-                        Gn[a * LD + b] = n01;
-                        Gn[b * LD + a] = n01;
-                        Gn[b * LD + b] = n11;
-                        cs[rr & 1][i1[u]] = double2{cp, sp};
-                    }
-                } else if (rr > 0) {
-                    e_item(u, r > 0 ? r - 1 : n1 - 1, (rr - 1) & 1);
-                }
-            }
-            // one flag write per wavefront that rotated
-            if (__any(any) && lane == 0) rflag[fl] = 1;
-            __syncthreads();
-            // the flag of sweep+2 is cleared after the first barrier of this
-            // sweep, when every thread has read it at the end of sweep-1
-            if (r == 0 && tid == 0) rflag[(sweep + 2) % 3] = 0;
-            cur ^= 1;
-        }
-        if (rflag[fl] == 0) {
-            conv = 1;
-            break;
-        }
-    }
-    // the eigenvectors take the last round's rotations
-    if (rr > 0) {
-#pragma unroll
-        for (int u = 0; u < IPT; ++u)
-            if (ik[u] == 1) e_item(u, (rr - 1) % n1, (rr - 1) & 1);
-    }
-    __syncthreads();
-    const double *G = Gb[cur];
+    int conv = 0;
+    const double *G = jacobi_eig<LP, QT>(Gb[0], Gb[1], Et, &cs[0][0], rflag, ell, trace, max_sweeps, conv);
     if (tid < ell) lam[tid] = fmax(G[tid * LD + tid], 0.0);
     __syncthreads();
     if (tid < ell) {

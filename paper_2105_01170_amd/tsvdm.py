@@ -53,7 +53,9 @@ class TsvdmFactors(ctypes.Structure):
 EXPORTS = ["tsvdm_version", "tsvdm_last_error", "tsvdm_tensor_from_blockmat",
            "tsvdm_check_orthogonal", "tsvdm_transform", "tsvdm_truncate_workspace_size",
            "tsvdm_truncate", "tsvdm_apply_workspace_size", "tsvdm_apply", "tsvdm_timing_enable",
-           "tsvdm_timing_count", "tsvdm_timing_get"]
+           "tsvdm_timing_count", "tsvdm_timing_get", "tsvdm_batched_workspace_size",
+           "tsvdm_batched_plan_create", "tsvdm_truncate_batched", "tsvdm_batched_autotune",
+           "tsvdm_batched_config", "tsvdm_batched_plan_destroy"]
 
 _LIB = None
 
@@ -93,6 +95,19 @@ def lib():
         L.tsvdm_timing_count.argtypes = []
         L.tsvdm_timing_get.restype = i32
         L.tsvdm_timing_get.argtypes = [i32, P(ctypes.c_char_p), P(i32), P(ctypes.c_double)]
+        L.tsvdm_batched_workspace_size.restype = sz
+        L.tsvdm_batched_workspace_size.argtypes = [i32, P(TsvdmTensor)]
+        L.tsvdm_batched_plan_create.restype = i32
+        L.tsvdm_batched_plan_create.argtypes = [i32, P(TsvdmTensor), P(TsvdmTruncateOpts),
+                                                P(TsvdmFactors), vp, sz, P(vp)]
+        L.tsvdm_truncate_batched.restype = i32
+        L.tsvdm_truncate_batched.argtypes = [vp, vp]
+        L.tsvdm_batched_autotune.restype = i32
+        L.tsvdm_batched_autotune.argtypes = [vp, vp]
+        L.tsvdm_batched_config.restype = i32
+        L.tsvdm_batched_config.argtypes = [vp, P(i32)]
+        L.tsvdm_batched_plan_destroy.restype = None
+        L.tsvdm_batched_plan_destroy.argtypes = [vp]
         _LIB = L
     return _LIB
 
@@ -154,6 +169,47 @@ def tsvdm_apply(M: TsvdmMdesc, F: TsvdmFactors, ell: int, q: int, nrhs: int, x_p
                 y_ptr: int, ldy: int, compute: int, ws_ptr: int, ws_bytes: int, stream: int = 0):
     _check(lib().tsvdm_apply(ctypes.byref(M), ctypes.byref(F), ell, q, nrhs, x_ptr, ldx, y_ptr,
                              ldy, compute, ws_ptr, ws_bytes, stream))
+
+
+def _array(ctype, items):
+    arr = (ctype * len(items))()
+    for i, it in enumerate(items):
+        arr[i] = it
+    return arr
+
+
+def tsvdm_batched_workspace_size(Xs: list) -> int:
+    return lib().tsvdm_batched_workspace_size(len(Xs), _array(TsvdmTensor, Xs))
+
+
+def tsvdm_batched_plan_create(Xs: list, opts: TsvdmTruncateOpts, Fs: list, ws_ptr: int,
+                              ws_bytes: int) -> int:
+    """Returns the opaque host plan handle (an address)."""
+    if len(Xs) != len(Fs):
+        raise ValueError("one factors descriptor per tensor")
+    h = ctypes.c_void_p()
+    _check(lib().tsvdm_batched_plan_create(len(Xs), _array(TsvdmTensor, Xs), ctypes.byref(opts),
+                                           _array(TsvdmFactors, Fs), ws_ptr, ws_bytes,
+                                           ctypes.byref(h)))
+    return h.value
+
+
+def tsvdm_truncate_batched(plan: int, stream: int = 0):
+    _check(lib().tsvdm_truncate_batched(plan, stream))
+
+
+def tsvdm_batched_autotune(plan: int, stream: int = 0):
+    _check(lib().tsvdm_batched_autotune(plan, stream))
+
+
+def tsvdm_batched_config(plan: int) -> list:
+    cfg = (ctypes.c_int32 * 4)()
+    _check(lib().tsvdm_batched_config(plan, cfg))
+    return list(cfg)
+
+
+def tsvdm_batched_plan_destroy(plan: int):
+    lib().tsvdm_batched_plan_destroy(plan)
 
 
 def tsvdm_timing_enable(on: bool):

@@ -78,10 +78,13 @@ def known_rank_factors(m: int = 512, p: int = 512, n3: int = 256, k: int = 32,
 
 
 def uneven_batch(count: int = 256, lo: int = 16, hi: int = 64, rmin: int = 2, rmax: int = 16,
-                 noise: float = 1e-6, index: int = 2, salt: int = 0):
+                 noise: float = 1e-6, index: int = 2, salt: int = 0, form: bool = True):
     """Independent Kronecker-sum matrices sum_{i<r} B_i kron C_i with square
     factors of sizes s_B, s_C = round(exp(U(ln lo, ln hi))) and r uniform in
-    {rmin..rmax}, iid N(0,1) entries, plus relative noise."""
+    {rmin..rmax}, iid N(0,1) entries, plus relative noise.  With form=False
+    only the factors are returned (no A; noise must be 0)."""
+    if not form and noise:
+        raise ValueError("noise needs the formed matrix")
     g = rng(index, salt)
     out = []
     for _ in range(count):
@@ -90,8 +93,11 @@ def uneven_batch(count: int = 256, lo: int = 16, hi: int = 64, rmin: int = 2, rm
         r = int(g.integers(rmin, rmax + 1))
         B = g.standard_normal((r, sB, sB))
         C = g.standard_normal((r, sC, sC))
-        A = add_relative_noise(g, kron_sum(B, C), noise)
-        out.append(dict(A=A, sB=sB, sC=sC, r=r, ell=sB, q=sB, m=sC, n=sC))
+        rec = dict(B=B, C=C, sB=sB, sC=sC, r=r, ell=sB, q=sB, m=sC, n=sC)
+        if form:
+            A = kron_sum(B, C)
+            rec["A"] = add_relative_noise(g, A, noise) if noise else A
+        out.append(rec)
     return out
 
 

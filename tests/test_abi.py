@@ -183,3 +183,47 @@ def test_apply_validation():
     assert e.value.status == C.EWORKSPACE
     with pytest.raises(C.TsvdmError):  # compute precision vs factors
         C.tsvdm_apply(M, F, 3, 4, 10, 0x1000, 32, 0x2000, 18, C.F64, 0x3000, 1 << 20, 0)
+
+
+def test_batched_validation_and_workspace():
+    """Shape, dtype, stride, option and workspace errors of the batched entry
+    points are reported before any device work (no GPU needed)."""
+    Xs = [_t(16, 256, 16, C.F32, 0x1000), _t(40, 900, 40, C.F32, 0x2000)]
+    ws = C.tsvdm_batched_workspace_size(Xs)
+    # face table + FP64 Gram of every face + queue counters
+    assert ws >= 16 * 16 * 16 * 8 + 40 * 40 * 40 * 8
+    Fs = [C.factors(16, 256, 16, 16, C.F32, 0x3000, 0x4000, 0x5000, 0x6000),
+          C.factors(40, 900, 40, 16, C.F32, 0x3000, 0x4000, 0x5000, 0x6000)]
+    o = C.truncate_opts(C.RANK_ENERGY, 16, 1e-4)
+    with pytest.raises(C.TsvdmError) as e:        # workspace too small
+        C.tsvdm_batched_plan_create(Xs, o, Fs, 0x7000, ws - 1)
+    assert e.value.status == C.EWORKSPACE
+    bad_tensors = [
+        [_t(65, 256, 16, C.F32)],                  # more than 64 rows
+        [_t(16, 256, 16, C.F64)],                  # FP32 only
+        [_t(0, 256, 16, C.F32)],                   # empty face
+    ]
+    for Xb in bad_tensors:
+        assert C.tsvdm_batched_workspace_size(Xb) == 0
+        with pytest.raises(C.TsvdmError) as e:
+            C.tsvdm_batched_plan_create(Xb, o, Fs[:1], 0x7000, 1 << 30)
+        assert e.value.status == C.EINVAL
+    strided = _t(16, 256, 16, C.F32)
+    strided.s_t += 1
+    assert C.tsvdm_batched_workspace_size([strided]) == 0
+    bad_opts = [C.truncate_opts(C.RANK_ENERGY, 0, 1e-4), C.truncate_opts(C.RANK_ENERGY, 33, 1e-4),
+                C.truncate_opts(C.RANK_ENERGY, 16, 0.0), C.truncate_opts(7, 16, 1e-4)]
+    for ob in bad_opts:
+        with pytest.raises(C.TsvdmError) as e:
+            C.tsvdm_batched_plan_create(Xs, ob, Fs, 0x7000, ws)
+        assert e.value.status == C.EINVAL
+    # factors that do not match their tensor, or kmax below the rank cap
+    Fbad = [C.factors(16, 255, 16, 16, C.F32, 0x3000, 0x4000, 0x5000, 0x6000), Fs[1]]
+    with pytest.raises(C.TsvdmError):
+        C.tsvdm_batched_plan_create(Xs, o, Fbad, 0x7000, ws)
+    Fbad = [C.factors(16, 256, 16, 8, C.F32, 0x3000, 0x4000, 0x5000, 0x6000), Fs[1]]
+    with pytest.raises(C.TsvdmError):
+        C.tsvdm_batched_plan_create(Xs, o, Fbad, 0x7000, ws)
+    with pytest.raises(C.TsvdmError):
+        C.tsvdm_truncate_batched(0, 0)
+    C.tsvdm_batched_plan_destroy(0)
