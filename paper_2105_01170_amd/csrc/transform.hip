@@ -342,6 +342,90 @@ __global__ __launch_bounds__(NT) void k_dense_tubes(const void *__restrict__ in,
     (void)E;
 }
 
+// Real M, n3 <= NMAX (64): the transform of a tile of 64 tubes is the product
+// Y = M X (n3 x n3 times n3 x 64).  The tile is staged through LDS (loads of
+// one time step contiguous across the tubes); four threads share a tube, each
+// holding it in registers and forming every fourth output, with M (row f
+// contiguous) read from LDS by broadcast.  DCT-II coefficients come from a
+// table of cos(pi j / (2 n3)), j < 4 n3.  FP32 data accumulates in FP32 (at
+// most 64 terms), FP64 data in FP64.  INV: M^T.
+template <typename T, int NMAX, bool INV, bool DENSE>
+__global__ __launch_bounds__(NT) void k_direct_small(const T *__restrict__ in, View iv,
+                                                     T *__restrict__ out, int64_t ntubes,
+                                                     int64_t mp, int N, const double *__restrict__ Md) {
+    constexpr int TB = 64, G = NT / TB;
+    constexpr int LDM = NMAX + 4;  // row pitch (keeps 16-byte alignment of rows)
+    __shared__ __align__(16) T Ms[NMAX * LDM];
+    __shared__ T xs[NMAX * TB];
+    __shared__ double ctab[4 * NMAX];
+    const int tid = threadIdx.x, u = tid % TB, g = tid / TB;
+    const int64_t i0 = (int64_t)blockIdx.x * TB;
+    // tile loads first, so that they are in flight while M is built; thread
+    // (u, g) stages time steps g, g+4, ... of tube u
+    {
+        const int64_t i = i0 + u;
+        const bool okl = i < ntubes;
+        const int64_t base = iv.tube_base(okl ? i : 0);
+        // all loads in flight before the first LDS store: clamped (in-bounds)
+        // addresses and a select instead of branches; rows t >= N get zeros
+        T v[NMAX / G];
+#pragma unroll
+        for (int q = 0; q < NMAX / G; ++q) {
+            const int t = g + G * q;
+            v[q] = in[base + (int64_t)(t < N ? t : N - 1) * iv.s_t];
+        }
+#pragma unroll
+        for (int q = 0; q < NMAX / G; ++q) {
+            const int t = g + G * q;
+            xs[t * TB + u] = (okl && t < N) ? v[q] : T(0);
+        }
+    }
+    if (!DENSE)
+        for (int j = tid; j < 4 * N; j += NT) ctab[j] = cospi((double)j / (2.0 * N));
+    for (int e = tid; e < NMAX * LDM; e += NT) Ms[e] = T(0);
+    __syncthreads();
+    // Ms[o * LDM + j]: coefficient of input j in output o.  Thread (o, g)
+    // fills row o at columns j = g, g+4, ...; the cosine table index
+    // (2t+1) f mod 4N advances by a fixed step along the row (no divisions).
+    if (u < N) {
+        const int o = u, fourN = 4 * N;
+        if (DENSE) {
+            for (int j = g; j < N; j += G) Ms[o * LDM + j] = (T)(INV ? Md[j + (int64_t)N * o] : Md[o + (int64_t)N * j]);
+        } else {
+            const double a0c = sqrt(1.0 / N), a1c = sqrt(2.0 / N);
+            // forward: M[o][j], index (2j+1) o; inverse: M[j][o], index (2o+1) j
+            int idx = INV ? ((2 * o + 1) * g) % fourN : ((2 * g + 1) * o) % fourN;
+            const int step = INV ? (G * (2 * o + 1)) % fourN : (2 * G * o) % fourN;
+            for (int j = g; j < N; j += G) {
+                const double a = (INV ? j : o) == 0 ? a0c : a1c;
+                Ms[o * LDM + j] = (T)(a * ctab[idx]);
+                idx += step;
+                if (idx >= fourN) idx -= fourN;
+            }
+        }
+    }
+    __syncthreads();
+    T x[NMAX];
+#pragma unroll
+    for (int t = 0; t < NMAX; ++t) x[t] = xs[t * TB + u];
+    const int64_t i = i0 + u;
+    const bool ok = i < ntubes;
+    for (int o = g; o < N; o += G) {
+        const T *row = Ms + o * LDM;
+        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+        for (int t = 0; t < NMAX; t += 4) {
+            if (t < N) {  // uniform; entries past N are zero in both operands
+                a0 += row[t] * x[t];
+                a1 += row[t + 1] * x[t + 1];
+                a2 += row[t + 2] * x[t + 2];
+                a3 += row[t + 3] * x[t + 3];
+            }
+        }
+        if (ok) out[i + mp * o] = (a0 + a1) + (a2 + a3);
+    }
+}
+
 template <typename K>
 hipError_t allow_lds(K kernel, size_t bytes) {
     if (bytes <= 65536) return hipSuccess;
@@ -412,6 +496,24 @@ tsvdm_status run_dense(int kind, int dir, const tsvdm_mdesc *M, const tsvdm_tens
         TSVDM_LAUNCH("transform_direct", kern, dim3((unsigned)grid), dim3(NT), lds, s, in->data, iv, \
                      out->data, ntubes, mp, N, nf_in, nf_out, TB, M->M);                             \
     } while (0)
+    if (kind != TSVDM_M_DFT && N <= 64) {
+        const int64_t g2 = (ntubes + 63) / 64;
+        const double *Md = M->M;
+#define TSVDM_SMALL_LAUNCH(NM, INV, DN)                                                          \
+    TSVDM_LAUNCH("transform_direct", (k_direct_small<T, NM, INV, DN>), dim3((unsigned)g2), dim3(NT), 0, s, \
+                 reinterpret_cast<const T *>(in->data), iv, reinterpret_cast<T *>(out->data), ntubes, mp, N, Md)
+        const bool dn = kind == TSVDM_M_DENSE;
+        if (N <= 32) {
+            if (dir > 0) { if (dn) TSVDM_SMALL_LAUNCH(32, false, true); else TSVDM_SMALL_LAUNCH(32, false, false); }
+            else { if (dn) TSVDM_SMALL_LAUNCH(32, true, true); else TSVDM_SMALL_LAUNCH(32, true, false); }
+        } else {
+            if (dir > 0) { if (dn) TSVDM_SMALL_LAUNCH(64, false, true); else TSVDM_SMALL_LAUNCH(64, false, false); }
+            else { if (dn) TSVDM_SMALL_LAUNCH(64, true, true); else TSVDM_SMALL_LAUNCH(64, true, false); }
+        }
+#undef TSVDM_SMALL_LAUNCH
+        TSVDM_LAUNCH_CHECK("k_direct_small");
+        return TSVDM_OK;
+    }
     if (kind == TSVDM_M_DCT2) {
         if (dir > 0) TSVDM_DENSE_LAUNCH(DENSE_DCT_FWD);
         else TSVDM_DENSE_LAUNCH(DENSE_DCT_INV);

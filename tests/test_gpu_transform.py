@@ -16,7 +16,9 @@ from paper_2105_01170_amd import tsvdm as C  # noqa: E402
 SHAPES = [(5, 7, 8), (33, 17, 16), (64, 40, 32), (9, 11, 256), (3, 5, 1024), (7, 13, 12),
           (6, 5, 31), (4, 3, 1), (2, 3, 2), (17, 9, 100),
           # whole tiles with 16-byte rows: the vector load/store path
-          (8, 16, 2), (16, 8, 1024), (32, 32, 64)]
+          (8, 16, 2), (16, 8, 1024), (32, 32, 64),
+          # register-tiled direct product for lengths 33..64
+          (9, 14, 45), (3, 300, 63)]
 TOL = {np.float32: 3e-6, np.float64: 1e-12}
 
 
