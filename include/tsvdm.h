@@ -275,6 +275,72 @@ tsvdm_status tsvdm_batched_config(const tsvdm_batched_plan *plan, int32_t cfg[4]
 /* Releases the host plan (the workspace stays the caller's). NULL is allowed. */
 void tsvdm_batched_plan_destroy(tsvdm_batched_plan *plan);
 
+/* ---------------------------------------------------------------- rank predictor
+ * A multilayer perceptron 32 -> 64 -> 64 -> 2 (ReLU hidden layers, linear
+ * output) that predicts, per transform-domain face, (k/32, l/48): the rank and
+ * the sketch width of the randomized truncation (step 2 of Algorithm
+ * alg:strategy), from the features log10(s_j / s_1), j = 1..32, of a 32-column
+ * sketch of the face (tsvdm_rank_features).  Half precision weights, inputs
+ * and hidden activations; FP32 accumulation.
+ * Parameters, flat (6402 values): W1 (64 x 32, row major), b1 (64),
+ * W2 (64 x 64), b2 (64), W3 (2 x 64), b3 (2).  Half buffers hold IEEE binary16
+ * bit patterns.  All pointers are device pointers owned by the caller. */
+
+/* Number of parameters (6402). */
+int64_t tsvdm_mlp_nparams(void);
+
+/* y (n x 2, FP32, row major) = MLP(x) for the n x 32 half inputs x (row major). */
+tsvdm_status tsvdm_mlp_forward(const uint16_t *w16, const uint16_t *x, int64_t n, float *y,
+                               void *stream);
+
+/* Workspace bytes for tsvdm_mlp_gradient / tsvdm_mlp_train_step on n samples. */
+size_t tsvdm_mlp_train_workspace_size(int64_t n);
+
+/* grad (6402, FP32) of loss = sum_s |MLP(x_s) - t_s|^2 / (2n) at the half
+ * weights w16 (forward as tsvdm_mlp_forward, backward in FP32); *loss (device,
+ * may be NULL) receives the loss.  target: n x 2 FP32, row major. */
+tsvdm_status tsvdm_mlp_gradient(const uint16_t *w16, const uint16_t *x, const float *target, int64_t n,
+                                float *grad, float *loss, void *workspace, size_t workspace_bytes,
+                                void *stream);
+
+/* One training step on the batch (x, target): the gradient at w16, then Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias correction for step >= 1) on the FP32
+ * master weights w32 with moments m, v; w16 is refreshed from w32. */
+tsvdm_status tsvdm_mlp_train_step(float *w32, uint16_t *w16, float *m, float *v, int32_t step, float lr,
+                                  const uint16_t *x, const float *target, int64_t n, float *loss,
+                                  void *workspace, size_t workspace_bytes, void *stream);
+
+/* b[i] = a[i] rounded to half (nearest even), i < n. */
+tsvdm_status tsvdm_f32_to_f16(const float *a, uint16_t *b, int64_t n, void *stream);
+
+/* Workspace bytes for tsvdm_rank_features (shapes only); 0 if invalid. */
+size_t tsvdm_rank_features_workspace_size(const tsvdm_tensor *Xhat);
+
+/* Predictor inputs of every face of the dense FP32 transform-domain tensor
+ * Xhat (m >= 32, p >= 40): the singular values s of the sketch
+ * Y = Xhat_f omega[:, :32] (BF16 products, FP32 accumulation; FP64 Gram and
+ * Jacobi eigenvalues), features[f][j] = log10(s_j / s_1) (0 when s_1 = 0, at
+ * least -30), j < 32, as halves (nf x 32, row major).  omega: p x 32 or wider
+ * (the first 32 columns are used), column major FP32. */
+tsvdm_status tsvdm_rank_features(const tsvdm_tensor *Xhat, const float *omega, uint16_t *features,
+                                 void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace bytes for tsvdm_truncate_learned (shapes only); 0 if invalid. */
+size_t tsvdm_truncate_learned_workspace_size(const tsvdm_tensor *Xhat);
+
+/* Mixed-precision truncation (as tsvdm_truncate with PREC_MIXED and the
+ * energy rule) whose sketch width is chosen per face by the predictor w16:
+ * features, prediction (k/32, l/48) -> width = the smallest of 16, 32, 40 not
+ * below ceil(48 l) + 1; the faces of each width are truncated together (rank
+ * caps 13, 26, 32); faces whose certified error then exceeds tau ||Xhat_f|| are
+ * truncated again with width 40.  widths (nf, device) receives each face's
+ * final width.  opts: ENERGY, tau, omega (p x 40), power_iters, max_sweeps.
+ * out->kmax >= 32; cert and fro are required.  Synchronizes the stream twice
+ * (bucket sizes), so it cannot be captured in a graph. */
+tsvdm_status tsvdm_truncate_learned(const tsvdm_tensor *Xhat, const tsvdm_truncate_opts *opts,
+                                    const uint16_t *w16, tsvdm_factors *out, int32_t *widths,
+                                    void *workspace, size_t workspace_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

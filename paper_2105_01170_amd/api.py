@@ -162,6 +162,88 @@ class BatchedTruncator:
             self.plan = None
 
 
+class RankPredictor:
+    """The rank/sketch-width predictor (tsvdm_mlp_*): FP32 master weights, the
+    half copy the kernels read, Adam moments, and the training workspace."""
+
+    def __init__(self, theta: torch.Tensor, device="cuda"):
+        n = C.tsvdm_mlp_nparams()
+        theta = theta.to(device=device, dtype=torch.float32).contiguous()
+        if theta.numel() != n:
+            raise ValueError(f"expected {n} parameters, got {theta.numel()}")
+        self.w32 = theta.clone()
+        self.w16 = torch.empty(n, dtype=torch.float16, device=device)
+        self.m = torch.zeros(n, dtype=torch.float32, device=device)
+        self.v = torch.zeros(n, dtype=torch.float32, device=device)
+        self.step = 0
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self._ws = None
+        C.tsvdm_f32_to_f16(self.w32.data_ptr(), self.w16.data_ptr(), n, _stream(None))
+
+    def _workspace(self, n):
+        need = C.tsvdm_mlp_train_workspace_size(n)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=self.w32.device)
+        return self._ws
+
+    def forward(self, x16: torch.Tensor, stream=None) -> torch.Tensor:
+        n = x16.shape[0]
+        y = torch.empty(n, 2, dtype=torch.float32, device=x16.device)
+        C.tsvdm_mlp_forward(self.w16.data_ptr(), x16.data_ptr(), n, y.data_ptr(), _stream(stream))
+        return y
+
+    def gradient(self, x16: torch.Tensor, target: torch.Tensor, stream=None) -> torch.Tensor:
+        n = x16.shape[0]
+        ws = self._workspace(n)
+        g = torch.empty(C.tsvdm_mlp_nparams(), dtype=torch.float32, device=x16.device)
+        C.tsvdm_mlp_gradient(self.w16.data_ptr(), x16.data_ptr(), target.data_ptr(), n, g.data_ptr(),
+                             self.loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+        return g
+
+    def train_step(self, x16: torch.Tensor, target: torch.Tensor, lr=1e-3, stream=None):
+        n = x16.shape[0]
+        ws = self._workspace(n)
+        self.step += 1
+        C.tsvdm_mlp_train_step(self.w32.data_ptr(), self.w16.data_ptr(), self.m.data_ptr(),
+                               self.v.data_ptr(), self.step, lr, x16.data_ptr(), target.data_ptr(), n,
+                               self.loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+        return self.loss
+
+
+def rank_features(xhat: torch.Tensor, m: int, p: int, nf: int, omega: torch.Tensor,
+                  stream=None) -> torch.Tensor:
+    """(nf, 32) half features of every face (tsvdm_rank_features)."""
+    X = C.dense_tensor(xhat.data_ptr(), m, p, nf, C.F32)
+    need = C.tsvdm_rank_features_workspace_size(X)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=xhat.device)
+    out = torch.empty(nf, 32, dtype=torch.float16, device=xhat.device)
+    C.tsvdm_rank_features(X, omega.data_ptr(), out.data_ptr(), ws.data_ptr(), need, _stream(stream))
+    return out
+
+
+class LearnedTruncator:
+    """tsvdm_truncate_learned on tensors of one shape: workspace, factors
+    (kmax 32) and the per-face widths."""
+
+    def __init__(self, m, p, nf, omega: torch.Tensor, tau=1e-4, power_iters=1, device="cuda"):
+        self.m, self.p, self.nf = m, p, nf
+        self.omega = omega
+        self.opts = C.truncate_opts(C.RANK_ENERGY, 32, tau, C.PREC_MIXED, 8, power_iters, 0, 1,
+                                    omega.data_ptr())
+        X = C.dense_tensor(0, m, p, nf, C.F32)
+        self.ws_bytes = C.tsvdm_truncate_learned_workspace_size(X)
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+        self.F = empty_factors(m, p, nf, 32, torch.float32, device)
+        self.widths = torch.zeros(nf, dtype=torch.int32, device=device)
+
+    def __call__(self, xhat: torch.Tensor, predictor: RankPredictor, stream=None) -> Factors:
+        X = C.dense_tensor(xhat.data_ptr(), self.m, self.p, self.nf, C.F32)
+        C.tsvdm_truncate_learned(X, self.opts, predictor.w16.data_ptr(), self.F.desc(),
+                                 self.widths.data_ptr(), self.ws.data_ptr(), self.ws_bytes,
+                                 _stream(stream))
+        return self.F
+
+
 def apply(F: Factors, kind: int, n3: int, ell: int, q: int, x: torch.Tensor, ldx: int | None = None,
           compute: int | None = None, M: torch.Tensor | None = None, y: torch.Tensor | None = None,
           ws: torch.Tensor | None = None, stream=None) -> torch.Tensor:

@@ -78,6 +78,13 @@ tsvdm_status launch_jacobi_truncate(const tsvdm_tensor *X, const tsvdm_truncate_
 size_t mixed_workspace(int64_t m, int64_t p, int64_t nf, int ell);
 tsvdm_status launch_mixed_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
                                    tsvdm_factors *F, void *ws, hipStream_t s);
+tsvdm_status launch_mlp_forward(const uint16_t *w16, const uint16_t *x, int64_t n, float *y, hipStream_t s);
+size_t features_workspace(int64_t m, int64_t p, int64_t nf);
+tsvdm_status launch_rank_features(const tsvdm_tensor *X, const float *omega, uint16_t *features, void *ws,
+                                  hipStream_t s);
+size_t learned_workspace(int64_t m, int64_t p, int64_t nf);
+tsvdm_status launch_learned_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, const uint16_t *w16,
+                                     tsvdm_factors *F, int32_t *widths, void *ws, hipStream_t s);
 size_t apply_workspace(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell, int64_t q,
                        int64_t nrhs, int32_t compute);
 tsvdm_status launch_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell, int64_t q,

@@ -201,6 +201,59 @@ tsvdm_status tsvdm_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
     return launch_mixed_truncate(X, o, F, ws, (hipStream_t)stream);
 }
 
+// ---------------------------------------------------------------- learned rank
+static tsvdm_status check_features(const tsvdm_tensor *X, bool need_data) {
+    tsvdm_status st;
+    if ((st = check_tensor(X, "Xhat", need_data)) != TSVDM_OK) return st;
+    if (!is_dense(*X)) FAIL(TSVDM_EINVAL, "Xhat must be dense (strides 1, m, m*p)");
+    if (X->dtype != TSVDM_F32) FAIL(TSVDM_EUNSUPPORTED, "the sketch features need a real F32 Xhat");
+    if (X->m < 32 || X->p < 40) FAIL(TSVDM_EUNSUPPORTED, "faces need m >= 32 and p >= 40");
+    if (X->m > 65536 || X->p > 65536 || X->n3 > 65535)
+        FAIL(TSVDM_EUNSUPPORTED, "face dims up to 65536 and up to 65535 faces");
+    return TSVDM_OK;
+}
+
+size_t tsvdm_rank_features_workspace_size(const tsvdm_tensor *X) {
+    if (check_features(X, false) != TSVDM_OK) return 0;
+    return features_workspace(X->m, X->p, X->n3);
+}
+
+tsvdm_status tsvdm_rank_features(const tsvdm_tensor *X, const float *omega, uint16_t *features, void *ws,
+                                 size_t ws_bytes, void *stream) {
+    tsvdm_status st;
+    if ((st = check_features(X, true)) != TSVDM_OK) return st;
+    if (!omega || !features) FAIL(TSVDM_EINVAL, "omega and features are required");
+    const size_t need = features_workspace(X->m, X->p, X->n3);
+    if (!ws || ws_bytes < need) FAIL(TSVDM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    return launch_rank_features(X, omega, features, ws, (hipStream_t)stream);
+}
+
+size_t tsvdm_truncate_learned_workspace_size(const tsvdm_tensor *X) {
+    if (check_features(X, false) != TSVDM_OK) return 0;
+    return learned_workspace(X->m, X->p, X->n3);
+}
+
+tsvdm_status tsvdm_truncate_learned(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, const uint16_t *w16,
+                                    tsvdm_factors *F, int32_t *widths, void *ws, size_t ws_bytes,
+                                    void *stream) {
+    tsvdm_status st;
+    if ((st = check_features(X, true)) != TSVDM_OK) return st;
+    if (!o || !w16 || !F || !widths) FAIL(TSVDM_EINVAL, "opts, w16, out and widths are required");
+    if (o->rank_mode != TSVDM_RANK_ENERGY || !(o->tau > 0.0 && o->tau < 1.0))
+        FAIL(TSVDM_EINVAL, "the learned truncation uses the energy rule with 0 < tau < 1");
+    if (!o->omega) FAIL(TSVDM_EINVAL, "omega (p x 40) is required");
+    if (o->power_iters < 0 || o->power_iters > 1) FAIL(TSVDM_EUNSUPPORTED, "power_iters must be 0 or 1");
+    if (o->max_sweeps < 0) FAIL(TSVDM_EINVAL, "max_sweeps must be >= 0");
+    if (F->m != X->m || F->p != X->p || F->nf != X->n3 || F->dtype != TSVDM_F32 || F->kmax < 32)
+        FAIL(TSVDM_EINVAL, "factors must be F32 with the dims of Xhat and kmax >= 32");
+    if (!F->U || !F->S || !F->V || !F->ranks || !F->cert || !F->fro)
+        FAIL(TSVDM_EINVAL, "factor pointers U, S, V, ranks, cert, fro must be set");
+    const size_t need = learned_workspace(X->m, X->p, X->n3);
+    if (!ws || ws_bytes < need) FAIL(TSVDM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need, ws_bytes);
+    if (X->n3 == 0) return TSVDM_OK;
+    return launch_learned_truncate(X, o, w16, F, widths, ws, (hipStream_t)stream);
+}
+
 static tsvdm_status check_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell, int64_t q,
                                 int64_t nrhs, int32_t compute) {
     if (!M || !F) FAIL(TSVDM_EINVAL, "M or F is NULL");

@@ -207,7 +207,8 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
                                            const float *__restrict__ W, int64_t w_stride, int ldw,
                                            int nw, float *__restrict__ Y,
                                            double *__restrict__ fro_part,
-                                           double *__restrict__ gram_part) {
+                                           double *__restrict__ gram_part,
+    const int32_t *__restrict__ fmap) {
     constexpr int KC = 64, LDK = KC + 8;  // LDS row pitch (bf16 elements)
     constexpr int NB = LP / 16, WPT = KC * LP / GT;
     constexpr bool SPL = PROD == PROD_SPLIT;
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
     int blk, f;
     xcd_map(blockIdx.x, nb, nf, blk, f);
     const int a0 = blk * 64;
-    const float *Xf = X + (int64_t)f * m * p;
+    const float *Xf = X + (int64_t)(fmap ? fmap[f] : f) * m * p;
     const float *Wf = W + (int64_t)f * w_stride;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = tid & 63, kg = tid >> 6;  // X load mapping: row, group of 16 columns
@@ -317,7 +318,8 @@ template <int LP, int PROD, bool GRAM>
 __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, int p, int nf,
                                             const float *__restrict__ W, int64_t w_stride, int ldw,
                                             int nw, float *__restrict__ Z,
-                                            double *__restrict__ gram_part) {
+                                            double *__restrict__ gram_part,
+    const int32_t *__restrict__ fmap) {
     constexpr int KC = 64, LDK = KC + 8;
     constexpr int NB = LP / 16, WPT = KC * LP / GT;
     constexpr bool SPL = PROD == PROD_SPLIT;
@@ -330,7 +332,7 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
     int blk, f;
     xcd_map(blockIdx.x, nb, nf, blk, f);
     const int b0 = blk * 64;
-    const float *Xf = X + (int64_t)f * m * p;
+    const float *Xf = X + (int64_t)(fmap ? fmap[f] : f) * m * p;
     const float *Wf = W + (int64_t)f * w_stride;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int q4 = tid & 15, cj0 = tid >> 4;  // X load mapping: 4 rows, column
@@ -615,7 +617,8 @@ __global__ __launch_bounds__(QT) void k_cholqr(const float *__restrict__ Sin, in
 template <int LP>
 __global__ __launch_bounds__(GT) void k_resid(const float *__restrict__ X, int m, int p, int nf,
                                               const float *__restrict__ Q, const float *__restrict__ Bt,
-                                              double *__restrict__ part) {
+                                              double *__restrict__ part,
+    const int32_t *__restrict__ fmap) {
     constexpr int LD = LP + 1;
     __shared__ float bs[64 * LD];  // [b][c] = B^T block
     __shared__ float qs[64 * LD];  // [a][c] = Q chunk
@@ -624,7 +627,7 @@ __global__ __launch_bounds__(GT) void k_resid(const float *__restrict__ X, int m
     int blk, f;
     xcd_map(blockIdx.x, nb, nf, blk, f);
     const int b0 = blk * 64, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const float *Xf = X + (int64_t)f * m * p;
+    const float *Xf = X + (int64_t)(fmap ? fmap[f] : f) * m * p;
     const float *Qf = Q + (int64_t)f * m * LP;
     const float *Bf = Bt + (int64_t)f * p * LP;
     stage_panel<LP, 64>(Bf, p, b0, bs);
@@ -686,7 +689,8 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
                                              double *__restrict__ UB, double *__restrict__ sig,
                                              int *__restrict__ perm_out, int *__restrict__ kf_out,
                                              double *__restrict__ fro2_out, double *__restrict__ cert,
-                                             int32_t *__restrict__ jinfo) {
+                                             int32_t *__restrict__ jinfo,
+    const int32_t *__restrict__ fmap) {
     constexpr int LD = LP + 1, LDE = LP + 2, NPM = LP / 2;
     __shared__ double Gb[2][LP * LD];
     __shared__ __align__(16) double Et[LP * LDE];  // eigenvectors transposed: Et[c * LDE + r] = E[r][c]
@@ -746,7 +750,7 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
         for (int j = ell - 1; j >= kf; --j) disc += lam[perm[j]];
         kf_out[f] = kf;
         fro2_out[f] = fro2;
-        if (cert) cert[f] = nres > 0 ? sqrt(res + disc) : -1.0;
+        if (cert) cert[fmap ? fmap[f] : f] = nres > 0 ? sqrt(res + disc) : -1.0;
         jinfo[f] = (conv || ell <= 1) ? 0 : 1;
     }
     for (int r = tid; r < LP; r += QT) {
@@ -772,10 +776,11 @@ __global__ __launch_bounds__(GT) void k_factors(const float *__restrict__ Q, con
                                                 const int32_t *__restrict__ jinfo,
                                                 float *__restrict__ Uo, double *__restrict__ So,
                                                 float *__restrict__ Vo, int32_t *__restrict__ ranks,
-                                                double *__restrict__ fro, int32_t *__restrict__ info) {
+                                                double *__restrict__ fro, int32_t *__restrict__ info,
+    const int32_t *__restrict__ fmap) {
     __shared__ double ub[LP * LP];  // ub[c * LP + r] = U_B[c, perm[r]] (and / s_r for V)
     __shared__ double ubv[LP * LP];
-    const int f = blockIdx.y, tid = threadIdx.x;
+    const int f = blockIdx.y, tid = threadIdx.x, fd = fmap ? fmap[f] : f;
     const int kf = kf_in[f];
     for (int e = tid; e < LP * LP; e += GT) {
         int c = e / LP, r = e % LP;
@@ -802,7 +807,7 @@ __global__ __launch_bounds__(GT) void k_factors(const float *__restrict__ Q, con
 #pragma unroll
                 for (int c = 0; c < LP; ++c) acc += qv[c] * ub[c * LP + (r < LP ? r : 0)];
             }
-            Uo[(int64_t)f * m * kmax + row + (int64_t)m * r] = (float)acc;
+            Uo[(int64_t)fd * m * kmax + row + (int64_t)m * r] = (float)acc;
         }
     }
     if (row < p) {
@@ -816,20 +821,20 @@ __global__ __launch_bounds__(GT) void k_factors(const float *__restrict__ Q, con
 #pragma unroll
                 for (int c = 0; c < LP; ++c) acc += bv[c] * ubv[c * LP + (r < LP ? r : 0)];
             }
-            Vo[(int64_t)f * p * kmax + row + (int64_t)p * r] = (float)acc;
+            Vo[(int64_t)fd * p * kmax + row + (int64_t)p * r] = (float)acc;
         }
     }
     if (blockIdx.x == 0) {
-        for (int r = tid; r < kmax; r += GT) So[(int64_t)f * kmax + r] = r < kf ? sig[(int64_t)f * LP + r] : 0.0;
+        for (int r = tid; r < kmax; r += GT) So[(int64_t)fd * kmax + r] = r < kf ? sig[(int64_t)f * LP + r] : 0.0;
         if (tid == 0) {
-            ranks[f] = kf;
-            if (fro) fro[f] = sqrt(fro2[f]);
+            ranks[fd] = kf;
+            if (fro) fro[fd] = sqrt(fro2[f]);
             if (info) {
                 int code = 0;
                 if (jinfo[f]) code = 1;
                 if (qr_info[f]) code = 2;
                 if (!isfinite(fro2[f])) code = 3;
-                info[f] = code;
+                info[fd] = code;
             }
         }
     }
@@ -877,12 +882,102 @@ size_t carve(char *base, int64_t m, int64_t p, int64_t nf, int LP, MixedWs *w) {
     return off;
 }
 
+// ---------------------------------------------------------------- learned rank
+// features[f][j] = log10(s_j / s_1) (0 when s_1 = 0, at least -30) of the
+// singular values s (decreasing, LP per face) of the face's sketch, as halves
+__global__ void k_rank_features(const double *__restrict__ sig, int LPs, int nf,
+                                _Float16 *__restrict__ feat) {
+    const int f = blockIdx.x, j = threadIdx.x;
+    if (f >= nf || j >= 32) return;
+    const double s1 = sig[(int64_t)f * LPs], sj = sig[(int64_t)f * LPs + j];
+    double v = 0.0;
+    if (s1 > 0.0) v = sj > 0.0 ? log10(sj / s1) : -30.0;
+    feat[(int64_t)f * 32 + j] = (_Float16)fmax(v, -30.0);
+}
+
+// Widths of the learned truncation: from the predictor's (k/32, l/48), round
+// up and add one; the sketch width is the smallest of 16, 32, 40 that is at
+// least that.  Stable partition of the faces into the three width lists
+// (lists[b * nf + i]), counts[b]; widths[f] records each face's width.
+__global__ __launch_bounds__(1024) void k_width_partition(const float *__restrict__ y, int nf,
+                                                          int32_t *__restrict__ lists,
+                                                          int32_t *__restrict__ counts,
+                                                          int32_t *__restrict__ widths) {
+    __shared__ int base[3];
+    __shared__ int wsum[3][16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 3) base[tid] = 0;
+    __syncthreads();
+    for (int f0 = 0; f0 < nf; f0 += 1024) {
+        const int f = f0 + tid;
+        int b = -1;
+        if (f < nf) {
+            const int lw = (int)ceilf(y[2 * f + 1] * 48.0f) + 1;
+            b = lw <= 16 ? 0 : lw <= 32 ? 1 : 2;
+            widths[f] = b == 0 ? 16 : b == 1 ? 32 : 40;
+        }
+        for (int c = 0; c < 3; ++c) {
+            const unsigned long long mask = __ballot(b == c);
+            const int before = __popcll(mask & ((1ull << lane) - 1ull));
+            if (lane == 0) wsum[c][wave] = __popcll(mask);
+            __syncthreads();
+            int off = base[c];
+            for (int w = 0; w < wave; ++w) off += wsum[c][w];
+            if (b == c) lists[c * nf + off + before] = f;
+            __syncthreads();
+            if (tid == 0) {
+                int t = 0;
+                for (int w = 0; w < 16; ++w) t += wsum[c][w];
+                base[c] += t;
+            }
+            __syncthreads();
+        }
+    }
+    if (tid < 3) counts[tid] = base[tid];
+}
+
+// Stable list of the faces whose width is below 40 and whose certified error
+// exceeds tau ||Xhat_f||: they are truncated again with the full width.
+__global__ __launch_bounds__(1024) void k_fallback_list(const double *__restrict__ cert,
+                                                        const double *__restrict__ fro, double tau, int nf,
+                                                        int32_t *__restrict__ widths,
+                                                        int32_t *__restrict__ list, int32_t *__restrict__ count) {
+    __shared__ int base;
+    __shared__ int wsum[16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) base = 0;
+    __syncthreads();
+    for (int f0 = 0; f0 < nf; f0 += 1024) {
+        const int f = f0 + tid;
+        const bool bad = f < nf && widths[f] < 40 && !(cert[f] <= tau * fro[f]);
+        const unsigned long long mask = __ballot(bad);
+        const int before = __popcll(mask & ((1ull << lane) - 1ull));
+        if (lane == 0) wsum[wave] = __popcll(mask);
+        __syncthreads();
+        int off = base;
+        for (int w = 0; w < wave; ++w) off += wsum[w];
+        if (bad) {
+            list[off + before] = f;
+            widths[f] = 40;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int t = 0;
+            for (int w = 0; w < 16; ++w) t += wsum[w];
+            base += t;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) *count = base;
+}
+
 // Faces [f0, f0 + nfg) through the whole path on stream s.  Every kernel
 // below works face by face, so the pointers are offset to the first face of
 // the range and the kernels see a tensor of nfg faces.
 template <int LP>
 tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
-                       const MixedWs &w0, int f0, int nfg, hipStream_t s) {
+                       const MixedWs &w0, int f0, int nfg, hipStream_t s,
+                       const int32_t *fmap = nullptr) {
     const int m = (int)X->m, p = (int)X->p, ell = o->k + o->oversample;
     const int mparts = (m + 63) / 64, pparts = (p + 63) / 64;
     const int64_t kmax = F->kmax;
@@ -920,40 +1015,40 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     if (power) {
         // pass 1: sketch Y = X Omega (BF16), ||X||^2, Gram partials of Y
         TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true>), gm, dim3(GT), 0, s, Xd, m, p, nf, o->omega,
-                     (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m);
+                     (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m, fmap);
         // basis of the sketch: one shifted Cholesky-QR step (its span is what
         // the power step needs)
         TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell,
                      w.Qm, 1, gm_c, mparts, w.qr_info);
         // pass 2: Z = X^T Q (BF16) and its Gram partials; basis of Z
         TSVDM_LAUNCH("power_xtw_bf16", (k_xtw<LP, PROD_BF16, true>), gp, dim3(GT), 0, s, Xd, m, p, nf,
-                     (const float *)w.Qm, (int64_t)m * LP, m, LP, w.Z, w.gram_p);
+                     (const float *)w.Qm, (int64_t)m * LP, m, LP, w.Z, w.gram_p, fmap);
         TSVDM_LAUNCH("cholqr_power_z", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Z, p, ell,
                      w.Qp, 1, gp_c, pparts, w.qr_info);
         // pass 3: Y' = X Qz, FP32-accurate (split BF16), and its Gram partials
         TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true>), gm, dim3(GT), 0, s, Xd, m, p, nf,
-                     (const float *)w.Qp, (int64_t)p * LP, p, LP, w.Y, (double *)nullptr, w.gram_m);
+                     (const float *)w.Qp, (int64_t)p * LP, p, LP, w.Y, (double *)nullptr, w.gram_m, fmap);
     } else {
         TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true>), gm, dim3(GT), 0, s, Xd, m, p, nf, o->omega,
-                     (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m);
+                     (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m, fmap);
     }
     // final basis: FP64 shifted Cholesky-QR2 (first Gram from the partials)
     TSVDM_LAUNCH("cholqr_final", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell, w.Qm,
                  2, gm_c, mparts, w.qr_info);
     // pass 4: B^T = X^T Q, FP32-accurate, and the Gram partials of B^T
     TSVDM_LAUNCH("project_xtw_split", (k_xtw<LP, PROD_SPLIT, true>), gp, dim3(GT), 0, s, Xd, m, p, nf,
-                 (const float *)w.Qm, (int64_t)m * LP, m, LP, w.Z, w.gram_p);
+                 (const float *)w.Qm, (int64_t)m * LP, m, LP, w.Z, w.gram_p, fmap);
     if (resid)  // pass 5: ||X - Q B||^2 per 64-column block
         TSVDM_LAUNCH("certificate_resid", (k_resid<LP>), gp, dim3(GT), 0, s, Xd, m, p, nf,
-                     (const float *)w.Qm, (const float *)w.Z, w.res_part);
+                     (const float *)w.Qm, (const float *)w.Z, w.res_part, fmap);
     const int msw = o->max_sweeps > 0 ? o->max_sweeps : 30;
     TSVDM_LAUNCH("core_gram_eig", (k_core<LP>), dim3(nf), dim3(QT), 0, s, gp_c, pparts, ell,
                  (const double *)w.fro_part, mparts, (const double *)w.res_part, resid ? pparts : 0,
-                 o->rank_mode, o->k, o->tau, msw, w.UB, w.sig, w.perm, w.kf, w.fro2, cert, w.jinfo);
+                 o->rank_mode, o->k, o->tau, msw, w.UB, w.sig, w.perm, w.kf, w.fro2, cert, w.jinfo, fmap);
     const int rows = m > p ? m : p;
     TSVDM_LAUNCH("factors", (k_factors<LP>), dim3((rows + GT - 1) / GT, nf), dim3(GT), 0, s,
                  (const float *)w.Qm, (const float *)w.Z, m, p, ell, kmax, w.UB, w.sig, w.perm, w.kf,
-                 w.fro2, w.qr_info, w.jinfo, Uo, So, Vo, ranks, fro, info);
+                 w.fro2, w.qr_info, w.jinfo, Uo, So, Vo, ranks, fro, info, fmap);
     TSVDM_LAUNCH_CHECK("mixed truncate");
     return TSVDM_OK;
 }
@@ -988,6 +1083,118 @@ tsvdm_status launch_mixed_truncate(const tsvdm_tensor *X, const tsvdm_truncate_o
         case 48: return run_mixed<48>(X, o, F, ws, s);
         default: return run_mixed<64>(X, o, F, ws, s);
     }
+}
+
+// ---------------------------------------------------------------- learned rank
+// Features: sketch Y = Xhat_f Omega[:, :32] (BF16, the first pass of the
+// mixed path), Gram of Y, its eigenvalues by the Jacobi core, s_j = sqrt.
+size_t features_workspace(int64_t m, int64_t p, int64_t nf) {
+    return carve(nullptr, m, p, nf, 32, nullptr);
+}
+
+tsvdm_status launch_rank_features(const tsvdm_tensor *X, const float *omega, uint16_t *features, void *ws,
+                                  hipStream_t s) {
+    const int m = (int)X->m, p = (int)X->p, nf = (int)X->n3;
+    if (nf == 0) return TSVDM_OK;
+    MixedWs w;
+    carve(reinterpret_cast<char *>(ws), m, p, nf, 32, &w);
+    const int mparts = (m + 63) / 64;
+    const float *Xd = reinterpret_cast<const float *>(X->data);
+    TSVDM_LAUNCH("features_sketch", (k_xw<32, PROD_BF16, true>), dim3((unsigned)(mparts * nf)), dim3(GT), 0, s,
+                 Xd, m, p, nf, omega, (int64_t)0, p, 32, w.Y, w.fro_part, w.gram_m, (const int32_t *)nullptr);
+    TSVDM_LAUNCH("features_eig", (k_core<32>), dim3(nf), dim3(QT), 0, s, (const double *)w.gram_m, mparts, 32,
+                 (const double *)w.fro_part, mparts, (const double *)nullptr, 0, (int)TSVDM_RANK_FIXED, 32, 0.0,
+                 30, w.UB, w.sig, w.perm, w.kf, w.fro2, (double *)nullptr, w.jinfo, (const int32_t *)nullptr);
+    TSVDM_LAUNCH("features_log", k_rank_features, dim3(nf), dim3(32), 0, s, (const double *)w.sig, 32, nf,
+                 reinterpret_cast<_Float16 *>(features));
+    TSVDM_LAUNCH_CHECK("rank features");
+    return TSVDM_OK;
+}
+
+namespace {
+struct LearnedWs {
+    uint16_t *feat;
+    float *y;
+    int32_t *lists, *counts, *fb_list;
+    char *feat_ws, *trunc_ws;
+};
+
+size_t learned_carve(char *base, int64_t m, int64_t p, int64_t nf, LearnedWs *w) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *ptr = base ? base + off : nullptr;
+        off += al256(bytes);
+        return ptr;
+    };
+    LearnedWs t;
+    t.feat = (uint16_t *)take(sizeof(uint16_t) * 32 * nf);
+    t.y = (float *)take(sizeof(float) * 2 * nf);
+    t.lists = (int32_t *)take(sizeof(int32_t) * 3 * nf);
+    t.counts = (int32_t *)take(sizeof(int32_t) * 8);
+    t.fb_list = (int32_t *)take(sizeof(int32_t) * nf);
+    t.feat_ws = take(features_workspace(m, p, nf));
+    t.trunc_ws = take(carve(nullptr, m, p, nf, 48, nullptr));
+    if (w) *w = t;
+    return off;
+}
+}  // namespace
+
+size_t learned_workspace(int64_t m, int64_t p, int64_t nf) { return learned_carve(nullptr, m, p, nf, nullptr); }
+
+tsvdm_status launch_learned_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, const uint16_t *w16,
+                                     tsvdm_factors *F, int32_t *widths, void *ws, hipStream_t s) {
+    const int m = (int)X->m, p = (int)X->p, nf = (int)X->n3;
+    if (nf == 0) return TSVDM_OK;
+    LearnedWs w;
+    learned_carve(reinterpret_cast<char *>(ws), m, p, nf, &w);
+    tsvdm_status st = launch_rank_features(X, o->omega, w.feat, w.feat_ws, s);
+    if (st != TSVDM_OK) return st;
+    st = launch_mlp_forward(w16, w.feat, nf, w.y, s);
+    if (st != TSVDM_OK) return st;
+    TSVDM_LAUNCH("width_partition", k_width_partition, dim3(1), dim3(1024), 0, s, (const float *)w.y, nf,
+                 w.lists, w.counts, widths);
+    TSVDM_LAUNCH_CHECK("width partition");
+    int32_t counts[3] = {0, 0, 0};
+    hipError_t e = hipMemcpyAsync(counts, w.counts, sizeof(counts), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_check(e, "learned truncate: bucket counts");
+    // per width: (rank cap, oversampling) with ell = cap + oversampling
+    const int caps[3] = {13, 26, 32}, overs[3] = {3, 6, 8};
+    MixedWs tw;
+    for (int b = 0; b < 3; ++b) {
+        if (counts[b] == 0) continue;
+        tsvdm_truncate_opts ob = *o;
+        ob.rank_mode = TSVDM_RANK_ENERGY;
+        ob.k = caps[b] < (int)F->kmax ? caps[b] : (int)F->kmax;
+        ob.oversample = caps[b] + overs[b] - ob.k;
+        ob.certify = 1;
+        const int LPb = b == 0 ? 16 : b == 1 ? 32 : 48;
+        carve(w.trunc_ws, m, p, counts[b], LPb, &tw);
+        const int32_t *list = w.lists + (int64_t)b * nf;
+        if (b == 0) st = run_group<16>(X, &ob, F, tw, 0, counts[b], s, list);
+        else if (b == 1) st = run_group<32>(X, &ob, F, tw, 0, counts[b], s, list);
+        else st = run_group<48>(X, &ob, F, tw, 0, counts[b], s, list);
+        if (st != TSVDM_OK) return st;
+    }
+    // faces whose certificate misses tau: again with the full width
+    TSVDM_LAUNCH("fallback_list", k_fallback_list, dim3(1), dim3(1024), 0, s, (const double *)F->cert,
+                 (const double *)F->fro, o->tau, nf, widths, w.fb_list, w.counts + 3);
+    TSVDM_LAUNCH_CHECK("fallback list");
+    int32_t nfb = 0;
+    e = hipMemcpyAsync(&nfb, w.counts + 3, sizeof(nfb), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_check(e, "learned truncate: fallback count");
+    if (nfb > 0) {
+        tsvdm_truncate_opts ob = *o;
+        ob.rank_mode = TSVDM_RANK_ENERGY;
+        ob.k = 32 < (int)F->kmax ? 32 : (int)F->kmax;
+        ob.oversample = 40 - ob.k;
+        ob.certify = 1;
+        carve(w.trunc_ws, m, p, nfb, 48, &tw);
+        st = run_group<48>(X, &ob, F, tw, 0, nfb, s, w.fb_list);
+        if (st != TSVDM_OK) return st;
+    }
+    return TSVDM_OK;
 }
 
 }  // namespace tsvdm

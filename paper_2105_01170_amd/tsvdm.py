@@ -55,7 +55,10 @@ EXPORTS = ["tsvdm_version", "tsvdm_last_error", "tsvdm_tensor_from_blockmat",
            "tsvdm_truncate", "tsvdm_apply_workspace_size", "tsvdm_apply", "tsvdm_timing_enable",
            "tsvdm_timing_count", "tsvdm_timing_get", "tsvdm_batched_workspace_size",
            "tsvdm_batched_plan_create", "tsvdm_truncate_batched", "tsvdm_batched_autotune",
-           "tsvdm_batched_config", "tsvdm_batched_plan_destroy"]
+           "tsvdm_batched_config", "tsvdm_batched_plan_destroy", "tsvdm_mlp_nparams",
+           "tsvdm_mlp_forward", "tsvdm_mlp_train_workspace_size", "tsvdm_mlp_gradient",
+           "tsvdm_mlp_train_step", "tsvdm_f32_to_f16", "tsvdm_rank_features_workspace_size",
+           "tsvdm_rank_features", "tsvdm_truncate_learned_workspace_size", "tsvdm_truncate_learned"]
 
 _LIB = None
 
@@ -108,6 +111,27 @@ def lib():
         L.tsvdm_batched_config.argtypes = [vp, P(i32)]
         L.tsvdm_batched_plan_destroy.restype = None
         L.tsvdm_batched_plan_destroy.argtypes = [vp]
+        L.tsvdm_mlp_nparams.restype = i64
+        L.tsvdm_mlp_nparams.argtypes = []
+        L.tsvdm_mlp_forward.restype = i32
+        L.tsvdm_mlp_forward.argtypes = [vp, vp, i64, vp, vp]
+        L.tsvdm_mlp_train_workspace_size.restype = sz
+        L.tsvdm_mlp_train_workspace_size.argtypes = [i64]
+        L.tsvdm_mlp_gradient.restype = i32
+        L.tsvdm_mlp_gradient.argtypes = [vp, vp, vp, i64, vp, vp, vp, sz, vp]
+        L.tsvdm_mlp_train_step.restype = i32
+        L.tsvdm_mlp_train_step.argtypes = [vp, vp, vp, vp, i32, ctypes.c_float, vp, vp, i64, vp, vp, sz, vp]
+        L.tsvdm_f32_to_f16.restype = i32
+        L.tsvdm_f32_to_f16.argtypes = [vp, vp, i64, vp]
+        L.tsvdm_rank_features_workspace_size.restype = sz
+        L.tsvdm_rank_features_workspace_size.argtypes = [P(TsvdmTensor)]
+        L.tsvdm_rank_features.restype = i32
+        L.tsvdm_rank_features.argtypes = [P(TsvdmTensor), vp, vp, vp, sz, vp]
+        L.tsvdm_truncate_learned_workspace_size.restype = sz
+        L.tsvdm_truncate_learned_workspace_size.argtypes = [P(TsvdmTensor)]
+        L.tsvdm_truncate_learned.restype = i32
+        L.tsvdm_truncate_learned.argtypes = [P(TsvdmTensor), P(TsvdmTruncateOpts), vp, P(TsvdmFactors), vp,
+                                             vp, sz, vp]
         _LIB = L
     return _LIB
 
@@ -210,6 +234,52 @@ def tsvdm_batched_config(plan: int) -> list:
 
 def tsvdm_batched_plan_destroy(plan: int):
     lib().tsvdm_batched_plan_destroy(plan)
+
+
+def tsvdm_mlp_nparams() -> int:
+    return lib().tsvdm_mlp_nparams()
+
+
+def tsvdm_mlp_forward(w16: int, x: int, n: int, y: int, stream: int = 0):
+    _check(lib().tsvdm_mlp_forward(w16, x, n, y, stream))
+
+
+def tsvdm_mlp_train_workspace_size(n: int) -> int:
+    return lib().tsvdm_mlp_train_workspace_size(n)
+
+
+def tsvdm_mlp_gradient(w16: int, x: int, target: int, n: int, grad: int, loss: int, ws: int,
+                       ws_bytes: int, stream: int = 0):
+    _check(lib().tsvdm_mlp_gradient(w16, x, target, n, grad, loss or None, ws, ws_bytes, stream))
+
+
+def tsvdm_mlp_train_step(w32: int, w16: int, m: int, v: int, step: int, lr: float, x: int,
+                         target: int, n: int, loss: int, ws: int, ws_bytes: int, stream: int = 0):
+    _check(lib().tsvdm_mlp_train_step(w32, w16, m, v, step, lr, x, target, n, loss or None, ws,
+                                      ws_bytes, stream))
+
+
+def tsvdm_f32_to_f16(a: int, b: int, n: int, stream: int = 0):
+    _check(lib().tsvdm_f32_to_f16(a, b, n, stream))
+
+
+def tsvdm_rank_features_workspace_size(X: TsvdmTensor) -> int:
+    return lib().tsvdm_rank_features_workspace_size(ctypes.byref(X))
+
+
+def tsvdm_rank_features(X: TsvdmTensor, omega: int, features: int, ws: int, ws_bytes: int,
+                        stream: int = 0):
+    _check(lib().tsvdm_rank_features(ctypes.byref(X), omega, features, ws, ws_bytes, stream))
+
+
+def tsvdm_truncate_learned_workspace_size(X: TsvdmTensor) -> int:
+    return lib().tsvdm_truncate_learned_workspace_size(ctypes.byref(X))
+
+
+def tsvdm_truncate_learned(X: TsvdmTensor, opts: TsvdmTruncateOpts, w16: int, F: TsvdmFactors,
+                           widths: int, ws: int, ws_bytes: int, stream: int = 0):
+    _check(lib().tsvdm_truncate_learned(ctypes.byref(X), ctypes.byref(opts), w16, ctypes.byref(F),
+                                        widths, ws, ws_bytes, stream))
 
 
 def tsvdm_timing_enable(on: bool):

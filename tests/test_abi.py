@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "tsvdm.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(tsvdm_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(tsvdm_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_loads_and_exports_every_declared_symbol():
