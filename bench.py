@@ -40,9 +40,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--kernel-table", action="store_true", help="print the per-kernel table to stderr")
-    ap.add_argument("--workload", choices=["dense", "uneven"], default="dense",
+    ap.add_argument("--workload", choices=["dense", "uneven", "learned"], default="dense",
                     help="dense: the 512x512x256 tensor (default); uneven: the batch of 256 "
-                         "Kronecker-sum matrices through the batched truncation")
+                         "Kronecker-sum matrices through the batched truncation; learned: the "
+                         "predicted-width truncation against the fixed width 40")
+    ap.add_argument("--train-faces", type=int, default=100_000,
+                    help="learned: number of training faces (generated in batches of 256)")
+    ap.add_argument("--epochs", type=int, default=20, help="learned: training epochs")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -237,6 +241,133 @@ def uneven_main(args):
     print(json.dumps(out))
 
 
+def learned_main(args):
+    """Faces 512 x 512 in the transform domain with M-rank 32 and singular
+    values 10^(-rho j), rho ~ U[1/16, 1/2] per face, energy rule tau = 1e-4.
+    The predictor is trained on args.train_faces such faces (features and
+    library labels, Adam, batch 1024), then the learned-width truncation and
+    the fixed-width (40) truncation are timed on held-out batches of 256 faces:
+    value = learned faces/s; the fixed rate, the gain and both certified
+    errors are reported beside it."""
+    import torch
+
+    from paper_2105_01170_amd import api, learned
+    from paper_2105_01170_amd import tsvdm as C
+    import synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    m = p = 512
+    B, tau = 256, 1e-4
+    t_setup = time.time()
+    g = np.random.default_rng(synth.SEED_BASE + 11)
+    omega = torch.from_numpy(np.asfortranarray(g.standard_normal((p, 40))).astype(np.float32).ravel(order="F")).to(dev)
+    nb = max(1, args.train_faces // B)
+    feats, tgts = [], []
+    for b in range(nb):
+        rho = synth.decay_profiles(B, index=3, salt=b)
+        xh, _ = synth.decay_faces_device(rho, m, p, 32, index=3, salt=b, device=dev)
+        feats.append(api.rank_features(xh, m, p, B, omega))
+        rank, width = learned.labels(xh, m, p, B, omega, tau)
+        tgts.append(learned.targets(rank, width))
+        del xh
+    feats = torch.cat(feats)
+    tgts = torch.cat(tgts)
+    t_data = time.time() - t_setup
+    # He-uniform initial weights, zero biases (seeded)
+    n = C.tsvdm_mlp_nparams()
+    gi = np.random.default_rng(synth.SEED_BASE + 12)
+    theta = np.zeros(n)
+    o = 0
+    for fo, fi in ((64, 32), (64, 64), (2, 64)):
+        bnd = np.sqrt(6.0 / fi)
+        theta[o:o + fo * fi] = gi.uniform(-bnd, bnd, fo * fi)
+        o += fo * fi + fo
+    pred = api.RankPredictor(torch.from_numpy(theta), device=dev)
+    t0 = time.time()
+    hist = learned.train(pred, feats, tgts, epochs=args.epochs, batch=1024, lr=1e-3, seed=0)
+    torch.cuda.synchronize()
+    t_train = time.time() - t0
+
+    # held-out batches: the learned and the fixed truncation on the same faces
+    ntest = 8
+    fixed = api.Truncator(m, p, B, torch.float32, rank_mode=C.RANK_ENERGY, k=32, tau=tau,
+                          precision=C.PREC_MIXED, oversample=8, power_iters=1, omega=omega, kmax=32,
+                          device=dev)
+    lt = api.LearnedTruncator(m, p, B, omega, tau=tau, device=dev)
+    ms_fixed, ms_learned, err_fixed, err_learned = 0.0, 0.0, 0.0, 0.0
+    widths, fallback, acc = [], 0, 0
+    for b in range(ntest):
+        salt = 10_000 + b
+        rho = synth.decay_profiles(B, index=3, salt=salt)
+        xh, _ = synth.decay_faces_device(rho, m, p, 32, index=3, salt=salt, device=dev)
+        rank_l, width_l = learned.labels(xh, m, p, B, omega, tau)
+        for fn in (lambda: fixed(xh), lambda: lt(xh, pred)):
+            fn()
+        torch.cuda.synchronize()
+        for which, fn in (("fixed", lambda: fixed(xh)), ("learned", lambda: lt(xh, pred))):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(args.steps):
+                F = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / args.steps
+            rel = float((F.cert / F.fro).max().item())
+            if which == "fixed":
+                ms_fixed += ms
+                err_fixed = max(err_fixed, rel)
+            else:
+                ms_learned += ms
+                err_learned = max(err_learned, rel)
+        w = lt.widths.cpu().numpy()
+        widths.append(w)
+        # faces recomputed with width 40 after a predicted narrower width
+        y = pred.forward(api.rank_features(xh, m, p, B, omega)).cpu().numpy()
+        _, lhat = mlp_widths(y)
+        fallback += int(np.sum((lhat < 40) & (w == 40)))
+        acc += int(np.sum(lhat == width_l.cpu().numpy()))
+        del xh
+    widths = np.concatenate(widths)
+    nt = ntest * B
+    out = {
+        "metric": "faces/sec truncated t-SVDM @1e-4 (certified), learned sketch width vs fixed width 40",
+        "value": nt / (ms_learned / 1e3),
+        "unit": "faces/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": ms_learned / ntest,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "precision": "as the mixed truncation; predictor FP16 with FP32 accumulation",
+        "data": "synthetic",
+        "config": {"workload": "512x512 transform-domain faces of M-rank 32, sigma_j = 10^(-rho j), "
+                               "rho ~ U[1/16, 1/2], energy rule tau = 1e-4, batches of 256 faces",
+                   "train_faces": int(feats.shape[0]), "epochs": args.epochs, "test_faces": nt},
+        "fixed_width_faces_per_s": nt / (ms_fixed / 1e3),
+        "gain_learned_over_fixed": ms_fixed / ms_learned,
+        "max_certified_rel_err": {"learned": err_learned, "fixed": err_fixed},
+        "width_histogram": {str(w): int(np.sum(widths == w)) for w in (16, 32, 40)},
+        "fallback_faces": fallback,
+        "width_label_accuracy": acc / nt,
+        "train_loss": {"first_epoch": hist[0], "last_epoch": hist[-1]},
+        "setup_s": {"data_and_labels": round(t_data, 2), "training": round(t_train, 2)},
+    }
+    print(json.dumps(out))
+
+
+def mlp_widths(y):
+    """Predicted (rank, width) from the predictor outputs, as the library rounds them."""
+    k = np.clip(np.ceil(y[:, 0] * 32.0).astype(int) + 1, 1, 32)
+    lw = np.ceil(y[:, 1] * 48.0).astype(int) + 1
+    w = np.where(lw <= 16, 16, np.where(lw <= 32, 32, 40))
+    return k, w
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -245,6 +376,8 @@ def main():
         sys.exit(2)
     if args.workload == "uneven":
         return uneven_main(args)
+    if args.workload == "learned":
+        return learned_main(args)
     import torch
 
     from paper_2105_01170_amd import api

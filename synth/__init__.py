@@ -121,3 +121,22 @@ def apply_factors(m: int = 64, ell: int = 64, q: int = 64, n: int = 64, k: int =
     sigma = 10.0 ** (-decay * np.arange(1, k + 1))
     X = gaussian(g, (q * n, nrhs))
     return dict(U=U, V=V, sigma=sigma, X=X, m=m, ell=ell, q=q, n=n, p=p, k=k, nrhs=nrhs)
+
+
+def decay_faces_device(rho, m: int = 512, p: int = 512, k: int = 32, index: int = 3, salt: int = 0,
+                       device: str = "cuda"):
+    """Transform-domain faces Xhat_f = U_f diag(10^(-rho_f j)) V_f^T, j = 1..k,
+    with U_f (m x k), V_f (p x k) the Q factors of iid N(0,1) matrices drawn on
+    the device (torch generator seeded from (index, salt)); FP64 products,
+    stored FP32 as a flat column-major (m, p, nf) buffer."""
+    import torch
+
+    nf = len(rho)
+    gen = torch.Generator(device=device).manual_seed(SEED_BASE * 1000 + index * 100003 + salt)
+    U = torch.linalg.qr(torch.randn(nf, m, k, generator=gen, device=device, dtype=torch.float64)).Q
+    V = torch.linalg.qr(torch.randn(nf, p, k, generator=gen, device=device, dtype=torch.float64)).Q
+    j = torch.arange(1, k + 1, device=device, dtype=torch.float64)
+    sig = 10.0 ** (-torch.as_tensor(rho, device=device, dtype=torch.float64)[:, None] * j)
+    # [f, b, a] = sum_r V[f, b, r] sig[f, r] U[f, a, r]: column-major (m, p) faces
+    X = torch.bmm((V * sig[:, None, :]).contiguous(), U.transpose(1, 2).contiguous())
+    return X.reshape(-1).to(torch.float32).contiguous(), sig.cpu().numpy()

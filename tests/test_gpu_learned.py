@@ -1,0 +1,133 @@
+"""GPU checks of the learned-width truncation (tsvdm_truncate_learned):
+certified errors, parity of sampled faces with the oracle's exact truncation,
+the certificate fallback, and training of the predictor on library labels."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2105_01170_amd import api, learned  # noqa: E402
+from paper_2105_01170_amd import tsvdm as C  # noqa: E402
+
+M = P = 128
+TAU = 1e-4
+
+
+def _omega():
+    g = np.random.default_rng(21)
+    return torch.from_numpy(np.asfortranarray(g.standard_normal((P, 40))).astype(np.float32)
+                            .ravel(order="F")).to("cuda")
+
+
+def _faces(n, salt, lo=1 / 16, hi=1 / 2):
+    rho = synth.decay_profiles(n, lo=lo, hi=hi, index=3, salt=salt)
+    xh, sig = synth.decay_faces_device(rho, M, P, 32, index=3, salt=salt)
+    return xh, sig
+
+
+def _host(F, nf):
+    k = F.kmax
+    U = F.U.cpu().numpy().reshape((M, k, nf), order="F")
+    S = F.S.cpu().numpy().reshape((k, nf), order="F")
+    V = F.V.cpu().numpy().reshape((P, k, nf), order="F")
+    return U, S, V
+
+
+def _constant_predictor(width_out):
+    """Zero weights, output bias (0.5, width_out): every face gets the same width."""
+    theta = np.zeros(mlp.NPARAMS)
+    mlp.unpack(theta)["b3"][...] = [0.5, width_out]
+    return api.RankPredictor(torch.from_numpy(theta))
+
+
+def _check_batch(xh, F, widths, nf, sample):
+    cert = F.cert.cpu().numpy()
+    fro = F.fro.cpu().numpy()
+    assert np.all(cert <= TAU * fro * (1 + 1e-12))
+    assert set(np.unique(widths)) <= {16, 32, 40}
+    U, S, V = _host(F, nf)
+    ranks = F.ranks.cpu().numpy()
+    X = xh.cpu().numpy().astype(np.float64).reshape((M, P, nf), order="F")
+    for f in sample:
+        xf = X[:, :, f]
+        ref = oracle.tsvdm_truncate_faces(xf[:, :, None], "energy", 32, TAU)
+        k = ranks[f]
+        T = (U[:, :k, f] * S[:k, f]) @ V[:, :k, f].T
+        true = np.linalg.norm(xf - T)
+        assert true <= cert[f] * (1 + 1e-3) + 1e-6 * fro[f]
+        # the randomized truncation keeps at least the optimal rank, not many more
+        assert ref["ranks"][0] <= k <= ref["ranks"][0] + 3
+        np.testing.assert_allclose(S[:k, f][:ref["ranks"][0]], ref["s"][:ref["ranks"][0], 0],
+                                   rtol=1e-3, atol=1e-6 * fro[f])
+
+
+def test_fallback_restores_the_tolerance():
+    """A predictor that always answers width 16, on slowly decaying faces (the
+    energy rank exceeds the width-16 cap of 13): every face fails its
+    certificate there and is truncated again with width 40."""
+    nf = 64
+    xh, _ = _faces(nf, salt=1, lo=1 / 16, hi=1 / 12)
+    pred = _constant_predictor(0.1)
+    lt = api.LearnedTruncator(M, P, nf, _omega(), tau=TAU)
+    F = lt(xh, pred)
+    widths = lt.widths.cpu().numpy()
+    assert np.all(widths == 40)
+    _check_batch(xh, F, widths, nf, range(0, nf, 9))
+
+
+def test_trained_predictor_widths_and_parity():
+    """Train on library labels of 4096 faces, truncate 256 held-out faces:
+    the certified error meets tau everywhere and sampled faces agree with the
+    oracle's exact truncation."""
+    om = _omega()
+    feats, tg = [], []
+    for b in range(16):
+        xh, _ = _faces(256, salt=100 + b)
+        feats.append(api.rank_features(xh, M, P, 256, om))
+        rank, width = learned.labels(xh, M, P, 256, om, TAU)
+        tg.append(learned.targets(rank, width))
+    feats = torch.cat(feats)
+    tg = torch.cat(tg)
+    pred = api.RankPredictor(torch.from_numpy(mlp.init_params(np.random.default_rng(4))))
+    hist = learned.train(pred, feats, tg, epochs=25, batch=512, lr=2e-3)
+    assert hist[-1] < 0.2 * hist[0]
+    xh, _ = _faces(256, salt=999)
+    lt = api.LearnedTruncator(M, P, 256, om, tau=TAU)
+    F = lt(xh, pred)
+    widths = lt.widths.cpu().numpy()
+    assert len(np.unique(widths)) >= 2  # the widths follow the faces
+    _check_batch(xh, F, widths, 256, range(0, 256, 23))
+
+
+def test_narrow_faces_take_the_narrow_width():
+    """Fast decay (rho in [0.4, 0.5], energy rank <= 10): a width-16 answer
+    holds for every face (no fallback), and the result is timed against the
+    fixed width 40 on the same faces (printed)."""
+    nf = 256
+    xh, _ = _faces(nf, salt=7, lo=0.4, hi=0.5)
+    om = _omega()
+    pred = _constant_predictor(0.1)
+    lt = api.LearnedTruncator(M, P, nf, om, tau=TAU)
+    F = lt(xh, pred)
+    widths = lt.widths.cpu().numpy()
+    assert np.all(widths == 16)
+    _check_batch(xh, F, widths, nf, range(0, nf, 31))
+    fixed = api.Truncator(M, P, nf, torch.float32, rank_mode=C.RANK_ENERGY, k=32, tau=TAU,
+                          precision=C.PREC_MIXED, oversample=8, power_iters=1, omega=om, kmax=32)
+    times = {}
+    for name, fn in (("fixed40", lambda: fixed(xh)), ("learned", lambda: lt(xh, pred))):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        times[name] = e0.elapsed_time(e1) / 5
+    print("narrow faces, ms per batch:", times)
