@@ -372,7 +372,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                          "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+                          "(sharding over several GPUs is designed but not built)"}))
         sys.exit(2)
     if args.workload == "uneven":
         return uneven_main(args)
