@@ -62,25 +62,30 @@ __device__ __forceinline__ bool jrot(double app, double aqq, double apq, bool va
     return go;
 }
 
-// Cyclic Jacobi eigensolver of the symmetric n x n matrix in G0 (LDS, pitch
-// LP+1, zero outside the leading n x n block) with the round-robin ordering:
-// in round r the ne/2 disjoint pairs (ne = n rounded up to even) are
-// (r, ne-1) and ((r+k) mod (ne-1), (r-k) mod (ne-1)), k = 1..ne/2-1; every
-// 2x2 block (pair p rows, pair q columns) becomes J_p^T B J_q at once.
-// One barrier per round: the matrix is double buffered (G0, G1) and every
-// thread forms the rotations its blocks need from the current buffer.  Only
-// blocks p <= q are computed; each writes its mirror.  The eigenvectors
-// accumulate in Et (transposed: Et[c*(LP+2) + r] = E[r][c]; the identity on
-// entry) one round late, from the rotations the diagonal blocks record in
-// cs[2][LP/2].  rflag[3]: zero on entry.  A sweep with no rotation ends the
-// iteration (conv = 1); at most max_sweeps sweeps.  NTH threads take part
-// (the whole workgroup).  Returns the buffer holding the final matrix, whose
-// diagonal is the eigenvalues.  Ends with a barrier.
+// Cyclic Jacobi eigensolver of the symmetric n x n matrix in G (LDS, pitch
+// LP+1; only the upper triangle i <= j is read or written) with the
+// round-robin ordering: in round r the ne/2 disjoint pairs (ne = n rounded up
+// to even) are (r, ne-1) and ((r+k) mod (ne-1), (r-k) mod (ne-1)),
+// k = 1..ne/2-1.  Two barriers per round:
+//  A. thread k < ne/2 forms the rotation (c, s) of pair k from the current
+//     diagonal pair and off-diagonal entry and stores it in cs (one record set
+//     per round parity, cs[2][LP/2]); meanwhile the eigenvector columns take
+//     the previous round's rotations (Et, transposed: Et[c*(LP+2) + r] =
+//     E[r][c], the identity on entry, rows in quads);
+//  B. every 2x2 block (pair p rows, pair q columns, p <= q) becomes
+//     J_p^T B J_q from its four stored entries and the two rotations.
+// Every entry of the upper triangle belongs to exactly one block, so the
+// blocks update in place.  The last round's rotations reach the eigenvectors
+// after the loop.  rflag[3]: zero on entry.  A sweep with no rotation
+// ends the iteration (conv = 1); at most max_sweeps sweeps.  NTH threads take
+// part (the whole workgroup).  Returns G (its diagonal is the eigenvalues).
+// Ends with a barrier.  G1 is not used (kept for the callers' layout).
 template <int LP, int NTH>
-__device__ const double *jacobi_eig(double *G0, double *G1, double *Et, double2 *cs, int *rflag,
+__device__ const double *jacobi_eig(double *G, double *G1, double *Et, double2 *cs, int *rflag,
                                     int n, double trace, int max_sweeps, int &conv) {
     constexpr int LD = LP + 1, LDE = LP + 2, NPM = LP / 2;
     constexpr int IPT = (NPM * (NPM + 1) / 2 + (LP / 4) * NPM + NTH - 1) / NTH;  // items per thread
+    (void)G1;
     const int tid = threadIdx.x, lane = tid & 63;
     const int ne = n + (n & 1), np = ne / 2, n1 = ne - 1;
     // this thread's items, fixed for all rounds: G block (pp <= qq) or E block
@@ -106,8 +111,8 @@ __device__ const double *jacobi_eig(double *G0, double *G1, double *Et, double2 
             i1[u] = i2[u] = 0;
         }
     }
-    // E block item: apply the rotations of round r (stored in cs[par]) to its
-    // four rows of the eigenvector columns of pair i2
+    auto up = [&](int i, int j) -> int { return i <= j ? i * LD + j : j * LD + i; };
+    // eigenvector block item: the rotations of round r (record set par)
     auto e_item = [&](int u, int r, int par) {
         int c2, d;
         rr_pair(r, i2[u], n1, c2, d);
@@ -122,62 +127,61 @@ __device__ const double *jacobi_eig(double *G0, double *G1, double *Et, double2 
         pd[1] = double2{rt.y * x1.x + rt.x * y1.x, rt.y * x1.y + rt.x * y1.y};
     };
 
-    int sweep = 0, cur = 0, rr = 0;  // rr counts rounds over all sweeps
+    int sweep = 0, rr = 0, rprev = 0;  // rr counts rounds over all sweeps
     conv = 0;
     for (sweep = 1; sweep <= max_sweeps && n > 1; ++sweep) {
         const int fl = sweep % 3;
         for (int r = 0; r < n1; ++r, ++rr) {
-            const double *Gc = cur ? G1 : G0;
-            double *Gn = cur ? G0 : G1;
+            const int par = rr & 1;
+            // ---- A: rotations; eigenvectors of the previous round
             bool any = false;
-#pragma unroll
-            for (int u = 0; u < IPT; ++u) {
-                if (ik[u] == 2) continue;
-                if (ik[u] == 0) {
-                    int a, b, c2, d;
-                    rr_pair(r, i1[u], n1, a, b);
-                    rr_pair(r, i2[u], n1, c2, d);
-                    // every load of the item first
-                    const double m00 = Gc[a * LD + c2], m01 = Gc[a * LD + d];
-                    const double m10 = Gc[b * LD + c2], m11 = Gc[b * LD + d];
-                    const double paa = Gc[a * LD + a], pbb = Gc[b * LD + b], pab = Gc[a * LD + b];
-                    const double qcc = Gc[c2 * LD + c2], qdd = Gc[d * LD + d], qcd = Gc[c2 * LD + d];
-                    double cp, sp, cq, sq;
-                    any |= jrot(paa, pbb, pab, b < n, trace, cp, sp);
-                    jrot(qcc, qdd, qcd, d < n, trace, cq, sq);
-                    // rows: (a, b) <- (cp a - sp b, sp a + cp b); then the columns
-                    const double t00 = cp * m00 - sp * m10, t01 = cp * m01 - sp * m11;
-                    const double t10 = sp * m00 + cp * m10, t11 = sp * m01 + cp * m11;
-                    const double n00 = cq * t00 - sq * t01, n01 = sq * t00 + cq * t01;
-                    const double n10 = cq * t10 - sq * t11, n11 = sq * t10 + cq * t11;
-                    if (i2[u] != i1[u]) {
-                        Gn[a * LD + c2] = n00;
-                        Gn[a * LD + d] = n01;
-                        Gn[b * LD + c2] = n10;
-                        Gn[b * LD + d] = n11;
-                        Gn[c2 * LD + a] = n00;
-                        Gn[d * LD + a] = n01;
-                        Gn[c2 * LD + b] = n10;
-                        Gn[d * LD + b] = n11;
-                    } else {  // diagonal block: kept exactly symmetric; its rotation
-                              // goes to the eigenvectors in the next round
-                        Gn[a * LD + a] = n00;
-                        Gn[a * LD + b] = n01;
-                        Gn[b * LD + a] = n01;
-                        Gn[b * LD + b] = n11;
-                        cs[(rr & 1) * NPM + i1[u]] = double2{cp, sp};
-                    }
-                } else if (rr > 0) {
-                    e_item(u, r > 0 ? r - 1 : n1 - 1, (rr - 1) & 1);
-                }
+            if (tid < np) {
+                int a, b;
+                rr_pair(r, tid, n1, a, b);
+                double c, s;
+                any = jrot(G[a * LD + a], G[b * LD + b], G[a * LD + b], b < n, trace, c, s);
+                cs[par * NPM + tid] = double2{c, s};
             }
-            // one flag write per wavefront that rotated
-            if (__any(any) && lane == 0) rflag[fl] = 1;
+            if (rr > 0) {
+#pragma unroll
+                for (int u = 0; u < IPT; ++u)
+                    if (ik[u] == 1) e_item(u, rprev, par ^ 1);
+            }
+            if (__any(any) && lane == 0) rflag[fl] = 1;  // one write per wavefront
             __syncthreads();
             // the flag of sweep+2 is cleared after the first barrier of this
             // sweep, when every thread has read it at the end of sweep-1
             if (r == 0 && tid == 0) rflag[(sweep + 2) % 3] = 0;
-            cur ^= 1;
+            // ---- B: blocks
+#pragma unroll
+            for (int u = 0; u < IPT; ++u) {
+                if (ik[u] == 0) {
+                    int a, b, c2, d;
+                    rr_pair(r, i1[u], n1, a, b);
+                    rr_pair(r, i2[u], n1, c2, d);
+                    const double2 rp = cs[par * NPM + i1[u]], rq = cs[par * NPM + i2[u]];
+                    const int p00 = up(a, c2), p01 = up(a, d), p10 = up(b, c2), p11 = up(b, d);
+                    const double m00 = G[p00], m01 = G[p01], m10 = G[p10], m11 = G[p11];
+                    const double cp = rp.x, sp = rp.y, cq = rq.x, sq = rq.y;
+                    // rows: (a, b) <- (cp a - sp b, sp a + cp b); then the columns
+                    const double t00 = cp * m00 - sp * m10, t01 = cp * m01 - sp * m11;
+                    const double t10 = sp * m00 + cp * m10, t11 = sp * m01 + cp * m11;
+                    const double n00 = cq * t00 - sq * t01, n01 = sq * t00 + cq * t01;
+                    const double n11 = sq * t10 + cq * t11;
+                    if (i2[u] != i1[u]) {
+                        G[p00] = n00;
+                        G[p01] = n01;
+                        G[p10] = cq * t10 - sq * t11;
+                        G[p11] = n11;
+                    } else {  // diagonal block: entries (a,a), (a,b), (b,b)
+                        G[p00] = n00;
+                        G[p01] = n01;
+                        G[p11] = n11;
+                    }
+                }
+            }
+            __syncthreads();
+            rprev = r;
         }
         if (rflag[fl] == 0) {
             conv = 1;
@@ -188,10 +192,10 @@ __device__ const double *jacobi_eig(double *G0, double *G1, double *Et, double2 
     if (rr > 0) {
 #pragma unroll
         for (int u = 0; u < IPT; ++u)
-            if (ik[u] == 1) e_item(u, (rr - 1) % n1, (rr - 1) & 1);
+            if (ik[u] == 1) e_item(u, rprev, (rr - 1) & 1);
     }
     __syncthreads();
-    return cur ? G1 : G0;
+    return G;
 }
 
 }  // namespace tsvdm
