@@ -1,6 +1,6 @@
 // Device helpers shared by the FP64 eigensolvers of the truncation kernels:
 // refined hardware reciprocals, the round-robin pair ordering, the symmetric
-// Schur 2x2 rotation and a one-barrier-per-round cyclic Jacobi eigensolver.
+// Schur 2x2 rotation and a cyclic Jacobi eigensolver for a workgroup.
 #pragma once
 
 #include "common.h"
@@ -44,21 +44,29 @@ __device__ __forceinline__ void rr_pair(int r, int k, int n1, int &a, int &b) {
     }
 }
 
-// rotation (c, s) of a pair from its entries app, aqq, apq; identity (and
-// false) when the pair is a padding pair or the off-diagonal entry is
-// negligible (relative to the diagonal pair, and at the rounding level of the
-// trace).  Branch free, so that the caller's loads are all issued up front.
+// a pair rotates when its off-diagonal entry is not negligible, relative to
+// the diagonal pair and at the rounding level of the trace
+__device__ __forceinline__ bool jneeds(double app, double aqq, double apq, double trace) {
+    return apq * apq > 1e-30 * fabs(app * aqq) && fabs(apq) > 1e-15 * trace;
+}
+
+// rotation (c, s) of a pair from its entries app, aqq, apq: the smaller of
+// the two angles that annihilate apq, by the half-angle formulas
+//   h = sqrt(d^2 + e^2),  c = sqrt((1 + |d|/h) / 2),  s = +-|e| / (2 h c)
+// (d = aqq - app, e = 2 apq; no cancellation, c^2 + s^2 = 1 up to rounding);
+// identity (and false) for a padding pair or a pair that need not rotate.
+// Branch free, so that the caller's loads are all issued up front.
 __device__ __forceinline__ bool jrot(double app, double aqq, double apq, bool valid, double trace,
                                      double &c, double &s) {
-    const bool go = valid && apq * apq > 1e-30 * fabs(app * aqq) && fabs(apq) > 1e-15 * trace;
+    const bool go = valid && jneeds(app, aqq, apq, trace);
     const double d = aqq - app, e = 2.0 * apq;
-    const double q = go ? fma(d, d, e * e) : 1.0;
-    const double h = q * rsqrt_nr(q);
-    double t = fabs(e) * recip(go ? fabs(d) + h : 1.0);
-    t = (d == 0.0 || ((d > 0.0) == (e > 0.0))) ? t : -t;
-    const double cc = rsqrt_nr(fma(t, t, 1.0));
-    c = go ? cc : 1.0;
-    s = go ? cc * t : 0.0;
+    const double y = rsqrt_nr(go ? fma(d, d, e * e) : 1.0);  // 1 / h
+    const double c2 = fma(0.5 * fabs(d), y, 0.5);          // cos^2 of the angle
+    const double z = rsqrt_nr(c2);                          // 1 / c
+    const double sa = 0.5 * fabs(e) * y * z;
+    const bool pos = d == 0.0 || ((d > 0.0) == (e > 0.0));
+    c = go ? c2 * z : 1.0;
+    s = go ? (pos ? sa : -sa) : 0.0;
     return go;
 }
 
@@ -76,8 +84,10 @@ __device__ __forceinline__ bool jrot(double app, double aqq, double apq, bool va
 //     J_p^T B J_q from its four stored entries and the two rotations.
 // Every entry of the upper triangle belongs to exactly one block, so the
 // blocks update in place.  The last round's rotations reach the eigenvectors
-// after the loop.  rflag[3]: zero on entry.  A sweep with no rotation
-// ends the iteration (conv = 1); at most max_sweeps sweeps.  NTH threads take
+// after the loop.  rflag[3]: zero on entry.  Before every sweep all pairs are
+// tested with the rotation criterion; when none would rotate the iteration
+// ends (conv = 1) -- the same result as a sweep without rotations, at the
+// cost of one parallel pass.  At most max_sweeps sweeps.  NTH threads take
 // part (the whole workgroup).  Returns G (its diagonal is the eigenvalues).
 // Ends with a barrier.  G1 is not used (kept for the callers' layout).
 template <int LP, int NTH>
@@ -129,17 +139,33 @@ __device__ const double *jacobi_eig(double *G, double *G1, double *Et, double2 *
 
     int sweep = 0, rr = 0, rprev = 0;  // rr counts rounds over all sweeps
     conv = 0;
-    for (sweep = 1; sweep <= max_sweeps && n > 1; ++sweep) {
+    for (sweep = 1;; ++sweep) {
+        // convergence test over the upper triangle; flag fl, cleared two
+        // tests ahead (every thread has read it by the next test's barrier)
         const int fl = sweep % 3;
+        {
+            bool need = false;
+            for (int e = tid; e < n * n; e += NTH) {
+                const int i = e / n, j = e - i * n;
+                if (i < j) need |= jneeds(G[i * LD + i], G[j * LD + j], G[i * LD + j], trace);
+            }
+            if (__any(need) && lane == 0) rflag[fl] = 1;
+            __syncthreads();
+            if (tid == 0) rflag[(sweep + 2) % 3] = 0;
+            if (rflag[fl] == 0) {
+                conv = 1;
+                break;
+            }
+        }
+        if (sweep > max_sweeps) break;
         for (int r = 0; r < n1; ++r, ++rr) {
             const int par = rr & 1;
             // ---- A: rotations; eigenvectors of the previous round
-            bool any = false;
             if (tid < np) {
                 int a, b;
                 rr_pair(r, tid, n1, a, b);
                 double c, s;
-                any = jrot(G[a * LD + a], G[b * LD + b], G[a * LD + b], b < n, trace, c, s);
+                jrot(G[a * LD + a], G[b * LD + b], G[a * LD + b], b < n, trace, c, s);
                 cs[par * NPM + tid] = double2{c, s};
             }
             if (rr > 0) {
@@ -147,11 +173,7 @@ __device__ const double *jacobi_eig(double *G, double *G1, double *Et, double2 *
                 for (int u = 0; u < IPT; ++u)
                     if (ik[u] == 1) e_item(u, rprev, par ^ 1);
             }
-            if (__any(any) && lane == 0) rflag[fl] = 1;  // one write per wavefront
             __syncthreads();
-            // the flag of sweep+2 is cleared after the first barrier of this
-            // sweep, when every thread has read it at the end of sweep-1
-            if (r == 0 && tid == 0) rflag[(sweep + 2) % 3] = 0;
             // ---- B: blocks
 #pragma unroll
             for (int u = 0; u < IPT; ++u) {
@@ -182,10 +204,6 @@ __device__ const double *jacobi_eig(double *G, double *G1, double *Et, double2 *
             }
             __syncthreads();
             rprev = r;
-        }
-        if (rflag[fl] == 0) {
-            conv = 1;
-            break;
         }
     }
     // the eigenvectors take the last round's rotations
