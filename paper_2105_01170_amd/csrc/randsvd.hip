@@ -314,20 +314,37 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
 // ---------------------------------------------------------------- Z = X^T W
 // Grid (ceil(p/64), nf).  Workgroup: output rows b0..b0+63 (columns of the
 // face), K = m in chunks of 64.  W is m x nw (leading dim ldw), per face.
-template <int LP, int PROD, bool GRAM>
+// RES (with GRAM, W = Q with ldw = m, the projection B^T = X^T Q): the
+// workgroup then also sums ||X[:, b0:b0+64] - Q B[:, b0:b0+64]||_F^2 into
+// res_part[f * nb + blk], computed directly (not by cancellation): Q B by
+// FP32 MFMA from the block of B^T it has just formed, differences and squares
+// in FP64.  It reads the X block a second time, last chunk first, so the
+// chunks it read most recently come from cache.  Together with the discarded
+// eigenvalues of B B^T this is the error of the truncated result.
+// VEC: m is a multiple of 4 and X 16-byte aligned (checked by the caller), so
+// the four consecutive rows a lane reads are one 16-byte load.  All loads
+// are branch free (clamped address, then a select), so they are in flight
+// together.
+template <int LP, int PROD, bool GRAM, bool RES, bool VEC>
 __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, int p, int nf,
                                             const float *__restrict__ W, int64_t w_stride, int ldw,
                                             int nw, float *__restrict__ Z,
                                             double *__restrict__ gram_part,
+                                            double *__restrict__ res_part,
     const int32_t *__restrict__ fmap) {
     constexpr int KC = 64, LDK = KC + 8;
     constexpr int NB = LP / 16, WPT = KC * LP / GT;
     constexpr bool SPL = PROD == PROD_SPLIT;
-    __shared__ __align__(16) uint16_t xh[64 * LDK];
-    __shared__ __align__(16) uint16_t xl[SPL ? 64 * LDK : 8];
-    __shared__ __align__(16) uint16_t wh[LP * LDK];
-    __shared__ __align__(16) uint16_t wl[SPL ? LP * LDK : 8];
+    static_assert(!RES || GRAM, "the residual takes B^T from the Gram staging");
+    // LDS: the BF16 operands of the main loop; the residual stages the FP32
+    // Q chunk (64 x (LP+1)) in the same bytes afterwards
+    constexpr int XS = 64 * LDK, WS = LP * LDK;  // uint16 elements, multiples of 8
+    constexpr int MAINB = (SPL ? 2 : 1) * (XS + WS) * 2, QSB = RES ? 64 * (LP + 1) * 4 : 0;
+    __shared__ __align__(16) uint16_t smem[(MAINB > QSB ? MAINB : QSB) / 2];
     __shared__ float ys[GRAM ? 64 * (LP + 1) : 1];
+    __shared__ double red[RES ? GT / 64 : 1];
+    uint16_t *xh = smem, *wh = smem + XS;
+    uint16_t *xl = SPL ? smem + XS + WS : xh, *wl = SPL ? smem + 2 * XS + WS : wh;
     const int nb = (p + 63) / 64;
     int blk, f;
     xcd_map(blockIdx.x, nb, nf, blk, f);
@@ -341,19 +358,30 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
     for (int j = 0; j < NB; ++j) acc[j] = f32x4{0, 0, 0, 0};
     float xr[16], wr[WPT];
     auto load = [&](int a0) {
+        const int a = a0 + 4 * q4;
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
             const int b = b0 + cj0 + 16 * it;
+            if constexpr (VEC) {  // a < m implies a + 3 < m
+                const bool ok = b < p && a < m;
+                const f32x4 x = *reinterpret_cast<const f32x4 *>(Xf + (ok ? a + (int64_t)m * b : 0));
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int a = a0 + 4 * q4 + v;
-                xr[4 * it + v] = (b < p && a < m) ? Xf[a + (int64_t)m * b] : 0.0f;
+                for (int v = 0; v < 4; ++v) xr[4 * it + v] = ok ? x[v] : 0.0f;
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const bool ok = b < p && a + v < m;
+                    const float x = Xf[ok ? a + v + (int64_t)m * b : 0];
+                    xr[4 * it + v] = ok ? x : 0.0f;
+                }
             }
         }
 #pragma unroll
         for (int q = 0; q < WPT; ++q) {
             const int e = tid + q * GT, k = e % KC, c = e / KC, a = a0 + k;
-            wr[q] = (c < nw && a < m) ? Wf[a + (int64_t)ldw * c] : 0.0f;
+            const bool ok = c < nw && a < m;
+            const float x = Wf[ok ? a + (int64_t)ldw * c : 0];
+            wr[q] = ok ? x : 0.0f;
         }
     };
     load(0);
@@ -414,6 +442,71 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
         }
     }
     if (GRAM) block_gram_f64<LP>(acc, gram_part + ((int64_t)f * nb + blk) * LP * LP, ys);
+    if (RES) {
+        // ys[b * (LP+1) + c] = B^T[b0 + b][c] (rows past p are zero): the
+        // B operands of the 16x16x4 MFMA (k = lane/16, column lane%16)
+        constexpr int LD = LP + 1, KK = LP / 4;
+        float *qs = reinterpret_cast<float *>(smem);
+        // X values of the MFMA output positions: rows a = a0 + 16*wave +
+        // 4*(lane/16) + v (four consecutive rows), columns b = b0 + 16t + lane%16
+        auto rload = [&](int a0, f32x4(&xv)[4]) {
+            const int a = a0 + 16 * wave + 4 * (lane >> 4);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int b = b0 + 16 * t + (lane & 15);
+                const bool bok = b < p;
+                if constexpr (VEC) {
+                    const bool ok = bok && a < m;
+                    const f32x4 x = *reinterpret_cast<const f32x4 *>(Xf + (ok ? a + (int64_t)m * b : 0));
+                    xv[t] = ok ? x : f32x4{0, 0, 0, 0};
+                } else {
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const bool ok = bok && a + v < m;
+                        const float x = Xf[ok ? a + v + (int64_t)m * b : 0];
+                        xv[t][v] = ok ? x : 0.0f;
+                    }
+                }
+            }
+        };
+        const int nch = (m + KC - 1) / KC;
+        double racc = 0.0;
+        f32x4 xv[4], xn[4];
+        rload((nch - 1) * KC, xv);
+        for (int ci = nch - 1; ci >= 0; --ci) {
+            const int a0 = ci * KC;
+            stage_panel<LP, 64>(Wf, m, a0, qs);
+            __syncthreads();
+            if (ci > 0) rload(a0 - KC, xn);  // next chunk in flight during the MFMAs
+            f32x4 pr[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) pr[t] = f32x4{0, 0, 0, 0};
+#pragma unroll
+            for (int kk = 0; kk < KK; ++kk) {
+                if (4 * kk >= nw) break;  // columns past ell of Q are zero
+                const float av = qs[(16 * wave + (lane & 15)) * LD + 4 * kk + (lane >> 4)];
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const float bv = ys[(16 * t + (lane & 15)) * LD + 4 * kk + (lane >> 4)];
+                    pr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, pr[t], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double d = (double)xv[t][v] - (double)pr[t][v];
+                    racc += d * d;
+                }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < 4; ++t) xv[t] = xn[t];
+        }
+        racc = wave_sum(racc);
+        if (lane == 0) red[wave] = racc;
+        __syncthreads();
+        if (tid == 0) res_part[(int64_t)f * nb + blk] = red[0] + red[1] + red[2] + red[3];
+    }
 }
 
 // ---------------------------------------------------------------- Cholesky-QR
@@ -607,69 +700,6 @@ __global__ __launch_bounds__(QT) void k_cholqr(const float *__restrict__ Sin, in
         }
     }
     if (tid == 0 && bad) qr_info[f] = 2;
-}
-
-// ---------------------------------------------------------------- residual
-// Partial sums over 64-column blocks of ||X - Q B||_F^2 with B^T = X^T Q (the
-// projection), computed directly (not by cancellation): Q B by FP32 MFMA,
-// differences and squares in FP64.  Together with the discarded eigenvalues
-// of B B^T this is the error of the truncated result.
-template <int LP>
-__global__ __launch_bounds__(GT) void k_resid(const float *__restrict__ X, int m, int p, int nf,
-                                              const float *__restrict__ Q, const float *__restrict__ Bt,
-                                              double *__restrict__ part,
-    const int32_t *__restrict__ fmap) {
-    constexpr int LD = LP + 1;
-    __shared__ float bs[64 * LD];  // [b][c] = B^T block
-    __shared__ float qs[64 * LD];  // [a][c] = Q chunk
-    __shared__ double red[GT / 64];
-    const int nb = (p + 63) / 64;
-    int blk, f;
-    xcd_map(blockIdx.x, nb, nf, blk, f);
-    const int b0 = blk * 64, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const float *Xf = X + (int64_t)(fmap ? fmap[f] : f) * m * p;
-    const float *Qf = Q + (int64_t)f * m * LP;
-    const float *Bf = Bt + (int64_t)f * p * LP;
-    stage_panel<LP, 64>(Bf, p, b0, bs);
-    double acc = 0.0;
-    const int ar = 16 * wave + (lane & 15), kl = lane >> 4;
-    for (int a0 = 0; a0 < m; a0 += 64) {
-        __syncthreads();
-        // X values this lane compares against, loaded with the Q chunk
-        float xv[4][4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                int a = a0 + 16 * wave + 4 * (lane >> 4) + v, b = b0 + 16 * t + (lane & 15);
-                xv[t][v] = (a < m && b < p) ? Xf[a + (int64_t)m * b] : 0.0f;
-            }
-        stage_panel<LP, 64>(Qf, m, a0, qs);
-        __syncthreads();
-        f32x4 pr[4];
-#pragma unroll
-        for (int t = 0; t < 4; ++t) pr[t] = f32x4{0, 0, 0, 0};
-#pragma unroll
-        for (int kk = 0; kk < LP / 4; ++kk) {
-            const float av = qs[ar * LD + 4 * kk + kl];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const float bv = bs[(16 * t + (lane & 15)) * LD + 4 * kk + kl];
-                pr[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, pr[t], 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                double d = (double)xv[t][v] - (double)pr[t][v];
-                acc += d * d;
-            }
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) red[wave] = acc;
-    __syncthreads();
-    if (tid == 0) part[(int64_t)f * nb + blk] = red[0] + red[1] + red[2] + red[3];
 }
 
 // ---------------------------------------------------------------- core SVD
@@ -1010,6 +1040,9 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     const bool power = o->power_iters > 0;
     // the residual is needed for the certificate and for the energy rule
     const bool resid = o->rank_mode == TSVDM_RANK_ENERGY || (o->certify && cert);
+    // 16-byte loads of four consecutive rows of X (every face start is then
+    // 16-byte aligned too)
+    const bool v4 = m % 4 == 0 && reinterpret_cast<uintptr_t>(Xd) % 16 == 0;
     TSVDM_LAUNCH("zero_info", k_zero_i32, dim3((nf + 255) / 256), dim3(256), 0, s, w.qr_info, nf);
     const double *gm_c = w.gram_m, *gp_c = w.gram_p;
     if (power) {
@@ -1021,8 +1054,12 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
         TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell,
                      w.Qm, 1, gm_c, mparts, w.qr_info);
         // pass 2: Z = X^T Q (BF16) and its Gram partials; basis of Z
-        TSVDM_LAUNCH("power_xtw_bf16", (k_xtw<LP, PROD_BF16, true>), gp, dim3(GT), 0, s, Xd, m, p, nf,
-                     (const float *)w.Qm, (int64_t)m * LP, m, LP, w.Z, w.gram_p, fmap);
+        if (v4)
+            TSVDM_LAUNCH("power_xtw_bf16", (k_xtw<LP, PROD_BF16, true, false, true>), gp, dim3(GT), 0, s, Xd, m,
+                         p, nf, (const float *)w.Qm, (int64_t)m * LP, m, ell, w.Z, w.gram_p, (double *)nullptr, fmap);
+        else
+            TSVDM_LAUNCH("power_xtw_bf16", (k_xtw<LP, PROD_BF16, true, false, false>), gp, dim3(GT), 0, s, Xd, m,
+                         p, nf, (const float *)w.Qm, (int64_t)m * LP, m, ell, w.Z, w.gram_p, (double *)nullptr, fmap);
         TSVDM_LAUNCH("cholqr_power_z", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Z, p, ell,
                      w.Qp, 1, gp_c, pparts, w.qr_info);
         // pass 3: Y' = X Qz, FP32-accurate (split BF16), and its Gram partials
@@ -1035,12 +1072,19 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     // final basis: FP64 shifted Cholesky-QR2 (first Gram from the partials)
     TSVDM_LAUNCH("cholqr_final", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell, w.Qm,
                  2, gm_c, mparts, w.qr_info);
-    // pass 4: B^T = X^T Q, FP32-accurate, and the Gram partials of B^T
-    TSVDM_LAUNCH("project_xtw_split", (k_xtw<LP, PROD_SPLIT, true>), gp, dim3(GT), 0, s, Xd, m, p, nf,
-                 (const float *)w.Qm, (int64_t)m * LP, m, LP, w.Z, w.gram_p, fmap);
-    if (resid)  // pass 5: ||X - Q B||^2 per 64-column block
-        TSVDM_LAUNCH("certificate_resid", (k_resid<LP>), gp, dim3(GT), 0, s, Xd, m, p, nf,
-                     (const float *)w.Qm, (const float *)w.Z, w.res_part, fmap);
+    // pass 4: B^T = X^T Q, FP32-accurate, the Gram partials of B^T and, for
+    // the certificate, ||X - Q B||^2 per 64-column block
+#define TSVDM_PROJECT(NAME, RES, V, RP)                                                                    \
+    TSVDM_LAUNCH(NAME, (k_xtw<LP, PROD_SPLIT, true, RES, V>), gp, dim3(GT), 0, s, Xd, m, p, nf,             \
+                 (const float *)w.Qm, (int64_t)m * LP, m, ell, w.Z, w.gram_p, RP, fmap)
+    if (resid) {
+        if (v4) TSVDM_PROJECT("project_resid_split", true, true, w.res_part);
+        else TSVDM_PROJECT("project_resid_split", true, false, w.res_part);
+    } else {
+        if (v4) TSVDM_PROJECT("project_xtw_split", false, true, (double *)nullptr);
+        else TSVDM_PROJECT("project_xtw_split", false, false, (double *)nullptr);
+    }
+#undef TSVDM_PROJECT
     const int msw = o->max_sweeps > 0 ? o->max_sweeps : 30;
     TSVDM_LAUNCH("core_gram_eig", (k_core<LP>), dim3(nf), dim3(QT), 0, s, gp_c, pparts, ell,
                  (const double *)w.fro_part, mparts, (const double *)w.res_part, resid ? pparts : 0,
