@@ -178,10 +178,10 @@ __global__ __launch_bounds__(BT) void k_bgram(const Item *__restrict__ items, in
 // the pivoted Cholesky: 1e-3 tau^2 trace(G) (ENERGY), 1e-15 trace(G) (FIXED).
 __global__ __launch_bounds__(64) void k_bcore(const Item *__restrict__ items, int mode, int kcap,
                                               double tau, int max_sweeps) {
-    constexpr int LD = RX + 1, LDE = RX + 2;
+    constexpr int LD = jacobi_ld<RX>(), LDE = jacobi_ld<RX>();
     __shared__ double R[RX * MX];  // R[t * MX + i]: row t of the factor, column i
-    __shared__ double Hb[2][RX * LD];
-    __shared__ __align__(16) double Et[RX * LDE];
+    __shared__ __align__(16) double Hb[2][RX * LD];
+    __shared__ __align__(16) double Eb[2][RX * LDE];
     __shared__ __align__(16) double2 cs[2 * (RX / 2)];
     __shared__ double diag[MX];
     __shared__ int chosen[MX];
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(64) void k_bcore(const Item *__restrict__ items, in
 
     // ---- H = R R^T (r x r) and its eigen-decomposition
     for (int e = lane; e < RX * LD; e += 64) Hb[0][e] = 0.0;
-    for (int e = lane; e < RX * LDE; e += 64) Et[e] = 0.0;
+    for (int e = lane; e < RX * LDE; e += 64) Eb[0][e] = Eb[1][e] = 0.0;
     if (lane < 3) rflag[lane] = 0;
     __syncthreads();
     for (int e = lane; e < r * r; e += 64) {
@@ -253,12 +253,17 @@ __global__ __launch_bounds__(64) void k_bcore(const Item *__restrict__ items, in
         Hb[0][a * LD + b] = h;
         Hb[0][b * LD + a] = h;
     }
-    if (lane < r) Et[lane * LDE + lane] = 1.0;
+    if (lane < r) Eb[0][lane * LDE + lane] = 1.0;
     __syncthreads();
     double trH = wave_sum(lane < r ? Hb[0][lane * LD + lane] : 0.0);
     int conv = 0;
-    const double *Hf = jacobi_eig<RX, 64>(Hb[0], Hb[1], Et, cs, rflag, r, trH, max_sweeps, conv);
-    if (lane < r) lam[lane] = fmax(Hf[lane * LD + lane], 0.0);
+    const double *Hf, *Ef;
+    int dslot;
+    jacobi_eig<RX, 64>(Hb[0], Hb[1], Eb[0], Eb[1], cs, rflag, r, trH, max_sweeps, conv, Hf, Ef, dslot);
+    if (lane < r) {
+        const int sl = jacobi_slot(lane, dslot);
+        lam[lane] = fmax(Hf[sl * LD + sl], 0.0);
+    }
     __syncthreads();
     if (lane < r) {
         int pos = 0;
@@ -307,7 +312,8 @@ __global__ __launch_bounds__(64) void k_bcore(const Item *__restrict__ items, in
                 const int c = perm[j];
                 const double sg = sqrt(lam[c]);
                 double u = 0.0;
-                for (int t = 0; t < r; ++t) u += R[t * MX + lane] * Et[c * LDE + t];
+                const int sl = jacobi_slot(c, dslot);
+                for (int t = 0; t < r; ++t) u += R[t * MX + lane] * Ef[sl * LDE + t];
                 out = sg > 0.0 ? (float)(u / sg) : 0.0f;
             }
             it.U[lane + (int64_t)m * j] = out;

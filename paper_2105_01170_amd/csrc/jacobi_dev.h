@@ -1,6 +1,7 @@
 // Device helpers shared by the FP64 eigensolvers of the truncation kernels:
-// refined hardware reciprocals, the round-robin pair ordering, the symmetric
-// Schur 2x2 rotation and a cyclic Jacobi eigensolver for a workgroup.
+// refined hardware reciprocals, the symmetric Schur 2x2 rotation, the
+// round-robin slot permutation and a cyclic Jacobi eigensolver for a
+// workgroup.
 #pragma once
 
 #include "common.h"
@@ -25,23 +26,6 @@ __device__ __forceinline__ double rsqrt_nr(double a) {
     y = fma(0.5 * y, e, y);
     e = fma(-a * y, y, 1.0);
     return fma(0.5 * y, e, y);
-}
-
-__device__ __forceinline__ void rr_pair(int r, int k, int n1, int &a, int &b) {
-    if (k == 0) {
-        a = r;
-        b = n1;
-    } else {
-        a = r + k;
-        if (a >= n1) a -= n1;
-        b = r - k;
-        if (b < 0) b += n1;
-    }
-    if (a > b) {
-        const int t = a;
-        a = b;
-        b = t;
-    }
 }
 
 // a pair rotates when its off-diagonal entry is not negligible, relative to
@@ -70,84 +54,118 @@ __device__ __forceinline__ bool jrot(double app, double aqq, double apq, bool va
     return go;
 }
 
-// Cyclic Jacobi eigensolver of the symmetric n x n matrix in G (LDS, pitch
-// LP+1; only the upper triangle i <= j is read or written) with the
-// round-robin ordering: in round r the ne/2 disjoint pairs (ne = n rounded up
-// to even) are (r, ne-1) and ((r+k) mod (ne-1), (r-k) mod (ne-1)),
-// k = 1..ne/2-1.  Two barriers per round:
-//  A. thread k < ne/2 forms the rotation (c, s) of pair k from the current
-//     diagonal pair and off-diagonal entry and stores it in cs (one record set
+// Pitch (doubles) of the matrix and eigenvector buffers of jacobi_eig: even,
+// so that rows of a pair of slots start 16-byte aligned.
+template <int LP>
+constexpr int jacobi_ld() {
+    return LP + 2;
+}
+
+// Slot permutation of the round-robin (circle) ordering on ne = 2h slots,
+// pair k in slots (2k, 2k+1): slot 0 stays; the top row 2, 4, .., 2h-2 moves
+// one place right, its last entry to 2h-1; the bottom row 2h-1, .., 3, 1
+// moves one place left, slot 1 to slot 2.  After ne-1 rounds every pair of
+// entries has shared a slot pair once.
+__device__ __forceinline__ int rr_next(int s, int h) {
+    if (s == 0 || h == 1) return s;
+    const int k = s >> 1;
+    if ((s & 1) == 0) return k <= h - 2 ? s + 2 : 2 * h - 1;
+    return k >= 1 ? s - 2 : 2;
+}
+
+// Cyclic Jacobi eigensolver of the symmetric n x n matrix in G0 (LDS, pitch
+// jacobi_ld<LP>(), upper triangle i <= j used) with the round-robin ordering,
+// run on slots: in every round pair k occupies slots (2k, 2k+1), and after the
+// round every entry moves to the slots rr_next gives, which is the same
+// permutation in every round.  So every work item reads and writes fixed
+// addresses for the whole solve.  Two barriers per round:
+//  A. thread k < ne/2 (ne = n rounded up to even) forms the rotation (c, s)
+//     of pair k from its diagonal block and stores it in cs (one record set
 //     per round parity, cs[2][LP/2]); meanwhile the eigenvector columns take
-//     the previous round's rotations (Et, transposed: Et[c*(LP+2) + r] =
-//     E[r][c], the identity on entry, rows in quads);
-//  B. every 2x2 block (pair p rows, pair q columns, p <= q) becomes
-//     J_p^T B J_q from its four stored entries and the two rotations.
-// Every entry of the upper triangle belongs to exactly one block, so the
-// blocks update in place.  The last round's rotations reach the eigenvectors
-// after the loop.  rflag[3]: zero on entry.  Before every sweep all pairs are
-// tested with the rotation criterion; when none would rotate the iteration
-// ends (conv = 1) -- the same result as a sweep without rotations, at the
-// cost of one parallel pass.  At most max_sweeps sweeps.  NTH threads take
-// part (the whole workgroup).  Returns G (its diagonal is the eigenvalues).
-// Ends with a barrier.  G1 is not used (kept for the callers' layout).
+//     the previous round's rotations and move to their next slots (E0/E1
+//     transposed, E[c * LDE + r] = entry r of the eigenvector in slot c, the
+//     identity on the first n slots of E0 on entry);
+//  B. every 2x2 block (pair p rows, pair q columns, p <= q) of the current
+//     buffer becomes J_p^T B J_q and is written to its next slots in the
+//     other buffer.
+// The last round's rotations reach the eigenvectors after the loop.  Before
+// every sweep all pairs are tested with the rotation criterion; when none
+// would rotate the iteration ends (conv = 1).  At most max_sweeps sweeps.
+// rflag[3]: zero on entry.  Entries past ne of G0 and E0 zero; G1, E1 any.
+// NTH threads take part (the whole workgroup); ends with a barrier.  On
+// return Gout holds the final matrix (its diagonal the eigenvalues, in slot
+// order) and Eout the eigenvectors in the same slot order; for odd n, dslot
+// is the slot of the zero padding entry (its eigenvalue and eigenvector are
+// zero), else -1.  The n real eigenpairs are in the other ne slots.
 template <int LP, int NTH>
-__device__ const double *jacobi_eig(double *G, double *G1, double *Et, double2 *cs, int *rflag,
-                                    int n, double trace, int max_sweeps, int &conv) {
-    constexpr int LD = LP + 1, LDE = LP + 2, NPM = LP / 2;
+__device__ void jacobi_eig(double *G0, double *G1, double *E0, double *E1, double2 *cs, int *rflag, int n,
+                           double trace, int max_sweeps, int &conv, const double *&Gout, const double *&Eout,
+                           int &dslot) {
+    constexpr int LD = jacobi_ld<LP>(), LDE = jacobi_ld<LP>(), NPM = LP / 2;
     constexpr int IPT = (NPM * (NPM + 1) / 2 + (LP / 4) * NPM + NTH - 1) / NTH;  // items per thread
-    (void)G1;
     const int tid = threadIdx.x, lane = tid & 63;
-    const int ne = n + (n & 1), np = ne / 2, n1 = ne - 1;
+    const int ne = n + (n & 1), h = ne / 2, n1 = ne - 1;
+    auto up = [&](int i, int j) -> int { return i <= j ? i * LD + j : j * LD + i; };
     // this thread's items, fixed for all rounds: G block (pp <= qq) or E block
-    // (rows 4*i1 .. 4*i1+3, pair i2)
-    const int ng = np * (np + 1) / 2, nq = (ne + 3) / 4, nitems = ng + nq * np;
-    int ik[IPT], i1[IPT], i2[IPT];
+    // (rows 4*i1 .. 4*i1+3, pair i2), with their source and destination offsets
+    const int ng = h * (h + 1) / 2, nq = (ne + 3) / 4, nitems = ng + nq * h;
+    int ik[IPT], i1[IPT], i2[IPT], src[IPT], d0[IPT], d1[IPT], d2[IPT], d3[IPT];
 #pragma unroll
     for (int u = 0; u < IPT; ++u) {
         const int it = tid + u * NTH;
         ik[u] = it < ng ? 0 : it < nitems ? 1 : 2;
+        i1[u] = i2[u] = src[u] = d0[u] = d1[u] = d2[u] = d3[u] = 0;
         if (ik[u] == 0) {
             int pp = 0, rem = it;
-            while (rem >= np - pp) {
-                rem -= np - pp;
+            while (rem >= h - pp) {
+                rem -= h - pp;
                 ++pp;
             }
+            const int qq = pp + rem;
             i1[u] = pp;
-            i2[u] = pp + rem;
+            i2[u] = qq;
+            src[u] = 2 * pp * LD + 2 * qq;
+            const int a = rr_next(2 * pp, h), b = rr_next(2 * pp + 1, h);
+            const int c = rr_next(2 * qq, h), d = rr_next(2 * qq + 1, h);
+            d0[u] = up(a, c);
+            d1[u] = up(a, d);
+            d2[u] = up(b, c);
+            d3[u] = up(b, d);
         } else if (ik[u] == 1) {
-            i1[u] = (it - ng) / np;
-            i2[u] = (it - ng) % np;
-        } else {
-            i1[u] = i2[u] = 0;
+            const int k = (it - ng) % h, r0 = 4 * ((it - ng) / h);
+            i1[u] = r0;
+            i2[u] = k;
+            src[u] = 2 * k * LDE + r0;
+            d0[u] = rr_next(2 * k, h) * LDE + r0;
+            d1[u] = rr_next(2 * k + 1, h) * LDE + r0;
         }
     }
-    auto up = [&](int i, int j) -> int { return i <= j ? i * LD + j : j * LD + i; };
-    // eigenvector block item: the rotations of round r (record set par)
-    auto e_item = [&](int u, int r, int par) {
-        int c2, d;
-        rr_pair(r, i2[u], n1, c2, d);
-        const int r0 = 4 * i1[u];
-        double2 *pc = reinterpret_cast<double2 *>(Et + c2 * LDE + r0);
-        double2 *pd = reinterpret_cast<double2 *>(Et + d * LDE + r0);
+    double *Gc = G0, *Gn = G1, *Ec = E0, *En = E1;
+    // eigenvector block item: the rotations of record set par
+    auto e_item = [&](int u, int par) {
+        const double2 *pc = reinterpret_cast<const double2 *>(Ec + src[u]);
+        const double2 *pd = reinterpret_cast<const double2 *>(Ec + src[u] + LDE);
         const double2 rt = cs[par * NPM + i2[u]];
         const double2 x0 = pc[0], x1 = pc[1], y0 = pd[0], y1 = pd[1];
-        pc[0] = double2{rt.x * x0.x - rt.y * y0.x, rt.x * x0.y - rt.y * y0.y};
-        pc[1] = double2{rt.x * x1.x - rt.y * y1.x, rt.x * x1.y - rt.y * y1.y};
-        pd[0] = double2{rt.y * x0.x + rt.x * y0.x, rt.y * x0.y + rt.x * y0.y};
-        pd[1] = double2{rt.y * x1.x + rt.x * y1.x, rt.y * x1.y + rt.x * y1.y};
+        double2 *qc = reinterpret_cast<double2 *>(En + d0[u]);
+        double2 *qd = reinterpret_cast<double2 *>(En + d1[u]);
+        qc[0] = double2{rt.x * x0.x - rt.y * y0.x, rt.x * x0.y - rt.y * y0.y};
+        qc[1] = double2{rt.x * x1.x - rt.y * y1.x, rt.x * x1.y - rt.y * y1.y};
+        qd[0] = double2{rt.y * x0.x + rt.x * y0.x, rt.y * x0.y + rt.x * y0.y};
+        qd[1] = double2{rt.y * x1.x + rt.x * y1.x, rt.y * x1.y + rt.x * y1.y};
     };
 
-    int sweep = 0, rr = 0, rprev = 0;  // rr counts rounds over all sweeps
+    int rr = 0;  // rounds over all sweeps
     conv = 0;
-    for (sweep = 1;; ++sweep) {
-        // convergence test over the upper triangle; flag fl, cleared two
-        // tests ahead (every thread has read it by the next test's barrier)
+    for (int sweep = 1;; ++sweep) {
+        // convergence test over the upper triangle of the slots; flag fl,
+        // cleared two tests ahead (every thread has read it by then)
         const int fl = sweep % 3;
         {
             bool need = false;
-            for (int e = tid; e < n * n; e += NTH) {
-                const int i = e / n, j = e - i * n;
-                if (i < j) need |= jneeds(G[i * LD + i], G[j * LD + j], G[i * LD + j], trace);
+            for (int e = tid; e < ne * ne; e += NTH) {
+                const int i = e / ne, j = e - i * ne;
+                if (i < j) need |= jneeds(Gc[i * LD + i], Gc[j * LD + j], Gc[i * LD + j], trace);
             }
             if (__any(need) && lane == 0) rflag[fl] = 1;
             __syncthreads();
@@ -161,59 +179,71 @@ __device__ const double *jacobi_eig(double *G, double *G1, double *Et, double2 *
         for (int r = 0; r < n1; ++r, ++rr) {
             const int par = rr & 1;
             // ---- A: rotations; eigenvectors of the previous round
-            if (tid < np) {
-                int a, b;
-                rr_pair(r, tid, n1, a, b);
+            if (tid < h) {
+                const double2 g = *reinterpret_cast<const double2 *>(Gc + 2 * tid * (LD + 1));
+                const double aqq = Gc[(2 * tid + 1) * (LD + 1)];
                 double c, s;
-                jrot(G[a * LD + a], G[b * LD + b], G[a * LD + b], b < n, trace, c, s);
+                jrot(g.x, aqq, g.y, true, trace, c, s);
                 cs[par * NPM + tid] = double2{c, s};
             }
             if (rr > 0) {
 #pragma unroll
                 for (int u = 0; u < IPT; ++u)
-                    if (ik[u] == 1) e_item(u, rprev, par ^ 1);
+                    if (ik[u] == 1) e_item(u, par ^ 1);
             }
             __syncthreads();
-            // ---- B: blocks
+            if (rr > 0) {
+                double *t = Ec;
+                Ec = En;
+                En = t;
+            }
+            // ---- B: blocks to their next slots
 #pragma unroll
             for (int u = 0; u < IPT; ++u) {
-                if (ik[u] == 0) {
-                    int a, b, c2, d;
-                    rr_pair(r, i1[u], n1, a, b);
-                    rr_pair(r, i2[u], n1, c2, d);
-                    const double2 rp = cs[par * NPM + i1[u]], rq = cs[par * NPM + i2[u]];
-                    const int p00 = up(a, c2), p01 = up(a, d), p10 = up(b, c2), p11 = up(b, d);
-                    const double m00 = G[p00], m01 = G[p01], m10 = G[p10], m11 = G[p11];
-                    const double cp = rp.x, sp = rp.y, cq = rq.x, sq = rq.y;
-                    // rows: (a, b) <- (cp a - sp b, sp a + cp b); then the columns
-                    const double t00 = cp * m00 - sp * m10, t01 = cp * m01 - sp * m11;
-                    const double t10 = sp * m00 + cp * m10, t11 = sp * m01 + cp * m11;
-                    const double n00 = cq * t00 - sq * t01, n01 = sq * t00 + cq * t01;
-                    const double n11 = sq * t10 + cq * t11;
-                    if (i2[u] != i1[u]) {
-                        G[p00] = n00;
-                        G[p01] = n01;
-                        G[p10] = cq * t10 - sq * t11;
-                        G[p11] = n11;
-                    } else {  // diagonal block: entries (a,a), (a,b), (b,b)
-                        G[p00] = n00;
-                        G[p01] = n01;
-                        G[p11] = n11;
-                    }
-                }
+                if (ik[u] != 0) continue;
+                const double2 r0 = *reinterpret_cast<const double2 *>(Gc + src[u]);
+                const double2 r1 = *reinterpret_cast<const double2 *>(Gc + src[u] + LD);
+                const double2 rp = cs[par * NPM + i1[u]], rq = cs[par * NPM + i2[u]];
+                const bool dg = i1[u] == i2[u];
+                // diagonal block: (b, a) is not stored; it equals (a, b)
+                const double m00 = r0.x, m01 = r0.y, m10 = dg ? r0.y : r1.x, m11 = r1.y;
+                const double cp = rp.x, sp = rp.y, cq = rq.x, sq = rq.y;
+                // rows: (a, b) <- (cp a - sp b, sp a + cp b); then the columns
+                const double t00 = cp * m00 - sp * m10, t01 = cp * m01 - sp * m11;
+                const double t10 = sp * m00 + cp * m10, t11 = sp * m01 + cp * m11;
+                Gn[d0[u]] = cq * t00 - sq * t01;
+                Gn[d1[u]] = sq * t00 + cq * t01;
+                if (!dg) Gn[d2[u]] = cq * t10 - sq * t11;
+                Gn[d3[u]] = sq * t10 + cq * t11;
             }
             __syncthreads();
-            rprev = r;
+            double *t = Gc;
+            Gc = Gn;
+            Gn = t;
         }
     }
     // the eigenvectors take the last round's rotations
     if (rr > 0) {
 #pragma unroll
         for (int u = 0; u < IPT; ++u)
-            if (ik[u] == 1) e_item(u, rprev, (rr - 1) & 1);
+            if (ik[u] == 1) e_item(u, (rr - 1) & 1);
+        __syncthreads();
+        Ec = En;
     }
     __syncthreads();
-    return G;
+    Gout = Gc;
+    Eout = Ec;
+    // the padding entry starts in slot ne-1 and moves once per round; the
+    // permutation has period ne-1 on the moving slots
+    dslot = -1;
+    if (n & 1) {
+        int sl = ne - 1;
+        for (int k = 0, nr = n1 > 0 ? rr % n1 : 0; k < nr; ++k) sl = rr_next(sl, h);
+        dslot = sl;
+    }
 }
+
+// Slot of the j-th real eigenpair (j < n) given the padding slot of jacobi_eig.
+__device__ __forceinline__ int jacobi_slot(int j, int dslot) { return dslot >= 0 && j >= dslot ? j + 1 : j; }
 
 }  // namespace tsvdm

@@ -38,15 +38,22 @@ namespace {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int GT = 256;  // threads per workgroup
 enum { PROD_BF16 = 0, PROD_SPLIT = 1 };
 
-__device__ __forceinline__ void split_bf16(float x, uint16_t &hi, uint16_t &lo) {
-    hi = f2bf(x);
-    lo = f2bf(x - bf2f(hi));
+// (x0, x1) -> packed BF16 pairs hi = RNE(x), lo = RNE(x - hi) (x - hi is
+// exact in FP32), element 0 in the low half; the hardware packed conversion
+__device__ __forceinline__ void split2(float x0, float x1, uint32_t &hi, uint32_t &lo) {
+    const f32x2 v = {x0, x1};
+    const bf16x2 h = __builtin_convertvector(v, bf16x2);
+    const bf16x2 l = __builtin_convertvector(v - __builtin_convertvector(h, f32x2), bf16x2);
+    hi = __builtin_bit_cast(uint32_t, h);
+    lo = __builtin_bit_cast(uint32_t, l);
 }
 
 __device__ __forceinline__ f32x4 mfma(const u16x8 &a, const u16x8 &b, f32x4 c) {
@@ -201,8 +208,14 @@ __device__ void block_gram_f64(const f32x4 (&acc)[LP / 16], double *__restrict__
 // The X slab and the W chunk are converted to BF16 (hi, and lo for the
 // split product) and staged in LDS with K contiguous, so each lane's MFMA
 // operand is one 16-byte LDS read; the next chunk is loaded into registers
-// while the current one is multiplied.
-template <int LP, int PROD, bool GRAM>
+// while the current one is multiplied.  A lane loads a 4 x 4 block of the
+// chunk (four consecutive rows of four adjacent columns).  VEC: m is a
+// multiple of 4, X is 16-byte aligned and a face spans less than 4 GiB
+// (checked by the caller), so each column of the block is one 16-byte load
+// at a 32-bit offset from the face.  Loads go to clamped addresses; bit masks
+// mark the valid values and are applied when the chunk is converted, so no
+// instruction waits on a load that is still in flight.
+template <int LP, int PROD, bool GRAM, bool VEC>
 __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, int p, int nf,
                                            const float *__restrict__ W, int64_t w_stride, int ldw,
                                            int nw, float *__restrict__ Y,
@@ -225,49 +238,72 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
     const float *Xf = X + (int64_t)(fmap ? fmap[f] : f) * m * p;
     const float *Wf = W + (int64_t)f * w_stride;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int lr = tid & 63, kg = tid >> 6;  // X load mapping: row, group of 16 columns
+    const int rq = tid & 15, cg = tid >> 4;  // X load mapping: rows 4rq.., columns 4cg..
     f32x4 acc[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[j] = f32x4{0, 0, 0, 0};
     double fro = 0.0;
-    const bool rok = a0 + lr < m;
-    float xr[16], wr[WPT];
+    const int arow = a0 + 4 * rq;
+    const char *Xb = reinterpret_cast<const char *>(Xf), *Wb = reinterpret_cast<const char *>(Wf);
+    float xr[16], wr[WPT];  // xr[4 * it + v] = X[arow + v][b0 + 4cg + it]
+    uint32_t xm = 0, wm = 0;
     auto load = [&](int b0) {
+        xm = 0;
+        wm = 0;
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            const int b = b0 + 16 * kg + v;
-            xr[v] = (rok && b < p) ? Xf[(a0 + lr) + (int64_t)m * b] : 0.0f;
+        for (int it = 0; it < 4; ++it) {
+            const int b = b0 + 4 * cg + it;
+            if constexpr (VEC) {  // arow < m implies arow + 3 < m
+                const bool ok = b < p && arow < m;
+                const uint32_t off = ok ? 4u * ((uint32_t)arow + (uint32_t)m * (uint32_t)b) : 0u;
+                const f32x4 x = *reinterpret_cast<const f32x4 *>(Xb + off);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) xr[4 * it + v] = x[v];
+                xm |= ok ? 0xFu << (4 * it) : 0u;
+            } else {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const bool ok = b < p && arow + v < m;
+                    xr[4 * it + v] = Xf[ok ? arow + v + (int64_t)m * b : 0];
+                    xm |= (uint32_t)ok << (4 * it + v);
+                }
+            }
         }
 #pragma unroll
         for (int q = 0; q < WPT; ++q) {
             const int e = tid + q * GT, k = e % KC, c = e / KC, b = b0 + k;
-            wr[q] = (c < nw && b < p) ? Wf[b + (int64_t)ldw * c] : 0.0f;
+            const bool ok = c < nw && b < p;
+            wr[q] = *reinterpret_cast<const float *>(Wb + (ok ? 4u * ((uint32_t)b + (uint32_t)ldw * (uint32_t)c) : 0u));
+            wm |= (uint32_t)ok << q;
         }
     };
     load(0);
     for (int b0 = 0; b0 < p; b0 += KC) {
 #pragma unroll
-        for (int hv = 0; hv < 2; ++hv) {
-            u16x8 h, l;
+        for (int v = 0; v < 4; ++v) {  // row 4rq + v, columns 4cg .. 4cg+3
+            float x[4];
 #pragma unroll
-            for (int v = 0; v < 8; ++v) {
-                const float x = xr[8 * hv + v];
-                fro += (double)x * (double)x;
-                uint16_t hh, ll;
-                split_bf16(x, hh, ll);
-                h[v] = hh;
-                l[v] = ll;
+            for (int it = 0; it < 4; ++it) {
+                x[it] = (xm >> (4 * it + v)) & 1u ? xr[4 * it + v] : 0.0f;
+                fro += (double)x[it] * (double)x[it];
             }
-            *reinterpret_cast<u16x8 *>(&xh[lr * LDK + 16 * kg + 8 * hv]) = h;
-            if (SPL) *reinterpret_cast<u16x8 *>(&xl[lr * LDK + 16 * kg + 8 * hv]) = l;
+            uint2 h, l;
+            split2(x[0], x[1], h.x, l.x);
+            split2(x[2], x[3], h.y, l.y);
+            *reinterpret_cast<uint2 *>(&xh[(4 * rq + v) * LDK + 4 * cg]) = h;
+            if (SPL) *reinterpret_cast<uint2 *>(&xl[(4 * rq + v) * LDK + 4 * cg]) = l;
         }
 #pragma unroll
-        for (int q = 0; q < WPT; ++q) {
-            const int e = tid + q * GT, k = e % KC, c = e / KC;
-            uint16_t hh, ll;
-            split_bf16(wr[q], hh, ll);
-            wh[c * LDK + k] = hh;
-            if (SPL) wl[c * LDK + k] = ll;
+        for (int q = 0; q < WPT; q += 2) {
+            const int e0 = tid + q * GT, e1 = e0 + GT;
+            uint32_t hh, ll;
+            split2((wm >> q) & 1u ? wr[q] : 0.0f, (wm >> (q + 1)) & 1u ? wr[q + 1] : 0.0f, hh, ll);
+            wh[(e0 / KC) * LDK + e0 % KC] = (uint16_t)hh;
+            wh[(e1 / KC) * LDK + e1 % KC] = (uint16_t)(hh >> 16);
+            if (SPL) {
+                wl[(e0 / KC) * LDK + e0 % KC] = (uint16_t)ll;
+                wl[(e1 / KC) * LDK + e1 % KC] = (uint16_t)(ll >> 16);
+            }
         }
         __syncthreads();
         if (b0 + KC < p) load(b0 + KC);  // next chunk in flight during the MFMAs
@@ -321,10 +357,11 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
 // in FP64.  It reads the X block a second time, last chunk first, so the
 // chunks it read most recently come from cache.  Together with the discarded
 // eigenvalues of B B^T this is the error of the truncated result.
-// VEC: m is a multiple of 4 and X 16-byte aligned (checked by the caller), so
-// the four consecutive rows a lane reads are one 16-byte load.  All loads
-// are branch free (clamped address, then a select), so they are in flight
-// together.
+// VEC: m is a multiple of 4, X is 16-byte aligned and a face spans less than
+// 4 GiB (checked by the caller), so the four consecutive rows a lane reads
+// are one 16-byte load at a 32-bit offset from the face.  Loads go to
+// clamped addresses; bit masks mark the valid values and are applied when
+// the values are used, so no instruction waits on a load still in flight.
 template <int LP, int PROD, bool GRAM, bool RES, bool VEC>
 __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, int p, int nf,
                                             const float *__restrict__ W, int64_t w_stride, int ldw,
@@ -356,23 +393,29 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
     f32x4 acc[NB];
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[j] = f32x4{0, 0, 0, 0};
+    const char *Xb = reinterpret_cast<const char *>(Xf), *Wb = reinterpret_cast<const char *>(Wf);
     float xr[16], wr[WPT];
+    uint32_t xm = 0, wm = 0;
     auto load = [&](int a0) {
         const int a = a0 + 4 * q4;
+        xm = 0;
+        wm = 0;
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
             const int b = b0 + cj0 + 16 * it;
             if constexpr (VEC) {  // a < m implies a + 3 < m
                 const bool ok = b < p && a < m;
-                const f32x4 x = *reinterpret_cast<const f32x4 *>(Xf + (ok ? a + (int64_t)m * b : 0));
+                const uint32_t off = ok ? 4u * ((uint32_t)a + (uint32_t)m * (uint32_t)b) : 0u;
+                const f32x4 x = *reinterpret_cast<const f32x4 *>(Xb + off);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) xr[4 * it + v] = ok ? x[v] : 0.0f;
+                for (int v = 0; v < 4; ++v) xr[4 * it + v] = x[v];
+                xm |= ok ? 0xFu << (4 * it) : 0u;
             } else {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const bool ok = b < p && a + v < m;
-                    const float x = Xf[ok ? a + v + (int64_t)m * b : 0];
-                    xr[4 * it + v] = ok ? x : 0.0f;
+                    xr[4 * it + v] = Xf[ok ? a + v + (int64_t)m * b : 0];
+                    xm |= (uint32_t)ok << (4 * it + v);
                 }
             }
         }
@@ -380,8 +423,8 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
         for (int q = 0; q < WPT; ++q) {
             const int e = tid + q * GT, k = e % KC, c = e / KC, a = a0 + k;
             const bool ok = c < nw && a < m;
-            const float x = Wf[ok ? a + (int64_t)ldw * c : 0];
-            wr[q] = ok ? x : 0.0f;
+            wr[q] = *reinterpret_cast<const float *>(Wb + (ok ? 4u * ((uint32_t)a + (uint32_t)ldw * (uint32_t)c) : 0u));
+            wm |= (uint32_t)ok << q;
         }
     };
     load(0);
@@ -389,24 +432,26 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
             const int cj = cj0 + 16 * it;
-            uint16_t hh[4], ll[4];
+            float x[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) split_bf16(xr[4 * it + v], hh[v], ll[v]);
+            for (int v = 0; v < 4; ++v) x[v] = (xm >> (4 * it + v)) & 1u ? xr[4 * it + v] : 0.0f;
             uint2 ph, pl;
-            ph.x = hh[0] | ((uint32_t)hh[1] << 16);
-            ph.y = hh[2] | ((uint32_t)hh[3] << 16);
-            pl.x = ll[0] | ((uint32_t)ll[1] << 16);
-            pl.y = ll[2] | ((uint32_t)ll[3] << 16);
+            split2(x[0], x[1], ph.x, pl.x);
+            split2(x[2], x[3], ph.y, pl.y);
             *reinterpret_cast<uint2 *>(&xh[cj * LDK + 4 * q4]) = ph;
             if (SPL) *reinterpret_cast<uint2 *>(&xl[cj * LDK + 4 * q4]) = pl;
         }
 #pragma unroll
-        for (int q = 0; q < WPT; ++q) {
-            const int e = tid + q * GT, k = e % KC, c = e / KC;
-            uint16_t hh, ll;
-            split_bf16(wr[q], hh, ll);
-            wh[c * LDK + k] = hh;
-            if (SPL) wl[c * LDK + k] = ll;
+        for (int q = 0; q < WPT; q += 2) {
+            const int e0 = tid + q * GT, e1 = e0 + GT;
+            uint32_t hh, ll;
+            split2((wm >> q) & 1u ? wr[q] : 0.0f, (wm >> (q + 1)) & 1u ? wr[q + 1] : 0.0f, hh, ll);
+            wh[(e0 / KC) * LDK + e0 % KC] = (uint16_t)hh;
+            wh[(e1 / KC) * LDK + e1 % KC] = (uint16_t)(hh >> 16);
+            if (SPL) {
+                wl[(e0 / KC) * LDK + e0 % KC] = (uint16_t)ll;
+                wl[(e1 / KC) * LDK + e1 % KC] = (uint16_t)(ll >> 16);
+            }
         }
         __syncthreads();
         if (a0 + KC < m) load(a0 + KC);  // next chunk in flight during the MFMAs
@@ -449,22 +494,24 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
         float *qs = reinterpret_cast<float *>(smem);
         // X values of the MFMA output positions: rows a = a0 + 16*wave +
         // 4*(lane/16) + v (four consecutive rows), columns b = b0 + 16t + lane%16
-        auto rload = [&](int a0, f32x4(&xv)[4]) {
+        auto rload = [&](int a0, f32x4(&xv)[4], uint32_t &msk) {
             const int a = a0 + 16 * wave + 4 * (lane >> 4);
+            msk = 0;
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int b = b0 + 16 * t + (lane & 15);
                 const bool bok = b < p;
                 if constexpr (VEC) {
                     const bool ok = bok && a < m;
-                    const f32x4 x = *reinterpret_cast<const f32x4 *>(Xf + (ok ? a + (int64_t)m * b : 0));
-                    xv[t] = ok ? x : f32x4{0, 0, 0, 0};
+                    const uint32_t off = ok ? 4u * ((uint32_t)a + (uint32_t)m * (uint32_t)b) : 0u;
+                    xv[t] = *reinterpret_cast<const f32x4 *>(Xb + off);
+                    msk |= ok ? 0xFu << (4 * t) : 0u;
                 } else {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
                         const bool ok = bok && a + v < m;
-                        const float x = Xf[ok ? a + v + (int64_t)m * b : 0];
-                        xv[t][v] = ok ? x : 0.0f;
+                        xv[t][v] = Xf[ok ? a + v + (int64_t)m * b : 0];
+                        msk |= (uint32_t)ok << (4 * t + v);
                     }
                 }
             }
@@ -472,12 +519,13 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
         const int nch = (m + KC - 1) / KC;
         double racc = 0.0;
         f32x4 xv[4], xn[4];
-        rload((nch - 1) * KC, xv);
+        uint32_t vm, nm = 0;
+        rload((nch - 1) * KC, xv, vm);
         for (int ci = nch - 1; ci >= 0; --ci) {
             const int a0 = ci * KC;
             stage_panel<LP, 64>(Wf, m, a0, qs);
             __syncthreads();
-            if (ci > 0) rload(a0 - KC, xn);  // next chunk in flight during the MFMAs
+            if (ci > 0) rload(a0 - KC, xn, nm);  // next chunk in flight during the MFMAs
             f32x4 pr[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) pr[t] = f32x4{0, 0, 0, 0};
@@ -495,12 +543,14 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
             for (int t = 0; t < 4; ++t)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const double d = (double)xv[t][v] - (double)pr[t][v];
+                    const float x = (vm >> (4 * t + v)) & 1u ? xv[t][v] : 0.0f;
+                    const double d = (double)x - (double)pr[t][v];
                     racc += d * d;
                 }
             __syncthreads();
 #pragma unroll
             for (int t = 0; t < 4; ++t) xv[t] = xn[t];
+            vm = nm;
         }
         racc = wave_sum(racc);
         if (lane == 0) red[wave] = racc;
@@ -721,22 +771,22 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
                                              double *__restrict__ fro2_out, double *__restrict__ cert,
                                              int32_t *__restrict__ jinfo,
     const int32_t *__restrict__ fmap) {
-    constexpr int LD = LP + 1, LDE = LP + 2, NPM = LP / 2;
-    __shared__ double Gb[2][LP * LD];
-    __shared__ __align__(16) double Et[LP * LDE];  // eigenvectors transposed: Et[c * LDE + r] = E[r][c]
-    __shared__ __align__(16) double2 cs[2][NPM];   // rotations of the previous round, for E
+    constexpr int LD = jacobi_ld<LP>(), LDE = jacobi_ld<LP>(), NPM = LP / 2;
+    __shared__ __align__(16) double Gb[2][LP * LD];
+    __shared__ __align__(16) double Eb[2][LP * LDE];  // eigenvectors transposed: E[c * LDE + r]
+    __shared__ __align__(16) double2 cs[2][NPM];      // rotations, by round parity
     __shared__ double lam[LP];
     __shared__ int perm[LP];
     __shared__ double trace_s;
     __shared__ int rflag[3];
     const int f = blockIdx.x, tid = threadIdx.x;
     for (int e = tid; e < LP * LD; e += QT) Gb[0][e] = 0.0;
-    for (int e = tid; e < LP * LDE; e += QT) Et[e] = 0.0;
+    for (int e = tid; e < LP * LDE; e += QT) Eb[0][e] = Eb[1][e] = 0.0;
     __syncthreads();
     // Gram into the leading block (the padded rows and columns of the
     // partials are zero), identity eigenvectors
     load_gram_partials<LP, QT>(gpart, f, nparts, Gb[0], LD);
-    if (tid < ell) Et[tid * LDE + tid] = 1.0;
+    if (tid < ell) Eb[0][tid * LDE + tid] = 1.0;
     if (tid < 3) rflag[tid] = 0;
     __syncthreads();
     if (tid < 64) {
@@ -749,8 +799,13 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
     const double trace = trace_s;
 
     int conv = 0;
-    const double *G = jacobi_eig<LP, QT>(Gb[0], Gb[1], Et, &cs[0][0], rflag, ell, trace, max_sweeps, conv);
-    if (tid < ell) lam[tid] = fmax(G[tid * LD + tid], 0.0);
+    const double *G, *E;
+    int dslot;
+    jacobi_eig<LP, QT>(Gb[0], Gb[1], Eb[0], Eb[1], &cs[0][0], rflag, ell, trace, max_sweeps, conv, G, E, dslot);
+    if (tid < ell) {
+        const int sl = jacobi_slot(tid, dslot);
+        lam[tid] = fmax(G[sl * LD + sl], 0.0);
+    }
     __syncthreads();
     if (tid < ell) {
         int pos = 0;
@@ -789,7 +844,7 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
         perm_out[(int64_t)f * LP + r] = j;
     }
     for (int e = tid; e < LP * LP; e += QT)
-        UB[(int64_t)f * LP * LP + e] = Et[(e / LP) * LDE + e % LP];  // column major, col = e/LP
+        UB[(int64_t)f * LP * LP + e] = e / LP < ell ? E[jacobi_slot(e / LP, dslot) * LDE + e % LP] : 0.0;  // col e/LP
 }
 
 // ---------------------------------------------------------------- factors
@@ -1004,6 +1059,13 @@ __global__ __launch_bounds__(1024) void k_fallback_list(const double *__restrict
 // Faces [f0, f0 + nfg) through the whole path on stream s.  Every kernel
 // below works face by face, so the pointers are offset to the first face of
 // the range and the kernels see a tensor of nfg faces.
+
+// The GEMM passes' 16-byte loads of four consecutive rows at 32-bit offsets
+// from the face: m a multiple of 4 (every face start is then as aligned as
+// X), X 16-byte aligned, a face below 4 GiB.
+bool vec_loads_ok(const float *X, int m, int p) {
+    return m % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 && (int64_t)m * p < (int64_t)1 << 30;
+}
 template <int LP>
 tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
                        const MixedWs &w0, int f0, int nfg, hipStream_t s,
@@ -1040,15 +1102,21 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     const bool power = o->power_iters > 0;
     // the residual is needed for the certificate and for the energy rule
     const bool resid = o->rank_mode == TSVDM_RANK_ENERGY || (o->certify && cert);
-    // 16-byte loads of four consecutive rows of X (every face start is then
-    // 16-byte aligned too)
-    const bool v4 = m % 4 == 0 && reinterpret_cast<uintptr_t>(Xd) % 16 == 0;
+    const bool v4 = vec_loads_ok(Xd, m, p);
     TSVDM_LAUNCH("zero_info", k_zero_i32, dim3((nf + 255) / 256), dim3(256), 0, s, w.qr_info, nf);
     const double *gm_c = w.gram_m, *gp_c = w.gram_p;
+#define TSVDM_SKETCH()                                                                                      \
+    do {                                                                                                    \
+        if (v4)                                                                                             \
+            TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true, true>), gm, dim3(GT), 0, s, Xd, m, p, nf, \
+                         o->omega, (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m, fmap);                     \
+        else                                                                                                \
+            TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true, false>), gm, dim3(GT), 0, s, Xd, m, p,    \
+                         nf, o->omega, (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m, fmap);                 \
+    } while (0)
     if (power) {
         // pass 1: sketch Y = X Omega (BF16), ||X||^2, Gram partials of Y
-        TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true>), gm, dim3(GT), 0, s, Xd, m, p, nf, o->omega,
-                     (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m, fmap);
+        TSVDM_SKETCH();
         // basis of the sketch: one shifted Cholesky-QR step (its span is what
         // the power step needs)
         TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell,
@@ -1063,12 +1131,16 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
         TSVDM_LAUNCH("cholqr_power_z", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Z, p, ell,
                      w.Qp, 1, gp_c, pparts, w.qr_info);
         // pass 3: Y' = X Qz, FP32-accurate (split BF16), and its Gram partials
-        TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true>), gm, dim3(GT), 0, s, Xd, m, p, nf,
-                     (const float *)w.Qp, (int64_t)p * LP, p, LP, w.Y, (double *)nullptr, w.gram_m, fmap);
+        if (v4)
+            TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true, true>), gm, dim3(GT), 0, s, Xd, m, p, nf,
+                         (const float *)w.Qp, (int64_t)p * LP, p, ell, w.Y, (double *)nullptr, w.gram_m, fmap);
+        else
+            TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true, false>), gm, dim3(GT), 0, s, Xd, m, p, nf,
+                         (const float *)w.Qp, (int64_t)p * LP, p, ell, w.Y, (double *)nullptr, w.gram_m, fmap);
     } else {
-        TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true>), gm, dim3(GT), 0, s, Xd, m, p, nf, o->omega,
-                     (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m, fmap);
+        TSVDM_SKETCH();
     }
+#undef TSVDM_SKETCH
     // final basis: FP64 shifted Cholesky-QR2 (first Gram from the partials)
     TSVDM_LAUNCH("cholqr_final", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell, w.Qm,
                  2, gm_c, mparts, w.qr_info);
@@ -1144,8 +1216,13 @@ tsvdm_status launch_rank_features(const tsvdm_tensor *X, const float *omega, uin
     carve(reinterpret_cast<char *>(ws), m, p, nf, 32, &w);
     const int mparts = (m + 63) / 64;
     const float *Xd = reinterpret_cast<const float *>(X->data);
-    TSVDM_LAUNCH("features_sketch", (k_xw<32, PROD_BF16, true>), dim3((unsigned)(mparts * nf)), dim3(GT), 0, s,
-                 Xd, m, p, nf, omega, (int64_t)0, p, 32, w.Y, w.fro_part, w.gram_m, (const int32_t *)nullptr);
+    const dim3 gm((unsigned)(mparts * nf));
+    if (vec_loads_ok(Xd, m, p))
+        TSVDM_LAUNCH("features_sketch", (k_xw<32, PROD_BF16, true, true>), gm, dim3(GT), 0, s, Xd, m, p, nf,
+                     omega, (int64_t)0, p, 32, w.Y, w.fro_part, w.gram_m, (const int32_t *)nullptr);
+    else
+        TSVDM_LAUNCH("features_sketch", (k_xw<32, PROD_BF16, true, false>), gm, dim3(GT), 0, s, Xd, m, p, nf,
+                     omega, (int64_t)0, p, 32, w.Y, w.fro_part, w.gram_m, (const int32_t *)nullptr);
     TSVDM_LAUNCH("features_eig", (k_core<32>), dim3(nf), dim3(QT), 0, s, (const double *)w.gram_m, mparts, 32,
                  (const double *)w.fro_part, mparts, (const double *)nullptr, 0, (int)TSVDM_RANK_FIXED, 32, 0.0,
                  30, w.UB, w.sig, w.perm, w.kf, w.fro2, (double *)nullptr, w.jinfo, (const int32_t *)nullptr);
