@@ -848,7 +848,13 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
 }
 
 // ---------------------------------------------------------------- factors
-// Uhat[:, r] = Q U_B[:, perm[r]],  Vhat[:, r] = B^T U_B[:, perm[r]] / s_r  (r < k_f)
+// Uhat[:, r] = Q U_B[:, perm[r]],  Vhat[:, r] = B^T U_B[:, perm[r]] / s_r  (r < k_f;
+// zero for k_f <= r < kmax).  Grid (ceil(m/64) + ceil(p/64), nf): the first
+// ceil(m/64) blocks of a face make 64 rows of Uhat each, the others rows of
+// Vhat.  A wavefront makes 16 rows by FP32 MFMA 16x16x4 on the transposed
+// product (U_B^T Q^T), so that a lane's four results are consecutive rows; the
+// inputs Q and B^T are FP32 and U_B is rounded to FP32, which adds an error of
+// the order of the FP32 rounding of the inputs themselves.
 template <int LP>
 __global__ __launch_bounds__(GT) void k_factors(const float *__restrict__ Q, const float *__restrict__ Bt,
                                                 int m, int p, int ell, int64_t kmax,
@@ -863,51 +869,60 @@ __global__ __launch_bounds__(GT) void k_factors(const float *__restrict__ Q, con
                                                 float *__restrict__ Vo, int32_t *__restrict__ ranks,
                                                 double *__restrict__ fro, int32_t *__restrict__ info,
     const int32_t *__restrict__ fmap) {
-    __shared__ double ub[LP * LP];  // ub[c * LP + r] = U_B[c, perm[r]] (and / s_r for V)
-    __shared__ double ubv[LP * LP];
-    const int f = blockIdx.y, tid = threadIdx.x, fd = fmap ? fmap[f] : f;
-    const int kf = kf_in[f];
+    constexpr int LU = LP + 1, NT = LP / 16;
+    __shared__ float ubs[LP * LU];  // ubs[r * LU + c] = U_B[c, perm[r]] (/ s_r for V), zero for r >= k_f
+    const int f = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int fd = fmap ? fmap[f] : f;
+    const int kf = kf_in[f], nbu = (m + 63) / 64;
+    const bool isv = (int)blockIdx.x >= nbu;
+    const int blk = isv ? blockIdx.x - nbu : blockIdx.x, rows = isv ? p : m;
+    const float *S = isv ? Bt + (int64_t)f * p * LP : Q + (int64_t)f * m * LP;  // rows x LP, column major
+    float *O = isv ? Vo + (int64_t)fd * p * kmax : Uo + (int64_t)fd * m * kmax;
     for (int e = tid; e < LP * LP; e += GT) {
-        int c = e / LP, r = e % LP;
-        double u = 0.0, v = 0.0;
+        const int r = e / LP, c = e % LP;
+        float u = 0.0f;
         if (r < kf && c < ell) {
-            int j = perm[(int64_t)f * LP + r];
-            double s = sig[(int64_t)f * LP + r];
-            u = UB[(int64_t)f * LP * LP + c + (int64_t)LP * j];
-            v = s > 0.0 ? u / s : 0.0;
+            const double v = UB[(int64_t)f * LP * LP + c + (int64_t)LP * perm[(int64_t)f * LP + r]];
+            const double s = sig[(int64_t)f * LP + r];
+            u = (float)(isv ? (s > 0.0 ? v / s : 0.0) : v);
         }
-        ub[e] = u;
-        ubv[e] = v;
+        ubs[r * LU + c] = u;
     }
     __syncthreads();
-    const int row = blockIdx.x * GT + tid;
-    if (row < m) {
-        const float *Qf = Q + (int64_t)f * m * LP;
-        double qv[LP];
+    const int kc = kf < kmax ? kf : (int)kmax;       // columns with values
+    const int nt = (kc + 15) / 16;                   // their 16-column tiles
+    const int row0 = blk * 64 + 16 * wave, jr = row0 + (lane & 15), kl = lane >> 4;
+    const bool rok = jr < rows;
+    f32x4 acc[NT];
 #pragma unroll
-        for (int c = 0; c < LP; ++c) qv[c] = Qf[row + (int64_t)m * c];
-        for (int r = 0; r < kmax; ++r) {
-            double acc = 0.0;
-            if (r < kf) {
+    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0, 0, 0, 0};
 #pragma unroll
-                for (int c = 0; c < LP; ++c) acc += qv[c] * ub[c * LP + (r < LP ? r : 0)];
-            }
-            Uo[(int64_t)fd * m * kmax + row + (int64_t)m * r] = (float)acc;
+    for (int kk = 0; kk < LP / 4; ++kk) {
+        if (4 * kk >= ell) break;  // columns past ell of U_B^T are zero
+        const float x = S[rok ? jr + (int64_t)rows * (4 * kk + kl) : 0];
+        const float bq = rok ? x : 0.0f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (t >= nt) break;
+            const float a = ubs[(16 * t + (lane & 15)) * LU + 4 * kk + kl];
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bq, acc[t], 0, 0, 0);
         }
     }
-    if (row < p) {
-        const float *Bf = Bt + (int64_t)f * p * LP;
-        double bv[LP];
+    // result (r = 16t + 4*(lane/16) + v, row = row0 + lane%16)
 #pragma unroll
-        for (int c = 0; c < LP; ++c) bv[c] = Bf[row + (int64_t)p * c];
-        for (int r = 0; r < kmax; ++r) {
-            double acc = 0.0;
-            if (r < kf) {
+    for (int t = 0; t < NT; ++t) {
+        if (t >= nt) break;
 #pragma unroll
-                for (int c = 0; c < LP; ++c) acc += bv[c] * ubv[c * LP + (r < LP ? r : 0)];
-            }
-            Vo[(int64_t)fd * p * kmax + row + (int64_t)p * r] = (float)acc;
+        for (int v = 0; v < 4; ++v) {
+            const int r = 16 * t + 4 * kl + v;
+            if (rok && r < kmax) O[jr + (int64_t)rows * r] = acc[t][v];
         }
+    }
+    // zero columns past the computed tiles
+    const int64_t zc = kmax - 16 * nt;
+    for (int64_t e = tid; e < 64 * zc; e += GT) {
+        const int row = blk * 64 + (int)(e % 64);
+        if (row < rows) O[row + (int64_t)rows * (16 * nt + e / 64)] = 0.0f;
     }
     if (blockIdx.x == 0) {
         for (int r = tid; r < kmax; r += GT) So[(int64_t)fd * kmax + r] = r < kf ? sig[(int64_t)f * LP + r] : 0.0;
@@ -1161,8 +1176,7 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     TSVDM_LAUNCH("core_gram_eig", (k_core<LP>), dim3(nf), dim3(QT), 0, s, gp_c, pparts, ell,
                  (const double *)w.fro_part, mparts, (const double *)w.res_part, resid ? pparts : 0,
                  o->rank_mode, o->k, o->tau, msw, w.UB, w.sig, w.perm, w.kf, w.fro2, cert, w.jinfo, fmap);
-    const int rows = m > p ? m : p;
-    TSVDM_LAUNCH("factors", (k_factors<LP>), dim3((rows + GT - 1) / GT, nf), dim3(GT), 0, s,
+    TSVDM_LAUNCH("factors", (k_factors<LP>), dim3((unsigned)(mparts + pparts), nf), dim3(GT), 0, s,
                  (const float *)w.Qm, (const float *)w.Z, m, p, ell, kmax, w.UB, w.sig, w.perm, w.kf,
                  w.fro2, w.qr_info, w.jinfo, Uo, So, Vo, ranks, fro, info, fmap);
     TSVDM_LAUNCH_CHECK("mixed truncate");
