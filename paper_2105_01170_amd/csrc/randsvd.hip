@@ -616,38 +616,36 @@ __global__ __launch_bounds__(QT) void k_cholqr(const float *__restrict__ Sin, in
         // ---- Cholesky of the leading ell x ell block.  Step j subtracts the
         // outer product of row j over the pivot from the rows below; row j of
         // the trailing matrix is final after step j, so the rows of R
-        // (row j / sqrt(pivot j)) are formed afterwards, all at once.
+        // (row j / sqrt(pivot j)) are formed afterwards, all at once.  The
+        // upper entries (i, c) are numbered by decreasing row, so the entries
+        // a step updates (i > j) are a prefix of the numbering: wavefronts
+        // past it skip the step, the others read their operands branch free.
         {
-            constexpr int NI = (LP + 31) / 32, NC = (LP + 15) / 16;
-            const int ty = tid >> 4, tx = tid & 15;
+            constexpr int NU = LP * (LP + 1) / 2, UPT = (NU + QT - 1) / QT;
+            int ei[UPT], ec[UPT];
+#pragma unroll
+            for (int u = 0; u < UPT; ++u) {
+                // entry e: rows ell-1, ell-2, .. 0, each with columns i .. ell-1
+                int rem = tid + u * QT, i = ell - 1;
+                while (i >= 0 && rem >= ell - i) {
+                    rem -= ell - i;
+                    --i;
+                }
+                ei[u] = i;  // -1: no entry
+                ec[u] = i >= 0 ? i + rem : 0;
+            }
             for (int j = 0; j < ell; ++j) {
+                const int cnt = (ell - j - 1) * (ell - j) / 2;  // entries with i > j
                 const double piv = G[j * LDG + j];
-                double gji[NI], gjc[NC], gic[NI][NC];
-#pragma unroll
-                for (int a = 0; a < NI; ++a) {
-                    const int i = j + 1 + ty + 32 * a;
-                    gji[a] = i < ell ? G[j * LDG + i] : 0.0;
-#pragma unroll
-                    for (int b = 0; b < NC; ++b) {
-                        const int c = j + 1 + tx + 16 * b;
-                        gic[a][b] = (i < ell && c < ell && c >= i) ? G[i * LDG + c] : 0.0;
-                    }
-                }
-#pragma unroll
-                for (int b = 0; b < NC; ++b) {
-                    const int c = j + 1 + tx + 16 * b;
-                    gjc[b] = c < ell ? G[j * LDG + c] : 0.0;
-                }
                 const double ipv = piv > 0.0 && isfinite(piv) ? recip(piv) : 0.0;
 #pragma unroll
-                for (int a = 0; a < NI; ++a) {
-                    const int i = j + 1 + ty + 32 * a;
-                    const double l = gji[a] * ipv;
-#pragma unroll
-                    for (int b = 0; b < NC; ++b) {
-                        const int c = j + 1 + tx + 16 * b;
-                        if (i < ell && c < ell && c >= i) G[i * LDG + c] = gic[a][b] - l * gjc[b];
-                    }
+                for (int u = 0; u < UPT; ++u) {
+                    if (u * QT + (tid & ~63) >= cnt) break;  // whole wavefront past the prefix
+                    const bool act = tid + u * QT < cnt;
+                    const int i = act ? ei[u] : j, c = act ? ec[u] : j;
+                    const double gji = G[j * LDG + i], gjc = G[j * LDG + c], gic = G[i * LDG + c];
+                    const double l = gji * ipv;
+                    if (act) G[i * LDG + c] = gic - l * gjc;
                 }
                 __syncthreads();
             }
