@@ -140,6 +140,28 @@ __device__ __forceinline__ void stage_panel(const float *__restrict__ S, int row
     }
 }
 
+// As stage_panel, with 16-byte loads of four consecutive rows: rows a multiple
+// of 4 and S 16-byte aligned (checked by the caller).
+template <int LP, int RC>
+__device__ __forceinline__ void stage_panel4(const float *__restrict__ S, int rows, int r0, float *st) {
+    constexpr int PER = RC * LP / (4 * GT);
+    static_assert(RC * LP % (4 * GT) == 0, "panel size");
+    f32x4 v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * GT, r = 4 * (e % (RC / 4)), c = e / (RC / 4);
+        const bool ok = r0 + r < rows;  // then r0 + r + 3 < rows
+        const f32x4 x = *reinterpret_cast<const f32x4 *>(S + (ok ? (r0 + r) + (int64_t)rows * c : 0));
+        v[q] = ok ? x : f32x4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * GT, r = 4 * (e % (RC / 4)), c = e / (RC / 4);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) st[(r + u) * (LP + 1) + c] = v[q][u];
+    }
+}
+
 // upper 16x16 tile t (row-major over the upper triangle) -> tile coordinates
 template <int NT>
 __device__ __forceinline__ void tile_ij(int t, int &ti, int &tj) {
@@ -269,12 +291,25 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
                 }
             }
         }
+        if constexpr (VEC) {  // four consecutive rows of W (p, ldw multiples of 4)
 #pragma unroll
-        for (int q = 0; q < WPT; ++q) {
-            const int e = tid + q * GT, k = e % KC, c = e / KC, b = b0 + k;
-            const bool ok = c < nw && b < p;
-            wr[q] = *reinterpret_cast<const float *>(Wb + (ok ? 4u * ((uint32_t)b + (uint32_t)ldw * (uint32_t)c) : 0u));
-            wm |= (uint32_t)ok << q;
+            for (int q = 0; q < WPT / 4; ++q) {
+                const int e = tid + q * GT, k4 = e % (KC / 4), c = e / (KC / 4), b = b0 + 4 * k4;
+                const bool ok = c < nw && b < p;
+                const f32x4 x = *reinterpret_cast<const f32x4 *>(
+                    Wb + (ok ? 4u * ((uint32_t)b + (uint32_t)ldw * (uint32_t)c) : 0u));
+#pragma unroll
+                for (int v = 0; v < 4; ++v) wr[4 * q + v] = x[v];
+                wm |= ok ? 0xFu << (4 * q) : 0u;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < WPT; ++q) {
+                const int e = tid + q * GT, k = e % KC, c = e / KC, b = b0 + k;
+                const bool ok = c < nw && b < p;
+                wr[q] = *reinterpret_cast<const float *>(Wb + (ok ? 4u * ((uint32_t)b + (uint32_t)ldw * (uint32_t)c) : 0u));
+                wm |= (uint32_t)ok << q;
+            }
         }
     };
     load(0);
@@ -293,16 +328,31 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
             *reinterpret_cast<uint2 *>(&xh[(4 * rq + v) * LDK + 4 * cg]) = h;
             if (SPL) *reinterpret_cast<uint2 *>(&xl[(4 * rq + v) * LDK + 4 * cg]) = l;
         }
+        if constexpr (VEC) {
 #pragma unroll
-        for (int q = 0; q < WPT; q += 2) {
-            const int e0 = tid + q * GT, e1 = e0 + GT;
-            uint32_t hh, ll;
-            split2((wm >> q) & 1u ? wr[q] : 0.0f, (wm >> (q + 1)) & 1u ? wr[q + 1] : 0.0f, hh, ll);
-            wh[(e0 / KC) * LDK + e0 % KC] = (uint16_t)hh;
-            wh[(e1 / KC) * LDK + e1 % KC] = (uint16_t)(hh >> 16);
-            if (SPL) {
-                wl[(e0 / KC) * LDK + e0 % KC] = (uint16_t)ll;
-                wl[(e1 / KC) * LDK + e1 % KC] = (uint16_t)(ll >> 16);
+            for (int q = 0; q < WPT / 4; ++q) {  // rows 4k4 .. 4k4+3 of column c
+                const int e = tid + q * GT, k4 = e % (KC / 4), c = e / (KC / 4);
+                float w4[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) w4[v] = (wm >> (4 * q + v)) & 1u ? wr[4 * q + v] : 0.0f;
+                uint2 h, l;
+                split2(w4[0], w4[1], h.x, l.x);
+                split2(w4[2], w4[3], h.y, l.y);
+                *reinterpret_cast<uint2 *>(&wh[c * LDK + 4 * k4]) = h;
+                if (SPL) *reinterpret_cast<uint2 *>(&wl[c * LDK + 4 * k4]) = l;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < WPT; q += 2) {
+                const int e0 = tid + q * GT, e1 = e0 + GT;
+                uint32_t hh, ll;
+                split2((wm >> q) & 1u ? wr[q] : 0.0f, (wm >> (q + 1)) & 1u ? wr[q + 1] : 0.0f, hh, ll);
+                wh[(e0 / KC) * LDK + e0 % KC] = (uint16_t)hh;
+                wh[(e1 / KC) * LDK + e1 % KC] = (uint16_t)(hh >> 16);
+                if (SPL) {
+                    wl[(e0 / KC) * LDK + e0 % KC] = (uint16_t)ll;
+                    wl[(e1 / KC) * LDK + e1 % KC] = (uint16_t)(ll >> 16);
+                }
             }
         }
         __syncthreads();
@@ -419,12 +469,25 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
                 }
             }
         }
+        if constexpr (VEC) {  // four consecutive rows of W (m, ldw multiples of 4)
 #pragma unroll
-        for (int q = 0; q < WPT; ++q) {
-            const int e = tid + q * GT, k = e % KC, c = e / KC, a = a0 + k;
-            const bool ok = c < nw && a < m;
-            wr[q] = *reinterpret_cast<const float *>(Wb + (ok ? 4u * ((uint32_t)a + (uint32_t)ldw * (uint32_t)c) : 0u));
-            wm |= (uint32_t)ok << q;
+            for (int q = 0; q < WPT / 4; ++q) {
+                const int e = tid + q * GT, k4 = e % (KC / 4), c = e / (KC / 4), aw = a0 + 4 * k4;
+                const bool ok = c < nw && aw < m;
+                const f32x4 x = *reinterpret_cast<const f32x4 *>(
+                    Wb + (ok ? 4u * ((uint32_t)aw + (uint32_t)ldw * (uint32_t)c) : 0u));
+#pragma unroll
+                for (int v = 0; v < 4; ++v) wr[4 * q + v] = x[v];
+                wm |= ok ? 0xFu << (4 * q) : 0u;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < WPT; ++q) {
+                const int e = tid + q * GT, k = e % KC, c = e / KC, aw = a0 + k;
+                const bool ok = c < nw && aw < m;
+                wr[q] = *reinterpret_cast<const float *>(Wb + (ok ? 4u * ((uint32_t)aw + (uint32_t)ldw * (uint32_t)c) : 0u));
+                wm |= (uint32_t)ok << q;
+            }
         }
     };
     load(0);
@@ -441,16 +504,31 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
             *reinterpret_cast<uint2 *>(&xh[cj * LDK + 4 * q4]) = ph;
             if (SPL) *reinterpret_cast<uint2 *>(&xl[cj * LDK + 4 * q4]) = pl;
         }
+        if constexpr (VEC) {
 #pragma unroll
-        for (int q = 0; q < WPT; q += 2) {
-            const int e0 = tid + q * GT, e1 = e0 + GT;
-            uint32_t hh, ll;
-            split2((wm >> q) & 1u ? wr[q] : 0.0f, (wm >> (q + 1)) & 1u ? wr[q + 1] : 0.0f, hh, ll);
-            wh[(e0 / KC) * LDK + e0 % KC] = (uint16_t)hh;
-            wh[(e1 / KC) * LDK + e1 % KC] = (uint16_t)(hh >> 16);
-            if (SPL) {
-                wl[(e0 / KC) * LDK + e0 % KC] = (uint16_t)ll;
-                wl[(e1 / KC) * LDK + e1 % KC] = (uint16_t)(ll >> 16);
+            for (int q = 0; q < WPT / 4; ++q) {  // rows 4k4 .. 4k4+3 of column c
+                const int e = tid + q * GT, k4 = e % (KC / 4), c = e / (KC / 4);
+                float w4[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) w4[v] = (wm >> (4 * q + v)) & 1u ? wr[4 * q + v] : 0.0f;
+                uint2 h, l;
+                split2(w4[0], w4[1], h.x, l.x);
+                split2(w4[2], w4[3], h.y, l.y);
+                *reinterpret_cast<uint2 *>(&wh[c * LDK + 4 * k4]) = h;
+                if (SPL) *reinterpret_cast<uint2 *>(&wl[c * LDK + 4 * k4]) = l;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < WPT; q += 2) {
+                const int e0 = tid + q * GT, e1 = e0 + GT;
+                uint32_t hh, ll;
+                split2((wm >> q) & 1u ? wr[q] : 0.0f, (wm >> (q + 1)) & 1u ? wr[q + 1] : 0.0f, hh, ll);
+                wh[(e0 / KC) * LDK + e0 % KC] = (uint16_t)hh;
+                wh[(e1 / KC) * LDK + e1 % KC] = (uint16_t)(hh >> 16);
+                if (SPL) {
+                    wl[(e0 / KC) * LDK + e0 % KC] = (uint16_t)ll;
+                    wl[(e1 / KC) * LDK + e1 % KC] = (uint16_t)(ll >> 16);
+                }
             }
         }
         __syncthreads();
@@ -523,7 +601,8 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
         rload((nch - 1) * KC, xv, vm);
         for (int ci = nch - 1; ci >= 0; --ci) {
             const int a0 = ci * KC;
-            stage_panel<LP, 64>(Wf, m, a0, qs);
+            if constexpr (VEC) stage_panel4<LP, 64>(Wf, m, a0, qs);
+            else stage_panel<LP, 64>(Wf, m, a0, qs);
             __syncthreads();
             if (ci > 0) rload(a0 - KC, xn, nm);  // next chunk in flight during the MFMAs
             f32x4 pr[4];
@@ -1074,10 +1153,13 @@ __global__ __launch_bounds__(1024) void k_fallback_list(const double *__restrict
 // the range and the kernels see a tensor of nfg faces.
 
 // The GEMM passes' 16-byte loads of four consecutive rows at 32-bit offsets
-// from the face: m a multiple of 4 (every face start is then as aligned as
-// X), X 16-byte aligned, a face below 4 GiB.
+// from the face: m and p multiples of 4 (every face start of X, and every
+// row block of a W with leading dimension m or p, is then as aligned as its
+// base), X 16-byte aligned, a face below 4 GiB.  The workspace panels are
+// 256-byte aligned; Omega is checked where it is used.
 bool vec_loads_ok(const float *X, int m, int p) {
-    return m % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 && (int64_t)m * p < (int64_t)1 << 30;
+    return m % 4 == 0 && p % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 &&
+           (int64_t)m * p < (int64_t)1 << 30;
 }
 template <int LP>
 tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
@@ -1115,12 +1197,12 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     const bool power = o->power_iters > 0;
     // the residual is needed for the certificate and for the energy rule
     const bool resid = o->rank_mode == TSVDM_RANK_ENERGY || (o->certify && cert);
-    const bool v4 = vec_loads_ok(Xd, m, p);
+    const bool v4 = vec_loads_ok(Xd, m, p) && reinterpret_cast<uintptr_t>(w.Y) % 16 == 0;
     TSVDM_LAUNCH("zero_info", k_zero_i32, dim3((nf + 255) / 256), dim3(256), 0, s, w.qr_info, nf);
     const double *gm_c = w.gram_m, *gp_c = w.gram_p;
 #define TSVDM_SKETCH()                                                                                      \
     do {                                                                                                    \
-        if (v4)                                                                                             \
+        if (v4 && reinterpret_cast<uintptr_t>(o->omega) % 16 == 0)                                          \
             TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true, true>), gm, dim3(GT), 0, s, Xd, m, p, nf, \
                          o->omega, (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m, fmap);                     \
         else                                                                                                \
@@ -1229,7 +1311,7 @@ tsvdm_status launch_rank_features(const tsvdm_tensor *X, const float *omega, uin
     const int mparts = (m + 63) / 64;
     const float *Xd = reinterpret_cast<const float *>(X->data);
     const dim3 gm((unsigned)(mparts * nf));
-    if (vec_loads_ok(Xd, m, p))
+    if (vec_loads_ok(Xd, m, p) && reinterpret_cast<uintptr_t>(omega) % 16 == 0)
         TSVDM_LAUNCH("features_sketch", (k_xw<32, PROD_BF16, true, true>), gm, dim3(GT), 0, s, Xd, m, p, nf,
                      omega, (int64_t)0, p, 32, w.Y, w.fro_part, w.gram_m, (const int32_t *)nullptr);
     else
