@@ -61,18 +61,23 @@ __device__ __forceinline__ f32x4 mfma(const u16x8 &a, const u16x8 &b, f32x4 c) {
                                                    __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
 }
 
-// ---------------------------------------------------------------- XCD map
-// Workgroups are dispatched round-robin over the 8 XCDs (workgroup L runs on
-// XCD L % 8, each with its own L2).  For a pass whose nb blocks of a face all
-// read the same per-face operand, give those blocks consecutive slots on one
-// XCD, so the operand is fetched into that L2 once instead of eight times.
-// G (LDS, pitch ldg) = ordered sum over pp of the nparts LP x LP row-major
-// FP64 partials of face f.  All loads of a block of 8 partials are issued
+// ---------------------------------------------------------------- Gram partials
+// Gram partials: the upper 16x16 tiles of the LP x LP block Gram (tile t in
+// row-major order over the upper triangle), each row major, packed one after
+// another; one partial per LP*LP doubles of the workspace.
+template <int LP>
+constexpr int gram_tiles() {
+    return (LP / 16) * (LP / 16 + 1) / 2;
+}
+
+// G (LDS, pitch ldg) = ordered sum over pp of the nparts packed partials of
+// face f, both triangles.  All loads of a block of 8 partials are issued
 // before any is summed (clamped addresses, zero-selected, no branches).
 template <int LP, int NTH>
 __device__ __forceinline__ void load_gram_partials(const double *__restrict__ gpart, int f, int nparts,
                                                    double *G, int ldg) {
-    constexpr int N2 = LP * LP / 2, E2 = (N2 + NTH - 1) / NTH, PB = 8;
+    constexpr int NT = LP / 16, NE2 = gram_tiles<LP>() * 128, S2 = LP * LP / 2;
+    constexpr int E2 = (NE2 + NTH - 1) / NTH, PB = 8;
     const int tid = threadIdx.x;
     const double2 *g2 = reinterpret_cast<const double2 *>(gpart + (int64_t)f * nparts * LP * LP);
     double2 acc[E2];
@@ -85,8 +90,8 @@ __device__ __forceinline__ void load_gram_partials(const double *__restrict__ gp
 #pragma unroll
             for (int u = 0; u < PB; ++u) {
                 const int e2 = tid + q * NTH, pp = p0 + u;
-                const bool in = e2 < N2 && pp < nparts;
-                const double2 t = g2[(int64_t)(pp < nparts ? pp : nparts - 1) * N2 + (e2 < N2 ? e2 : 0)];
+                const bool in = e2 < NE2 && pp < nparts;
+                const double2 t = g2[(int64_t)(pp < nparts ? pp : nparts - 1) * S2 + (e2 < NE2 ? e2 : 0)];
                 v[q][u] = in ? t : double2{0.0, 0.0};
             }
 #pragma unroll
@@ -100,14 +105,29 @@ __device__ __forceinline__ void load_gram_partials(const double *__restrict__ gp
 #pragma unroll
     for (int q = 0; q < E2; ++q) {
         const int e2 = tid + q * NTH;
-        if (e2 < N2) {
-            const int r = (2 * e2) / LP, c = (2 * e2) % LP;
-            G[r * ldg + c] = acc[q].x;
-            G[r * ldg + c + 1] = acc[q].y;
+        if (e2 < NE2) {
+            const int t = (2 * e2) >> 8, r = ((2 * e2) >> 4) & 15, c = (2 * e2) & 15;
+            int ti = 0, tt = t;
+            while (tt >= NT - ti) {
+                tt -= NT - ti;
+                ++ti;
+            }
+            const int tj = ti + tt, i = 16 * ti + r, j = 16 * tj + c;
+            G[i * ldg + j] = acc[q].x;
+            G[i * ldg + j + 1] = acc[q].y;
+            if (ti != tj) {
+                G[j * ldg + i] = acc[q].x;
+                G[(j + 1) * ldg + i] = acc[q].y;
+            }
         }
     }
 }
 
+// ---------------------------------------------------------------- XCD map
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup L runs on
+// XCD L % 8, each with its own L2).  For a pass whose nb blocks of a face all
+// read the same per-face operand, give those blocks consecutive slots on one
+// XCD, so the operand is fetched into that L2 once instead of eight times.
 __device__ __forceinline__ void xcd_map(int L, int nb, int nf, int &b, int &f) {
     if ((nf & 7) == 0) {
         const int x = L & 7, s = L >> 3;
@@ -193,11 +213,17 @@ __device__ __forceinline__ void put_sym_tile(T *G, int ld, int ti, int tj, const
 
 // FP64 Gram of the 64 x LP block held in the four wavefronts' MFMA
 // accumulators (row 16*wave + 4*(lane/16) + v, column 16*j + lane%16), by FP64
-// MFMA on the upper tiles (products of FP32 values are exact in FP64);
-// written row major LP x LP to `out`.  `ys` holds 64*(LP+1) floats.
+// MFMA on the upper tiles (products of FP32 values are exact in FP64), written
+// to `out` as packed upper tiles (gram_tiles).  Every tile is split into two
+// halves of 32 rows, so the 2 * gram_tiles items spread evenly over the four
+// wavefronts; the second half's sum goes through `red` (LDS, 256 doubles per
+// tile, written after every read of ys, so it may overlap ys) to the
+// first's.  The FP64 16x16x4 output (row lane/16 + 4v, column lane%16) at
+// index 64v + lane is the tile in row-major order, so the stores are
+// contiguous.  `ys` holds 64*(LP+1) floats.  Ends with a barrier.
 template <int LP>
-__device__ void block_gram_f64(const f32x4 (&acc)[LP / 16], double *__restrict__ out, float *ys) {
-    constexpr int NT = LP / 16, NTILE = NT * (NT + 1) / 2, TPW = (NTILE + 3) / 4;
+__device__ void block_gram_f64(const f32x4 (&acc)[LP / 16], double *__restrict__ out, float *ys, double *red) {
+    constexpr int NT = LP / 16, NTILE = gram_tiles<LP>(), IPW = (2 * NTILE + 3) / 4;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
 #pragma unroll
     for (int j = 0; j < NT; ++j)
@@ -205,22 +231,42 @@ __device__ void block_gram_f64(const f32x4 (&acc)[LP / 16], double *__restrict__
         for (int v = 0; v < 4; ++v)
             ys[(16 * wave + 4 * (lane >> 4) + v) * (LP + 1) + 16 * j + (lane & 15)] = acc[j][v];
     __syncthreads();
+    f64x4 g[IPW];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t) {
-        const int idx = wave + 4 * t;
-        if (idx >= NTILE) continue;
+    for (int u = 0; u < IPW; ++u) {
+        g[u] = f64x4{0, 0, 0, 0};
+        const int it = wave + 4 * u;
+        if (it >= 2 * NTILE) continue;
         int ti, tj;
-        tile_ij<NT>(idx, ti, tj);
-        f64x4 g = f64x4{0, 0, 0, 0};
+        tile_ij<NT>(it >> 1, ti, tj);
+        const int r0 = 32 * (it & 1);
 #pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            const int r = 4 * kk + (lane >> 4);
-            g = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ys[r * (LP + 1) + 16 * ti + (lane & 15)],
-                                                     (double)ys[r * (LP + 1) + 16 * tj + (lane & 15)], g,
-                                                     0, 0, 0);
+        for (int kk = 0; kk < 8; ++kk) {
+            const int r = r0 + 4 * kk + (lane >> 4);
+            g[u] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)ys[r * (LP + 1) + 16 * ti + (lane & 15)],
+                                                        (double)ys[r * (LP + 1) + 16 * tj + (lane & 15)], g[u],
+                                                        0, 0, 0);
         }
-        put_sym_tile<true>(out, LP, ti, tj, g, lane);
     }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < IPW; ++u) {
+        const int it = wave + 4 * u;
+        if (it < 2 * NTILE && (it & 1)) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[(it >> 1) * 256 + 64 * v + lane] = g[u][v];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < IPW; ++u) {
+        const int it = wave + 4 * u;
+        if (it >= 2 * NTILE || (it & 1)) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            out[(it >> 1) * 256 + 64 * v + lane] = g[u][v] + red[(it >> 1) * 256 + 64 * v + lane];
+    }
+    __syncthreads();
 }
 
 // ---------------------------------------------------------------- Y = X W
@@ -251,7 +297,9 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
     __shared__ __align__(16) uint16_t xl[SPL ? 64 * LDK : 8];
     __shared__ __align__(16) uint16_t wh[LP * LDK];
     __shared__ __align__(16) uint16_t wl[SPL ? LP * LDK : 8];
-    __shared__ float ys[GRAM ? 64 * (LP + 1) : 1];
+    // Gram staging; afterwards the Gram's half-tile sums (as doubles)
+    constexpr int YS = 64 * (LP + 1) > 512 * gram_tiles<LP>() ? 64 * (LP + 1) : 512 * gram_tiles<LP>();
+    __shared__ __align__(16) float ys[GRAM ? YS : 1];
     __shared__ double red[GT / 64];
     const int nb = (m + 63) / 64;
     int blk, f;
@@ -388,7 +436,7 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
             if (r < m) Yf[r + (int64_t)m * c] = acc[j][v];
         }
     }
-    if (GRAM) block_gram_f64<LP>(acc, gram_part + ((int64_t)f * nb + blk) * LP * LP, ys);
+    if (GRAM) block_gram_f64<LP>(acc, gram_part + ((int64_t)f * nb + blk) * LP * LP, ys, reinterpret_cast<double *>(ys));
     if (fro_part) {
         fro = wave_sum(fro);
         if (lane == 0) red[wave] = fro;
@@ -426,8 +474,10 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
     // LDS: the BF16 operands of the main loop; the residual stages the FP32
     // Q chunk (64 x (LP+1)) in the same bytes afterwards
     constexpr int XS = 64 * LDK, WS = LP * LDK;  // uint16 elements, multiples of 8
+    // and, after the loop, the Gram's half-tile sums (GRB bytes)
     constexpr int MAINB = (SPL ? 2 : 1) * (XS + WS) * 2, QSB = RES ? 64 * (LP + 1) * 4 : 0;
-    __shared__ __align__(16) uint16_t smem[(MAINB > QSB ? MAINB : QSB) / 2];
+    constexpr int GRB = GRAM ? 2048 * gram_tiles<LP>() : 0, SB0 = MAINB > QSB ? MAINB : QSB;
+    __shared__ __align__(16) uint16_t smem[(SB0 > GRB ? SB0 : GRB) / 2];
     __shared__ float ys[GRAM ? 64 * (LP + 1) : 1];
     __shared__ double red[RES ? GT / 64 : 1];
     uint16_t *xh = smem, *wh = smem + XS;
@@ -564,7 +614,8 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
             if (r < p) Zf[r + (int64_t)p * c] = acc[j][v];
         }
     }
-    if (GRAM) block_gram_f64<LP>(acc, gram_part + ((int64_t)f * nb + blk) * LP * LP, ys);
+    if (GRAM)
+        block_gram_f64<LP>(acc, gram_part + ((int64_t)f * nb + blk) * LP * LP, ys, reinterpret_cast<double *>(smem));
     if (RES) {
         // ys[b * (LP+1) + c] = B^T[b0 + b][c] (rows past p are zero): the
         // B operands of the 16x16x4 MFMA (k = lane/16, column lane%16)
