@@ -259,7 +259,7 @@ __global__ __launch_bounds__(64) void k_bcore(const Item *__restrict__ items, in
     int conv = 0;
     const double *Hf, *Ef;
     int dslot;
-    jacobi_eig<RX, 64>(Hb[0], Hb[1], Eb[0], Eb[1], cs, rflag, r, trH, max_sweeps, conv, Hf, Ef, dslot);
+    jacobi_eig<RX, 64>(Hb[0], Hb[1], Eb[0], Eb[1], cs, rflag, r, 1e-15 * trH, max_sweeps, conv, Hf, Ef, dslot);
     if (lane < r) {
         const int sl = jacobi_slot(lane, dslot);
         lam[lane] = fmax(Hf[sl * LD + sl], 0.0);

@@ -28,10 +28,11 @@ __device__ __forceinline__ double rsqrt_nr(double a) {
     return fma(0.5 * y, e, y);
 }
 
-// a pair rotates when its off-diagonal entry is not negligible, relative to
-// the diagonal pair and at the rounding level of the trace
-__device__ __forceinline__ bool jneeds(double app, double aqq, double apq, double trace) {
-    return apq * apq > 1e-30 * fabs(app * aqq) && fabs(apq) > 1e-15 * trace;
+// a pair rotates when its off-diagonal entry is not negligible: relative to
+// the diagonal pair (1e-15) and above the absolute threshold atol (the
+// caller's choice, a multiple of the trace)
+__device__ __forceinline__ bool jneeds(double app, double aqq, double apq, double atol) {
+    return apq * apq > 1e-30 * fabs(app * aqq) && fabs(apq) > atol;
 }
 
 // rotation (c, s) of a pair from its entries app, aqq, apq: the smaller of
@@ -40,9 +41,9 @@ __device__ __forceinline__ bool jneeds(double app, double aqq, double apq, doubl
 // (d = aqq - app, e = 2 apq; no cancellation, c^2 + s^2 = 1 up to rounding);
 // identity (and false) for a padding pair or a pair that need not rotate.
 // Branch free, so that the caller's loads are all issued up front.
-__device__ __forceinline__ bool jrot(double app, double aqq, double apq, bool valid, double trace,
+__device__ __forceinline__ bool jrot(double app, double aqq, double apq, bool valid, double atol,
                                      double &c, double &s) {
-    const bool go = valid && jneeds(app, aqq, apq, trace);
+    const bool go = valid && jneeds(app, aqq, apq, atol);
     const double d = aqq - app, e = 2.0 * apq;
     const double y = rsqrt_nr(go ? fma(d, d, e * e) : 1.0);  // 1 / h
     const double c2 = fma(0.5 * fabs(d), y, 0.5);          // cos^2 of the angle
@@ -89,8 +90,9 @@ __device__ __forceinline__ int rr_next(int s, int h) {
 //     buffer becomes J_p^T B J_q and is written to its next slots in the
 //     other buffer.
 // The last round's rotations reach the eigenvectors after the loop.  Before
-// every sweep all pairs are tested with the rotation criterion; when none
-// would rotate the iteration ends (conv = 1).  At most max_sweeps sweeps.
+// every sweep all pairs are tested with the rotation criterion (jneeds, with
+// the absolute threshold atol); when none would rotate the iteration ends
+// (conv = 1).  At most max_sweeps sweeps.
 // rflag[3]: zero on entry.  Entries past ne of G0 and E0 zero; G1, E1 any.
 // NTH threads take part (the whole workgroup); ends with a barrier.  On
 // return Gout holds the final matrix (its diagonal the eigenvalues, in slot
@@ -99,7 +101,7 @@ __device__ __forceinline__ int rr_next(int s, int h) {
 // zero), else -1.  The n real eigenpairs are in the other ne slots.
 template <int LP, int NTH>
 __device__ void jacobi_eig(double *G0, double *G1, double *E0, double *E1, double2 *cs, int *rflag, int n,
-                           double trace, int max_sweeps, int &conv, const double *&Gout, const double *&Eout,
+                           double atol, int max_sweeps, int &conv, const double *&Gout, const double *&Eout,
                            int &dslot) {
     constexpr int LD = jacobi_ld<LP>(), LDE = jacobi_ld<LP>(), NPM = LP / 2;
     constexpr int IPT = (NPM * (NPM + 1) / 2 + (LP / 4) * NPM + NTH - 1) / NTH;  // items per thread
@@ -165,7 +167,7 @@ __device__ void jacobi_eig(double *G0, double *G1, double *E0, double *E1, doubl
             bool need = false;
             for (int e = tid; e < ne * ne; e += NTH) {
                 const int i = e / ne, j = e - i * ne;
-                if (i < j) need |= jneeds(Gc[i * LD + i], Gc[j * LD + j], Gc[i * LD + j], trace);
+                if (i < j) need |= jneeds(Gc[i * LD + i], Gc[j * LD + j], Gc[i * LD + j], atol);
             }
             if (__any(need) && lane == 0) rflag[fl] = 1;
             __syncthreads();
@@ -183,7 +185,7 @@ __device__ void jacobi_eig(double *G0, double *G1, double *E0, double *E1, doubl
                 const double2 g = *reinterpret_cast<const double2 *>(Gc + 2 * tid * (LD + 1));
                 const double aqq = Gc[(2 * tid + 1) * (LD + 1)];
                 double c, s;
-                jrot(g.x, aqq, g.y, true, trace, c, s);
+                jrot(g.x, aqq, g.y, true, atol, c, s);
                 cs[par * NPM + tid] = double2{c, s};
             }
             if (rr > 0) {

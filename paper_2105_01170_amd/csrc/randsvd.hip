@@ -889,11 +889,16 @@ __global__ __launch_bounds__(QT) void k_cholqr(const float *__restrict__ Sin, in
 //   cert^2 = ||X - Q B||^2 + sum_{j > k_f} lambda_j
 // (the error of Q U_B[:, :k] U_B[:, :k]^T B, since Q has orthonormal columns).
 // The energy rule takes the smallest k whose certified error meets tau.
+// jtol: the Jacobi solver's absolute threshold over the trace.  The sums
+// above use the diagonal of the rotated matrix, E^T (B B^T) E, and equal
+// ||B - E_k E_k^T B||^2 for the orthogonal E the solver returns whether or
+// not it has converged, so the threshold moves no certificate.
+constexpr double kJacobiTolMixed = 1e-12;  // B carries ~1e-5 relative error
 template <int LP>
 __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, int nparts, int ell,
                                              const double *__restrict__ fro_part, int nfro,
                                              const double *__restrict__ res_part, int nres,
-                                             int mode, int kfix, double tau, int max_sweeps,
+                                             int mode, int kfix, double tau, int max_sweeps, double jtol,
                                              double *__restrict__ UB, double *__restrict__ sig,
                                              int *__restrict__ perm_out, int *__restrict__ kf_out,
                                              double *__restrict__ fro2_out, double *__restrict__ cert,
@@ -929,7 +934,8 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
     int conv = 0;
     const double *G, *E;
     int dslot;
-    jacobi_eig<LP, QT>(Gb[0], Gb[1], Eb[0], Eb[1], &cs[0][0], rflag, ell, trace, max_sweeps, conv, G, E, dslot);
+    jacobi_eig<LP, QT>(Gb[0], Gb[1], Eb[0], Eb[1], &cs[0][0], rflag, ell, jtol * trace, max_sweeps, conv, G, E,
+                       dslot);
     if (tid < ell) {
         const int sl = jacobi_slot(tid, dslot);
         lam[tid] = fmax(G[sl * LD + sl], 0.0);
@@ -1306,7 +1312,8 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     const int msw = o->max_sweeps > 0 ? o->max_sweeps : 30;
     TSVDM_LAUNCH("core_gram_eig", (k_core<LP>), dim3(nf), dim3(QT), 0, s, gp_c, pparts, ell,
                  (const double *)w.fro_part, mparts, (const double *)w.res_part, resid ? pparts : 0,
-                 o->rank_mode, o->k, o->tau, msw, w.UB, w.sig, w.perm, w.kf, w.fro2, cert, w.jinfo, fmap);
+                 o->rank_mode, o->k, o->tau, msw, kJacobiTolMixed, w.UB, w.sig, w.perm, w.kf, w.fro2, cert, w.jinfo,
+                 fmap);
     TSVDM_LAUNCH("factors", (k_factors<LP>), dim3((unsigned)(mparts + pparts), nf), dim3(GT), 0, s,
                  (const float *)w.Qm, (const float *)w.Z, m, p, ell, kmax, w.UB, w.sig, w.perm, w.kf,
                  w.fro2, w.qr_info, w.jinfo, Uo, So, Vo, ranks, fro, info, fmap);
@@ -1370,7 +1377,7 @@ tsvdm_status launch_rank_features(const tsvdm_tensor *X, const float *omega, uin
                      omega, (int64_t)0, p, 32, w.Y, w.fro_part, w.gram_m, (const int32_t *)nullptr);
     TSVDM_LAUNCH("features_eig", (k_core<32>), dim3(nf), dim3(QT), 0, s, (const double *)w.gram_m, mparts, 32,
                  (const double *)w.fro_part, mparts, (const double *)nullptr, 0, (int)TSVDM_RANK_FIXED, 32, 0.0,
-                 30, w.UB, w.sig, w.perm, w.kf, w.fro2, (double *)nullptr, w.jinfo, (const int32_t *)nullptr);
+                 30, 1e-15, w.UB, w.sig, w.perm, w.kf, w.fro2, (double *)nullptr, w.jinfo, (const int32_t *)nullptr);
     TSVDM_LAUNCH("features_log", k_rank_features, dim3(nf), dim3(32), 0, s, (const double *)w.sig, 32, nf,
                  reinterpret_cast<_Float16 *>(features));
     TSVDM_LAUNCH_CHECK("rank features");
