@@ -709,7 +709,7 @@ template <int LP>
 __global__ __launch_bounds__(QT) void k_cholqr(const float *__restrict__ Sin, int rows, int ell,
                                                float *__restrict__ Qout, int passes,
                                                const double *__restrict__ gpart, int nparts,
-                                               int32_t *__restrict__ qr_info) {
+                                               int32_t *__restrict__ qr_info, int first) {
     constexpr int LDG = LP + 1, LDR = LP + 2, LDS_ = LP + 1, HR = LP <= 48 ? QT : QT / 2;
     constexpr int NT = LP / 16, NTILE = NT * (NT + 1) / 2, TPW = (NTILE + 7) / 8;
     __shared__ double G[LP * LDG];
@@ -877,7 +877,11 @@ __global__ __launch_bounds__(QT) void k_cholqr(const float *__restrict__ Sin, in
             __syncthreads();
         }
     }
-    if (tid == 0 && bad) qr_info[f] = 2;
+    // the first Cholesky-QR of a truncation sets the flag, later ones raise it
+    if (tid == 0) {
+        if (first) qr_info[f] = bad ? 2 : 0;
+        else if (bad) qr_info[f] = 2;
+    }
 }
 
 // ---------------------------------------------------------------- core SVD
@@ -1074,11 +1078,6 @@ __global__ __launch_bounds__(GT) void k_factors(const float *__restrict__ Q, con
     }
 }
 
-__global__ void k_zero_i32(int32_t *__restrict__ x, int n) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = 0;
-}
-
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct MixedWs {
@@ -1255,7 +1254,6 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     // the residual is needed for the certificate and for the energy rule
     const bool resid = o->rank_mode == TSVDM_RANK_ENERGY || (o->certify && cert);
     const bool v4 = vec_loads_ok(Xd, m, p) && reinterpret_cast<uintptr_t>(w.Y) % 16 == 0;
-    TSVDM_LAUNCH("zero_info", k_zero_i32, dim3((nf + 255) / 256), dim3(256), 0, s, w.qr_info, nf);
     const double *gm_c = w.gram_m, *gp_c = w.gram_p;
 #define TSVDM_SKETCH()                                                                                      \
     do {                                                                                                    \
@@ -1272,7 +1270,7 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
         // basis of the sketch: one shifted Cholesky-QR step (its span is what
         // the power step needs)
         TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell,
-                     w.Qm, 1, gm_c, mparts, w.qr_info);
+                     w.Qm, 1, gm_c, mparts, w.qr_info, 1);
         // pass 2: Z = X^T Q (BF16) and its Gram partials; basis of Z
         if (v4)
             TSVDM_LAUNCH("power_xtw_bf16", (k_xtw<LP, PROD_BF16, true, false, true>), gp, dim3(GT), 0, s, Xd, m,
@@ -1281,7 +1279,7 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
             TSVDM_LAUNCH("power_xtw_bf16", (k_xtw<LP, PROD_BF16, true, false, false>), gp, dim3(GT), 0, s, Xd, m,
                          p, nf, (const float *)w.Qm, (int64_t)m * LP, m, ell, w.Z, w.gram_p, (double *)nullptr, fmap);
         TSVDM_LAUNCH("cholqr_power_z", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Z, p, ell,
-                     w.Qp, 1, gp_c, pparts, w.qr_info);
+                     w.Qp, 1, gp_c, pparts, w.qr_info, 0);
         // pass 3: Y' = X Qz, FP32-accurate (split BF16), and its Gram partials
         if (v4)
             TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true, true>), gm, dim3(GT), 0, s, Xd, m, p, nf,
@@ -1295,7 +1293,7 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
 #undef TSVDM_SKETCH
     // final basis: FP64 shifted Cholesky-QR2 (first Gram from the partials)
     TSVDM_LAUNCH("cholqr_final", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell, w.Qm,
-                 2, gm_c, mparts, w.qr_info);
+                 2, gm_c, mparts, w.qr_info, power ? 0 : 1);
     // pass 4: B^T = X^T Q, FP32-accurate, the Gram partials of B^T and, for
     // the certificate, ||X - Q B||^2 per 64-column block
 #define TSVDM_PROJECT(NAME, RES, V, RP)                                                                    \
