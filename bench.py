@@ -115,9 +115,10 @@ def uneven_main(args):
     """The uneven batch: 256 matrices A_i = sum_{r<r_i} B_r kron C_r with factor
     sizes s_B, s_C log-uniform in [16, 64] and r_i uniform in 2..16; each is
     mapped by T_E (zero-copy view, s_C x s_B^2 x s_C), transformed by the
-    DCT-II along the tubes (FP32) and truncated facewise by the energy rule
-    tau = 1e-4 in one batched call.  A step is the 256 transforms plus the
-    batched truncation, replayed from one captured graph; the per-kernel
+    DCT-II along the tubes (FP32, one batched transform) and truncated
+    facewise by the energy rule tau = 1e-4 in one batched call.  A step is the
+    256 transforms plus the batched truncation, replayed from one captured
+    graph; the per-kernel
     durations come from separate eager steps timed with events on the launch
     stream."""
     import torch
@@ -145,10 +146,12 @@ def uneven_main(args):
         xhs.append(torch.empty(m * ell * ell * m, dtype=torch.float32, device=dev))
         shapes.append((m, ell * ell, m))
     bt = api.BatchedTruncator(xhs, shapes, rank_mode=C.RANK_ENERGY, k=16, tau=1e-4, kmax=16, device=dev)
+    # the 256 transforms: one batched direct launch per length class (n3 <= 32,
+    # <= 64) over 64-tube tiles of all tensors, the zero-copy T_E views as input
+    btf = api.BatchedTransform(As, xhs, shapes, [C.M_DCT2] * len(shapes), +1, views=views, device=dev)
 
     def step():
-        for Acm, v, xh, (m, pp, n) in zip(As, views, xhs, shapes):
-            api.transform(Acm, m, pp, n, C.M_DCT2, +1, out=xh, view=v)
+        btf()
         bt()
 
     step()
@@ -194,6 +197,7 @@ def uneven_main(args):
     gram_flops = float(sum(sh[0] * (sh[0] + 1) * sh[1] * sh[2] for sh in shapes))
     work = {
         "transform_direct": ("hbm", 8.0 * elems),
+        "transform_direct_batched": ("hbm", 8.0 * elems),
         "transform_fft": ("hbm", 8.0 * elems),
         "batched_gram": ("fp64", gram_flops),
         "batched_vec": ("hbm", 4.0 * elems + 4.0 * 16 * sum(sh[1] * sh[2] for sh in shapes)),

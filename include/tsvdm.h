@@ -166,6 +166,43 @@ tsvdm_status tsvdm_check_orthogonal(const double *M_host, int64_t n3, double tol
 tsvdm_status tsvdm_transform(const tsvdm_mdesc *M, int32_t direction, const tsvdm_tensor *in,
                              tsvdm_tensor *out, void *stream);
 
+/* Batched mode-3 transform of nmat independent tensors (Sec. 2.1 for each;
+ * the inputs of the uneven batch below): out[i] = in[i] x_3 M[i]^(+-1), every
+ * (M[i], in[i], out[i]) as for tsvdm_transform, one direction for all.  The
+ * tensors whose M is DCT2 or DENSE with n3 <= 64 are transformed by the
+ * direct per-tube product in one launch per precision and length class
+ * (n3 <= 32, n3 <= 64): workgroup w takes tile w of a work list of 64-tube
+ * tiles of all of them.  The other tensors (DFT, n3 > 64) are launched one by
+ * one, as tsvdm_transform would.  Results equal tsvdm_transform's bit for bit
+ * where it too uses the direct product (n3 not a power of two, or DENSE); for
+ * a power-of-two n3 <= 64, where tsvdm_transform uses its FFT, they agree to
+ * rounding.
+ *
+ * Usage: size the workspace, create a plan (validation, one synchronous
+ * upload of the tensor descriptors and the work list into the workspace),
+ * then launch with tsvdm_transform_batched as often as needed (asynchronous;
+ * no allocation, no host-device copy: safe under stream capture).  The plan
+ * keeps the device pointers and M descriptors it was created with; the
+ * workspace must stay allocated and untouched while the plan is used. */
+typedef struct tsvdm_transform_plan_s tsvdm_transform_plan;
+
+/* Workspace bytes for the batch (host arrays M[nmat], in[nmat]; shapes and M
+ * kinds only).  0 if the arguments are invalid or nothing needs a table. */
+size_t tsvdm_transform_batched_workspace_size(int32_t nmat, const tsvdm_mdesc *M, const tsvdm_tensor *in);
+
+/* Validates every tensor (errors name the tensor index), builds the work
+ * list and uploads it into the caller's workspace (synchronous copy).  *plan
+ * is a host object released with tsvdm_transform_plan_destroy. */
+tsvdm_status tsvdm_transform_plan_create(int32_t nmat, const tsvdm_mdesc *M, int32_t direction,
+                                         const tsvdm_tensor *in, const tsvdm_tensor *out, void *workspace,
+                                         size_t workspace_bytes, tsvdm_transform_plan **plan);
+
+/* Launches the batch on `stream` (asynchronous). */
+tsvdm_status tsvdm_transform_batched(const tsvdm_transform_plan *plan, void *stream);
+
+/* Releases the host plan (the workspace stays the caller's). NULL is allowed. */
+void tsvdm_transform_plan_destroy(tsvdm_transform_plan *plan);
+
 /* Workspace bytes tsvdm_truncate needs for this input and options (only the
  * shapes are read: data and omega may be NULL).  0 if the arguments are invalid. */
 size_t tsvdm_truncate_workspace_size(const tsvdm_tensor *Xhat, const tsvdm_truncate_opts *opts);

@@ -121,6 +121,44 @@ class Truncator:
         return self.F
 
 
+class BatchedTransform:
+    """Mode-3 transforms of many tensors in few launches (tsvdm_transform_plan_*):
+    ins[i] is the input (a dense device buffer of shape (m, p, n3) or, with
+    views[i], any strided descriptor over it), outs[i] a dense output buffer,
+    M[i] = (kind, n3, dense M or None).  Creating the object uploads the work
+    list once; calling launches the batch asynchronously (safe to capture)."""
+
+    def __init__(self, ins: list, outs: list, shapes: list, kinds: list, direction: int = 1,
+                 Ms: list | None = None, views: list | None = None, device="cuda"):
+        self.keep = (ins, outs, Ms)
+        Ms = Ms if Ms is not None else [None] * len(ins)
+        self.md = [_mdesc(k, n3, M) for k, (m, p, n3), M in zip(kinds, shapes, Ms)]
+        def faces(kind, n3):  # (input faces, output faces), as for transform()
+            if kind != C.M_DFT:
+                return n3, n3
+            return (n3, n3 // 2 + 1) if direction > 0 else (n3 // 2 + 1, n3)
+
+        self.tin, self.tout = [], []
+        for i, (x, y, (m, p, n3), k) in enumerate(zip(ins, outs, shapes, kinds)):
+            fi, fo = faces(k, n3)
+            self.tin.append(views[i] if views is not None and views[i] is not None else
+                            C.dense_tensor(x.data_ptr(), m, p, fi, dtype_code(x)))
+            self.tout.append(C.dense_tensor(y.data_ptr(), m, p, fo, dtype_code(y)))
+        self.ws_bytes = C.tsvdm_transform_batched_workspace_size(self.md, self.tin)
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+        self.plan = C.tsvdm_transform_plan_create(self.md, direction, self.tin, self.tout, self.ws.data_ptr(),
+                                                  self.ws_bytes)
+
+    def __call__(self, stream=None):
+        C.tsvdm_transform_batched(self.plan, _stream(stream))
+
+    def __del__(self):
+        plan = getattr(self, "plan", None)
+        if plan:
+            C.tsvdm_transform_plan_destroy(plan)
+            self.plan = None
+
+
 class BatchedTruncator:
     """Facewise truncation of an uneven batch (tsvdm_batched_*): the tensors
     xhats[i] are dense FP32 (m_i, p_i, nf_i) device buffers with m_i <= 64.

@@ -46,6 +46,27 @@ struct View {
     }
 };
 
+// Batched direct transform: one descriptor per tensor and one work item per
+// tile of 64 tubes (device arrays in the plan's workspace).
+struct DirectDesc {
+    const void *in;
+    void *out;
+    View iv;
+    int64_t ntubes, mp;
+    const double *Md;  // dense M (device), or null for the DCT-II
+    int32_t N, dense;
+};
+struct DirectItem {
+    int32_t d, tile;
+};
+// tiles of one precision and one length class (N <= nmax), one launch
+struct TransformGroup {
+    bool dbl;
+    int nmax;
+    const DirectItem *items;
+    int64_t count;
+};
+
 inline View make_view(const tsvdm_tensor &t) {
     View v;
     v.m = t.m; v.p = t.p; v.n3 = t.n3;
@@ -72,6 +93,8 @@ tsvdm_status hip_check(hipError_t e, const char *what);
 // launchers implemented in the .hip files
 tsvdm_status launch_transform(const tsvdm_mdesc *M, int direction, const tsvdm_tensor *in,
                               tsvdm_tensor *out, hipStream_t s);
+tsvdm_status launch_direct_batched(const DirectDesc *desc, const TransformGroup &g, int direction,
+                                   hipStream_t s);
 size_t jacobi_workspace(int64_t m, int64_t p, int64_t nf, bool cplx);
 tsvdm_status launch_jacobi_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
                                     tsvdm_factors *F, void *ws, hipStream_t s);

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <cmath>
+#include <vector>
 
 #include "common.h"
 
@@ -56,6 +57,76 @@ static tsvdm_status check_tensor(const tsvdm_tensor *t, const char *name, bool n
     return TSVDM_OK;
 }
 
+// ---- batched transform plan (host object)
+struct tsvdm_transform_plan_s {
+    int32_t direction = 1;
+    const DirectDesc *desc = nullptr;
+    std::vector<TransformGroup> groups;  // batched direct launches
+    std::vector<int32_t> rest;           // tensors launched one by one
+    std::vector<tsvdm_mdesc> M;
+    std::vector<tsvdm_tensor> in, out;
+};
+
+static size_t al256h(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// group of tensor i in the batched direct launches (2*double + (N > 32)), or
+// -1 for a tensor launched by itself (DFT, N > 64) or an empty one
+static int tgroup(const tsvdm_mdesc &M, const tsvdm_tensor &in) {
+    if (M.kind == TSVDM_M_DFT || M.n3 > 64 || in.m * in.p == 0) return -1;
+    return 2 * (in.dtype == TSVDM_F64 ? 1 : 0) + (M.n3 > 32 ? 1 : 0);
+}
+
+// workspace layout: descriptors, then the work items of groups 0..3
+static size_t tplan_layout(int32_t nmat, const tsvdm_mdesc *M, const tsvdm_tensor *in, int64_t cnt[4],
+                           size_t off[5]) {
+    for (int g = 0; g < 4; ++g) cnt[g] = 0;
+    for (int32_t i = 0; i < nmat; ++i) {
+        const int g = tgroup(M[i], in[i]);
+        if (g >= 0) cnt[g] += (in[i].m * in[i].p + 63) / 64;
+    }
+    off[0] = al256h(sizeof(DirectDesc) * (size_t)nmat);
+    for (int g = 0; g < 4; ++g) off[g + 1] = off[g] + al256h(sizeof(DirectItem) * (size_t)cnt[g]);
+    return off[4];
+}
+
+static tsvdm_status check_transform(const tsvdm_mdesc *M, int32_t direction, const tsvdm_tensor *in,
+                                    const tsvdm_tensor *out, bool need_data = true) {
+    if (!M) FAIL(TSVDM_EINVAL, "M is NULL");
+    if (M->kind < TSVDM_M_DCT2 || M->kind > TSVDM_M_DENSE) FAIL(TSVDM_EINVAL, "unknown M kind %d", M->kind);
+    if (M->n3 < 1) FAIL(TSVDM_EINVAL, "M->n3 must be >= 1");
+    if (M->n3 > 1024) FAIL(TSVDM_EUNSUPPORTED, "transform length %lld > 1024", (long long)M->n3);
+    if (M->kind == TSVDM_M_DENSE && !M->M) FAIL(TSVDM_EINVAL, "dense M requires M->M");
+    if (direction != 1 && direction != -1) FAIL(TSVDM_EINVAL, "direction must be +1 or -1");
+    tsvdm_status st;
+    if ((st = check_tensor(in, "in", need_data)) != TSVDM_OK) return st;
+    if ((st = check_tensor(out, "out", need_data)) != TSVDM_OK) return st;
+    if (!is_dense(*out)) FAIL(TSVDM_EINVAL, "out must be dense (strides 1, m, m*p)");
+    if (in->m != out->m || in->p != out->p) FAIL(TSVDM_EINVAL, "in and out differ in m or p");
+    if (is_double(in->dtype) != is_double(out->dtype)) FAIL(TSVDM_EINVAL, "in and out differ in precision");
+    const int64_t n3 = M->n3, half = n3 / 2 + 1;
+    if (M->kind == TSVDM_M_DFT) {
+        if (direction > 0) {
+            if (!is_real(in->dtype) || !is_cplx(out->dtype))
+                FAIL(TSVDM_EINVAL, "forward DFT maps a real tensor to a complex one");
+            if (in->n3 != n3 || out->n3 != half)
+                FAIL(TSVDM_EINVAL, "forward DFT: in->n3 must be %lld and out->n3 %lld", (long long)n3,
+                     (long long)half);
+        } else {
+            if (!is_cplx(in->dtype) || !is_real(out->dtype))
+                FAIL(TSVDM_EINVAL, "inverse DFT maps a complex half spectrum to a real tensor");
+            if (in->n3 != half || out->n3 != n3)
+                FAIL(TSVDM_EINVAL, "inverse DFT: in->n3 must be %lld and out->n3 %lld", (long long)half,
+                     (long long)n3);
+        }
+    } else {
+        if (!is_real(in->dtype) || in->dtype != out->dtype)
+            FAIL(TSVDM_EINVAL, "DCT-II / dense M map real tensors to real tensors of the same type");
+        if (in->n3 != n3 || out->n3 != n3) FAIL(TSVDM_EINVAL, "tube length differs from M->n3");
+    }
+    if (need_data && in->data == out->data && in->m * in->p > 0) FAIL(TSVDM_EINVAL, "in and out must not alias");
+    return TSVDM_OK;
+}
+
 extern "C" {
 
 int32_t tsvdm_version(void) { return (1 << 16) | 0; }
@@ -100,42 +171,104 @@ tsvdm_status tsvdm_check_orthogonal(const double *M, int64_t n3, double tol) {
 
 tsvdm_status tsvdm_transform(const tsvdm_mdesc *M, int32_t direction, const tsvdm_tensor *in,
                              tsvdm_tensor *out, void *stream) {
-    if (!M) FAIL(TSVDM_EINVAL, "M is NULL");
-    if (M->kind < TSVDM_M_DCT2 || M->kind > TSVDM_M_DENSE) FAIL(TSVDM_EINVAL, "unknown M kind %d", M->kind);
-    if (M->n3 < 1) FAIL(TSVDM_EINVAL, "M->n3 must be >= 1");
-    if (M->n3 > 1024) FAIL(TSVDM_EUNSUPPORTED, "transform length %lld > 1024", (long long)M->n3);
-    if (M->kind == TSVDM_M_DENSE && !M->M) FAIL(TSVDM_EINVAL, "dense M requires M->M");
-    if (direction != 1 && direction != -1) FAIL(TSVDM_EINVAL, "direction must be +1 or -1");
-    tsvdm_status st;
-    if ((st = check_tensor(in, "in")) != TSVDM_OK) return st;
-    if ((st = check_tensor(out, "out")) != TSVDM_OK) return st;
-    if (!is_dense(*out)) FAIL(TSVDM_EINVAL, "out must be dense (strides 1, m, m*p)");
-    if (in->m != out->m || in->p != out->p) FAIL(TSVDM_EINVAL, "in and out differ in m or p");
-    if (is_double(in->dtype) != is_double(out->dtype)) FAIL(TSVDM_EINVAL, "in and out differ in precision");
-    const int64_t n3 = M->n3, half = n3 / 2 + 1;
-    if (M->kind == TSVDM_M_DFT) {
-        if (direction > 0) {
-            if (!is_real(in->dtype) || !is_cplx(out->dtype))
-                FAIL(TSVDM_EINVAL, "forward DFT maps a real tensor to a complex one");
-            if (in->n3 != n3 || out->n3 != half)
-                FAIL(TSVDM_EINVAL, "forward DFT: in->n3 must be %lld and out->n3 %lld", (long long)n3,
-                     (long long)half);
-        } else {
-            if (!is_cplx(in->dtype) || !is_real(out->dtype))
-                FAIL(TSVDM_EINVAL, "inverse DFT maps a complex half spectrum to a real tensor");
-            if (in->n3 != half || out->n3 != n3)
-                FAIL(TSVDM_EINVAL, "inverse DFT: in->n3 must be %lld and out->n3 %lld", (long long)half,
-                     (long long)n3);
-        }
-    } else {
-        if (!is_real(in->dtype) || in->dtype != out->dtype)
-            FAIL(TSVDM_EINVAL, "DCT-II / dense M map real tensors to real tensors of the same type");
-        if (in->n3 != n3 || out->n3 != n3) FAIL(TSVDM_EINVAL, "tube length differs from M->n3");
-    }
-    if (in->data == out->data && in->m * in->p > 0) FAIL(TSVDM_EINVAL, "in and out must not alias");
+    tsvdm_status st = check_transform(M, direction, in, out);
+    if (st != TSVDM_OK) return st;
     if (in->m * in->p == 0) return TSVDM_OK;
     return launch_transform(M, direction, in, out, (hipStream_t)stream);
 }
+
+size_t tsvdm_transform_batched_workspace_size(int32_t nmat, const tsvdm_mdesc *M, const tsvdm_tensor *in) {
+    if (nmat < 0 || (nmat > 0 && (!M || !in))) return 0;
+    for (int32_t i = 0; i < nmat; ++i)
+        if (M[i].kind < TSVDM_M_DCT2 || M[i].kind > TSVDM_M_DENSE || M[i].n3 < 1 || in[i].m < 0 || in[i].p < 0)
+            return 0;
+    int64_t cnt[4];
+    size_t off[5];
+    return tplan_layout(nmat, M, in, cnt, off);
+}
+
+tsvdm_status tsvdm_transform_plan_create(int32_t nmat, const tsvdm_mdesc *M, int32_t direction,
+                                         const tsvdm_tensor *in, const tsvdm_tensor *out, void *workspace,
+                                         size_t workspace_bytes, tsvdm_transform_plan **plan) {
+    if (!plan) FAIL(TSVDM_EINVAL, "plan is NULL");
+    *plan = nullptr;
+    if (nmat < 0) FAIL(TSVDM_EINVAL, "nmat must be >= 0");
+    if (nmat > 0 && (!M || !in || !out)) FAIL(TSVDM_EINVAL, "M, in and out must not be NULL");
+    for (int32_t i = 0; i < nmat; ++i) {
+        tsvdm_status st = check_transform(&M[i], direction, &in[i], &out[i]);
+        if (st != TSVDM_OK) {
+            char msg[512];
+            snprintf(msg, sizeof(msg), "tensor %d: %s", (int)i, tsvdm_last_error());
+            FAIL(st, "%s", msg);
+        }
+        if ((in[i].m * in[i].p + 63) / 64 > INT32_MAX) FAIL(TSVDM_EUNSUPPORTED, "tensor %d has too many tubes", (int)i);
+    }
+    int64_t cnt[4];
+    size_t off[5];
+    const size_t need = tplan_layout(nmat, M, in, cnt, off);
+    if (need > 0 && !workspace) FAIL(TSVDM_EWORKSPACE, "workspace is NULL");
+    if (workspace_bytes < need)
+        FAIL(TSVDM_EWORKSPACE, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
+    std::vector<unsigned char> h(need, 0);
+    DirectDesc *desc = reinterpret_cast<DirectDesc *>(h.data());
+    int64_t fill[4] = {0, 0, 0, 0};
+    auto *plan_obj = new tsvdm_transform_plan_s;
+    plan_obj->direction = direction;
+    for (int32_t i = 0; i < nmat; ++i) {
+        const int g = tgroup(M[i], in[i]);
+        if (g < 0) {
+            if (in[i].m * in[i].p > 0) plan_obj->rest.push_back(i);
+            continue;
+        }
+        DirectDesc &d = desc[i];
+        d.in = in[i].data;
+        d.out = out[i].data;
+        d.iv = make_view(in[i]);
+        d.ntubes = in[i].m * in[i].p;
+        d.mp = d.ntubes;
+        d.Md = M[i].kind == TSVDM_M_DENSE ? M[i].M : nullptr;
+        d.N = (int32_t)M[i].n3;
+        d.dense = M[i].kind == TSVDM_M_DENSE ? 1 : 0;
+        DirectItem *items = reinterpret_cast<DirectItem *>(h.data() + off[g]);
+        const int64_t nt = (d.ntubes + 63) / 64;
+        for (int64_t t = 0; t < nt; ++t) items[fill[g]++] = DirectItem{i, (int32_t)t};
+    }
+    if (need > 0) {
+        const hipError_t e = hipMemcpy(workspace, h.data(), need, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            delete plan_obj;
+            return hip_check(e, "hipMemcpy(transform plan)");
+        }
+    }
+    unsigned char *ws = reinterpret_cast<unsigned char *>(workspace);
+    plan_obj->desc = reinterpret_cast<const DirectDesc *>(ws);
+    for (int g = 0; g < 4; ++g)
+        if (cnt[g] > 0)
+            plan_obj->groups.push_back(
+                TransformGroup{g >= 2, (g & 1) ? 64 : 32, reinterpret_cast<const DirectItem *>(ws + off[g]), cnt[g]});
+    plan_obj->M.assign(M, M + nmat);
+    plan_obj->in.assign(in, in + nmat);
+    plan_obj->out.assign(out, out + nmat);
+    *plan = plan_obj;
+    return TSVDM_OK;
+}
+
+tsvdm_status tsvdm_transform_batched(const tsvdm_transform_plan *plan, void *stream) {
+    if (!plan) FAIL(TSVDM_EINVAL, "plan is NULL");
+    const hipStream_t s = (hipStream_t)stream;
+    for (const TransformGroup &g : plan->groups) {
+        tsvdm_status st = launch_direct_batched(plan->desc, g, plan->direction, s);
+        if (st != TSVDM_OK) return st;
+    }
+    for (int32_t i : plan->rest) {
+        tsvdm_tensor o = plan->out[i];
+        tsvdm_status st = launch_transform(&plan->M[i], plan->direction, &plan->in[i], &o, s);
+        if (st != TSVDM_OK) return st;
+    }
+    return TSVDM_OK;
+}
+
+void tsvdm_transform_plan_destroy(tsvdm_transform_plan *plan) { delete plan; }
 
 // need_data = false for the workspace query, which looks at shapes only
 static tsvdm_status check_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,

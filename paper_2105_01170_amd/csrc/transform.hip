@@ -349,17 +349,18 @@ __global__ __launch_bounds__(NT) void k_dense_tubes(const void *__restrict__ in,
 // contiguous) read from LDS by broadcast.  DCT-II coefficients come from a
 // table of cos(pi j / (2 n3)), j < 4 n3.  FP32 data accumulates in FP32 (at
 // most 64 terms), FP64 data in FP64.  INV: M^T.
-template <typename T, int NMAX, bool INV, bool DENSE>
-__global__ __launch_bounds__(NT) void k_direct_small(const T *__restrict__ in, View iv,
-                                                     T *__restrict__ out, int64_t ntubes,
-                                                     int64_t mp, int N, const double *__restrict__ Md) {
+// One tile of 64 tubes (i0 .. i0+63) of the direct product: the body of
+// k_direct_small and of its batched form.  dense: M is the explicit Md.
+template <typename T, int NMAX, bool INV>
+__device__ __forceinline__ void direct_tile(const T *__restrict__ in, const View &iv, T *__restrict__ out,
+                                            int64_t ntubes, int64_t mp, int N, const double *__restrict__ Md,
+                                            bool dense, int64_t i0) {
     constexpr int TB = 64, G = NT / TB;
     constexpr int LDM = NMAX + 4;  // row pitch (keeps 16-byte alignment of rows)
     __shared__ __align__(16) T Ms[NMAX * LDM];
     __shared__ T xs[NMAX * TB];
     __shared__ double ctab[4 * NMAX];
     const int tid = threadIdx.x, u = tid % TB, g = tid / TB;
-    const int64_t i0 = (int64_t)blockIdx.x * TB;
     // tile loads first, so that they are in flight while M is built; thread
     // (u, g) stages time steps g, g+4, ... of tube u
     {
@@ -380,7 +381,7 @@ __global__ __launch_bounds__(NT) void k_direct_small(const T *__restrict__ in, V
             xs[t * TB + u] = (okl && t < N) ? v[q] : T(0);
         }
     }
-    if (!DENSE)
+    if (!dense)
         for (int j = tid; j < 4 * N; j += NT) ctab[j] = cospi((double)j / (2.0 * N));
     for (int e = tid; e < NMAX * LDM; e += NT) Ms[e] = T(0);
     __syncthreads();
@@ -389,7 +390,7 @@ __global__ __launch_bounds__(NT) void k_direct_small(const T *__restrict__ in, V
     // (2t+1) f mod 4N advances by a fixed step along the row (no divisions).
     if (u < N) {
         const int o = u, fourN = 4 * N;
-        if (DENSE) {
+        if (dense) {
             for (int j = g; j < N; j += G) Ms[o * LDM + j] = (T)(INV ? Md[j + (int64_t)N * o] : Md[o + (int64_t)N * j]);
         } else {
             const double a0c = sqrt(1.0 / N), a1c = sqrt(2.0 / N);
@@ -424,6 +425,25 @@ __global__ __launch_bounds__(NT) void k_direct_small(const T *__restrict__ in, V
         }
         if (ok) out[i + mp * o] = (a0 + a1) + (a2 + a3);
     }
+}
+
+template <typename T, int NMAX, bool INV, bool DENSE>
+__global__ __launch_bounds__(NT) void k_direct_small(const T *__restrict__ in, View iv,
+                                                     T *__restrict__ out, int64_t ntubes,
+                                                     int64_t mp, int N, const double *__restrict__ Md) {
+    direct_tile<T, NMAX, INV>(in, iv, out, ntubes, mp, N, Md, DENSE, (int64_t)blockIdx.x * 64);
+}
+
+// Batched direct product: workgroup w transforms tile items[w].tile of the
+// tensor described by desc[items[w].d] (tensors of one precision and one
+// length class, up to NMAX).
+template <typename T, int NMAX, bool INV>
+__global__ __launch_bounds__(NT) void k_direct_batched(const DirectDesc *__restrict__ desc,
+                                                       const DirectItem *__restrict__ items) {
+    const DirectItem it = items[blockIdx.x];
+    const DirectDesc &d = desc[it.d];
+    direct_tile<T, NMAX, INV>(reinterpret_cast<const T *>(d.in), d.iv, reinterpret_cast<T *>(d.out), d.ntubes,
+                              d.mp, d.N, d.Md, d.dense != 0, (int64_t)it.tile * 64);
 }
 
 template <typename K>
@@ -536,6 +556,25 @@ tsvdm_status run_dense(int kind, int dir, const tsvdm_mdesc *M, const tsvdm_tens
 }  // namespace
 
 namespace tsvdm {
+
+tsvdm_status launch_direct_batched(const DirectDesc *desc, const TransformGroup &g, int direction,
+                                   hipStream_t s) {
+    if (g.count == 0) return TSVDM_OK;
+    const dim3 grid((unsigned)g.count);
+#define TSVDM_DB(T, NM, INV)                                                                         \
+    TSVDM_LAUNCH("transform_direct_batched", (k_direct_batched<T, NM, INV>), grid, dim3(NT), 0, s, desc, \
+                 g.items)
+    if (g.dbl) {
+        if (g.nmax == 32) { if (direction > 0) TSVDM_DB(double, 32, false); else TSVDM_DB(double, 32, true); }
+        else { if (direction > 0) TSVDM_DB(double, 64, false); else TSVDM_DB(double, 64, true); }
+    } else {
+        if (g.nmax == 32) { if (direction > 0) TSVDM_DB(float, 32, false); else TSVDM_DB(float, 32, true); }
+        else { if (direction > 0) TSVDM_DB(float, 64, false); else TSVDM_DB(float, 64, true); }
+    }
+#undef TSVDM_DB
+    TSVDM_LAUNCH_CHECK("k_direct_batched");
+    return TSVDM_OK;
+}
 
 tsvdm_status launch_transform(const tsvdm_mdesc *M, int direction, const tsvdm_tensor *in,
                               tsvdm_tensor *out, hipStream_t s) {

@@ -58,7 +58,9 @@ EXPORTS = ["tsvdm_version", "tsvdm_last_error", "tsvdm_tensor_from_blockmat",
            "tsvdm_batched_config", "tsvdm_batched_plan_destroy", "tsvdm_mlp_nparams",
            "tsvdm_mlp_forward", "tsvdm_mlp_train_workspace_size", "tsvdm_mlp_gradient",
            "tsvdm_mlp_train_step", "tsvdm_f32_to_f16", "tsvdm_rank_features_workspace_size",
-           "tsvdm_rank_features", "tsvdm_truncate_learned_workspace_size", "tsvdm_truncate_learned"]
+           "tsvdm_rank_features", "tsvdm_truncate_learned_workspace_size", "tsvdm_truncate_learned",
+           "tsvdm_transform_batched_workspace_size", "tsvdm_transform_plan_create",
+           "tsvdm_transform_batched", "tsvdm_transform_plan_destroy"]
 
 _LIB = None
 
@@ -83,6 +85,15 @@ def lib():
         L.tsvdm_check_orthogonal.argtypes = [vp, i64, ctypes.c_double]
         L.tsvdm_transform.restype = i32
         L.tsvdm_transform.argtypes = [P(TsvdmMdesc), i32, P(TsvdmTensor), P(TsvdmTensor), vp]
+        L.tsvdm_transform_batched_workspace_size.restype = sz
+        L.tsvdm_transform_batched_workspace_size.argtypes = [i32, P(TsvdmMdesc), P(TsvdmTensor)]
+        L.tsvdm_transform_plan_create.restype = i32
+        L.tsvdm_transform_plan_create.argtypes = [i32, P(TsvdmMdesc), i32, P(TsvdmTensor), P(TsvdmTensor), vp,
+                                                  sz, P(vp)]
+        L.tsvdm_transform_batched.restype = i32
+        L.tsvdm_transform_batched.argtypes = [vp, vp]
+        L.tsvdm_transform_plan_destroy.restype = None
+        L.tsvdm_transform_plan_destroy.argtypes = [vp]
         L.tsvdm_truncate_workspace_size.restype = sz
         L.tsvdm_truncate_workspace_size.argtypes = [P(TsvdmTensor), P(TsvdmTruncateOpts)]
         L.tsvdm_truncate.restype = i32
@@ -200,6 +211,33 @@ def _array(ctype, items):
     for i, it in enumerate(items):
         arr[i] = it
     return arr
+
+
+def tsvdm_transform_batched_workspace_size(Ms: list, ins: list) -> int:
+    if len(Ms) != len(ins):
+        raise ValueError("one M descriptor per tensor")
+    return lib().tsvdm_transform_batched_workspace_size(len(ins), _array(TsvdmMdesc, Ms),
+                                                        _array(TsvdmTensor, ins))
+
+
+def tsvdm_transform_plan_create(Ms: list, direction: int, ins: list, outs: list, ws_ptr: int,
+                                ws_bytes: int) -> int:
+    """Returns the opaque host plan handle (an address)."""
+    if not (len(Ms) == len(ins) == len(outs)):
+        raise ValueError("one M descriptor and one output per tensor")
+    h = ctypes.c_void_p()
+    _check(lib().tsvdm_transform_plan_create(len(ins), _array(TsvdmMdesc, Ms), direction,
+                                             _array(TsvdmTensor, ins), _array(TsvdmTensor, outs), ws_ptr,
+                                             ws_bytes, ctypes.byref(h)))
+    return h.value
+
+
+def tsvdm_transform_batched(plan: int, stream: int = 0):
+    _check(lib().tsvdm_transform_batched(plan, stream))
+
+
+def tsvdm_transform_plan_destroy(plan: int):
+    lib().tsvdm_transform_plan_destroy(plan)
 
 
 def tsvdm_batched_workspace_size(Xs: list) -> int:

@@ -227,3 +227,34 @@ def test_batched_validation_and_workspace():
     with pytest.raises(C.TsvdmError):
         C.tsvdm_truncate_batched(0, 0)
     C.tsvdm_batched_plan_destroy(0)
+
+
+def test_transform_batched_validation_and_workspace():
+    """Batched transform plans: workspace sizing, and argument errors (naming
+    the tensor) before any device work."""
+    Ms = [C.mdesc(C.M_DCT2, 12), C.mdesc(C.M_DCT2, 45), C.mdesc(C.M_DFT, 8), C.mdesc(C.M_DCT2, 100)]
+    ins = [_t(5, 7, 12, C.F32, 0x1000), _t(9, 14, 45, C.F32, 0x2000), _t(4, 5, 8, C.F32, 0x3000),
+           _t(3, 4, 100, C.F32, 0x4000)]
+    outs = [_t(5, 7, 12, C.F32, 0x5000), _t(9, 14, 45, C.F32, 0x6000), _t(4, 5, 5, C.C64, 0x7000),
+            _t(3, 4, 100, C.F32, 0x8000)]
+    ws = C.tsvdm_transform_batched_workspace_size(Ms, ins)
+    # descriptors of all four tensors, then work items (tensor, tile): one tile
+    # of 35 tubes (n3 <= 32 class) and two of 126 tubes (n3 <= 64 class)
+    assert ws >= 256 + 2 * 256
+    with pytest.raises(C.TsvdmError) as e:
+        C.tsvdm_transform_plan_create(Ms, 1, ins, outs, 0x9000, ws - 1)
+    assert e.value.status == C.EWORKSPACE
+    bad = list(outs)
+    bad[1] = _t(9, 14, 45, C.F64, 0x6000)  # precision differs from the input
+    with pytest.raises(C.TsvdmError) as e:
+        C.tsvdm_transform_plan_create(Ms, 1, ins, bad, 0x9000, ws)
+    assert e.value.status == C.EINVAL
+    assert "tensor 1" in C.tsvdm_last_error()
+    with pytest.raises(C.TsvdmError) as e:
+        C.tsvdm_transform_plan_create(Ms, 2, ins, outs, 0x9000, ws)  # direction
+    assert e.value.status == C.EINVAL
+    assert C.tsvdm_transform_batched_workspace_size([C.mdesc(7, 8)], ins[:1]) == 0
+    # an empty batch needs no workspace and launches nothing
+    assert C.tsvdm_transform_batched_workspace_size([], []) == 0
+    plan = C.tsvdm_transform_plan_create([], 1, [], [], 0, 0)
+    C.tsvdm_transform_plan_destroy(plan)

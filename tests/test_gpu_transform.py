@@ -95,3 +95,82 @@ def test_empty_tensor_is_noop():
     C.tsvdm_transform(C.mdesc(C.M_DCT2, 8), 1, t_in, t_out, 0)
     torch.cuda.synchronize()
     assert out.item() == 7.0
+
+
+@pytest.mark.parametrize("direction", [1, -1])
+def test_batched_transform_matches_single_and_oracle(direction):
+    """tsvdm_transform_batched over an uneven set (lengths in both direct
+    classes, FP32 and FP64, a dense M, a strided T_E view, and tensors it
+    launches one by one: DFT and n3 > 64) against tsvdm_transform and the
+    oracle; replays from a captured graph give the same bits."""
+    g = np.random.default_rng(7)
+    Q, _ = np.linalg.qr(g.standard_normal((20, 20)))
+    specs = [  # (m, p, n3, kind, dtype)
+        (5, 7, 12, C.M_DCT2, np.float32), (33, 17, 31, C.M_DCT2, np.float32),
+        (9, 14, 45, C.M_DCT2, np.float32), (3, 300, 63, C.M_DCT2, np.float64),
+        (16, 8, 64, C.M_DCT2, np.float32), (6, 5, 20, C.M_DENSE, np.float64),
+        (4, 5, 8, C.M_DFT, np.float32), (17, 9, 100, C.M_DCT2, np.float32),
+        (2, 3, 1, C.M_DCT2, np.float32)]
+    xs, outs, shapes, kinds, Ms, refs, views = [], [], [], [], [], [], []
+    for (m, p, n3, kind, dt) in specs:
+        if kind == C.M_DFT and direction < 0:
+            Xh = (g.standard_normal((m, p, n3 // 2 + 1)) + 1j * g.standard_normal((m, p, n3 // 2 + 1)))
+            X = np.asfortranarray(Xh.astype(np.complex64))
+        else:
+            X = np.asfortranarray(g.standard_normal((m, p, n3))).astype(dt)
+        Md = to_dev(np.asfortranarray(Q), np.float64) if kind == C.M_DENSE else None
+        xd = to_dev(X)
+        single = api.transform(xd, m, p, n3, kind, direction, M=Md)
+        xs.append(xd)
+        outs.append(torch.empty_like(single))
+        shapes.append((m, p, n3))
+        kinds.append(kind)
+        Ms.append(Md)
+        refs.append(single)
+        views.append(None)
+    # a strided T_E view as one more input (forward and inverse read it the same way)
+    ell, q, m, n = 3, 5, 7, 16
+    A = np.asfortranarray(g.standard_normal((ell * m, q * n))).astype(np.float32)
+    Ad = to_dev(A)
+    view = C.tsvdm_tensor_from_blockmat(Ad.data_ptr(), ell * m, C.F32, ell, q, m, n)
+    xs.append(Ad)
+    single = api.transform(Ad, m, ell * q, n, C.M_DCT2, direction, view=view)
+    outs.append(torch.empty_like(single))
+    shapes.append((m, ell * q, n))
+    kinds.append(C.M_DCT2)
+    Ms.append(None)
+    refs.append(single)
+    views.append(view)
+    bt = api.BatchedTransform(xs, outs, shapes, kinds, direction, Ms=Ms, views=views)
+    bt()
+    torch.cuda.synchronize()
+    first = [o.clone() for o in outs]
+    for i, (o, r, (m, p, n3), kind) in enumerate(zip(outs, refs, shapes, kinds)):
+        pow2 = n3 >= 2 and (n3 & (n3 - 1)) == 0
+        if kind != C.M_DFT and n3 <= 64 and pow2:
+            # the batch uses the direct product where tsvdm_transform uses its FFT
+            assert relerr(o.cpu().numpy(), r.cpu().numpy()) < (3e-6 if o.dtype == torch.float32 else 1e-12), i
+        else:
+            assert torch.equal(o, r), i
+    # against the oracle's explicit product
+    for i, ((m, p, n3, kind, dt), o) in enumerate(zip(specs, outs)):
+        x = xs[i].cpu().numpy()
+        if kind == C.M_DFT:
+            continue  # covered by test_forward_and_inverse
+        M = Q if kind == C.M_DENSE else oracle.dct2_matrix(n3)
+        X = x.reshape((m, p, n3), order="F").astype(np.float64)
+        ref = oracle.mode3(X, M if direction > 0 else M.T)
+        assert relerr(from_dev(o, ref.shape), ref) < TOL[dt], i
+    # replays of a captured graph reproduce the eager result
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=s):
+        bt(stream=s)
+    for _ in range(3):
+        for o in outs:
+            o.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        for o, f in zip(outs, first):
+            assert torch.equal(o, f)
