@@ -357,8 +357,9 @@ __device__ __forceinline__ void direct_tile(const T *__restrict__ in, const View
                                             bool dense, int64_t i0) {
     constexpr int TB = 64, G = NT / TB;
     constexpr int LDM = NMAX + 4;  // row pitch (keeps 16-byte alignment of rows)
+    constexpr int TBP = TB + 4;    // tile row pitch: the MFMA reads of 4 rows hit different banks
     __shared__ __align__(16) T Ms[NMAX * LDM];
-    __shared__ T xs[NMAX * TB];
+    __shared__ T xs[NMAX * TBP];
     __shared__ double ctab[4 * NMAX];
     const int tid = threadIdx.x, u = tid % TB, g = tid / TB;
     // tile loads first, so that they are in flight while M is built; thread
@@ -378,7 +379,7 @@ __device__ __forceinline__ void direct_tile(const T *__restrict__ in, const View
 #pragma unroll
         for (int q = 0; q < NMAX / G; ++q) {
             const int t = g + G * q;
-            xs[t * TB + u] = (okl && t < N) ? v[q] : T(0);
+            xs[t * TBP + u] = (okl && t < N) ? v[q] : T(0);
         }
     }
     if (!dense)
@@ -406,24 +407,42 @@ __device__ __forceinline__ void direct_tile(const T *__restrict__ in, const View
         }
     }
     __syncthreads();
-    T x[NMAX];
+    // out[o][u] = sum_t M[o][t] x[t][u] for the tile: a 16x16x4 MFMA GEMM
+    // (FP32 or FP64) on the LDS operands; wavefront w makes tubes 16w..16w+15
+    // for every 16-row block of outputs below N (entries past N are zero in
+    // both operands)
+    constexpr int NTI = NMAX / 16;
+    const int wave = tid >> 6, lane = tid & 63, kl = lane >> 4, l16 = lane & 15;
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    v4 acc[NTI];
 #pragma unroll
-    for (int t = 0; t < NMAX; ++t) x[t] = xs[t * TB + u];
-    const int64_t i = i0 + u;
-    const bool ok = i < ntubes;
-    for (int o = g; o < N; o += G) {
-        const T *row = Ms + o * LDM;
-        T a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    for (int ti = 0; ti < NTI; ++ti) acc[ti] = v4{0, 0, 0, 0};
+    const int ub = 16 * wave + l16;  // tube of the B operand and of the result
 #pragma unroll
-        for (int t = 0; t < NMAX; t += 4) {
-            if (t < N) {  // uniform; entries past N are zero in both operands
-                a0 += row[t] * x[t];
-                a1 += row[t + 1] * x[t + 1];
-                a2 += row[t + 2] * x[t + 2];
-                a3 += row[t + 3] * x[t + 3];
-            }
+    for (int kk = 0; kk < NMAX / 4; ++kk) {
+        if (4 * kk >= N) break;
+        const T bx = xs[(4 * kk + kl) * TBP + ub];
+#pragma unroll
+        for (int ti = 0; ti < NTI; ++ti) {
+            if (16 * ti >= N) break;
+            const T am = Ms[(16 * ti + l16) * LDM + 4 * kk + kl];
+            if constexpr (sizeof(T) == 4)
+                acc[ti] = __builtin_amdgcn_mfma_f32_16x16x4f32(am, bx, acc[ti], 0, 0, 0);
+            else
+                acc[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, bx, acc[ti], 0, 0, 0);
         }
-        if (ok) out[i + mp * o] = (a0 + a1) + (a2 + a3);
+    }
+    // result layout: FP32 row 4*(lane/16) + v, FP64 row lane/16 + 4v; column lane%16
+    const int64_t i = i0 + ub;
+    const bool ok = i < ntubes;
+#pragma unroll
+    for (int ti = 0; ti < NTI; ++ti) {
+        if (16 * ti >= N) break;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int o = 16 * ti + (sizeof(T) == 4 ? 4 * kl + v : kl + 4 * v);
+            if (ok && o < N) out[i + mp * o] = acc[ti][v];
+        }
     }
 }
 
