@@ -171,8 +171,8 @@ tsvdm_status tsvdm_transform(const tsvdm_mdesc *M, int32_t direction, const tsvd
  * (M[i], in[i], out[i]) as for tsvdm_transform, one direction for all.  The
  * tensors whose M is DCT2 or DENSE with n3 <= 64 are transformed by the
  * direct per-tube product in one launch per precision and length class
- * (n3 <= 32, n3 <= 64): workgroup w takes tile w of a work list of 64-tube
- * tiles of all of them.  The other tensors (DFT, n3 > 64) are launched one by
+ * (n3 in 1..16, 17..32, 33..48, 49..64): workgroup w takes chunk w of a work
+ * list of 512-tube chunks of all of them.  The other tensors (DFT, n3 > 64) are launched one by
  * one, as tsvdm_transform would.  Results equal tsvdm_transform's bit for bit
  * where it too uses the direct product (n3 not a power of two, or DENSE); for
  * a power-of-two n3 <= 64, where tsvdm_transform uses its FFT, they agree to

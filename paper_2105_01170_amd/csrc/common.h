@@ -46,8 +46,40 @@ struct View {
     }
 };
 
+// Direct (matrix-core) transform of tubes of length n3 <= 64: one workgroup
+// per chunk of kDirectChunk consecutive tubes; the length class is
+// direct_class(n3), the multiple of 16 at or above n3.
+constexpr int kDirectChunk = 512;
+__host__ __device__ constexpr int direct_class(int64_t n3) { return (int)(16 * ((n3 + 15) / 16)); }
+
+// Byte spans of the input view and of the dense output of the direct
+// transform, false unless both, counted up to direct_class(n3) time steps and
+// output faces, are below 2^31 with non-negative strides (the direct kernels
+// address both through buffer resources with 32-bit offsets).
+inline bool direct_span(const tsvdm_tensor &in, int64_t n3, size_t esz, uint32_t *in_bytes,
+                        uint32_t *out_bytes) {
+    const int64_t lim = (int64_t)1 << 31;
+    if (in.m <= 0 || in.p <= 0 || n3 <= 0) return false;
+    if (in.s_a < 0 || in.s_b < 0 || in.s_t < 0 || in.s_bk < 0) return false;
+    const int64_t nm = direct_class(n3);
+    // largest element offset of a tube start, then of its last (padded) step
+    int64_t base = (in.m - 1) * in.s_a;
+    if (in.bsplit > 0) {
+        const int64_t bs = in.bsplit < in.p ? in.bsplit : in.p;
+        base += (bs - 1) * in.s_b + ((in.p - 1) / in.bsplit) * in.s_bk;
+    } else {
+        base += (in.p - 1) * in.s_b;
+    }
+    const double in_b = ((double)base + (double)nm * (double)in.s_t + 1.0) * (double)esz;
+    const double out_b = (double)in.m * (double)in.p * (double)nm * (double)esz;
+    if (!(in_b < (double)lim) || !(out_b < (double)lim)) return false;
+    *in_bytes = (uint32_t)(((double)base + (double)(n3 - 1) * (double)in.s_t + 1.0) * (double)esz);
+    *out_bytes = (uint32_t)((double)in.m * (double)in.p * (double)n3 * (double)esz);
+    return true;
+}
+
 // Batched direct transform: one descriptor per tensor and one work item per
-// tile of 64 tubes (device arrays in the plan's workspace).
+// chunk of kDirectChunk tubes (device arrays in the plan's workspace).
 struct DirectDesc {
     const void *in;
     void *out;
@@ -55,11 +87,12 @@ struct DirectDesc {
     int64_t ntubes, mp;
     const double *Md;  // dense M (device), or null for the DCT-II
     int32_t N, dense;
+    uint32_t in_bytes, out_bytes;  // direct_span
 };
 struct DirectItem {
-    int32_t d, tile;
+    int32_t d, chunk;
 };
-// tiles of one precision and one length class (N <= nmax), one launch
+// chunks of one precision and one length class (nmax = direct_class(N)), one launch
 struct TransformGroup {
     bool dbl;
     int nmax;

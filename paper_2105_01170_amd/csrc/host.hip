@@ -69,24 +69,31 @@ struct tsvdm_transform_plan_s {
 
 static size_t al256h(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// group of tensor i in the batched direct launches (2*double + (N > 32)), or
-// -1 for a tensor launched by itself (DFT, N > 64) or an empty one
+// group of tensor i in the batched direct launches (4*double + length class
+// index, classes of 16), or -1 for a tensor launched by itself (DFT, N > 64,
+// a view or output spanning 2 GiB or more, negative strides) or an empty one
+constexpr int kTGroups = 8;
 static int tgroup(const tsvdm_mdesc &M, const tsvdm_tensor &in) {
     if (M.kind == TSVDM_M_DFT || M.n3 > 64 || in.m * in.p == 0) return -1;
-    return 2 * (in.dtype == TSVDM_F64 ? 1 : 0) + (M.n3 > 32 ? 1 : 0);
+    const bool dbl = in.dtype == TSVDM_F64;
+    uint32_t ib = 0, ob = 0;
+    if (!direct_span(in, M.n3, dbl ? 8 : 4, &ib, &ob)) return -1;
+    return 4 * (dbl ? 1 : 0) + direct_class(M.n3) / 16 - 1;
 }
 
-// workspace layout: descriptors, then the work items of groups 0..3
-static size_t tplan_layout(int32_t nmat, const tsvdm_mdesc *M, const tsvdm_tensor *in, int64_t cnt[4],
-                           size_t off[5]) {
-    for (int g = 0; g < 4; ++g) cnt[g] = 0;
+static int64_t tchunks(const tsvdm_tensor &in) { return (in.m * in.p + kDirectChunk - 1) / kDirectChunk; }
+
+// workspace layout: descriptors, then the work items of groups 0..kTGroups-1
+static size_t tplan_layout(int32_t nmat, const tsvdm_mdesc *M, const tsvdm_tensor *in,
+                           int64_t cnt[kTGroups], size_t off[kTGroups + 1]) {
+    for (int g = 0; g < kTGroups; ++g) cnt[g] = 0;
     for (int32_t i = 0; i < nmat; ++i) {
         const int g = tgroup(M[i], in[i]);
-        if (g >= 0) cnt[g] += (in[i].m * in[i].p + 63) / 64;
+        if (g >= 0) cnt[g] += tchunks(in[i]);
     }
     off[0] = al256h(sizeof(DirectDesc) * (size_t)nmat);
-    for (int g = 0; g < 4; ++g) off[g + 1] = off[g] + al256h(sizeof(DirectItem) * (size_t)cnt[g]);
-    return off[4];
+    for (int g = 0; g < kTGroups; ++g) off[g + 1] = off[g] + al256h(sizeof(DirectItem) * (size_t)cnt[g]);
+    return off[kTGroups];
 }
 
 static tsvdm_status check_transform(const tsvdm_mdesc *M, int32_t direction, const tsvdm_tensor *in,
@@ -182,8 +189,8 @@ size_t tsvdm_transform_batched_workspace_size(int32_t nmat, const tsvdm_mdesc *M
     for (int32_t i = 0; i < nmat; ++i)
         if (M[i].kind < TSVDM_M_DCT2 || M[i].kind > TSVDM_M_DENSE || M[i].n3 < 1 || in[i].m < 0 || in[i].p < 0)
             return 0;
-    int64_t cnt[4];
-    size_t off[5];
+    int64_t cnt[kTGroups];
+    size_t off[kTGroups + 1];
     return tplan_layout(nmat, M, in, cnt, off);
 }
 
@@ -201,17 +208,17 @@ tsvdm_status tsvdm_transform_plan_create(int32_t nmat, const tsvdm_mdesc *M, int
             snprintf(msg, sizeof(msg), "tensor %d: %s", (int)i, tsvdm_last_error());
             FAIL(st, "%s", msg);
         }
-        if ((in[i].m * in[i].p + 63) / 64 > INT32_MAX) FAIL(TSVDM_EUNSUPPORTED, "tensor %d has too many tubes", (int)i);
+        if (tchunks(in[i]) > INT32_MAX) FAIL(TSVDM_EUNSUPPORTED, "tensor %d has too many tubes", (int)i);
     }
-    int64_t cnt[4];
-    size_t off[5];
+    int64_t cnt[kTGroups];
+    size_t off[kTGroups + 1];
     const size_t need = tplan_layout(nmat, M, in, cnt, off);
     if (need > 0 && !workspace) FAIL(TSVDM_EWORKSPACE, "workspace is NULL");
     if (workspace_bytes < need)
         FAIL(TSVDM_EWORKSPACE, "workspace too small: %zu < %zu bytes", workspace_bytes, need);
     std::vector<unsigned char> h(need, 0);
     DirectDesc *desc = reinterpret_cast<DirectDesc *>(h.data());
-    int64_t fill[4] = {0, 0, 0, 0};
+    int64_t fill[kTGroups] = {};
     auto *plan_obj = new tsvdm_transform_plan_s;
     plan_obj->direction = direction;
     for (int32_t i = 0; i < nmat; ++i) {
@@ -229,8 +236,9 @@ tsvdm_status tsvdm_transform_plan_create(int32_t nmat, const tsvdm_mdesc *M, int
         d.Md = M[i].kind == TSVDM_M_DENSE ? M[i].M : nullptr;
         d.N = (int32_t)M[i].n3;
         d.dense = M[i].kind == TSVDM_M_DENSE ? 1 : 0;
+        direct_span(in[i], M[i].n3, g >= 4 ? 8 : 4, &d.in_bytes, &d.out_bytes);
         DirectItem *items = reinterpret_cast<DirectItem *>(h.data() + off[g]);
-        const int64_t nt = (d.ntubes + 63) / 64;
+        const int64_t nt = tchunks(in[i]);
         for (int64_t t = 0; t < nt; ++t) items[fill[g]++] = DirectItem{i, (int32_t)t};
     }
     if (need > 0) {
@@ -242,10 +250,10 @@ tsvdm_status tsvdm_transform_plan_create(int32_t nmat, const tsvdm_mdesc *M, int
     }
     unsigned char *ws = reinterpret_cast<unsigned char *>(workspace);
     plan_obj->desc = reinterpret_cast<const DirectDesc *>(ws);
-    for (int g = 0; g < 4; ++g)
+    for (int g = 0; g < kTGroups; ++g)
         if (cnt[g] > 0)
             plan_obj->groups.push_back(
-                TransformGroup{g >= 2, (g & 1) ? 64 : 32, reinterpret_cast<const DirectItem *>(ws + off[g]), cnt[g]});
+                TransformGroup{g >= 4, 16 * (g % 4 + 1), reinterpret_cast<const DirectItem *>(ws + off[g]), cnt[g]});
     plan_obj->M.assign(M, M + nmat);
     plan_obj->in.assign(in, in + nmat);
     plan_obj->out.assign(out, out + nmat);

@@ -342,127 +342,168 @@ __global__ __launch_bounds__(NT) void k_dense_tubes(const void *__restrict__ in,
     (void)E;
 }
 
-// Real M, n3 <= NMAX (64): the transform of a tile of 64 tubes is the product
-// Y = M X (n3 x n3 times n3 x 64).  The tile is staged through LDS (loads of
-// one time step contiguous across the tubes); four threads share a tube, each
-// holding it in registers and forming every fourth output, with M (row f
-// contiguous) read from LDS by broadcast.  DCT-II coefficients come from a
-// table of cos(pi j / (2 n3)), j < 4 n3.  FP32 data accumulates in FP32 (at
-// most 64 terms), FP64 data in FP64.  INV: M^T.
-// One tile of 64 tubes (i0 .. i0+63) of the direct product: the body of
-// k_direct_small and of its batched form.  dense: M is the explicit Md.
+// Real M, n3 <= NMAX (16, 32, 48 or 64; n3 > NMAX - 16): the transform of
+// the tubes is the product Y = M X (n3 x n3 times n3 x tubes) on the matrix
+// cores.  A workgroup takes a chunk of kDirectChunk consecutive tubes of one
+// tensor: it writes M (or M^T for INV) into LDS once, zero-padded to NMAX x
+// NMAX, then each wavefront forms 16 C tubes at a time with 16x16x4 MFMAs
+// (FP32 data in FP32, FP64 in FP64): the B operand (time step 4kk + lane/16 of
+// tube lane%16) is loaded from the input straight into registers, the A
+// operand (16 output rows by 4 time steps) comes from LDS.  After M is
+// written there is no further barrier: the wavefronts stream through the
+// chunk independently and many workgroups share a CU, so their loads,
+// products and stores overlap.  DCT-II coefficients come from a table of
+// cos(pi j / (2 n3)), j < 4 n3.
+//
+// Loads and stores go through buffer resources (base address and byte size
+// of the input view and of the output in scalar registers, a 32-bit byte
+// offset per lane, the offset of a group of time steps or output rows as a
+// scalar offset).  The host guarantees that both byte spans, including
+// NMAX time steps or rows, are below 2^31 (direct_span).  A lane whose
+// element does not exist (time step or output row past n3, tube past the
+// chunk) is given the offset 2^31: at or beyond the resource size whether or
+// not the scalar offset is added, so the load returns zero and the store is
+// dropped, with no select on a loaded value.
+constexpr uint32_t kOffNone = 0x80000000u;
+
+template <typename T>
+__device__ __forceinline__ T bload(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4)
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+    else
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, (int)voff, (int)soff, 0));
+}
+
+template <typename T>
+__device__ __forceinline__ void bstore(T v, __amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    if constexpr (sizeof(T) == 4)
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, (int)voff, (int)soff, 0);
+    else
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(uint32_t __attribute__((ext_vector_type(2))), v),
+                                              r, (int)voff, (int)soff, 0);
+}
+
 template <typename T, int NMAX, bool INV>
-__device__ __forceinline__ void direct_tile(const T *__restrict__ in, const View &iv, T *__restrict__ out,
-                                            int64_t ntubes, int64_t mp, int N, const double *__restrict__ Md,
-                                            bool dense, int64_t i0) {
-    constexpr int TB = 64, G = NT / TB;
-    constexpr int LDM = NMAX + 4;  // row pitch (keeps 16-byte alignment of rows)
-    constexpr int TBP = TB + 4;    // tile row pitch: the MFMA reads of 4 rows hit different banks
+__device__ __forceinline__ void direct_chunk(const T *__restrict__ in, const View &iv, uint32_t in_bytes,
+                                             T *__restrict__ out, uint32_t out_bytes, int64_t ntubes, int64_t mp,
+                                             int N, const double *__restrict__ Md, bool dense, int64_t c0) {
+    constexpr int G = NT / 64;                      // threads per row while M is written
+    constexpr int LDM = NMAX + 4;                   // row pitch of M (4-lane groups hit distinct banks)
+    constexpr int NTI = NMAX / 16, NK = NMAX / 4;   // output row blocks, time-step groups
+    constexpr int C = sizeof(T) == 4 ? 2 : 1;       // 16-tube column blocks per wavefront step
+    constexpr uint32_t SZ = sizeof(T);
     __shared__ __align__(16) T Ms[NMAX * LDM];
-    __shared__ T xs[NMAX * TBP];
     __shared__ double ctab[4 * NMAX];
-    const int tid = threadIdx.x, u = tid % TB, g = tid / TB;
-    // tile loads first, so that they are in flight while M is built; thread
-    // (u, g) stages time steps g, g+4, ... of tube u
-    {
-        const int64_t i = i0 + u;
-        const bool okl = i < ntubes;
-        const int64_t base = iv.tube_base(okl ? i : 0);
-        // all loads in flight before the first LDS store: clamped (in-bounds)
-        // addresses and a select instead of branches; rows t >= N get zeros
-        T v[NMAX / G];
-#pragma unroll
-        for (int q = 0; q < NMAX / G; ++q) {
-            const int t = g + G * q;
-            v[q] = in[base + (int64_t)(t < N ? t : N - 1) * iv.s_t];
-        }
-#pragma unroll
-        for (int q = 0; q < NMAX / G; ++q) {
-            const int t = g + G * q;
-            xs[t * TBP + u] = (okl && t < N) ? v[q] : T(0);
-        }
-    }
+    const int tid = threadIdx.x;
     if (!dense)
         for (int j = tid; j < 4 * N; j += NT) ctab[j] = cospi((double)j / (2.0 * N));
     for (int e = tid; e < NMAX * LDM; e += NT) Ms[e] = T(0);
     __syncthreads();
     // Ms[o * LDM + j]: coefficient of input j in output o.  Thread (o, g)
-    // fills row o at columns j = g, g+4, ...; the cosine table index
+    // fills row o at columns j = g, g+G, ...; the cosine table index
     // (2t+1) f mod 4N advances by a fixed step along the row (no divisions).
-    if (u < N) {
-        const int o = u, fourN = 4 * N;
-        if (dense) {
-            for (int j = g; j < N; j += G) Ms[o * LDM + j] = (T)(INV ? Md[j + (int64_t)N * o] : Md[o + (int64_t)N * j]);
-        } else {
-            const double a0c = sqrt(1.0 / N), a1c = sqrt(2.0 / N);
-            // forward: M[o][j], index (2j+1) o; inverse: M[j][o], index (2o+1) j
-            int idx = INV ? ((2 * o + 1) * g) % fourN : ((2 * g + 1) * o) % fourN;
-            const int step = INV ? (G * (2 * o + 1)) % fourN : (2 * G * o) % fourN;
-            for (int j = g; j < N; j += G) {
-                const double a = (INV ? j : o) == 0 ? a0c : a1c;
-                Ms[o * LDM + j] = (T)(a * ctab[idx]);
-                idx += step;
-                if (idx >= fourN) idx -= fourN;
+    {
+        const int o = tid % 64, g = tid / 64;
+        if (o < N) {
+            const int fourN = 4 * N;
+            if (dense) {
+                for (int j = g; j < N; j += G)
+                    Ms[o * LDM + j] = (T)(INV ? Md[j + (int64_t)N * o] : Md[o + (int64_t)N * j]);
+            } else {
+                const double a0c = sqrt(1.0 / N), a1c = sqrt(2.0 / N);
+                // forward: M[o][j], index (2j+1) o; inverse: M[j][o], index (2o+1) j
+                int idx = INV ? ((2 * o + 1) * g) % fourN : ((2 * g + 1) * o) % fourN;
+                const int step = INV ? (G * (2 * o + 1)) % fourN : (2 * G * o) % fourN;
+                for (int j = g; j < N; j += G) {
+                    const double a = (INV ? j : o) == 0 ? a0c : a1c;
+                    Ms[o * LDM + j] = (T)(a * ctab[idx]);
+                    idx += step;
+                    if (idx >= fourN) idx -= fourN;
+                }
             }
         }
     }
     __syncthreads();
-    // out[o][u] = sum_t M[o][t] x[t][u] for the tile: a 16x16x4 MFMA GEMM
-    // (FP32 or FP64) on the LDS operands; wavefront w makes tubes 16w..16w+15
-    // for every 16-row block of outputs below N (entries past N are zero in
-    // both operands)
-    constexpr int NTI = NMAX / 16;
-    const int wave = tid >> 6, lane = tid & 63, kl = lane >> 4, l16 = lane & 15;
     typedef T v4 __attribute__((ext_vector_type(4)));
-    v4 acc[NTI];
+    const __amdgpu_buffer_rsrc_t rin = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(in), 0, (int)in_bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc(out, 0, (int)out_bytes, 0x00020000);
+    const int wave = tid >> 6, lane = tid & 63, kl = lane >> 4, l16 = lane & 15;
+    const int64_t cend = c0 + kDirectChunk < ntubes ? c0 + kDirectChunk : ntubes;
+    const uint32_t st_b = (uint32_t)iv.s_t * SZ;    // byte stride of one time step
+    const uint32_t mp_b = (uint32_t)mp * SZ;        // byte stride of one output face
+    // output rows of a lane: FP32 4*(lane/16) + v, FP64 lane/16 + 4v (+16 ti)
+    const uint32_t orow = sizeof(T) == 4 ? 4 * kl : kl;
+    for (int64_t b0 = c0 + 16 * C * wave; b0 < cend; b0 += 16 * C * G) {
+        uint32_t vin[C], vout[C];
 #pragma unroll
-    for (int ti = 0; ti < NTI; ++ti) acc[ti] = v4{0, 0, 0, 0};
-    const int ub = 16 * wave + l16;  // tube of the B operand and of the result
-#pragma unroll
-    for (int kk = 0; kk < NMAX / 4; ++kk) {
-        if (4 * kk >= N) break;
-        const T bx = xs[(4 * kk + kl) * TBP + ub];
-#pragma unroll
-        for (int ti = 0; ti < NTI; ++ti) {
-            if (16 * ti >= N) break;
-            const T am = Ms[(16 * ti + l16) * LDM + 4 * kk + kl];
-            if constexpr (sizeof(T) == 4)
-                acc[ti] = __builtin_amdgcn_mfma_f32_16x16x4f32(am, bx, acc[ti], 0, 0, 0);
-            else
-                acc[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, bx, acc[ti], 0, 0, 0);
+        for (int c = 0; c < C; ++c) {
+            const int64_t i = b0 + l16 + 16 * c;
+            vin[c] = (uint32_t)iv.tube_base(i < cend ? i : b0) * SZ + (uint32_t)kl * st_b;
+            vout[c] = i < cend ? (uint32_t)i * SZ + orow * mp_b : kOffNone;
         }
-    }
-    // result layout: FP32 row 4*(lane/16) + v, FP64 row lane/16 + 4v; column lane%16
-    const int64_t i = i0 + ub;
-    const bool ok = i < ntubes;
+        // B operands: time step 4 kk + lane/16 of the lane's tubes; only the
+        // last four groups can reach past n3 (n3 > NMAX - 16)
+        T bx[C][NK];
 #pragma unroll
-    for (int ti = 0; ti < NTI; ++ti) {
-        if (16 * ti >= N) break;
+        for (int kk = 0; kk < NK; ++kk) {
+            const uint32_t soff = (uint32_t)(4 * kk) * st_b;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int o = 16 * ti + (sizeof(T) == 4 ? 4 * kl + v : kl + 4 * v);
-            if (ok && o < N) out[i + mp * o] = acc[ti][v];
+            for (int c = 0; c < C; ++c) {
+                const uint32_t vo = (kk >= NK - 4 && 4 * kk + kl >= N) ? kOffNone : vin[c];
+                bx[c][kk] = bload<T>(rin, vo, soff);
+            }
         }
+        v4 acc[C][NTI];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int ti = 0; ti < NTI; ++ti) acc[c][ti] = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk)
+#pragma unroll
+            for (int ti = 0; ti < NTI; ++ti) {
+                const T am = Ms[(16 * ti + l16) * LDM + 4 * kk + kl];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    if constexpr (sizeof(T) == 4)
+                        acc[c][ti] = __builtin_amdgcn_mfma_f32_16x16x4f32(am, bx[c][kk], acc[c][ti], 0, 0, 0);
+                    else
+                        acc[c][ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(am, bx[c][kk], acc[c][ti], 0, 0, 0);
+                }
+            }
+        // rows below NMAX - 16 exist for every n3 of the class; the last block
+        // drops rows past n3
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int ti = 0; ti < NTI; ++ti)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const uint32_t r0 = 16 * ti + (sizeof(T) == 4 ? v : 4 * v);  // row of lane group 0
+                    const uint32_t vo = (ti == NTI - 1 && (int)(r0 + orow) >= N) ? kOffNone : vout[c];
+                    bstore<T>(acc[c][ti][v], rout, vo, r0 * mp_b);
+                }
     }
 }
 
 template <typename T, int NMAX, bool INV, bool DENSE>
-__global__ __launch_bounds__(NT) void k_direct_small(const T *__restrict__ in, View iv,
-                                                     T *__restrict__ out, int64_t ntubes,
+__global__ __launch_bounds__(NT) void k_direct_small(const T *__restrict__ in, View iv, uint32_t in_bytes,
+                                                     T *__restrict__ out, uint32_t out_bytes, int64_t ntubes,
                                                      int64_t mp, int N, const double *__restrict__ Md) {
-    direct_tile<T, NMAX, INV>(in, iv, out, ntubes, mp, N, Md, DENSE, (int64_t)blockIdx.x * 64);
+    direct_chunk<T, NMAX, INV>(in, iv, in_bytes, out, out_bytes, ntubes, mp, N, Md, DENSE,
+                               (int64_t)blockIdx.x * kDirectChunk);
 }
 
-// Batched direct product: workgroup w transforms tile items[w].tile of the
+// Batched direct product: workgroup w transforms chunk items[w].chunk of the
 // tensor described by desc[items[w].d] (tensors of one precision and one
-// length class, up to NMAX).
+// length class, NMAX - 16 < n3 <= NMAX).
 template <typename T, int NMAX, bool INV>
 __global__ __launch_bounds__(NT) void k_direct_batched(const DirectDesc *__restrict__ desc,
                                                        const DirectItem *__restrict__ items) {
     const DirectItem it = items[blockIdx.x];
     const DirectDesc &d = desc[it.d];
-    direct_tile<T, NMAX, INV>(reinterpret_cast<const T *>(d.in), d.iv, reinterpret_cast<T *>(d.out), d.ntubes,
-                              d.mp, d.N, d.Md, d.dense != 0, (int64_t)it.tile * 64);
+    direct_chunk<T, NMAX, INV>(reinterpret_cast<const T *>(d.in), d.iv, d.in_bytes, reinterpret_cast<T *>(d.out),
+                               d.out_bytes, d.ntubes, d.mp, d.N, d.Md, d.dense != 0, (int64_t)it.chunk * kDirectChunk);
 }
 
 template <typename K>
@@ -539,20 +580,27 @@ tsvdm_status run_dense(int kind, int dir, const tsvdm_mdesc *M, const tsvdm_tens
         TSVDM_LAUNCH("transform_direct", kern, dim3((unsigned)grid), dim3(NT), lds, s, in->data, iv, \
                      out->data, ntubes, mp, N, nf_in, nf_out, TB, M->M);                             \
     } while (0)
-    if (kind != TSVDM_M_DFT && N <= 64) {
-        const int64_t g2 = (ntubes + 63) / 64;
+    uint32_t in_bytes = 0, out_bytes = 0;
+    if (kind != TSVDM_M_DFT && N <= 64 && direct_span(*in, N, sizeof(T), &in_bytes, &out_bytes)) {
+        const int64_t g2 = (ntubes + kDirectChunk - 1) / kDirectChunk;
         const double *Md = M->M;
 #define TSVDM_SMALL_LAUNCH(NM, INV, DN)                                                          \
     TSVDM_LAUNCH("transform_direct", (k_direct_small<T, NM, INV, DN>), dim3((unsigned)g2), dim3(NT), 0, s, \
-                 reinterpret_cast<const T *>(in->data), iv, reinterpret_cast<T *>(out->data), ntubes, mp, N, Md)
+                 reinterpret_cast<const T *>(in->data), iv, in_bytes, reinterpret_cast<T *>(out->data), out_bytes, \
+                 ntubes, mp, N, Md)
+#define TSVDM_SMALL_CLASS(NM)                                                                                 \
+    do {                                                                                                      \
+        if (dir > 0) { if (dn) TSVDM_SMALL_LAUNCH(NM, false, true); else TSVDM_SMALL_LAUNCH(NM, false, false); } \
+        else { if (dn) TSVDM_SMALL_LAUNCH(NM, true, true); else TSVDM_SMALL_LAUNCH(NM, true, false); }          \
+    } while (0)
         const bool dn = kind == TSVDM_M_DENSE;
-        if (N <= 32) {
-            if (dir > 0) { if (dn) TSVDM_SMALL_LAUNCH(32, false, true); else TSVDM_SMALL_LAUNCH(32, false, false); }
-            else { if (dn) TSVDM_SMALL_LAUNCH(32, true, true); else TSVDM_SMALL_LAUNCH(32, true, false); }
-        } else {
-            if (dir > 0) { if (dn) TSVDM_SMALL_LAUNCH(64, false, true); else TSVDM_SMALL_LAUNCH(64, false, false); }
-            else { if (dn) TSVDM_SMALL_LAUNCH(64, true, true); else TSVDM_SMALL_LAUNCH(64, true, false); }
+        switch (direct_class(N)) {
+            case 16: TSVDM_SMALL_CLASS(16); break;
+            case 32: TSVDM_SMALL_CLASS(32); break;
+            case 48: TSVDM_SMALL_CLASS(48); break;
+            default: TSVDM_SMALL_CLASS(64); break;
         }
+#undef TSVDM_SMALL_CLASS
 #undef TSVDM_SMALL_LAUNCH
         TSVDM_LAUNCH_CHECK("k_direct_small");
         return TSVDM_OK;
@@ -583,13 +631,18 @@ tsvdm_status launch_direct_batched(const DirectDesc *desc, const TransformGroup 
 #define TSVDM_DB(T, NM, INV)                                                                         \
     TSVDM_LAUNCH("transform_direct_batched", (k_direct_batched<T, NM, INV>), grid, dim3(NT), 0, s, desc, \
                  g.items)
-    if (g.dbl) {
-        if (g.nmax == 32) { if (direction > 0) TSVDM_DB(double, 32, false); else TSVDM_DB(double, 32, true); }
-        else { if (direction > 0) TSVDM_DB(double, 64, false); else TSVDM_DB(double, 64, true); }
-    } else {
-        if (g.nmax == 32) { if (direction > 0) TSVDM_DB(float, 32, false); else TSVDM_DB(float, 32, true); }
-        else { if (direction > 0) TSVDM_DB(float, 64, false); else TSVDM_DB(float, 64, true); }
-    }
+#define TSVDM_DB_CLASS(T)                                                                   \
+    do {                                                                                    \
+        switch (g.nmax) {                                                                   \
+            case 16: if (direction > 0) TSVDM_DB(T, 16, false); else TSVDM_DB(T, 16, true); break; \
+            case 32: if (direction > 0) TSVDM_DB(T, 32, false); else TSVDM_DB(T, 32, true); break; \
+            case 48: if (direction > 0) TSVDM_DB(T, 48, false); else TSVDM_DB(T, 48, true); break; \
+            default: if (direction > 0) TSVDM_DB(T, 64, false); else TSVDM_DB(T, 64, true); break; \
+        }                                                                                   \
+    } while (0)
+    if (g.dbl) TSVDM_DB_CLASS(double);
+    else TSVDM_DB_CLASS(float);
+#undef TSVDM_DB_CLASS
 #undef TSVDM_DB
     TSVDM_LAUNCH_CHECK("k_direct_batched");
     return TSVDM_OK;

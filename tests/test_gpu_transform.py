@@ -61,9 +61,11 @@ def test_dense_orthogonal_M(dt):
 
 
 @pytest.mark.parametrize("dt", [np.float32, np.float64])
-def test_blockmat_view_zero_copy(dt):
-    """T_E[A] read in place through the strided view (Sec. 3 map, generic E)."""
-    ell, q, m, n = 3, 5, 7, 16
+@pytest.mark.parametrize("ell,q,m,n", [(3, 5, 7, 16), (3, 5, 7, 21), (8, 6, 13, 37)])
+def test_blockmat_view_zero_copy(dt, ell, q, m, n):
+    """T_E[A] read in place through the strided view (Sec. 3 map, generic E):
+    a power-of-two length (FFT) and two others (matrix-core direct product,
+    the last over two chunks of tubes with a ragged tail)."""
     lda = ell * m + 3  # padded leading dimension
     g = np.random.default_rng(4)
     Afull = np.asfortranarray(g.standard_normal((lda, q * n))).astype(dt)
