@@ -304,8 +304,9 @@ tsvdm_status tsvdm_truncate_batched(const tsvdm_batched_plan *plan, void *stream
  * batch signature, which later plans of the same signature start from. */
 tsvdm_status tsvdm_batched_autotune(tsvdm_batched_plan *plan, void *stream);
 
-/* The plan's configuration: cfg[0] Gram workgroups per CU, cfg[1] Gram column
- * chunk, cfg[2] V workgroups per CU, cfg[3] 1 if it came from the autotuner
+/* The plan's configuration: cfg[0] Gram workgroups (of four wavefronts, one
+ * face each at a time) per CU, cfg[1] Gram columns per prefetch step (16 or
+ * 32), cfg[2] V workgroups per CU, cfg[3] 1 if it came from the autotuner
  * (here or through the table). */
 tsvdm_status tsvdm_batched_config(const tsvdm_batched_plan *plan, int32_t cfg[4]);
 

@@ -4,9 +4,9 @@
 //
 // Three kernels per batch, all items (faces) listed in a table built once on
 // the host and ordered by cost, largest first:
-//  * k_bgram (persistent, HBM + FP64 MFMA): workgroups pull faces from an
+//  * k_bgram (persistent, HBM + FP64 MFMA): wavefronts pull faces from an
 //    atomic queue and form G = X X^T in FP64 (exact products of FP32 data)
-//    from column chunks of the face staged in LDS; G goes to the workspace.
+//    from operands loaded straight into registers; G goes to the workspace.
 //  * k_bcore (one wavefront per face): rank-revealing pivoted Cholesky
 //    P G P^T = R^T R + S (left-looking, largest remaining diagonal first),
 //    stopped once trace(S) is below the rule's tolerance; Jacobi
@@ -113,62 +113,125 @@ __device__ __forceinline__ int next_item(int *counter, int *s_idx) {
 }
 
 // ---------------------------------------------------------------- Gram
-template <int KC>
-__global__ __launch_bounds__(BT) void k_bgram(const Item *__restrict__ items, int nitems,
-                                              int *__restrict__ counter) {
-    __shared__ float xs[KC * LDX];
-    __shared__ int s_idx;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    for (;;) {
-        const int idx = next_item(counter, &s_idx);
-        if (idx >= nitems) break;
-        const Item it = items[idx];
-        const int m = it.m, p = it.p, nt = (m + 15) >> 4, ntile = nt * (nt + 1) / 2;
-        int ti[3], tj[3];
+// One wavefront per face; the wavefronts of a workgroup pull faces from the
+// queue independently (no LDS, no barriers).  For the group of columns
+// 4g..4g+3, lane (l16, kl) = (lane % 16, lane / 16) holds X(16t + l16, 4g + kl)
+// for every 16-row block t < NT.  That register is at once the A operand of
+// the FP64 16x16x4 MFMA for row block t and its B operand for column block t,
+// so each group of columns is loaded once, widened to FP64 (exactly) and used
+// for all NT(NT+1)/2 upper tiles of G = X X^T.  Rows past m load row m - 1
+// (they only reach rows and columns of G past m, which are not stored);
+// columns past p, in the last step, load zero through the buffer resource:
+// their byte offset gets bit 31 (faces are below 2^30 bytes, so the offset is
+// then beyond the face whether or not the scalar offset is counted).  Steps of U groups are
+// double-buffered in registers so the next step's loads are in flight during
+// this step's products.  The product order over the columns is fixed: the
+// result does not depend on U or on the launch configuration.
+__device__ __forceinline__ float bload_f32(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)voff, (int)soff, 0));
+}
+
+template <int NT>
+__device__ __forceinline__ void gram_group(const float (&x)[NT], f64x4 (&acc)[NT * (NT + 1) / 2]) {
+    double d[NT];
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const int id = wave + 4 * t;
-            if (id < ntile) tile_of(id, nt, ti[t], tj[t]);
-            else ti[t] = tj[t] = -1;
+    for (int t = 0; t < NT; ++t) d[t] = (double)x[t];
+    int q = 0;
+#pragma unroll
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < NT; ++tj, ++q)
+            acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(d[ti], d[tj], acc[q], 0, 0, 0);
+}
+
+// the face's fields in scalar registers (the queue index is uniform, but the
+// face table is read inside a loop with global stores, so the compiler cannot
+// prove it; buffer resources must be uniform)
+template <typename P>
+__device__ __forceinline__ P *uniform_ptr(P *ptr) {
+    const uint64_t v = reinterpret_cast<uint64_t>(ptr);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v), hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return reinterpret_cast<P *>(((uint64_t)hi << 32) | lo);
+}
+
+template <int NT, int U>
+__device__ __forceinline__ void gram_face(const Item &it, int lane) {
+    constexpr int NTILE = NT * (NT + 1) / 2;
+    const int m = __builtin_amdgcn_readfirstlane(it.m), p = __builtin_amdgcn_readfirstlane(it.p);
+    const int kl = lane >> 4, l16 = lane & 15;
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(const_cast<float *>(it.X)), 0, m * p * 4, 0x00020000);
+    uint32_t lb[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) lb[t] = (uint32_t)(min(16 * t + l16, m - 1) + m * kl) * 4u;
+    const uint32_t gb = 16u * (uint32_t)m;  // bytes of one group of 4 columns
+    f64x4 acc[NTILE];
+#pragma unroll
+    for (int q = 0; q < NTILE; ++q) acc[q] = f64x4{0, 0, 0, 0};
+    // steps of U groups; a step past the last reads zeros only
+    auto load_step = [&](float (&x)[U][NT], int st) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int g = st * U + u;
+            // bit 31 set for a column past p (offsets of the face stay below
+            // 2^30; an arithmetic mask, not a select, keeps the loads unpredicated)
+            const uint32_t miss = ((uint32_t)(p - 1 - (4 * g + kl)) >> 31) << 31;
+            const uint32_t go = (uint32_t)g * gb;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) x[u][t] = bload_f32(r, (lb[t] + go) | miss, 0);
         }
-        f64x4 acc[3];
+    };
+    // two register buffers in turn, without a branch between the halves (a
+    // copy between buffers, or a conditional second half, lets the compiler
+    // wait for the prefetched loads); loads past the last step read zeros,
+    // whose products add exact zeros
+    const int nsteps = (p + 4 * U - 1) / (4 * U);
+    float xa[U][NT], xb[U][NT];
+    load_step(xa, 0);
+    for (int st = 0; st < nsteps; st += 2) {
+        load_step(xb, st + 1);
 #pragma unroll
-        for (int t = 0; t < 3; ++t) acc[t] = f64x4{0, 0, 0, 0};
-        for (int e = tid; e < KC * LDX; e += BT) xs[e] = 0.0f;
-        Stager<KC> sg;
-        sg.init(it.X, m, p);
-        const int nck = (p + KC - 1) / KC;
-        sg.load(0);
-        __syncthreads();
-        for (int c = 0; c < nck; ++c) {
-            sg.store(xs);
-            __syncthreads();
-            if (c + 1 < nck) sg.load(c + 1);
-#pragma unroll 4
-            for (int kk = 0; kk < KC / 4; ++kk) {
-                const int r = 4 * kk + (lane >> 4);
+        for (int u = 0; u < U; ++u) gram_group<NT>(xa[u], acc);
+        load_step(xa, st + 2);
 #pragma unroll
-                for (int t = 0; t < 3; ++t) {
-                    if (ti[t] < 0) continue;
-                    const double a = xs[r * LDX + 16 * ti[t] + (lane & 15)];
-                    const double b = xs[r * LDX + 16 * tj[t] + (lane & 15)];
-                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
-                }
-            }
-            __syncthreads();
-        }
-        // FP64 16x16x4 output: row lane/16 + 4v, column lane%16 of the tile
+        for (int u = 0; u < U; ++u) gram_group<NT>(xb[u], acc);
+    }
+    // FP64 16x16x4 output: row lane/16 + 4v, column lane%16 of the tile; G is
+    // m x m row major, entries past m dropped by the buffer resource
+    const __amdgpu_buffer_rsrc_t rg = __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(it.G), 0, m * m * 8, 0x00020000);
+    int q = 0;
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            if (ti[t] < 0) continue;
+    for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+        for (int tj = ti; tj < NT; ++tj, ++q)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = 16 * ti[t] + (lane >> 4) + 4 * v, j = 16 * tj[t] + (lane & 15);
-                if (i < m && j < m) {
-                    it.G[i * m + j] = acc[t][v];
-                    it.G[j * m + i] = acc[t][v];
-                }
+                const int i = 16 * ti + kl + 4 * v, j = 16 * tj + l16;
+                const uint32_t miss = ((uint32_t)((m - 1 - i) | (m - 1 - j)) >> 31) << 31;
+                // the element is copied first: a bit cast of the vector
+                // element itself was compiled as a cast of element 0
+                const double dv = acc[q][v];
+                const auto val = __builtin_bit_cast(uint32_t __attribute__((ext_vector_type(2))), dv);
+                __builtin_amdgcn_raw_buffer_store_b64(val, rg, (int)(((uint32_t)(i * m + j) * 8u) | miss), 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b64(val, rg, (int)(((uint32_t)(j * m + i) * 8u) | miss), 0, 0);
             }
+}
+
+template <int U>
+__global__ __launch_bounds__(BT) void k_bgram(const Item *__restrict__ items, int nitems,
+                                              int *__restrict__ counter) {
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        int idx = 0;
+        if (lane == 0) idx = atomicAdd(counter, 1);
+        idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
+        if (idx >= nitems) break;
+        const Item it = items[idx];
+        switch ((__builtin_amdgcn_readfirstlane(it.m) + 15) >> 4) {
+            case 1: gram_face<1, U>(it, lane); break;
+            case 2: gram_face<2, U>(it, lane); break;
+            case 3: gram_face<3, U>(it, lane); break;
+            default: gram_face<4, U>(it, lane); break;
         }
     }
 }
@@ -409,7 +472,7 @@ struct tsvdm_batched_plan_s {
     int32_t *d_counter = nullptr;
     int mode = 0, kcap = 0, max_sweeps = 30;
     double tau = 0.0;
-    Cfg cfg{2, 64, 2, 0};
+    Cfg cfg{2, 16, 2, 0};
     uint64_t sig = 0;
 };
 
@@ -427,8 +490,8 @@ bool check_batch(int32_t nmat, const tsvdm_tensor *X, int64_t *nitems, int64_t *
             set_error("batched: tensor %d must be TSVDM_F32", i);
             return false;
         }
-        if (t.m < 1 || t.m > MX || t.p < 1 || t.n3 < 1 || t.p > (int64_t(1) << 24) || t.n3 > (1 << 20)) {
-            set_error("batched: tensor %d has m=%lld p=%lld n3=%lld (need 1 <= m <= 64, p <= 2^24)", i,
+        if (t.m < 1 || t.m > MX || t.p < 1 || t.n3 < 1 || t.m * t.p > (int64_t(1) << 28) || t.n3 > (1 << 20)) {
+            set_error("batched: tensor %d has m=%lld p=%lld n3=%lld (need 1 <= m <= 64, m*p <= 2^28)", i,
                       (long long)t.m, (long long)t.p, (long long)t.n3);
             return false;
         }
@@ -467,10 +530,10 @@ tsvdm_status launch(const tsvdm_batched_plan_s *P, const Cfg &cfg, hipStream_t s
     TSVDM_LAUNCH("batched_reset", k_bzero, dim3(1), dim3(64), 0, s, P->d_counter);
     if (which & 1) {
         const dim3 grid((unsigned)(P->num_cu * cfg.gram_wpc));
-        if (cfg.gram_kc == 32)
-            TSVDM_LAUNCH("batched_gram", k_bgram<32>, grid, dim3(BT), 0, s, P->d_items, P->nitems, P->d_counter);
+        if (cfg.gram_kc == 16)
+            TSVDM_LAUNCH("batched_gram", k_bgram<4>, grid, dim3(BT), 0, s, P->d_items, P->nitems, P->d_counter);
         else
-            TSVDM_LAUNCH("batched_gram", k_bgram<64>, grid, dim3(BT), 0, s, P->d_items, P->nitems, P->d_counter);
+            TSVDM_LAUNCH("batched_gram", k_bgram<8>, grid, dim3(BT), 0, s, P->d_items, P->nitems, P->d_counter);
     }
     if (which & 2)
         TSVDM_LAUNCH("batched_core", k_bcore, dim3((unsigned)P->nitems), dim3(64), 0, s, P->d_items, P->mode,
@@ -640,7 +703,7 @@ tsvdm_status tsvdm_batched_autotune(tsvdm_batched_plan *plan, void *stream) {
     };
     Cfg best = plan->cfg;
     float tg = 1e30f, tv = 1e30f;
-    const int wpcs[3] = {1, 2, 4}, kcs[2] = {32, 64};
+    const int wpcs[3] = {1, 2, 4}, kcs[2] = {16, 32};
     for (int w : wpcs)
         for (int kc : kcs) {
             Cfg c = best;

@@ -117,7 +117,7 @@ def test_graph_capture_replays_and_autotune_match_eager():
     assert cfg0[3] in (0, 1)
     cfg = bt.autotune()
     torch.cuda.synchronize()
-    assert cfg[3] == 1 and cfg[0] in (1, 2, 4) and cfg[1] in (32, 64) and cfg[2] in (1, 2, 4)
+    assert cfg[3] == 1 and cfg[0] in (1, 2, 4) and cfg[1] in (16, 32) and cfg[2] in (1, 2, 4)
     for F, r in zip(Fs, ref):
         for a, b in zip((F.U, F.S, F.V, F.ranks, F.cert), r):
             assert torch.equal(a, b)
