@@ -258,7 +258,8 @@ tsvdm_status tsvdm_timing_get(int32_t i, const char **name, int32_t *launches, d
 
 /* ---------------------------------------------------------------- batches
  * Facewise truncation of an uneven batch: nmat dense transform-domain tensors
- * Xhat[i] (FP32, m_i x p_i x nf_i, each face with m_i <= 64 rows), each with
+ * Xhat[i] (FP32, m_i x p_i x nf_i, each face with m_i <= 64 rows, at most 2^28
+ * elements per face and p_i < 2^24), each with
  * its own factors F[i] (F32 U and V, kmax_i columns).  This is the truncation
  * step of Algorithm alg:strategy for many independent inputs at once (e.g.
  * the Kronecker-sum matrices of Sec. 3 mapped by T_E and transformed).

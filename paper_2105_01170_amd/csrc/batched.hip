@@ -12,7 +12,7 @@
 //    stopped once trace(S) is below the rule's tolerance; Jacobi
 //    eigensolver of R R^T (at most 32 x 32); rank rule with the discarded
 //    energy sum_{j>k} lambda_j + trace(S); U = P^T R^T U_H diag(1/sigma).
-//  * k_bvec (persistent, HBM): V = X^T U diag(1/sigma), a second pass over
+//  * k_bvec (persistent, HBM + FP32 MFMA): V = X^T U diag(1/sigma), a second pass over
 //    the face.
 // A queue reset kernel precedes the two persistent kernels, so a launch
 // sequence can be captured in a graph and replayed.
@@ -31,11 +31,11 @@ using namespace tsvdm;
 namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BT = 256;      // threads per workgroup of the streaming kernels
 constexpr int MX = 64;       // largest face row count
 constexpr int RX = 32;       // largest pivoted-Cholesky rank (Jacobi size)
-constexpr int LDX = MX + 1;  // LDS pitch (floats) of one staged column
 constexpr int KMAXB = 32;    // largest rank returned
 
 struct Item {
@@ -50,67 +50,6 @@ struct Item {
     int32_t *info; // may be null
     int32_t m, p, kmax, pad;
 };
-
-// staging of a chunk of KC columns of the m x p face (m*KC consecutive floats)
-// into LDS as xs[k * LDX + i]; rows m..63 of xs stay zero.  Each thread holds
-// KC*MX/BT floats between the global load and the LDS store, so the next
-// chunk's loads are in flight while the current chunk is consumed.
-template <int KC>
-struct Stager {
-    static constexpr int PER = KC * MX / BT;
-    float v[PER];
-    int i0, k0, di, dk, m, p;
-    const float *X;
-    __device__ void init(const float *X_, int m_, int p_) {
-        X = X_;
-        m = m_;
-        p = p_;
-        i0 = threadIdx.x % m;
-        k0 = threadIdx.x / m;
-        di = BT % m;
-        dk = BT / m;
-    }
-    __device__ void load(int c) {
-        const int ncol = min(KC, p - c * KC);
-        const int lim = m * ncol;
-        const float *src = X + (int64_t)m * KC * c;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const int l = threadIdx.x + q * BT;
-            v[q] = l < lim ? src[l] : 0.0f;
-        }
-    }
-    __device__ void store(float *xs) const {
-        int i = i0, k = k0;
-#pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            if (k < KC) xs[k * LDX + i] = v[q];
-            i += di;
-            k += dk;
-            if (i >= m) {
-                i -= m;
-                ++k;
-            }
-        }
-    }
-};
-
-__device__ __forceinline__ void tile_of(int t, int nt, int &ti, int &tj) {
-    ti = 0;
-    while (t >= nt - ti) {
-        t -= nt - ti;
-        ++ti;
-    }
-    tj = ti + t;
-}
-
-__device__ __forceinline__ int next_item(int *counter, int *s_idx) {
-    if (threadIdx.x == 0) *s_idx = atomicAdd(counter, 1);
-    __syncthreads();
-    const int idx = *s_idx;
-    __syncthreads();
-    return idx;
-}
 
 // ---------------------------------------------------------------- Gram
 // One wavefront per face; the wavefronts of a workgroup pull faces from the
@@ -391,49 +330,111 @@ __global__ __launch_bounds__(64) void k_bcore(const Item *__restrict__ items, in
 }
 
 // ---------------------------------------------------------------- V
-template <int KC>
+// One wavefront per face: V(col, j) = sum_i X(i, col) W(i, j) with
+// W = U diag(1/sigma) (zero in the columns j >= rank), as FP32 16x16x4 MFMAs
+// D = W^T X over 16 ranks by 16 columns of the face.  W^T is the A operand,
+// formed once per face in registers: lane (l16, kl) holds W(4kk + kl, 16jb + l16)
+// for every group kk of four rows, zero for rows past m.  X is the B operand,
+// loaded straight from the face: lane (l16, kl) of column block c holds
+// X(4kk + kl, col) for col = 32 step + 16c + l16, at byte offset
+// 4 (kl + m col) + 16 kk (the group in the instruction's offset field).  A row
+// past m lands on the next column of the same face (finite, times a zero of
+// W); anything past the face, including columns past p, reads zero through
+// the buffer resource.  Stores of columns past p or ranks past kmax get bit 31
+// of the offset and are dropped.  Steps of 32 columns are double-buffered.
+template <int NT, int NJ>
+__device__ __forceinline__ void vec_face(const Item &it, int lane) {
+    constexpr int NK = 4 * NT, C = 2;
+    const int m = __builtin_amdgcn_readfirstlane(it.m), p = __builtin_amdgcn_readfirstlane(it.p);
+    const int kmax = __builtin_amdgcn_readfirstlane(it.kmax);
+    const int kf = __builtin_amdgcn_readfirstlane(*uniform_ptr(it.rank));
+    const int kl = lane >> 4, l16 = lane & 15;
+    const float *U = uniform_ptr(it.U);
+    const double *S = uniform_ptr(it.S);
+    float w[NJ][NK];
+#pragma unroll
+    for (int jb = 0; jb < NJ; ++jb) {
+        const int j = 16 * jb + l16;
+        float isg = 0.0f;
+        if (j < kf) {
+            const double sv = S[j];
+            isg = sv > 0.0 ? (float)(1.0 / sv) : 0.0f;
+        }
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) {
+            const int i = 4 * kk + kl;
+            w[jb][kk] = (j < kf && i < m) ? U[i + (int64_t)m * j] * isg : 0.0f;
+        }
+    }
+    const __amdgpu_buffer_rsrc_t rx =
+        __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(const_cast<float *>(it.X)), 0, m * p * 4, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rv =
+        __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(it.V), 0, p * kmax * 4, 0x00020000);
+    auto load_step = [&](float (&x)[C][NK], int st) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const uint32_t vo = (uint32_t)(kl + m * (32 * st + 16 * c + l16)) * 4u;
+#pragma unroll
+            for (int kk = 0; kk < NK; ++kk) x[c][kk] = bload_f32(rx, vo + 16u * kk, 0);
+        }
+    };
+    auto mma_store = [&](const float (&x)[C][NK], int st) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int col = 32 * st + 16 * c + l16;
+#pragma unroll
+            for (int jb = 0; jb < NJ; ++jb) {
+                f32x4 acc = f32x4{0, 0, 0, 0};
+#pragma unroll
+                for (int kk = 0; kk < NK; ++kk)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w[jb][kk], x[c][kk], acc, 0, 0, 0);
+                // FP32 16x16x4 output: rank 4 (lane/16) + v, column lane%16
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int j = 16 * jb + 4 * kl + v;
+                    const uint32_t miss = ((uint32_t)((p - 1 - col) | (kmax - 1 - j)) >> 31) << 31;
+                    const float dv = acc[v];
+                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, dv), rv,
+                                                          (int)(((uint32_t)(col + p * j) * 4u) | miss), 0, 0);
+                }
+            }
+        }
+    };
+    const int nsteps = (p + 31) / 32;
+    float xa[C][NK], xb[C][NK];
+    load_step(xa, 0);
+    for (int st = 0; st < nsteps; st += 2) {
+        load_step(xb, st + 1);
+        mma_store(xa, st);
+        load_step(xa, st + 2);
+        mma_store(xb, st + 1);
+    }
+}
+
 __global__ __launch_bounds__(BT) void k_bvec(const Item *__restrict__ items, int nitems,
                                              int *__restrict__ counter) {
-    constexpr int NG = BT / KC;  // column threads share a column, NG rank groups
-    __shared__ float xs[KC * LDX];
-    __shared__ float us[MX * (KMAXB + 1)];
-    __shared__ float isg[KMAXB];
-    __shared__ int s_idx;
-    const int tid = threadIdx.x, c = tid % KC, g = tid / KC;
+    const int lane = threadIdx.x & 63;
     for (;;) {
-        const int idx = next_item(counter, &s_idx);
+        int idx = 0;
+        if (lane == 0) idx = atomicAdd(counter, 1);
+        idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
         if (idx >= nitems) break;
         const Item it = items[idx];
-        const int m = it.m, p = it.p, kmax = it.kmax;
-        const int kf = *it.rank;
-        for (int e = tid; e < m * kf; e += BT) {
-            const int i = e % m, j = e / m;
-            us[i * (KMAXB + 1) + j] = it.U[i + (int64_t)m * j];
-        }
-        for (int j = tid; j < kf; j += BT) {
-            const double s = it.S[j];
-            isg[j] = s > 0.0 ? (float)(1.0 / s) : 0.0f;
-        }
-        for (int e = tid; e < KC * LDX; e += BT) xs[e] = 0.0f;
-        Stager<KC> sg;
-        sg.init(it.X, m, p);
-        const int nck = (p + KC - 1) / KC;
-        sg.load(0);
-        __syncthreads();
-        for (int ch = 0; ch < nck; ++ch) {
-            sg.store(xs);
-            __syncthreads();
-            if (ch + 1 < nck) sg.load(ch + 1);
-            const int col = ch * KC + c;
-            for (int j = g; j < kmax; j += NG) {
-                float acc = 0.0f;
-                if (j < kf) {
-                    for (int i = 0; i < m; ++i) acc += xs[c * LDX + i] * us[i * (KMAXB + 1) + j];
-                    acc *= isg[j];
-                }
-                if (col < p) it.V[col + (int64_t)p * j] = acc;
+        const int nt = (__builtin_amdgcn_readfirstlane(it.m) + 15) >> 4;
+        if (__builtin_amdgcn_readfirstlane(it.kmax) <= 16) {
+            switch (nt) {
+                case 1: vec_face<1, 1>(it, lane); break;
+                case 2: vec_face<2, 1>(it, lane); break;
+                case 3: vec_face<3, 1>(it, lane); break;
+                default: vec_face<4, 1>(it, lane); break;
             }
-            __syncthreads();
+        } else {
+            switch (nt) {
+                case 1: vec_face<1, 2>(it, lane); break;
+                case 2: vec_face<2, 2>(it, lane); break;
+                case 3: vec_face<3, 2>(it, lane); break;
+                default: vec_face<4, 2>(it, lane); break;
+            }
         }
     }
 }
@@ -490,8 +491,9 @@ bool check_batch(int32_t nmat, const tsvdm_tensor *X, int64_t *nitems, int64_t *
             set_error("batched: tensor %d must be TSVDM_F32", i);
             return false;
         }
-        if (t.m < 1 || t.m > MX || t.p < 1 || t.n3 < 1 || t.m * t.p > (int64_t(1) << 28) || t.n3 > (1 << 20)) {
-            set_error("batched: tensor %d has m=%lld p=%lld n3=%lld (need 1 <= m <= 64, m*p <= 2^28)", i,
+        if (t.m < 1 || t.m > MX || t.p < 1 || t.n3 < 1 || t.m * t.p > (int64_t(1) << 28) || t.p >= (int64_t(1) << 24) ||
+            t.n3 > (1 << 20)) {
+            set_error("batched: tensor %d has m=%lld p=%lld n3=%lld (need 1 <= m <= 64, m*p <= 2^28, p < 2^24)", i,
                       (long long)t.m, (long long)t.p, (long long)t.n3);
             return false;
         }
@@ -540,7 +542,7 @@ tsvdm_status launch(const tsvdm_batched_plan_s *P, const Cfg &cfg, hipStream_t s
                      P->kcap, P->tau, P->max_sweeps);
     if (which & 4) {
         const dim3 grid((unsigned)(P->num_cu * cfg.vec_wpc));
-        TSVDM_LAUNCH("batched_vec", k_bvec<64>, grid, dim3(BT), 0, s, P->d_items, P->nitems, P->d_counter + 1);
+        TSVDM_LAUNCH("batched_vec", k_bvec, grid, dim3(BT), 0, s, P->d_items, P->nitems, P->d_counter + 1);
     }
     TSVDM_LAUNCH_CHECK("batched truncate");
     return TSVDM_OK;
