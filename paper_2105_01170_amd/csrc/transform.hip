@@ -391,10 +391,45 @@ __device__ __forceinline__ void direct_chunk(const T *__restrict__ in, const Vie
     constexpr int LDM = NMAX + 4;                   // row pitch of M (4-lane groups hit distinct banks)
     constexpr int NTI = NMAX / 16, NK = NMAX / 4;   // output row blocks, time-step groups
     constexpr int C = sizeof(T) == 4 ? 2 : 1;       // 16-tube column blocks per wavefront step
+    constexpr int NB = kDirectChunk / (16 * C * G); // steps of a wavefront per chunk
+    static_assert(NB % 2 == 0, "steps are taken in pairs");
     constexpr uint32_t SZ = sizeof(T);
     __shared__ __align__(16) T Ms[NMAX * LDM];
     __shared__ double ctab[4 * NMAX];
+    typedef T v4 __attribute__((ext_vector_type(4)));
     const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63, kl = lane >> 4, l16 = lane & 15;
+    const __amdgpu_buffer_rsrc_t rin = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(in), 0, (int)in_bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc(out, 0, (int)out_bytes, 0x00020000);
+    const int64_t cend = c0 + kDirectChunk < ntubes ? c0 + kDirectChunk : ntubes;
+    const uint32_t st_b = (uint32_t)iv.s_t * SZ;    // byte stride of one time step
+    const uint32_t mp_b = (uint32_t)mp * SZ;        // byte stride of one output face
+    // output rows of a lane: FP32 4*(lane/16) + v, FP64 lane/16 + 4v (+16 ti)
+    const uint32_t orow = sizeof(T) == 4 ? 4 * kl : kl;
+    // B operands of step s of this wavefront (tubes b0 + 16c + lane%16, time
+    // step 4 kk + lane/16); tubes past the chunk read tube c0; only the last
+    // four groups can reach past n3 (n3 > NMAX - 16)
+    auto load_step = [&](T (&bx)[C][NK], int st) {
+        const int64_t b0 = c0 + 16 * C * (wave + G * st);
+        uint32_t vin[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int64_t i = b0 + l16 + 16 * c;
+            vin[c] = (uint32_t)iv.tube_base(i < cend ? i : c0) * SZ + (uint32_t)kl * st_b;
+        }
+#pragma unroll
+        for (int kk = 0; kk < NK; ++kk) {
+            const uint32_t soff = (uint32_t)(4 * kk) * st_b;
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const uint32_t vo = (kk >= NK - 4 && 4 * kk + kl >= N) ? kOffNone : vin[c];
+                bx[c][kk] = bload<T>(rin, vo, soff);
+            }
+        }
+    };
+    // the first step's loads are in flight while M is written
+    T xa[C][NK], xb[C][NK];
+    load_step(xa, 0);
     if (!dense)
         for (int j = tid; j < 4 * N; j += NT) ctab[j] = cospi((double)j / (2.0 * N));
     for (int e = tid; e < NMAX * LDM; e += NT) Ms[e] = T(0);
@@ -424,35 +459,14 @@ __device__ __forceinline__ void direct_chunk(const T *__restrict__ in, const Vie
         }
     }
     __syncthreads();
-    typedef T v4 __attribute__((ext_vector_type(4)));
-    const __amdgpu_buffer_rsrc_t rin = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(in), 0, (int)in_bytes, 0x00020000);
-    const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc(out, 0, (int)out_bytes, 0x00020000);
-    const int wave = tid >> 6, lane = tid & 63, kl = lane >> 4, l16 = lane & 15;
-    const int64_t cend = c0 + kDirectChunk < ntubes ? c0 + kDirectChunk : ntubes;
-    const uint32_t st_b = (uint32_t)iv.s_t * SZ;    // byte stride of one time step
-    const uint32_t mp_b = (uint32_t)mp * SZ;        // byte stride of one output face
-    // output rows of a lane: FP32 4*(lane/16) + v, FP64 lane/16 + 4v (+16 ti)
-    const uint32_t orow = sizeof(T) == 4 ? 4 * kl : kl;
-    for (int64_t b0 = c0 + 16 * C * wave; b0 < cend; b0 += 16 * C * G) {
-        uint32_t vin[C], vout[C];
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const int64_t i = b0 + l16 + 16 * c;
-            vin[c] = (uint32_t)iv.tube_base(i < cend ? i : b0) * SZ + (uint32_t)kl * st_b;
-            vout[c] = i < cend ? (uint32_t)i * SZ + orow * mp_b : kOffNone;
-        }
-        // B operands: time step 4 kk + lane/16 of the lane's tubes; only the
-        // last four groups can reach past n3 (n3 > NMAX - 16)
-        T bx[C][NK];
-#pragma unroll
-        for (int kk = 0; kk < NK; ++kk) {
-            const uint32_t soff = (uint32_t)(4 * kk) * st_b;
-#pragma unroll
-            for (int c = 0; c < C; ++c) {
-                const uint32_t vo = (kk >= NK - 4 && 4 * kk + kl >= N) ? kOffNone : vin[c];
-                bx[c][kk] = bload<T>(rin, vo, soff);
-            }
-        }
+    auto mma_store = [&](const T (&bx)[C][NK], int st) {
+        const int64_t b0 = c0 + 16 * C * (wave + G * st);
+        // M is read from LDS in every step: an opaque zero offset keeps the
+        // compiler from merging the reads of all steps into registers held
+        // across the chunk (64 more registers, fewer wavefronts per SIMD)
+        int zoff;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(zoff));
+        const T *Mz = Ms + zoff;
         v4 acc[C][NTI];
 #pragma unroll
         for (int c = 0; c < C; ++c)
@@ -462,7 +476,7 @@ __device__ __forceinline__ void direct_chunk(const T *__restrict__ in, const Vie
         for (int kk = 0; kk < NK; ++kk)
 #pragma unroll
             for (int ti = 0; ti < NTI; ++ti) {
-                const T am = Ms[(16 * ti + l16) * LDM + 4 * kk + kl];
+                const T am = Mz[(16 * ti + l16) * LDM + 4 * kk + kl];
 #pragma unroll
                 for (int c = 0; c < C; ++c) {
                     if constexpr (sizeof(T) == 4)
@@ -474,15 +488,27 @@ __device__ __forceinline__ void direct_chunk(const T *__restrict__ in, const Vie
         // rows below NMAX - 16 exist for every n3 of the class; the last block
         // drops rows past n3
 #pragma unroll
-        for (int c = 0; c < C; ++c)
+        for (int c = 0; c < C; ++c) {
+            const int64_t i = b0 + l16 + 16 * c;
+            const uint32_t vout = i < cend ? (uint32_t)i * SZ + orow * mp_b : kOffNone;
 #pragma unroll
             for (int ti = 0; ti < NTI; ++ti)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const uint32_t r0 = 16 * ti + (sizeof(T) == 4 ? v : 4 * v);  // row of lane group 0
-                    const uint32_t vo = (ti == NTI - 1 && (int)(r0 + orow) >= N) ? kOffNone : vout[c];
+                    const uint32_t vo = (ti == NTI - 1 && (int)(r0 + orow) >= N) ? kOffNone : vout;
                     bstore<T>(acc[c][ti][v], rout, vo, r0 * mp_b);
                 }
+        }
+    };
+    // steps in pairs through two register buffers; a wavefront's steps past
+    // the end of a short chunk read tube c0 and store nothing
+#pragma unroll
+    for (int st = 0; st < NB; st += 2) {
+        load_step(xb, st + 1);
+        mma_store(xa, st);
+        if (st + 2 < NB) load_step(xa, st + 2);
+        mma_store(xb, st + 1);
     }
 }
 
