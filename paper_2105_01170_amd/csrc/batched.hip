@@ -7,7 +7,7 @@
 //  * k_bgram (persistent, HBM + FP64 MFMA): wavefronts pull faces from an
 //    atomic queue and form G = X X^T in FP64 (exact products of FP32 data)
 //    from operands loaded straight into registers; G goes to the workspace.
-//  * k_bcore (one wavefront per face): rank-revealing pivoted Cholesky
+//  * k_bcore16 / k_bcore32 (one wavefront per face): rank-revealing pivoted Cholesky
 //    P G P^T = R^T R + S (left-looking, largest remaining diagonal first),
 //    stopped once trace(S) is below the rule's tolerance; Jacobi
 //    eigensolver of R R^T (at most 32 x 32); rank rule with the discarded
@@ -178,8 +178,15 @@ __global__ __launch_bounds__(BT) void k_bgram(const Item *__restrict__ items, in
 // ---------------------------------------------------------------- core
 // One wavefront per face.  mode/kcap/tau: the rank rule; stop tolerance of
 // the pivoted Cholesky: 1e-3 tau^2 trace(G) (ENERGY), 1e-15 trace(G) (FIXED).
-__global__ __launch_bounds__(64) void k_bcore(const Item *__restrict__ items, int mode, int kcap,
-                                              double tau, int max_sweeps) {
+// RXT: the most pivots (and the Jacobi size) this instance holds in LDS.  The
+// 16-pivot instance needs a third of the LDS of the 32-pivot one, so more
+// faces share a CU; a face whose Cholesky would go past 16 pivots is deferred
+// (nothing written, returns true) to the 32-pivot instance.  Up to the 16th
+// pivot both take the same steps, and the Jacobi rounds depend only on the
+// order r, so a face finished by either gets the same bits.
+template <int RXT>
+__device__ bool core_face(const Item &it, int mode, int kcap, double tau, int max_sweeps, bool may_defer) {
+    constexpr int RX = RXT;
     constexpr int LD = jacobi_ld<RX>(), LDE = jacobi_ld<RX>();
     __shared__ double R[RX * MX];  // R[t * MX + i]: row t of the factor, column i
     __shared__ __align__(16) double Hb[2][RX * LD];
@@ -192,9 +199,9 @@ __global__ __launch_bounds__(64) void k_bcore(const Item *__restrict__ items, in
     __shared__ int perm[RX];
     __shared__ int rflag[3];
     const int lane = threadIdx.x;
-    const Item it = items[blockIdx.x];
     const int m = it.m;
     const double *G = it.G;
+    __syncthreads();  // the previous face of this workgroup is done with LDS
 
     // ---- pivoted Cholesky
     const double gii = lane < m ? G[lane * m + lane] : 0.0;
@@ -206,7 +213,7 @@ __global__ __launch_bounds__(64) void k_bcore(const Item *__restrict__ items, in
     const int rlim = m < RX ? m : RX;
     __syncthreads();
     int r = 0;
-    for (int j = 0; j < rlim; ++j) {
+    for (int j = 0;; ++j) {
         const double d = chosen[lane] ? -1.0 : diag[lane];
         const double rem = wave_sum(fmax(d, 0.0));
         if (!(rem > stop)) break;
@@ -223,6 +230,11 @@ __global__ __launch_bounds__(64) void k_bcore(const Item *__restrict__ items, in
             }
         }
         if (!(best > 0.0)) break;
+        if (j == rlim) {
+            // a further pivot would be taken: with more room, defer the face
+            if (may_defer && rlim < (m < 32 ? m : 32)) return true;
+            break;
+        }
         const double rjj = sqrt(best), inv = 1.0 / rjj;
         if (lane < m && !chosen[lane] && lane != q) {
             double sacc = G[q * m + lane];
@@ -326,6 +338,25 @@ __global__ __launch_bounds__(64) void k_bcore(const Item *__restrict__ items, in
         if (it.cert) *it.cert = sqrt(fmax(tail_k, 0.0));
         if (it.fro) *it.fro = sqrt(trG);
         if (it.info) *it.info = code;
+    }
+    return false;
+}
+
+// first pass: every face with at most 16 pivots; defer[f] = 1 marks a face
+// left to the second pass
+__global__ __launch_bounds__(64) void k_bcore16(const Item *__restrict__ items, int mode, int kcap, double tau,
+                                                int max_sweeps, int *__restrict__ defer) {
+    const bool d = core_face<16>(items[blockIdx.x], mode, kcap, tau, max_sweeps, true);
+    if (threadIdx.x == 0) defer[blockIdx.x] = d ? 1 : 0;
+}
+
+// second pass (or the only one): the faces marked in defer (every face when
+// defer is null), up to 32 pivots; workgroups stride over the face table
+__global__ __launch_bounds__(64) void k_bcore32(const Item *__restrict__ items, int nitems, int mode, int kcap,
+                                                double tau, int max_sweeps, const int *__restrict__ defer) {
+    for (int idx = blockIdx.x; idx < nitems; idx += gridDim.x) {
+        if (defer && defer[idx] == 0) continue;
+        core_face<32>(items[idx], mode, kcap, tau, max_sweeps, false);
     }
 }
 
@@ -446,14 +477,15 @@ __global__ void k_bzero(int *__restrict__ c) {
 constexpr size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t items, gram, counters, total;
+    size_t items, gram, defer, counters, total;
 };
 
 Layout layout(int64_t nitems, int64_t gram_doubles) {
     Layout L;
     L.items = 0;
     L.gram = L.items + al256(sizeof(Item) * nitems);
-    L.counters = L.gram + al256(sizeof(double) * gram_doubles);
+    L.defer = L.gram + al256(sizeof(double) * gram_doubles);
+    L.counters = L.defer + al256(sizeof(int32_t) * nitems);
     L.total = L.counters + 256;
     return L;
 }
@@ -471,6 +503,7 @@ struct tsvdm_batched_plan_s {
     int32_t nmat = 0, nitems = 0, num_cu = 0;
     Item *d_items = nullptr;
     int32_t *d_counter = nullptr;
+    int32_t *d_defer = nullptr;
     int mode = 0, kcap = 0, max_sweeps = 30;
     double tau = 0.0;
     Cfg cfg{2, 16, 2, 0};
@@ -537,9 +570,21 @@ tsvdm_status launch(const tsvdm_batched_plan_s *P, const Cfg &cfg, hipStream_t s
         else
             TSVDM_LAUNCH("batched_gram", k_bgram<8>, grid, dim3(BT), 0, s, P->d_items, P->nitems, P->d_counter);
     }
-    if (which & 2)
-        TSVDM_LAUNCH("batched_core", k_bcore, dim3((unsigned)P->nitems), dim3(64), 0, s, P->d_items, P->mode,
-                     P->kcap, P->tau, P->max_sweeps);
+    if (which & 2) {
+        // ENERGY: a 16-pivot pass over every face, then a 32-pivot pass over
+        // the faces it deferred; FIXED (the Cholesky runs to the numerical
+        // rank): the 32-pivot pass over every face
+        if (P->mode == TSVDM_RANK_ENERGY) {
+            TSVDM_LAUNCH("batched_core", k_bcore16, dim3((unsigned)P->nitems), dim3(64), 0, s, P->d_items,
+                         P->mode, P->kcap, P->tau, P->max_sweeps, P->d_defer);
+            const unsigned g2 = (unsigned)std::min<int64_t>(P->nitems, (int64_t)P->num_cu * 4);
+            TSVDM_LAUNCH("batched_core_deferred", k_bcore32, dim3(g2), dim3(64), 0, s, P->d_items, P->nitems,
+                         P->mode, P->kcap, P->tau, P->max_sweeps, (const int *)P->d_defer);
+        } else {
+            TSVDM_LAUNCH("batched_core", k_bcore32, dim3((unsigned)P->nitems), dim3(64), 0, s, P->d_items,
+                         P->nitems, P->mode, P->kcap, P->tau, P->max_sweeps, (const int *)nullptr);
+        }
+    }
     if (which & 4) {
         const dim3 grid((unsigned)(P->num_cu * cfg.vec_wpc));
         TSVDM_LAUNCH("batched_vec", k_bvec, grid, dim3(BT), 0, s, P->d_items, P->nitems, P->d_counter + 1);
@@ -652,6 +697,7 @@ tsvdm_status tsvdm_batched_plan_create(int32_t nmat, const tsvdm_tensor *Xhat,
     P->num_cu = ncu > 0 ? ncu : 1;
     P->d_items = reinterpret_cast<Item *>(base + L.items);
     P->d_counter = reinterpret_cast<int32_t *>(base + L.counters);
+    P->d_defer = reinterpret_cast<int32_t *>(base + L.defer);
     P->mode = o->rank_mode;
     P->kcap = o->k;
     P->tau = o->tau;

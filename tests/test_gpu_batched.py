@@ -75,6 +75,35 @@ def test_uneven_kronecker_batch_matches_oracle(mode):
                         ref["s"][:, f], ref["ranks"][f], ref["That"][:, :, f], ref["fro2"][f], mode)
 
 
+def test_energy_faces_needing_more_than_16_pivots():
+    """Faces with singular values 10^(-i/3.3): the energy rule keeps 14 of them
+    (the discarded energy at ranks 13 and 14 is 1.32 and 0.33 times the bound,
+    clear of it), but the pivoted Cholesky stops only after about 19 pivots
+    (its trace tolerance is 1e-3 tau^2), so these faces take the 32-pivot
+    pass, in one batch with Kronecker faces that finish within 16; all match
+    the oracle."""
+    g = np.random.default_rng(11)
+    m, p, nf = 40, 50, 3
+    graded = np.empty((m, p, nf))
+    sig = 10.0 ** (-np.arange(m) / 3.3)
+    for f in range(nf):
+        q1, _ = np.linalg.qr(g.standard_normal((m, m)))
+        q2, _ = np.linalg.qr(g.standard_normal((p, m)))
+        graded[:, :, f] = (q1 * sig) @ q2.T
+    xhs = [np.asfortranarray(graded.astype(np.float32).astype(np.float64))] + _kron_tensors(3, 6, 20, 2, 6, 1e-6,
+                                                                                          salt=4)
+    bt, _, Fs = _run(xhs, rank_mode=C.RANK_ENERGY, k=16, tau=TAU, kmax=16)
+    for i, (xh, F) in enumerate(zip(xhs, Fs)):
+        U, S, V, ranks, cert, fro, info = _host(F, xh.shape)
+        ref = oracle.tsvdm_truncate_faces(xh, "energy", 16, TAU)
+        assert np.all(info == 0)
+        if i == 0:
+            assert np.all(ranks == 14)
+        for f in range(xh.shape[2]):
+            _check_face(xh[:, :, f], U[:, :, f], S[:, f], V[:, :, f], ranks[f], cert[f], fro[f],
+                        ref["s"][:, f], ref["ranks"][f], ref["That"][:, :, f], ref["fro2"][f], "energy")
+
+
 def test_edge_faces_single_row_zero_face_and_cap():
     """A one-row tensor, an all-zero face, a tensor of 64-row faces of full
     rank (the energy target cannot be met within the cap: rank = cap, flag 4,
