@@ -311,6 +311,12 @@ tsvdm_status tsvdm_batched_autotune(tsvdm_batched_plan *plan, void *stream);
  * (here or through the table). */
 tsvdm_status tsvdm_batched_config(const tsvdm_batched_plan *plan, int32_t cfg[4]);
 
+/* Sets the plan's launch configuration (cfg[0..2] as above; cfg[3] ignored,
+ * the result reads as not tuned).  1 <= cfg[0], cfg[2] <= 16, cfg[1] 16 or
+ * 32, else TSVDM_EINVAL and the plan is unchanged.  The results do not depend
+ * on the configuration. */
+tsvdm_status tsvdm_batched_set_config(tsvdm_batched_plan *plan, const int32_t cfg[4]);
+
 /* Releases the host plan (the workspace stays the caller's). NULL is allowed. */
 void tsvdm_batched_plan_destroy(tsvdm_batched_plan *plan);
 

@@ -193,6 +193,9 @@ class BatchedTruncator:
     def config(self) -> list:
         return C.tsvdm_batched_config(self.plan)
 
+    def set_config(self, cfg) -> None:
+        C.tsvdm_batched_set_config(self.plan, cfg)
+
     def __del__(self):
         plan = getattr(self, "plan", None)
         if plan:

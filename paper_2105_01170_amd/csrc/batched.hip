@@ -350,14 +350,12 @@ __global__ __launch_bounds__(64) void k_bcore16(const Item *__restrict__ items, 
     if (threadIdx.x == 0) defer[blockIdx.x] = d ? 1 : 0;
 }
 
-// second pass (or the only one): the faces marked in defer (every face when
-// defer is null), up to 32 pivots; workgroups stride over the face table
-__global__ __launch_bounds__(64) void k_bcore32(const Item *__restrict__ items, int nitems, int mode, int kcap,
-                                                double tau, int max_sweeps, const int *__restrict__ defer) {
-    for (int idx = blockIdx.x; idx < nitems; idx += gridDim.x) {
-        if (defer && defer[idx] == 0) continue;
-        core_face<32>(items[idx], mode, kcap, tau, max_sweeps, false);
-    }
+// second pass (or the only one): workgroup f takes face f if defer marks it
+// (every face when defer is null), up to 32 pivots; the others exit at once
+__global__ __launch_bounds__(64) void k_bcore32(const Item *__restrict__ items, int mode, int kcap, double tau,
+                                                int max_sweeps, const int *__restrict__ defer) {
+    if (defer && defer[blockIdx.x] == 0) return;
+    core_face<32>(items[blockIdx.x], mode, kcap, tau, max_sweeps, false);
 }
 
 // ---------------------------------------------------------------- V
@@ -442,6 +440,9 @@ __device__ __forceinline__ void vec_face(const Item &it, int lane) {
     }
 }
 
+// NJ = 1 serves batches whose factors all have kmax <= 16 (121 registers, four
+// wavefronts per SIMD); NJ = 2 any kmax <= 32.
+template <int NJ>
 __global__ __launch_bounds__(BT) void k_bvec(const Item *__restrict__ items, int nitems,
                                              int *__restrict__ counter) {
     const int lane = threadIdx.x & 63;
@@ -451,21 +452,11 @@ __global__ __launch_bounds__(BT) void k_bvec(const Item *__restrict__ items, int
         idx = __builtin_amdgcn_readfirstlane(__shfl(idx, 0, 64));
         if (idx >= nitems) break;
         const Item it = items[idx];
-        const int nt = (__builtin_amdgcn_readfirstlane(it.m) + 15) >> 4;
-        if (__builtin_amdgcn_readfirstlane(it.kmax) <= 16) {
-            switch (nt) {
-                case 1: vec_face<1, 1>(it, lane); break;
-                case 2: vec_face<2, 1>(it, lane); break;
-                case 3: vec_face<3, 1>(it, lane); break;
-                default: vec_face<4, 1>(it, lane); break;
-            }
-        } else {
-            switch (nt) {
-                case 1: vec_face<1, 2>(it, lane); break;
-                case 2: vec_face<2, 2>(it, lane); break;
-                case 3: vec_face<3, 2>(it, lane); break;
-                default: vec_face<4, 2>(it, lane); break;
-            }
+        switch ((__builtin_amdgcn_readfirstlane(it.m) + 15) >> 4) {
+            case 1: vec_face<1, NJ>(it, lane); break;
+            case 2: vec_face<2, NJ>(it, lane); break;
+            case 3: vec_face<3, NJ>(it, lane); break;
+            default: vec_face<4, NJ>(it, lane); break;
         }
     }
 }
@@ -500,13 +491,13 @@ std::map<uint64_t, Cfg> g_tune;
 }  // namespace
 
 struct tsvdm_batched_plan_s {
-    int32_t nmat = 0, nitems = 0, num_cu = 0;
+    int32_t nmat = 0, nitems = 0, num_cu = 0, kmax_max = 0;
     Item *d_items = nullptr;
     int32_t *d_counter = nullptr;
     int32_t *d_defer = nullptr;
     int mode = 0, kcap = 0, max_sweeps = 30;
     double tau = 0.0;
-    Cfg cfg{2, 16, 2, 0};
+    Cfg cfg{1, 16, 1, 0};
     uint64_t sig = 0;
 };
 
@@ -577,17 +568,19 @@ tsvdm_status launch(const tsvdm_batched_plan_s *P, const Cfg &cfg, hipStream_t s
         if (P->mode == TSVDM_RANK_ENERGY) {
             TSVDM_LAUNCH("batched_core", k_bcore16, dim3((unsigned)P->nitems), dim3(64), 0, s, P->d_items,
                          P->mode, P->kcap, P->tau, P->max_sweeps, P->d_defer);
-            const unsigned g2 = (unsigned)std::min<int64_t>(P->nitems, (int64_t)P->num_cu * 4);
-            TSVDM_LAUNCH("batched_core_deferred", k_bcore32, dim3(g2), dim3(64), 0, s, P->d_items, P->nitems,
-                         P->mode, P->kcap, P->tau, P->max_sweeps, (const int *)P->d_defer);
+            TSVDM_LAUNCH("batched_core_deferred", k_bcore32, dim3((unsigned)P->nitems), dim3(64), 0, s,
+                         P->d_items, P->mode, P->kcap, P->tau, P->max_sweeps, (const int *)P->d_defer);
         } else {
             TSVDM_LAUNCH("batched_core", k_bcore32, dim3((unsigned)P->nitems), dim3(64), 0, s, P->d_items,
-                         P->nitems, P->mode, P->kcap, P->tau, P->max_sweeps, (const int *)nullptr);
+                         P->mode, P->kcap, P->tau, P->max_sweeps, (const int *)nullptr);
         }
     }
     if (which & 4) {
         const dim3 grid((unsigned)(P->num_cu * cfg.vec_wpc));
-        TSVDM_LAUNCH("batched_vec", k_bvec, grid, dim3(BT), 0, s, P->d_items, P->nitems, P->d_counter + 1);
+        if (P->kmax_max <= 16)
+            TSVDM_LAUNCH("batched_vec", k_bvec<1>, grid, dim3(BT), 0, s, P->d_items, P->nitems, P->d_counter + 1);
+        else
+            TSVDM_LAUNCH("batched_vec", k_bvec<2>, grid, dim3(BT), 0, s, P->d_items, P->nitems, P->d_counter + 1);
     }
     TSVDM_LAUNCH_CHECK("batched truncate");
     return TSVDM_OK;
@@ -694,6 +687,7 @@ tsvdm_status tsvdm_batched_plan_create(int32_t nmat, const tsvdm_tensor *Xhat,
     }
     P->nmat = nmat;
     P->nitems = (int32_t)n;
+    for (int32_t i = 0; i < nmat; ++i) P->kmax_max = std::max(P->kmax_max, (int32_t)F[i].kmax);
     P->num_cu = ncu > 0 ? ncu : 1;
     P->d_items = reinterpret_cast<Item *>(base + L.items);
     P->d_counter = reinterpret_cast<int32_t *>(base + L.counters);
@@ -735,7 +729,7 @@ tsvdm_status tsvdm_batched_autotune(tsvdm_batched_plan *plan, void *stream) {
     if (e != hipSuccess) return hip_check(e, "batched_autotune: events");
     auto time_cfg = [&](const Cfg &c, int which, float *best) -> tsvdm_status {
         *best = 1e30f;
-        for (int rep = 0; rep < 3; ++rep) {
+        for (int rep = 0; rep < 5; ++rep) {
             hipError_t er = hipEventRecord(a, s);
             if (er != hipSuccess) return hip_check(er, "batched_autotune: record");
             tsvdm_status st2 = launch(plan, c, s, which);
@@ -749,6 +743,9 @@ tsvdm_status tsvdm_batched_autotune(tsvdm_batched_plan *plan, void *stream) {
         }
         return TSVDM_OK;
     };
+    // each candidate is timed over the whole batch (queue reset, Gram, core,
+    // V): a kernel timed alone, with the others' traffic absent, favoured
+    // configurations that are slower in the sequence
     Cfg best = plan->cfg;
     float tg = 1e30f, tv = 1e30f;
     const int wpcs[3] = {1, 2, 4}, kcs[2] = {16, 32};
@@ -758,7 +755,7 @@ tsvdm_status tsvdm_batched_autotune(tsvdm_batched_plan *plan, void *stream) {
             c.gram_wpc = w;
             c.gram_kc = kc;
             float t = 0.0f;
-            st = time_cfg(c, 1, &t);
+            st = time_cfg(c, 7, &t);
             if (st != TSVDM_OK) break;
             if (t < tg) {
                 tg = t;
@@ -771,7 +768,7 @@ tsvdm_status tsvdm_batched_autotune(tsvdm_batched_plan *plan, void *stream) {
             Cfg c = best;
             c.vec_wpc = w;
             float t = 0.0f;
-            st = time_cfg(c, 4, &t);
+            st = time_cfg(c, 7, &t);
             if (st != TSVDM_OK) break;
             if (t < tv) {
                 tv = t;
@@ -800,6 +797,19 @@ tsvdm_status tsvdm_batched_config(const tsvdm_batched_plan *plan, int32_t cfg[4]
     cfg[1] = plan->cfg.gram_kc;
     cfg[2] = plan->cfg.vec_wpc;
     cfg[3] = plan->cfg.tuned;
+    return TSVDM_OK;
+}
+
+tsvdm_status tsvdm_batched_set_config(tsvdm_batched_plan *plan, const int32_t cfg[4]) {
+    if (!plan || !cfg) {
+        set_error("batched_set_config: NULL argument");
+        return TSVDM_EINVAL;
+    }
+    if (cfg[0] < 1 || cfg[0] > 16 || (cfg[1] != 16 && cfg[1] != 32) || cfg[2] < 1 || cfg[2] > 16) {
+        set_error("batched_set_config: need 1 <= cfg[0], cfg[2] <= 16 and cfg[1] in {16, 32}");
+        return TSVDM_EINVAL;
+    }
+    plan->cfg = Cfg{cfg[0], cfg[1], cfg[2], 0};
     return TSVDM_OK;
 }
 

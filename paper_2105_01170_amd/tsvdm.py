@@ -55,7 +55,7 @@ EXPORTS = ["tsvdm_version", "tsvdm_last_error", "tsvdm_tensor_from_blockmat",
            "tsvdm_truncate", "tsvdm_apply_workspace_size", "tsvdm_apply", "tsvdm_timing_enable",
            "tsvdm_timing_count", "tsvdm_timing_get", "tsvdm_batched_workspace_size",
            "tsvdm_batched_plan_create", "tsvdm_truncate_batched", "tsvdm_batched_autotune",
-           "tsvdm_batched_config", "tsvdm_batched_plan_destroy", "tsvdm_mlp_nparams",
+           "tsvdm_batched_config", "tsvdm_batched_set_config", "tsvdm_batched_plan_destroy", "tsvdm_mlp_nparams",
            "tsvdm_mlp_forward", "tsvdm_mlp_train_workspace_size", "tsvdm_mlp_gradient",
            "tsvdm_mlp_train_step", "tsvdm_f32_to_f16", "tsvdm_rank_features_workspace_size",
            "tsvdm_rank_features", "tsvdm_truncate_learned_workspace_size", "tsvdm_truncate_learned",
@@ -120,6 +120,8 @@ def lib():
         L.tsvdm_batched_autotune.argtypes = [vp, vp]
         L.tsvdm_batched_config.restype = i32
         L.tsvdm_batched_config.argtypes = [vp, P(i32)]
+        L.tsvdm_batched_set_config.restype = i32
+        L.tsvdm_batched_set_config.argtypes = [vp, P(i32)]
         L.tsvdm_batched_plan_destroy.restype = None
         L.tsvdm_batched_plan_destroy.argtypes = [vp]
         L.tsvdm_mlp_nparams.restype = i64
@@ -268,6 +270,11 @@ def tsvdm_batched_config(plan: int) -> list:
     cfg = (ctypes.c_int32 * 4)()
     _check(lib().tsvdm_batched_config(plan, cfg))
     return list(cfg)
+
+
+def tsvdm_batched_set_config(plan: int, cfg) -> None:
+    arr = (ctypes.c_int32 * 4)(*[int(v) for v in list(cfg)[:3]], 0)
+    _check(lib().tsvdm_batched_set_config(plan, arr))
 
 
 def tsvdm_batched_plan_destroy(plan: int):

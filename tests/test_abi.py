@@ -258,3 +258,8 @@ def test_transform_batched_validation_and_workspace():
     assert C.tsvdm_transform_batched_workspace_size([], []) == 0
     plan = C.tsvdm_transform_plan_create([], 1, [], [], 0, 0)
     C.tsvdm_transform_plan_destroy(plan)
+
+
+def test_batched_set_config_rejects_null_plan():
+    arr = (ctypes.c_int32 * 4)(2, 16, 2, 0)
+    assert C.lib().tsvdm_batched_set_config(None, arr) == C.EINVAL

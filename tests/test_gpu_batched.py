@@ -104,6 +104,24 @@ def test_energy_faces_needing_more_than_16_pivots():
                         ref["s"][:, f], ref["ranks"][f], ref["That"][:, :, f], ref["fro2"][f], "energy")
 
 
+def test_fixed_rank_above_16():
+    """FIXED rank 20 with kmax 24 (the V kernel for ranks above 16): random
+    faces of at most 32 rows, so the pivoted Cholesky is exact and the
+    factors match the oracle's truncated SVD."""
+    g = np.random.default_rng(13)
+    xhs = [np.asfortranarray(g.standard_normal(sh).astype(np.float32).astype(np.float64))
+           for sh in [(30, 50, 2), (21, 37, 3), (32, 20, 1)]]
+    bt, _, Fs = _run(xhs, rank_mode=C.RANK_FIXED, k=20, tau=0.5, kmax=24)
+    for xh, F in zip(xhs, Fs):
+        U, S, V, ranks, cert, fro, info = _host(F, xh.shape)
+        ref = oracle.tsvdm_truncate_faces(xh, "fixed", 20, TAU)
+        assert np.all(info == 0) and np.all(ranks == 20)
+        assert np.all(U[:, 20:, :] == 0) and np.all(V[:, 20:, :] == 0)
+        for f in range(xh.shape[2]):
+            _check_face(xh[:, :, f], U[:, :, f], S[:, f], V[:, :, f], ranks[f], cert[f], fro[f],
+                        ref["s"][:, f], ref["ranks"][f], ref["That"][:, :, f], ref["fro2"][f], "fixed")
+
+
 def test_edge_faces_single_row_zero_face_and_cap():
     """A one-row tensor, an all-zero face, a tensor of 64-row faces of full
     rank (the energy target cannot be met within the cap: rank = cap, flag 4,
