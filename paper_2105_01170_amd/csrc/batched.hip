@@ -361,26 +361,28 @@ __global__ __launch_bounds__(64) void k_bcore32(const Item *__restrict__ items, 
 // ---------------------------------------------------------------- V
 // One wavefront per face: V(col, j) = sum_i X(i, col) W(i, j) with
 // W = U diag(1/sigma) (zero in the columns j >= rank), as FP32 16x16x4 MFMAs
-// D = W^T X over 16 ranks by 16 columns of the face.  W^T is the A operand,
-// formed once per face in registers: lane (l16, kl) holds W(4kk + kl, 16jb + l16)
-// for every group kk of four rows, zero for rows past m.  X is the B operand,
-// loaded straight from the face: lane (l16, kl) of column block c holds
-// X(4kk + kl, col) for col = 32 step + 16c + l16, at byte offset
-// 4 (kl + m col) + 16 kk (the group in the instruction's offset field).  A row
-// past m lands on the next column of the same face (finite, times a zero of
-// W); anything past the face, including columns past p, reads zero through
-// the buffer resource.  Stores of columns past p or ranks past kmax get bit 31
-// of the offset and are dropped.  Steps of 32 columns are double-buffered.
+// D = W^T X over 16 ranks by 16 columns of the face.  The contraction runs
+// over the rows in groups of 16: lane (l16, kl) = (lane % 16, lane / 16) loads
+// rows 16 kk + 4 kl .. 16 kk + 4 kl + 3 of column col (one 16-byte load per
+// group, col = 32 step + 16 c + l16), and MFMA step (kk, r) takes row
+// 16 kk + 4 kl + r of lane (l16, kl) as its B operand; the A operand, formed
+// once per face in registers, holds W(16 kk + 4 kl + r, 16 jb + l16) to match
+// (zero for rows past m).  A row past m lands on the next column of the same
+// face (finite, times a zero of W); bytes past the face, including columns
+// past p, read as zero (the buffer resource checks each dword).  Stores of
+// columns past p or ranks past kmax get bit 31 of the offset and are dropped.
+// Steps of 32 columns are double-buffered.
 template <int NT, int NJ>
 __device__ __forceinline__ void vec_face(const Item &it, int lane) {
-    constexpr int NK = 4 * NT, C = 2;
+    constexpr int C = 2;
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     const int m = __builtin_amdgcn_readfirstlane(it.m), p = __builtin_amdgcn_readfirstlane(it.p);
     const int kmax = __builtin_amdgcn_readfirstlane(it.kmax);
     const int kf = __builtin_amdgcn_readfirstlane(*uniform_ptr(it.rank));
     const int kl = lane >> 4, l16 = lane & 15;
     const float *U = uniform_ptr(it.U);
     const double *S = uniform_ptr(it.S);
-    float w[NJ][NK];
+    float w[NJ][NT][4];
 #pragma unroll
     for (int jb = 0; jb < NJ; ++jb) {
         const int j = 16 * jb + l16;
@@ -390,33 +392,49 @@ __device__ __forceinline__ void vec_face(const Item &it, int lane) {
             isg = sv > 0.0 ? (float)(1.0 / sv) : 0.0f;
         }
 #pragma unroll
-        for (int kk = 0; kk < NK; ++kk) {
-            const int i = 4 * kk + kl;
-            w[jb][kk] = (j < kf && i < m) ? U[i + (int64_t)m * j] * isg : 0.0f;
-        }
+        for (int kk = 0; kk < NT; ++kk)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = 16 * kk + 4 * kl + r;
+                w[jb][kk][r] = (j < kf && i < m) ? U[i + (int64_t)m * j] * isg : 0.0f;
+            }
     }
     const __amdgpu_buffer_rsrc_t rx =
         __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(const_cast<float *>(it.X)), 0, m * p * 4, 0x00020000);
     const __amdgpu_buffer_rsrc_t rv =
         __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(it.V), 0, p * kmax * 4, 0x00020000);
-    auto load_step = [&](float (&x)[C][NK], int st) {
+    auto load_step = [&](u32x4 (&x)[C][NT], int st) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const uint32_t vo = (uint32_t)(kl + m * (32 * st + 16 * c + l16)) * 4u;
+            const uint32_t vo = (uint32_t)(4 * kl + m * (32 * st + 16 * c + l16)) * 4u;
 #pragma unroll
-            for (int kk = 0; kk < NK; ++kk) x[c][kk] = bload_f32(rx, vo + 16u * kk, 0);
+            for (int kk = 0; kk < NT; ++kk)
+                x[c][kk] = __builtin_amdgcn_raw_buffer_load_b128(rx, (int)(vo + 64u * kk), 0, 0);
         }
     };
-    auto mma_store = [&](const float (&x)[C][NK], int st) {
+    auto mma_store = [&](const u32x4 (&x)[C][NT], int st) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int col = 32 * st + 16 * c + l16;
+            // the four rows of each group as scalars (a bit cast of a vector
+            // element itself was compiled as a cast of element 0)
+            float xs[NT][4];
+#pragma unroll
+            for (int kk = 0; kk < NT; ++kk) {
+                const uint32_t e0 = x[c][kk].x, e1 = x[c][kk].y, e2 = x[c][kk].z, e3 = x[c][kk].w;
+                xs[kk][0] = __builtin_bit_cast(float, e0);
+                xs[kk][1] = __builtin_bit_cast(float, e1);
+                xs[kk][2] = __builtin_bit_cast(float, e2);
+                xs[kk][3] = __builtin_bit_cast(float, e3);
+            }
 #pragma unroll
             for (int jb = 0; jb < NJ; ++jb) {
                 f32x4 acc = f32x4{0, 0, 0, 0};
 #pragma unroll
-                for (int kk = 0; kk < NK; ++kk)
-                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w[jb][kk], x[c][kk], acc, 0, 0, 0);
+                for (int kk = 0; kk < NT; ++kk)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(w[jb][kk][r], xs[kk][r], acc, 0, 0, 0);
                 // FP32 16x16x4 output: rank 4 (lane/16) + v, column lane%16
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
@@ -430,7 +448,7 @@ __device__ __forceinline__ void vec_face(const Item &it, int lane) {
         }
     };
     const int nsteps = (p + 31) / 32;
-    float xa[C][NK], xb[C][NK];
+    u32x4 xa[C][NT], xb[C][NT];
     load_step(xa, 0);
     for (int st = 0; st < nsteps; st += 2) {
         load_step(xb, st + 1);
