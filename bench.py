@@ -111,6 +111,21 @@ def measured_traffic(kernel):
     return None
 
 
+def calib_copy(args, dev):
+    """A plain device copy of --calib-copy-mib MiB (three times): under rocprofv3
+    its FETCH_SIZE / WRITE_SIZE give the scale of the HBM counters."""
+    if args.calib_copy_mib <= 0:
+        return
+    import torch
+    n = args.calib_copy_mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def uneven_main(args):
     """The uneven batch: 256 matrices A_i = sum_{r<r_i} B_r kron C_r with factor
     sizes s_B, s_C log-uniform in [16, 64] and r_i uniform in 2..16; each is
@@ -129,6 +144,7 @@ def uneven_main(args):
 
     dev = "cuda:0"
     torch.cuda.set_device(0)
+    calib_copy(args, dev)
     t_setup = time.time()
     mats = synth.uneven_batch(count=256, noise=0.0, form=False)
     As, views, xhs, shapes = [], [], [], []
@@ -416,14 +432,7 @@ def main():
         api.transform(X, m, p, n3, C.M_DCT2, +1, out=xh)
         return tr(xh)
 
-    if args.calib_copy_mib > 0:  # a copy kernel of known size for the HBM counter scale
-        n = args.calib_copy_mib * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    calib_copy(args, dev)
     for _ in range(args.warmup):
         F = step()
     torch.cuda.synchronize()
