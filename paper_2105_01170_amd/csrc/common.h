@@ -46,6 +46,45 @@ struct View {
     }
 };
 
+// Division of 32-bit n < 2^31 by an invariant d >= 1 (Granlund and Montgomery,
+// "Division by invariant integers using multiplication", 1994): with
+// l = ceil(log2 d) and mul = floor(2^32 (2^l - d) / d) + 1 (< 2^32),
+// floor(n / d) = (mulhi(mul, n) + n) >> l, the sum below 2^32 since n < 2^31.
+struct UDiv {
+    uint32_t d, mul, sh;
+};
+__host__ __device__ inline UDiv make_udiv(uint32_t d) {
+    uint32_t l = 0;
+    while (l < 31 && (1u << l) < d) ++l;
+    const uint64_t mul = ((((uint64_t)1 << l) - d) << 32) / d + 1;
+    return UDiv{d, (uint32_t)mul, l};
+}
+__device__ __forceinline__ uint32_t udiv(uint32_t n, const UDiv &u) {
+    return (__umulhi(u.mul, n) + n) >> u.sh;
+}
+
+// A View whose element offsets are below 2^31 (direct_span), with the tube
+// index split by invariant-divisor multiplication instead of 64-bit division.
+struct View32 {
+    UDiv m, bs;  // bs.d = 0: no block split
+    uint32_t s_a, s_b, s_bk;
+    __device__ __forceinline__ uint32_t tube_base(uint32_t i) const {
+        const uint32_t b = udiv(i, m), a = i - b * m.d;
+        if (bs.d == 0) return a * s_a + b * s_b;
+        const uint32_t k = udiv(b, bs);
+        return a * s_a + (b - k * bs.d) * s_b + k * s_bk;
+    }
+};
+__device__ __forceinline__ View32 make_view32(const View &v) {
+    View32 w;
+    w.m = make_udiv((uint32_t)v.m);
+    w.bs = v.bsplit > 0 ? make_udiv((uint32_t)v.bsplit) : UDiv{0, 0, 0};
+    w.s_a = (uint32_t)v.s_a;
+    w.s_b = (uint32_t)v.s_b;
+    w.s_bk = (uint32_t)v.s_bk;
+    return w;
+}
+
 // Direct (matrix-core) transform of tubes of length n3 <= 64: one workgroup
 // per chunk of kDirectChunk consecutive tubes; the length class is
 // direct_class(n3), the multiple of 16 at or above n3.
@@ -94,7 +133,7 @@ struct DirectItem {
 };
 // chunks of one precision and one length class (nmax = direct_class(N)), one launch
 struct TransformGroup {
-    bool dbl;
+    bool dbl, dense;
     int nmax;
     const DirectItem *items;
     int64_t count;

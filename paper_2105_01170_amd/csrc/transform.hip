@@ -406,6 +406,7 @@ __device__ __forceinline__ void direct_chunk(const T *__restrict__ in, const Vie
     const uint32_t mp_b = (uint32_t)mp * SZ;        // byte stride of one output face
     // output rows of a lane: FP32 4*(lane/16) + v, FP64 lane/16 + 4v (+16 ti)
     const uint32_t orow = sizeof(T) == 4 ? 4 * kl : kl;
+    const View32 v32 = make_view32(iv);  // tube offsets without 64-bit division
     // B operands of step s of this wavefront (tubes b0 + 16c + lane%16, time
     // step 4 kk + lane/16); tubes past the chunk read tube c0; only the last
     // four groups can reach past n3 (n3 > NMAX - 16)
@@ -415,7 +416,7 @@ __device__ __forceinline__ void direct_chunk(const T *__restrict__ in, const Vie
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int64_t i = b0 + l16 + 16 * c;
-            vin[c] = (uint32_t)iv.tube_base(i < cend ? i : c0) * SZ + (uint32_t)kl * st_b;
+            vin[c] = v32.tube_base((uint32_t)(i < cend ? i : c0)) * SZ + (uint32_t)kl * st_b;
         }
 #pragma unroll
         for (int kk = 0; kk < NK; ++kk) {
@@ -512,24 +513,211 @@ __device__ __forceinline__ void direct_chunk(const T *__restrict__ in, const Vie
     }
 }
 
+// DCT-II variant of direct_chunk: the even/odd symmetry of the orthonormal
+// DCT-II, M[o][N-1-t] = (-1)^o M[o][t], splits each tube's product into two
+// half-size ones (half the matrix-core work).  With H = ceil(N/2):
+//  forward: u[t] = x[t] + x[N-1-t], w[t] = x[t] - x[N-1-t] (t < H; for odd N
+//    the middle sample has no partner, which reads as zero), then
+//    out[2o'] = sum_t M[2o'][t] u[t] and out[2o'+1] = sum_t M[2o'+1][t] w[t];
+//  inverse: A[t] = sum_o' M[2o'][t] y[2o'], B[t] = sum_o' M[2o'+1][t] y[2o'+1]
+//    (t < H), then out[t] = A[t] + B[t] and out[N-1-t] = A[t] - B[t]
+//    (the odd-N middle row only once; its odd coefficients are zero).
+// LDS holds the two half matrices (rows by depth, zero-padded to HM = NMAX/2
+// deep and to whole 16-row blocks); the rest is as in direct_chunk.
+template <typename T, int NMAX, bool INV>
+__device__ __forceinline__ void direct_chunk_dct(const T *__restrict__ in, const View &iv, uint32_t in_bytes,
+                                                 T *__restrict__ out, uint32_t out_bytes, int64_t ntubes,
+                                                 int64_t mp, int N, int64_t c0) {
+    constexpr int G = NT / 64;
+    constexpr int HM = NMAX / 2;                    // depth of each half product (a multiple of 4)
+    constexpr int NTH = (HM + 15) / 16;             // 16-row output blocks of each half product
+    constexpr int LDH = HM + 4;                     // row pitch of the half matrices
+    constexpr int NKH = HM / 4;                     // time-step groups of each half product
+    constexpr int C = sizeof(T) == 4 ? 2 : 1;
+    constexpr int NB = kDirectChunk / (16 * C * G);
+    static_assert(NB % 2 == 0, "steps are taken in pairs");
+    constexpr uint32_t SZ = sizeof(T);
+    __shared__ __align__(16) T Me[16 * NTH * LDH];
+    __shared__ __align__(16) T Mo[16 * NTH * LDH];
+    __shared__ double ctab[4 * NMAX];
+    typedef T v4 __attribute__((ext_vector_type(4)));
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63, kl = lane >> 4, l16 = lane & 15;
+    const __amdgpu_buffer_rsrc_t rin = __builtin_amdgcn_make_buffer_rsrc(const_cast<T *>(in), 0, (int)in_bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc(out, 0, (int)out_bytes, 0x00020000);
+    const int64_t cend = c0 + kDirectChunk < ntubes ? c0 + kDirectChunk : ntubes;
+    const int H = (N + 1) / 2;
+    const uint32_t st_b = (uint32_t)iv.s_t * SZ;
+    const uint32_t mp_b = (uint32_t)mp * SZ;
+    const uint32_t orow = sizeof(T) == 4 ? 4 * kl : kl;  // output row of lane group (+ v or 4v)
+    const View32 v32 = make_view32(iv);  // tube offsets without 64-bit division
+    // the lane's two operands of group kk: forward x[t], x[N-1-t]; inverse
+    // y[2o'], y[2o'+1] (t, o' = 4 kk + lane/16); zero past the tube.  The
+    // group's part of the offset (4 kk steps) is uniform: a scalar offset for
+    // x[t] and y[2o'], y[2o'+1], one subtraction for the mirrored x[N-1-t].
+    const uint32_t lrow = INV ? 2 * kl : kl;  // the lane's first time step in a group
+    auto load_step = [&](T (&xa)[C][NKH], T (&xb)[C][NKH], int st) {
+        const int64_t b0 = c0 + 16 * C * (wave + G * st);
+        uint32_t va[C], vb[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int64_t i = b0 + l16 + 16 * c;
+            const uint32_t vin = v32.tube_base((uint32_t)(i < cend ? i : c0)) * SZ;
+            va[c] = vin + lrow * st_b;
+            vb[c] = INV ? va[c] + st_b : vin + (uint32_t)(N - 1 - kl) * st_b;
+        }
+#pragma unroll
+        for (int kk = 0; kk < NKH; ++kk) {
+            const int t = 4 * kk + kl;
+            bool oka, okb;
+            if (INV) {
+                oka = 2 * t < N;
+                okb = 2 * t + 1 < N;
+            } else {
+                oka = t < H;
+                okb = N - 1 - t > t;
+            }
+            const uint32_t sa = (uint32_t)((INV ? 8 : 4) * kk) * st_b;  // uniform
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                xa[c][kk] = bload<T>(rin, oka ? va[c] : kOffNone, sa);
+                if (INV)
+                    xb[c][kk] = bload<T>(rin, okb ? vb[c] : kOffNone, sa);
+                else
+                    xb[c][kk] = bload<T>(rin, okb ? vb[c] - sa : kOffNone, 0);
+            }
+        }
+    };
+    T xa0[C][NKH], xb0[C][NKH], xa1[C][NKH], xb1[C][NKH];
+    load_step(xa0, xb0, 0);
+    for (int j = tid; j < 4 * N; j += NT) ctab[j] = cospi((double)j / (2.0 * N));
+    for (int e = tid; e < 16 * NTH * LDH; e += NT) {
+        Me[e] = T(0);
+        Mo[e] = T(0);
+    }
+    __syncthreads();
+    {
+        // entry (row r, depth k) of each half matrix: forward Me = M[2k'][..],
+        // rows o' and depth t; inverse rows t and depth o'
+        const double a0c = sqrt(1.0 / N), a1c = sqrt(2.0 / N);
+        for (int e = tid; e < 2 * H * H; e += NT) {
+            const int half = e / (H * H), rr = (e % (H * H)) / H, kk = e % H;
+            const int o = INV ? 2 * kk + half : 2 * rr + half;  // DCT frequency
+            const int t = INV ? rr : kk;                        // sample
+            if (o >= N) continue;
+            const double v = (o == 0 ? a0c : a1c) * ctab[((2 * t + 1) * o) % (4 * N)];
+            (half ? Mo : Me)[rr * LDH + kk] = (T)v;
+        }
+    }
+    __syncthreads();
+    auto mma_store = [&](const T (&xa)[C][NKH], const T (&xb)[C][NKH], int st) {
+        const int64_t b0 = c0 + 16 * C * (wave + G * st);
+        int zoff;
+        asm volatile("s_mov_b32 %0, 0" : "=s"(zoff));
+        const T *Mez = Me + zoff, *Moz = Mo + zoff;
+        v4 ae[C][NTH], ao[C][NTH];
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+#pragma unroll
+            for (int ti = 0; ti < NTH; ++ti) ae[c][ti] = ao[c][ti] = v4{0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < NKH; ++kk) {
+            T be[C], bo[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                if (INV) {
+                    be[c] = xa[c][kk];
+                    bo[c] = xb[c][kk];
+                } else {
+                    be[c] = xa[c][kk] + xb[c][kk];
+                    bo[c] = xa[c][kk] - xb[c][kk];
+                }
+            }
+#pragma unroll
+            for (int ti = 0; ti < NTH; ++ti) {
+                const T me = Mez[(16 * ti + l16) * LDH + 4 * kk + kl];
+                const T mo = Moz[(16 * ti + l16) * LDH + 4 * kk + kl];
+#pragma unroll
+                for (int c = 0; c < C; ++c) {
+                    if constexpr (sizeof(T) == 4) {
+                        ae[c][ti] = __builtin_amdgcn_mfma_f32_16x16x4f32(me, be[c], ae[c][ti], 0, 0, 0);
+                        ao[c][ti] = __builtin_amdgcn_mfma_f32_16x16x4f32(mo, bo[c], ao[c][ti], 0, 0, 0);
+                    } else {
+                        ae[c][ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(me, be[c], ae[c][ti], 0, 0, 0);
+                        ao[c][ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(mo, bo[c], ao[c][ti], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // stores: the lane's part of the offset once per column block, the
+        // row block's part (16 ti + v rows) as a scalar offset; only the last
+        // row block can pass n3 and checks its rows
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int64_t i = b0 + l16 + 16 * c;
+            const uint32_t vi = i < cend ? (uint32_t)i * SZ : kOffNone;
+            const uint32_t v1 = vi + (INV ? orow : 2 * orow) * mp_b;          // rows r or 2r
+            const uint32_t v2 = INV ? vi + (uint32_t)(N - 1 - (int)orow) * mp_b  // rows N-1-r
+                                    : v1 + mp_b;                               // rows 2r+1
+#pragma unroll
+            for (int ti = 0; ti < NTH; ++ti)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const uint32_t ru = 16 * ti + (sizeof(T) == 4 ? v : 4 * v);  // uniform part of r
+                    const int r = (int)(ru + orow);
+                    const T e = ae[c][ti][v], od = ao[c][ti][v];
+                    const bool last = ti == NTH - 1;
+                    if (INV) {
+                        // rows r (A + B) and N-1-r (A - B), r < H; the middle row of odd N once
+                        const bool ok1 = !last || r < H, ok2 = N - 1 - r > r;
+                        bstore<T>(e + od, rout, ok1 ? v1 : kOffNone, ru * mp_b);
+                        bstore<T>(e - od, rout, ok2 ? v2 - ru * mp_b : kOffNone, 0);
+                    } else {
+                        // rows 2r (even product) and 2r + 1 (odd product)
+                        const bool ok1 = !last || 2 * r < N, ok2 = !last || 2 * r + 1 < N;
+                        bstore<T>(e, rout, ok1 ? v1 : kOffNone, 2 * ru * mp_b);
+                        bstore<T>(od, rout, ok2 ? v2 : kOffNone, 2 * ru * mp_b);
+                    }
+                }
+        }
+    };
+#pragma unroll
+    for (int st = 0; st < NB; st += 2) {
+        load_step(xa1, xb1, st + 1);
+        mma_store(xa0, xb0, st);
+        if (st + 2 < NB) load_step(xa0, xb0, st + 2);
+        mma_store(xa1, xb1, st + 1);
+    }
+}
+
 template <typename T, int NMAX, bool INV, bool DENSE>
 __global__ __launch_bounds__(NT) void k_direct_small(const T *__restrict__ in, View iv, uint32_t in_bytes,
                                                      T *__restrict__ out, uint32_t out_bytes, int64_t ntubes,
                                                      int64_t mp, int N, const double *__restrict__ Md) {
-    direct_chunk<T, NMAX, INV>(in, iv, in_bytes, out, out_bytes, ntubes, mp, N, Md, DENSE,
-                               (int64_t)blockIdx.x * kDirectChunk);
+    if constexpr (DENSE)
+        direct_chunk<T, NMAX, INV>(in, iv, in_bytes, out, out_bytes, ntubes, mp, N, Md, true,
+                                   (int64_t)blockIdx.x * kDirectChunk);
+    else
+        direct_chunk_dct<T, NMAX, INV>(in, iv, in_bytes, out, out_bytes, ntubes, mp, N,
+                                       (int64_t)blockIdx.x * kDirectChunk);
 }
 
 // Batched direct product: workgroup w transforms chunk items[w].chunk of the
 // tensor described by desc[items[w].d] (tensors of one precision and one
 // length class, NMAX - 16 < n3 <= NMAX).
-template <typename T, int NMAX, bool INV>
+template <typename T, int NMAX, bool INV, bool DENSE>
 __global__ __launch_bounds__(NT) void k_direct_batched(const DirectDesc *__restrict__ desc,
                                                        const DirectItem *__restrict__ items) {
     const DirectItem it = items[blockIdx.x];
     const DirectDesc &d = desc[it.d];
-    direct_chunk<T, NMAX, INV>(reinterpret_cast<const T *>(d.in), d.iv, d.in_bytes, reinterpret_cast<T *>(d.out),
-                               d.out_bytes, d.ntubes, d.mp, d.N, d.Md, d.dense != 0, (int64_t)it.chunk * kDirectChunk);
+    if constexpr (DENSE)
+        direct_chunk<T, NMAX, INV>(reinterpret_cast<const T *>(d.in), d.iv, d.in_bytes,
+                                   reinterpret_cast<T *>(d.out), d.out_bytes, d.ntubes, d.mp, d.N, d.Md, true,
+                                   (int64_t)it.chunk * kDirectChunk);
+    else
+        direct_chunk_dct<T, NMAX, INV>(reinterpret_cast<const T *>(d.in), d.iv, d.in_bytes,
+                                       reinterpret_cast<T *>(d.out), d.out_bytes, d.ntubes, d.mp, d.N,
+                                       (int64_t)it.chunk * kDirectChunk);
 }
 
 template <typename K>
@@ -654,9 +842,15 @@ tsvdm_status launch_direct_batched(const DirectDesc *desc, const TransformGroup 
                                    hipStream_t s) {
     if (g.count == 0) return TSVDM_OK;
     const dim3 grid((unsigned)g.count);
-#define TSVDM_DB(T, NM, INV)                                                                         \
-    TSVDM_LAUNCH("transform_direct_batched", (k_direct_batched<T, NM, INV>), grid, dim3(NT), 0, s, desc, \
-                 g.items)
+#define TSVDM_DB(T, NM, INV)                                                                          \
+    do {                                                                                                  \
+        if (g.dense)                                                                                      \
+            TSVDM_LAUNCH("transform_direct_batched", (k_direct_batched<T, NM, INV, true>), grid, dim3(NT), 0, \
+                         s, desc, g.items);                                                               \
+        else                                                                                              \
+            TSVDM_LAUNCH("transform_direct_batched", (k_direct_batched<T, NM, INV, false>), grid, dim3(NT), 0, \
+                         s, desc, g.items);                                                               \
+    } while (0)
 #define TSVDM_DB_CLASS(T)                                                                   \
     do {                                                                                    \
         switch (g.nmax) {                                                                   \
