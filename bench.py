@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--train-faces", type=int, default=100_000,
                     help="learned: number of training faces (generated in batches of 256)")
     ap.add_argument("--epochs", type=int, default=20, help="learned: training epochs")
+    ap.add_argument("--batched-config", default="",
+                    help="uneven: launch configuration 'gram_wpc,gram_cols,vec_wpc' instead of the autotuner "
+                         "(profiling: timings under a profiler mislead the tuner)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration under rocprofv3)")
     return ap.parse_args()
@@ -172,7 +175,11 @@ def uneven_main(args):
 
     step()
     torch.cuda.synchronize()
-    cfg = bt.autotune()
+    if args.batched_config:
+        bt.set_config([int(v) for v in args.batched_config.split(",")])
+        cfg = bt.config()
+    else:
+        cfg = bt.autotune()
     torch.cuda.synchronize()
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())

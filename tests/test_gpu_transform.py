@@ -176,3 +176,31 @@ def test_batched_transform_matches_single_and_oracle(direction):
         torch.cuda.synchronize()
         for o, f in zip(outs, first):
             assert torch.equal(o, f)
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+@pytest.mark.parametrize("direction", [1, -1])
+def test_batched_direct_dct_every_length(dt, direction):
+    """The batched plan transforms every tensor with n3 <= 64 by the direct
+    product (the DCT-II as two half-size products over its even/odd symmetry),
+    powers of two included: every length 1..64, each tensor over two chunks of
+    tubes with a ragged tail, against the oracle's DCT-II matrix (forward) or
+    its transpose (inverse)."""
+    g = np.random.default_rng(17)
+    m, p = 23, 41  # 943 tubes: two 512-tube chunks, the second partial
+    xs, outs, shapes, Xs = [], [], [], []
+    for n in range(1, 65):
+        X = np.asfortranarray(g.standard_normal((m, p, n))).astype(dt)
+        xd = to_dev(X)
+        xs.append(xd)
+        outs.append(torch.empty_like(xd))
+        shapes.append((m, p, n))
+        Xs.append(X)
+    bt = api.BatchedTransform(xs, outs, shapes, [C.M_DCT2] * len(shapes), direction)
+    bt()
+    torch.cuda.synchronize()
+    for X, o, (m_, p_, n) in zip(Xs, outs, shapes):
+        M = oracle.dct2_matrix(n)
+        ref = oracle.mode3(X.astype(np.float64), M if direction > 0 else np.ascontiguousarray(M.T))
+        err = relerr(from_dev(o, ref.shape), ref)
+        assert err < TOL[dt], (n, err)
