@@ -8,6 +8,8 @@
 #include <cmath>
 #include <vector>
 
+#include <algorithm>
+
 #include "common.h"
 
 namespace tsvdm {
@@ -69,17 +71,18 @@ struct tsvdm_transform_plan_s {
 
 static size_t al256h(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// group of tensor i in the batched direct launches (8*dense + 4*double +
-// length class index, classes of 16), or -1 for a tensor launched by itself
-// (DFT, N > 64, a view or output spanning 2 GiB or more, negative strides) or
-// an empty one
+// group of tensor i in the batched direct launches: DCT-II 4*double (every
+// length class in one launch), dense M 8 + 4*double + length class index
+// (classes of 16); or -1 for a tensor launched by itself (DFT, N > 64, a view
+// or output spanning 2 GiB or more, negative strides) or an empty one
 constexpr int kTGroups = 16;
 static int tgroup(const tsvdm_mdesc &M, const tsvdm_tensor &in) {
     if (M.kind == TSVDM_M_DFT || M.n3 > 64 || in.m * in.p == 0) return -1;
     const bool dbl = in.dtype == TSVDM_F64;
     uint32_t ib = 0, ob = 0;
     if (!direct_span(in, M.n3, dbl ? 8 : 4, &ib, &ob)) return -1;
-    return 8 * (M.kind == TSVDM_M_DENSE ? 1 : 0) + 4 * (dbl ? 1 : 0) + direct_class(M.n3) / 16 - 1;
+    if (M.kind != TSVDM_M_DENSE) return 4 * (dbl ? 1 : 0);
+    return 8 + 4 * (dbl ? 1 : 0) + direct_class(M.n3) / 16 - 1;
 }
 
 static int64_t tchunks(const tsvdm_tensor &in) { return (in.m * in.p + kDirectChunk - 1) / kDirectChunk; }
@@ -242,6 +245,15 @@ tsvdm_status tsvdm_transform_plan_create(int32_t nmat, const tsvdm_mdesc *M, int
         const int64_t nt = tchunks(in[i]);
         for (int64_t t = 0; t < nt; ++t) items[fill[g]++] = DirectItem{i, (int32_t)t};
     }
+    // the DCT groups hold every length class: largest class first, so the
+    // launch ends on the cheapest chunks
+    for (int g = 0; g < kTGroups; ++g) {
+        if ((g & 8) || cnt[g] == 0) continue;
+        DirectItem *items = reinterpret_cast<DirectItem *>(h.data() + off[g]);
+        std::stable_sort(items, items + cnt[g], [&](const DirectItem &a, const DirectItem &b) {
+            return direct_class(desc[a.d].N) > direct_class(desc[b.d].N);
+        });
+    }
     if (need > 0) {
         const hipError_t e = hipMemcpy(workspace, h.data(), need, hipMemcpyHostToDevice);
         if (e != hipSuccess) {
@@ -254,7 +266,7 @@ tsvdm_status tsvdm_transform_plan_create(int32_t nmat, const tsvdm_mdesc *M, int
     for (int g = 0; g < kTGroups; ++g)
         if (cnt[g] > 0)
             plan_obj->groups.push_back(
-                TransformGroup{(g & 4) != 0, (g & 8) != 0, 16 * (g % 4 + 1), reinterpret_cast<const DirectItem *>(ws + off[g]), cnt[g]});
+                TransformGroup{(g & 4) != 0, (g & 8) != 0, (g & 8) ? 16 * (g % 4 + 1) : 0, reinterpret_cast<const DirectItem *>(ws + off[g]), cnt[g]});
     plan_obj->M.assign(M, M + nmat);
     plan_obj->in.assign(in, in + nmat);
     plan_obj->out.assign(out, out + nmat);

@@ -705,6 +705,25 @@ __global__ __launch_bounds__(NT) void k_direct_small(const T *__restrict__ in, V
 // Batched direct product: workgroup w transforms chunk items[w].chunk of the
 // tensor described by desc[items[w].d] (tensors of one precision and one
 // length class, NMAX - 16 < n3 <= NMAX).
+// Batched DCT-II: one launch for every length class (the class of each work
+// item from its tensor's n3), so the classes share one tail; the plan lists
+// the items largest class first.
+template <typename T, bool INV>
+__global__ __launch_bounds__(NT) void k_direct_batched_dct(const DirectDesc *__restrict__ desc,
+                                                           const DirectItem *__restrict__ items) {
+    const DirectItem it = items[blockIdx.x];
+    const DirectDesc &d = desc[it.d];
+    const T *in = reinterpret_cast<const T *>(d.in);
+    T *out = reinterpret_cast<T *>(d.out);
+    const int64_t c0 = (int64_t)it.chunk * kDirectChunk;
+    switch (direct_class(d.N)) {
+        case 16: direct_chunk_dct<T, 16, INV>(in, d.iv, d.in_bytes, out, d.out_bytes, d.ntubes, d.mp, d.N, c0); break;
+        case 32: direct_chunk_dct<T, 32, INV>(in, d.iv, d.in_bytes, out, d.out_bytes, d.ntubes, d.mp, d.N, c0); break;
+        case 48: direct_chunk_dct<T, 48, INV>(in, d.iv, d.in_bytes, out, d.out_bytes, d.ntubes, d.mp, d.N, c0); break;
+        default: direct_chunk_dct<T, 64, INV>(in, d.iv, d.in_bytes, out, d.out_bytes, d.ntubes, d.mp, d.N, c0); break;
+    }
+}
+
 template <typename T, int NMAX, bool INV, bool DENSE>
 __global__ __launch_bounds__(NT) void k_direct_batched(const DirectDesc *__restrict__ desc,
                                                        const DirectItem *__restrict__ items) {
@@ -860,8 +879,27 @@ tsvdm_status launch_direct_batched(const DirectDesc *desc, const TransformGroup 
             default: if (direction > 0) TSVDM_DB(T, 64, false); else TSVDM_DB(T, 64, true); break; \
         }                                                                                   \
     } while (0)
-    if (g.dbl) TSVDM_DB_CLASS(double);
-    else TSVDM_DB_CLASS(float);
+    if (!g.dense) {  // DCT-II: every length class in one launch
+        if (g.dbl) {
+            if (direction > 0)
+                TSVDM_LAUNCH("transform_direct_batched", (k_direct_batched_dct<double, false>), grid, dim3(NT), 0, s,
+                             desc, g.items);
+            else
+                TSVDM_LAUNCH("transform_direct_batched", (k_direct_batched_dct<double, true>), grid, dim3(NT), 0, s,
+                             desc, g.items);
+        } else {
+            if (direction > 0)
+                TSVDM_LAUNCH("transform_direct_batched", (k_direct_batched_dct<float, false>), grid, dim3(NT), 0, s,
+                             desc, g.items);
+            else
+                TSVDM_LAUNCH("transform_direct_batched", (k_direct_batched_dct<float, true>), grid, dim3(NT), 0, s,
+                             desc, g.items);
+        }
+    } else if (g.dbl) {
+        TSVDM_DB_CLASS(double);
+    } else {
+        TSVDM_DB_CLASS(float);
+    }
 #undef TSVDM_DB_CLASS
 #undef TSVDM_DB
     TSVDM_LAUNCH_CHECK("k_direct_batched");
