@@ -169,11 +169,14 @@ tsvdm_status tsvdm_transform(const tsvdm_mdesc *M, int32_t direction, const tsvd
 /* Batched mode-3 transform of nmat independent tensors (Sec. 2.1 for each;
  * the inputs of the uneven batch below): out[i] = in[i] x_3 M[i]^(+-1), every
  * (M[i], in[i], out[i]) as for tsvdm_transform, one direction for all.  The
- * tensors whose M is DCT2 or DENSE with n3 <= 64 are transformed by the
- * direct per-tube product in one launch per precision and length class
- * (n3 in 1..16, 17..32, 33..48, 49..64): workgroup w takes chunk w of a work
- * list of 512-tube chunks of all of them.  The other tensors (DFT, n3 > 64) are launched one by
- * one, as tsvdm_transform would.  Results equal tsvdm_transform's bit for bit
+ * tensors whose M is DCT2 or DENSE with n3 <= 64 (and whose view and output
+ * span less than 2 GiB) are transformed by the direct per-tube product:
+ * workgroup w takes chunk w of a work list of 512-tube chunks of all of them,
+ * in one launch per precision for the DCT2 tensors (the DCT-II as two
+ * half-size products over its even/odd symmetry) and one per precision and
+ * length class (n3 in 1..16, 17..32, 33..48, 49..64) for the DENSE ones.  The
+ * other tensors (DFT, n3 > 64, larger spans) are launched one by one, as
+ * tsvdm_transform would.  Results equal tsvdm_transform's bit for bit
  * where it too uses the direct product (n3 not a power of two, or DENSE); for
  * a power-of-two n3 <= 64, where tsvdm_transform uses its FFT, they agree to
  * rounding.
