@@ -55,6 +55,24 @@ __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, V
     int64_t *base = reinterpret_cast<int64_t *>(wq + N);  // [2TP]
     const int tid = threadIdx.x;
     const int64_t i0 = (int64_t)blockIdx.x * TT;
+    constexpr int UNR = 16;
+    constexpr int VW = 16 / sizeof(T);  // elements per 16-byte vector
+    typedef T vec_t __attribute__((ext_vector_type(VW)));
+    // vector path, forward: the tile (at most 32 KiB, so at most 2048 vectors,
+    // VMAX a thread) is loaded before the twiddles are computed, which then
+    // overlap the loads' latency
+    constexpr int VMAX = 2048 / NT;
+    const int lvpr = logtt - (VW == 4 ? 2 : 1), vpr = 1 << lvpr, vtotal = vpr * N;
+    vec_t vfirst[VMAX];
+    if constexpr (DIR > 0 && VEC) {
+        const T *X = reinterpret_cast<const T *>(in) + i0;
+#pragma unroll
+        for (int q = 0; q < VMAX; ++q) {
+            const int w = tid + q * NT;
+            const int u4 = w & (vpr - 1), t = w >> lvpr;
+            if (w < vtotal) vfirst[q] = *reinterpret_cast<const vec_t *>(X + u4 * VW + (int64_t)t * iv.s_t);
+        }
+    }
 
     for (int j = tid; j < H; j += NT) {
         double s, c;
@@ -74,32 +92,18 @@ __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, V
     // ---------------------------------------------------------------- load
     // Every thread issues a batch of UNR independent loads before it touches
     // LDS, so that many loads are in flight per wavefront.
-    constexpr int UNR = 16;
-    constexpr int VW = 16 / sizeof(T);  // elements per 16-byte vector
-    typedef T vec_t __attribute__((ext_vector_type(VW)));
-    if (DIR > 0 && VEC) {
-        const T *X = reinterpret_cast<const T *>(in) + i0;
-        const int lvpr = logtt - (VW == 4 ? 2 : 1), vpr = 1 << lvpr, total = vpr * N;
-        for (int w0 = tid; w0 < total; w0 += NT * UNR) {
-            vec_t vals[UNR];
+    if constexpr (DIR > 0 && VEC) {
 #pragma unroll
-            for (int q = 0; q < UNR; ++q) {
-                const int w = w0 + q * NT;
-                const int u4 = w & (vpr - 1), t = w >> lvpr;
-                if (w < total) vals[q] = *reinterpret_cast<const vec_t *>(X + u4 * VW + (int64_t)t * iv.s_t);
-            }
+        for (int q = 0; q < VMAX; ++q) {
+            const int w = tid + q * NT;
+            if (w >= vtotal) break;
+            const int u4 = w & (vpr - 1), t = w >> lvpr;
+            const int n = KIND == KIND_DCT ? makhoul(t, N) : t;
+            cx<T> *rowp = &buf[bitrev(n, logn) * TP];
 #pragma unroll
-            for (int q = 0; q < UNR; ++q) {
-                const int w = w0 + q * NT;
-                if (w >= total) break;
-                const int u4 = w & (vpr - 1), t = w >> lvpr;
-                const int n = KIND == KIND_DCT ? makhoul(t, N) : t;
-                cx<T> *rowp = &buf[bitrev(n, logn) * TP];
-#pragma unroll
-                for (int e = 0; e < VW; ++e) {
-                    const int u = u4 * VW + e;
-                    reinterpret_cast<T *>(&rowp[u & (TP - 1)])[u >= TP] = vals[q][e];
-                }
+            for (int e = 0; e < VW; ++e) {
+                const int u = u4 * VW + e;
+                reinterpret_cast<T *>(&rowp[u & (TP - 1)])[u >= TP] = vfirst[q][e];
             }
         }
     } else if (DIR > 0) {  // real tubes in; tube u < TP -> real part, u >= TP -> imaginary part
