@@ -152,3 +152,45 @@ def test_mixed_truncation_below_rank():
     assert err_opt <= err_gpu <= 1.05 * err_opt
     true = np.array([np.linalg.norm(Xh64[:, :, f] - That[:, :, f]) for f in range(n3)])
     np.testing.assert_allclose(cert, true, rtol=1e-3)
+
+
+def test_mixed_step_graph_replays_match_eager():
+    """The transform and the mixed truncation (launches only: no host
+    synchronisation, allocation or memset) captured in a graph give, on every
+    replay, with eager work and synchronisation in between, exactly the eager
+    result (the timed step of the benchmark replays such a graph)."""
+    m, p, n3 = 96, 80, 12  # n3 not a power of two: the direct transform
+    k, os_ = 10, 8
+    X, fac = _known_rank_input(m, p, n3, 14, 1.0 / 8.0, 3)
+    Xd = to_dev(X)
+    g = np.random.default_rng(21)
+    omega = to_dev(g.standard_normal((p, k + os_)), np.float32)
+    xh = torch.empty(m * p * n3, dtype=torch.float32, device="cuda")
+    tr = api.Truncator(m, p, n3, torch.float32, k=k, precision=C.PREC_MIXED, oversample=os_,
+                       power_iters=1, omega=omega)
+
+    def step():
+        api.transform(Xd, m, p, n3, C.M_DCT2, +1, out=xh)
+        return tr(xh)
+
+    F = step()
+    torch.cuda.synchronize()
+    ref = [t.clone() for t in (F.U, F.S, F.V, F.ranks, F.cert, F.fro, F.info)]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for rep in range(3):
+        for t in (F.U, F.S, F.V, F.cert, F.fro):
+            t.fill_(-7.0)
+        xh.fill_(3.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip((F.U, F.S, F.V, F.ranks, F.cert, F.fro, F.info), ref):
+            assert torch.equal(a, b), rep
