@@ -35,7 +35,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BT = 256;      // threads per workgroup of the streaming kernels
 constexpr int MX = 64;       // largest face row count
-constexpr int RX = 32;       // largest pivoted-Cholesky rank (Jacobi size)
 constexpr int KMAXB = 32;    // largest rank returned
 
 struct Item {

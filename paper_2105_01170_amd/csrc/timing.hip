@@ -46,7 +46,10 @@ void trace_begin(const char *name, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_mu);
     g_pending = get_event();
     g_pending_name = name;
-    if (g_pending) hipEventRecord(g_pending, s);
+    if (g_pending && hipEventRecord(g_pending, s) != hipSuccess) {  // the launch goes untimed
+        g_pool.push_back(g_pending);
+        g_pending = nullptr;
+    }
 }
 
 void trace_end(hipStream_t s) {
@@ -54,8 +57,12 @@ void trace_end(hipStream_t s) {
     if (!g_pending) return;
     hipEvent_t b = get_event();
     if (!b) return;
-    hipEventRecord(b, s);
-    g_recs.push_back({g_pending_name, g_pending, b});
+    if (hipEventRecord(b, s) == hipSuccess) {
+        g_recs.push_back({g_pending_name, g_pending, b});
+    } else {  // the launch goes untimed
+        g_pool.push_back(b);
+        g_pool.push_back(g_pending);
+    }
     g_pending = nullptr;
 }
 
