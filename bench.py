@@ -27,6 +27,7 @@ if ROOT not in sys.path:
 METRIC = "faces/sec truncated t-SVDM @1e-4 rel err, mixed vs FP64 GPU; % HBM/MFMA peak"
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_VECTOR_PEAK_TFLOPS = 157.3
 M_, P_, N3, K, OS = 512, 512, 256, 32, 8
 
 
@@ -40,10 +41,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--kernel-table", action="store_true", help="print the per-kernel table to stderr")
-    ap.add_argument("--workload", choices=["dense", "uneven", "learned"], default="dense",
+    ap.add_argument("--workload", choices=["dense", "uneven", "learned", "apply"], default="dense",
                     help="dense: the 512x512x256 tensor (default); uneven: the batch of 256 "
                          "Kronecker-sum matrices through the batched truncation; learned: the "
-                         "predicted-width truncation against the fixed width 40")
+                         "predicted-width truncation against the fixed width 40; apply: "
+                         "y = M_E[T] x for a 4096 x 4096 structured matrix on 1024 columns")
     ap.add_argument("--train-faces", type=int, default=100_000,
                     help="learned: number of training faces (generated in batches of 256)")
     ap.add_argument("--epochs", type=int, default=20, help="learned: training epochs")
@@ -270,6 +272,137 @@ def uneven_main(args):
     print(json.dumps(out))
 
 
+def apply_main(args):
+    """y = M_E[T] x without forming the matrix: l = q = m = n3 = 64 (a 4096 x 4096
+    matrix), rank 16 on every face, M = the unitary DFT (33 stored complex faces
+    of the real data), 1024 right-hand sides, FP32.  A step is one tsvdm_apply
+    call: the transform of the right-hand side tubes and the fused per-face
+    contraction.  The factors are the library's transforms of seeded spatial
+    factors; the rate counts the dense-equivalent 2 (l m)(q n3) nrhs flops."""
+    import torch
+
+    from paper_2105_01170_amd import api
+    from paper_2105_01170_amd import tsvdm as C
+    import synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    calib_copy(args, dev)
+    m = ell = q = n = 64
+    k, nrhs = 16, 1024
+    p = ell * q
+    w = synth.apply_factors(m=m, ell=ell, q=q, n=n, k=k, nrhs=nrhs)
+    Ud = api.transform(torch.from_numpy(np.asfortranarray(w["U"]).ravel(order="F")).to(dev, torch.float32),
+                       m, k, n, C.M_DFT, +1)
+    Vd = api.transform(torch.from_numpy(np.asfortranarray(w["V"]).ravel(order="F")).to(dev, torch.float32),
+                       p, k, n, C.M_DFT, +1)
+    nf = n // 2 + 1
+    S = torch.tensor(np.tile(w["sigma"][:, None], (1, nf)).ravel(order="F"), dtype=torch.float64, device=dev)
+    F = api.Factors(m, p, nf, k, Ud, S, Vd, torch.full((nf,), k, dtype=torch.int32, device=dev),
+                    torch.zeros(nf, dtype=torch.float64, device=dev), torch.zeros(nf, dtype=torch.float64, device=dev),
+                    torch.zeros(nf, dtype=torch.int32, device=dev))
+    x = torch.from_numpy(np.asfortranarray(w["X"]).ravel(order="F")).to(dev, torch.float32)
+    y = torch.empty(ell * m * nrhs, dtype=torch.float32, device=dev)
+    md = api._mdesc(C.M_DFT, n, None)
+    desc = F.desc()
+    need = C.tsvdm_apply_workspace_size(md, desc, ell, q, nrhs, C.F32)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        C.tsvdm_apply(md, desc, ell, q, nrhs, x.data_ptr(), q * n, y.data_ptr(), ell * m, C.F32, ws.data_ptr(),
+                      need, stream.cuda_stream)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_step = e0.elapsed_time(e1) / args.steps
+    dense_flops = 2.0 * (ell * m) * (q * n) * nrhs
+    C.tsvdm_timing_enable(True)
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    table = C.timing_table()
+    C.tsvdm_timing_enable(False)
+    kern = {name: {"launches": nl, "ms_per_step": ms / 3} for name, (nl, ms) in table.items()}
+    # the fused contraction as executed on the stored half spectrum: per face,
+    # Z = conj(V_j)^T xt (complex multiply-adds over q, 8 flops each) for every
+    # block row j and column, then Re(U S Z) (4 flops per rank term)
+    work = {"apply_fused": ("alu", nf * ell * nrhs * k * q * 8.0 + nf * ell * m * nrhs * k * 4.0),
+            "transform_fft": ("hbm", 4.0 * q * n * nrhs + 8.0 * q * nrhs * nf)}
+    dom = max(table.items(), key=lambda kv: kv[1][1] if kv[0] in work else -1)[0]
+    n_dom, ms_dom = table[dom]
+    bound, amount = work[dom]
+    avg_s = ms_dom / n_dom / 1e3
+    per_launch = amount * 3 / n_dom
+    if bound == "hbm":
+        roof = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": per_launch / avg_s / 1e12, "peak": FP32_VECTOR_PEAK_TFLOPS,
+                "unit": "TFLOP/s (fp32)"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_us"] = 1e6 * avg_s
+    out = {
+        "metric": "apply y = M_E[T] x, dense-equivalent GFLOP/s",
+        "value": dense_flops / (ms_step / 1e3) / 1e9,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "4096 x 4096 structured matrix (l = q = m = n3 = 64), rank 16 per face, "
+                               "DFT (33 stored complex faces), 1024 right-hand sides, FP32"},
+        "roofline": roof,
+        "kernels_ms_per_step": {k2: round(v["ms_per_step"], 4) for k2, v in kern.items()},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = apply_cpu_baseline(w, ell, q, m, n, k, nrhs)
+    if args.kernel_table:
+        for kname, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+            print(f"{kname:24s} {v['launches']:6d} launches  {v['ms_per_step'] * 1e3:10.1f} us/step",
+                  file=sys.stderr)
+    print(json.dumps(out))
+
+
+def apply_cpu_baseline(w, ell, q, m, n, k, ncols):
+    """The oracle's apply (the dense matrix formed from the factors, then the
+    product) on the first ncols right-hand sides, in the metric's unit."""
+    import oracle
+
+    t0 = time.time()
+    M = oracle.dft_matrix(n)
+    Uh, Vh = oracle.mode3(w["U"], M), oracle.mode3(w["V"], M)
+    That = np.zeros((m, ell * q, n), dtype=Uh.dtype, order="F")
+    for f in range(n):
+        That[:, :, f] = (Uh[:, :, f] * w["sigma"]) @ np.conj(Vh[:, :, f]).T
+    Ahat = oracle.blockmat_from_tensor(np.real(oracle.inverse_mode3(That, M)), ell, q)
+    oracle.dense_apply(Ahat, w["X"][:, :ncols])
+    dt = time.time() - t0
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count()
+    return {"value": 2.0 * (ell * m) * (q * n) * ncols / dt / 1e9, "unit": "GFLOP/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"first {ncols} of the 1024 right-hand sides, the dense matrix formed from the factors "
+                      f"(FP64), {dt:.1f} s on the host"}
+
+
 def learned_main(args):
     """Faces 512 x 512 in the transform domain with M-rank 32 and singular
     values 10^(-rho j), rho ~ U[1/16, 1/2] per face, energy rule tau = 1e-4.
@@ -405,6 +538,8 @@ def main():
         sys.exit(2)
     if args.workload == "uneven":
         return uneven_main(args)
+    if args.workload == "apply":
+        return apply_main(args)
     if args.workload == "learned":
         return learned_main(args)
     import torch

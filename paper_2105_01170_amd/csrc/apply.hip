@@ -132,6 +132,166 @@ __global__ __launch_bounds__(AT) void k_apply(const T *__restrict__ U, const dou
     }
 }
 
+// ---------------------------------------------------------------- matrix cores
+// The same contraction on FP32 16x16x4 MFMAs (FP32 and BF16-rounded operands).
+// Workgroup: block row j, rows a0 .. a0+63 of it and 64 columns; wavefront w
+// owns columns c0 + 16 w .. + 15 and all 64 rows.  Per stored face f:
+//   Z(r, c) = sum_k conj(V(j + l k, r)) conj(xt(k, c))  (real M: no conj)
+// in registers, 16 ranks per block (NRB blocks), over steps of 16 k: lane
+// (l16, kl) = (lane % 16, lane / 16) holds xt(16 kk + 4 kl + t, c0 + 16 w + l16),
+// t = 0..3, from one contiguous load, and MFMA step t takes entry t as its B
+// operand, so the A operand (lane l16 = rank) takes V at the same k.  Then
+//   y(a, c) += w_f Re(sum_r (U S)(a, r) Z(r, c))
+// with Z straight from the accumulators: the FP32 16x16x4 output holds rank
+// 4 kl + v of the block in entry v, so step s of the second product takes
+// entry s as its B operand and (U S)(a, 16 rb + 4 kl + s) as its A operand.
+// Complex products: Zr = Vr Xr - Vi Xi and nZi = Vr Xi + Vi Xr (= -Im Z), so
+// Re(US Z) = USr Zr + USi nZi.  Elements that do not exist (k >= q, r >= rank,
+// a >= m, c >= nrhs) load as zero through the 2^31 offset of a buffer
+// resource per face (each under 2 GiB, checked on the host) or a select.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+constexpr uint32_t kMiss = 0x80000000u;
+
+__device__ __forceinline__ uint32_t miss_if(bool bad) { return bad ? kMiss : 0u; }
+
+template <bool CPLX, bool BF, int NRB>
+__global__ __launch_bounds__(AT) void k_apply_mfma(const float *__restrict__ U, const double *__restrict__ S,
+                                                   const float *__restrict__ V, const int32_t *__restrict__ ranks,
+                                                   int m, int p, int kmax, int nf, int n3, int ell, int q,
+                                                   const float *__restrict__ xt, int nrhs, float *__restrict__ y,
+                                                   int64_t ldy) {
+    constexpr int E = CPLX ? 2 : 1;
+    const int kcap = kmax < 16 * NRB ? kmax : 16 * NRB;
+    const int mtiles = (m + 63) >> 6;
+    const int j = blockIdx.x / mtiles, a0 = (blockIdx.x % mtiles) * 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int l16 = lane & 15, kl = lane >> 4;
+    const int c = blockIdx.y * 64 + 16 * w + l16;
+    const bool cok = c < nrhs;
+    const int nkk = (q + 15) >> 4;
+    f32x4 acc[4];
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab) acc[ab] = f32x4{0, 0, 0, 0};
+    for (int f = 0; f < nf; ++f) {
+        int kf = ranks[f];
+        kf = kf < kcap ? kf : kcap;
+        if (kf <= 0) continue;
+        const float wgt = (CPLX && !(f == 0 || 2 * f == n3)) ? 2.0f : 1.0f;
+        const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(xt) + (int64_t)f * q * nrhs * E, 0, q * nrhs * E * 4, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(V) + (int64_t)f * p * kmax * E, 0, p * kmax * E * 4, 0x00020000);
+        const __amdgpu_buffer_rsrc_t ru = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(U) + (int64_t)f * m * kmax * E, 0, m * kmax * E * 4, 0x00020000);
+        f32x4 zr[NRB], zi[NRB];
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) zr[rb] = zi[rb] = f32x4{0, 0, 0, 0};
+        for (int kk = 0; kk < nkk; ++kk) {
+            const int k0 = 16 * kk + 4 * kl;
+            // B operand: xt(k0 .. k0+3, c)
+            const uint32_t xo = (((uint32_t)k0 + (uint32_t)q * (uint32_t)c) * (4u * E)) | miss_if(!cok || k0 >= q);
+            float xr[4], xi[4];
+            if (CPLX) {
+                const u32x4 x01 = __builtin_amdgcn_raw_buffer_load_b128(rx, (int)xo, 0, 0);
+                const u32x4 x23 = __builtin_amdgcn_raw_buffer_load_b128(rx, (int)(xo + 16u), 0, 0);
+                const uint32_t e0 = x01.x, e1 = x01.y, e2 = x01.z, e3 = x01.w;
+                const uint32_t e4 = x23.x, e5 = x23.y, e6 = x23.z, e7 = x23.w;
+                xr[0] = __uint_as_float(e0); xi[0] = __uint_as_float(e1);
+                xr[1] = __uint_as_float(e2); xi[1] = __uint_as_float(e3);
+                xr[2] = __uint_as_float(e4); xi[2] = __uint_as_float(e5);
+                xr[3] = __uint_as_float(e6); xi[3] = __uint_as_float(e7);
+            } else {
+                const u32x4 x03 = __builtin_amdgcn_raw_buffer_load_b128(rx, (int)xo, 0, 0);
+                const uint32_t e0 = x03.x, e1 = x03.y, e2 = x03.z, e3 = x03.w;
+                xr[0] = __uint_as_float(e0); xr[1] = __uint_as_float(e1);
+                xr[2] = __uint_as_float(e2); xr[3] = __uint_as_float(e3);
+                xi[0] = xi[1] = xi[2] = xi[3] = 0.0f;
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const bool kin = k0 + t < q;  // a partial last group reads the next column
+                xr[t] = kin ? (BF ? rbf(xr[t]) : xr[t]) : 0.0f;
+                xi[t] = kin ? (BF ? rbf(xi[t]) : xi[t]) : 0.0f;
+            }
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb) {
+                const int r = 16 * rb + l16;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const uint32_t vo =
+                        (((uint32_t)j + (uint32_t)ell * (uint32_t)(k0 + t) + (uint32_t)p * (uint32_t)r) * (4u * E)) | miss_if(r >= kf || k0 + t >= q);
+                    float vr, vi = 0.0f;
+                    if (CPLX) {
+                        const u32x2 v2 = __builtin_amdgcn_raw_buffer_load_b64(rv, (int)vo, 0, 0);
+                        const uint32_t g0 = v2.x, g1 = v2.y;
+                        vr = __uint_as_float(g0);
+                        vi = __uint_as_float(g1);
+                    } else {
+                        vr = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rv, (int)vo, 0, 0));
+                    }
+                    if (BF) {
+                        vr = rbf(vr);
+                        vi = rbf(vi);
+                    }
+                    zr[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr, xr[t], zr[rb], 0, 0, 0);
+                    if (CPLX) {
+                        zr[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-vi, xi[t], zr[rb], 0, 0, 0);
+                        zi[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr, xi[t], zi[rb], 0, 0, 0);
+                        zi[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vi, xr[t], zi[rb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+        // y += w Re(U S Z): A operand (U S)(a0 + 16 ab + l16, 16 rb + 4 kl + s)
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int r = 16 * rb + 4 * kl + s;
+                const bool rin = r < kf;
+                const double sr = rin ? S[(int64_t)f * kmax + r] : 0.0;
+                const float bzr = zr[rb][s];
+                const float bzi = zi[rb][s];
+#pragma unroll
+                for (int ab = 0; ab < 4; ++ab) {
+                    const int a = a0 + 16 * ab + l16;
+                    const uint32_t uo = (((uint32_t)a + (uint32_t)m * (uint32_t)r) * (4u * E)) | miss_if(!rin || a >= m);
+                    float ur, ui = 0.0f;
+                    if (CPLX) {
+                        const u32x2 u2 = __builtin_amdgcn_raw_buffer_load_b64(ru, (int)uo, 0, 0);
+                        const uint32_t g0 = u2.x, g1 = u2.y;
+                        ur = __uint_as_float(g0);
+                        ui = __uint_as_float(g1);
+                    } else {
+                        ur = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ru, (int)uo, 0, 0));
+                    }
+                    // (U S) rounded as stored by the plain kernel, then the
+                    // exact conjugate-pair weight
+                    float usr = (float)((double)ur * sr), usi = (float)((double)ui * sr);
+                    if (BF) {
+                        usr = rbf(usr);
+                        usi = rbf(usi);
+                    }
+                    acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(usr * wgt, bzr, acc[ab], 0, 0, 0);
+                    if (CPLX) acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(usi * wgt, bzi, acc[ab], 0, 0, 0);
+                }
+            }
+        }
+    }
+    // FP32 16x16x4 output: row 4 kl + v of block ab, column l16
+    if (cok) {
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = a0 + 16 * ab + 4 * kl + v;
+                if (a < m) y[((int64_t)j * m + a) + ldy * c] = acc[ab][v];
+            }
+    }
+}
+
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
@@ -181,6 +341,43 @@ tsvdm_status launch_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t 
     }
     const int64_t mtiles = (F->m + 63) / 64;
     dim3 grid((unsigned)(mtiles * ell), (unsigned)((nrhs + 63) / 64));
+    // FP32 and BF16: the matrix-core kernel, when every per-face buffer and
+    // every offset it forms (64 past the last column, row and rank included)
+    // stays below 2 GiB
+    const int64_t E = cplx ? 2 : 1, lim = int64_t(1) << 31;
+    const bool mfma_fits = !dbl && (int64_t)q * (nrhs + 64) * 4 * E + 64 < lim &&
+                           ((int64_t)ell * (q + 16) + F->p * (int64_t)64) * 4 * E < lim &&
+                           (F->m + 64 + F->m * (int64_t)64) * 4 * E < lim && F->p * F->kmax * 4 * E < lim &&
+                           mtiles * ell < lim;
+    if (mfma_fits) {
+        const int nrb = (kcap + 15) / 16;
+#define TSVDM_APPLY_MFMA(C, B, NRB)                                                                        \
+    TSVDM_LAUNCH("apply_fused", (k_apply_mfma<C, B, NRB>), grid, dim3(AT), 0, s,                             \
+                 reinterpret_cast<const float *>(F->U), F->S, reinterpret_cast<const float *>(F->V), F->ranks, \
+                 (int)F->m, (int)F->p, (int)F->kmax, (int)nf, (int)n3, (int)ell, (int)q,                    \
+                 reinterpret_cast<const float *>(ws), (int)nrhs, reinterpret_cast<float *>(y), ldy)
+#define TSVDM_APPLY_NRB(C, B)                         \
+    do {                                              \
+        switch (nrb) {                                \
+            case 1: TSVDM_APPLY_MFMA(C, B, 1); break; \
+            case 2: TSVDM_APPLY_MFMA(C, B, 2); break; \
+            case 3: TSVDM_APPLY_MFMA(C, B, 3); break; \
+            default: TSVDM_APPLY_MFMA(C, B, 4); break; \
+        }                                             \
+    } while (0)
+        const bool bf = compute == TSVDM_BF16;
+        if (cplx) {
+            if (bf) TSVDM_APPLY_NRB(true, true);
+            else TSVDM_APPLY_NRB(true, false);
+        } else {
+            if (bf) TSVDM_APPLY_NRB(false, true);
+            else TSVDM_APPLY_NRB(false, false);
+        }
+#undef TSVDM_APPLY_NRB
+#undef TSVDM_APPLY_MFMA
+        TSVDM_LAUNCH_CHECK("k_apply_mfma");
+        return TSVDM_OK;
+    }
 #define TSVDM_APPLY(T, C, B)                                                                        \
     do {                                                                                            \
         if (lds > 65536) {                                                                          \

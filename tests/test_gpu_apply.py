@@ -15,15 +15,20 @@ from paper_2105_01170_amd import tsvdm as C  # noqa: E402
 TOL = {C.F64: 1e-10, C.F32: 2e-5, C.BF16: 3e-2}
 
 
-def _case(kind, m, ell, q, n, k, nrhs, compute, salt=0):
+def _case(kind, m, ell, q, n, k, nrhs, compute, salt=0, ranks=None):
+    """ranks: rank of every stored face (default k); a DFT face t and its
+    conjugate n - t share the rank of stored face min(t, n - t)."""
     w = synth.apply_factors(m=m, ell=ell, q=q, n=n, k=k, nrhs=nrhs, salt=salt)
     p = ell * q
     M = oracle.dct2_matrix(n) if kind == C.M_DCT2 else oracle.dft_matrix(n)
+    nf = n // 2 + 1 if kind == C.M_DFT else n
+    ranks = np.full(nf, k, dtype=np.int32) if ranks is None else np.asarray(ranks, dtype=np.int32)
     # oracle: dense A_hat from the spatial factors, every face of the transform domain
     Uh, Vh = oracle.mode3(w["U"], M), oracle.mode3(w["V"], M)
     That = np.zeros((m, p, n), dtype=Uh.dtype, order="F")
     for f in range(n):
-        That[:, :, f] = (Uh[:, :, f] * w["sigma"]) @ np.conj(Vh[:, :, f]).T
+        r = ranks[min(f, n - f)] if kind == C.M_DFT else ranks[f]
+        That[:, :, f] = (Uh[:, :r, f] * w["sigma"][:r]) @ np.conj(Vh[:, :r, f]).T
     T = oracle.inverse_mode3(That, M)
     if kind == C.M_DFT:
         T = np.real(T)
@@ -34,10 +39,9 @@ def _case(kind, m, ell, q, n, k, nrhs, compute, salt=0):
     tdt = torch.float64 if compute == C.F64 else torch.float32
     Ud = api.transform(to_dev(w["U"], rdt), m, k, n, kind, +1)
     Vd = api.transform(to_dev(w["V"], rdt), p, k, n, kind, +1)
-    nf = n // 2 + 1 if kind == C.M_DFT else n
     S = torch.tensor(np.tile(w["sigma"][:, None], (1, nf)).ravel(order="F"), dtype=torch.float64,
                      device="cuda")
-    F = api.Factors(m, p, nf, k, Ud, S, Vd, torch.full((nf,), k, dtype=torch.int32, device="cuda"),
+    F = api.Factors(m, p, nf, k, Ud, S, Vd, torch.from_numpy(ranks).to("cuda"),
                     torch.zeros(nf, dtype=torch.float64, device="cuda"),
                     torch.zeros(nf, dtype=torch.float64, device="cuda"),
                     torch.zeros(nf, dtype=torch.int32, device="cuda"))
@@ -61,3 +65,17 @@ def test_apply_full_size_dft_fp32():
     right-hand sides, FP32, against the dense FP64 product."""
     y, y_ref = _case(C.M_DFT, 64, 64, 64, 64, 16, 1024, C.F32)
     assert relerr(y, y_ref) < TOL[C.F32]
+
+
+@pytest.mark.parametrize("compute", [C.F32, C.BF16, C.F64])
+@pytest.mark.parametrize("kind", [C.M_DCT2, C.M_DFT])
+def test_apply_face_ranks_below_kmax(kind, compute):
+    """Per-face ranks below the stored width (zero included) and a width above
+    16 (two blocks of 16 ranks), 70 rows (two row tiles), a ragged column tile."""
+    m, ell, q, n, k, nrhs = 70, 3, 21, 10, 24, 70
+    g = np.random.default_rng(11)
+    nf = n // 2 + 1 if kind == C.M_DFT else n
+    ranks = g.integers(0, k + 1, size=nf)
+    ranks[0], ranks[-1] = 0, k
+    y, y_ref = _case(kind, m, ell, q, n, k, nrhs, compute, ranks=ranks)
+    assert relerr(y, y_ref) < TOL[compute], relerr(y, y_ref)
