@@ -140,7 +140,8 @@ __global__ __launch_bounds__(AT) void k_apply(const T *__restrict__ U, const dou
 // in registers, 16 ranks per block (NRB blocks), over steps of 16 k: lane
 // (l16, kl) = (lane % 16, lane / 16) holds xt(16 kk + 4 kl + t, c0 + 16 w + l16),
 // t = 0..3, from one contiguous load, and MFMA step t takes entry t as its B
-// operand, so the A operand (lane l16 = rank) takes V at the same k.  Then
+// operand, so the A operand (lane l16 = rank) takes V at the same k, read
+// from a copy Vp whose rows j + l k of block row j are contiguous in k.  Then
 //   y(a, c) += w_f Re(sum_r (U S)(a, r) Z(r, c))
 // with Z straight from the accumulators: the FP32 16x16x4 output holds rank
 // 4 kl + v of the block in entry v, so step s of the second product takes
@@ -156,9 +157,23 @@ constexpr uint32_t kMiss = 0x80000000u;
 
 __device__ __forceinline__ uint32_t miss_if(bool bad) { return bad ? kMiss : 0u; }
 
+// Vp_f(k + q j, r) = Vhat_f(j + l k, r): the rows a block row j takes, made
+// contiguous in k (one thread per element of E floats, read in order)
+template <int E>
+__global__ __launch_bounds__(256) void k_vrelayout(const float *__restrict__ V, float *__restrict__ Vp, int64_t p,
+                                                   int64_t ell, int64_t q, int64_t total) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= total) return;
+    const int64_t col = i / p, b = i - col * p;  // col = r + kmax f
+    const int64_t j = b % ell, k = b / ell;
+    const int64_t o = col * p + k + q * j;
+#pragma unroll
+    for (int e = 0; e < E; ++e) Vp[o * E + e] = V[i * E + e];
+}
+
 template <bool CPLX, bool BF, int NRB>
 __global__ __launch_bounds__(AT) void k_apply_mfma(const float *__restrict__ U, const double *__restrict__ S,
-                                                   const float *__restrict__ V, const int32_t *__restrict__ ranks,
+                                                   const float *__restrict__ Vp, const int32_t *__restrict__ ranks,
                                                    int m, int p, int kmax, int nf, int n3, int ell, int q,
                                                    const float *__restrict__ xt, int nrhs, float *__restrict__ y,
                                                    int64_t ldy) {
@@ -182,7 +197,7 @@ __global__ __launch_bounds__(AT) void k_apply_mfma(const float *__restrict__ U, 
         const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float *>(xt) + (int64_t)f * q * nrhs * E, 0, q * nrhs * E * 4, 0x00020000);
         const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(
-            const_cast<float *>(V) + (int64_t)f * p * kmax * E, 0, p * kmax * E * 4, 0x00020000);
+            const_cast<float *>(Vp) + (int64_t)f * p * kmax * E, 0, p * kmax * E * 4, 0x00020000);
         const __amdgpu_buffer_rsrc_t ru = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float *>(U) + (int64_t)f * m * kmax * E, 0, m * kmax * E * 4, 0x00020000);
         f32x4 zr[NRB], zi[NRB];
@@ -218,19 +233,32 @@ __global__ __launch_bounds__(AT) void k_apply_mfma(const float *__restrict__ U, 
 #pragma unroll
             for (int rb = 0; rb < NRB; ++rb) {
                 const int r = 16 * rb + l16;
+                // A operand: Vp(k0 .. k0+3 + q j, r), zero past the rank or q
+                const uint32_t vo =
+                    (((uint32_t)k0 + (uint32_t)q * (uint32_t)j + (uint32_t)p * (uint32_t)r) * (4u * E)) |
+                    miss_if(r >= kf || k0 >= q);
+                float vra[4], via[4];
+                if (CPLX) {
+                    const u32x4 v01 = __builtin_amdgcn_raw_buffer_load_b128(rv, (int)vo, 0, 0);
+                    const uint32_t g0 = v01.x, g1 = v01.y, g2 = v01.z, g3 = v01.w;
+                    const u32x4 v23 = __builtin_amdgcn_raw_buffer_load_b128(rv, (int)(vo + 16u), 0, 0);
+                    const uint32_t g4 = v23.x, g5 = v23.y, g6 = v23.z, g7 = v23.w;
+                    vra[0] = __uint_as_float(g0); via[0] = __uint_as_float(g1);
+                    vra[1] = __uint_as_float(g2); via[1] = __uint_as_float(g3);
+                    vra[2] = __uint_as_float(g4); via[2] = __uint_as_float(g5);
+                    vra[3] = __uint_as_float(g6); via[3] = __uint_as_float(g7);
+                } else {
+                    const u32x4 v03 = __builtin_amdgcn_raw_buffer_load_b128(rv, (int)vo, 0, 0);
+                    const uint32_t g0 = v03.x, g1 = v03.y, g2 = v03.z, g3 = v03.w;
+                    vra[0] = __uint_as_float(g0); vra[1] = __uint_as_float(g1);
+                    vra[2] = __uint_as_float(g2); vra[3] = __uint_as_float(g3);
+                    via[0] = via[1] = via[2] = via[3] = 0.0f;
+                }
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const uint32_t vo =
-                        (((uint32_t)j + (uint32_t)ell * (uint32_t)(k0 + t) + (uint32_t)p * (uint32_t)r) * (4u * E)) | miss_if(r >= kf || k0 + t >= q);
-                    float vr, vi = 0.0f;
-                    if (CPLX) {
-                        const u32x2 v2 = __builtin_amdgcn_raw_buffer_load_b64(rv, (int)vo, 0, 0);
-                        const uint32_t g0 = v2.x, g1 = v2.y;
-                        vr = __uint_as_float(g0);
-                        vi = __uint_as_float(g1);
-                    } else {
-                        vr = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rv, (int)vo, 0, 0));
-                    }
+                    // a partial last group reads the next block row's rows
+                    const bool kin = k0 + t < q;
+                    float vr = kin ? vra[t] : 0.0f, vi = kin ? via[t] : 0.0f;
                     if (BF) {
                         vr = rbf(vr);
                         vi = rbf(vi);
@@ -303,7 +331,9 @@ size_t apply_workspace(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell
     (void)ell;
     const bool cplx = M->kind == TSVDM_M_DFT;
     const size_t es = (compute == TSVDM_F64 ? 8 : 4) * (cplx ? 2 : 1);
-    return al256(es * (size_t)q * nrhs * F->nf);
+    // the transformed right-hand sides; FP32 and BF16 also the relaid-out V
+    return al256(es * (size_t)q * nrhs * F->nf) +
+           (compute == TSVDM_F64 ? 0 : al256(es * (size_t)F->p * F->kmax * F->nf));
 }
 
 tsvdm_status launch_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell, int64_t q,
@@ -346,14 +376,25 @@ tsvdm_status launch_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t 
     // stays below 2 GiB
     const int64_t E = cplx ? 2 : 1, lim = int64_t(1) << 31;
     const bool mfma_fits = !dbl && (int64_t)q * (nrhs + 64) * 4 * E + 64 < lim &&
-                           ((int64_t)ell * (q + 16) + F->p * (int64_t)64) * 4 * E < lim &&
+                           ((int64_t)q * (ell + 1) + 16 + F->p * (int64_t)64) * 4 * E + 64 < lim &&
                            (F->m + 64 + F->m * (int64_t)64) * 4 * E < lim && F->p * F->kmax * 4 * E < lim &&
                            mtiles * ell < lim;
     if (mfma_fits) {
         const int nrb = (kcap + 15) / 16;
+        float *Vp = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + al256(es * (size_t)q * nrhs * nf));
+        const int64_t tot = F->p * F->kmax * nf;
+        if (tot > 0) {
+            const dim3 gr((unsigned)((tot + 255) / 256));
+            if (cplx)
+                TSVDM_LAUNCH("apply_v_relayout", k_vrelayout<2>, gr, dim3(256), 0, s,
+                             reinterpret_cast<const float *>(F->V), Vp, F->p, ell, q, tot);
+            else
+                TSVDM_LAUNCH("apply_v_relayout", k_vrelayout<1>, gr, dim3(256), 0, s,
+                             reinterpret_cast<const float *>(F->V), Vp, F->p, ell, q, tot);
+        }
 #define TSVDM_APPLY_MFMA(C, B, NRB)                                                                        \
     TSVDM_LAUNCH("apply_fused", (k_apply_mfma<C, B, NRB>), grid, dim3(AT), 0, s,                             \
-                 reinterpret_cast<const float *>(F->U), F->S, reinterpret_cast<const float *>(F->V), F->ranks, \
+                 reinterpret_cast<const float *>(F->U), F->S, Vp, F->ranks,                                  \
                  (int)F->m, (int)F->p, (int)F->kmax, (int)nf, (int)n3, (int)ell, (int)q,                    \
                  reinterpret_cast<const float *>(ws), (int)nrhs, reinterpret_cast<float *>(y), ldy)
 #define TSVDM_APPLY_NRB(C, B)                         \
