@@ -146,8 +146,9 @@ __global__ __launch_bounds__(AT) void k_apply(const T *__restrict__ U, const dou
 // with Z straight from the accumulators: the FP32 16x16x4 output holds rank
 // 4 kl + v of the block in entry v, so step s of the second product takes
 // entry s as its B operand and (U S)(a, 16 rb + 4 kl + s) as its A operand.
-// Complex products: Zr = Vr Xr - Vi Xi and nZi = Vr Xi + Vi Xr (= -Im Z), so
-// Re(US Z) = USr Zr + USi nZi.  Elements that do not exist (k >= q, r >= rank,
+// Complex products: Zr = Vr Xr - Vi Xi and nZi = Vr Xi + Vi Xr (= -Im Z), the
+// latter as (Vr + Vi)(Xr + Xi) - Vr Xr - Vi Xi (three real products, Gauss),
+// so Re(US Z) = USr Zr + USi nZi.  Elements that do not exist (k >= q, r >= rank,
 // a >= m, c >= nrhs) load as zero through the 2^31 offset of a buffer
 // resource per face (each under 2 GiB, checked on the host) or a select.
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -200,9 +201,12 @@ __global__ __launch_bounds__(AT) void k_apply_mfma(const float *__restrict__ U, 
             const_cast<float *>(Vp) + (int64_t)f * p * kmax * E, 0, p * kmax * E * 4, 0x00020000);
         const __amdgpu_buffer_rsrc_t ru = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float *>(U) + (int64_t)f * m * kmax * E, 0, m * kmax * E * 4, 0x00020000);
-        f32x4 zr[NRB], zi[NRB];
+        // complex: zr, zi and z3 collect Vr Xr, Vi Xi and (Vr + Vi)(Xr + Xi)
+        // (three real products per complex one); Zr and nZi are formed after
+        // the k loop
+        f32x4 zr[NRB], zi[NRB], z3[NRB];
 #pragma unroll
-        for (int rb = 0; rb < NRB; ++rb) zr[rb] = zi[rb] = f32x4{0, 0, 0, 0};
+        for (int rb = 0; rb < NRB; ++rb) zr[rb] = zi[rb] = z3[rb] = f32x4{0, 0, 0, 0};
         for (int kk = 0; kk < nkk; ++kk) {
             const int k0 = 16 * kk + 4 * kl;
             // B operand: xt(k0 .. k0+3, c)
@@ -265,11 +269,18 @@ __global__ __launch_bounds__(AT) void k_apply_mfma(const float *__restrict__ U, 
                     }
                     zr[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr, xr[t], zr[rb], 0, 0, 0);
                     if (CPLX) {
-                        zr[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(-vi, xi[t], zr[rb], 0, 0, 0);
-                        zi[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr, xi[t], zi[rb], 0, 0, 0);
-                        zi[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vi, xr[t], zi[rb], 0, 0, 0);
+                        zi[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vi, xi[t], zi[rb], 0, 0, 0);
+                        z3[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr + vi, xr[t] + xi[t], z3[rb], 0, 0, 0);
                     }
                 }
+            }
+        }
+        if (CPLX) {
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb) {
+                const f32x4 p1 = zr[rb], p2 = zi[rb];
+                zr[rb] = p1 - p2;          // Vr Xr - Vi Xi
+                zi[rb] = z3[rb] - p1 - p2; // Vr Xi + Vi Xr = -Im Z
             }
         }
         // y += w Re(U S Z): A operand (U S)(a0 + 16 ab + l16, 16 rb + 4 kl + s)
