@@ -97,11 +97,11 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 summary
+def measured_traffic(kernel, profile="tsvdm_mixed_512x512x256_k32.md"):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 summary
     (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy), or None when the
     kernel sources changed since the counters were taken."""
-    fn = os.path.join(ROOT, "profiles", "tsvdm_mixed_512x512x256_k32.md")
+    fn = os.path.join(ROOT, "profiles", profile)
     try:
         with open(fn) as f:
             for line in f:
@@ -349,7 +349,7 @@ def apply_main(args):
         roof = {"bound": "mfma", "achieved": per_launch / avg_s / 1e12, "peak": FP32_MFMA_PEAK_TFLOPS,
                 "unit": "TFLOP/s (fp32)"}
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom, "tsvdm_apply_4096_dft_r16.md")
     roof["kernel"] = dom
     roof["avg_us"] = 1e6 * avg_s
     out = {
