@@ -331,6 +331,191 @@ __global__ __launch_bounds__(AT) void k_apply_mfma(const float *__restrict__ U, 
     }
 }
 
+// Ranks <= 16: the same products with the workgroup's operands staged in LDS.
+// Per face and chunk of 32 k, the 256 threads copy x~ (64 columns), the 16
+// rank rows of Vp and, on the first chunk, U S w (64 rows, rounded as the
+// plain kernel rounds it) with 16-byte loads, consecutive lanes on
+// consecutive 16-byte pieces of one column or row; elements that do not
+// exist are stored as zero.  Columns of x~ and rows of Vp are padded by 16
+// bytes (no bank conflicts for the 16-byte operand reads).  The four
+// wavefronts then read their MFMA operands from LDS in the layout above.
+template <bool CPLX, bool BF>
+__global__ __launch_bounds__(AT) void k_apply_lds(const float *__restrict__ U, const double *__restrict__ S,
+                                                  const float *__restrict__ Vp, const int32_t *__restrict__ ranks,
+                                                  int m, int p, int kmax, int nf, int n3, int ell, int q,
+                                                  const float *__restrict__ xt, int nrhs, float *__restrict__ y,
+                                                  int64_t ldy) {
+    constexpr int E = CPLX ? 2 : 1;
+    constexpr int KC = 32;              // k per chunk
+    constexpr int XS = KC * E + 4;      // floats per staged column of x~ or row of Vp
+    constexpr int US = 16 * E + 4;      // floats per staged row of U S
+    constexpr int KPC = 4 / E;          // k (or rows a) per 16-byte piece
+    constexpr int CH = KC / KPC;        // pieces per column
+    __shared__ __align__(16) float xs[64 * XS];
+    __shared__ __align__(16) float vs[16 * XS];
+    __shared__ __align__(16) float us[64 * US];
+    const int kcap = kmax < 16 ? kmax : 16;
+    const int mtiles = (m + 63) >> 6;
+    const int j = blockIdx.x / mtiles, a0 = (blockIdx.x % mtiles) * 64;
+    const int c0 = blockIdx.y * 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int l16 = lane & 15, kl = lane >> 4;
+    f32x4 acc[4];
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab) acc[ab] = f32x4{0, 0, 0, 0};
+    for (int f = 0; f < nf; ++f) {
+        int kf = ranks[f];
+        kf = kf < kcap ? kf : kcap;
+        if (kf <= 0) continue;
+        const float wgt = (CPLX && !(f == 0 || 2 * f == n3)) ? 2.0f : 1.0f;
+        const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(xt) + (int64_t)f * q * nrhs * E, 0, q * nrhs * E * 4, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(Vp) + (int64_t)f * p * kmax * E, 0, p * kmax * E * 4, 0x00020000);
+        const __amdgpu_buffer_rsrc_t ru = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<float *>(U) + (int64_t)f * m * kmax * E, 0, m * kmax * E * 4, 0x00020000);
+        f32x4 zr = f32x4{0, 0, 0, 0}, zi = zr, z3 = zr;
+        for (int kc0 = 0; kc0 < q; kc0 += KC) {
+            __syncthreads();  // the previous chunk's (or face's) operands are consumed
+            // x~: 64 columns x CH pieces
+            for (int g = tid; g < 64 * CH; g += AT) {
+                const int cc = g / CH, h = g % CH;
+                const int k = kc0 + KPC * h, c = c0 + cc;
+                const uint32_t xo = (((uint32_t)k + (uint32_t)q * (uint32_t)c) * (4u * E)) | miss_if(c >= nrhs || k >= q);
+                const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rx, (int)xo, 0, 0);
+                const uint32_t e0 = v.x, e1 = v.y, e2 = v.z, e3 = v.w;
+                float4 o;
+                // a piece across q reads the next column: its entries past q are zeroed
+                o.x = __uint_as_float(e0);
+                o.y = (CPLX ? k : k + 1) < q ? __uint_as_float(e1) : 0.0f;
+                o.z = (CPLX ? k + 1 : k + 2) < q ? __uint_as_float(e2) : 0.0f;
+                o.w = (CPLX ? k + 1 : k + 3) < q ? __uint_as_float(e3) : 0.0f;
+                if (BF) {
+                    o.x = rbf(o.x);
+                    o.y = rbf(o.y);
+                    o.z = rbf(o.z);
+                    o.w = rbf(o.w);
+                }
+                *reinterpret_cast<float4 *>(&xs[cc * XS + KPC * h * E]) = o;
+            }
+            // Vp rows of the 16 ranks
+            for (int g = tid; g < 16 * CH; g += AT) {
+                const int r = g / CH, h = g % CH;
+                const int k = kc0 + KPC * h;
+                const uint32_t vo = (((uint32_t)k + (uint32_t)q * (uint32_t)j + (uint32_t)p * (uint32_t)r) * (4u * E)) |
+                                    miss_if(r >= kf || k >= q);
+                const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rv, (int)vo, 0, 0);
+                const uint32_t e0 = v.x, e1 = v.y, e2 = v.z, e3 = v.w;
+                float4 o;
+                o.x = __uint_as_float(e0);
+                o.y = (CPLX ? k : k + 1) < q ? __uint_as_float(e1) : 0.0f;
+                o.z = (CPLX ? k + 1 : k + 2) < q ? __uint_as_float(e2) : 0.0f;
+                o.w = (CPLX ? k + 1 : k + 3) < q ? __uint_as_float(e3) : 0.0f;
+                if (BF) {
+                    o.x = rbf(o.x);
+                    o.y = rbf(o.y);
+                    o.z = rbf(o.z);
+                    o.w = rbf(o.w);
+                }
+                *reinterpret_cast<float4 *>(&vs[r * XS + KPC * h * E]) = o;
+            }
+            if (kc0 == 0) {
+                // U S w, transposed to rows a: 16 ranks x (64 / KPC) pieces of KPC rows
+                for (int g = tid; g < 16 * (64 / KPC); g += AT) {
+                    const int r = g / (64 / KPC), h = g % (64 / KPC);
+                    const int a = a0 + KPC * h;
+                    const bool rin = r < kf;
+                    const uint32_t uo = (((uint32_t)a + (uint32_t)m * (uint32_t)r) * (4u * E)) | miss_if(!rin || a >= m);
+                    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(ru, (int)uo, 0, 0);
+                    const uint32_t e[4] = {v.x, v.y, v.z, v.w};
+                    const double sr = rin ? S[(int64_t)f * kmax + r] : 0.0;
+#pragma unroll
+                    for (int i = 0; i < KPC; ++i) {
+                        const bool ain = a + i < m;  // the next rank's rows past m
+#pragma unroll
+                        for (int ee = 0; ee < E; ++ee) {
+                            float x = ain ? (float)((double)__uint_as_float(e[i * E + ee]) * sr) : 0.0f;
+                            if (BF) x = rbf(x);
+                            us[(KPC * h + i) * US + r * E + ee] = x * wgt;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // Z += conj(V^T x~) over this chunk's k, in steps of 16
+            const int nkk = (q - kc0 < KC ? q - kc0 + 15 : KC) >> 4;
+            for (int kk = 0; kk < nkk; ++kk) {
+                const float *xp = &xs[(16 * w + l16) * XS + (16 * kk + 4 * kl) * E];
+                const float *vp = &vs[l16 * XS + (16 * kk + 4 * kl) * E];
+                float xr[4], xi[4], vr[4], vi[4];
+                if (CPLX) {
+                    const float4 xa = *reinterpret_cast<const float4 *>(xp);
+                    const float4 xb = *reinterpret_cast<const float4 *>(xp + 4);
+                    const float4 va = *reinterpret_cast<const float4 *>(vp);
+                    const float4 vb = *reinterpret_cast<const float4 *>(vp + 4);
+                    xr[0] = xa.x; xi[0] = xa.y; xr[1] = xa.z; xi[1] = xa.w;
+                    xr[2] = xb.x; xi[2] = xb.y; xr[3] = xb.z; xi[3] = xb.w;
+                    vr[0] = va.x; vi[0] = va.y; vr[1] = va.z; vi[1] = va.w;
+                    vr[2] = vb.x; vi[2] = vb.y; vr[3] = vb.z; vi[3] = vb.w;
+                } else {
+                    const float4 xa = *reinterpret_cast<const float4 *>(xp);
+                    const float4 va = *reinterpret_cast<const float4 *>(vp);
+                    xr[0] = xa.x; xr[1] = xa.y; xr[2] = xa.z; xr[3] = xa.w;
+                    vr[0] = va.x; vr[1] = va.y; vr[2] = va.z; vr[3] = va.w;
+                    xi[0] = xi[1] = xi[2] = xi[3] = 0.0f;
+                    vi[0] = vi[1] = vi[2] = vi[3] = 0.0f;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    zr = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[t], xr[t], zr, 0, 0, 0);
+                    if (CPLX) {
+                        zi = __builtin_amdgcn_mfma_f32_16x16x4f32(vi[t], xi[t], zi, 0, 0, 0);
+                        z3 = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[t] + vi[t], xr[t] + xi[t], z3, 0, 0, 0);
+                    }
+                }
+            }
+        }
+        if (CPLX) {
+            const f32x4 p1 = zr, p2 = zi;
+            zr = p1 - p2;       // Vr Xr - Vi Xi
+            zi = z3 - p1 - p2;  // Vr Xi + Vi Xr = -Im Z
+        }
+        // y += Re(U S w Z), A operand from the staged rows of U S w
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab) {
+            const float *up = &us[(16 * ab + l16) * US + 4 * kl * E];
+            float ur[4], ui[4];
+            if (CPLX) {
+                const float4 ua = *reinterpret_cast<const float4 *>(up);
+                const float4 ub = *reinterpret_cast<const float4 *>(up + 4);
+                ur[0] = ua.x; ui[0] = ua.y; ur[1] = ua.z; ui[1] = ua.w;
+                ur[2] = ub.x; ui[2] = ub.y; ur[3] = ub.z; ui[3] = ub.w;
+            } else {
+                const float4 ua = *reinterpret_cast<const float4 *>(up);
+                ur[0] = ua.x; ur[1] = ua.y; ur[2] = ua.z; ur[3] = ua.w;
+                ui[0] = ui[1] = ui[2] = ui[3] = 0.0f;
+            }
+#pragma unroll
+            for (int sx = 0; sx < 4; ++sx) {
+                const float bzr = zr[sx];
+                const float bzi = zi[sx];
+                acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[sx], bzr, acc[ab], 0, 0, 0);
+                if (CPLX) acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(ui[sx], bzi, acc[ab], 0, 0, 0);
+            }
+        }
+    }
+    const int c = c0 + 16 * w + l16;
+    if (c < nrhs) {
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = a0 + 16 * ab + 4 * kl + v;
+                if (a < m) y[((int64_t)j * m + a) + ldy * c] = acc[ab][v];
+            }
+    }
+}
+
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
@@ -418,7 +603,21 @@ tsvdm_status launch_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t 
         }                                             \
     } while (0)
         const bool bf = compute == TSVDM_BF16;
-        if (cplx) {
+        if (nrb == 1) {
+#define TSVDM_APPLY_LDS(C, B)                                                                                \
+    TSVDM_LAUNCH("apply_fused", (k_apply_lds<C, B>), grid, dim3(AT), 0, s,                                   \
+                 reinterpret_cast<const float *>(F->U), F->S, Vp, F->ranks, (int)F->m, (int)F->p, (int)F->kmax, \
+                 (int)nf, (int)n3, (int)ell, (int)q, reinterpret_cast<const float *>(ws), (int)nrhs,          \
+                 reinterpret_cast<float *>(y), ldy)
+            if (cplx) {
+                if (bf) TSVDM_APPLY_LDS(true, true);
+                else TSVDM_APPLY_LDS(true, false);
+            } else {
+                if (bf) TSVDM_APPLY_LDS(false, true);
+                else TSVDM_APPLY_LDS(false, false);
+            }
+#undef TSVDM_APPLY_LDS
+        } else if (cplx) {
             if (bf) TSVDM_APPLY_NRB(true, true);
             else TSVDM_APPLY_NRB(true, false);
         } else {
