@@ -339,6 +339,8 @@ __global__ __launch_bounds__(AT) void k_apply_mfma(const float *__restrict__ U, 
 // exist are stored as zero.  Columns of x~ and rows of Vp are padded by 16
 // bytes (no bank conflicts for the 16-byte operand reads).  The four
 // wavefronts then read their MFMA operands from LDS in the layout above.
+// The global loads of the next stage (face, chunk) are issued before the
+// current stage's products.
 template <bool CPLX, bool BF>
 __global__ __launch_bounds__(AT) void k_apply_lds(const float *__restrict__ U, const double *__restrict__ S,
                                                   const float *__restrict__ Vp, const int32_t *__restrict__ ranks,
@@ -360,149 +362,189 @@ __global__ __launch_bounds__(AT) void k_apply_lds(const float *__restrict__ U, c
     const int c0 = blockIdx.y * 64;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int l16 = lane & 15, kl = lane >> 4;
+    constexpr int NXU = (64 * CH + AT - 1) / AT;         // staging loads per thread: x~
+    constexpr int NVU = (16 * CH + AT - 1) / AT;         // Vp
+    constexpr int NUU = (16 * (64 / KPC) + AT - 1) / AT; // U
     f32x4 acc[4];
 #pragma unroll
     for (int ab = 0; ab < 4; ++ab) acc[ab] = f32x4{0, 0, 0, 0};
-    for (int f = 0; f < nf; ++f) {
-        int kf = ranks[f];
-        kf = kf < kcap ? kf : kcap;
-        if (kf <= 0) continue;
-        const float wgt = (CPLX && !(f == 0 || 2 * f == n3)) ? 2.0f : 1.0f;
+    auto face_rank = [&](int f) {
+        const int r = ranks[f];
+        return r < kcap ? r : kcap;
+    };
+    auto next_face = [&](int f) {  // first face from f on with a nonzero rank
+        while (f < nf && face_rank(f) <= 0) ++f;
+        return f;
+    };
+    // one stage = one face and chunk of k; its global loads go to registers
+    // one stage ahead, so that they are in flight during the previous stage's
+    // products
+    u32x4 gx[NXU], gv[NVU], gu[NUU];
+    double gs[NUU];
+    auto load_stage = [&](int f, int kc0) {
+        const int kf = face_rank(f);
         const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float *>(xt) + (int64_t)f * q * nrhs * E, 0, q * nrhs * E * 4, 0x00020000);
         const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float *>(Vp) + (int64_t)f * p * kmax * E, 0, p * kmax * E * 4, 0x00020000);
         const __amdgpu_buffer_rsrc_t ru = __builtin_amdgcn_make_buffer_rsrc(
             const_cast<float *>(U) + (int64_t)f * m * kmax * E, 0, m * kmax * E * 4, 0x00020000);
-        f32x4 zr = f32x4{0, 0, 0, 0}, zi = zr, z3 = zr;
-        for (int kc0 = 0; kc0 < q; kc0 += KC) {
-            __syncthreads();  // the previous chunk's (or face's) operands are consumed
-            // x~: 64 columns x CH pieces
-            for (int g = tid; g < 64 * CH; g += AT) {
-                const int cc = g / CH, h = g % CH;
-                const int k = kc0 + KPC * h, c = c0 + cc;
-                const uint32_t xo = (((uint32_t)k + (uint32_t)q * (uint32_t)c) * (4u * E)) | miss_if(c >= nrhs || k >= q);
-                const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rx, (int)xo, 0, 0);
-                const uint32_t e0 = v.x, e1 = v.y, e2 = v.z, e3 = v.w;
-                float4 o;
-                // a piece across q reads the next column: its entries past q are zeroed
-                o.x = __uint_as_float(e0);
-                o.y = (CPLX ? k : k + 1) < q ? __uint_as_float(e1) : 0.0f;
-                o.z = (CPLX ? k + 1 : k + 2) < q ? __uint_as_float(e2) : 0.0f;
-                o.w = (CPLX ? k + 1 : k + 3) < q ? __uint_as_float(e3) : 0.0f;
-                if (BF) {
-                    o.x = rbf(o.x);
-                    o.y = rbf(o.y);
-                    o.z = rbf(o.z);
-                    o.w = rbf(o.w);
-                }
-                *reinterpret_cast<float4 *>(&xs[cc * XS + KPC * h * E]) = o;
-            }
-            // Vp rows of the 16 ranks
-            for (int g = tid; g < 16 * CH; g += AT) {
-                const int r = g / CH, h = g % CH;
-                const int k = kc0 + KPC * h;
-                const uint32_t vo = (((uint32_t)k + (uint32_t)q * (uint32_t)j + (uint32_t)p * (uint32_t)r) * (4u * E)) |
-                                    miss_if(r >= kf || k >= q);
-                const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rv, (int)vo, 0, 0);
-                const uint32_t e0 = v.x, e1 = v.y, e2 = v.z, e3 = v.w;
-                float4 o;
-                o.x = __uint_as_float(e0);
-                o.y = (CPLX ? k : k + 1) < q ? __uint_as_float(e1) : 0.0f;
-                o.z = (CPLX ? k + 1 : k + 2) < q ? __uint_as_float(e2) : 0.0f;
-                o.w = (CPLX ? k + 1 : k + 3) < q ? __uint_as_float(e3) : 0.0f;
-                if (BF) {
-                    o.x = rbf(o.x);
-                    o.y = rbf(o.y);
-                    o.z = rbf(o.z);
-                    o.w = rbf(o.w);
-                }
-                *reinterpret_cast<float4 *>(&vs[r * XS + KPC * h * E]) = o;
-            }
-            if (kc0 == 0) {
-                // U S w, transposed to rows a: 16 ranks x (64 / KPC) pieces of KPC rows
-                for (int g = tid; g < 16 * (64 / KPC); g += AT) {
-                    const int r = g / (64 / KPC), h = g % (64 / KPC);
-                    const int a = a0 + KPC * h;
-                    const bool rin = r < kf;
-                    const uint32_t uo = (((uint32_t)a + (uint32_t)m * (uint32_t)r) * (4u * E)) | miss_if(!rin || a >= m);
-                    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(ru, (int)uo, 0, 0);
-                    const uint32_t e[4] = {v.x, v.y, v.z, v.w};
-                    const double sr = rin ? S[(int64_t)f * kmax + r] : 0.0;
 #pragma unroll
-                    for (int i = 0; i < KPC; ++i) {
-                        const bool ain = a + i < m;  // the next rank's rows past m
+        for (int u = 0; u < NXU; ++u) {
+            const int g = u * AT + tid, cc = g / CH, h = g % CH;
+            const int k = kc0 + KPC * h, c = c0 + cc;
+            const uint32_t xo = (((uint32_t)k + (uint32_t)q * (uint32_t)c) * (4u * E)) |
+                                miss_if(g >= 64 * CH || c >= nrhs || k >= q);
+            gx[u] = __builtin_amdgcn_raw_buffer_load_b128(rx, (int)xo, 0, 0);
+        }
 #pragma unroll
-                        for (int ee = 0; ee < E; ++ee) {
-                            float x = ain ? (float)((double)__uint_as_float(e[i * E + ee]) * sr) : 0.0f;
-                            if (BF) x = rbf(x);
-                            us[(KPC * h + i) * US + r * E + ee] = x * wgt;
-                        }
-                    }
-                }
+        for (int u = 0; u < NVU; ++u) {
+            const int g = u * AT + tid, r = g / CH, h = g % CH;
+            const int k = kc0 + KPC * h;
+            const uint32_t vo = (((uint32_t)k + (uint32_t)q * (uint32_t)j + (uint32_t)p * (uint32_t)r) * (4u * E)) |
+                                miss_if(g >= 16 * CH || r >= kf || k >= q);
+            gv[u] = __builtin_amdgcn_raw_buffer_load_b128(rv, (int)vo, 0, 0);
+        }
+        if (kc0 == 0) {
+#pragma unroll
+            for (int u = 0; u < NUU; ++u) {
+                const int g = u * AT + tid, r = g / (64 / KPC), h = g % (64 / KPC);
+                const int a = a0 + KPC * h;
+                const bool rin = g < 16 * (64 / KPC) && r < kf;
+                const uint32_t uo = (((uint32_t)a + (uint32_t)m * (uint32_t)r) * (4u * E)) | miss_if(!rin || a >= m);
+                gu[u] = __builtin_amdgcn_raw_buffer_load_b128(ru, (int)uo, 0, 0);
+                gs[u] = rin ? S[(int64_t)f * kmax + r] : 0.0;
             }
-            __syncthreads();
-            // Z += conj(V^T x~) over this chunk's k, in steps of 16
-            const int nkk = (q - kc0 < KC ? q - kc0 + 15 : KC) >> 4;
-            for (int kk = 0; kk < nkk; ++kk) {
-                const float *xp = &xs[(16 * w + l16) * XS + (16 * kk + 4 * kl) * E];
-                const float *vp = &vs[l16 * XS + (16 * kk + 4 * kl) * E];
-                float xr[4], xi[4], vr[4], vi[4];
-                if (CPLX) {
-                    const float4 xa = *reinterpret_cast<const float4 *>(xp);
-                    const float4 xb = *reinterpret_cast<const float4 *>(xp + 4);
-                    const float4 va = *reinterpret_cast<const float4 *>(vp);
-                    const float4 vb = *reinterpret_cast<const float4 *>(vp + 4);
-                    xr[0] = xa.x; xi[0] = xa.y; xr[1] = xa.z; xi[1] = xa.w;
-                    xr[2] = xb.x; xi[2] = xb.y; xr[3] = xb.z; xi[3] = xb.w;
-                    vr[0] = va.x; vi[0] = va.y; vr[1] = va.z; vi[1] = va.w;
-                    vr[2] = vb.x; vi[2] = vb.y; vr[3] = vb.z; vi[3] = vb.w;
-                } else {
-                    const float4 xa = *reinterpret_cast<const float4 *>(xp);
-                    const float4 va = *reinterpret_cast<const float4 *>(vp);
-                    xr[0] = xa.x; xr[1] = xa.y; xr[2] = xa.z; xr[3] = xa.w;
-                    vr[0] = va.x; vr[1] = va.y; vr[2] = va.z; vr[3] = va.w;
-                    xi[0] = xi[1] = xi[2] = xi[3] = 0.0f;
-                    vi[0] = vi[1] = vi[2] = vi[3] = 0.0f;
-                }
+        }
+    };
+    // the registers of a stage into LDS; entries that do not exist as zero
+    auto put = [&](float *dst, const u32x4 &v, int k) {
+        const uint32_t e0 = v.x, e1 = v.y, e2 = v.z, e3 = v.w;
+        float4 o;
+        // a piece across q reads the next column or row: its entries past q are zeroed
+        o.x = __uint_as_float(e0);
+        o.y = (CPLX ? k : k + 1) < q ? __uint_as_float(e1) : 0.0f;
+        o.z = (CPLX ? k + 1 : k + 2) < q ? __uint_as_float(e2) : 0.0f;
+        o.w = (CPLX ? k + 1 : k + 3) < q ? __uint_as_float(e3) : 0.0f;
+        if (BF) {
+            o.x = rbf(o.x);
+            o.y = rbf(o.y);
+            o.z = rbf(o.z);
+            o.w = rbf(o.w);
+        }
+        *reinterpret_cast<float4 *>(dst) = o;
+    };
+    auto store_stage = [&](int f, int kc0) {
+        const float wgt = (CPLX && !(f == 0 || 2 * f == n3)) ? 2.0f : 1.0f;
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    zr = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[t], xr[t], zr, 0, 0, 0);
-                    if (CPLX) {
-                        zi = __builtin_amdgcn_mfma_f32_16x16x4f32(vi[t], xi[t], zi, 0, 0, 0);
-                        z3 = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[t] + vi[t], xr[t] + xi[t], z3, 0, 0, 0);
+        for (int u = 0; u < NXU; ++u) {
+            const int g = u * AT + tid, cc = g / CH, h = g % CH;
+            if (g < 64 * CH) put(&xs[cc * XS + KPC * h * E], gx[u], kc0 + KPC * h);
+        }
+#pragma unroll
+        for (int u = 0; u < NVU; ++u) {
+            const int g = u * AT + tid, r = g / CH, h = g % CH;
+            if (g < 16 * CH) put(&vs[r * XS + KPC * h * E], gv[u], kc0 + KPC * h);
+        }
+        if (kc0 == 0) {
+            // U S w, transposed to rows a
+#pragma unroll
+            for (int u = 0; u < NUU; ++u) {
+                const int g = u * AT + tid, r = g / (64 / KPC), h = g % (64 / KPC);
+                if (g >= 16 * (64 / KPC)) continue;
+                const int a = a0 + KPC * h;
+                const uint32_t e[4] = {gu[u].x, gu[u].y, gu[u].z, gu[u].w};
+#pragma unroll
+                for (int i = 0; i < KPC; ++i) {
+                    const bool ain = a + i < m;  // the next rank's rows past m
+#pragma unroll
+                    for (int ee = 0; ee < E; ++ee) {
+                        float x = ain ? (float)((double)__uint_as_float(e[i * E + ee]) * gs[u]) : 0.0f;
+                        if (BF) x = rbf(x);
+                        us[(KPC * h + i) * US + r * E + ee] = x * wgt;
                     }
                 }
             }
         }
-        if (CPLX) {
-            const f32x4 p1 = zr, p2 = zi;
-            zr = p1 - p2;       // Vr Xr - Vi Xi
-            zi = z3 - p1 - p2;  // Vr Xi + Vi Xr = -Im Z
+    };
+    f32x4 zr = f32x4{0, 0, 0, 0}, zi = zr, z3 = zr;
+    int f = next_face(0), kc0 = 0;
+    if (f < nf) load_stage(f, 0);
+    while (f < nf) {
+        __syncthreads();  // the previous stage's operands are consumed
+        store_stage(f, kc0);
+        __syncthreads();
+        int fn = f, kn = kc0 + KC;
+        if (kn >= q) {
+            fn = next_face(f + 1);
+            kn = 0;
         }
-        // y += Re(U S w Z), A operand from the staged rows of U S w
-#pragma unroll
-        for (int ab = 0; ab < 4; ++ab) {
-            const float *up = &us[(16 * ab + l16) * US + 4 * kl * E];
-            float ur[4], ui[4];
+        if (fn < nf) load_stage(fn, kn);
+        // Z += conj(V^T x~) over this chunk's k, in steps of 16
+        const int nkk = (q - kc0 < KC ? q - kc0 + 15 : KC) >> 4;
+        for (int kk = 0; kk < nkk; ++kk) {
+            const float *xp = &xs[(16 * w + l16) * XS + (16 * kk + 4 * kl) * E];
+            const float *vp = &vs[l16 * XS + (16 * kk + 4 * kl) * E];
+            float xr[4], xi[4], vr[4], vi[4];
             if (CPLX) {
-                const float4 ua = *reinterpret_cast<const float4 *>(up);
-                const float4 ub = *reinterpret_cast<const float4 *>(up + 4);
-                ur[0] = ua.x; ui[0] = ua.y; ur[1] = ua.z; ui[1] = ua.w;
-                ur[2] = ub.x; ui[2] = ub.y; ur[3] = ub.z; ui[3] = ub.w;
+                const float4 xa = *reinterpret_cast<const float4 *>(xp);
+                const float4 xb = *reinterpret_cast<const float4 *>(xp + 4);
+                const float4 va = *reinterpret_cast<const float4 *>(vp);
+                const float4 vb = *reinterpret_cast<const float4 *>(vp + 4);
+                xr[0] = xa.x; xi[0] = xa.y; xr[1] = xa.z; xi[1] = xa.w;
+                xr[2] = xb.x; xi[2] = xb.y; xr[3] = xb.z; xi[3] = xb.w;
+                vr[0] = va.x; vi[0] = va.y; vr[1] = va.z; vi[1] = va.w;
+                vr[2] = vb.x; vi[2] = vb.y; vr[3] = vb.z; vi[3] = vb.w;
             } else {
-                const float4 ua = *reinterpret_cast<const float4 *>(up);
-                ur[0] = ua.x; ur[1] = ua.y; ur[2] = ua.z; ur[3] = ua.w;
-                ui[0] = ui[1] = ui[2] = ui[3] = 0.0f;
+                const float4 xa = *reinterpret_cast<const float4 *>(xp);
+                const float4 va = *reinterpret_cast<const float4 *>(vp);
+                xr[0] = xa.x; xr[1] = xa.y; xr[2] = xa.z; xr[3] = xa.w;
+                vr[0] = va.x; vr[1] = va.y; vr[2] = va.z; vr[3] = va.w;
+                xi[0] = xi[1] = xi[2] = xi[3] = 0.0f;
+                vi[0] = vi[1] = vi[2] = vi[3] = 0.0f;
             }
 #pragma unroll
-            for (int sx = 0; sx < 4; ++sx) {
-                const float bzr = zr[sx];
-                const float bzi = zi[sx];
-                acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[sx], bzr, acc[ab], 0, 0, 0);
-                if (CPLX) acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(ui[sx], bzi, acc[ab], 0, 0, 0);
+            for (int t = 0; t < 4; ++t) {
+                zr = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[t], xr[t], zr, 0, 0, 0);
+                if (CPLX) {
+                    zi = __builtin_amdgcn_mfma_f32_16x16x4f32(vi[t], xi[t], zi, 0, 0, 0);
+                    z3 = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[t] + vi[t], xr[t] + xi[t], z3, 0, 0, 0);
+                }
             }
         }
+        if (kc0 + KC >= q) {
+            // the face is complete: y += Re(U S w Z)
+            if (CPLX) {
+                const f32x4 p1 = zr, p2 = zi;
+                zr = p1 - p2;       // Vr Xr - Vi Xi
+                zi = z3 - p1 - p2;  // Vr Xi + Vi Xr = -Im Z
+            }
+#pragma unroll
+            for (int ab = 0; ab < 4; ++ab) {
+                const float *up = &us[(16 * ab + l16) * US + 4 * kl * E];
+                float ur[4], ui[4];
+                if (CPLX) {
+                    const float4 ua = *reinterpret_cast<const float4 *>(up);
+                    const float4 ub = *reinterpret_cast<const float4 *>(up + 4);
+                    ur[0] = ua.x; ui[0] = ua.y; ur[1] = ua.z; ui[1] = ua.w;
+                    ur[2] = ub.x; ui[2] = ub.y; ur[3] = ub.z; ui[3] = ub.w;
+                } else {
+                    const float4 ua = *reinterpret_cast<const float4 *>(up);
+                    ur[0] = ua.x; ur[1] = ua.y; ur[2] = ua.z; ur[3] = ua.w;
+                    ui[0] = ui[1] = ui[2] = ui[3] = 0.0f;
+                }
+#pragma unroll
+                for (int sx = 0; sx < 4; ++sx) {
+                    const float bzr = zr[sx];
+                    const float bzi = zi[sx];
+                    acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[sx], bzr, acc[ab], 0, 0, 0);
+                    if (CPLX) acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(ui[sx], bzi, acc[ab], 0, 0, 0);
+                }
+            }
+            zr = zi = z3 = f32x4{0, 0, 0, 0};
+        }
+        f = fn;
+        kc0 = kn;
     }
     const int c = c0 + 16 * w + l16;
     if (c < nrhs) {
