@@ -67,15 +67,18 @@ def test_apply_full_size_dft_fp32():
     assert relerr(y, y_ref) < TOL[C.F32]
 
 
+@pytest.mark.parametrize("k", [12, 24])
 @pytest.mark.parametrize("compute", [C.F32, C.BF16, C.F64])
 @pytest.mark.parametrize("kind", [C.M_DCT2, C.M_DFT])
-def test_apply_face_ranks_below_kmax(kind, compute):
-    """Per-face ranks below the stored width (zero included) and a width above
-    16 (two blocks of 16 ranks), 70 rows (two row tiles), a ragged column tile."""
-    m, ell, q, n, k, nrhs = 70, 3, 21, 10, 24, 70
-    g = np.random.default_rng(11)
+def test_apply_face_ranks_below_kmax(kind, compute, k):
+    """Per-face ranks below the stored width, zero included (faces skipped);
+    widths up to 16 (operands staged in LDS, 45 k over two chunks) and above
+    16 (two blocks of 16 ranks, direct loads); 70 rows (two row tiles), a
+    ragged column tile."""
+    m, ell, q, n, nrhs = 70, 3, 45, 10, 70
+    g = np.random.default_rng(11 + k)
     nf = n // 2 + 1 if kind == C.M_DFT else n
     ranks = g.integers(0, k + 1, size=nf)
-    ranks[0], ranks[-1] = 0, k
+    ranks[0], ranks[2], ranks[-1] = 0, 0, k  # zero-rank faces first and in the middle
     y, y_ref = _case(kind, m, ell, q, n, k, nrhs, compute, ranks=ranks)
     assert relerr(y, y_ref) < TOL[compute], relerr(y, y_ref)
