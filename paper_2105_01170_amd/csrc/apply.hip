@@ -331,8 +331,8 @@ __global__ __launch_bounds__(AT) void k_apply_mfma(const float *__restrict__ U, 
     }
 }
 
-// Ranks <= 16: the same products with the workgroup's operands staged in LDS.
-// Per face and chunk of 32 k, the 256 threads copy x~ (64 columns), the 16
+// Ranks <= 32: the same products with the workgroup's operands staged in LDS.
+// Per face and chunk of 32 k, the 256 threads copy x~ (64 columns), the 16 NRB
 // rank rows of Vp and, on the first chunk, U S w (64 rows, rounded as the
 // plain kernel rounds it) with 16-byte loads, consecutive lanes on
 // consecutive 16-byte pieces of one column or row; elements that do not
@@ -341,7 +341,7 @@ __global__ __launch_bounds__(AT) void k_apply_mfma(const float *__restrict__ U, 
 // wavefronts then read their MFMA operands from LDS in the layout above.
 // The global loads of the next stage (face, chunk) are issued before the
 // current stage's products.
-template <bool CPLX, bool BF>
+template <bool CPLX, bool BF, int NRB>
 __global__ __launch_bounds__(AT) void k_apply_lds(const float *__restrict__ U, const double *__restrict__ S,
                                                   const float *__restrict__ Vp, const int32_t *__restrict__ ranks,
                                                   int m, int p, int kmax, int nf, int n3, int ell, int q,
@@ -350,21 +350,22 @@ __global__ __launch_bounds__(AT) void k_apply_lds(const float *__restrict__ U, c
     constexpr int E = CPLX ? 2 : 1;
     constexpr int KC = 32;              // k per chunk
     constexpr int XS = KC * E + 4;      // floats per staged column of x~ or row of Vp
-    constexpr int US = 16 * E + 4;      // floats per staged row of U S
+    constexpr int RK = 16 * NRB;        // ranks held
+    constexpr int US = RK * E + 4;      // floats per staged row of U S
     constexpr int KPC = 4 / E;          // k (or rows a) per 16-byte piece
     constexpr int CH = KC / KPC;        // pieces per column
     __shared__ __align__(16) float xs[64 * XS];
-    __shared__ __align__(16) float vs[16 * XS];
+    __shared__ __align__(16) float vs[RK * XS];
     __shared__ __align__(16) float us[64 * US];
-    const int kcap = kmax < 16 ? kmax : 16;
+    const int kcap = kmax < RK ? kmax : RK;
     const int mtiles = (m + 63) >> 6;
     const int j = blockIdx.x / mtiles, a0 = (blockIdx.x % mtiles) * 64;
     const int c0 = blockIdx.y * 64;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int l16 = lane & 15, kl = lane >> 4;
     constexpr int NXU = (64 * CH + AT - 1) / AT;         // staging loads per thread: x~
-    constexpr int NVU = (16 * CH + AT - 1) / AT;         // Vp
-    constexpr int NUU = (16 * (64 / KPC) + AT - 1) / AT; // U
+    constexpr int NVU = (RK * CH + AT - 1) / AT;         // Vp
+    constexpr int NUU = (RK * (64 / KPC) + AT - 1) / AT; // U
     f32x4 acc[4];
 #pragma unroll
     for (int ab = 0; ab < 4; ++ab) acc[ab] = f32x4{0, 0, 0, 0};
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(AT) void k_apply_lds(const float *__restrict__ U, c
             const int g = u * AT + tid, r = g / CH, h = g % CH;
             const int k = kc0 + KPC * h;
             const uint32_t vo = (((uint32_t)k + (uint32_t)q * (uint32_t)j + (uint32_t)p * (uint32_t)r) * (4u * E)) |
-                                miss_if(g >= 16 * CH || r >= kf || k >= q);
+                                miss_if(g >= RK * CH || r >= kf || k >= q);
             gv[u] = __builtin_amdgcn_raw_buffer_load_b128(rv, (int)vo, 0, 0);
         }
         if (kc0 == 0) {
@@ -410,7 +411,7 @@ __global__ __launch_bounds__(AT) void k_apply_lds(const float *__restrict__ U, c
             for (int u = 0; u < NUU; ++u) {
                 const int g = u * AT + tid, r = g / (64 / KPC), h = g % (64 / KPC);
                 const int a = a0 + KPC * h;
-                const bool rin = g < 16 * (64 / KPC) && r < kf;
+                const bool rin = g < RK * (64 / KPC) && r < kf;
                 const uint32_t uo = (((uint32_t)a + (uint32_t)m * (uint32_t)r) * (4u * E)) | miss_if(!rin || a >= m);
                 gu[u] = __builtin_amdgcn_raw_buffer_load_b128(ru, (int)uo, 0, 0);
                 gs[u] = rin ? S[(int64_t)f * kmax + r] : 0.0;
@@ -444,14 +445,14 @@ __global__ __launch_bounds__(AT) void k_apply_lds(const float *__restrict__ U, c
 #pragma unroll
         for (int u = 0; u < NVU; ++u) {
             const int g = u * AT + tid, r = g / CH, h = g % CH;
-            if (g < 16 * CH) put(&vs[r * XS + KPC * h * E], gv[u], kc0 + KPC * h);
+            if (g < RK * CH) put(&vs[r * XS + KPC * h * E], gv[u], kc0 + KPC * h);
         }
         if (kc0 == 0) {
             // U S w, transposed to rows a
 #pragma unroll
             for (int u = 0; u < NUU; ++u) {
                 const int g = u * AT + tid, r = g / (64 / KPC), h = g % (64 / KPC);
-                if (g >= 16 * (64 / KPC)) continue;
+                if (g >= RK * (64 / KPC)) continue;
                 const int a = a0 + KPC * h;
                 const uint32_t e[4] = {gu[u].x, gu[u].y, gu[u].z, gu[u].w};
 #pragma unroll
@@ -467,7 +468,9 @@ __global__ __launch_bounds__(AT) void k_apply_lds(const float *__restrict__ U, c
             }
         }
     };
-    f32x4 zr = f32x4{0, 0, 0, 0}, zi = zr, z3 = zr;
+    f32x4 zr[NRB], zi[NRB], z3[NRB];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) zr[rb] = zi[rb] = z3[rb] = f32x4{0, 0, 0, 0};
     int f = next_face(0), kc0 = 0;
     if (f < nf) load_stage(f, 0);
     while (f < nf) {
@@ -484,64 +487,74 @@ __global__ __launch_bounds__(AT) void k_apply_lds(const float *__restrict__ U, c
         const int nkk = (q - kc0 < KC ? q - kc0 + 15 : KC) >> 4;
         for (int kk = 0; kk < nkk; ++kk) {
             const float *xp = &xs[(16 * w + l16) * XS + (16 * kk + 4 * kl) * E];
-            const float *vp = &vs[l16 * XS + (16 * kk + 4 * kl) * E];
-            float xr[4], xi[4], vr[4], vi[4];
+            float xr[4], xi[4];
             if (CPLX) {
                 const float4 xa = *reinterpret_cast<const float4 *>(xp);
                 const float4 xb = *reinterpret_cast<const float4 *>(xp + 4);
-                const float4 va = *reinterpret_cast<const float4 *>(vp);
-                const float4 vb = *reinterpret_cast<const float4 *>(vp + 4);
                 xr[0] = xa.x; xi[0] = xa.y; xr[1] = xa.z; xi[1] = xa.w;
                 xr[2] = xb.x; xi[2] = xb.y; xr[3] = xb.z; xi[3] = xb.w;
-                vr[0] = va.x; vi[0] = va.y; vr[1] = va.z; vi[1] = va.w;
-                vr[2] = vb.x; vi[2] = vb.y; vr[3] = vb.z; vi[3] = vb.w;
             } else {
                 const float4 xa = *reinterpret_cast<const float4 *>(xp);
-                const float4 va = *reinterpret_cast<const float4 *>(vp);
                 xr[0] = xa.x; xr[1] = xa.y; xr[2] = xa.z; xr[3] = xa.w;
-                vr[0] = va.x; vr[1] = va.y; vr[2] = va.z; vr[3] = va.w;
                 xi[0] = xi[1] = xi[2] = xi[3] = 0.0f;
-                vi[0] = vi[1] = vi[2] = vi[3] = 0.0f;
             }
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                zr = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[t], xr[t], zr, 0, 0, 0);
+            for (int rb = 0; rb < NRB; ++rb) {
+                const float *vp = &vs[(16 * rb + l16) * XS + (16 * kk + 4 * kl) * E];
+                float vr[4], vi[4];
                 if (CPLX) {
-                    zi = __builtin_amdgcn_mfma_f32_16x16x4f32(vi[t], xi[t], zi, 0, 0, 0);
-                    z3 = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[t] + vi[t], xr[t] + xi[t], z3, 0, 0, 0);
+                    const float4 va = *reinterpret_cast<const float4 *>(vp);
+                    const float4 vb = *reinterpret_cast<const float4 *>(vp + 4);
+                    vr[0] = va.x; vi[0] = va.y; vr[1] = va.z; vi[1] = va.w;
+                    vr[2] = vb.x; vi[2] = vb.y; vr[3] = vb.z; vi[3] = vb.w;
+                } else {
+                    const float4 va = *reinterpret_cast<const float4 *>(vp);
+                    vr[0] = va.x; vr[1] = va.y; vr[2] = va.z; vr[3] = va.w;
+                    vi[0] = vi[1] = vi[2] = vi[3] = 0.0f;
+                }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    zr[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[t], xr[t], zr[rb], 0, 0, 0);
+                    if (CPLX) {
+                        zi[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vi[t], xi[t], zi[rb], 0, 0, 0);
+                        z3[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[t] + vi[t], xr[t] + xi[t], z3[rb], 0, 0, 0);
+                    }
                 }
             }
         }
         if (kc0 + KC >= q) {
             // the face is complete: y += Re(U S w Z)
-            if (CPLX) {
-                const f32x4 p1 = zr, p2 = zi;
-                zr = p1 - p2;       // Vr Xr - Vi Xi
-                zi = z3 - p1 - p2;  // Vr Xi + Vi Xr = -Im Z
-            }
 #pragma unroll
-            for (int ab = 0; ab < 4; ++ab) {
-                const float *up = &us[(16 * ab + l16) * US + 4 * kl * E];
-                float ur[4], ui[4];
+            for (int rb = 0; rb < NRB; ++rb) {
                 if (CPLX) {
-                    const float4 ua = *reinterpret_cast<const float4 *>(up);
-                    const float4 ub = *reinterpret_cast<const float4 *>(up + 4);
-                    ur[0] = ua.x; ui[0] = ua.y; ur[1] = ua.z; ui[1] = ua.w;
-                    ur[2] = ub.x; ui[2] = ub.y; ur[3] = ub.z; ui[3] = ub.w;
-                } else {
-                    const float4 ua = *reinterpret_cast<const float4 *>(up);
-                    ur[0] = ua.x; ur[1] = ua.y; ur[2] = ua.z; ur[3] = ua.w;
-                    ui[0] = ui[1] = ui[2] = ui[3] = 0.0f;
+                    const f32x4 p1 = zr[rb], p2 = zi[rb];
+                    zr[rb] = p1 - p2;           // Vr Xr - Vi Xi
+                    zi[rb] = z3[rb] - p1 - p2;  // Vr Xi + Vi Xr = -Im Z
                 }
 #pragma unroll
-                for (int sx = 0; sx < 4; ++sx) {
-                    const float bzr = zr[sx];
-                    const float bzi = zi[sx];
-                    acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[sx], bzr, acc[ab], 0, 0, 0);
-                    if (CPLX) acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(ui[sx], bzi, acc[ab], 0, 0, 0);
+                for (int ab = 0; ab < 4; ++ab) {
+                    const float *up = &us[(16 * ab + l16) * US + (16 * rb + 4 * kl) * E];
+                    float ur[4], ui[4];
+                    if (CPLX) {
+                        const float4 ua = *reinterpret_cast<const float4 *>(up);
+                        const float4 ub = *reinterpret_cast<const float4 *>(up + 4);
+                        ur[0] = ua.x; ui[0] = ua.y; ur[1] = ua.z; ui[1] = ua.w;
+                        ur[2] = ub.x; ui[2] = ub.y; ur[3] = ub.z; ui[3] = ub.w;
+                    } else {
+                        const float4 ua = *reinterpret_cast<const float4 *>(up);
+                        ur[0] = ua.x; ur[1] = ua.y; ur[2] = ua.z; ur[3] = ua.w;
+                        ui[0] = ui[1] = ui[2] = ui[3] = 0.0f;
+                    }
+#pragma unroll
+                    for (int sx = 0; sx < 4; ++sx) {
+                        const float bzr = zr[rb][sx];
+                        const float bzi = zi[rb][sx];
+                        acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[sx], bzr, acc[ab], 0, 0, 0);
+                        if (CPLX) acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(ui[sx], bzi, acc[ab], 0, 0, 0);
+                    }
                 }
+                zr[rb] = zi[rb] = z3[rb] = f32x4{0, 0, 0, 0};
             }
-            zr = zi = z3 = f32x4{0, 0, 0, 0};
         }
         f = fn;
         kc0 = kn;
@@ -645,12 +658,17 @@ tsvdm_status launch_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t 
         }                                             \
     } while (0)
         const bool bf = compute == TSVDM_BF16;
-        if (nrb == 1) {
-#define TSVDM_APPLY_LDS(C, B)                                                                                \
-    TSVDM_LAUNCH("apply_fused", (k_apply_lds<C, B>), grid, dim3(AT), 0, s,                                   \
+        if (nrb <= 2) {
+#define TSVDM_APPLY_LDS1(C, B, NRB)                                                                          \
+    TSVDM_LAUNCH("apply_fused", (k_apply_lds<C, B, NRB>), grid, dim3(AT), 0, s,                              \
                  reinterpret_cast<const float *>(F->U), F->S, Vp, F->ranks, (int)F->m, (int)F->p, (int)F->kmax, \
                  (int)nf, (int)n3, (int)ell, (int)q, reinterpret_cast<const float *>(ws), (int)nrhs,          \
                  reinterpret_cast<float *>(y), ldy)
+#define TSVDM_APPLY_LDS(C, B)                     \
+    do {                                          \
+        if (nrb == 1) TSVDM_APPLY_LDS1(C, B, 1);  \
+        else TSVDM_APPLY_LDS1(C, B, 2);           \
+    } while (0)
             if (cplx) {
                 if (bf) TSVDM_APPLY_LDS(true, true);
                 else TSVDM_APPLY_LDS(true, false);
@@ -659,6 +677,7 @@ tsvdm_status launch_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t 
                 else TSVDM_APPLY_LDS(false, false);
             }
 #undef TSVDM_APPLY_LDS
+#undef TSVDM_APPLY_LDS1
         } else if (cplx) {
             if (bf) TSVDM_APPLY_NRB(true, true);
             else TSVDM_APPLY_NRB(true, false);

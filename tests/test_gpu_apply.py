@@ -72,9 +72,8 @@ def test_apply_full_size_dft_fp32():
 @pytest.mark.parametrize("kind", [C.M_DCT2, C.M_DFT])
 def test_apply_face_ranks_below_kmax(kind, compute, k):
     """Per-face ranks below the stored width, zero included (faces skipped);
-    widths up to 16 (operands staged in LDS, 45 k over two chunks) and above
-    16 (two blocks of 16 ranks, direct loads); 70 rows (two row tiles), a
-    ragged column tile."""
+    one and two blocks of 16 ranks (operands staged in LDS, 45 k over two
+    chunks); 70 rows (two row tiles), a ragged column tile."""
     m, ell, q, n, nrhs = 70, 3, 45, 10, 70
     g = np.random.default_rng(11 + k)
     nf = n // 2 + 1 if kind == C.M_DFT else n
