@@ -134,6 +134,8 @@ __global__ __launch_bounds__(AT) void k_apply(const T *__restrict__ U, const dou
 
 // ---------------------------------------------------------------- matrix cores
 // The same contraction on FP32 16x16x4 MFMAs (FP32 and BF16-rounded operands).
+// k_apply_mfma reads its operands straight from memory and serves ranks 33..64;
+// k_apply_lds below (ranks up to 32) stages them in LDS first.
 // Workgroup: block row j, rows a0 .. a0+63 of it and 64 columns; wavefront w
 // owns columns c0 + 16 w .. + 15 and all 64 rows.  Per stored face f:
 //   Z(r, c) = sum_k conj(V(j + l k, r)) conj(xt(k, c))  (real M: no conj)
