@@ -363,17 +363,18 @@ __global__ __launch_bounds__(64) void k_bcore32(const Item *__restrict__ items, 
 // D = W^T X over 16 ranks by 16 columns of the face.  The contraction runs
 // over the rows in groups of 16: lane (l16, kl) = (lane % 16, lane / 16) loads
 // rows 16 kk + 4 kl .. 16 kk + 4 kl + 3 of column col (one 16-byte load per
-// group, col = 32 step + 16 c + l16), and MFMA step (kk, r) takes row
+// group, col = 16 C step + 16 c + l16), and MFMA step (kk, r) takes row
 // 16 kk + 4 kl + r of lane (l16, kl) as its B operand; the A operand, formed
 // once per face in registers, holds W(16 kk + 4 kl + r, 16 jb + l16) to match
 // (zero for rows past m).  A row past m lands on the next column of the same
 // face (finite, times a zero of W); bytes past the face, including columns
 // past p, read as zero (the buffer resource checks each dword).  Stores of
 // columns past p or ranks past kmax get bit 31 of the offset and are dropped.
-// Steps of 32 columns are double-buffered.
+// Steps of 16 C columns, C = 8 / NT groups of 16 (so about the same bytes per
+// step for every row count), are double-buffered.
 template <int NT, int NJ>
 __device__ __forceinline__ void vec_face(const Item &it, int lane) {
-    constexpr int C = 2;
+    constexpr int C = NT == 1 ? 8 : NT == 2 ? 4 : 2;  // 16-column groups per step
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     const int m = __builtin_amdgcn_readfirstlane(it.m), p = __builtin_amdgcn_readfirstlane(it.p);
     const int kmax = __builtin_amdgcn_readfirstlane(it.kmax);
@@ -405,7 +406,7 @@ __device__ __forceinline__ void vec_face(const Item &it, int lane) {
     auto load_step = [&](u32x4 (&x)[C][NT], int st) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const uint32_t vo = (uint32_t)(4 * kl + m * (32 * st + 16 * c + l16)) * 4u;
+            const uint32_t vo = (uint32_t)(4 * kl + m * (16 * C * st + 16 * c + l16)) * 4u;
 #pragma unroll
             for (int kk = 0; kk < NT; ++kk)
                 x[c][kk] = __builtin_amdgcn_raw_buffer_load_b128(rx, (int)(vo + 64u * kk), 0, 0);
@@ -414,7 +415,7 @@ __device__ __forceinline__ void vec_face(const Item &it, int lane) {
     auto mma_store = [&](const u32x4 (&x)[C][NT], int st) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            const int col = 32 * st + 16 * c + l16;
+            const int col = 16 * C * st + 16 * c + l16;
             // the four rows of each group as scalars (a bit cast of a vector
             // element itself was compiled as a cast of element 0)
             float xs[NT][4];
@@ -446,7 +447,7 @@ __device__ __forceinline__ void vec_face(const Item &it, int lane) {
             }
         }
     };
-    const int nsteps = (p + 31) / 32;
+    const int nsteps = (p + 16 * C - 1) / (16 * C);
     u32x4 xa[C][NT], xb[C][NT];
     load_step(xa, 0);
     for (int st = 0; st < nsteps; st += 2) {
@@ -457,7 +458,7 @@ __device__ __forceinline__ void vec_face(const Item &it, int lane) {
     }
 }
 
-// NJ = 1 serves batches whose factors all have kmax <= 16 (121 registers, four
+// NJ = 1 serves batches whose factors all have kmax <= 16 (160 registers, three
 // wavefronts per SIMD); NJ = 2 any kmax <= 32.
 template <int NJ>
 __global__ __launch_bounds__(BT) void k_bvec(const Item *__restrict__ items, int nitems,
