@@ -382,6 +382,22 @@ __device__ __forceinline__ void vec_face(const Item &it, int lane) {
     const int kl = lane >> 4, l16 = lane & 15;
     const float *U = uniform_ptr(it.U);
     const double *S = uniform_ptr(it.S);
+    const __amdgpu_buffer_rsrc_t rx =
+        __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(const_cast<float *>(it.X)), 0, m * p * 4, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rv =
+        __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(it.V), 0, p * kmax * 4, 0x00020000);
+    auto load_step = [&](u32x4 (&x)[C][NT], int st) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const uint32_t vo = (uint32_t)(4 * kl + m * (16 * C * st + 16 * c + l16)) * 4u;
+#pragma unroll
+            for (int kk = 0; kk < NT; ++kk)
+                x[c][kk] = __builtin_amdgcn_raw_buffer_load_b128(rx, (int)(vo + 64u * kk), 0, 0);
+        }
+    };
+    // the first step's loads are in flight while W is formed
+    u32x4 xa[C][NT], xb[C][NT];
+    load_step(xa, 0);
     float w[NJ][NT][4];
 #pragma unroll
     for (int jb = 0; jb < NJ; ++jb) {
@@ -399,19 +415,6 @@ __device__ __forceinline__ void vec_face(const Item &it, int lane) {
                 w[jb][kk][r] = (j < kf && i < m) ? U[i + (int64_t)m * j] * isg : 0.0f;
             }
     }
-    const __amdgpu_buffer_rsrc_t rx =
-        __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(const_cast<float *>(it.X)), 0, m * p * 4, 0x00020000);
-    const __amdgpu_buffer_rsrc_t rv =
-        __builtin_amdgcn_make_buffer_rsrc(uniform_ptr(it.V), 0, p * kmax * 4, 0x00020000);
-    auto load_step = [&](u32x4 (&x)[C][NT], int st) {
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const uint32_t vo = (uint32_t)(4 * kl + m * (16 * C * st + 16 * c + l16)) * 4u;
-#pragma unroll
-            for (int kk = 0; kk < NT; ++kk)
-                x[c][kk] = __builtin_amdgcn_raw_buffer_load_b128(rx, (int)(vo + 64u * kk), 0, 0);
-        }
-    };
     auto mma_store = [&](const u32x4 (&x)[C][NT], int st) {
 #pragma unroll
         for (int c = 0; c < C; ++c) {
@@ -448,8 +451,6 @@ __device__ __forceinline__ void vec_face(const Item &it, int lane) {
         }
     };
     const int nsteps = (p + 16 * C - 1) / (16 * C);
-    u32x4 xa[C][NT], xb[C][NT];
-    load_step(xa, 0);
     for (int st = 0; st < nsteps; st += 2) {
         load_step(xb, st + 1);
         mma_store(xa, st);
