@@ -370,11 +370,11 @@ __global__ __launch_bounds__(64) void k_bcore32(const Item *__restrict__ items, 
 // face (finite, times a zero of W); bytes past the face, including columns
 // past p, read as zero (the buffer resource checks each dword).  Stores of
 // columns past p or ranks past kmax get bit 31 of the offset and are dropped.
-// Steps of 16 C columns, C = 8 / NT groups of 16 (so about the same bytes per
-// step for every row count), are double-buffered.
+// Steps of 16 C columns, C = 16 / NT groups of 16 (about 16 KB per step for
+// every row count), are double-buffered.
 template <int NT, int NJ>
 __device__ __forceinline__ void vec_face(const Item &it, int lane) {
-    constexpr int C = NT == 1 ? 8 : NT == 2 ? 4 : 2;  // 16-column groups per step
+    constexpr int C = NT == 1 ? 16 : NT == 2 ? 8 : 4;  // 16-column groups per step
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     const int m = __builtin_amdgcn_readfirstlane(it.m), p = __builtin_amdgcn_readfirstlane(it.p);
     const int kmax = __builtin_amdgcn_readfirstlane(it.kmax);
@@ -459,8 +459,8 @@ __device__ __forceinline__ void vec_face(const Item &it, int lane) {
     }
 }
 
-// NJ = 1 serves batches whose factors all have kmax <= 16 (160 registers, three
-// wavefronts per SIMD); NJ = 2 any kmax <= 32.
+// NJ = 1 serves batches whose factors all have kmax <= 16; NJ = 2 any kmax <=
+// 32 (about 250 registers: two wavefronts per SIMD).
 template <int NJ>
 __global__ __launch_bounds__(BT) void k_bvec(const Item *__restrict__ items, int nitems,
                                              int *__restrict__ counter) {
