@@ -332,7 +332,7 @@ void tsvdm_batched_plan_destroy(tsvdm_batched_plan *plan);
 /* ---------------------------------------------------------------- rank predictor
  * A multilayer perceptron 32 -> 64 -> 64 -> 2 (ReLU hidden layers, linear
  * output) that predicts, per transform-domain face, (k/32, l/48): the rank and
- * the sketch width of the randomized truncation (step 2 of Algorithm
+ * the sketch width of the randomized truncation (step 3 of Algorithm
  * alg:strategy), from the features log10(s_j / s_1), j = 1..32, of a 32-column
  * sketch of the face (tsvdm_rank_features).  Half precision weights, inputs
  * and hidden activations; FP32 accumulation.

@@ -8,7 +8,7 @@ uses this module.  It shares no code with the HIP kernels.
 
 The predictor is not part of the paper; it chooses, per transform-domain face,
 the rank and sketch width of the randomized truncation that the paper's
-compression step (Algorithm alg:strategy, step 2) needs.  Readings:
+compression step (Algorithm alg:strategy, step 3) needs.  Readings:
 * features: log10(s_j / s_1), j = 1..32, of the singular values s of a
   32-column Gaussian sketch Y = Xhat_f Omega[:, :32] (0 when s_1 = 0, clipped
   below at -30);
@@ -125,3 +125,12 @@ def predict_widths(y: np.ndarray, kcap: int = 32, widths=(16, 32, 40)):
     idx = np.searchsorted(ws, lw, side="left")
     l = ws[np.minimum(idx, len(ws) - 1)]
     return k, l
+
+
+def rank_label(sigma: np.ndarray, tau: float, kcap: int = 32) -> int:
+    """Rank label of a face whose singular values are prescribed (sigma,
+    decreasing): its exact energy rank at tau, the smallest k <= kcap with
+    sum_{j>k} s_j^2 <= tau^2 sum_j s_j^2 (the cap when none is)."""
+    from . import oracle as _o
+    s = np.asarray(sigma, dtype=np.float64)
+    return _o.rank_energy(s, float(np.sum(s * s)), tau, kmax=kcap)

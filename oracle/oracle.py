@@ -379,10 +379,22 @@ def shifted_cholqr3(Y: np.ndarray):
     return Q, R2 @ R1
 
 
+def householder_qr(Y: np.ndarray):
+    """Thin Householder QR (numpy): an orthonormal basis of the columns of Y,
+    also when Y is rank deficient (its extra columns then span arbitrary
+    directions orthogonal to the range, which the projection B = Q^H F maps
+    to zero rows)."""
+    Q, R = np.linalg.qr(Y)
+    return Q, R
+
+
 def randomized_face(F: np.ndarray, Omega: np.ndarray, power_iters: int = 1,
-                    qr=shifted_cholqr3):
+                    qr=householder_qr):
     """Randomized range finder with power iteration, then the small SVD
-    (Halko, Martinsson, Tropp 2011, Algs. 4.4 and 5.1), all in float64:
+    (Halko, Martinsson, Tropp 2011, Algs. 4.4 and 5.1), all in float64.  The
+    range finder only needs an orthonormal basis of each sketch; the default
+    is Householder QR, which, unlike Cholesky-based QR, also holds when a
+    sketch is exactly rank deficient (inputs of exact rank below ell):
 
       Y = F Omega; Q = qr(Y)
       repeat power_iters times: Z = F^H Q; Qz = qr(Z); Y = F Qz; Q = qr(Y)
@@ -406,9 +418,10 @@ def randomized_tsvdm_faces(Xh: np.ndarray, Omega: np.ndarray, k: int, power_iter
     """Randomized facewise truncation of a real transform-domain tensor with
     one shared Gaussian test matrix Omega (p x ell).
 
-    Rank rule on the small SVD: fixed k, or the smallest k with
+    Rank rule on the small SVD: fixed k, or the smallest k <= the cap k with
     ||F||^2 - sum_{j<=k} s_j^2 <= tau^2 ||F||^2 (the left side is the squared
-    error of the rank-k result because Q has orthonormal columns).  cert[f] is
+    error of the rank-k result because Q has orthonormal columns), the cap
+    when no such k exists.  cert[f] is
     the error ||F - T_f||_F of the kept approximation, formed explicitly."""
     m, p, nf = Xh.shape
     ell = Omega.shape[1]
@@ -427,7 +440,8 @@ def randomized_tsvdm_faces(Xh: np.ndarray, Omega: np.ndarray, k: int, power_iter
         if mode == "fixed":
             kf = min(k, ns)
         else:
-            kf = ns
+            # smallest k <= the cap meeting tau; the cap itself when none does
+            kf = min(k, ns)
             for kk in range(min(k, ns) + 1):
                 if fro2 - np.sum(sf[:kk] ** 2) <= tau * tau * fro2:
                     kf = kk

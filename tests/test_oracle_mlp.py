@@ -81,3 +81,20 @@ def test_predicted_widths_round_up():
     k, l = mlp.predict_widths(np.array([[10.2 / 32, 14.5 / 48], [1.0, 1.0], [0.0, 0.0]]))
     assert list(k) == [12, 32, 1]
     assert list(l) == [16, 40, 16]
+
+
+def test_rank_label_closed_form_of_geometric_profiles():
+    """Labels of the decaying-face workload (s_j = 10^(-rho j), j = 1..32)
+    against the closed form of the geometric tail: the energy rule holds iff
+    q^k <= tau^2 + (1 - tau^2) q^32 with q = 10^(-2 rho)."""
+    tau = 1e-4
+    seen = set()
+    for rho in np.linspace(1 / 16, 1 / 2, 57):
+        q = 10.0 ** (-2 * rho)
+        x = np.log(tau ** 2 + (1 - tau ** 2) * q ** 32) / np.log(q)
+        if min(x - np.floor(x), np.ceil(x) - x) < 1e-6:
+            continue
+        k = min(int(np.ceil(x)), 32)
+        assert mlp.rank_label(10.0 ** (-rho * np.arange(1, 33)), tau) == k
+        seen.add(k)
+    assert len(seen) > 15

@@ -402,3 +402,137 @@ def test_kron_sum_faces_match_the_map_and_transform():
     for i, f in enumerate(faces):
         np.testing.assert_allclose(F[:, :, i], Xh[:, :, f], atol=1e-12 * np.abs(Xh).max())
         assert np.linalg.matrix_rank(F[:, :, i], tol=1e-10 * np.linalg.norm(F[:, :, i])) <= r
+
+
+# ------------------------------------------------------------ randomized energy rule
+def _faces_with_spectra(m, p, spectra, seed):
+    """Faces U_f diag(s_f) V_f^T with U_f, V_f the Q factors (numpy QR) of
+    Gaussian matrices, so the singular values of face f are exactly s_f."""
+    g = np.random.default_rng(seed)
+    Xh = np.zeros((m, p, len(spectra)), order="F")
+    for f, s in enumerate(spectra):
+        Ua, _ = np.linalg.qr(g.standard_normal((m, len(s))))
+        Va, _ = np.linalg.qr(g.standard_normal((p, len(s))))
+        Xh[:, :, f] = (Ua * s) @ Va.T
+    return Xh
+
+
+def _geometric_crossing(rho, tau, r):
+    """For s_j = 10^(-rho j), j = 1..r (q = 10^(-2 rho)): the discarded energy
+    after k terms is sum_{j=k+1..r} q^j = q (q^k - q^r) / (1 - q) and the total
+    q (1 - q^r) / (1 - q), so the energy rule holds iff
+    q^k <= tau^2 + (1 - tau^2) q^r, i.e. k >= x = log(tau^2 + (1 - tau^2) q^r) / log q.
+    Returns (ceil(x), x): the crossing rank in closed form, and x itself (its
+    distance from the integers is the margin of the rank decision)."""
+    q = 10.0 ** (-2.0 * rho)
+    x = np.log(tau ** 2 + (1.0 - tau ** 2) * q ** r) / np.log(q)
+    return int(np.ceil(x)), x
+
+
+def test_randomized_energy_rule_exact_rank_closed_form():
+    """Faces of exact rank 12 <= the sketch width 16, geometric spectra: the
+    randomized reference (same Omega for every face, one power iteration)
+    captures the range exactly, so its energy rule must return the
+    closed-form crossing rank of each spectrum, and its certificate the
+    discarded singular values (Eckart-Young); the margin of every decision is
+    at least a fifth of a rank step (x at least 0.2 from an integer)."""
+    m, p, r, ell, tau = 60, 48, 12, 16, 1e-3
+    rhos = [0.25, 0.35, 0.45, 0.7, 0.9, 1.3]
+    spectra = [10.0 ** (-rho * np.arange(1, r + 1)) for rho in rhos]
+    want = []
+    for rho in rhos:
+        k, x = _geometric_crossing(rho, tau, r)
+        assert min(x - np.floor(x), np.ceil(x) - x) >= 0.2 or k == r
+        want.append(min(k, r))
+    assert len(set(want)) >= 5
+    Xh = _faces_with_spectra(m, p, spectra, 301)
+    Omega = _rand((p, ell), 302)
+    rr = oracle.randomized_tsvdm_faces(Xh, Omega, ell, power_iters=1, mode="energy", tau=tau)
+    assert list(rr["ranks"]) == want
+    for f, s in enumerate(spectra):
+        tail = np.sqrt(np.sum(s[want[f]:] ** 2))
+        assert rr["cert"][f] == pytest.approx(tail, rel=1e-6, abs=1e-13)
+        assert rr["cert"][f] <= tau * np.linalg.norm(s)
+    # a rank cap below the crossing rank returns the cap
+    rc = oracle.randomized_tsvdm_faces(Xh, Omega, 4, power_iters=1, mode="energy", tau=tau)
+    assert list(rc["ranks"]) == [min(w, 4) for w in want]
+
+
+@pytest.mark.parametrize("tau", [2e-3, 5e-4, 2e-4])
+def test_randomized_energy_rule_rank_beyond_sketch(tau):
+    """Rank 40 > sketch width 20 with s_j = 10^(-j/4): the discarded energy
+    includes the 20 directions the sketch never sees, so a rule that forgot
+    them, or an off-by-one in the tail, returns another rank than the closed
+    form; with one power iteration the leading Ritz values are accurate to
+    far below the decision margins (checked here to be at least 15% of the
+    threshold)."""
+    m, p, r, ell, cap, rho = 70, 64, 40, 20, 16, 0.25
+    k, x = _geometric_crossing(rho, tau, r)
+    assert min(x - np.floor(x), np.ceil(x) - x) >= 0.15 and k <= cap
+    s = 10.0 ** (-rho * np.arange(1, r + 1))
+    Xh = _faces_with_spectra(m, p, [s, s], 311)
+    Omega = _rand((p, ell), 312)
+    rr = oracle.randomized_tsvdm_faces(Xh, Omega, cap, power_iters=1, mode="energy", tau=tau)
+    assert list(rr["ranks"]) == [k, k]
+    tail = np.sqrt(np.sum(s[k:] ** 2))
+    np.testing.assert_allclose(rr["cert"], tail, rtol=1e-3)
+
+
+def test_geometric_crossing_matches_a_direct_count():
+    """The closed form used above against counting the tail term by term."""
+    for rho in (0.1, 0.25, 0.4, 0.7):
+        for tau in (1e-2, 3e-3, 1e-4):
+            s2 = 10.0 ** (-2 * rho * np.arange(1, 33))
+            k, x = _geometric_crossing(rho, tau, 32)
+            if min(x - np.floor(x), np.ceil(x) - x) < 1e-6:
+                continue
+            ks = [kk for kk in range(33) if s2[kk:].sum() <= tau ** 2 * s2.sum()]
+            assert ks[0] == k
+
+
+# ------------------------------------------------------------ factors -> tensor
+@pytest.mark.parametrize("n", [7, 8])
+def test_hermitian_expansion_and_reconstruction_from_library_svd(n):
+    """Half of the DFT faces of a real tensor (numpy FFT), their thin SVD by
+    numpy, expanded to all n faces by conjugation and mapped back by
+    approx_from_factors: with every triplet kept the real input returns and
+    the imaginary part vanishes (a missing conjugation leaves it non-zero);
+    truncated to 2 triplets the error equals the discarded singular values of
+    all n library faces (Eckart-Young per face, isometry of the unitary DFT)."""
+    m, p = 5, 6
+    X = _rand((m, p, n), 321)
+    Xh = np.fft.fft(X, axis=2, norm="ortho")
+    half = n // 2 + 1
+    r = min(m, p)
+    U = np.zeros((m, r, half), dtype=complex, order="F")
+    V = np.zeros((p, r, half), dtype=complex, order="F")
+    S = np.zeros((r, half), order="F")
+    for f in range(half):
+        u, s, vh = np.linalg.svd(Xh[:, :, f], full_matrices=False)
+        U[:, :, f], S[:, f], V[:, :, f] = u, s, vh.conj().T
+    M = oracle.dft_matrix(n)
+    Uf, Sf, Vf, Rf = oracle.expand_hermitian(U, S, V, np.full(half, r), n)
+    T = oracle.approx_from_factors(Uf, Sf, Vf, Rf, M)
+    assert np.max(np.abs(np.imag(T))) < 1e-13
+    assert np.max(np.abs(np.real(T) - X)) < 1e-13
+    Uf, Sf, Vf, Rf = oracle.expand_hermitian(U, S, V, np.full(half, 2), n)
+    T2 = oracle.approx_from_factors(Uf, Sf, Vf, Rf, M)
+    assert np.max(np.abs(np.imag(T2))) < 1e-13
+    tail = sum(np.sum(np.linalg.svd(Xh[:, :, f], compute_uv=False)[2:] ** 2) for f in range(n))
+    assert np.linalg.norm(np.real(T2) - X) == pytest.approx(np.sqrt(tail), rel=1e-12)
+
+
+def test_approx_from_factors_dct_full_rank_returns_input():
+    """DCT-II: library DCT of the tensor, numpy SVD of every face, all
+    triplets kept, then approx_from_factors returns the input."""
+    m, p, n = 6, 4, 5
+    X = _rand((m, p, n), 331)
+    Xh = scipy.fft.dct(X, type=2, norm="ortho", axis=2)
+    U = np.zeros((m, 4, n), order="F")
+    V = np.zeros((p, 4, n), order="F")
+    S = np.zeros((4, n), order="F")
+    for f in range(n):
+        u, s, vh = np.linalg.svd(Xh[:, :, f], full_matrices=False)
+        U[:, :, f], S[:, f], V[:, :, f] = u, s, vh.T
+    T = oracle.approx_from_factors(U, S, V, np.full(n, 4), oracle.dct2_matrix(n))
+    assert np.max(np.abs(T - X)) < 1e-13
