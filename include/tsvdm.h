@@ -130,7 +130,10 @@ typedef struct {
     double *cert;      /* nf or NULL: ||Xhat_f - Uhat_f S_f Vhat_f^H||_F         */
     double *fro;       /* nf or NULL: ||Xhat_f||_F                               */
     int32_t *info;     /* nf or NULL: 0 ok, 1 Jacobi sweep cap reached,
-                          2 Cholesky breakdown in the range finder, 3 non-finite */
+                          2 Cholesky breakdown in the range finder, 3 non-finite,
+                          4 ENERGY: no rank up to the cap meets tau (the cap is
+                          returned).  When several apply, the larger code of
+                          1..3 wins over 4 */
 } tsvdm_factors;
 
 /* Library version, (major << 16) | minor. */

@@ -202,7 +202,7 @@ __global__ __launch_bounds__(JT) void k_jac_finish(int64_t m, int64_t p, int64_t
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int kf;
+        int kf, miss = 0;
         const int cap = (int)(kmax < n ? kmax : n);
         if (mode == TSVDM_RANK_FIXED) {
             kf = kfix < n ? kfix : n;
@@ -210,10 +210,14 @@ __global__ __launch_bounds__(JT) void k_jac_finish(int64_t m, int64_t p, int64_t
             int kc = kfix > 0 && kfix < cap ? kfix : cap;
             double bound = tau * tau * fro2[f], tail = 0.0;
             for (int j = 0; j < n; ++j) tail += nrm[perm[j]] * nrm[perm[j]];
-            kf = kc;
+            kf = -1;
             for (int k = 0; k <= kc; ++k) {
                 if (tail <= bound) { kf = k; break; }
                 if (k < n) tail -= nrm[perm[k]] * nrm[perm[k]];
+            }
+            if (kf < 0) {  // the tolerance is not met within the cap
+                kf = kc;
+                miss = 1;
             }
         }
         double disc = 0.0;
@@ -223,7 +227,7 @@ __global__ __launch_bounds__(JT) void k_jac_finish(int64_t m, int64_t p, int64_t
         ranks[f] = kf;
         if (cert) cert[f] = sqrt(disc);
         if (fro) fro[f] = sqrt(fro2[f]);
-        if (info) info[f] = sweeps_used[f] < 0 ? 1 : (isfinite(fro2[f]) ? 0 : 3);
+        if (info) info[f] = !isfinite(fro2[f]) ? 3 : sweeps_used[f] < 0 ? 1 : miss ? 4 : 0;
     }
     __syncthreads();
     const int kf = kf_s;

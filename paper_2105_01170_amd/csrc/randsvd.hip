@@ -956,17 +956,21 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
         double fro2 = 0.0, res = 0.0;
         for (int i = 0; i < nfro; ++i) fro2 += fro_part[(int64_t)f * nfro + i];
         for (int i = 0; i < nres; ++i) res += res_part[(int64_t)f * nres + i];
-        int kf;
+        int kf, miss = 0;
         if (mode == TSVDM_RANK_FIXED) {
             kf = kfix < ell ? kfix : ell;
         } else {
             int cap = kfix > 0 && kfix < ell ? kfix : ell;
             double tail = res, bound = tau * tau * fro2;
             for (int j = 0; j < ell; ++j) tail += lam[j];
-            kf = cap;
+            kf = -1;
             for (int k = 0; k <= cap; ++k) {
                 if (tail <= bound) { kf = k; break; }
                 if (k < ell) tail -= lam[perm[k]];
+            }
+            if (kf < 0) {  // the tolerance is not met within the cap
+                kf = cap;
+                miss = 1;
             }
         }
         double disc = 0.0;
@@ -974,7 +978,8 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
         kf_out[f] = kf;
         fro2_out[f] = fro2;
         if (cert) cert[fmap ? fmap[f] : f] = nres > 0 ? sqrt(res + disc) : -1.0;
-        jinfo[f] = (conv || ell <= 1) ? 0 : 1;
+        // bit 0: sweep cap reached; bit 2: energy target missed at the cap
+        jinfo[f] = ((conv || ell <= 1) ? 0 : 1) | (miss ? 4 : 0);
     }
     for (int r = tid; r < LP; r += QT) {
         int j = r < ell ? perm[r] : r;
@@ -1068,8 +1073,8 @@ __global__ __launch_bounds__(GT) void k_factors(const float *__restrict__ Q, con
             ranks[fd] = kf;
             if (fro) fro[fd] = sqrt(fro2[f]);
             if (info) {
-                int code = 0;
-                if (jinfo[f]) code = 1;
+                int code = (jinfo[f] & 4) ? 4 : 0;
+                if (jinfo[f] & 1) code = 1;
                 if (qr_info[f]) code = 2;
                 if (!isfinite(fro2[f])) code = 3;
                 info[fd] = code;
