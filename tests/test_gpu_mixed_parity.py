@@ -143,7 +143,10 @@ def test_mixed_headline_shape_512_k32_ell40():
     sample = [0, 7, 15]
     ex = oracle.tsvdm_truncate_faces(np.asfortranarray(Xh64[:, :, sample]), "fixed", k)
     assert relerr(That[:, :, sample], ex["That"]) < 1e-4
-    np.testing.assert_allclose(got["S"][:k, sample], ex["s"][:k], rtol=1e-4)
+    # Weyl: |s_j(A) - s_j(B)| <= ||A - B||_2, so the singular values are compared
+    # on the scale of ||Xhat_f||, not relative to each (small) s_j
+    for i, f in enumerate(sample):
+        np.testing.assert_allclose(got["S"][:k, f], ex["s"][:k, i], rtol=0, atol=1e-6 * got["fro"][f])
     np.testing.assert_allclose(got["fro"], np.sqrt(np.sum(Xh64 ** 2, axis=(0, 1))), rtol=1e-6)
     # the certificate against the error of the returned factors
     true = np.array([np.linalg.norm(Xh64[:, :, f] - That[:, :, f]) for f in range(n3)])
