@@ -229,6 +229,25 @@ tsvdm_status tsvdm_truncate(const tsvdm_tensor *Xhat, const tsvdm_truncate_opts 
                             tsvdm_factors *out, void *workspace, size_t workspace_bytes,
                             void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * tsvdm_truncate with PREC_MIXED and no workspace argument.  Its scratch is a
+ * static device array of tsvdm_noalloc_scratch_bytes() bytes (32 MiB), one
+ * per GPU the library runs on, held until the process ends; the call itself
+ * allocates nothing.  The faces are processed in consecutive groups whose
+ * workspace fits the array (the results equal tsvdm_truncate's bit for bit).
+ * Returns TSVDM_EWORKSPACE if a single face needs more scratch than the array
+ * holds, TSVDM_EUNSUPPORTED for PREC_F64; other arguments as for
+ * tsvdm_truncate.  Every call on one GPU uses that GPU's one array: calls
+ * that overlap on the same GPU (other streams, other threads) race and give
+ * wrong results; serialise them.  Nothing needs clearing between calls (every
+ * scratch value is written before it is read). */
+tsvdm_status tsvdm_truncate_noalloc(const tsvdm_tensor *Xhat, const tsvdm_truncate_opts *opts,
+                                    tsvdm_factors *out, void *stream);
+
+/* Size of the static scratch array of tsvdm_truncate_noalloc, in bytes. */
+size_t tsvdm_noalloc_scratch_bytes(void);
+
 /* Workspace bytes tsvdm_apply needs: the transformed right-hand sides and,
  * for compute = F32 or BF16, a copy of Vhat with the rows j + ell*k of each
  * block row j contiguous in k. */

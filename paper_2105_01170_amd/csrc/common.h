@@ -173,6 +173,9 @@ tsvdm_status launch_jacobi_truncate(const tsvdm_tensor *X, const tsvdm_truncate_
 size_t mixed_workspace(int64_t m, int64_t p, int64_t nf, int ell);
 tsvdm_status launch_mixed_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
                                    tsvdm_factors *F, void *ws, hipStream_t s);
+tsvdm_status launch_mixed_truncate_noalloc(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
+                                           tsvdm_factors *F, hipStream_t s);
+size_t noalloc_scratch_bytes();
 tsvdm_status launch_mlp_forward(const uint16_t *w16, const uint16_t *x, int64_t n, float *y, hipStream_t s);
 size_t features_workspace(int64_t m, int64_t p, int64_t nf);
 tsvdm_status launch_rank_features(const tsvdm_tensor *X, const float *omega, uint16_t *features, void *ws,

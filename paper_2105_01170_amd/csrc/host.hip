@@ -327,10 +327,9 @@ size_t tsvdm_truncate_workspace_size(const tsvdm_tensor *X, const tsvdm_truncate
     return mixed_workspace(X->m, X->p, X->n3, o->k + o->oversample);
 }
 
-tsvdm_status tsvdm_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
-                            void *ws, size_t ws_bytes, void *stream) {
-    tsvdm_status st;
-    if ((st = check_truncate(X, o)) != TSVDM_OK) return st;
+// the factors of a truncation of X with options o
+static tsvdm_status check_truncate_out(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
+                                       const tsvdm_factors *F) {
     if (!F) FAIL(TSVDM_EINVAL, "out is NULL");
     if (F->m != X->m || F->p != X->p || F->nf != X->n3)
         FAIL(TSVDM_EINVAL, "factor dims (%lld, %lld, %lld) differ from Xhat (%lld, %lld, %lld)",
@@ -347,6 +346,14 @@ tsvdm_status tsvdm_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
     if (F->dtype != want) FAIL(TSVDM_EINVAL, "factor dtype %d, expected %d", F->dtype, want);
     if (X->m * X->p * X->n3 > 0 && (!F->U || !F->S || !F->V || !F->ranks))
         FAIL(TSVDM_EINVAL, "factor pointers U, S, V, ranks must be set");
+    return TSVDM_OK;
+}
+
+tsvdm_status tsvdm_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
+                            void *ws, size_t ws_bytes, void *stream) {
+    tsvdm_status st;
+    if ((st = check_truncate(X, o)) != TSVDM_OK) return st;
+    if ((st = check_truncate_out(X, o, F)) != TSVDM_OK) return st;
     size_t need_ws = tsvdm_truncate_workspace_size(X, o);
     if (need_ws > 0 && (!ws || ws_bytes < need_ws))
         FAIL(TSVDM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need_ws, ws_bytes);
@@ -354,6 +361,18 @@ tsvdm_status tsvdm_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
     if (o->precision == TSVDM_PREC_F64) return launch_jacobi_truncate(X, o, F, ws, (hipStream_t)stream);
     return launch_mixed_truncate(X, o, F, ws, (hipStream_t)stream);
 }
+
+tsvdm_status tsvdm_truncate_noalloc(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
+                                    void *stream) {
+    tsvdm_status st;
+    if ((st = check_truncate(X, o)) != TSVDM_OK) return st;
+    if (o->precision != TSVDM_PREC_MIXED) FAIL(TSVDM_EUNSUPPORTED, "tsvdm_truncate_noalloc: PREC_MIXED only");
+    if ((st = check_truncate_out(X, o, F)) != TSVDM_OK) return st;
+    if (X->n3 == 0) return TSVDM_OK;
+    return launch_mixed_truncate_noalloc(X, o, F, (hipStream_t)stream);
+}
+
+size_t tsvdm_noalloc_scratch_bytes(void) { return noalloc_scratch_bytes(); }
 
 // ---------------------------------------------------------------- learned rank
 static tsvdm_status check_features(const tsvdm_tensor *X, bool need_data) {

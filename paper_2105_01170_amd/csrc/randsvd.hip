@@ -32,6 +32,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 using namespace tsvdm;
 
 namespace {
@@ -1222,29 +1224,32 @@ bool vec_loads_ok(const float *X, int m, int p) {
     return m % 4 == 0 && p % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 &&
            (int64_t)m * p < (int64_t)1 << 30;
 }
+// wf0: the face of the workspace w0 the group starts at (f0 when w0 was carved
+// for the whole tensor, 0 when it was carved for the group alone).
 template <int LP>
 tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
                        const MixedWs &w0, int f0, int nfg, hipStream_t s,
-                       const int32_t *fmap = nullptr) {
+                       const int32_t *fmap = nullptr, int wf0 = -1) {
     const int m = (int)X->m, p = (int)X->p, ell = o->k + o->oversample;
     const int mparts = (m + 63) / 64, pparts = (p + 63) / 64;
     const int64_t kmax = F->kmax;
     MixedWs w = w0;
-    w.Y += (int64_t)f0 * m * LP;
-    w.Qm += (int64_t)f0 * m * LP;
-    w.Z += (int64_t)f0 * p * LP;
-    w.Qp += (int64_t)f0 * p * LP;
-    w.gram_m += (int64_t)f0 * mparts * LP * LP;
-    w.gram_p += (int64_t)f0 * pparts * LP * LP;
-    w.fro_part += (int64_t)f0 * mparts;
-    w.res_part += (int64_t)f0 * pparts;
-    w.UB += (int64_t)f0 * LP * LP;
-    w.sig += (int64_t)f0 * LP;
-    w.fro2 += f0;
-    w.perm += (int64_t)f0 * LP;
-    w.kf += f0;
-    w.qr_info += f0;
-    w.jinfo += f0;
+    const int64_t g0 = wf0 < 0 ? f0 : wf0;
+    w.Y += g0 * m * LP;
+    w.Qm += g0 * m * LP;
+    w.Z += g0 * p * LP;
+    w.Qp += g0 * p * LP;
+    w.gram_m += g0 * mparts * LP * LP;
+    w.gram_p += g0 * pparts * LP * LP;
+    w.fro_part += g0 * mparts;
+    w.res_part += g0 * pparts;
+    w.UB += g0 * LP * LP;
+    w.sig += g0 * LP;
+    w.fro2 += g0;
+    w.perm += g0 * LP;
+    w.kf += g0;
+    w.qr_info += g0;
+    w.jinfo += g0;
     const float *Xd = reinterpret_cast<const float *>(X->data) + (int64_t)f0 * m * p;
     float *Uo = reinterpret_cast<float *>(F->U) + (int64_t)f0 * m * kmax;
     float *Vo = reinterpret_cast<float *>(F->V) + (int64_t)f0 * p * kmax;
@@ -1332,6 +1337,70 @@ tsvdm_status run_mixed(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     return run_group<LP>(X, o, F, w, 0, (int)X->n3, s);
 }
 
+// ---------------------------------------------------------------- no allocation
+// Scratch of tsvdm_truncate_noalloc: one copy per GPU (each device holds its
+// own instance of this array at its own address), kept until the process
+// ends.  Host code never uses the name `scratch` as an address: it is a
+// host-side stand-in; the device address comes from hipGetSymbolAddress.
+constexpr size_t kNoallocScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device
+
+// Device address of the current device's scratch array (looked up once per device).
+tsvdm_status noalloc_scratch(void **ptr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_check(e, "noalloc: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("noalloc: device %d beyond the %d devices the scratch table holds", dev, kMaxDevices);
+        return TSVDM_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_check(e, "noalloc: hipGetSymbolAddress(scratch)");
+        if (!p) {
+            set_error("noalloc: no device address for the scratch array");
+            return TSVDM_EDEVICE;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return TSVDM_OK;
+}
+
+// The faces in groups whose workspace fits the scratch array, one run_group
+// each, with the workspace carved for the group alone.
+template <int LP>
+tsvdm_status run_mixed_noalloc(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
+                               hipStream_t s) {
+    const int64_t m = X->m, p = X->p, nf = X->n3;
+    const size_t one = carve(nullptr, m, p, 1, LP, nullptr);
+    if (one > kNoallocScratchBytes) {
+        set_error("noalloc: one %lld x %lld face needs %zu bytes of scratch, the static scratch holds %zu",
+                  (long long)m, (long long)p, one, kNoallocScratchBytes);
+        return TSVDM_EWORKSPACE;
+    }
+    int64_t g = (int64_t)(kNoallocScratchBytes / one);
+    if (g > nf) g = nf;
+    while (g > 1 && carve(nullptr, m, p, g, LP, nullptr) > kNoallocScratchBytes) --g;
+    void *base = nullptr;
+    tsvdm_status st = noalloc_scratch(&base);
+    if (st != TSVDM_OK) return st;
+    for (int64_t f0 = 0; f0 < nf; f0 += g) {
+        const int64_t n = nf - f0 < g ? nf - f0 : g;
+        MixedWs w;
+        carve(reinterpret_cast<char *>(base), m, p, n, LP, &w);
+        st = run_group<LP>(X, o, F, w, (int)f0, (int)n, s, nullptr, 0);
+        if (st != TSVDM_OK) return st;
+    }
+    return TSVDM_OK;
+}
+
 }  // namespace
 
 namespace tsvdm {
@@ -1355,6 +1424,22 @@ tsvdm_status launch_mixed_truncate(const tsvdm_tensor *X, const tsvdm_truncate_o
         default: return run_mixed<64>(X, o, F, ws, s);
     }
 }
+
+tsvdm_status launch_mixed_truncate_noalloc(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
+                                           tsvdm_factors *F, hipStream_t s) {
+    if (X->m > 65536 || X->p > 65536 || X->n3 > 65535) {
+        set_error("PREC_MIXED: face dims up to 65536 and up to 65535 faces");
+        return TSVDM_EUNSUPPORTED;
+    }
+    switch (padded(o->k + o->oversample)) {
+        case 16: return run_mixed_noalloc<16>(X, o, F, s);
+        case 32: return run_mixed_noalloc<32>(X, o, F, s);
+        case 48: return run_mixed_noalloc<48>(X, o, F, s);
+        default: return run_mixed_noalloc<64>(X, o, F, s);
+    }
+}
+
+size_t noalloc_scratch_bytes() { return kNoallocScratchBytes; }
 
 // ---------------------------------------------------------------- learned rank
 // Features: sketch Y = Xhat_f Omega[:, :32] (BF16, the first pass of the

@@ -60,7 +60,8 @@ EXPORTS = ["tsvdm_version", "tsvdm_last_error", "tsvdm_tensor_from_blockmat",
            "tsvdm_mlp_train_step", "tsvdm_f32_to_f16", "tsvdm_rank_features_workspace_size",
            "tsvdm_rank_features", "tsvdm_truncate_learned_workspace_size", "tsvdm_truncate_learned",
            "tsvdm_transform_batched_workspace_size", "tsvdm_transform_plan_create",
-           "tsvdm_transform_batched", "tsvdm_transform_plan_destroy"]
+           "tsvdm_transform_batched", "tsvdm_transform_plan_destroy", "tsvdm_truncate_noalloc",
+           "tsvdm_noalloc_scratch_bytes"]
 
 _LIB = None
 
@@ -99,6 +100,10 @@ def lib():
         L.tsvdm_truncate.restype = i32
         L.tsvdm_truncate.argtypes = [P(TsvdmTensor), P(TsvdmTruncateOpts), P(TsvdmFactors), vp, sz, vp]
         L.tsvdm_apply_workspace_size.restype = sz
+        L.tsvdm_truncate_noalloc.argtypes = [P(TsvdmTensor), P(TsvdmTruncateOpts), P(TsvdmFactors), vp]
+        L.tsvdm_truncate_noalloc.restype = i32
+        L.tsvdm_noalloc_scratch_bytes.argtypes = []
+        L.tsvdm_noalloc_scratch_bytes.restype = sz
         L.tsvdm_apply_workspace_size.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, i32]
         L.tsvdm_apply.restype = i32
         L.tsvdm_apply.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, vp, i64, vp, i64,
@@ -195,6 +200,14 @@ def tsvdm_truncate(X: TsvdmTensor, opts: TsvdmTruncateOpts, F: TsvdmFactors, ws_
                    ws_bytes: int, stream: int = 0):
     _check(lib().tsvdm_truncate(ctypes.byref(X), ctypes.byref(opts), ctypes.byref(F), ws_ptr,
                                 ws_bytes, stream))
+
+
+def tsvdm_truncate_noalloc(X: TsvdmTensor, opts: TsvdmTruncateOpts, F: TsvdmFactors, stream: int = 0):
+    _check(lib().tsvdm_truncate_noalloc(ctypes.byref(X), ctypes.byref(opts), ctypes.byref(F), stream))
+
+
+def tsvdm_noalloc_scratch_bytes() -> int:
+    return lib().tsvdm_noalloc_scratch_bytes()
 
 
 def tsvdm_apply_workspace_size(M: TsvdmMdesc, F: TsvdmFactors, ell: int, q: int, nrhs: int,
