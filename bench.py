@@ -371,12 +371,52 @@ def apply_main(args):
         "kernels_ms_per_step": {k2: round(v["ms_per_step"], 4) for k2, v in kern.items()},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = apply_cpu_baseline(w, ell, q, m, n, k, nrhs)
+        out["cpu_baseline"], y_ref = apply_cpu_baseline(w, ell, q, m, n, k, nrhs)
+        # the result of the last timed call against the oracle's dense FP64 product
+        step()
+        torch.cuda.synchronize()
+        yg = y.cpu().numpy().astype(np.float64).reshape((ell * m, nrhs), order="F")
+        out["oracle_rel_err"] = float(np.linalg.norm(yg - y_ref) / np.linalg.norm(y_ref))
     if args.kernel_table:
         for kname, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms_per_step"]):
             print(f"{kname:24s} {v['launches']:6d} launches  {v['ms_per_step'] * 1e3:10.1f} us/step",
                   file=sys.stderr)
     print(json.dumps(out))
+
+
+def host_cpu():
+    """The host CPU's model name and the number of logical CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:  # pragma: no cover
+        pass
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        ncpu = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": ncpu}
+
+
+def blas_threads():
+    try:
+        from threadpoolctl import threadpool_info
+        return int(max([d.get("num_threads", 1) for d in threadpool_info()] or [1]))
+    except Exception:  # pragma: no cover
+        return os.cpu_count()
+
+
+def one_thread(fn):
+    """fn() with every BLAS/OpenMP pool limited to one thread; (result, seconds)."""
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.time()
+        r = fn()
+        return r, time.time() - t0
 
 
 def apply_cpu_baseline(w, ell, q, m, n, k, ncols):
@@ -391,17 +431,17 @@ def apply_cpu_baseline(w, ell, q, m, n, k, ncols):
     for f in range(n):
         That[:, :, f] = (Uh[:, :, f] * w["sigma"]) @ np.conj(Vh[:, :, f]).T
     Ahat = oracle.blockmat_from_tensor(np.real(oracle.inverse_mode3(That, M)), ell, q)
-    oracle.dense_apply(Ahat, w["X"][:, :ncols])
+    y_ref = oracle.dense_apply(Ahat, w["X"][:, :ncols])
     dt = time.time() - t0
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count()
-    return {"value": 2.0 * (ell * m) * (q * n) * ncols / dt / 1e9, "unit": "GFLOP/s", "cores": int(threads),
-            "kind": "oracle",
-            "sample": f"first {ncols} of the 1024 right-hand sides, the dense matrix formed from the factors "
-                      f"(FP64), {dt:.1f} s on the host"}
+    # the product alone on one thread, 64 columns
+    _, dt1 = one_thread(lambda: oracle.dense_apply(Ahat, w["X"][:, :64]))
+    out = {"value": 2.0 * (ell * m) * (q * n) * ncols / dt / 1e9, "unit": "GFLOP/s", "cores": blas_threads(),
+           "kind": "oracle",
+           "sample": f"first {ncols} of the 1024 right-hand sides, the dense matrix formed from the factors "
+                     f"(FP64), {dt:.1f} s on the host",
+           "value_1thread_product": 2.0 * (ell * m) * (q * n) * 64 / dt1 / 1e9}
+    out.update(host_cpu())
+    return out, y_ref
 
 
 def learned_main(args):
@@ -674,13 +714,9 @@ def main():
     # CPU baseline: the oracle (double precision randomized t-SVDM, same
     # algorithm and test matrix) on a bounded sample of faces of the same input
     cpu = None
+    oracle_err = None
     if not args.no_cpu_baseline:
         import oracle
-        try:
-            from threadpoolctl import threadpool_info
-            blas_threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-        except Exception:  # pragma: no cover
-            blas_threads = os.cpu_count()
         Xh_host = X.cpu().numpy().astype(np.float64).reshape((m, p, n3), order="F")
         sel = np.linspace(0, n3 - 1, args.cpu_faces).round().astype(int)
         Msel = oracle.dct2_matrix(n3)[sel, :]
@@ -688,12 +724,32 @@ def main():
         xs = oracle.mode3(Xh_host, Msel)
         rr = oracle.randomized_tsvdm_faces(xs, fac["Omega"], k, power_iters=1)
         c1 = time.time()
-        cpu = {"value": args.cpu_faces / (c1 - c0), "unit": "faces/s", "cores": int(blas_threads),
+        n1 = min(8, args.cpu_faces)
+        _, dt1 = one_thread(lambda: oracle.randomized_tsvdm_faces(
+            oracle.mode3(Xh_host, Msel[:n1]), fac["Omega"], k, power_iters=1))
+        cpu = {"value": args.cpu_faces / (c1 - c0), "unit": "faces/s", "cores": blas_threads(),
                "kind": "oracle",
                "sample": f"{args.cpu_faces} of the {n3} faces of the same tensor: explicit DCT-II rows "
                          f"for those faces, FP64 randomized truncation with the same Omega and the "
                          f"explicit residual; {c1 - c0:.1f} s on the host",
+               "value_1thread": n1 / dt1,
                "max_cert_rel": float(np.max(rr["cert"] / np.sqrt(np.sum(xs ** 2, axis=(0, 1)))))}
+        cpu.update(host_cpu())
+        # the GPU's factors of the sampled faces against the oracle's FP64 result
+        kmax = F.kmax
+        Ug = F.U.cpu().numpy().reshape((m, kmax, n3), order="F")[:, :, sel].astype(np.float64)
+        Vg = F.V.cpu().numpy().reshape((p, kmax, n3), order="F")[:, :, sel].astype(np.float64)
+        Sg = F.S.cpu().numpy().reshape((kmax, n3), order="F")[:, sel]
+        rk = F.ranks.cpu().numpy()[sel]
+        Tg = np.zeros_like(xs)
+        for i in range(len(sel)):
+            Tg[:, :, i] = (Ug[:, :rk[i], i] * Sg[:rk[i], i]) @ Vg[:, :rk[i], i].T
+        nx = np.linalg.norm(xs)
+        oracle_err = {"faces": int(len(sel)),
+                      "vs_oracle": float(np.linalg.norm(Tg - rr["That"]) / nx),
+                      "true_rel_err": float(np.linalg.norm(xs - Tg) / nx),
+                      "oracle_true_rel_err": float(np.linalg.norm(xs - rr["That"]) / nx),
+                      "ranks_equal": bool(np.array_equal(rk, rr["ranks"]))}
 
     out = {
         "metric": METRIC,
@@ -713,6 +769,7 @@ def main():
                                "DCT-II; randomized k=32, oversample 8, 1 power iteration, certified",
                    "m": m, "p": p, "n3": n3, "k": k, "oversample": os_, "power_iters": 1},
         "certified_rel_err": rel_err,
+        "oracle_rel_err": oracle_err,
         "faces_flagged": int(np.sum(info != 0)),
         "roofline": roof,
         "hbm_pass_frac": passes,
