@@ -72,10 +72,13 @@ def algorithmic_work(m, p, nf, ell, k, sweeps=5):
         "sketch_xw_bf16": ("hbm", X + 4.0 * m * ell * nf),                # read Xhat, write Y
         "power_xtw_bf16": ("hbm", X + 4.0 * (m + p) * ell * nf),          # + read Q
         "power_xw_split": ("hbm", X + 4.0 * (m + p) * ell * nf),
-        # projection and residual in one pass: X is read once algorithmically
-        # (its second read, for the residual, is served by the cache)
+        "project_xtw_split": ("hbm", X + 4.0 * (m + p) * ell * nf),
+        # projection and the energy rule's residual estimate in one pass (ENERGY only)
         "project_resid_split": ("hbm", X + 4.0 * (m + p) * ell * nf),
         "factors": ("hbm", 4.0 * (m + p) * (ell + k) * nf),
+        # the certificate: read Xhat and the stored factors once (2 m p k FP64
+        # matrix-core flops per face besides)
+        "resid_factors": ("hbm", X + 4.0 * (m + p) * k * nf),
         "cholqr_sketch": ("fp64", chol_qr(m, 1)),
         "cholqr_power_z": ("fp64", chol_qr(p, 1)),
         "cholqr_final": ("fp64", chol_qr(m, 2)),

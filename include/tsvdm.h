@@ -127,7 +127,14 @@ typedef struct {
     double *S;         /* kmax x nf, singular values, decreasing per face       */
     void *V;           /* p x kmax x nf  */
     int32_t *ranks;    /* nf */
-    double *cert;      /* nf or NULL: ||Xhat_f - Uhat_f S_f Vhat_f^H||_F         */
+    double *cert;      /* nf or NULL: the certificate ||Xhat_f - Uhat_f S_f Vhat_f^H||_F
+                          of the returned factors.  PREC_F64: the discarded
+                          singular values of the full SVD.  PREC_MIXED with
+                          certify: evaluated after the factors are stored, from
+                          the stored values (FP64 products and sums), so it is
+                          the error of the factors the caller receives to within
+                          ~1e-15 ||Xhat_f||_F; without certify: -1 (FIXED) or
+                          the estimate the energy rule used (ENERGY) */
     double *fro;       /* nf or NULL: ||Xhat_f||_F                               */
     int32_t *info;     /* nf or NULL: 0 ok, 1 Jacobi sweep cap reached,
                           2 Cholesky breakdown in the range finder, 3 non-finite,
@@ -220,8 +227,11 @@ size_t tsvdm_truncate_workspace_size(const tsvdm_tensor *Xhat, const tsvdm_trunc
  *   PREC_F64:   Xhat FP64 or C128; factors F64 / C128; full SVD per face.
  *   PREC_MIXED: Xhat FP32 (real M); factors F32; randomized range finder
  *               with the caller's Gaussian omega, power iteration, FP64
- *               shifted Cholesky-QR, FP64 core SVD; cert from an explicit
- *               residual pass when opts->certify is set (else cert = -1).
+ *               shifted Cholesky-QR, FP64 core SVD.  ENERGY decides each
+ *               rank from the estimate ||Xhat_f - Q B||^2 + sum_{j>k} s_j(B)^2
+ *               (Q the basis, B = Q^T Xhat_f; a residual pass with the
+ *               projection).  With opts->certify, a pass after the factors
+ *               computes cert from the stored factors (see tsvdm_factors).
  * out->kmax >= the largest rank that can be returned (k for FIXED, the cap
  * for ENERGY).  The error of the approximation in the original domain is
  * sqrt(sum_f w_f cert_f^2) (w_f = 1, or 2 for DFT faces 0 < f < n3/2). */

@@ -1085,11 +1085,138 @@ __global__ __launch_bounds__(GT) void k_factors(const float *__restrict__ Q, con
     }
 }
 
+// ---------------------------------------------------------------- certificate
+// Error of the returned factors: res_part[f * nb + blk] = the squared
+// Frobenius norm of rows a0 .. a0+63 of Xhat_f - Uhat_f diag(S_f) Vhat_f^T,
+// with Uhat, S, Vhat the values just stored (the first ranks[f] <= KP
+// triplets).  The product is formed by FP64 MFMA 16x16x4 (A = rows of Uhat,
+// exact in FP64; B = S_r times rows of Vhat, one rounding of the FP64
+// product; FP64 accumulation), the differences and squares in FP64, so the
+// sum is the exact error of the stored factors to a relative ~1e-15 of
+// ||Xhat_f||^2.  Grid (ceil(m/64) * nf) through xcd_map; the workgroup walks
+// the face's columns in chunks of 64: the X chunk (64 x 64 FP32, 16-byte
+// loads of four rows when VEC) and the Vhat chunk (KP x 64) staged in LDS,
+// the next chunk's loads issued before the current chunk's products (the
+// S_r scaling of W is applied as the operand is read).  Wavefront w owns rows a0 + 16w .. +15 and four 16-column output tiles
+// (independent accumulators); the FP64 output layout (row lane/16 + 4v,
+// column lane%16) picks the X values from LDS.
+template <int KP, bool VEC>
+__global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_resid(const float *__restrict__ X, int m, int p, int nf,
+                                              const float *__restrict__ U, const double *__restrict__ S,
+                                              const float *__restrict__ V, int64_t kmax,
+                                              const int32_t *__restrict__ ranks, double *__restrict__ res_part,
+                                              const int32_t *__restrict__ fmap) {
+    constexpr int NS = KP / 4, XP = 66, VPT = KP / 4;  // V loads per thread per chunk
+    __shared__ float xs[64 * XP];    // xs[c * XP + r] = X[a0 + r][b0 + c]
+    constexpr int WP = 80;  // rows 4 apart fall 16 banks apart
+    __shared__ float ws[KP * WP];    // ws[r * WP + c] = V[b0 + c][r]
+    __shared__ double ss[KP];        // S_r
+    __shared__ double red[GT / 64];
+    const int nb = (m + 63) / 64;
+    int blk, f;
+    xcd_map(blockIdx.x, nb, nf, blk, f);
+    const int fd = fmap ? fmap[f] : f;
+    const int a0 = blk * 64;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int kf = ranks[fd] < KP ? ranks[fd] : KP, ns = (kf + 3) / 4;
+    const float *Xf = X + (int64_t)fd * m * p;
+    const float *Uf = U + (int64_t)fd * m * kmax;
+    const float *Vf = V + (int64_t)fd * p * kmax;
+    const double *Sf = S + (int64_t)fd * kmax;
+    double ua[NS];  // A operands: Uhat[a0 + 16 wave + lane%16][4 s + lane/16]
+    {
+        const int row = a0 + 16 * wave + (lane & 15);
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            const int r = 4 * st + (lane >> 4);
+            ua[st] = row < m && r < kf ? (double)Uf[row + (int64_t)m * r] : 0.0;
+        }
+    }
+    const int xq = tid & 15, xc = tid >> 4, vc = tid & 63, vr0 = tid >> 6;
+    if (tid < KP) ss[tid] = tid < kf ? Sf[tid] : 0.0;
+    // chunk loads: X rows a0 + 4 (tid%16) .. +3 of columns b0 + tid/16 + 16 it;
+    // V row b0 + tid%64 of ranks tid/64 + 4 q
+    float xr[16], vr[VPT];
+    auto load = [&](int b0) {
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int b = b0 + xc + 16 * it, a = a0 + 4 * xq;
+            if constexpr (VEC) {
+                const bool ok = b < p && a < m;  // then a + 3 < m
+                const f32x4 v = *reinterpret_cast<const f32x4 *>(Xf + (ok ? a + (int64_t)m * b : 0));
+#pragma unroll
+                for (int u = 0; u < 4; ++u) xr[4 * it + u] = ok ? v[u] : 0.0f;
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool ok = b < p && a + u < m;
+                    const float v = Xf[ok ? a + u + (int64_t)m * b : 0];
+                    xr[4 * it + u] = ok ? v : 0.0f;
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) {
+            const int r = vr0 + 4 * q, b = b0 + vc;
+            const bool ok = r < kf && b < p;
+            const float v = Vf[ok ? b + (int64_t)p * r : 0];
+            vr[q] = ok ? v : 0.0f;
+        }
+    };
+    double racc = 0.0;
+    load(0);
+    for (int b0 = 0; b0 < p; b0 += 64) {
+#pragma unroll
+        for (int it = 0; it < 4; ++it)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xs[(xc + 16 * it) * XP + 4 * xq + u] = xr[4 * it + u];
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) ws[(vr0 + 4 * q) * WP + vc] = vr[q];
+        __syncthreads();
+        if (b0 + 64 < p) load(b0 + 64);  // next chunk in flight during the products
+        f64x4 acc[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[t] = f64x4{0, 0, 0, 0};
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            if (st >= ns) break;
+            const int r = 4 * st + (lane >> 4);
+            const double sr = ss[r];
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(ua[st], sr * (double)ws[r * WP + 16 * t + (lane & 15)],
+                                                           acc[t], 0, 0, 0);
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double d = (double)xs[(16 * t + (lane & 15)) * XP + 16 * wave + (lane >> 4) + 4 * v] - acc[t][v];
+                racc += d * d;
+            }
+        __syncthreads();
+    }
+    racc = wave_sum(racc);
+    if (lane == 0) red[wave] = racc;
+    __syncthreads();
+    if (tid == 0) res_part[(int64_t)f * nb + blk] = red[0] + red[1] + red[2] + red[3];
+}
+
+// cert[f] = sqrt of the ordered sum of face f's residual partials
+__global__ void k_cert(const double *__restrict__ res_part, int nparts, int nf, double *__restrict__ cert,
+                       const int32_t *__restrict__ fmap) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nf) return;
+    double r = 0.0;
+    for (int i = 0; i < nparts; ++i) r += res_part[(int64_t)f * nparts + i];
+    cert[fmap ? fmap[f] : f] = sqrt(r);
+}
+
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct MixedWs {
     float *Y, *Qm, *Z, *Qp;
-    double *gram_m, *gram_p, *fro_part, *res_part, *UB, *sig, *fro2;
+    double *gram_m, *gram_p, *fro_part, *res_part, *cert_part, *UB, *sig, *fro2;
     int *perm, *kf;
     int32_t *qr_info, *jinfo;
 };
@@ -1111,6 +1238,7 @@ size_t carve(char *base, int64_t m, int64_t p, int64_t nf, int LP, MixedWs *w) {
     t.gram_p = (double *)take(sizeof(double) * nf * pparts * LP * LP);
     t.fro_part = (double *)take(sizeof(double) * nf * mparts);
     t.res_part = (double *)take(sizeof(double) * nf * pparts);
+    t.cert_part = (double *)take(sizeof(double) * nf * mparts);
     t.UB = (double *)take(sizeof(double) * nf * LP * LP);
     t.sig = (double *)take(sizeof(double) * nf * LP);
     t.fro2 = (double *)take(sizeof(double) * nf);
@@ -1243,6 +1371,7 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     w.gram_p += g0 * pparts * LP * LP;
     w.fro_part += g0 * mparts;
     w.res_part += g0 * pparts;
+    w.cert_part += g0 * mparts;
     w.UB += g0 * LP * LP;
     w.sig += g0 * LP;
     w.fro2 += g0;
@@ -1261,8 +1390,11 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     const int nf = nfg;
     const dim3 gm((unsigned)(mparts * nf)), gp((unsigned)(pparts * nf));
     const bool power = o->power_iters > 0;
-    // the residual is needed for the certificate and for the energy rule
-    const bool resid = o->rank_mode == TSVDM_RANK_ENERGY || (o->certify && cert);
+    // the energy rule needs the sketch residual ||X - Q B||^2 before the rank
+    // is chosen (an estimate of the error, computed with the projection); the
+    // certificate is the error of the returned factors, computed after them
+    const bool resid = o->rank_mode == TSVDM_RANK_ENERGY;
+    const bool exact = o->certify && cert;
     const bool v4 = vec_loads_ok(Xd, m, p) && reinterpret_cast<uintptr_t>(w.Y) % 16 == 0;
     const double *gm_c = w.gram_m, *gp_c = w.gram_p;
 #define TSVDM_SKETCH()                                                                                      \
@@ -1305,7 +1437,7 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     TSVDM_LAUNCH("cholqr_final", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell, w.Qm,
                  2, gm_c, mparts, w.qr_info, power ? 0 : 1);
     // pass 4: B^T = X^T Q, FP32-accurate, the Gram partials of B^T and, for
-    // the certificate, ||X - Q B||^2 per 64-column block
+    // the energy rule, ||X - Q B||^2 per 64-column block
 #define TSVDM_PROJECT(NAME, RES, V, RP)                                                                    \
     TSVDM_LAUNCH(NAME, (k_xtw<LP, PROD_SPLIT, true, RES, V>), gp, dim3(GT), 0, s, Xd, m, p, nf,             \
                  (const float *)w.Qm, (int64_t)m * LP, m, ell, w.Z, w.gram_p, RP, fmap)
@@ -1320,11 +1452,35 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     const int msw = o->max_sweeps > 0 ? o->max_sweeps : 30;
     TSVDM_LAUNCH("core_gram_eig", (k_core<LP>), dim3(nf), dim3(QT), 0, s, gp_c, pparts, ell,
                  (const double *)w.fro_part, mparts, (const double *)w.res_part, resid ? pparts : 0,
-                 o->rank_mode, o->k, o->tau, msw, kJacobiTolMixed, w.UB, w.sig, w.perm, w.kf, w.fro2, cert, w.jinfo,
-                 fmap);
+                 o->rank_mode, o->k, o->tau, msw, kJacobiTolMixed, w.UB, w.sig, w.perm, w.kf, w.fro2,
+                 exact ? (double *)nullptr : cert, w.jinfo, fmap);
     TSVDM_LAUNCH("factors", (k_factors<LP>), dim3((unsigned)(mparts + pparts), nf), dim3(GT), 0, s,
                  (const float *)w.Qm, (const float *)w.Z, m, p, ell, kmax, w.UB, w.sig, w.perm, w.kf,
                  w.fro2, w.qr_info, w.jinfo, Uo, So, Vo, ranks, fro, info, fmap);
+    if (exact) {
+        // the certificate: ||Xhat_f - Uhat_f S_f Vhat_f^T||_F of the stored factors
+        // ranks are at most min(kmax, ell): the W staging is sized for that
+        const int kcap = (int)(kmax < ell ? kmax : ell);
+        const bool xv = m % 4 == 0 && reinterpret_cast<uintptr_t>(Xd) % 16 == 0;
+#define TSVDM_RESID(KP)                                                                                        \
+    do {                                                                                                      \
+        if (xv)                                                                                               \
+            TSVDM_LAUNCH("resid_factors", (k_resid<KP, true>), gm, dim3(GT), 0, s, Xd, m, p, nf,              \
+                         (const float *)Uo, (const double *)So, (const float *)Vo, kmax, (const int32_t *)ranks, \
+                         w.cert_part, fmap);                                                                  \
+        else                                                                                                  \
+            TSVDM_LAUNCH("resid_factors", (k_resid<KP, false>), gm, dim3(GT), 0, s, Xd, m, p, nf,             \
+                         (const float *)Uo, (const double *)So, (const float *)Vo, kmax, (const int32_t *)ranks, \
+                         w.cert_part, fmap);                                                                  \
+    } while (0)
+        if (kcap <= 16) TSVDM_RESID(16);
+        else if (kcap <= 32) TSVDM_RESID(32);
+        else if (kcap <= 48) TSVDM_RESID(48);
+        else TSVDM_RESID(64);
+#undef TSVDM_RESID
+        TSVDM_LAUNCH("cert", k_cert, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s,
+                     (const double *)w.cert_part, mparts, nf, cert, fmap);
+    }
     TSVDM_LAUNCH_CHECK("mixed truncate");
     return TSVDM_OK;
 }
