@@ -157,6 +157,73 @@ const char *tsvdm_last_error(void);
 tsvdm_status tsvdm_tensor_from_blockmat(const void *A, int64_t lda, int32_t dtype, int64_t ell,
                                         int64_t q, int64_t m, int64_t n, tsvdm_tensor *out);
 
+/* ---------------------------------------------------------------- structured placements
+ * Sec. 3 (block matrix to tensor mapping) for a block matrix A ((ell m) x
+ * (q n), ell x q blocks of m x n) whose blocks repeat: p distinct blocks A_k,
+ * block (i, j) of A equal to A_{k(i,j)}, or a zero block (k = -1).  E_k holds
+ * 1/sqrt(eta_k) at the eta_k positions of A_k (||E_k||_F = 1, eq. fnormw), and
+ *   T_E[A](:, k, :) = sqrt(eta_k) twist(A_k)            (X is m x p x n),
+ *   M_E[X] = sum_k E_k kron sq(X(:, k, :)),
+ * so block (i, j) of M_E[X] is X(:, k(i,j), :) / sqrt(eta_k).  The block map is
+ * an int32 HOST array block_of[i + ell j] (column major over the block grid,
+ * 0-based).  Step 1 of Algorithm alg:strategy (determine E and A) for the
+ * structures of the examples of Sec. 3: */
+enum {
+    TSVDM_PLACE_GENERIC = 0,       /* k = i + ell j, p = ell q (every block distinct)        */
+    TSVDM_PLACE_DIAGONAL = 1,      /* block-diagonal example: k = i on the diagonal, p = ell */
+    TSVDM_PLACE_BANDED = 2,        /* block-banded example, |i - j| <= b, every block in the
+                                      band distinct, numbered column by column              */
+    TSVDM_PLACE_BANDED_SYM = 3,    /* block-banded with (i, j) and (j, i) equal, numbered
+                                      column by column over i <= j (ell == q)                */
+    TSVDM_PLACE_TOEPLITZ = 4,      /* block-Toeplitz (example ex:btoep): k = i - j on the main
+                                      and lower diagonals, ell - 1 + (j - i) above, p = ell+q-1 */
+    TSVDM_PLACE_TOEPLITZ_SYM = 5,  /* block-Toeplitz with equal blocks on diagonals +-d:
+                                      k = |i - j|, p = max(ell, q)                           */
+    TSVDM_PLACE_HANKEL = 6         /* block-Hankel: k = i + j, p = ell + q - 1               */
+};
+
+/* Fills the host array block_of (ell*q entries) for `kind` (b: the block
+ * semibandwidth of the banded kinds, ignored otherwise) and *p. */
+tsvdm_status tsvdm_block_structure(int32_t kind, int64_t ell, int64_t q, int64_t b, int32_t *block_of,
+                                   int64_t *p);
+
+/* A placement: validation of block_of (entries in -1..p-1, every k occurring),
+ * eta_k, a representative block of each k (the first in row-major block
+ * order) and the weights sqrt(eta_k), 1/sqrt(eta_k) (IEEE double on the host),
+ * uploaded (synchronous copy) into the caller's device workspace of
+ * tsvdm_placement_workspace_size bytes, which must stay allocated while the
+ * placement is used.  *pl is a host object released with
+ * tsvdm_placement_destroy. */
+typedef struct tsvdm_placement_s tsvdm_placement;
+size_t tsvdm_placement_workspace_size(int64_t ell, int64_t q, int64_t p);
+tsvdm_status tsvdm_placement_create(int64_t ell, int64_t q, int64_t p, const int32_t *block_of, void *workspace,
+                                    size_t workspace_bytes, tsvdm_placement **pl);
+/* eta (host, p entries): the occurrence counts. */
+tsvdm_status tsvdm_placement_eta(const tsvdm_placement *pl, int32_t *eta);
+void tsvdm_placement_destroy(tsvdm_placement *pl);
+
+/* X = T_E[A]: A (device, column major, lda >= ell m) -> X (device, dense
+ * m x p x n), dtype F32 or F64 (the weight product in FP64, then rounded to
+ * the dtype).  Asynchronous on stream. */
+tsvdm_status tsvdm_tensor_from_blockmat_E(const tsvdm_placement *pl, const void *A, int64_t lda, int32_t dtype,
+                                          int64_t m, int64_t n, void *X, void *stream);
+
+/* A = M_E[X]: X (device, dense m x p x n) -> A (device, (ell m) x (q n),
+ * lda >= ell m; zero blocks written as zeros).  Asynchronous on stream. */
+tsvdm_status tsvdm_blockmat_from_tensor_E(const tsvdm_placement *pl, const void *X, int32_t dtype, int64_t m,
+                                          int64_t n, void *A, int64_t lda, void *stream);
+
+/* y = M_E[T] x for the structured placement (T = That x_3 M^{-1}, That_f =
+ * Uhat_f S_f Vhat_f^H from F, whose lateral size F->p is the placement's p):
+ * the factors of the generic placement, Vg_f(i + ell j, r) = Vhat_f(k(i,j), r)
+ * / sqrt(eta_k) (zero for zero blocks), are formed in the workspace and the
+ * generic tsvdm_apply runs on them (same arguments, precisions and limits). */
+size_t tsvdm_apply_E_workspace_size(const tsvdm_placement *pl, const tsvdm_mdesc *M, const tsvdm_factors *F,
+                                    int64_t nrhs, int32_t compute);
+tsvdm_status tsvdm_apply_E(const tsvdm_placement *pl, const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t nrhs,
+                           const void *x, int64_t ldx, void *y, int64_t ldy, int32_t compute, void *workspace,
+                           size_t workspace_bytes, void *stream);
+
 /* Host-side check that the n3 x n3 column-major HOST matrix M is orthogonal:
  * max |M^T M - I| <= tol.  Returns TSVDM_OK or TSVDM_EINVAL. */
 tsvdm_status tsvdm_check_orthogonal(const double *M_host, int64_t n3, double tol);

@@ -305,3 +305,69 @@ def apply(F: Factors, kind: int, n3: int, ell: int, q: int, x: torch.Tensor, ldx
     C.tsvdm_apply(md, desc, ell, q, nrhs, x.data_ptr(), ldx, y.data_ptr(), ell * F.m, compute,
                   ws.data_ptr(), need, _stream(stream))
     return y
+
+
+class Placement:
+    """A structured placement (Sec. 3): the block map of an ell x q block grid
+    with p distinct blocks (block_of[i + ell*j] = k or -1), its device table
+    in a torch-owned workspace, and the maps T_E, M_E and the structured apply
+    through the C interface."""
+
+    def __init__(self, ell: int, q: int, block_of, p: int | None = None, device="cuda"):
+        block_of = [int(v) for v in block_of]
+        self.ell, self.q = ell, q
+        self.p = p if p is not None else max(block_of) + 1
+        need = C.tsvdm_placement_workspace_size(ell, q, self.p)
+        self.ws = torch.empty(max(need, 1), dtype=torch.uint8, device=device)
+        self.handle = C.tsvdm_placement_create(ell, q, self.p, block_of, self.ws.data_ptr(), need)
+        self.block_of = block_of
+
+    @classmethod
+    def structure(cls, kind: int, ell: int, q: int, b: int = 0, device="cuda"):
+        block_of, p = C.tsvdm_block_structure(kind, ell, q, b)
+        return cls(ell, q, block_of, p, device)
+
+    def eta(self) -> list:
+        return C.tsvdm_placement_eta(self.handle, self.p)
+
+    def tensor_from_blockmat(self, A: torch.Tensor, m: int, n: int, lda: int | None = None,
+                             out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """X = T_E[A] (dense m x p x n) from the column-major block matrix A (flat)."""
+        lda = lda or self.ell * m
+        if out is None:
+            out = torch.empty(m * self.p * n, dtype=A.dtype, device=A.device)
+        C.tsvdm_tensor_from_blockmat_E(self.handle, A.data_ptr(), lda, dtype_code(A), m, n, out.data_ptr(),
+                                       _stream(stream))
+        return out
+
+    def blockmat_from_tensor(self, X: torch.Tensor, m: int, n: int, out: torch.Tensor | None = None,
+                             stream=None) -> torch.Tensor:
+        """A = M_E[X] ((ell m) x (q n), flat column major) from the dense m x p x n tensor X."""
+        if out is None:
+            out = torch.empty(self.ell * m * self.q * n, dtype=X.dtype, device=X.device)
+        C.tsvdm_blockmat_from_tensor_E(self.handle, X.data_ptr(), dtype_code(X), m, n, out.data_ptr(),
+                                       self.ell * m, _stream(stream))
+        return out
+
+    def apply(self, F: Factors, kind: int, n3: int, x: torch.Tensor, compute: int | None = None,
+              M: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        """y = M_E[T] x for the factors F of the structured tensor (F.p == p)."""
+        if compute is None:
+            compute = C.F64 if F.U.dtype in (torch.float64, torch.complex128) else C.F32
+        rdt = torch.float64 if compute == C.F64 else torch.float32
+        ldx = self.q * n3
+        nrhs = x.numel() // ldx
+        md = _mdesc(kind, n3, M)
+        desc = F.desc()
+        need = C.tsvdm_apply_E_workspace_size(self.handle, md, desc, nrhs, compute)
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+        y = torch.empty(self.ell * F.m * nrhs, dtype=rdt, device=x.device)
+        C.tsvdm_apply_E(self.handle, md, desc, nrhs, x.data_ptr(), ldx, y.data_ptr(), self.ell * F.m, compute,
+                        ws.data_ptr(), need, _stream(stream))
+        return y
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            C.tsvdm_placement_destroy(h)
+            self.handle = None

@@ -20,6 +20,8 @@ F64, F32, BF16, C64, C128 = 0, 1, 2, 3, 4
 M_DCT2, M_DFT, M_DENSE = 0, 1, 2
 RANK_FIXED, RANK_ENERGY = 0, 1
 PREC_F64, PREC_MIXED = 0, 1
+(PLACE_GENERIC, PLACE_DIAGONAL, PLACE_BANDED, PLACE_BANDED_SYM, PLACE_TOEPLITZ, PLACE_TOEPLITZ_SYM,
+ PLACE_HANKEL) = range(7)
 
 
 class TsvdmMdesc(ctypes.Structure):
@@ -61,7 +63,10 @@ EXPORTS = ["tsvdm_version", "tsvdm_last_error", "tsvdm_tensor_from_blockmat",
            "tsvdm_rank_features", "tsvdm_truncate_learned_workspace_size", "tsvdm_truncate_learned",
            "tsvdm_transform_batched_workspace_size", "tsvdm_transform_plan_create",
            "tsvdm_transform_batched", "tsvdm_transform_plan_destroy", "tsvdm_truncate_noalloc",
-           "tsvdm_noalloc_scratch_bytes"]
+           "tsvdm_noalloc_scratch_bytes", "tsvdm_block_structure", "tsvdm_placement_workspace_size",
+           "tsvdm_placement_create", "tsvdm_placement_eta", "tsvdm_placement_destroy",
+           "tsvdm_tensor_from_blockmat_E", "tsvdm_blockmat_from_tensor_E", "tsvdm_apply_E_workspace_size",
+           "tsvdm_apply_E"]
 
 _LIB = None
 
@@ -104,6 +109,24 @@ def lib():
         L.tsvdm_truncate_noalloc.restype = i32
         L.tsvdm_noalloc_scratch_bytes.argtypes = []
         L.tsvdm_noalloc_scratch_bytes.restype = sz
+        L.tsvdm_block_structure.argtypes = [i32, i64, i64, i64, vp, P(i64)]
+        L.tsvdm_block_structure.restype = i32
+        L.tsvdm_placement_workspace_size.argtypes = [i64, i64, i64]
+        L.tsvdm_placement_workspace_size.restype = sz
+        L.tsvdm_placement_create.argtypes = [i64, i64, i64, vp, vp, sz, P(vp)]
+        L.tsvdm_placement_create.restype = i32
+        L.tsvdm_placement_eta.argtypes = [vp, vp]
+        L.tsvdm_placement_eta.restype = i32
+        L.tsvdm_placement_destroy.argtypes = [vp]
+        L.tsvdm_placement_destroy.restype = None
+        L.tsvdm_tensor_from_blockmat_E.argtypes = [vp, vp, i64, i32, i64, i64, vp, vp]
+        L.tsvdm_tensor_from_blockmat_E.restype = i32
+        L.tsvdm_blockmat_from_tensor_E.argtypes = [vp, vp, i32, i64, i64, vp, i64, vp]
+        L.tsvdm_blockmat_from_tensor_E.restype = i32
+        L.tsvdm_apply_E_workspace_size.argtypes = [vp, P(TsvdmMdesc), P(TsvdmFactors), i64, i32]
+        L.tsvdm_apply_E_workspace_size.restype = sz
+        L.tsvdm_apply_E.argtypes = [vp, P(TsvdmMdesc), P(TsvdmFactors), i64, vp, i64, vp, i64, i32, vp, sz, vp]
+        L.tsvdm_apply_E.restype = i32
         L.tsvdm_apply_workspace_size.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, i32]
         L.tsvdm_apply.restype = i32
         L.tsvdm_apply.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, vp, i64, vp, i64,
@@ -208,6 +231,55 @@ def tsvdm_truncate_noalloc(X: TsvdmTensor, opts: TsvdmTruncateOpts, F: TsvdmFact
 
 def tsvdm_noalloc_scratch_bytes() -> int:
     return lib().tsvdm_noalloc_scratch_bytes()
+
+
+def tsvdm_block_structure(kind: int, ell: int, q: int, b: int = 0):
+    """(block_of as a list of ell*q ints, column major over the block grid; p)."""
+    arr = (ctypes.c_int32 * (ell * q))()
+    p = ctypes.c_int64(0)
+    _check(lib().tsvdm_block_structure(kind, ell, q, b, arr, ctypes.byref(p)))
+    return list(arr), p.value
+
+
+def tsvdm_placement_workspace_size(ell: int, q: int, p: int) -> int:
+    return lib().tsvdm_placement_workspace_size(ell, q, p)
+
+
+def tsvdm_placement_create(ell: int, q: int, p: int, block_of, ws_ptr: int, ws_bytes: int) -> int:
+    arr = (ctypes.c_int32 * (ell * q))(*block_of)
+    h = ctypes.c_void_p(0)
+    _check(lib().tsvdm_placement_create(ell, q, p, arr, ws_ptr, ws_bytes, ctypes.byref(h)))
+    return h.value
+
+
+def tsvdm_placement_eta(pl: int, p: int) -> list:
+    arr = (ctypes.c_int32 * p)()
+    _check(lib().tsvdm_placement_eta(pl, arr))
+    return list(arr)
+
+
+def tsvdm_placement_destroy(pl: int):
+    lib().tsvdm_placement_destroy(pl)
+
+
+def tsvdm_tensor_from_blockmat_E(pl: int, A_ptr: int, lda: int, dtype: int, m: int, n: int, X_ptr: int,
+                                 stream: int = 0):
+    _check(lib().tsvdm_tensor_from_blockmat_E(pl, A_ptr, lda, dtype, m, n, X_ptr, stream))
+
+
+def tsvdm_blockmat_from_tensor_E(pl: int, X_ptr: int, dtype: int, m: int, n: int, A_ptr: int, lda: int,
+                                 stream: int = 0):
+    _check(lib().tsvdm_blockmat_from_tensor_E(pl, X_ptr, dtype, m, n, A_ptr, lda, stream))
+
+
+def tsvdm_apply_E_workspace_size(pl: int, M: TsvdmMdesc, F: TsvdmFactors, nrhs: int, compute: int) -> int:
+    return lib().tsvdm_apply_E_workspace_size(pl, ctypes.byref(M), ctypes.byref(F), nrhs, compute)
+
+
+def tsvdm_apply_E(pl: int, M: TsvdmMdesc, F: TsvdmFactors, nrhs: int, x_ptr: int, ldx: int, y_ptr: int,
+                  ldy: int, compute: int, ws_ptr: int, ws_bytes: int, stream: int = 0):
+    _check(lib().tsvdm_apply_E(pl, ctypes.byref(M), ctypes.byref(F), nrhs, x_ptr, ldx, y_ptr, ldy, compute,
+                               ws_ptr, ws_bytes, stream))
 
 
 def tsvdm_apply_workspace_size(M: TsvdmMdesc, F: TsvdmFactors, ell: int, q: int, nrhs: int,

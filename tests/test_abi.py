@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "tsvdm.h")
 def _declared_functions():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(tsvdm_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(tsvdm_[A-Za-z0-9_]+)\s*\(", text)))
 
 
 def test_library_loads_and_exports_every_declared_symbol():
@@ -263,3 +263,78 @@ def test_transform_batched_validation_and_workspace():
 def test_batched_set_config_rejects_null_plan():
     arr = (ctypes.c_int32 * 4)(2, 16, 2, 0)
     assert C.lib().tsvdm_batched_set_config(None, arr) == C.EINVAL
+
+
+# ------------------------------------------------------------ Sec. 3 placements (host code)
+def _occurrences(block_of, ell, q):
+    occ = {}
+    for j in range(q):
+        for i in range(ell):
+            k = block_of[i + ell * j]
+            if k >= 0:
+                occ.setdefault(k, []).append((i, j))
+    return occ
+
+
+def test_block_structure_paper_block_tridiagonal_example():
+    """BANDED_SYM with b = 1 on 4 x 4 blocks is the block-tridiagonal display of
+    Sec. 3 (tests/golden/block_tridiagonal_4x4.txt): p = 7 and the same
+    occurrences of every distinct block."""
+    block_of, p = C.tsvdm_block_structure(C.PLACE_BANDED_SYM, 4, 4, 1)
+    assert p == 7
+    rows = np.loadtxt(os.path.join(ROOT, "tests", "golden", "block_tridiagonal_4x4.txt"), dtype=int)
+    want = {}
+    for k, i, j in rows:
+        want.setdefault(k - 1, set()).add((i - 1, j - 1))
+    got = {k: set(v) for k, v in _occurrences(block_of, 4, 4).items()}
+    assert got == want
+
+
+@pytest.mark.parametrize("ell,b", [(4, 1), (7, 1), (7, 2), (9, 3)])
+def test_block_structure_banded_counts_match_the_paper(ell, b):
+    """Sec. 3 block-banded example: p = l(2b+1) - b(b+1) distinct blocks when
+    block-non-symmetric, p = l(b+1) - b(b+1)/2 when block-symmetric (l = ell
+    blocks per side, b the block semibandwidth); for b = 1 these are 3l - 2 and
+    2l - 1.  Every block in the band is covered, none outside."""
+    bo, p = C.tsvdm_block_structure(C.PLACE_BANDED, ell, ell, b)
+    assert p == ell * (2 * b + 1) - b * (b + 1)
+    bs, ps = C.tsvdm_block_structure(C.PLACE_BANDED_SYM, ell, ell, b)
+    assert ps == ell * (b + 1) - b * (b + 1) // 2
+    if b == 1:
+        assert (p, ps) == (3 * ell - 2, 2 * ell - 1)
+    for j in range(ell):
+        for i in range(ell):
+            inside = abs(i - j) <= b
+            assert (bo[i + ell * j] >= 0) == inside and (bs[i + ell * j] >= 0) == inside
+    assert sorted(set(v for v in bo if v >= 0)) == list(range(p))
+    # block-non-symmetric: every block in the band distinct; symmetric: (i, j) ~ (j, i)
+    assert all(len(v) == 1 for v in _occurrences(bo, ell, ell).values())
+    for j in range(ell):
+        for i in range(ell):
+            assert bs[i + ell * j] == bs[j + ell * i]
+
+
+def test_block_structure_toeplitz_hankel_diagonal():
+    """ex:btoep: 2l - 1 distinct blocks, the d-th lower diagonal repeated l - d
+    times (weights 1/sqrt(l - d)); Hankel: constant anti-diagonals; the
+    block-diagonal example: p = l; generic: p = l q, b = i + l j."""
+    ell = 5
+    bt, p = C.tsvdm_block_structure(C.PLACE_TOEPLITZ, ell, ell)
+    assert p == 2 * ell - 1
+    occ = _occurrences(bt, ell, ell)
+    for d in range(ell):
+        assert sorted(occ[d]) == sorted((i, i - d) for i in range(d, ell))
+    for d in range(1, ell):
+        assert sorted(occ[ell - 1 + d]) == sorted((i, i + d) for i in range(ell - d))
+    bh, ph = C.tsvdm_block_structure(C.PLACE_HANKEL, 3, 4)
+    assert ph == 6 and all(bh[i + 3 * j] == i + j for i in range(3) for j in range(4))
+    bd, pd = C.tsvdm_block_structure(C.PLACE_DIAGONAL, 4, 4)
+    assert pd == 4 and bd == [0, -1, -1, -1, -1, 1, -1, -1, -1, -1, 2, -1, -1, -1, -1, 3]
+    bg, pg = C.tsvdm_block_structure(C.PLACE_GENERIC, 3, 2)
+    assert pg == 6 and bg == list(range(6))
+    bts, pts = C.tsvdm_block_structure(C.PLACE_TOEPLITZ_SYM, 4, 3)
+    assert pts == 4 and all(bts[i + 4 * j] == abs(i - j) for i in range(4) for j in range(3))
+    with pytest.raises(C.TsvdmError):
+        C.tsvdm_block_structure(C.PLACE_DIAGONAL, 3, 4)
+    with pytest.raises(C.TsvdmError):
+        C.tsvdm_block_structure(99, 3, 4)
