@@ -490,3 +490,99 @@ def expand_hermitian(Uh: np.ndarray, s: np.ndarray, Vh: np.ndarray, ranks: np.nd
         S[:, f] = s[:, g]
         R[f] = ranks[g]
     return U, S, V, R
+
+
+# --------------------------------------------------------------------------
+# Unfoldings, mode products and HOSVD factors (Sec. 2.1, Sec. 2.4); the
+# mode-2 compression of Sec. 6.3
+# --------------------------------------------------------------------------
+def unfold(X: np.ndarray, mode: int) -> np.ndarray:
+    """The mode-i unfolding of Sec. 2.1 for a (m, p, n) tensor:
+    mode 1: [X_1, X_2, .., X_n] (m x pn, X_t the frontal slices);
+    mode 2: [X_1^T, X_2^T, .., X_n^T] (p x mn);
+    mode 3: [sq(X_{:,1,:})^T, .., sq(X_{:,p,:})^T] (n x mp, eq. mode3unfold)."""
+    m, p, n = X.shape
+    if mode == 1:
+        return np.hstack([X[:, :, t] for t in range(n)])
+    if mode == 2:
+        return np.hstack([X[:, :, t].T for t in range(n)])
+    if mode == 3:
+        return np.hstack([X[:, b, :].T for b in range(p)])
+    raise ValueError("mode must be 1, 2 or 3")
+
+
+def fold(Am: np.ndarray, mode: int, shape) -> np.ndarray:
+    """Inverse of unfold for a tensor of the given shape (m, p, n)."""
+    m, p, n = shape
+    X = np.zeros(shape, dtype=Am.dtype, order="F")
+    if mode == 1:
+        for t in range(n):
+            X[:, :, t] = Am[:, t * p:(t + 1) * p]
+    elif mode == 2:
+        for t in range(n):
+            X[:, :, t] = Am[:, t * m:(t + 1) * m].T
+    elif mode == 3:
+        for b in range(p):
+            X[:, b, :] = Am[:, b * m:(b + 1) * m].T
+    else:
+        raise ValueError("mode must be 1, 2 or 3")
+    return X
+
+
+def mode_product(X: np.ndarray, U: np.ndarray, mode: int) -> np.ndarray:
+    """X x_i U = fold(U X_(i)) (Sec. 2.1 definition of the mode-i product)."""
+    shape = list(X.shape)
+    shape[mode - 1] = U.shape[0]
+    return fold(U @ unfold(X, mode), mode, tuple(shape))
+
+
+def sign_fix(W: np.ndarray) -> np.ndarray:
+    """Columns of W with their largest-magnitude entry made positive (the
+    first such entry on ties): a deterministic choice among the sign-equivalent
+    singular vectors."""
+    W = np.array(W, dtype=np.float64, copy=True)
+    for j in range(W.shape[1]):
+        i = int(np.argmax(np.abs(W[:, j])))
+        if W[i, j] < 0:
+            W[:, j] = -W[:, j]
+    return W
+
+
+def hosvd_factor(X: np.ndarray, mode: int, r: int | None = None):
+    """HOSVD factor of one mode (Sec. 2.4): the leading r left singular
+    vectors of the mode unfolding (library SVD), sign-fixed, and all the
+    singular values of the unfolding."""
+    Um, s, _ = np.linalg.svd(unfold(X, mode), full_matrices=False)
+    r = Um.shape[1] if r is None else r
+    return sign_fix(Um[:, :r]), s
+
+
+def mode3_transform_matrix(X: np.ndarray) -> np.ndarray:
+    """The data-driven orthogonal transform M = W^T, W the full mode-3 HOSVD
+    factor of X (n x n): X x_3 M is the mode-3 core of the HOSVD, and face f of
+    it carries the energy s_f^2 of the unfolding."""
+    W, _ = hosvd_factor(X, 3)
+    assert W.shape[0] == W.shape[1], "needs n <= m p"
+    return W.T
+
+
+def mode2_compress(X: np.ndarray, r: int):
+    """The mode-2 compression of Sec. 6.3: V the leading r left singular
+    vectors of X_(2) (p x r), core G = X x_2 V^T (m x r x n) and the
+    approximation T = G x_2 V; the error ||X - T||_F equals the root of the
+    discarded squared singular values of X_(2) (Eckart-Young on the
+    unfolding, V having orthonormal columns)."""
+    V, s = hosvd_factor(X, 2, r)
+    G = mode_product(X, V.T, 2)
+    T = mode_product(G, V, 2)
+    return dict(V=V, G=G, T=T, s=s)
+
+
+def kron_terms_mode2(V: np.ndarray, G: np.ndarray, E):
+    """Kronecker terms of the mode-2 compressed tensor (Sec. 6.3, Thm
+    thm:tuckerkron with U = I, W = I): C_j = struct(v_{kj})_{k=1..p}
+    (l x q) and D_j = sq(G_{:,j,:}) (m x n), so M_E[G x_2 V] = sum_j C_j kron D_j."""
+    r = V.shape[1]
+    C = [struct_kron(E, [np.array([[V[k, j]]]) for k in range(V.shape[0])]) for j in range(r)]
+    D = [G[:, j, :] for j in range(r)]
+    return C, D
