@@ -224,6 +224,41 @@ tsvdm_status tsvdm_apply_E(const tsvdm_placement *pl, const tsvdm_mdesc *M, cons
                            const void *x, int64_t ldx, void *y, int64_t ldy, int32_t compute, void *workspace,
                            size_t workspace_bytes, void *stream);
 
+/* ---------------------------------------------------------------- data-driven transforms
+ * Unfoldings of Sec. 2.1 for a dense real tensor X (m x p x n3, F32 or F64):
+ * X_(3) (n3 x mp, row t = frontal face t, eq. mode3unfold) and X_(2) (p x mn,
+ * row b = lateral slice b).  FP64 results throughout. */
+
+/* G = X_(mode) X_(mode)^T for mode 3 (n3 x n3: inner products of the frontal
+ * faces) or mode 2 (p x p: sum over faces of X_t^T X_t), order at most 64;
+ * G device, column major.  Fixed workgroup count, partials summed in order
+ * (deterministic).  Asynchronous on stream. */
+size_t tsvdm_mode_gram_workspace_size(const tsvdm_tensor *X, int32_t mode);
+tsvdm_status tsvdm_mode_gram(const tsvdm_tensor *X, int32_t mode, double *G, void *workspace, size_t workspace_bytes,
+                             void *stream);
+
+/* Eigendecomposition of a symmetric N x N FP64 matrix G (device, column major,
+ * N <= 64) by the cyclic Jacobi solver in one workgroup: lam (N, device)
+ * decreasing, W (N x N, device, column major) the eigenvectors, each with its
+ * largest-magnitude entry positive (the first such entry on ties). */
+tsvdm_status tsvdm_sym_eig(const double *G, int64_t N, double *lam, double *W, void *stream);
+
+/* The mode-3 HOSVD factor (Sec. 2.4) as the transform: with W the left singular
+ * vectors of X_(3) (eigenvectors of the mode-3 Gram, sign-fixed as above), M =
+ * W^T (n3 x n3, device, column major, FP64) for TSVDM_M_DENSE, so that face f
+ * of X x_3 M carries the energy sv[f]^2 of the unfolding; sv (n3, device, may
+ * be NULL): the singular values of X_(3), decreasing.  n3 <= 64. */
+size_t tsvdm_mode3_transform_workspace_size(const tsvdm_tensor *X);
+tsvdm_status tsvdm_mode3_transform(const tsvdm_tensor *X, double *M, double *sv, void *workspace,
+                                   size_t workspace_bytes, void *stream);
+
+/* Mode-2 products of Sec. 6.3 with V (pv x r, device, column major, FP64):
+ * direction +1: out = X x_2 V^T (X m x pv x n3 -> out m x r x n3, the core G);
+ * direction -1: out = X x_2 V   (X m x r x n3 -> out m x pv x n3, T = G x_2 V).
+ * out dense with X's dtype; FP64 accumulation.  Asynchronous on stream. */
+tsvdm_status tsvdm_mode2_product(const tsvdm_tensor *X, const double *V, int64_t pv, int64_t r, int32_t direction,
+                                 void *out, void *stream);
+
 /* Host-side check that the n3 x n3 column-major HOST matrix M is orthogonal:
  * max |M^T M - I| <= tol.  Returns TSVDM_OK or TSVDM_EINVAL. */
 tsvdm_status tsvdm_check_orthogonal(const double *M_host, int64_t n3, double tol);

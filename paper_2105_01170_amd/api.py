@@ -371,3 +371,43 @@ class Placement:
         if h:
             C.tsvdm_placement_destroy(h)
             self.handle = None
+
+
+def mode_gram(x: torch.Tensor, m: int, p: int, n3: int, mode: int, stream=None) -> torch.Tensor:
+    """G = X_(mode) X_(mode)^T (FP64, column major flat) of the dense tensor x."""
+    X = C.dense_tensor(x.data_ptr(), m, p, n3, dtype_code(x))
+    N = n3 if mode == 3 else p
+    need = C.tsvdm_mode_gram_workspace_size(X, mode)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    G = torch.empty(N * N, dtype=torch.float64, device=x.device)
+    C.tsvdm_mode_gram(X, mode, G.data_ptr(), ws.data_ptr(), need, _stream(stream))
+    return G
+
+
+def sym_eig(G: torch.Tensor, N: int, stream=None):
+    """(lam decreasing, W column major flat) of the symmetric N x N FP64 matrix G."""
+    lam = torch.empty(N, dtype=torch.float64, device=G.device)
+    W = torch.empty(N * N, dtype=torch.float64, device=G.device)
+    C.tsvdm_sym_eig(G.data_ptr(), N, lam.data_ptr(), W.data_ptr(), _stream(stream))
+    return lam, W
+
+
+def mode3_transform(x: torch.Tensor, m: int, p: int, n3: int, stream=None):
+    """(M = W^T, the singular values of X_(3)): the mode-3 HOSVD factor as a dense transform."""
+    X = C.dense_tensor(x.data_ptr(), m, p, n3, dtype_code(x))
+    need = C.tsvdm_mode3_transform_workspace_size(X)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    M = torch.empty(n3 * n3, dtype=torch.float64, device=x.device)
+    sv = torch.empty(n3, dtype=torch.float64, device=x.device)
+    C.tsvdm_mode3_transform(X, M.data_ptr(), sv.data_ptr(), ws.data_ptr(), need, _stream(stream))
+    return M, sv
+
+
+def mode2_product(x: torch.Tensor, m: int, p: int, n3: int, V: torch.Tensor, pv: int, r: int, direction: int,
+                  stream=None) -> torch.Tensor:
+    """x (m x p x n3) x_2 V^T (direction +1, p == pv) or x_2 V (direction -1, p == r)."""
+    X = C.dense_tensor(x.data_ptr(), m, p, n3, dtype_code(x))
+    pout = r if direction == 1 else pv
+    out = torch.empty(m * pout * n3, dtype=x.dtype, device=x.device)
+    C.tsvdm_mode2_product(X, V.data_ptr(), pv, r, direction, out.data_ptr(), _stream(stream))
+    return out

@@ -66,7 +66,8 @@ EXPORTS = ["tsvdm_version", "tsvdm_last_error", "tsvdm_tensor_from_blockmat",
            "tsvdm_noalloc_scratch_bytes", "tsvdm_block_structure", "tsvdm_placement_workspace_size",
            "tsvdm_placement_create", "tsvdm_placement_eta", "tsvdm_placement_destroy",
            "tsvdm_tensor_from_blockmat_E", "tsvdm_blockmat_from_tensor_E", "tsvdm_apply_E_workspace_size",
-           "tsvdm_apply_E"]
+           "tsvdm_apply_E", "tsvdm_mode_gram_workspace_size", "tsvdm_mode_gram", "tsvdm_sym_eig",
+           "tsvdm_mode3_transform_workspace_size", "tsvdm_mode3_transform", "tsvdm_mode2_product"]
 
 _LIB = None
 
@@ -127,6 +128,18 @@ def lib():
         L.tsvdm_apply_E_workspace_size.restype = sz
         L.tsvdm_apply_E.argtypes = [vp, P(TsvdmMdesc), P(TsvdmFactors), i64, vp, i64, vp, i64, i32, vp, sz, vp]
         L.tsvdm_apply_E.restype = i32
+        L.tsvdm_mode_gram_workspace_size.argtypes = [P(TsvdmTensor), i32]
+        L.tsvdm_mode_gram_workspace_size.restype = sz
+        L.tsvdm_mode_gram.argtypes = [P(TsvdmTensor), i32, vp, vp, sz, vp]
+        L.tsvdm_mode_gram.restype = i32
+        L.tsvdm_sym_eig.argtypes = [vp, i64, vp, vp, vp]
+        L.tsvdm_sym_eig.restype = i32
+        L.tsvdm_mode3_transform_workspace_size.argtypes = [P(TsvdmTensor)]
+        L.tsvdm_mode3_transform_workspace_size.restype = sz
+        L.tsvdm_mode3_transform.argtypes = [P(TsvdmTensor), vp, vp, vp, sz, vp]
+        L.tsvdm_mode3_transform.restype = i32
+        L.tsvdm_mode2_product.argtypes = [P(TsvdmTensor), vp, i64, i64, i32, vp, vp]
+        L.tsvdm_mode2_product.restype = i32
         L.tsvdm_apply_workspace_size.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, i32]
         L.tsvdm_apply.restype = i32
         L.tsvdm_apply.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, vp, i64, vp, i64,
@@ -280,6 +293,31 @@ def tsvdm_apply_E(pl: int, M: TsvdmMdesc, F: TsvdmFactors, nrhs: int, x_ptr: int
                   ldy: int, compute: int, ws_ptr: int, ws_bytes: int, stream: int = 0):
     _check(lib().tsvdm_apply_E(pl, ctypes.byref(M), ctypes.byref(F), nrhs, x_ptr, ldx, y_ptr, ldy, compute,
                                ws_ptr, ws_bytes, stream))
+
+
+def tsvdm_mode_gram_workspace_size(X: TsvdmTensor, mode: int) -> int:
+    return lib().tsvdm_mode_gram_workspace_size(ctypes.byref(X), mode)
+
+
+def tsvdm_mode_gram(X: TsvdmTensor, mode: int, G_ptr: int, ws_ptr: int, ws_bytes: int, stream: int = 0):
+    _check(lib().tsvdm_mode_gram(ctypes.byref(X), mode, G_ptr, ws_ptr, ws_bytes, stream))
+
+
+def tsvdm_sym_eig(G_ptr: int, N: int, lam_ptr: int, W_ptr: int, stream: int = 0):
+    _check(lib().tsvdm_sym_eig(G_ptr, N, lam_ptr, W_ptr, stream))
+
+
+def tsvdm_mode3_transform_workspace_size(X: TsvdmTensor) -> int:
+    return lib().tsvdm_mode3_transform_workspace_size(ctypes.byref(X))
+
+
+def tsvdm_mode3_transform(X: TsvdmTensor, M_ptr: int, sv_ptr: int, ws_ptr: int, ws_bytes: int, stream: int = 0):
+    _check(lib().tsvdm_mode3_transform(ctypes.byref(X), M_ptr, sv_ptr, ws_ptr, ws_bytes, stream))
+
+
+def tsvdm_mode2_product(X: TsvdmTensor, V_ptr: int, pv: int, r: int, direction: int, out_ptr: int,
+                        stream: int = 0):
+    _check(lib().tsvdm_mode2_product(ctypes.byref(X), V_ptr, pv, r, direction, out_ptr, stream))
 
 
 def tsvdm_apply_workspace_size(M: TsvdmMdesc, F: TsvdmFactors, ell: int, q: int, nrhs: int,
