@@ -586,3 +586,21 @@ def kron_terms_mode2(V: np.ndarray, G: np.ndarray, E):
     C = [struct_kron(E, [np.array([[V[k, j]]]) for k in range(V.shape[0])]) for j in range(r)]
     D = [G[:, j, :] for j in range(r)]
     return C, D
+
+
+def kron_terms_tsvdm(U: np.ndarray, s: np.ndarray, V: np.ndarray, ranks: np.ndarray, M: np.ndarray, E):
+    """Kronecker terms of the truncated t-SVDM (the analogue of Thm
+    thm:tuckerkron for the t-SVDM; derived): with T = That x_3 M^{-1} and That_f
+    = sum_r s_fr U_f[:, r] V_f[:, r]^H, lateral slice b of T is
+        sq(T_{:, b, :}) = sum_{f, r} conj(V_f[b, r]) s_fr U_f[:, r] (M^{-1}[:, f])^T,
+    so M_E[T] = sum_{f, r} struct(conj V_f[:, r]) kron D_fr with
+    D_fr = s_fr U_f[:, r] (M^{-1}[:, f])^T (a rank-one m x n matrix) and
+    struct(v) = sum_b E_b v_b (Sec. 3, eq. kronsum).  Factors of all n faces
+    (full spectrum); returns the lists C, D."""
+    Minv = m_inverse(M)
+    C, D = [], []
+    for f in range(U.shape[2]):
+        for r in range(int(ranks[f])):
+            C.append(struct_kron(E, [np.array([[np.conj(V[b, r, f])]]) for b in range(V.shape[0])]))
+            D.append(s[r, f] * np.outer(U[:, r, f], Minv[:, f]))
+    return C, D

@@ -109,3 +109,35 @@ def test_mode2_compression_error_and_kronecker_terms():
     # full mode-2 rank: exact
     full = oracle.mode2_compress(X, p)
     np.testing.assert_allclose(full["T"], X, atol=1e-12)
+
+
+@pytest.mark.parametrize("kind", ["dct", "dft"])
+def test_kronecker_terms_of_the_tsvdm(kind):
+    """M_E[T] of a truncated t-SVDM equals the sum of the Kronecker terms
+    struct(conj v_fr) kron s_fr u_fr (M^{-1}[:, f])^T (generic placement and a
+    block-Toeplitz placement); each D_fr has rank one."""
+    ell, q, m, n, k = 3, 3, 4, 6, 2
+    M = oracle.dct2_matrix(n) if kind == "dct" else oracle.dft_matrix(n)
+    Ed = np.diag(np.ones(ell - 1), -1)
+    toep = [np.linalg.matrix_power(Ed, j) / np.sqrt(ell - j) for j in range(ell)] + \
+        [np.linalg.matrix_power(Ed.T, j) / np.sqrt(ell - j) for j in range(1, ell)]
+    for E in (oracle.placement_generic(ell, q), toep):
+        p = len(E)
+        X = _rand((m, p, n), 11 + p)
+        res = oracle.tsvdm(X, M, "fixed", k)
+        Uf, sf, Vf = [], [], []
+        for f in range(n):
+            u, sv, vh = np.linalg.svd(res["Xh"][:, :, f], full_matrices=False)
+            Uf.append(u[:, :k])
+            sf.append(sv[:k])
+            Vf.append(np.conj(vh[:k]).T)
+        U, s, V = np.stack(Uf, 2), np.stack(sf, 1), np.stack(Vf, 2)
+        C, D = oracle.kron_terms_tsvdm(U, s, V, np.full(n, k), M, E)
+        assert len(C) == n * k
+        total = sum(np.kron(Cj, Dj) for Cj, Dj in zip(C, D))
+        want = oracle.blockmat_from_tensor_E(res["T"], E)
+        np.testing.assert_allclose(total, want, atol=1e-12)
+        if kind == "dft":
+            assert np.max(np.abs(np.imag(total))) < 1e-12
+        for Dj in D:
+            assert np.linalg.matrix_rank(Dj, tol=1e-12 * max(np.abs(Dj).max(), 1e-300)) <= 1
