@@ -259,6 +259,31 @@ tsvdm_status tsvdm_mode3_transform(const tsvdm_tensor *X, double *M, double *sv,
 tsvdm_status tsvdm_mode2_product(const tsvdm_tensor *X, const double *V, int64_t pv, int64_t r, int32_t direction,
                                  void *out, void *stream);
 
+/* ---------------------------------------------------------------- the t-SVDM as a Kronecker sum and an operator
+ * Kronecker terms of the truncated t-SVDM (the t-SVDM analogue of Thm
+ * thm:tuckerkron; derived from T = That x_3 M^{-1}): M_E[T] = sum_j C_j kron D_j,
+ *   C_j = struct(conj v_fr) = sum_b E_b conj(Vhat_f[b, r])   (ell x q; it keeps the
+ *         block structure of the placement),
+ *   D_j = S_f[r] Uhat_f[:, r] (M^{-1}[:, f])^T               (m x n3, rank one).
+ * Real M: term j = f kmax + r.  DFT (stored half spectrum): each stored complex
+ * triplet gives two real terms, 2 (f kmax + r) + {0, 1}: (Re C, w_f Re D) and
+ * (Im C, -w_f Im D), w_f = 2 except faces 0 and n3/2, whose sum over the stored
+ * faces is the real M_E[T] (Re D and Im D have rank at most two).  Terms with r >= ranks[f] are zero.  C (device):
+ * ell*q*nterms, D (device): m*n3*nterms, column major, the factors' real type.
+ * pl = NULL: the generic placement with ell*q = F->p.  Asynchronous. */
+int64_t tsvdm_kron_terms_count(const tsvdm_mdesc *M, const tsvdm_factors *F);
+tsvdm_status tsvdm_kron_terms(const tsvdm_mdesc *M, const tsvdm_factors *F, const tsvdm_placement *pl, int64_t ell,
+                              int64_t q, void *C, void *D, void *stream);
+
+/* The truncated t-SVDM as an M-product operator: Y = T *_M X for X (p x s x n3,
+ * original domain, real, the factors' precision, any view tsvdm_transform
+ * accepts), Y (m x s x n3, dense): Xhat = X x_3 M, Yhat_f = Uhat_f diag(S_f)
+ * Vhat_f^H Xhat_f on every stored face, Y = Yhat x_3 M^{-1} (the product is
+ * facewise in the transform domain).  kmax <= 64.  Asynchronous. */
+size_t tsvdm_mprod_workspace_size(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t s);
+tsvdm_status tsvdm_mprod(const tsvdm_mdesc *M, const tsvdm_factors *F, const tsvdm_tensor *X, tsvdm_tensor *Y,
+                         void *workspace, size_t workspace_bytes, void *stream);
+
 /* Host-side check that the n3 x n3 column-major HOST matrix M is orthogonal:
  * max |M^T M - I| <= tol.  Returns TSVDM_OK or TSVDM_EINVAL. */
 tsvdm_status tsvdm_check_orthogonal(const double *M_host, int64_t n3, double tol);

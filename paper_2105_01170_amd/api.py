@@ -411,3 +411,34 @@ def mode2_product(x: torch.Tensor, m: int, p: int, n3: int, V: torch.Tensor, pv:
     out = torch.empty(m * pout * n3, dtype=x.dtype, device=x.device)
     C.tsvdm_mode2_product(X, V.data_ptr(), pv, r, direction, out.data_ptr(), _stream(stream))
     return out
+
+
+def kron_terms(F: Factors, kind: int, n3: int, ell: int = 0, q: int = 0, placement: Placement | None = None,
+               M: torch.Tensor | None = None, stream=None):
+    """(C, D, nterms): the Kronecker terms of the truncated t-SVDM, C flat
+    (ell*q*nterms), D flat (m*n3*nterms), column major per term."""
+    md = _mdesc(kind, n3, M)
+    desc = F.desc()
+    nt = C.tsvdm_kron_terms_count(md, desc)
+    if placement is not None:
+        ell, q = placement.ell, placement.q
+    rdt = torch.float64 if F.U.dtype in (torch.float64, torch.complex128) else torch.float32
+    Cout = torch.empty(max(ell * q * nt, 1), dtype=rdt, device=F.U.device)
+    Dout = torch.empty(max(F.m * n3 * nt, 1), dtype=rdt, device=F.U.device)
+    C.tsvdm_kron_terms(md, desc, placement.handle if placement is not None else 0, ell, q, Cout.data_ptr(),
+                       Dout.data_ptr(), _stream(stream))
+    return Cout, Dout, nt
+
+
+def mprod(F: Factors, kind: int, n3: int, x: torch.Tensor, s: int, M: torch.Tensor | None = None,
+          stream=None) -> torch.Tensor:
+    """Y = T *_M X for X (p x s x n3, flat column major) with the truncated t-SVDM F."""
+    md = _mdesc(kind, n3, M)
+    desc = F.desc()
+    X = C.dense_tensor(x.data_ptr(), F.p, s, n3, dtype_code(x))
+    y = torch.empty(F.m * s * n3, dtype=x.dtype, device=x.device)
+    Y = C.dense_tensor(y.data_ptr(), F.m, s, n3, dtype_code(y))
+    need = C.tsvdm_mprod_workspace_size(md, desc, s)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    C.tsvdm_mprod(md, desc, X, Y, ws.data_ptr(), need, _stream(stream))
+    return y

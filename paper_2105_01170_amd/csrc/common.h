@@ -176,6 +176,9 @@ tsvdm_status launch_mixed_truncate(const tsvdm_tensor *X, const tsvdm_truncate_o
 tsvdm_status launch_mixed_truncate_noalloc(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
                                            tsvdm_factors *F, hipStream_t s);
 size_t noalloc_scratch_bytes();
+// the device tables of a structured placement (structure.hip)
+void placement_tables(const tsvdm_placement *pl, int64_t *ell, int64_t *q, int64_t *p, const int32_t **blk,
+                      const double **winv);
 tsvdm_status launch_mlp_forward(const uint16_t *w16, const uint16_t *x, int64_t n, float *y, hipStream_t s);
 size_t features_workspace(int64_t m, int64_t p, int64_t nf);
 tsvdm_status launch_rank_features(const tsvdm_tensor *X, const float *omega, uint16_t *features, void *ws,

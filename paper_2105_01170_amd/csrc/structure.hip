@@ -334,3 +334,14 @@ tsvdm_status tsvdm_apply_E(const tsvdm_placement *pl, const tsvdm_mdesc *M, cons
 }
 
 }  // extern "C"
+
+namespace tsvdm {
+void placement_tables(const tsvdm_placement *pl, int64_t *ell, int64_t *q, int64_t *p, const int32_t **blk,
+                      const double **winv) {
+    *ell = pl->ell;
+    *q = pl->q;
+    *p = pl->p;
+    *blk = pl->blk;
+    *winv = pl->winv;
+}
+}  // namespace tsvdm

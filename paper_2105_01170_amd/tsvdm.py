@@ -67,7 +67,8 @@ EXPORTS = ["tsvdm_version", "tsvdm_last_error", "tsvdm_tensor_from_blockmat",
            "tsvdm_placement_create", "tsvdm_placement_eta", "tsvdm_placement_destroy",
            "tsvdm_tensor_from_blockmat_E", "tsvdm_blockmat_from_tensor_E", "tsvdm_apply_E_workspace_size",
            "tsvdm_apply_E", "tsvdm_mode_gram_workspace_size", "tsvdm_mode_gram", "tsvdm_sym_eig",
-           "tsvdm_mode3_transform_workspace_size", "tsvdm_mode3_transform", "tsvdm_mode2_product"]
+           "tsvdm_mode3_transform_workspace_size", "tsvdm_mode3_transform", "tsvdm_mode2_product",
+           "tsvdm_kron_terms_count", "tsvdm_kron_terms", "tsvdm_mprod_workspace_size", "tsvdm_mprod"]
 
 _LIB = None
 
@@ -140,6 +141,14 @@ def lib():
         L.tsvdm_mode3_transform.restype = i32
         L.tsvdm_mode2_product.argtypes = [P(TsvdmTensor), vp, i64, i64, i32, vp, vp]
         L.tsvdm_mode2_product.restype = i32
+        L.tsvdm_kron_terms_count.argtypes = [P(TsvdmMdesc), P(TsvdmFactors)]
+        L.tsvdm_kron_terms_count.restype = i64
+        L.tsvdm_kron_terms.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), vp, i64, i64, vp, vp, vp]
+        L.tsvdm_kron_terms.restype = i32
+        L.tsvdm_mprod_workspace_size.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64]
+        L.tsvdm_mprod_workspace_size.restype = sz
+        L.tsvdm_mprod.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), P(TsvdmTensor), P(TsvdmTensor), vp, sz, vp]
+        L.tsvdm_mprod.restype = i32
         L.tsvdm_apply_workspace_size.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, i32]
         L.tsvdm_apply.restype = i32
         L.tsvdm_apply.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, vp, i64, vp, i64,
@@ -318,6 +327,25 @@ def tsvdm_mode3_transform(X: TsvdmTensor, M_ptr: int, sv_ptr: int, ws_ptr: int, 
 def tsvdm_mode2_product(X: TsvdmTensor, V_ptr: int, pv: int, r: int, direction: int, out_ptr: int,
                         stream: int = 0):
     _check(lib().tsvdm_mode2_product(ctypes.byref(X), V_ptr, pv, r, direction, out_ptr, stream))
+
+
+def tsvdm_kron_terms_count(M: TsvdmMdesc, F: TsvdmFactors) -> int:
+    return lib().tsvdm_kron_terms_count(ctypes.byref(M), ctypes.byref(F))
+
+
+def tsvdm_kron_terms(M: TsvdmMdesc, F: TsvdmFactors, pl: int, ell: int, q: int, C_ptr: int, D_ptr: int,
+                     stream: int = 0):
+    _check(lib().tsvdm_kron_terms(ctypes.byref(M), ctypes.byref(F), pl or None, ell, q, C_ptr, D_ptr, stream))
+
+
+def tsvdm_mprod_workspace_size(M: TsvdmMdesc, F: TsvdmFactors, s: int) -> int:
+    return lib().tsvdm_mprod_workspace_size(ctypes.byref(M), ctypes.byref(F), s)
+
+
+def tsvdm_mprod(M: TsvdmMdesc, F: TsvdmFactors, X: TsvdmTensor, Y: TsvdmTensor, ws_ptr: int, ws_bytes: int,
+                stream: int = 0):
+    _check(lib().tsvdm_mprod(ctypes.byref(M), ctypes.byref(F), ctypes.byref(X), ctypes.byref(Y), ws_ptr, ws_bytes,
+                             stream))
 
 
 def tsvdm_apply_workspace_size(M: TsvdmMdesc, F: TsvdmFactors, ell: int, q: int, nrhs: int,
