@@ -604,3 +604,20 @@ def kron_terms_tsvdm(U: np.ndarray, s: np.ndarray, V: np.ndarray, ranks: np.ndar
             C.append(struct_kron(E, [np.array([[np.conj(V[b, r, f])]]) for b in range(V.shape[0])]))
             D.append(s[r, f] * np.outer(U[:, r, f], Minv[:, f]))
     return C, D
+
+
+def spsd_two_sided(X: np.ndarray, U: np.ndarray):
+    """The two-sided compression of Sec. 5.1 for a tensor X = T_E[A] of a
+    symmetric block matrix (m x p x m): G = X x_1 U^T x_3 U^T and
+    T = G x_1 U x_3 U."""
+    G = mode_product(mode_product(X, U.T, 1), U.T, 3)
+    T = mode_product(mode_product(G, U, 1), U, 3)
+    return G, T
+
+
+def spsd_factor(X: np.ndarray, r: int) -> np.ndarray:
+    """U of Sec. 5.1: the dominant r left singular vectors of the mode-1
+    unfolding (which has the mode-3 unfolding's range for a symmetric block
+    matrix)."""
+    U, _ = hosvd_factor(X, 1, r)
+    return U

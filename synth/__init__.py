@@ -140,3 +140,22 @@ def decay_faces_device(rho, m: int = 512, p: int = 512, k: int = 32, index: int 
     # [f, b, a] = sum_r V[f, b, r] sig[f, r] U[f, a, r]: column-major (m, p) faces
     X = torch.bmm((V * sig[:, None, :]).contiguous(), U.transpose(1, 2).contiguous())
     return X.reshape(-1).to(torch.float32).contiguous(), sig.cpu().numpy()
+
+
+def spacetime_covariance(N: int = 1351, T: int = 30, index: int = 9, salt: int = 0,
+                         length: float = 90.0, tscale: float = 0.5):
+    """Blocks of a space-time covariance matrix (the input of Sec. 6.2): N
+    points x_j drawn uniformly on a longitude/latitude box (degrees; a
+    stand-in for the land-mass grid points), T equidistant times in [0, 1],
+    and the T distinct N x N blocks C_i[j, k] = phi(|x_j - x_k|, |t_1 - t_i|)
+    of the symmetric block-Toeplitz matrix, phi(r, tau) = exp(-((r/90)^2 +
+    (tau/0.5)^2)) (Euclidean distance in degrees).  Returns the blocks stacked
+    N x N x T (float64, Fortran order), the points and the times."""
+    g = rng(index, salt)
+    pts = np.stack([g.uniform(-180.0, 180.0, N), g.uniform(-60.0, 80.0, N)], axis=1)
+    times = np.linspace(0.0, 1.0, T)
+    d = np.sqrt(np.sum((pts[:, None, :] - pts[None, :, :]) ** 2, axis=2))
+    blocks = np.empty((N, N, T), order="F")
+    for i in range(T):
+        blocks[:, :, i] = np.exp(-((d / length) ** 2 + (abs(times[0] - times[i]) / tscale) ** 2))
+    return blocks, pts, times

@@ -141,3 +141,38 @@ def test_kronecker_terms_of_the_tsvdm(kind):
             assert np.max(np.abs(np.imag(total))) < 1e-12
         for Dj in D:
             assert np.linalg.matrix_rank(Dj, tol=1e-12 * max(np.abs(Dj).max(), 1e-300)) <= 1
+
+
+def test_spsd_two_sided_compression_pins():
+    """Sec. 5.1 on a small symmetric block-Toeplitz covariance (Sec. 6.2's
+    kernel): the mode-1 and mode-3 unfoldings of T_E[C] have the same range;
+    M_E[G x_1 U x_3 U] = (I kron P) C (I kron P) with P = U U^T; the
+    approximation stays positive semidefinite; tr = T tr(U^T C_1 U)."""
+    import synth
+    N, T, r = 12, 5, 4
+    blocks, _, _ = synth.spacetime_covariance(N, T, salt=3)
+    # symmetric block-Toeplitz placement: block (i, j) is C_{|i-j|}, eta_k = 2(T-k) (T for k = 0)
+    E = []
+    for k in range(T):
+        Ek = np.zeros((T, T))
+        for i in range(T):
+            for j in range(T):
+                if abs(i - j) == k:
+                    Ek[i, j] = 1.0
+        E.append(Ek / np.linalg.norm(Ek))
+    eta = [np.count_nonzero(Ek) for Ek in E]
+    Cmat = oracle.struct_kron(E, [np.sqrt(e) * blocks[:, :, k] for k, e in enumerate(eta)])
+    assert np.allclose(Cmat, Cmat.T) and np.min(np.linalg.eigvalsh(Cmat)) > -1e-10
+    X = oracle.tensor_from_blockmat_E(Cmat, E, N, N)
+    W1, _ = oracle.hosvd_factor(X, 1)
+    W3, _ = oracle.hosvd_factor(X, 3)
+    np.testing.assert_allclose(W1 @ W1.T, W3 @ W3.T, atol=1e-10)
+    U = oracle.spsd_factor(X, r)
+    G, Tt = oracle.spsd_two_sided(X, U)
+    Chat = oracle.blockmat_from_tensor_E(Tt, E)
+    P = U @ U.T
+    IP = np.kron(np.eye(T), P)
+    np.testing.assert_allclose(Chat, IP @ Cmat @ IP, atol=1e-12)
+    assert np.min(np.linalg.eigvalsh(Chat)) > -1e-12
+    assert np.trace(Chat) == pytest.approx(T * np.trace(U.T @ blocks[:, :, 0] @ U), rel=1e-12)
+    assert np.trace(Cmat) == pytest.approx(N * T, rel=1e-14)
