@@ -213,6 +213,14 @@ tsvdm_status tsvdm_tensor_from_blockmat_E(const tsvdm_placement *pl, const void 
 tsvdm_status tsvdm_blockmat_from_tensor_E(const tsvdm_placement *pl, const void *X, int32_t dtype, int64_t m,
                                           int64_t n, void *A, int64_t lda, void *stream);
 
+/* X = T_E from the tuple of distinct blocks (the definition of Sec. 3,
+ * T_E[A](:, k, :) = sqrt(eta_k) twist(A_k)): blocks (device) holds A_k at
+ * blocks + m n k (m x n each, column major, the p blocks stacked), X (device,
+ * dense m x p x n).  For matrices too large to form: only the p distinct blocks
+ * are read.  Asynchronous. */
+tsvdm_status tsvdm_tensor_from_blocks_E(const tsvdm_placement *pl, const void *blocks, int32_t dtype, int64_t m,
+                                        int64_t n, void *X, void *stream);
+
 /* y = M_E[T] x for the structured placement (T = That x_3 M^{-1}, That_f =
  * Uhat_f S_f Vhat_f^H from F, whose lateral size F->p is the placement's p):
  * the factors of the generic placement, Vg_f(i + ell j, r) = Vhat_f(k(i,j), r)
@@ -283,6 +291,20 @@ tsvdm_status tsvdm_kron_terms(const tsvdm_mdesc *M, const tsvdm_factors *F, cons
 size_t tsvdm_mprod_workspace_size(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t s);
 tsvdm_status tsvdm_mprod(const tsvdm_mdesc *M, const tsvdm_factors *F, const tsvdm_tensor *X, tsvdm_tensor *Y,
                          void *workspace, size_t workspace_bytes, void *stream);
+
+/* ---------------------------------------------------------------- SPSD-preserving compression
+ * Sec. 5.1: for a symmetric positive semidefinite block matrix (ell = q, m = n)
+ * the mode-1 and mode-3 unfoldings of X = T_E[A] (m x p x m) share their range
+ * and one factor U (m x r, orthonormal columns, e.g. the dominant left singular
+ * vectors of X_(1), which is X's memory read as one m x (p m) face) compresses
+ * both: direction +1: G = X x_1 U^T x_3 U^T, G(:, b, :) = U^T sq(X(:, b, :)) U
+ * (G device FP64, r x p x r); direction -1: X = G x_1 U x_3 U (X is the output).
+ * M_E of the reconstruction is (I kron U U^T) A (I kron U U^T), positive
+ * semidefinite whenever A is.  U: F32 or F64 (udtype), r <= 64.  FP64
+ * accumulation.  Asynchronous. */
+size_t tsvdm_two_sided_workspace_size(const tsvdm_tensor *X, int64_t r);
+tsvdm_status tsvdm_two_sided(const tsvdm_tensor *X, const void *U, int32_t udtype, int64_t r, int32_t direction,
+                             double *G, void *workspace, size_t workspace_bytes, void *stream);
 
 /* Host-side check that the n3 x n3 column-major HOST matrix M is orthogonal:
  * max |M^T M - I| <= tol.  Returns TSVDM_OK or TSVDM_EINVAL. */

@@ -340,6 +340,15 @@ class Placement:
                                        _stream(stream))
         return out
 
+    def tensor_from_blocks(self, blocks: torch.Tensor, m: int, n: int, out: torch.Tensor | None = None,
+                           stream=None) -> torch.Tensor:
+        """X = T_E from the distinct blocks stacked m x n x p (flat, column major)."""
+        if out is None:
+            out = torch.empty(m * self.p * n, dtype=blocks.dtype, device=blocks.device)
+        C.tsvdm_tensor_from_blocks_E(self.handle, blocks.data_ptr(), dtype_code(blocks), m, n, out.data_ptr(),
+                                     _stream(stream))
+        return out
+
     def blockmat_from_tensor(self, X: torch.Tensor, m: int, n: int, out: torch.Tensor | None = None,
                              stream=None) -> torch.Tensor:
         """A = M_E[X] ((ell m) x (q n), flat column major) from the dense m x p x n tensor X."""
@@ -442,3 +451,22 @@ def mprod(F: Factors, kind: int, n3: int, x: torch.Tensor, s: int, M: torch.Tens
     ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
     C.tsvdm_mprod(md, desc, X, Y, ws.data_ptr(), need, _stream(stream))
     return y
+
+
+def two_sided(x: torch.Tensor, m: int, p: int, U: torch.Tensor, r: int, stream=None) -> torch.Tensor:
+    """G = X x_1 U^T x_3 U^T (r x p x r, FP64 flat) of the dense m x p x m tensor x."""
+    X = C.dense_tensor(x.data_ptr(), m, p, m, dtype_code(x))
+    need = C.tsvdm_two_sided_workspace_size(X, r)
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=x.device)
+    G = torch.empty(r * p * r, dtype=torch.float64, device=x.device)
+    C.tsvdm_two_sided(X, U.data_ptr(), dtype_code(U), r, 1, G.data_ptr(), ws.data_ptr(), need, _stream(stream))
+    return G
+
+
+def two_sided_inverse(G: torch.Tensor, m: int, p: int, U: torch.Tensor, r: int, dtype=torch.float64,
+                      stream=None) -> torch.Tensor:
+    """T = G x_1 U x_3 U (m x p x m, flat)."""
+    out = torch.empty(m * p * m, dtype=dtype, device=G.device)
+    X = C.dense_tensor(out.data_ptr(), m, p, m, dtype_code(out))
+    C.tsvdm_two_sided(X, U.data_ptr(), dtype_code(U), r, -1, G.data_ptr(), 0, 0, _stream(stream))
+    return out

@@ -68,7 +68,8 @@ EXPORTS = ["tsvdm_version", "tsvdm_last_error", "tsvdm_tensor_from_blockmat",
            "tsvdm_tensor_from_blockmat_E", "tsvdm_blockmat_from_tensor_E", "tsvdm_apply_E_workspace_size",
            "tsvdm_apply_E", "tsvdm_mode_gram_workspace_size", "tsvdm_mode_gram", "tsvdm_sym_eig",
            "tsvdm_mode3_transform_workspace_size", "tsvdm_mode3_transform", "tsvdm_mode2_product",
-           "tsvdm_kron_terms_count", "tsvdm_kron_terms", "tsvdm_mprod_workspace_size", "tsvdm_mprod"]
+           "tsvdm_kron_terms_count", "tsvdm_kron_terms", "tsvdm_mprod_workspace_size", "tsvdm_mprod",
+           "tsvdm_tensor_from_blocks_E", "tsvdm_two_sided_workspace_size", "tsvdm_two_sided"]
 
 _LIB = None
 
@@ -149,6 +150,12 @@ def lib():
         L.tsvdm_mprod_workspace_size.restype = sz
         L.tsvdm_mprod.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), P(TsvdmTensor), P(TsvdmTensor), vp, sz, vp]
         L.tsvdm_mprod.restype = i32
+        L.tsvdm_tensor_from_blocks_E.argtypes = [vp, vp, i32, i64, i64, vp, vp]
+        L.tsvdm_tensor_from_blocks_E.restype = i32
+        L.tsvdm_two_sided_workspace_size.argtypes = [P(TsvdmTensor), i64]
+        L.tsvdm_two_sided_workspace_size.restype = sz
+        L.tsvdm_two_sided.argtypes = [P(TsvdmTensor), vp, i32, i64, i32, vp, vp, sz, vp]
+        L.tsvdm_two_sided.restype = i32
         L.tsvdm_apply_workspace_size.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, i32]
         L.tsvdm_apply.restype = i32
         L.tsvdm_apply.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, vp, i64, vp, i64,
@@ -346,6 +353,19 @@ def tsvdm_mprod(M: TsvdmMdesc, F: TsvdmFactors, X: TsvdmTensor, Y: TsvdmTensor, 
                 stream: int = 0):
     _check(lib().tsvdm_mprod(ctypes.byref(M), ctypes.byref(F), ctypes.byref(X), ctypes.byref(Y), ws_ptr, ws_bytes,
                              stream))
+
+
+def tsvdm_tensor_from_blocks_E(pl: int, blocks_ptr: int, dtype: int, m: int, n: int, X_ptr: int, stream: int = 0):
+    _check(lib().tsvdm_tensor_from_blocks_E(pl, blocks_ptr, dtype, m, n, X_ptr, stream))
+
+
+def tsvdm_two_sided_workspace_size(X: TsvdmTensor, r: int) -> int:
+    return lib().tsvdm_two_sided_workspace_size(ctypes.byref(X), r)
+
+
+def tsvdm_two_sided(X: TsvdmTensor, U_ptr: int, udtype: int, r: int, direction: int, G_ptr: int, ws_ptr: int,
+                    ws_bytes: int, stream: int = 0):
+    _check(lib().tsvdm_two_sided(ctypes.byref(X), U_ptr, udtype, r, direction, G_ptr, ws_ptr, ws_bytes, stream))
 
 
 def tsvdm_apply_workspace_size(M: TsvdmMdesc, F: TsvdmFactors, ell: int, q: int, nrhs: int,
