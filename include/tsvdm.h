@@ -545,6 +545,18 @@ tsvdm_status tsvdm_mlp_train_step(float *w32, uint16_t *w16, float *m, float *v,
                                   const uint16_t *x, const float *target, int64_t n, float *loss,
                                   void *workspace, size_t workspace_bytes, void *stream);
 
+/* Checkpoint of the predictor's training state (resume a training run): a
+ * versioned little-endian binary file, header {magic "TSVDMMLP", uint32 version
+ * = 1, uint32 nparams, int32 step, uint32 0}, then the half weights w16, the
+ * FP32 master weights w32 and the Adam moments m, v (nparams values each), then
+ * the CRC-32 (IEEE 802.3) of all preceding bytes.  The buffers are device (or
+ * host) pointers, copied synchronously.  Load validates magic, version,
+ * parameter count, length and CRC (TSVDM_EINVAL with a message otherwise)
+ * before writing anything. */
+tsvdm_status tsvdm_mlp_save(const char *path, const uint16_t *w16, const float *w32, const float *m, const float *v,
+                            int32_t step);
+tsvdm_status tsvdm_mlp_load(const char *path, uint16_t *w16, float *w32, float *m, float *v, int32_t *step);
+
 /* b[i] = a[i] rounded to half (nearest even), i < n. */
 tsvdm_status tsvdm_f32_to_f16(const float *a, uint16_t *b, int64_t n, void *stream);
 

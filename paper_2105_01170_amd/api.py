@@ -250,6 +250,19 @@ class RankPredictor:
                                self.loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
         return self.loss
 
+    def save(self, path: str):
+        """Write the training state (weights, Adam moments, step) to a checksummed file."""
+        torch.cuda.synchronize(self.w32.device)
+        C.tsvdm_mlp_save(str(path), self.w16.data_ptr(), self.w32.data_ptr(), self.m.data_ptr(),
+                         self.v.data_ptr(), self.step)
+
+    def load(self, path: str):
+        """Restore the state written by save(); raises on a corrupt or foreign file."""
+        torch.cuda.synchronize(self.w32.device)
+        self.step = C.tsvdm_mlp_load(str(path), self.w16.data_ptr(), self.w32.data_ptr(), self.m.data_ptr(),
+                                     self.v.data_ptr())
+        return self
+
 
 def rank_features(xhat: torch.Tensor, m: int, p: int, nf: int, omega: torch.Tensor,
                   stream=None) -> torch.Tensor:

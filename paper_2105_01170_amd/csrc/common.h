@@ -148,6 +148,16 @@ inline View make_view(const tsvdm_tensor &t) {
 }
 
 // Wave-level sum (64 lanes) via cross-lane shuffles.
+// Strict total order for a descending sort by value with NaN last and ties
+// broken by index: the rank sum_j sorts_before(v[j], j, v[i], i) of entry i is
+// then a permutation of 0..n-1 whatever the values (a NaN input cannot leave
+// a slot of the permutation unwritten).
+__device__ __forceinline__ bool sorts_before(double a, int i, double b, int j) {
+    const bool na = a != a, nb = b != b;
+    if (na || nb) return nb && (!na || i < j);
+    return a > b || (a == b && i < j);
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
 #pragma unroll

@@ -158,7 +158,7 @@ __global__ __launch_bounds__(ET) void k_sym_eig(const double *__restrict__ G, in
     if (tid < N) {
         int pos = 0;
         const double li = lv[tid];
-        for (int j = 0; j < N; ++j) pos += (lv[j] > li) || (lv[j] == li && j < tid);
+        for (int j = 0; j < N; ++j) pos += sorts_before(lv[j], j, li, tid);
         perm[pos] = tid;
     }
     __syncthreads();

@@ -194,10 +194,7 @@ __global__ __launch_bounds__(JT) void k_jac_finish(int64_t m, int64_t p, int64_t
     for (int i = threadIdx.x; i < n; i += JT) {  // stable descending order
         int pos = 0;
         double si = nrm[i];
-        for (int j = 0; j < n; ++j) {
-            double sj = nrm[j];
-            pos += (sj > si) || (sj == si && j < i);
-        }
+        for (int j = 0; j < n; ++j) pos += sorts_before(nrm[j], j, si, i);
         perm[pos] = i;
     }
     __syncthreads();

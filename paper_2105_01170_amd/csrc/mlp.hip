@@ -14,6 +14,11 @@
 //    (bias-corrected) to the master weights and refreshes the half copy.
 #include "common.h"
 
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
 using namespace tsvdm;
 
 namespace {
@@ -237,9 +242,117 @@ tsvdm_status launch_mlp_forward(const uint16_t *w16, const uint16_t *x, int64_t 
 }
 }  // namespace tsvdm
 
+namespace {
+// CRC-32 of the IEEE 802.3 polynomial (reflected, 0xEDB88320), bit by bit
+uint32_t crc32_update(uint32_t crc, const unsigned char *p, size_t n) {
+    for (size_t i = 0; i < n; ++i) {
+        crc ^= p[i];
+        for (int b = 0; b < 8; ++b) crc = (crc >> 1) ^ (0xEDB88320u & (0u - (crc & 1u)));
+    }
+    return crc;
+}
+
+constexpr char kMagic[8] = {'T', 'S', 'V', 'D', 'M', 'M', 'L', 'P'};
+constexpr uint32_t kVersion = 1;
+
+struct CkptHeader {
+    char magic[8];
+    uint32_t version, nparams;
+    int32_t step;
+    uint32_t reserved;
+};
+static_assert(sizeof(CkptHeader) == 24, "checkpoint header layout");
+}  // namespace
+
 extern "C" {
 
 int64_t tsvdm_mlp_nparams(void) { return NPAR; }
+
+tsvdm_status tsvdm_mlp_save(const char *path, const uint16_t *w16, const float *w32, const float *m, const float *v,
+                            int32_t step) {
+    if (!path || !w16 || !w32 || !m || !v) {
+        set_error("mlp_save: NULL argument");
+        return TSVDM_EINVAL;
+    }
+    std::vector<unsigned char> buf(sizeof(CkptHeader) + NPAR * (2 + 3 * 4) + 4);
+    CkptHeader h{};
+    memcpy(h.magic, kMagic, 8);
+    h.version = kVersion;
+    h.nparams = NPAR;
+    h.step = step;
+    memcpy(buf.data(), &h, sizeof(h));
+    size_t off = sizeof(h);
+    hipError_t e = hipMemcpy(buf.data() + off, w16, NPAR * 2, hipMemcpyDefault);
+    off += NPAR * 2;
+    const float *src[3] = {w32, m, v};
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+        e = hipMemcpy(buf.data() + off, src[i], NPAR * 4, hipMemcpyDefault);
+        off += NPAR * 4;
+    }
+    if (e != hipSuccess) return hip_check(e, "mlp_save: copy to host");
+    const uint32_t crc = crc32_update(0xFFFFFFFFu, buf.data(), off) ^ 0xFFFFFFFFu;
+    memcpy(buf.data() + off, &crc, 4);
+    FILE *f = fopen(path, "wb");
+    if (!f) {
+        set_error("mlp_save: cannot open %s", path);
+        return TSVDM_EINVAL;
+    }
+    const size_t wrote = fwrite(buf.data(), 1, buf.size(), f);
+    const int closed = fclose(f);
+    if (wrote != buf.size() || closed != 0) {
+        set_error("mlp_save: short write to %s", path);
+        return TSVDM_EINVAL;
+    }
+    return TSVDM_OK;
+}
+
+tsvdm_status tsvdm_mlp_load(const char *path, uint16_t *w16, float *w32, float *m, float *v, int32_t *step) {
+    if (!path || !w16 || !w32 || !m || !v || !step) {
+        set_error("mlp_load: NULL argument");
+        return TSVDM_EINVAL;
+    }
+    const size_t total = sizeof(CkptHeader) + NPAR * (2 + 3 * 4) + 4;
+    std::vector<unsigned char> buf(total + 1);
+    FILE *f = fopen(path, "rb");
+    if (!f) {
+        set_error("mlp_load: cannot open %s", path);
+        return TSVDM_EINVAL;
+    }
+    const size_t got = fread(buf.data(), 1, buf.size(), f);
+    fclose(f);
+    CkptHeader h{};
+    if (got >= sizeof(h)) memcpy(&h, buf.data(), sizeof(h));
+    if (got < sizeof(h) || memcmp(h.magic, kMagic, 8) != 0) {
+        set_error("mlp_load: %s is not a predictor checkpoint", path);
+        return TSVDM_EINVAL;
+    }
+    if (h.version != kVersion || h.nparams != (uint32_t)NPAR) {
+        set_error("mlp_load: checkpoint version %u with %u parameters; expected version %u with %d", h.version,
+                  h.nparams, kVersion, NPAR);
+        return TSVDM_EINVAL;
+    }
+    if (got != total) {
+        set_error("mlp_load: %s has %zu bytes, expected %zu", path, got, total);
+        return TSVDM_EINVAL;
+    }
+    uint32_t crc;
+    memcpy(&crc, buf.data() + total - 4, 4);
+    if ((crc32_update(0xFFFFFFFFu, buf.data(), total - 4) ^ 0xFFFFFFFFu) != crc) {
+        set_error("mlp_load: CRC mismatch in %s", path);
+        return TSVDM_EINVAL;
+    }
+    size_t off = sizeof(h);
+    hipError_t e = hipMemcpy(w16, buf.data() + off, NPAR * 2, hipMemcpyDefault);
+    off += NPAR * 2;
+    float *dst[3] = {w32, m, v};
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) {
+        e = hipMemcpy(dst[i], buf.data() + off, NPAR * 4, hipMemcpyDefault);
+        off += NPAR * 4;
+    }
+    if (e != hipSuccess) return hip_check(e, "mlp_load: copy to the device");
+    *step = h.step;
+    return TSVDM_OK;
+}
 
 size_t tsvdm_mlp_train_workspace_size(int64_t n) {
     if (n < 1 || n > (int64_t(1) << 26)) return 0;

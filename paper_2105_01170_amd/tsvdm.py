@@ -69,7 +69,8 @@ EXPORTS = ["tsvdm_version", "tsvdm_last_error", "tsvdm_tensor_from_blockmat",
            "tsvdm_apply_E", "tsvdm_mode_gram_workspace_size", "tsvdm_mode_gram", "tsvdm_sym_eig",
            "tsvdm_mode3_transform_workspace_size", "tsvdm_mode3_transform", "tsvdm_mode2_product",
            "tsvdm_kron_terms_count", "tsvdm_kron_terms", "tsvdm_mprod_workspace_size", "tsvdm_mprod",
-           "tsvdm_tensor_from_blocks_E", "tsvdm_two_sided_workspace_size", "tsvdm_two_sided"]
+           "tsvdm_tensor_from_blocks_E", "tsvdm_two_sided_workspace_size", "tsvdm_two_sided", "tsvdm_mlp_save",
+           "tsvdm_mlp_load"]
 
 _LIB = None
 
@@ -156,6 +157,10 @@ def lib():
         L.tsvdm_two_sided_workspace_size.restype = sz
         L.tsvdm_two_sided.argtypes = [P(TsvdmTensor), vp, i32, i64, i32, vp, vp, sz, vp]
         L.tsvdm_two_sided.restype = i32
+        L.tsvdm_mlp_save.argtypes = [ctypes.c_char_p, vp, vp, vp, vp, i32]
+        L.tsvdm_mlp_save.restype = i32
+        L.tsvdm_mlp_load.argtypes = [ctypes.c_char_p, vp, vp, vp, vp, P(i32)]
+        L.tsvdm_mlp_load.restype = i32
         L.tsvdm_apply_workspace_size.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, i32]
         L.tsvdm_apply.restype = i32
         L.tsvdm_apply.argtypes = [P(TsvdmMdesc), P(TsvdmFactors), i64, i64, i64, vp, i64, vp, i64,
@@ -366,6 +371,16 @@ def tsvdm_two_sided_workspace_size(X: TsvdmTensor, r: int) -> int:
 def tsvdm_two_sided(X: TsvdmTensor, U_ptr: int, udtype: int, r: int, direction: int, G_ptr: int, ws_ptr: int,
                     ws_bytes: int, stream: int = 0):
     _check(lib().tsvdm_two_sided(ctypes.byref(X), U_ptr, udtype, r, direction, G_ptr, ws_ptr, ws_bytes, stream))
+
+
+def tsvdm_mlp_save(path: str, w16: int, w32: int, m: int, v: int, step: int):
+    _check(lib().tsvdm_mlp_save(path.encode(), w16, w32, m, v, step))
+
+
+def tsvdm_mlp_load(path: str, w16: int, w32: int, m: int, v: int) -> int:
+    step = ctypes.c_int32(0)
+    _check(lib().tsvdm_mlp_load(path.encode(), w16, w32, m, v, ctypes.byref(step)))
+    return step.value
 
 
 def tsvdm_apply_workspace_size(M: TsvdmMdesc, F: TsvdmFactors, ell: int, q: int, nrhs: int,

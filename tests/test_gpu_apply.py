@@ -67,13 +67,15 @@ def test_apply_full_size_dft_fp32():
     assert relerr(y, y_ref) < TOL[C.F32]
 
 
-@pytest.mark.parametrize("k", [12, 24])
+@pytest.mark.parametrize("k", [12, 24, 40, 64])
 @pytest.mark.parametrize("compute", [C.F32, C.BF16, C.F64])
 @pytest.mark.parametrize("kind", [C.M_DCT2, C.M_DFT])
 def test_apply_face_ranks_below_kmax(kind, compute, k):
     """Per-face ranks below the stored width, zero included (faces skipped);
     one and two blocks of 16 ranks (operands staged in LDS, 45 k over two
-    chunks); 70 rows (two row tiles), a ragged column tile."""
+    chunks), three and four blocks (widths 40 and 64: the direct-load matrix
+    core kernel); 70 rows (two row tiles), a ragged column tile, q = 45 not a
+    multiple of 4."""
     m, ell, q, n, nrhs = 70, 3, 45, 10, 70
     g = np.random.default_rng(11 + k)
     nf = n // 2 + 1 if kind == C.M_DFT else n

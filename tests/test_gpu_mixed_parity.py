@@ -154,3 +154,62 @@ def test_mixed_headline_shape_512_k32_ell40():
     true = np.array([np.linalg.norm(xg[:, :, f] - That[:, :, f]) for f in range(n3)])
     np.testing.assert_allclose(got["cert"], true, rtol=1e-9, atol=1e-14 * np.max(got["fro"]))
     assert np.max(got["cert"] / got["fro"]) < 1e-5
+
+
+@pytest.mark.parametrize("precision", [C.PREC_MIXED, C.PREC_F64])
+def test_zero_and_nonfinite_faces(precision):
+    """An all-zero face and a face holding a NaN, between ordinary faces, ENERGY
+    rule: the zero face gets rank 0, ||X_f|| = 0, certificate 0 and zero
+    factors (mixed path: info = 2, the range finder's Cholesky breaks down on
+    a zero sketch; FP64 path: info = 0); the NaN face info = 3; the ordinary
+    faces come out bit for bit as in a run without the degenerate faces."""
+    m, p, cap, tau = 96, 80, 16, 1e-3
+    Xh32, _ = _decaying_faces(m, p, [1 / 3, 1 / 2, 1 / 4, 0.4], 24, salt=91)
+    nf = Xh32.shape[2]
+    bad = Xh32.copy(order="F")
+    bad[:, :, 1] = 0.0
+    bad[5, 7, 2] = np.nan
+    if precision == C.PREC_MIXED:
+        dt, npdt, kw = torch.float32, np.float32, dict(oversample=8, power_iters=1)
+        Omega = synth.gaussian(synth.rng(1, 92), (p, cap + 8)).astype(np.float32)
+        kw["omega"] = to_dev(Omega)
+    else:
+        dt, npdt, kw = torch.float64, np.float64, dict(kmax=cap)
+    tr = api.Truncator(m, p, nf, dt, rank_mode=C.RANK_ENERGY, k=cap, tau=tau, precision=precision, **kw)
+    good = _factors(tr(to_dev(Xh32.astype(npdt))), nf)
+    got = _factors(tr(to_dev(bad.astype(npdt))), nf)
+    assert np.all(good["info"] == 0)
+    for f in (0, 3):
+        for key in ("U", "S", "V", "ranks", "cert", "fro", "info"):
+            a, b = np.take(got[key], f, axis=-1), np.take(good[key], f, axis=-1)
+            assert np.array_equal(a, b), (f, key)
+    assert got["ranks"][1] == 0 and got["fro"][1] == 0.0 and got["cert"][1] == 0.0
+    assert not np.any(got["U"][:, :, 1]) and not np.any(got["S"][:, 1]) and not np.any(got["V"][:, :, 1])
+    assert got["info"][1] == (2 if precision == C.PREC_MIXED else 0)
+    assert got["info"][2] == 3 and not np.isfinite(got["fro"][2])
+
+
+def test_mixed_rows_over_several_qr_chunks():
+    """m = 1100 rows: the Cholesky-QR passes over the sketch and the final
+    basis take three chunks of 512 rows, the last one ragged (76 rows), with
+    the second pass re-reading Q from memory; p = 300.  FIXED k = 20,
+    oversampling 8, one power iteration: ranks and the truncation equal the
+    oracle's FP64 randomized truncation with the same Omega, at 1e-4."""
+    m, p, k, os_ = 1100, 300, 20, 8
+    Xh32, _ = _decaying_faces(m, p, [1 / 10, 1 / 6, 1 / 4], 40, salt=93)
+    nf = Xh32.shape[2]
+    Omega = synth.gaussian(synth.rng(1, 94), (p, k + os_)).astype(np.float32)
+    tr = api.Truncator(m, p, nf, torch.float32, k=k, precision=C.PREC_MIXED, oversample=os_, power_iters=1,
+                       omega=to_dev(Omega))
+    got = _factors(tr(to_dev(Xh32)), nf)
+    assert np.all(got["ranks"] == k) and np.all(got["info"] == 0)
+    Xh64 = Xh32.astype(np.float64)
+    rnd = oracle.randomized_tsvdm_faces(Xh64, Omega.astype(np.float64), k, 1)
+    That = reconstruct(got["U"], got["S"], got["V"], got["ranks"])
+    assert relerr(That, rnd["That"]) < 1e-4
+    # orthonormal columns of U to FP32 accuracy
+    for f in range(nf):
+        Uf = got["U"][:, :k, f]
+        assert np.abs(Uf.T @ Uf - np.eye(k)).max() < 1e-5
+    true = np.array([np.linalg.norm(Xh64[:, :, f] - That[:, :, f]) for f in range(nf)])
+    np.testing.assert_allclose(got["cert"], true, rtol=1e-9, atol=1e-14 * np.max(got["fro"]))

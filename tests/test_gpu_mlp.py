@@ -1,5 +1,8 @@
 """GPU parity of the rank predictor kernels (tsvdm_mlp_*, tsvdm_rank_features)
 against the oracle MLP with the same half-precision roundings."""
+import struct
+import zlib
+
 import numpy as np
 import pytest
 
@@ -97,3 +100,53 @@ def test_rank_features_match_sketch_singular_values():
         # are accurate to a few 1e-3 in log10, the smallest ones less so
         np.testing.assert_allclose(feats[f, :16].astype(np.float64), ref[:16], atol=2e-2)
         assert np.all(np.diff(feats[f].astype(np.float64)) <= 1e-3)
+
+
+def test_checkpoint_round_trip_corruption_and_resume(tmp_path):
+    """Saving after a few Adam steps and loading into a fresh predictor restores
+    weights, moments and step exactly; training on from the checkpoint gives
+    the same weights as training on without it; a flipped byte, a truncated
+    file and a foreign file are rejected."""
+    theta = _params(7)
+    X, T = _inputs(8, 256)
+    x16 = torch.from_numpy(X).to("cuda", torch.float16)
+    t32 = torch.from_numpy(T).to("cuda", torch.float32)
+    a = api.RankPredictor(torch.from_numpy(theta))
+    for _ in range(3):
+        a.train_step(x16, t32, lr=1e-3)
+    path = tmp_path / "pred.ckpt"
+    a.save(path)
+    saved_w32 = a.w32.cpu().numpy()
+    b = api.RankPredictor(torch.zeros(C.tsvdm_mlp_nparams())).load(path)
+    assert b.step == 3
+    for name in ("w16", "w32", "m", "v"):
+        assert torch.equal(getattr(a, name), getattr(b, name)), name
+    for _ in range(2):
+        a.train_step(x16, t32, lr=1e-3)
+        b.train_step(x16, t32, lr=1e-3)
+    assert a.step == b.step == 5
+    assert torch.equal(a.w32, b.w32) and torch.equal(a.m, b.m) and torch.equal(a.v, b.v)
+
+    raw = bytearray(path.read_bytes())
+    nbytes = 24 + C.tsvdm_mlp_nparams() * 14 + 4
+    assert len(raw) == nbytes and raw[:8] == b"TSVDMMLP"
+    # the documented layout: header fields, then the CRC-32 (IEEE 802.3) of all preceding bytes
+    assert struct.unpack_from("<IIiI", raw, 8) == (1, C.tsvdm_mlp_nparams(), 3, 0)
+    assert zlib.crc32(bytes(raw[:-4])) == struct.unpack_from("<I", raw, nbytes - 4)[0]
+    n = C.tsvdm_mlp_nparams()
+    w32 = np.frombuffer(bytes(raw[24 + 2 * n:24 + 6 * n]), dtype="<f4")
+    np.testing.assert_array_equal(w32, saved_w32)
+    c = api.RankPredictor(torch.from_numpy(theta))
+    before = c.w32.clone()
+    bad = tmp_path / "bad.ckpt"
+    raw[1000] ^= 0x10
+    bad.write_bytes(bytes(raw))
+    with pytest.raises(C.TsvdmError, match="CRC"):
+        c.load(bad)
+    bad.write_bytes(path.read_bytes()[:-100])
+    with pytest.raises(C.TsvdmError, match="bytes"):
+        c.load(bad)
+    bad.write_bytes(b"not a checkpoint" * 10)
+    with pytest.raises(C.TsvdmError, match="not a predictor checkpoint"):
+        c.load(bad)
+    assert c.step == 0 and torch.equal(c.w32, before)  # nothing written on failure
