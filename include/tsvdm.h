@@ -510,6 +510,20 @@ tsvdm_status tsvdm_batched_set_config(tsvdm_batched_plan *plan, const int32_t cf
 /* Releases the host plan (the workspace stays the caller's). NULL is allowed. */
 void tsvdm_batched_plan_destroy(tsvdm_batched_plan *plan);
 
+/* Persistent autotune table.  The process-wide table of tuned configurations
+ * (filled by tsvdm_batched_autotune, keyed by the batch signature and the
+ * device's CU count) is written to / merged from a text file:
+ *   line 1 "tsvdm-autotune 1", then one line per entry:
+ *   "<key, 16 hex digits> <cfg[0]> <cfg[1]> <cfg[2]>".
+ * Save writes a temporary file and renames it over `path`.  Load validates the
+ * whole file (header, ranges as for tsvdm_batched_set_config) before merging
+ * any entry (TSVDM_EINVAL with the line otherwise); *n_entries (may be NULL)
+ * receives the number merged.  Plans created afterwards start from a matching
+ * entry and read as tuned.  Clear empties the table.  Host-only, thread-safe. */
+tsvdm_status tsvdm_autotune_save(const char *path);
+tsvdm_status tsvdm_autotune_load(const char *path, int32_t *n_entries);
+void tsvdm_autotune_clear(void);
+
 /* ---------------------------------------------------------------- rank predictor
  * A multilayer perceptron 32 -> 64 -> 64 -> 2 (ReLU hidden layers, linear
  * output) that predicts, per transform-domain face, (k/32, l/48): the rank and

@@ -16,11 +16,14 @@
 //    the face.
 // A queue reset kernel precedes the two persistent kernels, so a launch
 // sequence can be captured in a graph and replayed.
+#include <stdio.h>
+
 #include <algorithm>
 #include <cmath>
 #include <map>
 #include <new>
 #include <mutex>
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -556,7 +559,10 @@ bool check_batch(int32_t nmat, const tsvdm_tensor *X, int64_t *nitems, int64_t *
     return true;
 }
 
-uint64_t signature(int64_t nitems, const std::vector<Item> &items) {
+// Key of the tuned-configuration table: the shape of the batch (largest face
+// height, log2 of the element count, log2 of the item count) and the CU count
+// of the device it was tuned on.
+uint64_t signature(int64_t nitems, const std::vector<Item> &items, int num_cu) {
     int maxm = 0;
     double elems = 0.0;
     for (const Item &it : items) {
@@ -567,7 +573,7 @@ uint64_t signature(int64_t nitems, const std::vector<Item> &items) {
     while (lg < 62 && std::ldexp(1.0, lg + 1) <= elems) ++lg;
     int ln = 0;
     while (ln < 40 && (int64_t(1) << (ln + 1)) <= nitems) ++ln;
-    return (uint64_t)maxm | ((uint64_t)lg << 8) | ((uint64_t)ln << 16);
+    return (uint64_t)maxm | ((uint64_t)lg << 8) | ((uint64_t)ln << 16) | ((uint64_t)(num_cu & 0xFFFF) << 24);
 }
 
 tsvdm_status launch(const tsvdm_batched_plan_s *P, const Cfg &cfg, hipStream_t s, int which) {
@@ -715,7 +721,7 @@ tsvdm_status tsvdm_batched_plan_create(int32_t nmat, const tsvdm_tensor *Xhat,
     P->kcap = o->k;
     P->tau = o->tau;
     P->max_sweeps = o->max_sweeps > 0 ? o->max_sweeps : 30;
-    P->sig = signature(n, items);
+    P->sig = signature(n, items, P->num_cu);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto hit = g_tune.find(P->sig);
@@ -833,5 +839,81 @@ tsvdm_status tsvdm_batched_set_config(tsvdm_batched_plan *plan, const int32_t cf
 }
 
 void tsvdm_batched_plan_destroy(tsvdm_batched_plan *plan) { delete plan; }
+
+tsvdm_status tsvdm_autotune_save(const char *path) {
+    if (!path) {
+        set_error("autotune_save: path is NULL");
+        return TSVDM_EINVAL;
+    }
+    std::map<uint64_t, Cfg> snap;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        snap = g_tune;
+    }
+    // written to a temporary file first and renamed, so a reader never sees a
+    // partial table
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) {
+        set_error("autotune_save: cannot open %s", tmp.c_str());
+        return TSVDM_EINVAL;
+    }
+    bool ok = fprintf(f, "tsvdm-autotune 1\n") > 0;
+    for (const auto &kv : snap)
+        ok = ok && fprintf(f, "%016llx %d %d %d\n", (unsigned long long)kv.first, kv.second.gram_wpc,
+                           kv.second.gram_kc, kv.second.vec_wpc) > 0;
+    ok = (fclose(f) == 0) && ok;
+    if (!ok || rename(tmp.c_str(), path) != 0) {
+        remove(tmp.c_str());
+        set_error("autotune_save: writing %s failed", path);
+        return TSVDM_EINVAL;
+    }
+    return TSVDM_OK;
+}
+
+tsvdm_status tsvdm_autotune_load(const char *path, int32_t *n_entries) {
+    if (!path) {
+        set_error("autotune_load: path is NULL");
+        return TSVDM_EINVAL;
+    }
+    FILE *f = fopen(path, "r");
+    if (!f) {
+        set_error("autotune_load: cannot open %s", path);
+        return TSVDM_EINVAL;
+    }
+    char line[256];
+    int version = 0;
+    std::map<uint64_t, Cfg> got;
+    tsvdm_status st = TSVDM_OK;
+    if (!fgets(line, sizeof line, f) || sscanf(line, "tsvdm-autotune %d", &version) != 1 || version != 1) {
+        set_error("autotune_load: %s is not a version 1 autotune table", path);
+        st = TSVDM_EINVAL;
+    }
+    for (int ln = 2; st == TSVDM_OK && fgets(line, sizeof line, f); ++ln) {
+        unsigned long long key = 0;
+        int a = 0, b = 0, c = 0;
+        char extra = 0;
+        const int nf = sscanf(line, "%llx %d %d %d %c", &key, &a, &b, &c, &extra);
+        if (nf != 4 || a < 1 || a > 16 || (b != 16 && b != 32) || c < 1 || c > 16) {
+            set_error("autotune_load: %s line %d is malformed or out of range", path, ln);
+            st = TSVDM_EINVAL;
+            break;
+        }
+        got[(uint64_t)key] = Cfg{a, b, c, 1};
+    }
+    fclose(f);
+    if (st != TSVDM_OK) return st;  // nothing merged from a bad file
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        for (const auto &kv : got) g_tune[kv.first] = kv.second;
+    }
+    if (n_entries) *n_entries = (int32_t)got.size();
+    return TSVDM_OK;
+}
+
+void tsvdm_autotune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
+}
 
 }  // extern "C"

@@ -70,7 +70,7 @@ EXPORTS = ["tsvdm_version", "tsvdm_last_error", "tsvdm_tensor_from_blockmat",
            "tsvdm_mode3_transform_workspace_size", "tsvdm_mode3_transform", "tsvdm_mode2_product",
            "tsvdm_kron_terms_count", "tsvdm_kron_terms", "tsvdm_mprod_workspace_size", "tsvdm_mprod",
            "tsvdm_tensor_from_blocks_E", "tsvdm_two_sided_workspace_size", "tsvdm_two_sided", "tsvdm_mlp_save",
-           "tsvdm_mlp_load"]
+           "tsvdm_mlp_load", "tsvdm_autotune_save", "tsvdm_autotune_load", "tsvdm_autotune_clear"]
 
 _LIB = None
 
@@ -157,6 +157,12 @@ def lib():
         L.tsvdm_two_sided_workspace_size.restype = sz
         L.tsvdm_two_sided.argtypes = [P(TsvdmTensor), vp, i32, i64, i32, vp, vp, sz, vp]
         L.tsvdm_two_sided.restype = i32
+        L.tsvdm_autotune_save.argtypes = [ctypes.c_char_p]
+        L.tsvdm_autotune_save.restype = i32
+        L.tsvdm_autotune_load.argtypes = [ctypes.c_char_p, P(i32)]
+        L.tsvdm_autotune_load.restype = i32
+        L.tsvdm_autotune_clear.argtypes = []
+        L.tsvdm_autotune_clear.restype = None
         L.tsvdm_mlp_save.argtypes = [ctypes.c_char_p, vp, vp, vp, vp, i32]
         L.tsvdm_mlp_save.restype = i32
         L.tsvdm_mlp_load.argtypes = [ctypes.c_char_p, vp, vp, vp, vp, P(i32)]
@@ -371,6 +377,20 @@ def tsvdm_two_sided_workspace_size(X: TsvdmTensor, r: int) -> int:
 def tsvdm_two_sided(X: TsvdmTensor, U_ptr: int, udtype: int, r: int, direction: int, G_ptr: int, ws_ptr: int,
                     ws_bytes: int, stream: int = 0):
     _check(lib().tsvdm_two_sided(ctypes.byref(X), U_ptr, udtype, r, direction, G_ptr, ws_ptr, ws_bytes, stream))
+
+
+def tsvdm_autotune_save(path: str):
+    _check(lib().tsvdm_autotune_save(str(path).encode()))
+
+
+def tsvdm_autotune_load(path: str) -> int:
+    n = ctypes.c_int32(0)
+    _check(lib().tsvdm_autotune_load(str(path).encode(), ctypes.byref(n)))
+    return n.value
+
+
+def tsvdm_autotune_clear():
+    lib().tsvdm_autotune_clear()
 
 
 def tsvdm_mlp_save(path: str, w16: int, w32: int, m: int, v: int, step: int):

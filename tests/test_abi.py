@@ -338,3 +338,32 @@ def test_block_structure_toeplitz_hankel_diagonal():
         C.tsvdm_block_structure(C.PLACE_DIAGONAL, 3, 4)
     with pytest.raises(C.TsvdmError):
         C.tsvdm_block_structure(99, 3, 4)
+
+
+def test_autotune_table_file_round_trip_and_rejection(tmp_path):
+    """The autotune table file: entries loaded from a file are saved back
+    unchanged (sorted by key); a bad header, an out-of-range configuration or
+    trailing junk is rejected with the line and merges nothing."""
+    C.tsvdm_autotune_clear()
+    src = tmp_path / "tune.txt"
+    src.write_text("tsvdm-autotune 1\n0000010000132040 2 32 4\n00000100000f1030 1 16 1\n")
+    assert C.tsvdm_autotune_load(src) == 2
+    out = tmp_path / "out.txt"
+    C.tsvdm_autotune_save(out)
+    assert out.read_text() == "tsvdm-autotune 1\n00000100000f1030 1 16 1\n0000010000132040 2 32 4\n"
+    assert not (tmp_path / "out.txt.tmp").exists()
+    for body, msg in [("tsvdm-autotune 2\n", "not a version 1"),
+                      ("tsvdm-autotune 1\n0000000000000001 2 24 4\n", "line 2"),
+                      ("tsvdm-autotune 1\n0000000000000001 2 16 4\n0000000000000002 2 16 4 x\n", "line 3"),
+                      ("tsvdm-autotune 1\n0000000000000003 0 16 4\n", "line 2")]:
+        bad = tmp_path / "bad.txt"
+        bad.write_text(body)
+        with pytest.raises(C.TsvdmError, match=msg):
+            C.tsvdm_autotune_load(bad)
+    C.tsvdm_autotune_save(out)  # the failed loads merged nothing
+    assert out.read_text().count("\n") == 3
+    with pytest.raises(C.TsvdmError, match="cannot open"):
+        C.tsvdm_autotune_load(tmp_path / "missing.txt")
+    C.tsvdm_autotune_clear()
+    C.tsvdm_autotune_save(out)
+    assert out.read_text() == "tsvdm-autotune 1\n"

@@ -152,7 +152,7 @@ def test_edge_faces_single_row_zero_face_and_cap():
         assert cert[f] > TAU * np.linalg.norm(xf)
 
 
-def test_graph_capture_replays_and_autotune_match_eager():
+def test_graph_capture_replays_and_autotune_match_eager(tmp_path):
     """The launch sequence captured in a graph gives, on every replay (with
     eager work and synchronisation in between), exactly the eager result; the
     autotuned configuration gives exactly the same result too (the per-face
@@ -172,6 +172,16 @@ def test_graph_capture_replays_and_autotune_match_eager():
     bt2 = api.BatchedTruncator(xd, [x.shape for x in xhs], rank_mode=C.RANK_ENERGY, k=8, tau=TAU,
                                kmax=8)
     assert bt2.config() == cfg
+    # the table survives the process through its file: cleared, a new plan is
+    # untuned; loaded back, a new plan starts tuned with the same configuration
+    tune = tmp_path / "tune.txt"
+    C.tsvdm_autotune_save(tune)
+    C.tsvdm_autotune_clear()
+    bt3 = api.BatchedTruncator(xd, [x.shape for x in xhs], rank_mode=C.RANK_ENERGY, k=8, tau=TAU, kmax=8)
+    assert bt3.config()[3] == 0
+    assert C.tsvdm_autotune_load(tune) >= 1
+    bt4 = api.BatchedTruncator(xd, [x.shape for x in xhs], rank_mode=C.RANK_ENERGY, k=8, tau=TAU, kmax=8)
+    assert bt4.config() == cfg
     s = torch.cuda.Stream()
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
