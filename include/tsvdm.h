@@ -96,9 +96,12 @@ enum {
 /* Arithmetic of the facewise truncation */
 enum {
     TSVDM_PREC_F64 = 0,     /* plain: full facewise SVD by one-sided Jacobi in FP64     */
-    TSVDM_PREC_MIXED = 1    /* randomized range finder: BF16 sketch and first power
+    TSVDM_PREC_MIXED = 1,   /* randomized range finder: BF16 sketch and first power
                                half-step, split-BF16 (FP32-accurate) final half-step
                                and projection, FP64 orthogonalisation and core SVD    */
+    TSVDM_PREC_F64_RAND = 2 /* the same randomized range finder with every product in
+                               FP64 (FP64 MFMA) on an FP64 Xhat: FP64 accuracy of the
+                               sketched truncation, for real M                        */
 };
 
 typedef struct {
@@ -106,12 +109,13 @@ typedef struct {
     int32_t k;             /* FIXED: the rank.  ENERGY: cap on the rank (<= kmax)   */
     double tau;            /* ENERGY: relative tolerance per face                   */
     int32_t precision;     /* TSVDM_PREC_* */
-    int32_t oversample;    /* MIXED: sketch width ell = k + oversample (ell <= 64)  */
-    int32_t power_iters;   /* MIXED: 0 or 1 power iterations                        */
+    int32_t oversample;    /* MIXED, F64_RAND: sketch width ell = k + oversample
+                              (ell <= 64)                                            */
+    int32_t power_iters;   /* MIXED, F64_RAND: 0 or 1 power iterations              */
     int32_t max_sweeps;    /* Jacobi sweep cap, 0 = default (60 plain, 30 core)     */
-    int32_t certify;       /* MIXED: 1 = compute cert by an explicit residual pass  */
+    int32_t certify;       /* MIXED, F64_RAND: 1 = cert by an explicit residual pass */
     int32_t reserved;
-    const float *omega;    /* MIXED: device, p x ell Gaussian test matrix, column
+    const float *omega;    /* MIXED, F64_RAND: device, p x ell Gaussian test matrix, column
                               major FP32 (the random draws of the range finder)     */
 } tsvdm_truncate_opts;
 
@@ -134,7 +138,9 @@ typedef struct {
                           the stored values (FP64 products and sums), so it is
                           the error of the factors the caller receives to within
                           ~1e-15 ||Xhat_f||_F; without certify: -1 (FIXED) or
-                          the estimate the energy rule used (ENERGY) */
+                          the estimate the energy rule used (ENERGY).
+                          PREC_F64_RAND: with certify as for MIXED; without,
+                          the estimate sqrt(||Xhat_f||^2 - sum_{j<=k} s_j^2) */
     double *fro;       /* nf or NULL: ||Xhat_f||_F                               */
     int32_t *info;     /* nf or NULL: 0 ok, 1 Jacobi sweep cap reached,
                           2 Cholesky breakdown in the range finder, 3 non-finite,
@@ -381,6 +387,10 @@ size_t tsvdm_truncate_workspace_size(const tsvdm_tensor *Xhat, const tsvdm_trunc
  *               (Q the basis, B = Q^T Xhat_f; a residual pass with the
  *               projection).  With opts->certify, a pass after the factors
  *               computes cert from the stored factors (see tsvdm_factors).
+ *   PREC_F64_RAND: Xhat FP64 (real M); factors F64; the PREC_MIXED steps
+ *               with every product in FP64 (FP64 MFMA, FP64 panels), the
+ *               residual ||Xhat_f - Q B||^2 taken as ||Xhat_f||^2 - ||B||^2;
+ *               finite data below 1e100 in magnitude.
  * out->kmax >= the largest rank that can be returned (k for FIXED, the cap
  * for ENERGY).  The error of the approximation in the original domain is
  * sqrt(sum_f w_f cert_f^2) (w_f = 1, or 2 for DFT faces 0 < f < n3/2). */

@@ -109,9 +109,9 @@ class Truncator:
         if kmax is None:
             ns = min(m, p)
             kmax = min(k if k > 0 else ns, ns)
-            if precision == C.PREC_MIXED:
+            if precision != C.PREC_F64:
                 kmax = min(kmax, k + oversample)
-        fdt = dtype if precision == C.PREC_F64 else torch.float32
+        fdt = torch.float32 if precision == C.PREC_MIXED else dtype
         self.F = empty_factors(m, p, nf, max(kmax, 1), fdt, device)
 
     def __call__(self, xhat: torch.Tensor, stream=None) -> Factors:

@@ -181,6 +181,9 @@ size_t jacobi_workspace(int64_t m, int64_t p, int64_t nf, bool cplx);
 tsvdm_status launch_jacobi_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
                                     tsvdm_factors *F, void *ws, hipStream_t s);
 size_t mixed_workspace(int64_t m, int64_t p, int64_t nf, int ell);
+size_t f64rand_workspace(int64_t m, int64_t p, int64_t nf, int ell);
+tsvdm_status launch_f64rand_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
+                                     void *ws, hipStream_t s);
 tsvdm_status launch_mixed_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
                                    tsvdm_factors *F, void *ws, hipStream_t s);
 tsvdm_status launch_mixed_truncate_noalloc(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,

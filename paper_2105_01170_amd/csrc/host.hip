@@ -305,8 +305,11 @@ static tsvdm_status check_truncate(const tsvdm_tensor *X, const tsvdm_truncate_o
     if (o->max_sweeps < 0) FAIL(TSVDM_EINVAL, "max_sweeps must be >= 0");
     if (o->precision == TSVDM_PREC_F64) {
         if (!is_double(X->dtype)) FAIL(TSVDM_EINVAL, "PREC_F64 needs an F64 or C128 Xhat");
-    } else if (o->precision == TSVDM_PREC_MIXED) {
-        if (X->dtype != TSVDM_F32) FAIL(TSVDM_EUNSUPPORTED, "PREC_MIXED needs a real F32 Xhat");
+    } else if (o->precision == TSVDM_PREC_MIXED || o->precision == TSVDM_PREC_F64_RAND) {
+        if (o->precision == TSVDM_PREC_MIXED && X->dtype != TSVDM_F32)
+            FAIL(TSVDM_EUNSUPPORTED, "PREC_MIXED needs a real F32 Xhat");
+        if (o->precision == TSVDM_PREC_F64_RAND && X->dtype != TSVDM_F64)
+            FAIL(TSVDM_EUNSUPPORTED, "PREC_F64_RAND needs a real F64 Xhat");
         if (o->oversample < 0) FAIL(TSVDM_EINVAL, "oversample must be >= 0");
         if (o->power_iters < 0 || o->power_iters > 1) FAIL(TSVDM_EUNSUPPORTED, "power_iters must be 0 or 1");
         int ell = o->k + o->oversample;
@@ -314,7 +317,7 @@ static tsvdm_status check_truncate(const tsvdm_tensor *X, const tsvdm_truncate_o
         if (ell > X->m || ell > X->p)
             FAIL(TSVDM_EINVAL, "sketch width %d exceeds min(m, p) = %lld", ell,
                  (long long)(X->m < X->p ? X->m : X->p));
-        if (need_data && !o->omega) FAIL(TSVDM_EINVAL, "PREC_MIXED needs the test matrix omega");
+        if (need_data && !o->omega) FAIL(TSVDM_EINVAL, "the randomized truncation needs the test matrix omega");
     } else {
         FAIL(TSVDM_EINVAL, "unknown precision %d", o->precision);
     }
@@ -324,6 +327,7 @@ static tsvdm_status check_truncate(const tsvdm_tensor *X, const tsvdm_truncate_o
 size_t tsvdm_truncate_workspace_size(const tsvdm_tensor *X, const tsvdm_truncate_opts *o) {
     if (check_truncate(X, o, false) != TSVDM_OK) return 0;
     if (o->precision == TSVDM_PREC_F64) return jacobi_workspace(X->m, X->p, X->n3, is_cplx(X->dtype));
+    if (o->precision == TSVDM_PREC_F64_RAND) return f64rand_workspace(X->m, X->p, X->n3, o->k + o->oversample);
     return mixed_workspace(X->m, X->p, X->n3, o->k + o->oversample);
 }
 
@@ -339,10 +343,10 @@ static tsvdm_status check_truncate_out(const tsvdm_tensor *X, const tsvdm_trunca
     int64_t need = o->k;
     if (o->rank_mode == TSVDM_RANK_ENERGY && o->k == 0) need = ns;
     if (need > ns) need = ns;
-    if (o->precision == TSVDM_PREC_MIXED && need > o->k + o->oversample) need = o->k + o->oversample;
+    if (o->precision != TSVDM_PREC_F64 && need > o->k + o->oversample) need = o->k + o->oversample;
     if (F->kmax < need || F->kmax < 1)
         FAIL(TSVDM_EINVAL, "out->kmax (%lld) < largest possible rank (%lld)", (long long)F->kmax, (long long)need);
-    const int32_t want = o->precision == TSVDM_PREC_F64 ? X->dtype : TSVDM_F32;
+    const int32_t want = o->precision == TSVDM_PREC_MIXED ? TSVDM_F32 : X->dtype;
     if (F->dtype != want) FAIL(TSVDM_EINVAL, "factor dtype %d, expected %d", F->dtype, want);
     if (X->m * X->p * X->n3 > 0 && (!F->U || !F->S || !F->V || !F->ranks))
         FAIL(TSVDM_EINVAL, "factor pointers U, S, V, ranks must be set");
@@ -359,6 +363,7 @@ tsvdm_status tsvdm_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
         FAIL(TSVDM_EWORKSPACE, "workspace of %zu bytes needed, %zu given", need_ws, ws_bytes);
     if (X->n3 == 0) return TSVDM_OK;
     if (o->precision == TSVDM_PREC_F64) return launch_jacobi_truncate(X, o, F, ws, (hipStream_t)stream);
+    if (o->precision == TSVDM_PREC_F64_RAND) return launch_f64rand_truncate(X, o, F, ws, (hipStream_t)stream);
     return launch_mixed_truncate(X, o, F, ws, (hipStream_t)stream);
 }
 

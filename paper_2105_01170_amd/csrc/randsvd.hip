@@ -691,6 +691,226 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
     }
 }
 
+// ---------------------------------------------------------------- FP64 passes
+// The passes of the FP64 randomized truncation (PREC_F64_RAND): the same
+// products as above on FP64 data, by FP64 MFMA 16x16x4 (A[i][k]: lane%16 = i,
+// lane/16 = k; B[k][j]: lane/16 = k, lane%16 = j; result row lane/16 + 4v,
+// column lane%16), FP64 accumulation.  Workgroups as above (64 rows, or 64
+// columns, of one face; all LP result columns), K in chunks of 32 staged in
+// LDS, the next chunk's loads issued before the current chunk's products.
+// Loads: consecutive lanes read consecutive rows of one column (512 bytes per
+// wavefront and instruction), addresses clamped, invalid values zeroed.
+
+// FP64 Gram of the 64 x LP block held in the four wavefronts' FP64
+// accumulators (row 16*wave + lane/16 + 4v, column 16*j + lane%16), packed
+// upper tiles as block_gram_f64 writes them.  ys: 64 * (LP + 1) doubles.
+template <int LP>
+__device__ void block_gram_f64d(const f64x4 (&acc)[LP / 16], double *__restrict__ out, double *ys, double *red) {
+    constexpr int NT = LP / 16, NTILE = gram_tiles<LP>(), IPW = (2 * NTILE + 3) / 4;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NT; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) ys[(16 * wave + (lane >> 4) + 4 * v) * (LP + 1) + 16 * j + (lane & 15)] = acc[j][v];
+    __syncthreads();
+    f64x4 g[IPW];
+#pragma unroll
+    for (int u = 0; u < IPW; ++u) {
+        g[u] = f64x4{0, 0, 0, 0};
+        const int it = wave + 4 * u;
+        if (it >= 2 * NTILE) continue;
+        int ti, tj;
+        tile_ij<NT>(it >> 1, ti, tj);
+        const int r0 = 32 * (it & 1);
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+            const int r = r0 + 4 * kk + (lane >> 4);
+            g[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(ys[r * (LP + 1) + 16 * ti + (lane & 15)],
+                                                        ys[r * (LP + 1) + 16 * tj + (lane & 15)], g[u], 0, 0, 0);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < IPW; ++u) {
+        const int it = wave + 4 * u;
+        if (it < 2 * NTILE && (it & 1)) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[(it >> 1) * 256 + 64 * v + lane] = g[u][v];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < IPW; ++u) {
+        const int it = wave + 4 * u;
+        if (it >= 2 * NTILE || (it & 1)) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            out[(it >> 1) * 256 + 64 * v + lane] = g[u][v] + red[(it >> 1) * 256 + 64 * v + lane];
+    }
+    __syncthreads();
+}
+
+template <int LP>
+constexpr int gram64_lds() {  // doubles for the Gram staging and its tile halves
+    return 64 * (LP + 1) > 256 * gram_tiles<LP>() ? 64 * (LP + 1) : 256 * gram_tiles<LP>();
+}
+
+// Y = X W: grid (ceil(m/64) * nf) through xcd_map.  W (p x nw used columns,
+// leading dim ldw, FP32 or FP64) per face (stride w_stride) or shared.
+template <int LP, typename TW, bool GRAM>
+__global__ __launch_bounds__(GT) void k_xw64(const double *__restrict__ X, int m, int p, int nf,
+                                             const TW *__restrict__ W, int64_t w_stride, int ldw, int nw,
+                                             double *__restrict__ Y, double *__restrict__ fro_part,
+                                             double *__restrict__ gram_part) {
+    constexpr int KC = 32, XL = KC + 1, WL = LP + 1, NB = LP / 16, WPT = KC * LP / GT;
+    __shared__ double xs[64 * XL];  // xs[r * XL + k] = X[a0 + r][b0 + k]
+    __shared__ double ws[KC * WL];  // ws[k * WL + c] = W[b0 + k][c]
+    __shared__ double ys[GRAM ? gram64_lds<LP>() : 1];
+    __shared__ double red[GT / 64];
+    const int nb = (m + 63) / 64;
+    int blk, f;
+    xcd_map(blockIdx.x, nb, nf, blk, f);
+    const int a0 = blk * 64, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const double *Xf = X + (int64_t)f * m * p;
+    const TW *Wf = W + (int64_t)f * w_stride;
+    const int xr_ = tid & 63, xc0 = tid >> 6;  // X loads: row a0 + xr_, columns xc0 + 4i
+    const bool rok = a0 + xr_ < m;
+    double xv[KC / 4], wv[WPT];
+    auto load = [&](int b0) {
+#pragma unroll
+        for (int i = 0; i < KC / 4; ++i) {
+            const int b = b0 + xc0 + 4 * i;
+            const bool ok = rok && b < p;
+            const double v = Xf[ok ? (a0 + xr_) + (int64_t)m * b : 0];
+            xv[i] = ok ? v : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int e = tid + q * GT, k = e % KC, c = e / KC, b = b0 + k;
+            const bool ok = c < nw && b < p;
+            const double v = (double)Wf[ok ? b + (int64_t)ldw * c : 0];
+            wv[q] = ok ? v : 0.0;
+        }
+    };
+    f64x4 acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = f64x4{0, 0, 0, 0};
+    double fro = 0.0;
+    load(0);
+    for (int b0 = 0; b0 < p; b0 += KC) {
+#pragma unroll
+        for (int i = 0; i < KC / 4; ++i) {
+            xs[xr_ * XL + xc0 + 4 * i] = xv[i];
+            fro += xv[i] * xv[i];
+        }
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int e = tid + q * GT;
+            ws[(e % KC) * WL + e / KC] = wv[q];
+        }
+        __syncthreads();
+        if (b0 + KC < p) load(b0 + KC);
+        const int ar = 16 * wave + (lane & 15);
+#pragma unroll
+        for (int kk = 0; kk < KC / 4; ++kk) {
+            const int k = 4 * kk + (lane >> 4);
+            const double a = xs[ar * XL + k];
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ws[k * WL + 16 * j + (lane & 15)], acc[j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    double *Yf = Y + (int64_t)f * m * LP;
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = a0 + 16 * wave + (lane >> 4) + 4 * v;
+            if (r < m) Yf[r + (int64_t)m * (16 * j + (lane & 15))] = acc[j][v];
+        }
+    if (GRAM) block_gram_f64d<LP>(acc, gram_part + ((int64_t)f * nb + blk) * LP * LP, ys, ys);
+    if (fro_part) {
+        fro = wave_sum(fro);
+        if (lane == 0) red[wave] = fro;
+        __syncthreads();
+        if (tid == 0) fro_part[(int64_t)f * nb + blk] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+// Z = X^T W: grid (ceil(p/64) * nf) through xcd_map; workgroup: columns
+// b0 .. b0+63 of X (rows of Z), K = m.  W (m x nw, leading dim ldw, FP64)
+// per face (stride w_stride).
+template <int LP, bool GRAM>
+__global__ __launch_bounds__(GT) void k_xtw64(const double *__restrict__ X, int m, int p, int nf,
+                                              const double *__restrict__ W, int64_t w_stride, int ldw, int nw,
+                                              double *__restrict__ Z, double *__restrict__ gram_part) {
+    constexpr int KC = 32, XL = KC + 1, WL = LP + 1, NB = LP / 16, WPT = KC * LP / GT;
+    __shared__ double xs[64 * XL];  // xs[c * XL + k] = X[a0 + k][b0 + c]
+    __shared__ double ws[KC * WL];  // ws[k * WL + j] = W[a0 + k][j]
+    __shared__ double ys[GRAM ? gram64_lds<LP>() : 1];
+    const int nb = (p + 63) / 64;
+    int blk, f;
+    xcd_map(blockIdx.x, nb, nf, blk, f);
+    const int b0 = blk * 64, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const double *Xf = X + (int64_t)f * m * p;
+    const double *Wf = W + (int64_t)f * w_stride;
+    const int xk = tid & 31, xc0 = tid >> 5;  // X loads: row a0 + xk, columns b0 + xc0 + 8i
+    double xv[8], wv[WPT];
+    auto load = [&](int a0) {
+        const bool kok = a0 + xk < m;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int b = b0 + xc0 + 8 * i;
+            const bool ok = kok && b < p;
+            const double v = Xf[ok ? (a0 + xk) + (int64_t)m * b : 0];
+            xv[i] = ok ? v : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int e = tid + q * GT, k = e % KC, c = e / KC, a = a0 + k;
+            const bool ok = c < nw && a < m;
+            const double v = Wf[ok ? a + (int64_t)ldw * c : 0];
+            wv[q] = ok ? v : 0.0;
+        }
+    };
+    f64x4 acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[j] = f64x4{0, 0, 0, 0};
+    load(0);
+    for (int a0 = 0; a0 < m; a0 += KC) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) xs[(xc0 + 8 * i) * XL + xk] = xv[i];
+#pragma unroll
+        for (int q = 0; q < WPT; ++q) {
+            const int e = tid + q * GT;
+            ws[(e % KC) * WL + e / KC] = wv[q];
+        }
+        __syncthreads();
+        if (a0 + KC < m) load(a0 + KC);
+        const int cr = 16 * wave + (lane & 15);
+#pragma unroll
+        for (int kk = 0; kk < KC / 4; ++kk) {
+            const int k = 4 * kk + (lane >> 4);
+            const double a = xs[cr * XL + k];
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, ws[k * WL + 16 * j + (lane & 15)], acc[j], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    double *Zf = Z + (int64_t)f * p * LP;
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = b0 + 16 * wave + (lane >> 4) + 4 * v;
+            if (r < p) Zf[r + (int64_t)p * (16 * j + (lane & 15))] = acc[j][v];
+        }
+    if (GRAM) block_gram_f64d<LP>(acc, gram_part + ((int64_t)f * nb + blk) * LP * LP, ys, ys);
+}
+
 // ---------------------------------------------------------------- Cholesky-QR
 // Orthonormal basis Q (rows x LP, FP32, columns >= ell zero) of the rows x ell
 // panel S by shifted Cholesky-QR (Fukaya et al. 2020): G = S^T S (+ shift on
@@ -707,22 +927,26 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
 //    when the panel fits in one chunk of QT rows.
 constexpr int QT = 512;
 
-template <int LP>
-__global__ __launch_bounds__(QT) void k_cholqr(const float *__restrict__ Sin, int rows, int ell,
-                                               float *__restrict__ Qout, int passes,
+// T: the panel's element type (FP32 in the mixed path, FP64 in the FP64
+// randomized path, which stages fewer rows per LDS pass).
+template <int LP, typename T = float>
+__global__ __launch_bounds__(QT) void k_cholqr(const T *__restrict__ Sin, int rows, int ell,
+                                               T *__restrict__ Qout, int passes,
                                                const double *__restrict__ gpart, int nparts,
                                                int32_t *__restrict__ qr_info, int first) {
-    constexpr int LDG = LP + 1, LDR = LP + 2, LDS_ = LP + 1, HR = LP <= 48 ? QT : QT / 2;
+    constexpr bool D = sizeof(T) == 8;
+    constexpr int LDG = LP + 1, LDR = LP + 2, LDS_ = LP + 1;
+    constexpr int HR = D ? (LP <= 32 ? QT / 2 : QT / 4) : (LP <= 48 ? QT : QT / 2);
     constexpr int NT = LP / 16, NTILE = NT * (NT + 1) / 2, TPW = (NTILE + 7) / 8;
     __shared__ double G[LP * LDG];
     __shared__ __align__(16) double Rt[LP * LDR];  // Rt[c * LDR + j] = R[j][c]
     __shared__ double rinv[LP];
-    __shared__ float st[HR * LDS_];  // FP32 rows of the chunk (or half of it) for the Gram
+    __shared__ T st[HR * LDS_];  // rows of the chunk (or part of it) for the Gram
     __shared__ double trace_s;
     __shared__ int bad;
     const int f = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const float *S = Sin + (int64_t)f * rows * LP;
-    float *Q = Qout + (int64_t)f * rows * LP;
+    const T *S = Sin + (int64_t)f * rows * LP;
+    T *Q = Qout + (int64_t)f * rows * LP;
     if (tid == 0) bad = 0;
 
     // ---- first Gram: ordered sum of the partials
@@ -730,19 +954,24 @@ __global__ __launch_bounds__(QT) void k_cholqr(const float *__restrict__ Sin, in
     __syncthreads();
 
     const int nch = (rows + QT - 1) / QT;
-    float x[LP];
+    T x[LP];
     for (int pass = 0; pass < passes; ++pass) {
-        // ---- shift of the first pass: 11 (rows*ell + ell(ell+1)) u tr(G), u = 2^-53
+        // ---- the rounding level of the Gram, 11 (rows*ell + ell(ell+1)) u tr(G)
+        // (u = 2^-53): the first pass adds it to the diagonal as the shift;
+        // later passes, on a basis the shifted pass has already equilibrated,
+        // take a pivot at or below it as a numerically dependent direction
+        // and drop it (zero column of Q, no flag) instead of dividing by it
+        if (wave == 0) {
+            double t = 0.0;
+            for (int c = lane; c < ell; c += 64) t += G[c * LDG + c];
+            t = wave_sum(t);
+            if (lane == 0) trace_s = t;
+        }
+        __syncthreads();
+        const double level = 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * 0x1p-53 * trace_s;
+        const double pfloor = pass == 0 ? 0.0 : level;
         if (pass == 0) {
-            if (wave == 0) {
-                double t = 0.0;
-                for (int c = lane; c < ell; c += 64) t += G[c * LDG + c];
-                t = wave_sum(t);
-                if (lane == 0) trace_s = t;
-            }
-            __syncthreads();
-            const double sh = 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * 0x1p-53 * trace_s;
-            if (tid < ell) G[tid * LDG + tid] += sh;
+            if (tid < ell) G[tid * LDG + tid] += level;
             __syncthreads();
         }
         // ---- Cholesky of the leading ell x ell block.  Step j subtracts the
@@ -769,7 +998,7 @@ __global__ __launch_bounds__(QT) void k_cholqr(const float *__restrict__ Sin, in
             for (int j = 0; j < ell; ++j) {
                 const int cnt = (ell - j - 1) * (ell - j) / 2;  // entries with i > j
                 const double piv = G[j * LDG + j];
-                const double ipv = piv > 0.0 && isfinite(piv) ? recip(piv) : 0.0;
+                const double ipv = piv > pfloor && isfinite(piv) ? recip(piv) : 0.0;
 #pragma unroll
                 for (int u = 0; u < UPT; ++u) {
                     if (u * QT + (tid & ~63) >= cnt) break;  // whole wavefront past the prefix
@@ -781,18 +1010,21 @@ __global__ __launch_bounds__(QT) void k_cholqr(const float *__restrict__ Sin, in
                 }
                 __syncthreads();
             }
-            // R[j][c] = G[j][c] / sqrt(G[j][j]), c >= j; a non-positive pivot
-            // (rank deficiency beyond the shift) gives a unit row and a flag
+            // R[j][c] = G[j][c] / sqrt(G[j][j]), c >= j.  A pivot at or below
+            // the floor of a later pass drops direction j (rinv 0: a zero
+            // column, skipped by the elimination above); a non-positive pivot
+            // of the shifted pass (a zero or non-finite panel) gives a unit
+            // row and the flag
             for (int e = tid; e < ell * ell; e += QT) {
                 const int j = e / ell, c = e % ell;
                 if (c < j) continue;
                 const double piv = G[j * LDG + j];
-                const bool ok = piv > 0.0 && isfinite(piv);
+                const bool fin = isfinite(piv), ok = fin && piv > pfloor, drop = fin && !ok && pass > 0;
                 const double d = ok ? sqrt(piv) : 1.0;
                 Rt[c * LDR + j] = ok ? G[j * LDG + c] / d : (c == j ? 1.0 : 0.0);
                 if (c == j) {
-                    rinv[j] = 1.0 / d;
-                    if (!ok) bad = 1;
+                    rinv[j] = drop ? 0.0 : 1.0 / d;
+                    if (!ok && !drop) bad = 1;
                 }
             }
             __syncthreads();
@@ -805,12 +1037,12 @@ __global__ __launch_bounds__(QT) void k_cholqr(const float *__restrict__ Sin, in
         for (int ch = 0; ch < nch; ++ch) {
             const int row = ch * QT + tid;
             if (pass == 0 || nch > 1) {
-                const float *src = (pass == 0 ? S : Q) + (row < rows ? row : rows - 1);
+                const T *src = (pass == 0 ? S : Q) + (row < rows ? row : rows - 1);
 #pragma unroll
                 for (int c = 0; c < LP; ++c) x[c] = src[(int64_t)rows * c];
                 if (row >= rows) {
 #pragma unroll
-                    for (int c = 0; c < LP; ++c) x[c] = 0.0f;
+                    for (int c = 0; c < LP; ++c) x[c] = (T)0;
                 }
             }
             double qd[LP];
@@ -834,7 +1066,7 @@ __global__ __launch_bounds__(QT) void k_cholqr(const float *__restrict__ Sin, in
                 } else {
                     qd[c] = 0.0;
                 }
-                x[c] = (float)qd[c];
+                x[c] = (T)qd[c];
             }
             if (row < rows) {
 #pragma unroll
@@ -895,6 +1127,8 @@ __global__ __launch_bounds__(QT) void k_cholqr(const float *__restrict__ Sin, in
 //   cert^2 = ||X - Q B||^2 + sum_{j > k_f} lambda_j
 // (the error of Q U_B[:, :k] U_B[:, :k]^T B, since Q has orthonormal columns).
 // The energy rule takes the smallest k whose certified error meets tau.
+// nres < 0 (FP64 data): ||X - Q B||^2 is taken as ||X||^2 - sum_j lambda_j,
+// accurate to ~1e-16 ||X||^2, far below any tolerance tau^2 ||X||^2 in use.
 // jtol: the Jacobi solver's absolute threshold over the trace.  The sums
 // above use the diagonal of the rotated matrix, E^T (B B^T) E, and equal
 // ||B - E_k E_k^T B||^2 for the orthogonal E the solver returns whether or
@@ -958,6 +1192,11 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
         double fro2 = 0.0, res = 0.0;
         for (int i = 0; i < nfro; ++i) fro2 += fro_part[(int64_t)f * nfro + i];
         for (int i = 0; i < nres; ++i) res += res_part[(int64_t)f * nres + i];
+        if (nres < 0) {  // FP64 data: ||X - Q B||^2 = ||X||^2 - ||B||^2 (Q orthonormal)
+            double b2 = 0.0;
+            for (int j = 0; j < ell; ++j) b2 += lam[j];
+            res = fmax(fro2 - b2, 0.0);
+        }
         int kf, miss = 0;
         if (mode == TSVDM_RANK_FIXED) {
             kf = kfix < ell ? kfix : ell;
@@ -979,7 +1218,7 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
         for (int j = ell - 1; j >= kf; --j) disc += lam[perm[j]];
         kf_out[f] = kf;
         fro2_out[f] = fro2;
-        if (cert) cert[fmap ? fmap[f] : f] = nres > 0 ? sqrt(res + disc) : -1.0;
+        if (cert) cert[fmap ? fmap[f] : f] = nres != 0 ? sqrt(res + disc) : -1.0;
         // bit 0: sweep cap reached; bit 2: energy target missed at the cap
         jinfo[f] = ((conv || ell <= 1) ? 0 : 1) | (miss ? 4 : 0);
     }
@@ -1000,8 +1239,21 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
 // product (U_B^T Q^T), so that a lane's four results are consecutive rows; the
 // inputs Q and B^T are FP32 and U_B is rounded to FP32, which adds an error of
 // the order of the FP32 rounding of the inputs themselves.
-template <int LP>
-__global__ __launch_bounds__(GT) void k_factors(const float *__restrict__ Q, const float *__restrict__ Bt,
+template <typename T>
+struct Acc4;
+template <>
+struct Acc4<float> {
+    typedef f32x4 type;
+};
+template <>
+struct Acc4<double> {
+    typedef f64x4 type;
+};
+
+// T: element type of Q, B^T and the factors (FP32 mixed, FP64 randomized);
+// FP64 uses the FP64 MFMA, whose output holds row lane/16 + 4v.
+template <int LP, typename T = float>
+__global__ __launch_bounds__(GT) void k_factors(const T *__restrict__ Q, const T *__restrict__ Bt,
                                                 int m, int p, int ell, int64_t kmax,
                                                 const double *__restrict__ UB,
                                                 const double *__restrict__ sig,
@@ -1010,26 +1262,28 @@ __global__ __launch_bounds__(GT) void k_factors(const float *__restrict__ Q, con
                                                 const double *__restrict__ fro2,
                                                 const int32_t *__restrict__ qr_info,
                                                 const int32_t *__restrict__ jinfo,
-                                                float *__restrict__ Uo, double *__restrict__ So,
-                                                float *__restrict__ Vo, int32_t *__restrict__ ranks,
+                                                T *__restrict__ Uo, double *__restrict__ So,
+                                                T *__restrict__ Vo, int32_t *__restrict__ ranks,
                                                 double *__restrict__ fro, int32_t *__restrict__ info,
     const int32_t *__restrict__ fmap) {
     constexpr int LU = LP + 1, NT = LP / 16;
-    __shared__ float ubs[LP * LU];  // ubs[r * LU + c] = U_B[c, perm[r]] (/ s_r for V), zero for r >= k_f
+    constexpr bool D = sizeof(T) == 8;
+    typedef typename Acc4<T>::type V4;
+    __shared__ T ubs[LP * LU];  // ubs[r * LU + c] = U_B[c, perm[r]] (/ s_r for V), zero for r >= k_f
     const int f = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int fd = fmap ? fmap[f] : f;
     const int kf = kf_in[f], nbu = (m + 63) / 64;
     const bool isv = (int)blockIdx.x >= nbu;
     const int blk = isv ? blockIdx.x - nbu : blockIdx.x, rows = isv ? p : m;
-    const float *S = isv ? Bt + (int64_t)f * p * LP : Q + (int64_t)f * m * LP;  // rows x LP, column major
-    float *O = isv ? Vo + (int64_t)fd * p * kmax : Uo + (int64_t)fd * m * kmax;
+    const T *S = isv ? Bt + (int64_t)f * p * LP : Q + (int64_t)f * m * LP;  // rows x LP, column major
+    T *O = isv ? Vo + (int64_t)fd * p * kmax : Uo + (int64_t)fd * m * kmax;
     for (int e = tid; e < LP * LP; e += GT) {
         const int r = e / LP, c = e % LP;
-        float u = 0.0f;
+        T u = (T)0;
         if (r < kf && c < ell) {
             const double v = UB[(int64_t)f * LP * LP + c + (int64_t)LP * perm[(int64_t)f * LP + r]];
             const double s = sig[(int64_t)f * LP + r];
-            u = (float)(isv ? (s > 0.0 ? v / s : 0.0) : v);
+            u = (T)(isv ? (s > 0.0 ? v / s : 0.0) : v);
         }
         ubs[r * LU + c] = u;
     }
@@ -1038,28 +1292,30 @@ __global__ __launch_bounds__(GT) void k_factors(const float *__restrict__ Q, con
     const int nt = (kc + 15) / 16;                   // their 16-column tiles
     const int row0 = blk * 64 + 16 * wave, jr = row0 + (lane & 15), kl = lane >> 4;
     const bool rok = jr < rows;
-    f32x4 acc[NT];
+    V4 acc[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0, 0, 0, 0};
+    for (int t = 0; t < NT; ++t) acc[t] = V4{0, 0, 0, 0};
 #pragma unroll
     for (int kk = 0; kk < LP / 4; ++kk) {
         if (4 * kk >= ell) break;  // columns past ell of U_B^T are zero
-        const float x = S[rok ? jr + (int64_t)rows * (4 * kk + kl) : 0];
-        const float bq = rok ? x : 0.0f;
+        const T x = S[rok ? jr + (int64_t)rows * (4 * kk + kl) : 0];
+        const T bq = rok ? x : (T)0;
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             if (t >= nt) break;
-            const float a = ubs[(16 * t + (lane & 15)) * LU + 4 * kk + kl];
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bq, acc[t], 0, 0, 0);
+            const T a = ubs[(16 * t + (lane & 15)) * LU + 4 * kk + kl];
+            if constexpr (D) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bq, acc[t], 0, 0, 0);
+            else acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bq, acc[t], 0, 0, 0);
         }
     }
-    // result (r = 16t + 4*(lane/16) + v, row = row0 + lane%16)
+    // result (r = 16t + 4*(lane/16) + v for FP32, 16t + lane/16 + 4v for FP64;
+    // row = row0 + lane%16)
 #pragma unroll
     for (int t = 0; t < NT; ++t) {
         if (t >= nt) break;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int r = 16 * t + 4 * kl + v;
+            const int r = 16 * t + (D ? kl + 4 * v : 4 * kl + v);
             if (rok && r < kmax) O[jr + (int64_t)rows * r] = acc[t][v];
         }
     }
@@ -1067,7 +1323,7 @@ __global__ __launch_bounds__(GT) void k_factors(const float *__restrict__ Q, con
     const int64_t zc = kmax - 16 * nt;
     for (int64_t e = tid; e < 64 * zc; e += GT) {
         const int row = blk * 64 + (int)(e % 64);
-        if (row < rows) O[row + (int64_t)rows * (16 * nt + e / 64)] = 0.0f;
+        if (row < rows) O[row + (int64_t)rows * (16 * nt + e / 64)] = (T)0;
     }
     if (blockIdx.x == 0) {
         for (int r = tid; r < kmax; r += GT) So[(int64_t)fd * kmax + r] = r < kf ? sig[(int64_t)f * LP + r] : 0.0;
@@ -1100,16 +1356,17 @@ __global__ __launch_bounds__(GT) void k_factors(const float *__restrict__ Q, con
 // S_r scaling of W is applied as the operand is read).  Wavefront w owns rows a0 + 16w .. +15 and four 16-column output tiles
 // (independent accumulators); the FP64 output layout (row lane/16 + 4v,
 // column lane%16) picks the X values from LDS.
-template <int KP, bool VEC>
-__global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_resid(const float *__restrict__ X, int m, int p, int nf,
-                                              const float *__restrict__ U, const double *__restrict__ S,
-                                              const float *__restrict__ V, int64_t kmax,
+// T: element type of X and the factors (FP32 mixed, FP64 randomized).
+template <int KP, bool VEC, typename T = float>
+__global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_resid(const T *__restrict__ X, int m, int p, int nf,
+                                              const T *__restrict__ U, const double *__restrict__ S,
+                                              const T *__restrict__ V, int64_t kmax,
                                               const int32_t *__restrict__ ranks, double *__restrict__ res_part,
                                               const int32_t *__restrict__ fmap) {
     constexpr int NS = KP / 4, XP = 66, VPT = KP / 4;  // V loads per thread per chunk
-    __shared__ float xs[64 * XP];    // xs[c * XP + r] = X[a0 + r][b0 + c]
+    __shared__ T xs[64 * XP];    // xs[c * XP + r] = X[a0 + r][b0 + c]
     constexpr int WP = 80;  // rows 4 apart fall 16 banks apart
-    __shared__ float ws[KP * WP];    // ws[r * WP + c] = V[b0 + c][r]
+    __shared__ T ws[KP * WP];    // ws[r * WP + c] = V[b0 + c][r]
     __shared__ double ss[KP];        // S_r
     __shared__ double red[GT / 64];
     const int nb = (m + 63) / 64;
@@ -1119,9 +1376,9 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     const int a0 = blk * 64;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int kf = ranks[fd] < KP ? ranks[fd] : KP, ns = (kf + 3) / 4;
-    const float *Xf = X + (int64_t)fd * m * p;
-    const float *Uf = U + (int64_t)fd * m * kmax;
-    const float *Vf = V + (int64_t)fd * p * kmax;
+    const T *Xf = X + (int64_t)fd * m * p;
+    const T *Uf = U + (int64_t)fd * m * kmax;
+    const T *Vf = V + (int64_t)fd * p * kmax;
     const double *Sf = S + (int64_t)fd * kmax;
     double ua[NS];  // A operands: Uhat[a0 + 16 wave + lane%16][4 s + lane/16]
     {
@@ -1136,22 +1393,32 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if (tid < KP) ss[tid] = tid < kf ? Sf[tid] : 0.0;
     // chunk loads: X rows a0 + 4 (tid%16) .. +3 of columns b0 + tid/16 + 16 it;
     // V row b0 + tid%64 of ranks tid/64 + 4 q
-    float xr[16], vr[VPT];
+    T xr[16], vr[VPT];
     auto load = [&](int b0) {
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
             const int b = b0 + xc + 16 * it, a = a0 + 4 * xq;
             if constexpr (VEC) {
                 const bool ok = b < p && a < m;  // then a + 3 < m
-                const f32x4 v = *reinterpret_cast<const f32x4 *>(Xf + (ok ? a + (int64_t)m * b : 0));
+                const T *src = Xf + (ok ? a + (int64_t)m * b : 0);
+                if constexpr (sizeof(T) == 8) {
+                    const double2 v0 = *reinterpret_cast<const double2 *>(src);
+                    const double2 v1 = *reinterpret_cast<const double2 *>(src + 2);
+                    xr[4 * it + 0] = ok ? v0.x : 0.0;
+                    xr[4 * it + 1] = ok ? v0.y : 0.0;
+                    xr[4 * it + 2] = ok ? v1.x : 0.0;
+                    xr[4 * it + 3] = ok ? v1.y : 0.0;
+                } else {
+                    const f32x4 v = *reinterpret_cast<const f32x4 *>(src);
 #pragma unroll
-                for (int u = 0; u < 4; ++u) xr[4 * it + u] = ok ? v[u] : 0.0f;
+                    for (int u = 0; u < 4; ++u) xr[4 * it + u] = ok ? v[u] : 0.0f;
+                }
             } else {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const bool ok = b < p && a + u < m;
-                    const float v = Xf[ok ? a + u + (int64_t)m * b : 0];
-                    xr[4 * it + u] = ok ? v : 0.0f;
+                    const T v = Xf[ok ? a + u + (int64_t)m * b : 0];
+                    xr[4 * it + u] = ok ? v : (T)0;
                 }
             }
         }
@@ -1159,8 +1426,8 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         for (int q = 0; q < VPT; ++q) {
             const int r = vr0 + 4 * q, b = b0 + vc;
             const bool ok = r < kf && b < p;
-            const float v = Vf[ok ? b + (int64_t)p * r : 0];
-            vr[q] = ok ? v : 0.0f;
+            const T v = Vf[ok ? b + (int64_t)p * r : 0];
+            vr[q] = ok ? v : (T)0;
         }
     };
     double racc = 0.0;
@@ -1221,7 +1488,8 @@ struct MixedWs {
     int32_t *qr_info, *jinfo;
 };
 
-size_t carve(char *base, int64_t m, int64_t p, int64_t nf, int LP, MixedWs *w) {
+// esz: bytes per element of the panels Y, Q, Z, Qz (4 mixed, 8 FP64 randomized)
+size_t carve(char *base, int64_t m, int64_t p, int64_t nf, int LP, MixedWs *w, int esz = 4) {
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
         char *ptr = base ? base + off : nullptr;
@@ -1230,10 +1498,10 @@ size_t carve(char *base, int64_t m, int64_t p, int64_t nf, int LP, MixedWs *w) {
     };
     const int64_t mparts = (m + 63) / 64, pparts = (p + 63) / 64;
     MixedWs t;
-    t.Y = (float *)take(sizeof(float) * nf * m * LP);
-    t.Qm = (float *)take(sizeof(float) * nf * m * LP);
-    t.Z = (float *)take(sizeof(float) * nf * p * LP);
-    t.Qp = (float *)take(sizeof(float) * nf * p * LP);
+    t.Y = (float *)take((size_t)esz * nf * m * LP);
+    t.Qm = (float *)take((size_t)esz * nf * m * LP);
+    t.Z = (float *)take((size_t)esz * nf * p * LP);
+    t.Qp = (float *)take((size_t)esz * nf * p * LP);
     t.gram_m = (double *)take(sizeof(double) * nf * mparts * LP * LP);
     t.gram_p = (double *)take(sizeof(double) * nf * pparts * LP * LP);
     t.fro_part = (double *)take(sizeof(double) * nf * mparts);
@@ -1493,6 +1761,83 @@ tsvdm_status run_mixed(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     return run_group<LP>(X, o, F, w, 0, (int)X->n3, s);
 }
 
+// ---------------------------------------------------------------- FP64 randomized
+// PREC_F64_RAND: the randomized range finder of the mixed path with every
+// product in FP64 (FP64 MFMA) on an FP64 Xhat: Y = X Omega, Q = qr(Y),
+// Z = X^T Q, Qz = qr(Z), Y = X Qz, Q = qr(Y) (each shifted Cholesky-QR2),
+// B^T = X^T Q, core eigensolver of B B^T, factors, and the certificate of the
+// stored factors as in the mixed path (or, without certify, the estimate
+// sqrt(||X||^2 - sum_{j<=k} lambda_j)).
+constexpr double kJacobiTolF64 = 1e-15;
+template <int LP>
+tsvdm_status run_f64rand(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F, void *wsp,
+                         hipStream_t s) {
+    const int m = (int)X->m, p = (int)X->p, nf = (int)X->n3, ell = o->k + o->oversample;
+    const int mparts = (m + 63) / 64, pparts = (p + 63) / 64;
+    const int64_t kmax = F->kmax;
+    MixedWs w;
+    carve(reinterpret_cast<char *>(wsp), m, p, nf, LP, &w, 8);
+    double *Y = reinterpret_cast<double *>(w.Y), *Qm = reinterpret_cast<double *>(w.Qm);
+    double *Z = reinterpret_cast<double *>(w.Z), *Qp = reinterpret_cast<double *>(w.Qp);
+    const double *Xd = reinterpret_cast<const double *>(X->data);
+    double *Uo = reinterpret_cast<double *>(F->U), *Vo = reinterpret_cast<double *>(F->V);
+    const dim3 gm((unsigned)(mparts * nf)), gp((unsigned)(pparts * nf));
+    const bool power = o->power_iters > 0;
+    const bool exact = o->certify && F->cert;
+    TSVDM_LAUNCH("f64_sketch_xw", (k_xw64<LP, float, true>), gm, dim3(GT), 0, s, Xd, m, p, nf, o->omega,
+                 (int64_t)0, p, ell, Y, w.fro_part, w.gram_m);
+    if (power) {
+        // both intermediate bases are made orthonormal (two passes): a single
+        // shifted pass leaves columns of norm ~sqrt(shift) along directions
+        // below the shift, and on FP64 data (no FP32 rounding floor) two such
+        // steps in a row push the final sketch's condition number past 1/u
+        TSVDM_LAUNCH("f64_cholqr_sketch", (k_cholqr<LP, double>), dim3(nf), dim3(QT), 0, s, (const double *)Y, m,
+                     ell, Qm, 2, (const double *)w.gram_m, mparts, w.qr_info, 1);
+        TSVDM_LAUNCH("f64_power_xtw", (k_xtw64<LP, true>), gp, dim3(GT), 0, s, Xd, m, p, nf, (const double *)Qm,
+                     (int64_t)m * LP, m, ell, Z, w.gram_p);
+        TSVDM_LAUNCH("f64_cholqr_power_z", (k_cholqr<LP, double>), dim3(nf), dim3(QT), 0, s, (const double *)Z,
+                     p, ell, Qp, 2, (const double *)w.gram_p, pparts, w.qr_info, 0);
+        TSVDM_LAUNCH("f64_power_xw", (k_xw64<LP, double, true>), gm, dim3(GT), 0, s, Xd, m, p, nf,
+                     (const double *)Qp, (int64_t)p * LP, p, ell, Y, (double *)nullptr, w.gram_m);
+    }
+    TSVDM_LAUNCH("f64_cholqr_final", (k_cholqr<LP, double>), dim3(nf), dim3(QT), 0, s, (const double *)Y, m, ell,
+                 Qm, 2, (const double *)w.gram_m, mparts, w.qr_info, power ? 0 : 1);
+    TSVDM_LAUNCH("f64_project_xtw", (k_xtw64<LP, true>), gp, dim3(GT), 0, s, Xd, m, p, nf, (const double *)Qm,
+                 (int64_t)m * LP, m, ell, Z, w.gram_p);
+    const int msw = o->max_sweeps > 0 ? o->max_sweeps : 30;
+    TSVDM_LAUNCH("f64_core_gram_eig", (k_core<LP>), dim3(nf), dim3(QT), 0, s, (const double *)w.gram_p, pparts,
+                 ell, (const double *)w.fro_part, mparts, (const double *)nullptr, -1, o->rank_mode, o->k, o->tau,
+                 msw, kJacobiTolF64, w.UB, w.sig, w.perm, w.kf, w.fro2, exact ? (double *)nullptr : F->cert,
+                 w.jinfo, (const int32_t *)nullptr);
+    TSVDM_LAUNCH("f64_factors", (k_factors<LP, double>), dim3((unsigned)(mparts + pparts), nf), dim3(GT), 0, s,
+                 (const double *)Qm, (const double *)Z, m, p, ell, kmax, w.UB, w.sig, w.perm, w.kf, w.fro2,
+                 w.qr_info, w.jinfo, Uo, F->S, Vo, F->ranks, F->fro, F->info, (const int32_t *)nullptr);
+    if (exact) {
+        const int kcap = (int)(kmax < ell ? kmax : ell);
+        const bool xv = m % 4 == 0 && reinterpret_cast<uintptr_t>(Xd) % 16 == 0;
+#define TSVDM_RESID64(KP)                                                                                       \
+    do {                                                                                                        \
+        if (xv)                                                                                                 \
+            TSVDM_LAUNCH("f64_resid_factors", (k_resid<KP, true, double>), gm, dim3(GT), 0, s, Xd, m, p, nf,    \
+                         (const double *)Uo, (const double *)F->S, (const double *)Vo, kmax,                   \
+                         (const int32_t *)F->ranks, w.cert_part, (const int32_t *)nullptr);                    \
+        else                                                                                                    \
+            TSVDM_LAUNCH("f64_resid_factors", (k_resid<KP, false, double>), gm, dim3(GT), 0, s, Xd, m, p, nf,   \
+                         (const double *)Uo, (const double *)F->S, (const double *)Vo, kmax,                   \
+                         (const int32_t *)F->ranks, w.cert_part, (const int32_t *)nullptr);                    \
+    } while (0)
+        if (kcap <= 16) TSVDM_RESID64(16);
+        else if (kcap <= 32) TSVDM_RESID64(32);
+        else if (kcap <= 48) TSVDM_RESID64(48);
+        else TSVDM_RESID64(64);
+#undef TSVDM_RESID64
+        TSVDM_LAUNCH("f64_cert", k_cert, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s,
+                     (const double *)w.cert_part, mparts, nf, F->cert, (const int32_t *)nullptr);
+    }
+    TSVDM_LAUNCH_CHECK("FP64 randomized truncate");
+    return TSVDM_OK;
+}
+
 // ---------------------------------------------------------------- no allocation
 // Scratch of tsvdm_truncate_noalloc: one copy per GPU (each device holds its
 // own instance of this array at its own address), kept until the process
@@ -1578,6 +1923,24 @@ tsvdm_status launch_mixed_truncate(const tsvdm_tensor *X, const tsvdm_truncate_o
         case 32: return run_mixed<32>(X, o, F, ws, s);
         case 48: return run_mixed<48>(X, o, F, ws, s);
         default: return run_mixed<64>(X, o, F, ws, s);
+    }
+}
+
+size_t f64rand_workspace(int64_t m, int64_t p, int64_t nf, int ell) {
+    return carve(nullptr, m, p, nf, padded(ell), nullptr, 8);
+}
+
+tsvdm_status launch_f64rand_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
+                                     void *ws, hipStream_t s) {
+    if (X->m > 65536 || X->p > 65536 || X->n3 > 65535) {
+        set_error("PREC_F64_RAND: face dims up to 65536 and up to 65535 faces");
+        return TSVDM_EUNSUPPORTED;
+    }
+    switch (padded(o->k + o->oversample)) {
+        case 16: return run_f64rand<16>(X, o, F, ws, s);
+        case 32: return run_f64rand<32>(X, o, F, ws, s);
+        case 48: return run_f64rand<48>(X, o, F, ws, s);
+        default: return run_f64rand<64>(X, o, F, ws, s);
     }
 }
 

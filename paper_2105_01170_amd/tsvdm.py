@@ -19,7 +19,7 @@ OK, EINVAL, EUNSUPPORTED, EWORKSPACE, EDEVICE = 0, 1, 2, 3, 4
 F64, F32, BF16, C64, C128 = 0, 1, 2, 3, 4
 M_DCT2, M_DFT, M_DENSE = 0, 1, 2
 RANK_FIXED, RANK_ENERGY = 0, 1
-PREC_F64, PREC_MIXED = 0, 1
+PREC_F64, PREC_MIXED, PREC_F64_RAND = 0, 1, 2
 (PLACE_GENERIC, PLACE_DIAGONAL, PLACE_BANDED, PLACE_BANDED_SYM, PLACE_TOEPLITZ, PLACE_TOEPLITZ_SYM,
  PLACE_HANKEL) = range(7)
 
