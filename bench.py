@@ -54,6 +54,18 @@ def parse():
                          "(profiling: timings under a profiler mislead the tuner)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration under rocprofv3)")
+    ps = ap.add_argument_group("profile summary (no GPU: writes a markdown summary of rocprofv3 CSV output)")
+    ps.add_argument("--profile-summary", action="store_true")
+    ps.add_argument("--pattern", choices=sorted(STEP_PATTERNS), default="mixed")
+    ps.add_argument("--trace-dir")
+    ps.add_argument("--fetch-dir")
+    ps.add_argument("--write-dir")
+    ps.add_argument("--mfma-dir", default="")
+    ps.add_argument("--last-steps", type=int, default=10)
+    ps.add_argument("--title", default="")
+    ps.add_argument("--description", default="")
+    ps.add_argument("--cmd", action="append", default=[])
+    ps.add_argument("--out")
     return ap.parse_args()
 
 
@@ -574,8 +586,188 @@ def mlp_widths(y):
     return k, w
 
 
+# ---------------------------------------------------------------- profile summaries
+# Launch sequence of one step of each profiled workload: (launch name as the
+# library's timing table names it, kernel name in a rocprofv3 -T trace).
+STEP_PATTERNS = {
+    "mixed": [("transform_fft", "k_fft_tubes"), ("sketch_xw_bf16", "k_xw"), ("cholqr_sketch", "k_cholqr"),
+              ("power_xtw_bf16", "k_xtw"), ("cholqr_power_z", "k_cholqr"), ("power_xw_split", "k_xw"),
+              ("cholqr_final", "k_cholqr"), ("project_xtw_split", "k_xtw"), ("core_gram_eig", "k_core"),
+              ("factors", "k_factors"), ("resid_factors", "k_resid"), ("cert", "k_cert")],
+    "f64rand": [("transform_fft", "k_fft_tubes"), ("f64_sketch_xw", "k_xw64"), ("f64_cholqr_sketch", "k_cholqr"),
+                ("f64_power_xtw", "k_xtw64"), ("f64_cholqr_power_z", "k_cholqr"), ("f64_power_xw", "k_xw64"),
+                ("f64_cholqr_final", "k_cholqr"), ("f64_project_xtw", "k_xtw64"),
+                ("f64_core_gram_eig", "k_core"), ("f64_factors", "k_factors"),
+                ("f64_resid_factors", "k_resid"), ("f64_cert", "k_cert")],
+    "apply": [("transform_fft", "k_fft_tubes"), ("apply_v_relayout", "k_vrelayout"),
+              ("apply_fused", "k_apply_lds")],
+    "uneven": [("transform_direct_batched[0]", "k_direct_batched_dct"), ("batched_reset", "k_bzero"),
+               ("batched_gram", "k_bgram"), ("batched_core", "k_bcore16"), ("batched_core_deferred", "k_bcore32"),
+               ("batched_vec", "k_bvec")],
+}
+MFMA_PEAK_TFLOPS = {"BF16": 2500.0, "F32": 157.3, "F64": 78.6}
+
+
+def _read_csv(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def _find_csv(d, suffix):
+    import glob
+    hits = sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def _pmc_dispatches(d):
+    """[(kernel name, {counter: value})] in dispatch order from a --pmc run."""
+    rows = _read_csv(_find_csv(d, "_counter_collection.csv"))
+    order, by = [], {}
+    for r in rows:
+        did = int(r["Dispatch_Id"])
+        if did not in by:
+            by[did] = (r["Kernel_Name"], {})
+            order.append(did)
+        by[did][1][r["Counter_Name"]] = by[did][1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return [by[i] for i in order]
+
+
+def _match_steps(names, pattern):
+    """Start indices of the non-overlapping occurrences of the pattern's kernel
+    names (None matches any kernel whose name starts with 'k_')."""
+    want = [k for _, k in pattern]
+    out, i = [], 0
+    while i + len(want) <= len(names):
+        if all((w is None and names[i + j].startswith("k_")) or names[i + j] == w for j, w in enumerate(want)):
+            out.append(i)
+            i += len(want)
+        else:
+            i += 1
+    return out
+
+
+def profile_summary(args):
+    """Markdown summary of rocprofv3 runs of one workload: kernel durations
+    (kernel trace), HBM bytes per launch (FETCH_SIZE and WRITE_SIZE runs,
+    scaled by the plain device copy of --calib-copy-mib MiB in the same runs)
+    and, when given, matrix-core use (MfmaUtil, MfmaFlops* run)."""
+    pat = STEP_PATTERNS[args.pattern]
+    launches = [l for l, _ in pat]
+    trace = _read_csv(_find_csv(args.trace_dir, "_kernel_trace.csv"))
+    tnames = [r["Kernel_Name"] for r in trace]
+    starts = _match_steps(tnames, pat)
+    if not starts:
+        raise SystemExit("no step of the pattern in the kernel trace")
+    starts = starts[-args.last_steps:]
+    dur = {l: [] for l in launches}
+    kname = {}
+    for s0 in starts:
+        for j, l in enumerate(launches):
+            r = trace[s0 + j]
+            dur[l].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+            kname[l] = r["Kernel_Name"]
+    mean = {l: float(np.mean(v)) for l, v in dur.items()}
+
+    def per_launch(d, counter):
+        disp = _pmc_dispatches(d)
+        names = [n for n, _ in disp]
+        st = _match_steps(names, pat)
+        if not st:
+            raise SystemExit(f"no step of the pattern in {d}")
+        vals = {l: float(np.mean([disp[s0 + j][1][counter] for s0 in st])) for j, l in enumerate(launches)}
+        copies = [c[counter] for n, c in disp if n == "__amd_rocclr_copyBuffer" and
+                  c[counter] > 0.25 * args.calib_copy_mib * 1024]
+        scale = args.calib_copy_mib * 1024.0 / float(np.median(copies)) if copies else float("nan")
+        return vals, scale, (float(np.median(copies)) if copies else float("nan"))
+
+    fetch, sf, rawf = per_launch(args.fetch_dir, "FETCH_SIZE")
+    write, sw, raww = per_launch(args.write_dir, "WRITE_SIZE")
+    tbytes = {l: 1024.0 * (fetch[l] * sf + write[l] * sw) for l in launches}
+    alg = {}
+    if args.pattern == "mixed":
+        alg = {l: b for l, (kind, b) in algorithmic_work(M_, P_, N3, K + OS, K).items() if kind == "hbm"}
+    elif args.pattern == "f64rand":
+        X8 = 8.0 * M_ * P_ * N3
+        pan = 8.0 * (M_ + P_) * (K + OS) * N3
+        alg = {"transform_fft": 2 * 4.0 * M_ * P_ * N3 * 2, "f64_sketch_xw": X8 + 8.0 * M_ * (K + OS) * N3,
+               "f64_power_xtw": X8 + pan, "f64_power_xw": X8 + pan, "f64_project_xtw": X8 + pan,
+               "f64_factors": 8.0 * (M_ + P_) * (2 * K + OS) * N3, "f64_resid_factors": X8 + 8.0 * (M_ + P_) * K * N3}
+    mfma = None
+    if args.mfma_dir:
+        disp = _pmc_dispatches(args.mfma_dir)
+        st = _match_steps([n for n, _ in disp], pat)
+        mfma = {}
+        for j, l in enumerate(launches):
+            c = [disp[s0 + j][1] for s0 in st]
+            util = float(np.mean([x.get("MfmaUtil", 0.0) for x in c]))
+            fl = {t: float(np.mean([x.get("MfmaFlops" + t, 0.0) for x in c])) for t in ("BF16", "F32", "F64")}
+            mfma[l] = (util, fl)
+
+    sha = kernel_sources_sha256()
+    out = [f"# {args.title}", "", args.description, "",
+           "Commands, from the repository root (rocprofv3 runs with `export TMPDIR=/tmp`):", ""]
+    out += ["    " + c for c in args.cmd]
+    # this summary's own command (its text arguments left out)
+    own, skip = ["python3", "bench.py"], False
+    for a in sys.argv[1:]:
+        if skip:
+            skip = False
+            continue
+        if a in ("--cmd", "--title", "--description"):
+            skip = True
+            continue
+        own.append(a)
+    out += ["    " + " ".join(own) + "  # this summary"]
+    out += ["", f"Kernel sources: sha256 of paper_2105_01170_amd/csrc/*.hip and *.h = `{sha}`", "",
+            f"## Kernel durations (last {len(starts)} steps of the kernel trace)", "",
+            "| Launch | Kernel | Mean (us) | Min (us) | Max (us) |", "|---|---|---|---|---|"]
+    for l in launches:
+        out.append(f"| {l} | {kname[l]} | {mean[l]:.1f} | {min(dur[l]):.1f} | {max(dur[l]):.1f} |")
+    out.append(f"| (sum) | | {sum(mean.values()):.1f} | | |")
+    out += ["", "## HBM traffic per launch (PMC, scaled)", "",
+            f"Scale from the plain {args.calib_copy_mib} MiB device copy in the same runs: FETCH_SIZE x {sf:.3f}, "
+            f"WRITE_SIZE x {sw:.3f} (the copy reads {rawf:.0f} KiB and writes {raww:.0f} KiB by the raw "
+            f"counters, {args.calib_copy_mib * 1024} KiB each by construction).  Algorithmic bytes: "
+            "bench.py, algorithmic_work (FP64 path: the same passes on 8-byte data).", "",
+            "| Launch | Fetch MB | Write MB | Total MB | Algorithmic MB | Total / algorithmic | Achieved GB/s |",
+            "|---|---|---|---|---|---|---|"]
+    for l in launches:
+        a = alg.get(l)
+        rat = f"{tbytes[l] / a:.2f}" if a else "-"
+        am = f"{a / 1e6:.1f}" if a else "-"
+        gbs = f"{tbytes[l] / (mean[l] * 1e-6) / 1e9:.0f}"
+        out.append(f"| {l} | {1.024 * fetch[l] * sf / 1e3:.1f} | {1.024 * write[l] * sw / 1e3:.1f} | "
+                   f"{tbytes[l] / 1e6:.1f} | {am} | {rat} | {gbs} |")
+    if mfma:
+        out += ["", "## Matrix cores (PMC: MfmaUtil, MfmaFlopsBF16/F32/F64)", "",
+                "MfmaUtil: matrix-core busy cycles over active cycles x SIMDs.  Achieved: the counted MFMA flops "
+                "over the traced mean duration, against the dense peak of that type (BF16 2500, FP32 157.3, "
+                "FP64 78.6 TFLOP/s).", "",
+                "| Launch | MfmaUtil % | BF16 TFLOP/s | FP32 TFLOP/s | FP64 TFLOP/s | Fraction of peak |",
+                "|---|---|---|---|---|---|"]
+        for l in launches:
+            util, fl = mfma[l]
+            if util == 0 and not any(fl.values()):
+                continue
+            tf = {t: fl[t] / (mean[l] * 1e-6) / 1e12 for t in fl}
+            frac = sum(tf[t] / MFMA_PEAK_TFLOPS[t] for t in tf)
+            out.append(f"| {l} | {util:.1f} | {tf['BF16']:.1f} | {tf['F32']:.1f} | {tf['F64']:.2f} | {frac:.3f} |")
+    out += ["", "Machine-readable traffic (bytes per launch), read by bench.py when the source hash matches:", "",
+            "    traffic-json " + json.dumps({"sha256": sha, "bytes": {l: int(round(tbytes[l])) for l in launches}}),
+            ""]
+    text = "\n".join(out)
+    with open(args.out, "w") as f:
+        f.write(text)
+    print(text)
+
+
 def main():
     args = parse()
+    if args.profile_summary:
+        return profile_summary(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                           "(sharding over several GPUs is designed but not built)"}))
@@ -753,9 +945,9 @@ def main():
         del xr
 
     # comparator 2: the plain FP64 GPU t-SVDM (exact facewise SVD by one-sided
-    # Jacobi, truncated to k = 32) of the same input
+    # Jacobi, truncated to k = 32) of the same input (--fp64-steps 0 skips it)
     fp64 = None
-    if not args.no_fp64:
+    if not args.no_fp64 and args.fp64_steps > 0:
         xh64 = torch.empty(m * p * n3, dtype=torch.float64, device=dev)
         tr64 = api.Truncator(m, p, n3, torch.float64, k=k, precision=C.PREC_F64, device=dev)
         torch.cuda.synchronize()
