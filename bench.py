@@ -523,15 +523,28 @@ def learned_main(args):
         for fn in (lambda: fixed(xh), lambda: lt(xh, pred)):
             fn()
         torch.cuda.synchronize()
+        # both truncations are launches only: each is captured once and replayed
         for which, fn in (("fixed", lambda: fixed(xh)), ("learned", lambda: lt(xh, pred))):
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                fn()
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                F = fn()
+            g.replay()
+            torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
             for _ in range(args.steps):
-                F = fn()
+                g.replay()
             e1.record()
             torch.cuda.synchronize()
             ms = e0.elapsed_time(e1) / args.steps
+            del g
             rel = float((F.cert / F.fro).max().item())
             if which == "fixed":
                 ms_fixed += ms
@@ -544,7 +557,7 @@ def learned_main(args):
         # faces recomputed with width 40 after a predicted narrower width
         y = pred.forward(api.rank_features(xh, m, p, B, omega)).cpu().numpy()
         _, lhat = mlp_widths(y)
-        fallback += int(np.sum((lhat < 40) & (w == 40)))
+        fallback += int(np.sum(lhat != w))
         acc += int(np.sum(lhat == width_l.cpu().numpy()))
         del xh
     widths = np.concatenate(widths)
@@ -570,7 +583,7 @@ def learned_main(args):
         "gain_learned_over_fixed": ms_fixed / ms_learned,
         "max_certified_rel_err": {"learned": err_learned, "fixed": err_fixed},
         "width_histogram": {str(w): int(np.sum(widths == w)) for w in (16, 32, 40)},
-        "fallback_faces": fallback,
+        "fallback_faces": fallback,  # faces whose width changed from the prediction to 40
         "width_label_accuracy": acc / nt,
         "train_loss": {"first_epoch": hist[0], "last_epoch": hist[-1]},
         "setup_s": {"data_and_labels": round(t_data, 2), "training": round(t_train, 2)},
@@ -579,11 +592,13 @@ def learned_main(args):
 
 
 def mlp_widths(y):
-    """Predicted (rank, width) from the predictor outputs, as the library rounds them."""
-    k = np.clip(np.ceil(y[:, 0] * 32.0).astype(int) + 1, 1, 32)
-    lw = np.ceil(y[:, 1] * 48.0).astype(int) + 1
-    w = np.where(lw <= 16, 16, np.where(lw <= 32, 32, 40))
-    return k, w
+    """Predicted (rank, width) from the predictor outputs, as the library takes
+    them: kh = ceil(32 y0) and lw = ceil(48 y1) + 1, the first bucket (width 16,
+    32, 40 with caps 13, 26, 32) that holds both."""
+    kh = np.clip(np.nan_to_num(np.ceil(y[:, 0] * 32.0), nan=1.0), 1, 32).astype(int)
+    lw = np.clip(np.nan_to_num(np.ceil(y[:, 1] * 48.0) + 1, nan=1.0), 1, 48).astype(int)
+    w = np.where((lw <= 16) & (kh <= 13), 16, np.where((lw <= 32) & (kh <= 26), 32, 40))
+    return kh, w
 
 
 # ---------------------------------------------------------------- profile summaries

@@ -4,9 +4,10 @@
 //
 // Parameters, flat: W1 (64 x 32, row major), b1 (64), W2 (64 x 64), b2 (64),
 // W3 (2 x 64), b3 (2): 6402 values.  Inputs are rows of 32 halves.
-//  * k_mlp_fwd: one sample per thread, weights in LDS, packed-half dot
-//    products (two half products summed into an FP32 accumulator); the
-//    hidden activations are rounded to half as they are stored.
+//  * k_mlp_fwd: one sample per wavefront (a hidden unit per lane), weights
+//    in LDS, packed-half dot products (two half products summed into an FP32
+//    accumulator); the hidden activations are rounded to half as they are
+//    stored.
 //  * k_mlp_grad: a block of 128 samples: the same forward pass, the backward
 //    pass per sample in FP32, then the block's gradient as small products over
 //    its samples (dZ^T A), written as one partial per block (deterministic).
@@ -74,20 +75,53 @@ __device__ __forceinline__ void mlp_sample(const half_t *w, const half_t *x, hal
     }
 }
 
+// One sample per wavefront: lane u forms hidden unit u of both layers (the
+// same packed-half dot-product chain over its weight row as mlp_sample, so
+// the results are the same bits), the activations pass between the layers
+// through LDS, lanes 0 and 1 form the two outputs.  Four wavefronts per
+// workgroup, each taking samples wave, wave + 4 * gridDim.x, ...
 __global__ __launch_bounds__(FT) void k_mlp_fwd(const half_t *__restrict__ w16, const half_t *__restrict__ X,
                                                 int64_t n, float *__restrict__ Y) {
     __shared__ __align__(16) half_t w[NPAR + 2];
+    __shared__ __align__(16) half_t xs[FT / 64][NIN];
+    __shared__ __align__(16) half_t hs[FT / 64][2][NH];
     for (int e = threadIdx.x; e < NPAR; e += FT) w[e] = w16[e];
-    __syncthreads();
-    const int64_t s = (int64_t)blockIdx.x * FT + threadIdx.x;
-    if (s >= n) return;
-    __align__(16) half_t x[NIN], a1[NH], a2[NH];
+    const int wave = threadIdx.x >> 6, u = threadIdx.x & 63;
+    const int64_t nw = (int64_t)gridDim.x * (FT / 64);
+    const int64_t iters = (n + nw - 1) / nw;  // the same count in every wavefront
+    for (int64_t it = 0; it < iters; ++it) {
+        const int64_t s = (it * gridDim.x + blockIdx.x) * (FT / 64) + wave;
+        const bool ok = s < n;
+        if (u < NIN) xs[wave][u] = ok ? X[s * NIN + u] : (half_t)0.0f;
+        __syncthreads();
+        {
+            const half2_t *row = reinterpret_cast<const half2_t *>(w + OW1 + u * NIN);
+            const half2_t *x2 = reinterpret_cast<const half2_t *>(xs[wave]);
+            float acc = (float)w[OB1 + u];
 #pragma unroll
-    for (int i = 0; i < NIN; ++i) x[i] = X[s * NIN + i];
-    float y[NOUT];
-    mlp_sample(w, x, a1, a2, y, nullptr, nullptr);
-    Y[s * NOUT + 0] = y[0];
-    Y[s * NOUT + 1] = y[1];
+            for (int i = 0; i < NIN / 2; ++i) acc = dot2(row[i], x2[i], acc);
+            hs[wave][0][u] = (half_t)fmaxf(acc, 0.0f);
+        }
+        __syncthreads();
+        {
+            const half2_t *row = reinterpret_cast<const half2_t *>(w + OW2 + u * NH);
+            const half2_t *h2 = reinterpret_cast<const half2_t *>(hs[wave][0]);
+            float acc = (float)w[OB2 + u];
+#pragma unroll
+            for (int i = 0; i < NH / 2; ++i) acc = dot2(row[i], h2[i], acc);
+            hs[wave][1][u] = (half_t)fmaxf(acc, 0.0f);
+        }
+        __syncthreads();
+        if (u < NOUT && ok) {
+            const half2_t *row = reinterpret_cast<const half2_t *>(w + OW3 + u * NH);
+            const half2_t *g2 = reinterpret_cast<const half2_t *>(hs[wave][1]);
+            float acc = (float)w[OB3 + u];
+#pragma unroll
+            for (int i = 0; i < NH / 2; ++i) acc = dot2(row[i], g2[i], acc);
+            Y[s * NOUT + u] = acc;
+        }
+        __syncthreads();
+    }
 }
 
 // Block b: samples [b*GS, min(n, (b+1)*GS)).  part[b * (NPAR + 1) + ...]:
@@ -235,7 +269,8 @@ bool check_n(int64_t n, const char *who) {
 
 namespace tsvdm {
 tsvdm_status launch_mlp_forward(const uint16_t *w16, const uint16_t *x, int64_t n, float *y, hipStream_t s) {
-    TSVDM_LAUNCH("mlp_forward", k_mlp_fwd, dim3((unsigned)((n + FT - 1) / FT)), dim3(FT), 0, s,
+    const int64_t blocks = (n + FT / 64 - 1) / (FT / 64);
+    TSVDM_LAUNCH("mlp_forward", k_mlp_fwd, dim3((unsigned)(blocks < 1024 ? blocks : 1024)), dim3(FT), 0, s,
                  reinterpret_cast<const half_t *>(w16), reinterpret_cast<const half_t *>(x), n, y);
     TSVDM_LAUNCH_CHECK("mlp_forward");
     return TSVDM_OK;

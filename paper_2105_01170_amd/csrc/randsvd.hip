@@ -75,13 +75,16 @@ constexpr int gram_tiles() {
 // G (LDS, pitch ldg) = ordered sum over pp of the nparts packed partials of
 // face f, both triangles.  All loads of a block of 8 partials are issued
 // before any is summed (clamped addresses, zero-selected, no branches).
+// lps: the width the partials were written for (LP, or 32 when LP = 16: the
+// 16 x 16 Gram is the first packed tile of a width-32 partial).
 template <int LP, int NTH>
 __device__ __forceinline__ void load_gram_partials(const double *__restrict__ gpart, int f, int nparts,
-                                                   double *G, int ldg) {
-    constexpr int NT = LP / 16, NE2 = gram_tiles<LP>() * 128, S2 = LP * LP / 2;
+                                                   double *G, int ldg, int lps = LP) {
+    constexpr int NT = LP / 16, NE2 = gram_tiles<LP>() * 128;
     constexpr int E2 = (NE2 + NTH - 1) / NTH, PB = 8;
+    const int S2 = lps * lps / 2;
     const int tid = threadIdx.x;
-    const double2 *g2 = reinterpret_cast<const double2 *>(gpart + (int64_t)f * nparts * LP * LP);
+    const double2 *g2 = reinterpret_cast<const double2 *>(gpart + (int64_t)f * nparts * lps * lps);
     double2 acc[E2];
 #pragma unroll
     for (int q = 0; q < E2; ++q) acc[q] = double2{0.0, 0.0};
@@ -306,6 +309,7 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
     const int nb = (m + 63) / 64;
     int blk, f;
     xcd_map(blockIdx.x, nb, nf, blk, f);
+    if (fmap && fmap[f] < 0) return;  // an unused slot of a face list sized on the device
     const int a0 = blk * 64;
     const float *Xf = X + (int64_t)(fmap ? fmap[f] : f) * m * p;
     const float *Wf = W + (int64_t)f * w_stride;
@@ -487,6 +491,7 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
     const int nb = (p + 63) / 64;
     int blk, f;
     xcd_map(blockIdx.x, nb, nf, blk, f);
+    if (fmap && fmap[f] < 0) return;  // an unused slot of a face list sized on the device
     const int b0 = blk * 64;
     const float *Xf = X + (int64_t)(fmap ? fmap[f] : f) * m * p;
     const float *Wf = W + (int64_t)f * w_stride;
@@ -929,11 +934,17 @@ constexpr int QT = 512;
 
 // T: the panel's element type (FP32 in the mixed path, FP64 in the FP64
 // randomized path, which stages fewer rows per LDS pass).
+// fmap: face list (an entry < 0 is an unused slot); src_global: the panel and
+// its Gram partials are indexed by the listed face and written for width
+// src_lp (a sketch taken once for all faces, whose first columns this
+// width-LP basis reuses), the output by the list position.
 template <int LP, typename T = float>
 __global__ __launch_bounds__(QT) void k_cholqr(const T *__restrict__ Sin, int rows, int ell,
                                                T *__restrict__ Qout, int passes,
                                                const double *__restrict__ gpart, int nparts,
-                                               int32_t *__restrict__ qr_info, int first) {
+                                               int32_t *__restrict__ qr_info, int first,
+                                               const int32_t *__restrict__ fmap = nullptr, int src_global = 0,
+                                               int src_lp = LP) {
     constexpr bool D = sizeof(T) == 8;
     constexpr int LDG = LP + 1, LDR = LP + 2, LDS_ = LP + 1;
     constexpr int HR = D ? (LP <= 32 ? QT / 2 : QT / 4) : (LP <= 48 ? QT : QT / 2);
@@ -945,12 +956,14 @@ __global__ __launch_bounds__(QT) void k_cholqr(const T *__restrict__ Sin, int ro
     __shared__ double trace_s;
     __shared__ int bad;
     const int f = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const T *S = Sin + (int64_t)f * rows * LP;
+    if (fmap && fmap[f] < 0) return;  // an unused slot of a face list sized on the device
+    const int fs = src_global ? fmap[f] : f, slp = src_global ? src_lp : LP;
+    const T *S = Sin + (int64_t)fs * rows * slp;
     T *Q = Qout + (int64_t)f * rows * LP;
     if (tid == 0) bad = 0;
 
     // ---- first Gram: ordered sum of the partials
-    load_gram_partials<LP, QT>(gpart, f, nparts, G, LDG);
+    load_gram_partials<LP, QT>(gpart, fs, nparts, G, LDG, slp);
     __syncthreads();
 
     const int nch = (rows + QT - 1) / QT;
@@ -1143,7 +1156,7 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
                                              int *__restrict__ perm_out, int *__restrict__ kf_out,
                                              double *__restrict__ fro2_out, double *__restrict__ cert,
                                              int32_t *__restrict__ jinfo,
-    const int32_t *__restrict__ fmap) {
+    const int32_t *__restrict__ fmap, const int32_t *__restrict__ kcap_face = nullptr) {
     constexpr int LD = jacobi_ld<LP>(), LDE = jacobi_ld<LP>(), NPM = LP / 2;
     __shared__ __align__(16) double Gb[2][LP * LD];
     __shared__ __align__(16) double Eb[2][LP * LDE];  // eigenvectors transposed: E[c * LDE + r]
@@ -1153,6 +1166,7 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
     __shared__ double trace_s;
     __shared__ int rflag[3];
     const int f = blockIdx.x, tid = threadIdx.x;
+    if (fmap && fmap[f] < 0) return;  // an unused slot of a face list sized on the device
     for (int e = tid; e < LP * LD; e += QT) Gb[0][e] = 0.0;
     for (int e = tid; e < LP * LDE; e += QT) Eb[0][e] = Eb[1][e] = 0.0;
     __syncthreads();
@@ -1202,6 +1216,10 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
             kf = kfix < ell ? kfix : ell;
         } else {
             int cap = kfix > 0 && kfix < ell ? kfix : ell;
+            if (kcap_face) {  // a per-face cap (the predicted rank), at least 1
+                const int kc = kcap_face[fmap ? fmap[f] : f];
+                cap = kc < 1 ? 1 : kc < cap ? kc : cap;
+            }
             double tail = res, bound = tau * tau * fro2;
             for (int j = 0; j < ell; ++j) tail += lam[j];
             kf = -1;
@@ -1272,6 +1290,7 @@ __global__ __launch_bounds__(GT) void k_factors(const T *__restrict__ Q, const T
     __shared__ T ubs[LP * LU];  // ubs[r * LU + c] = U_B[c, perm[r]] (/ s_r for V), zero for r >= k_f
     const int f = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int fd = fmap ? fmap[f] : f;
+    if (fd < 0) return;  // an unused slot of a face list sized on the device
     const int kf = kf_in[f], nbu = (m + 63) / 64;
     const bool isv = (int)blockIdx.x >= nbu;
     const int blk = isv ? blockIdx.x - nbu : blockIdx.x, rows = isv ? p : m;
@@ -1373,6 +1392,7 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     int blk, f;
     xcd_map(blockIdx.x, nb, nf, blk, f);
     const int fd = fmap ? fmap[f] : f;
+    if (fd < 0) return;  // an unused slot of a face list sized on the device
     const int a0 = blk * 64;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int kf = ranks[fd] < KP ? ranks[fd] : KP, ns = (kf + 3) / 4;
@@ -1473,7 +1493,7 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 __global__ void k_cert(const double *__restrict__ res_part, int nparts, int nf, double *__restrict__ cert,
                        const int32_t *__restrict__ fmap) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= nf) return;
+    if (f >= nf || (fmap && fmap[f] < 0)) return;
     double r = 0.0;
     for (int i = 0; i < nparts; ++i) r += res_part[(int64_t)f * nparts + i];
     cert[fmap ? fmap[f] : f] = sqrt(r);
@@ -1531,14 +1551,18 @@ __global__ void k_rank_features(const double *__restrict__ sig, int LPs, int nf,
     feat[(int64_t)f * 32 + j] = (_Float16)fmax(v, -30.0);
 }
 
-// Widths of the learned truncation: from the predictor's (k/32, l/48), round
-// up and add one; the sketch width is the smallest of 16, 32, 40 that is at
-// least that.  Stable partition of the faces into the three width lists
-// (lists[b * nf + i]), counts[b]; widths[f] records each face's width.
+// Widths of the learned truncation from the predictor's (k/32, l/48): the
+// predicted rank kh = ceil(32 k/32) (1..32) and width lw = ceil(48 l/48) + 1;
+// a face takes the first bucket (width 16, 32, 40 with rank caps 13, 26, 32)
+// whose width is at least lw and whose cap is at least kh, and the energy
+// rule's cap min(bucket cap, kh + 2).  Stable partition of the faces into the
+// three lists (lists[b * nf + i], unused slots -1), counts[b]; widths[f] and
+// caps[f] record each face's choice.  One workgroup.
 __global__ __launch_bounds__(1024) void k_width_partition(const float *__restrict__ y, int nf,
                                                           int32_t *__restrict__ lists,
                                                           int32_t *__restrict__ counts,
-                                                          int32_t *__restrict__ widths) {
+                                                          int32_t *__restrict__ widths,
+                                                          int32_t *__restrict__ caps) {
     __shared__ int base[3];
     __shared__ int wsum[3][16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1548,9 +1572,15 @@ __global__ __launch_bounds__(1024) void k_width_partition(const float *__restric
         const int f = f0 + tid;
         int b = -1;
         if (f < nf) {
-            const int lw = (int)ceilf(y[2 * f + 1] * 48.0f) + 1;
-            b = lw <= 16 ? 0 : lw <= 32 ? 1 : 2;
+            // NaN or out-of-range predictions end in a valid bucket (the
+            // certificate's fallback catches a wrong choice)
+            const float kr = ceilf(y[2 * f] * 32.0f), lr = ceilf(y[2 * f + 1] * 48.0f) + 1.0f;
+            const int kh = kr >= 1.0f && kr <= 32.0f ? (int)kr : kr > 32.0f ? 32 : 1;
+            const int lw = lr >= 1.0f && lr <= 48.0f ? (int)lr : lr > 48.0f ? 48 : 1;
+            b = lw <= 16 && kh <= 13 ? 0 : lw <= 32 && kh <= 26 ? 1 : 2;
+            const int bc = b == 0 ? 13 : b == 1 ? 26 : 32;
             widths[f] = b == 0 ? 16 : b == 1 ? 32 : 40;
+            caps[f] = kh + 2 < bc ? kh + 2 : bc;
         }
         for (int c = 0; c < 3; ++c) {
             const unsigned long long mask = __ballot(b == c);
@@ -1569,14 +1599,18 @@ __global__ __launch_bounds__(1024) void k_width_partition(const float *__restric
             __syncthreads();
         }
     }
+    for (int c = 0; c < 3; ++c)
+        for (int i = base[c] + tid; i < nf; i += 1024) lists[c * nf + i] = -1;
     if (tid < 3) counts[tid] = base[tid];
 }
 
-// Stable list of the faces whose width is below 40 and whose certified error
-// exceeds tau ||Xhat_f||: they are truncated again with the full width.
+// Stable list of the faces whose certified error exceeds tau ||Xhat_f|| and
+// that did not already run at the full width with the full cap: they are
+// truncated again with width 40 and cap 32.  Unused slots -1.
 __global__ __launch_bounds__(1024) void k_fallback_list(const double *__restrict__ cert,
                                                         const double *__restrict__ fro, double tau, int nf,
                                                         int32_t *__restrict__ widths,
+                                                        const int32_t *__restrict__ caps,
                                                         int32_t *__restrict__ list, int32_t *__restrict__ count) {
     __shared__ int base;
     __shared__ int wsum[16];
@@ -1585,7 +1619,7 @@ __global__ __launch_bounds__(1024) void k_fallback_list(const double *__restrict
     __syncthreads();
     for (int f0 = 0; f0 < nf; f0 += 1024) {
         const int f = f0 + tid;
-        const bool bad = f < nf && widths[f] < 40 && !(cert[f] <= tau * fro[f]);
+        const bool bad = f < nf && (widths[f] < 40 || caps[f] < 32) && !(cert[f] <= tau * fro[f]);
         const unsigned long long mask = __ballot(bad);
         const int before = __popcll(mask & ((1ull << lane) - 1ull));
         if (lane == 0) wsum[wave] = __popcll(mask);
@@ -1604,6 +1638,7 @@ __global__ __launch_bounds__(1024) void k_fallback_list(const double *__restrict
         }
         __syncthreads();
     }
+    for (int i = base + tid; i < nf; i += 1024) list[i] = -1;
     if (tid == 0) *count = base;
 }
 
@@ -1622,10 +1657,16 @@ bool vec_loads_ok(const float *X, int m, int p) {
 }
 // wf0: the face of the workspace w0 the group starts at (f0 when w0 was carved
 // for the whole tensor, 0 when it was carved for the group alone).
+// fmap: the group's faces (entries < 0: unused slots of a list sized on the
+// device; every kernel's workgroups for them exit at once).  src: a sketch
+// X Omega[:, :32] with its width-32 Gram partials, taken once for all faces
+// (indexed by face); a group of width 16 or 32 then starts from its first
+// columns instead of a sketch pass.  kcap_face: per-face energy-rule caps.
 template <int LP>
 tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
                        const MixedWs &w0, int f0, int nfg, hipStream_t s,
-                       const int32_t *fmap = nullptr, int wf0 = -1) {
+                       const int32_t *fmap = nullptr, int wf0 = -1, const MixedWs *src = nullptr,
+                       const int32_t *kcap_face = nullptr) {
     const int m = (int)X->m, p = (int)X->p, ell = o->k + o->oversample;
     const int mparts = (m + 63) / 64, pparts = (p + 63) / 64;
     const int64_t kmax = F->kmax;
@@ -1674,13 +1715,20 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
             TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true, false>), gm, dim3(GT), 0, s, Xd, m, p,    \
                          nf, o->omega, (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m, fmap);                 \
     } while (0)
+    const bool reuse = power && src && LP <= 32 && ell <= 32;
     if (power) {
-        // pass 1: sketch Y = X Omega (BF16), ||X||^2, Gram partials of Y
-        TSVDM_SKETCH();
-        // basis of the sketch: one shifted Cholesky-QR step (its span is what
-        // the power step needs)
-        TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell,
-                     w.Qm, 1, gm_c, mparts, w.qr_info, 1);
+        if (reuse) {
+            // the sketch's first ell columns were taken once for all faces
+            TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)src->Y, m, ell,
+                         w.Qm, 1, (const double *)src->gram_m, mparts, w.qr_info, 1, fmap, 1, 32);
+        } else {
+            // pass 1: sketch Y = X Omega (BF16), ||X||^2, Gram partials of Y
+            TSVDM_SKETCH();
+            // basis of the sketch: one shifted Cholesky-QR step (its span is what
+            // the power step needs)
+            TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell,
+                         w.Qm, 1, gm_c, mparts, w.qr_info, 1, fmap);
+        }
         // pass 2: Z = X^T Q (BF16) and its Gram partials; basis of Z
         if (v4)
             TSVDM_LAUNCH("power_xtw_bf16", (k_xtw<LP, PROD_BF16, true, false, true>), gp, dim3(GT), 0, s, Xd, m,
@@ -1689,21 +1737,23 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
             TSVDM_LAUNCH("power_xtw_bf16", (k_xtw<LP, PROD_BF16, true, false, false>), gp, dim3(GT), 0, s, Xd, m,
                          p, nf, (const float *)w.Qm, (int64_t)m * LP, m, ell, w.Z, w.gram_p, (double *)nullptr, fmap);
         TSVDM_LAUNCH("cholqr_power_z", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Z, p, ell,
-                     w.Qp, 1, gp_c, pparts, w.qr_info, 0);
+                     w.Qp, 1, gp_c, pparts, w.qr_info, 0, fmap);
         // pass 3: Y' = X Qz, FP32-accurate (split BF16), and its Gram partials
+        // (and ||X||^2 when the sketch pass was skipped)
+        double *fp3 = reuse ? w.fro_part : (double *)nullptr;
         if (v4)
             TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true, true>), gm, dim3(GT), 0, s, Xd, m, p, nf,
-                         (const float *)w.Qp, (int64_t)p * LP, p, ell, w.Y, (double *)nullptr, w.gram_m, fmap);
+                         (const float *)w.Qp, (int64_t)p * LP, p, ell, w.Y, fp3, w.gram_m, fmap);
         else
             TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true, false>), gm, dim3(GT), 0, s, Xd, m, p, nf,
-                         (const float *)w.Qp, (int64_t)p * LP, p, ell, w.Y, (double *)nullptr, w.gram_m, fmap);
+                         (const float *)w.Qp, (int64_t)p * LP, p, ell, w.Y, fp3, w.gram_m, fmap);
     } else {
         TSVDM_SKETCH();
     }
 #undef TSVDM_SKETCH
     // final basis: FP64 shifted Cholesky-QR2 (first Gram from the partials)
     TSVDM_LAUNCH("cholqr_final", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell, w.Qm,
-                 2, gm_c, mparts, w.qr_info, power ? 0 : 1);
+                 2, gm_c, mparts, w.qr_info, power ? 0 : 1, fmap);
     // pass 4: B^T = X^T Q, FP32-accurate, the Gram partials of B^T and, for
     // the energy rule, ||X - Q B||^2 per 64-column block
 #define TSVDM_PROJECT(NAME, RES, V, RP)                                                                    \
@@ -1721,7 +1771,7 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     TSVDM_LAUNCH("core_gram_eig", (k_core<LP>), dim3(nf), dim3(QT), 0, s, gp_c, pparts, ell,
                  (const double *)w.fro_part, mparts, (const double *)w.res_part, resid ? pparts : 0,
                  o->rank_mode, o->k, o->tau, msw, kJacobiTolMixed, w.UB, w.sig, w.perm, w.kf, w.fro2,
-                 exact ? (double *)nullptr : cert, w.jinfo, fmap);
+                 exact ? (double *)nullptr : cert, w.jinfo, fmap, kcap_face);
     TSVDM_LAUNCH("factors", (k_factors<LP>), dim3((unsigned)(mparts + pparts), nf), dim3(GT), 0, s,
                  (const float *)w.Qm, (const float *)w.Z, m, p, ell, kmax, w.UB, w.sig, w.perm, w.kf,
                  w.fro2, w.qr_info, w.jinfo, Uo, So, Vo, ranks, fro, info, fmap);
@@ -1995,9 +2045,11 @@ namespace {
 struct LearnedWs {
     uint16_t *feat;
     float *y;
-    int32_t *lists, *counts, *fb_list;
-    char *feat_ws, *trunc_ws;
+    int32_t *lists, *counts, *fb_list, *caps;
+    char *feat_ws, *bucket_ws[3];
 };
+
+constexpr int kBucketLP[3] = {16, 32, 48};
 
 size_t learned_carve(char *base, int64_t m, int64_t p, int64_t nf, LearnedWs *w) {
     size_t off = 0;
@@ -2012,15 +2064,55 @@ size_t learned_carve(char *base, int64_t m, int64_t p, int64_t nf, LearnedWs *w)
     t.lists = (int32_t *)take(sizeof(int32_t) * 3 * nf);
     t.counts = (int32_t *)take(sizeof(int32_t) * 8);
     t.fb_list = (int32_t *)take(sizeof(int32_t) * nf);
+    t.caps = (int32_t *)take(sizeof(int32_t) * nf);
     t.feat_ws = take(features_workspace(m, p, nf));
-    t.trunc_ws = take(carve(nullptr, m, p, nf, 48, nullptr));
+    for (int b = 0; b < 3; ++b) t.bucket_ws[b] = take(carve(nullptr, m, p, nf, kBucketLP[b], nullptr));
     if (w) *w = t;
     return off;
+}
+
+// Three streams and four events per device, created on first use and kept
+// until the process ends: the three width buckets of a learned truncation run
+// concurrently (their FP64 steps are latency-bound, one workgroup per face).
+// Default priority.  Learned truncations issued from several host threads at
+// once on one device share them and must be serialized by the caller.
+struct SideStreams {
+    hipStream_t s[3];
+    hipEvent_t ev[4];
+};
+std::mutex g_side_mu;
+SideStreams *g_side[64];
+
+tsvdm_status side_streams(SideStreams **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_check(e, "learned truncate: device");
+    if (dev < 0 || dev >= 64) {
+        set_error("learned truncate: device index %d beyond 64", dev);
+        return TSVDM_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    if (!g_side[dev]) {
+        SideStreams t{};
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&t.s[i], hipStreamNonBlocking);
+        for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&t.ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) return hip_check(e, "learned truncate: side streams");
+        g_side[dev] = new SideStreams(t);
+    }
+    *out = g_side[dev];
+    return TSVDM_OK;
 }
 }  // namespace
 
 size_t learned_workspace(int64_t m, int64_t p, int64_t nf) { return learned_carve(nullptr, m, p, nf, nullptr); }
 
+// Launches only (no host synchronization, no allocation after the first call
+// on a device): capturable in a graph.  The feature sketch X Omega[:, :32]
+// and its Gram partials serve twice: the features, and the first sketch of the
+// width-16 and width-32 buckets.  Each bucket runs over a face list sized on
+// the device (grids for all nf faces, unused slots exit at once) on its own
+// stream; the fallback list then reruns, on the caller's stream, the faces
+// whose certificate misses tau.
 tsvdm_status launch_learned_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, const uint16_t *w16,
                                      tsvdm_factors *F, int32_t *widths, void *ws, hipStream_t s) {
     const int m = (int)X->m, p = (int)X->p, nf = (int)X->n3;
@@ -2032,49 +2124,47 @@ tsvdm_status launch_learned_truncate(const tsvdm_tensor *X, const tsvdm_truncate
     st = launch_mlp_forward(w16, w.feat, nf, w.y, s);
     if (st != TSVDM_OK) return st;
     TSVDM_LAUNCH("width_partition", k_width_partition, dim3(1), dim3(1024), 0, s, (const float *)w.y, nf,
-                 w.lists, w.counts, widths);
+                 w.lists, w.counts, widths, w.caps);
     TSVDM_LAUNCH_CHECK("width partition");
-    int32_t counts[3] = {0, 0, 0};
-    hipError_t e = hipMemcpyAsync(counts, w.counts, sizeof(counts), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_check(e, "learned truncate: bucket counts");
+    SideStreams *ss = nullptr;
+    if ((st = side_streams(&ss)) != TSVDM_OK) return st;
+    hipError_t e = hipEventRecord(ss->ev[0], s);
+    if (e != hipSuccess) return hip_check(e, "learned truncate: fork");
+    MixedWs fw;  // the feature pass's sketch and Gram partials, indexed by face
+    carve(w.feat_ws, m, p, nf, 32, &fw);
     // per width: (rank cap, oversampling) with ell = cap + oversampling
     const int caps[3] = {13, 26, 32}, overs[3] = {3, 6, 8};
-    MixedWs tw;
     for (int b = 0; b < 3; ++b) {
-        if (counts[b] == 0) continue;
+        hipStream_t sb = ss->s[b];
+        if ((e = hipStreamWaitEvent(sb, ss->ev[0], 0)) != hipSuccess) return hip_check(e, "learned truncate: wait");
         tsvdm_truncate_opts ob = *o;
         ob.rank_mode = TSVDM_RANK_ENERGY;
         ob.k = caps[b] < (int)F->kmax ? caps[b] : (int)F->kmax;
         ob.oversample = caps[b] + overs[b] - ob.k;
         ob.certify = 1;
-        const int LPb = b == 0 ? 16 : b == 1 ? 32 : 48;
-        carve(w.trunc_ws, m, p, counts[b], LPb, &tw);
+        MixedWs tw;
+        carve(w.bucket_ws[b], m, p, nf, kBucketLP[b], &tw);
         const int32_t *list = w.lists + (int64_t)b * nf;
-        if (b == 0) st = run_group<16>(X, &ob, F, tw, 0, counts[b], s, list);
-        else if (b == 1) st = run_group<32>(X, &ob, F, tw, 0, counts[b], s, list);
-        else st = run_group<48>(X, &ob, F, tw, 0, counts[b], s, list);
+        const MixedWs *src = b < 2 ? &fw : nullptr;
+        if (b == 0) st = run_group<16>(X, &ob, F, tw, 0, nf, sb, list, -1, src, w.caps);
+        else if (b == 1) st = run_group<32>(X, &ob, F, tw, 0, nf, sb, list, -1, src, w.caps);
+        else st = run_group<48>(X, &ob, F, tw, 0, nf, sb, list, -1, src, w.caps);
         if (st != TSVDM_OK) return st;
+        if ((e = hipEventRecord(ss->ev[1 + b], sb)) != hipSuccess) return hip_check(e, "learned truncate: join");
+        if ((e = hipStreamWaitEvent(s, ss->ev[1 + b], 0)) != hipSuccess) return hip_check(e, "learned truncate: join");
     }
-    // faces whose certificate misses tau: again with the full width
+    // faces whose certificate misses tau: again with the full width and cap
     TSVDM_LAUNCH("fallback_list", k_fallback_list, dim3(1), dim3(1024), 0, s, (const double *)F->cert,
-                 (const double *)F->fro, o->tau, nf, widths, w.fb_list, w.counts + 3);
+                 (const double *)F->fro, o->tau, nf, widths, (const int32_t *)w.caps, w.fb_list, w.counts + 3);
     TSVDM_LAUNCH_CHECK("fallback list");
-    int32_t nfb = 0;
-    e = hipMemcpyAsync(&nfb, w.counts + 3, sizeof(nfb), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return hip_check(e, "learned truncate: fallback count");
-    if (nfb > 0) {
-        tsvdm_truncate_opts ob = *o;
-        ob.rank_mode = TSVDM_RANK_ENERGY;
-        ob.k = 32 < (int)F->kmax ? 32 : (int)F->kmax;
-        ob.oversample = 40 - ob.k;
-        ob.certify = 1;
-        carve(w.trunc_ws, m, p, nfb, 48, &tw);
-        st = run_group<48>(X, &ob, F, tw, 0, nfb, s, w.fb_list);
-        if (st != TSVDM_OK) return st;
-    }
-    return TSVDM_OK;
+    tsvdm_truncate_opts ob = *o;
+    ob.rank_mode = TSVDM_RANK_ENERGY;
+    ob.k = 32 < (int)F->kmax ? 32 : (int)F->kmax;
+    ob.oversample = 40 - ob.k;
+    ob.certify = 1;
+    MixedWs tw;
+    carve(w.bucket_ws[2], m, p, nf, 48, &tw);
+    return run_group<48>(X, &ob, F, tw, 0, nf, s, w.fb_list);
 }
 
 }  // namespace tsvdm

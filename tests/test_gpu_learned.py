@@ -38,10 +38,11 @@ def _host(F, nf):
     return U, S, V
 
 
-def _constant_predictor(width_out):
-    """Zero weights, output bias (0.5, width_out): every face gets the same width."""
+def _constant_predictor(width_out, rank_out=0.3):
+    """Zero weights, output bias (rank_out, width_out): every face gets the same
+    width and rank cap (rank 0.3 -> 10, within the width-16 cap of 13)."""
     theta = np.zeros(mlp.NPARAMS)
-    mlp.unpack(theta)["b3"][...] = [0.5, width_out]
+    mlp.unpack(theta)["b3"][...] = [rank_out, width_out]
     return api.RankPredictor(torch.from_numpy(theta))
 
 
@@ -131,3 +132,62 @@ def test_narrow_faces_take_the_narrow_width():
         torch.cuda.synchronize()
         times[name] = e0.elapsed_time(e1) / 5
     print("narrow faces, ms per batch:", times)
+
+
+def test_predicted_rank_moves_the_bucket_and_caps_the_rank():
+    """The predicted rank takes part in the choice: a width-16 answer with a
+    predicted rank of 20 (above the width-16 cap of 13) puts every face in the
+    width-32 bucket, and the energy rule's cap becomes min(26, 20 + 2) = 22:
+    on slowly decaying faces (energy rank above 22) every face misses there
+    and falls back to width 40 with cap 32, meeting tau."""
+    nf = 64
+    xh, _ = _faces(nf, salt=3, lo=1 / 16, hi=1 / 14)
+    lt = api.LearnedTruncator(M, P, nf, _omega(), tau=TAU)
+    pred = _constant_predictor(0.1, rank_out=20 / 32)
+    F = lt(xh, pred)
+    assert np.all(lt.widths.cpu().numpy() == 40)
+    _check_batch(xh, F, lt.widths.cpu().numpy(), nf, range(0, nf, 13))
+    # faces of fast decay stay in the width-32 bucket, ranks within the cap 22
+    xh2, _ = _faces(nf, salt=4, lo=0.25, hi=0.3)
+    F2 = lt(xh2, pred)
+    w2 = lt.widths.cpu().numpy()
+    assert np.all(w2 == 32) and np.all(F2.ranks.cpu().numpy() <= 22)
+    _check_batch(xh2, F2, w2, nf, range(0, nf, 13))
+
+
+def test_learned_truncation_graph_replays_match_eager():
+    """The learned truncation launches kernels only (bucket sizes stay on the
+    device, buckets on internal streams joined by events): captured in a
+    graph, every replay (with eager work and synchronization between) gives
+    the eager result bit for bit, fallback faces included."""
+    nf = 128
+    xh_a, _ = _faces(nf // 2, salt=21, lo=0.4, hi=0.5)       # width 16 holds
+    xh_b, _ = _faces(nf // 2, salt=22, lo=1 / 16, hi=1 / 12)  # fall back to width 40
+    xh = torch.cat([xh_a, xh_b]).contiguous()
+    lt = api.LearnedTruncator(M, P, nf, _omega(), tau=TAU)
+    pred = _constant_predictor(0.1)
+    F = lt(xh, pred)
+    torch.cuda.synchronize()
+    outs = (F.U, F.S, F.V, F.ranks, F.cert, F.fro, F.info, lt.widths)
+    ref = [t.clone() for t in outs]
+    w = lt.widths.cpu().numpy()
+    assert np.all(w[: nf // 2] == 16) and np.all(w[nf // 2:] == 40)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        lt(xh, pred, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        lt(xh, pred)
+    for rep in range(3):
+        for t in outs:
+            t.fill_(-7)
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(outs, ref):
+            assert torch.equal(a, b), rep
+        del junk
