@@ -385,6 +385,38 @@ def apply_main(args):
         "roofline": roof,
         "kernels_ms_per_step": {k2: round(v["ms_per_step"], 4) for k2, v in kern.items()},
     }
+    # the other compute types on the same operator: BF16 (BF16 matrix cores) on
+    # the FP32 factors, FP64 (vector units) on FP64 factors of the same draws
+    Ud64 = api.transform(torch.from_numpy(np.asfortranarray(w["U"]).ravel(order="F")).to(dev), m, k, n, C.M_DFT, +1)
+    Vd64 = api.transform(torch.from_numpy(np.asfortranarray(w["V"]).ravel(order="F")).to(dev), p, k, n, C.M_DFT, +1)
+    F64 = api.Factors(m, p, nf, k, Ud64, S, Vd64, F.ranks, F.cert, F.fro, F.info)
+    x64 = torch.from_numpy(np.asfortranarray(w["X"]).ravel(order="F")).to(dev)
+    y64 = torch.empty(ell * m * nrhs, dtype=torch.float64, device=dev)
+    ybf = torch.empty_like(y)
+    other = {}
+    for name, cmp, Fx, xx, yy in (("bf16", C.BF16, F, x, ybf), ("f64", C.F64, F64, x64, y64)):
+        dsc = Fx.desc()
+        nd = C.tsvdm_apply_workspace_size(md, dsc, ell, q, nrhs, cmp)
+        wsx = torch.empty(max(nd, 1), dtype=torch.uint8, device=dev)
+
+        def run(dsc=dsc, cmp=cmp, xx=xx, yy=yy, wsx=wsx, nd=nd):
+            C.tsvdm_apply(md, dsc, ell, q, nrhs, xx.data_ptr(), q * n, yy.data_ptr(), ell * m, cmp, wsx.data_ptr(),
+                          nd, stream.cuda_stream)
+
+        run()
+        torch.cuda.synchronize()
+        reps = max(1, min(args.steps, 10))
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        a0.record(stream)
+        for _ in range(reps):
+            run()
+        a1.record(stream)
+        torch.cuda.synchronize()
+        msx = a0.elapsed_time(a1) / reps
+        other[name] = {"ms_per_call": msx, "dense_equiv_gflops": dense_flops / (msx / 1e3) / 1e9}
+        del wsx
+    out["other_compute_types"] = other
     if not args.no_cpu_baseline:
         out["cpu_baseline"], y_ref = apply_cpu_baseline(w, ell, q, m, n, k, nrhs)
         # the result of the last timed call against the oracle's dense FP64 product
@@ -392,6 +424,9 @@ def apply_main(args):
         torch.cuda.synchronize()
         yg = y.cpu().numpy().astype(np.float64).reshape((ell * m, nrhs), order="F")
         out["oracle_rel_err"] = float(np.linalg.norm(yg - y_ref) / np.linalg.norm(y_ref))
+        for name, yy in (("bf16", ybf), ("f64", y64)):
+            yo = yy.cpu().numpy().astype(np.float64).reshape((ell * m, nrhs), order="F")
+            other[name]["oracle_rel_err"] = float(np.linalg.norm(yo - y_ref) / np.linalg.norm(y_ref))
     if args.kernel_table:
         for kname, v in sorted(kern.items(), key=lambda kv: -kv[1]["ms_per_step"]):
             print(f"{kname:24s} {v['launches']:6d} launches  {v['ms_per_step'] * 1e3:10.1f} us/step",

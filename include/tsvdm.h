@@ -432,10 +432,11 @@ size_t tsvdm_apply_workspace_size(const tsvdm_mdesc *M, const tsvdm_factors *F, 
  * x: (q*n3) x nrhs, column major (ldx), y: (ell*m) x nrhs (ldy), both real of
  * the compute type's precision: FP32 for compute = F32 (or BF16), FP64 for
  * compute = F64.  Factor precision must match (F32/C64 or F64/C128).
- * F32 and BF16 (operands rounded to BF16, FP32 products) run the per-face
- * products on FP32 matrix cores when every per-face buffer is under 2 GiB,
- * else, like F64, on the vector units.  Asynchronous on stream; launches
- * kernels only. */
+ * F32 runs the per-face products on FP32 matrix cores, BF16 on BF16 matrix
+ * cores (operands, and Z between the two products, rounded to BF16; FP32
+ * accumulation), when every per-face buffer is under 2 GiB; otherwise, and
+ * for F64, on the vector units (BF16 then rounds the operands only).
+ * Asynchronous on stream; launches kernels only. */
 tsvdm_status tsvdm_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell, int64_t q,
                          int64_t nrhs, const void *x, int64_t ldx, void *y, int64_t ldy,
                          int32_t compute, void *workspace, size_t workspace_bytes, void *stream);

@@ -160,6 +160,19 @@ constexpr uint32_t kMiss = 0x80000000u;
 
 __device__ __forceinline__ uint32_t miss_if(bool bad) { return bad ? kMiss : 0u; }
 
+// BF16 compute: four FP32 16x16x4 steps t = 0..3 of a lane take operands at
+// k = 4 kl + t, which is the lane's operand of one BF16 16x16x16 MFMA (a lane
+// holds k = 4 (lane/16) .. + 3 of its row, or column), with the same output
+// layout; so each group of four FP32 MFMAs becomes one on BF16 operands
+// (rounded to nearest even; V, x~ and U S are BF16 values already).
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ s16x4 pk4(float a, float b, float c, float d) {
+    return s16x4{(short)f2bf(a), (short)f2bf(b), (short)f2bf(c), (short)f2bf(d)};
+}
+__device__ __forceinline__ f32x4 mfma_bf4(const s16x4 &a, const s16x4 &b, const f32x4 &c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
 // Vp_f(k + q j, r) = Vhat_f(j + l k, r): the rows a block row j takes, made
 // contiguous in k (one thread per element of E floats, read in order)
 template <int E>
@@ -260,19 +273,33 @@ __global__ __launch_bounds__(AT) void k_apply_mfma(const float *__restrict__ U, 
                     vra[2] = __uint_as_float(g2); vra[3] = __uint_as_float(g3);
                     via[0] = via[1] = via[2] = via[3] = 0.0f;
                 }
+                float vrt[4], vit[4];
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
                     // a partial last group reads the next block row's rows
                     const bool kin = k0 + t < q;
-                    float vr = kin ? vra[t] : 0.0f, vi = kin ? via[t] : 0.0f;
+                    vrt[t] = kin ? vra[t] : 0.0f;
+                    vit[t] = kin ? via[t] : 0.0f;
                     if (BF) {
-                        vr = rbf(vr);
-                        vi = rbf(vi);
+                        vrt[t] = rbf(vrt[t]);
+                        vit[t] = rbf(vit[t]);
                     }
-                    zr[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr, xr[t], zr[rb], 0, 0, 0);
+                }
+                if constexpr (BF) {
+                    zr[rb] = mfma_bf4(pk4(vrt[0], vrt[1], vrt[2], vrt[3]), pk4(xr[0], xr[1], xr[2], xr[3]), zr[rb]);
                     if (CPLX) {
-                        zi[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vi, xi[t], zi[rb], 0, 0, 0);
-                        z3[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr + vi, xr[t] + xi[t], z3[rb], 0, 0, 0);
+                        zi[rb] = mfma_bf4(pk4(vit[0], vit[1], vit[2], vit[3]), pk4(xi[0], xi[1], xi[2], xi[3]), zi[rb]);
+                        z3[rb] = mfma_bf4(pk4(vrt[0] + vit[0], vrt[1] + vit[1], vrt[2] + vit[2], vrt[3] + vit[3]),
+                                          pk4(xr[0] + xi[0], xr[1] + xi[1], xr[2] + xi[2], xr[3] + xi[3]), z3[rb]);
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        zr[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vrt[t], xr[t], zr[rb], 0, 0, 0);
+                        if (CPLX) {
+                            zi[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vit[t], xi[t], zi[rb], 0, 0, 0);
+                            z3[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vrt[t] + vit[t], xr[t] + xi[t], z3[rb], 0, 0, 0);
+                        }
                     }
                 }
             }
@@ -288,6 +315,7 @@ __global__ __launch_bounds__(AT) void k_apply_mfma(const float *__restrict__ U, 
         // y += w Re(U S Z): A operand (U S)(a0 + 16 ab + l16, 16 rb + 4 kl + s)
 #pragma unroll
         for (int rb = 0; rb < NRB; ++rb) {
+            float bu[4][4], bv[4][4];  // BF16 compute: (U S w) of the four steps, per ab
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const int r = 16 * rb + 4 * kl + s;
@@ -314,9 +342,22 @@ __global__ __launch_bounds__(AT) void k_apply_mfma(const float *__restrict__ U, 
                     if (BF) {
                         usr = rbf(usr);
                         usi = rbf(usi);
+                        bu[ab][s] = usr * wgt;
+                        bv[ab][s] = usi * wgt;
+                    } else {
+                        acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(usr * wgt, bzr, acc[ab], 0, 0, 0);
+                        if (CPLX) acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(usi * wgt, bzi, acc[ab], 0, 0, 0);
                     }
-                    acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(usr * wgt, bzr, acc[ab], 0, 0, 0);
-                    if (CPLX) acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(usi * wgt, bzi, acc[ab], 0, 0, 0);
+                }
+            }
+            if constexpr (BF) {
+                const float z0 = zr[rb][0], z1 = zr[rb][1], z2 = zr[rb][2], z3v = zr[rb][3];
+                const float w0 = zi[rb][0], w1 = zi[rb][1], w2 = zi[rb][2], w3 = zi[rb][3];
+#pragma unroll
+                for (int ab = 0; ab < 4; ++ab) {
+                    acc[ab] = mfma_bf4(pk4(bu[ab][0], bu[ab][1], bu[ab][2], bu[ab][3]), pk4(z0, z1, z2, z3v), acc[ab]);
+                    if (CPLX)
+                        acc[ab] = mfma_bf4(pk4(bv[ab][0], bv[ab][1], bv[ab][2], bv[ab][3]), pk4(w0, w1, w2, w3), acc[ab]);
                 }
             }
         }
@@ -514,12 +555,21 @@ __global__ __launch_bounds__(AT) void k_apply_lds(const float *__restrict__ U, c
                     vr[0] = va.x; vr[1] = va.y; vr[2] = va.z; vr[3] = va.w;
                     vi[0] = vi[1] = vi[2] = vi[3] = 0.0f;
                 }
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    zr[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[t], xr[t], zr[rb], 0, 0, 0);
+                if constexpr (BF) {
+                    zr[rb] = mfma_bf4(pk4(vr[0], vr[1], vr[2], vr[3]), pk4(xr[0], xr[1], xr[2], xr[3]), zr[rb]);
                     if (CPLX) {
-                        zi[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vi[t], xi[t], zi[rb], 0, 0, 0);
-                        z3[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[t] + vi[t], xr[t] + xi[t], z3[rb], 0, 0, 0);
+                        zi[rb] = mfma_bf4(pk4(vi[0], vi[1], vi[2], vi[3]), pk4(xi[0], xi[1], xi[2], xi[3]), zi[rb]);
+                        z3[rb] = mfma_bf4(pk4(vr[0] + vi[0], vr[1] + vi[1], vr[2] + vi[2], vr[3] + vi[3]),
+                                          pk4(xr[0] + xi[0], xr[1] + xi[1], xr[2] + xi[2], xr[3] + xi[3]), z3[rb]);
+                    }
+                } else {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        zr[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[t], xr[t], zr[rb], 0, 0, 0);
+                        if (CPLX) {
+                            zi[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vi[t], xi[t], zi[rb], 0, 0, 0);
+                            z3[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(vr[t] + vi[t], xr[t] + xi[t], z3[rb], 0, 0, 0);
+                        }
                     }
                 }
             }
@@ -547,12 +597,21 @@ __global__ __launch_bounds__(AT) void k_apply_lds(const float *__restrict__ U, c
                         ur[0] = ua.x; ur[1] = ua.y; ur[2] = ua.z; ur[3] = ua.w;
                         ui[0] = ui[1] = ui[2] = ui[3] = 0.0f;
                     }
+                    if constexpr (BF) {
+                        const float z0 = zr[rb][0], z1 = zr[rb][1], z2 = zr[rb][2], z3v = zr[rb][3];
+                        acc[ab] = mfma_bf4(pk4(ur[0], ur[1], ur[2], ur[3]), pk4(z0, z1, z2, z3v), acc[ab]);
+                        if (CPLX) {
+                            const float w0 = zi[rb][0], w1 = zi[rb][1], w2 = zi[rb][2], w3 = zi[rb][3];
+                            acc[ab] = mfma_bf4(pk4(ui[0], ui[1], ui[2], ui[3]), pk4(w0, w1, w2, w3), acc[ab]);
+                        }
+                    } else {
 #pragma unroll
-                    for (int sx = 0; sx < 4; ++sx) {
-                        const float bzr = zr[rb][sx];
-                        const float bzi = zi[rb][sx];
-                        acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[sx], bzr, acc[ab], 0, 0, 0);
-                        if (CPLX) acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(ui[sx], bzi, acc[ab], 0, 0, 0);
+                        for (int sx = 0; sx < 4; ++sx) {
+                            const float bzr = zr[rb][sx];
+                            const float bzi = zi[rb][sx];
+                            acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(ur[sx], bzr, acc[ab], 0, 0, 0);
+                            if (CPLX) acc[ab] = __builtin_amdgcn_mfma_f32_16x16x4f32(ui[sx], bzi, acc[ab], 0, 0, 0);
+                        }
                     }
                 }
                 zr[rb] = zi[rb] = z3[rb] = f32x4{0, 0, 0, 0};

@@ -83,3 +83,12 @@ def test_apply_face_ranks_below_kmax(kind, compute, k):
     ranks[0], ranks[2], ranks[-1] = 0, 0, k  # zero-rank faces first and in the middle
     y, y_ref = _case(kind, m, ell, q, n, k, nrhs, compute, ranks=ranks)
     assert relerr(y, y_ref) < TOL[compute], relerr(y, y_ref)
+
+
+@pytest.mark.parametrize("compute", [C.BF16, C.F64])
+def test_apply_full_size_dft_other_precisions(compute):
+    """The 4096 x 4096 structured matrix (l = q = m = n = 64, rank 16, DFT) on
+    1024 right-hand sides in BF16 (BF16 matrix cores) and FP64, against the
+    dense FP64 product: BF16 within its tolerance, FP64 to 1e-10."""
+    y, y_ref = _case(C.M_DFT, 64, 64, 64, 64, 16, 1024, compute)
+    assert relerr(y, y_ref) < TOL[compute], relerr(y, y_ref)
