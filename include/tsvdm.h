@@ -434,9 +434,9 @@ size_t tsvdm_apply_workspace_size(const tsvdm_mdesc *M, const tsvdm_factors *F, 
  * compute = F64.  Factor precision must match (F32/C64 or F64/C128).
  * F32 runs the per-face products on FP32 matrix cores, BF16 on BF16 matrix
  * cores (operands, and Z between the two products, rounded to BF16; FP32
- * accumulation), when every per-face buffer is under 2 GiB; otherwise, and
- * for F64, on the vector units (BF16 then rounds the operands only).
- * Asynchronous on stream; launches kernels only. */
+ * accumulation), F64 on FP64 matrix cores, when every per-face buffer is
+ * under 2 GiB; otherwise on the vector units (BF16 then rounds the operands
+ * only).  Asynchronous on stream; launches kernels only. */
 tsvdm_status tsvdm_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell, int64_t q,
                          int64_t nrhs, const void *x, int64_t ldx, void *y, int64_t ldy,
                          int32_t compute, void *workspace, size_t workspace_bytes, void *stream);

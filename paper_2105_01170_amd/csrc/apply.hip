@@ -632,6 +632,203 @@ __global__ __launch_bounds__(AT) void k_apply_lds(const float *__restrict__ U, c
     }
 }
 
+// FP64 compute on FP64 matrix cores: the contraction of k_apply_lds with FP64
+// operands and the FP64 16x16x4 MFMA (A[i][k]: lane%16 = i, lane/16 = k;
+// B[k][j]: lane/16 = k, lane%16 = j; result row lane/16 + 4v, column lane%16).
+// Workgroup: block row j, rows a0 .. a0+63, 64 columns; wavefront w owns
+// columns c0 + 16 w .. + 15.  Per face and chunk of 16 k the workgroup stages
+// x~ (64 columns), the NRB*16 rank rows of Vp and, on the first chunk, U S w
+// (64 rows) in LDS with 16-byte loads (one complex, or two real, values);
+// instruction kk of a chunk takes k = 4 kk + lane/16.  Z stays in the
+// accumulators: entry v of lane (l16, kl) is Z(16 rb + kl + 4 v, l16), which
+// is the B operand of step v of the second product, whose A operand is
+// (U S w)(a, 16 rb + kl + 4 v).  Complex products by three real ones, as in
+// the FP32 kernel.  Elements that do not exist load as zero (2^31 offset of a
+// buffer resource per face, each under 2 GiB, checked on the host).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+template <bool CPLX, int NRB>
+__global__ __launch_bounds__(AT) void k_apply_f64(const double *__restrict__ U, const double *__restrict__ S,
+                                                  const double *__restrict__ Vp, const int32_t *__restrict__ ranks,
+                                                  int m, int p, int kmax, int nf, int n3, int ell, int q,
+                                                  const double *__restrict__ xt, int nrhs, double *__restrict__ y,
+                                                  int64_t ldy) {
+    constexpr int E = CPLX ? 2 : 1;
+    constexpr int KC = 16;              // k per chunk
+    constexpr int XS = KC * E + 2;      // doubles per staged column of x~ or row of Vp
+    constexpr int RK = 16 * NRB;        // ranks held
+    constexpr int US = RK * E + 2;      // doubles per staged row of U S
+    constexpr int KPC = 2 / E;          // k (or rows a) per 16-byte piece
+    constexpr int CH = KC / KPC;        // pieces per column
+    __shared__ __align__(16) double xs[64 * XS];
+    __shared__ __align__(16) double vs[RK * XS];
+    __shared__ __align__(16) double us[64 * US];
+    const int kcap = kmax < RK ? kmax : RK;
+    const int mtiles = (m + 63) >> 6;
+    const int j = blockIdx.x / mtiles, a0 = (blockIdx.x % mtiles) * 64;
+    const int c0 = blockIdx.y * 64;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int l16 = lane & 15, kl = lane >> 4;
+    constexpr int NXU = (64 * CH + AT - 1) / AT;
+    constexpr int NVU = (RK * CH + AT - 1) / AT;
+    constexpr int NUU = (RK * (64 / KPC) + AT - 1) / AT;
+    f64x4 acc[4];
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab) acc[ab] = f64x4{0, 0, 0, 0};
+    auto face_rank = [&](int f) {
+        const int r = ranks[f];
+        return r < kcap ? r : kcap;
+    };
+    auto next_face = [&](int f) {
+        while (f < nf && face_rank(f) <= 0) ++f;
+        return f;
+    };
+    u32x4 gx[NXU], gv[NVU], gu[NUU];
+    double gs[NUU];
+    auto load_stage = [&](int f, int kc0) {
+        const int kf = face_rank(f);
+        const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<double *>(xt) + (int64_t)f * q * nrhs * E, 0, q * nrhs * E * 8, 0x00020000);
+        const __amdgpu_buffer_rsrc_t rv = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<double *>(Vp) + (int64_t)f * p * kmax * E, 0, p * kmax * E * 8, 0x00020000);
+        const __amdgpu_buffer_rsrc_t ru = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<double *>(U) + (int64_t)f * m * kmax * E, 0, m * kmax * E * 8, 0x00020000);
+#pragma unroll
+        for (int u = 0; u < NXU; ++u) {
+            const int g = u * AT + tid, cc = g / CH, hh = g % CH;
+            const int k = kc0 + KPC * hh, c = c0 + cc;
+            const uint32_t xo = (((uint32_t)k + (uint32_t)q * (uint32_t)c) * (8u * E)) |
+                                miss_if(g >= 64 * CH || c >= nrhs || k >= q);
+            gx[u] = __builtin_amdgcn_raw_buffer_load_b128(rx, (int)xo, 0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < NVU; ++u) {
+            const int g = u * AT + tid, r = g / CH, hh = g % CH;
+            const int k = kc0 + KPC * hh;
+            const uint32_t vo = (((uint32_t)k + (uint32_t)q * (uint32_t)j + (uint32_t)p * (uint32_t)r) * (8u * E)) |
+                                miss_if(g >= RK * CH || r >= kf || k >= q);
+            gv[u] = __builtin_amdgcn_raw_buffer_load_b128(rv, (int)vo, 0, 0);
+        }
+        if (kc0 == 0) {
+#pragma unroll
+            for (int u = 0; u < NUU; ++u) {
+                const int g = u * AT + tid, r = g / (64 / KPC), hh = g % (64 / KPC);
+                const int a = a0 + KPC * hh;
+                const bool rin = g < RK * (64 / KPC) && r < kf;
+                const uint32_t uo = (((uint32_t)a + (uint32_t)m * (uint32_t)r) * (8u * E)) | miss_if(!rin || a >= m);
+                gu[u] = __builtin_amdgcn_raw_buffer_load_b128(ru, (int)uo, 0, 0);
+                gs[u] = rin ? S[(int64_t)f * kmax + r] : 0.0;
+            }
+        }
+    };
+    // a 16-byte piece as two doubles; a real piece across q reads the next
+    // column or row: its second entry past q is zeroed
+    auto put = [&](double *dst, const u32x4 &v, int k) {
+        const uint32_t e0 = v.x, e1 = v.y, e2 = v.z, e3 = v.w;
+        const double d0 = __hiloint2double((int)e1, (int)e0);
+        double d1 = __hiloint2double((int)e3, (int)e2);
+        if (!CPLX && k + 1 >= q) d1 = 0.0;
+        *reinterpret_cast<double2 *>(dst) = double2{d0, d1};
+    };
+    auto store_stage = [&](int f, int kc0) {
+        const double wgt = (CPLX && !(f == 0 || 2 * f == n3)) ? 2.0 : 1.0;
+#pragma unroll
+        for (int u = 0; u < NXU; ++u) {
+            const int g = u * AT + tid, cc = g / CH, hh = g % CH;
+            if (g < 64 * CH) put(&xs[cc * XS + KPC * hh * E], gx[u], kc0 + KPC * hh);
+        }
+#pragma unroll
+        for (int u = 0; u < NVU; ++u) {
+            const int g = u * AT + tid, r = g / CH, hh = g % CH;
+            if (g < RK * CH) put(&vs[r * XS + KPC * hh * E], gv[u], kc0 + KPC * hh);
+        }
+        if (kc0 == 0) {
+#pragma unroll
+            for (int u = 0; u < NUU; ++u) {
+                const int g = u * AT + tid, r = g / (64 / KPC), hh = g % (64 / KPC);
+                if (g >= RK * (64 / KPC)) continue;
+                const int a = a0 + KPC * hh;
+                const uint32_t e0 = gu[u].x, e1 = gu[u].y, e2 = gu[u].z, e3 = gu[u].w;
+                const double d[2] = {__hiloint2double((int)e1, (int)e0), __hiloint2double((int)e3, (int)e2)};
+#pragma unroll
+                for (int i = 0; i < KPC; ++i) {
+                    const bool ain = a + i < m;
+#pragma unroll
+                    for (int ee = 0; ee < E; ++ee)
+                        us[(KPC * hh + i) * US + r * E + ee] = ain ? d[i * E + ee] * gs[u] * wgt : 0.0;
+                }
+            }
+        }
+    };
+    f64x4 zr[NRB], zi[NRB], z3[NRB];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb) zr[rb] = zi[rb] = z3[rb] = f64x4{0, 0, 0, 0};
+    int f = next_face(0), kc0 = 0;
+    if (f < nf) load_stage(f, 0);
+    while (f < nf) {
+        __syncthreads();  // the previous stage's operands are consumed
+        store_stage(f, kc0);
+        __syncthreads();
+        int fn = f, kn = kc0 + KC;
+        if (kn >= q) {
+            fn = next_face(f + 1);
+            kn = 0;
+        }
+        if (fn < nf) load_stage(fn, kn);
+        const int nkk = (q - kc0 < KC ? q - kc0 + 3 : KC) >> 2;
+        for (int kk = 0; kk < nkk; ++kk) {
+            const double *xp = &xs[(16 * w + l16) * XS + (4 * kk + kl) * E];
+            const double xr = xp[0], xi = CPLX ? xp[1] : 0.0;
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb) {
+                const double *vp = &vs[(16 * rb + l16) * XS + (4 * kk + kl) * E];
+                const double vr = vp[0], vi = CPLX ? vp[1] : 0.0;
+                zr[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr, xr, zr[rb], 0, 0, 0);
+                if (CPLX) {
+                    zi[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(vi, xi, zi[rb], 0, 0, 0);
+                    z3[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(vr + vi, xr + xi, z3[rb], 0, 0, 0);
+                }
+            }
+        }
+        if (kc0 + KC >= q) {
+            // the face is complete: y += Re(U S w Z)
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb) {
+                if (CPLX) {
+                    const f64x4 p1 = zr[rb], p2 = zi[rb];
+                    zr[rb] = p1 - p2;           // Vr Xr - Vi Xi
+                    zi[rb] = z3[rb] - p1 - p2;  // Vr Xi + Vi Xr = -Im Z
+                }
+#pragma unroll
+                for (int ab = 0; ab < 4; ++ab) {
+#pragma unroll
+                    for (int sx = 0; sx < 4; ++sx) {
+                        const double *up = &us[(16 * ab + l16) * US + (16 * rb + kl + 4 * sx) * E];
+                        const double bzr = zr[rb][sx];
+                        acc[ab] = __builtin_amdgcn_mfma_f64_16x16x4f64(up[0], bzr, acc[ab], 0, 0, 0);
+                        if (CPLX) {
+                            const double bzi = zi[rb][sx];
+                            acc[ab] = __builtin_amdgcn_mfma_f64_16x16x4f64(up[1], bzi, acc[ab], 0, 0, 0);
+                        }
+                    }
+                }
+                zr[rb] = zi[rb] = z3[rb] = f64x4{0, 0, 0, 0};
+            }
+        }
+        f = fn;
+        kc0 = kn;
+    }
+    const int c = c0 + 16 * w + l16;
+    if (c < nrhs) {
+#pragma unroll
+        for (int ab = 0; ab < 4; ++ab)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int a = a0 + 16 * ab + kl + 4 * v;
+                if (a < m) y[((int64_t)j * m + a) + ldy * c] = acc[ab][v];
+            }
+    }
+}
+
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
@@ -643,9 +840,8 @@ size_t apply_workspace(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell
     (void)ell;
     const bool cplx = M->kind == TSVDM_M_DFT;
     const size_t es = (compute == TSVDM_F64 ? 8 : 4) * (cplx ? 2 : 1);
-    // the transformed right-hand sides; FP32 and BF16 also the relaid-out V
-    return al256(es * (size_t)q * nrhs * F->nf) +
-           (compute == TSVDM_F64 ? 0 : al256(es * (size_t)F->p * F->kmax * F->nf));
+    // the transformed right-hand sides and the relaid-out V
+    return al256(es * (size_t)q * nrhs * F->nf) + al256(es * (size_t)F->p * F->kmax * F->nf);
 }
 
 tsvdm_status launch_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t ell, int64_t q,
@@ -691,6 +887,47 @@ tsvdm_status launch_apply(const tsvdm_mdesc *M, const tsvdm_factors *F, int64_t 
                            ((int64_t)q * (ell + 1) + 16 + F->p * (int64_t)64) * 4 * E + 64 < lim &&
                            (F->m + 64 + F->m * (int64_t)64) * 4 * E < lim && F->p * F->kmax * 4 * E < lim &&
                            mtiles * ell < lim;
+    // FP64: the FP64 matrix-core kernel under the same 2 GiB conditions on
+    // 8-byte elements
+    const bool mfma64_fits = dbl && (int64_t)q * (nrhs + 64) * 8 * E + 64 < lim &&
+                             ((int64_t)q * (ell + 1) + 16 + F->p * (int64_t)64) * 8 * E + 64 < lim &&
+                             (F->m + 64 + F->m * (int64_t)64) * 8 * E < lim && F->p * F->kmax * 8 * E < lim &&
+                             mtiles * ell < lim;
+    if (mfma64_fits) {
+        const int nrb = (kcap + 15) / 16;
+        double *Vp = reinterpret_cast<double *>(reinterpret_cast<char *>(ws) + al256(es * (size_t)q * nrhs * nf));
+        const int64_t tot = F->p * F->kmax * nf;
+        if (tot > 0) {
+            // the relayout moves whole elements: 4 (complex) or 2 (real) floats each
+            const dim3 gr((unsigned)((tot + 255) / 256));
+            if (cplx)
+                TSVDM_LAUNCH("apply_v_relayout", k_vrelayout<4>, gr, dim3(256), 0, s,
+                             reinterpret_cast<const float *>(F->V), reinterpret_cast<float *>(Vp), F->p, ell, q, tot);
+            else
+                TSVDM_LAUNCH("apply_v_relayout", k_vrelayout<2>, gr, dim3(256), 0, s,
+                             reinterpret_cast<const float *>(F->V), reinterpret_cast<float *>(Vp), F->p, ell, q, tot);
+        }
+#define TSVDM_APPLY64(C, NRB)                                                                                 \
+    TSVDM_LAUNCH("apply_fused", (k_apply_f64<C, NRB>), grid, dim3(AT), 0, s,                                   \
+                 reinterpret_cast<const double *>(F->U), F->S, (const double *)Vp, F->ranks, (int)F->m, (int)F->p, \
+                 (int)F->kmax, (int)nf, (int)n3, (int)ell, (int)q, reinterpret_cast<const double *>(ws), (int)nrhs, \
+                 reinterpret_cast<double *>(y), ldy)
+#define TSVDM_APPLY64_NRB(C)                          \
+    do {                                              \
+        switch (nrb) {                                \
+            case 1: TSVDM_APPLY64(C, 1); break;       \
+            case 2: TSVDM_APPLY64(C, 2); break;       \
+            case 3: TSVDM_APPLY64(C, 3); break;       \
+            default: TSVDM_APPLY64(C, 4); break;      \
+        }                                             \
+    } while (0)
+        if (cplx) TSVDM_APPLY64_NRB(true);
+        else TSVDM_APPLY64_NRB(false);
+#undef TSVDM_APPLY64_NRB
+#undef TSVDM_APPLY64
+        TSVDM_LAUNCH_CHECK("k_apply_f64");
+        return TSVDM_OK;
+    }
     if (mfma_fits) {
         const int nrb = (kcap + 15) / 16;
         float *Vp = reinterpret_cast<float *>(reinterpret_cast<char *>(ws) + al256(es * (size_t)q * nrhs * nf));
