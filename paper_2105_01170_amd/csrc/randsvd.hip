@@ -947,7 +947,10 @@ __global__ __launch_bounds__(QT) void k_cholqr(const T *__restrict__ Sin, int ro
                                                int src_lp = LP) {
     constexpr bool D = sizeof(T) == 8;
     constexpr int LDG = LP + 1, LDR = LP + 2, LDS_ = LP + 1;
-    constexpr int HR = D ? (LP <= 32 ? QT / 2 : QT / 4) : (LP <= 48 ? QT : QT / 2);
+    // rows staged per LDS round for the second pass's Gram: a quarter of the
+    // chunk keeps the kernel's LDS near 60 KB at width 48, so GEMM workgroups
+    // of another face group can share the CU with it
+    constexpr int HR = D ? (LP <= 32 ? QT / 2 : QT / 4) : QT / 4;
     constexpr int NT = LP / 16, NTILE = NT * (NT + 1) / 2, TPW = (NTILE + 7) / 8;
     __shared__ double G[LP * LDG];
     __shared__ __align__(16) double Rt[LP * LDR];  // Rt[c * LDR + j] = R[j][c]
@@ -1655,6 +1658,38 @@ bool vec_loads_ok(const float *X, int m, int p) {
     return m % 4 == 0 && p % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0 &&
            (int64_t)m * p < (int64_t)1 << 30;
 }
+// Three streams and four events per device, created on first use and kept
+// until the process ends: the three width buckets of a learned truncation run
+// concurrently (their FP64 steps are latency-bound, one workgroup per face).
+// Default priority.  Learned truncations issued from several host threads at
+// once on one device share them and must be serialized by the caller.
+struct SideStreams {
+    hipStream_t s[3];
+    hipEvent_t ev[4];
+};
+std::mutex g_side_mu;
+SideStreams *g_side[64];
+
+tsvdm_status side_streams(SideStreams **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_check(e, "side streams: device");
+    if (dev < 0 || dev >= 64) {
+        set_error("side streams: device index %d beyond 64", dev);
+        return TSVDM_EUNSUPPORTED;
+    }
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    if (!g_side[dev]) {
+        SideStreams t{};
+        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&t.s[i], hipStreamNonBlocking);
+        for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&t.ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) return hip_check(e, "side streams: create");
+        g_side[dev] = new SideStreams(t);
+    }
+    *out = g_side[dev];
+    return TSVDM_OK;
+}
+
 // wf0: the face of the workspace w0 the group starts at (f0 when w0 was carved
 // for the whole tensor, 0 when it was carved for the group alone).
 // fmap: the group's faces (entries < 0: unused slots of a list sized on the
@@ -2071,37 +2106,6 @@ size_t learned_carve(char *base, int64_t m, int64_t p, int64_t nf, LearnedWs *w)
     return off;
 }
 
-// Three streams and four events per device, created on first use and kept
-// until the process ends: the three width buckets of a learned truncation run
-// concurrently (their FP64 steps are latency-bound, one workgroup per face).
-// Default priority.  Learned truncations issued from several host threads at
-// once on one device share them and must be serialized by the caller.
-struct SideStreams {
-    hipStream_t s[3];
-    hipEvent_t ev[4];
-};
-std::mutex g_side_mu;
-SideStreams *g_side[64];
-
-tsvdm_status side_streams(SideStreams **out) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_check(e, "learned truncate: device");
-    if (dev < 0 || dev >= 64) {
-        set_error("learned truncate: device index %d beyond 64", dev);
-        return TSVDM_EUNSUPPORTED;
-    }
-    std::lock_guard<std::mutex> lk(g_side_mu);
-    if (!g_side[dev]) {
-        SideStreams t{};
-        for (int i = 0; i < 3 && e == hipSuccess; ++i) e = hipStreamCreateWithFlags(&t.s[i], hipStreamNonBlocking);
-        for (int i = 0; i < 4 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&t.ev[i], hipEventDisableTiming);
-        if (e != hipSuccess) return hip_check(e, "learned truncate: side streams");
-        g_side[dev] = new SideStreams(t);
-    }
-    *out = g_side[dev];
-    return TSVDM_OK;
-}
 }  // namespace
 
 size_t learned_workspace(int64_t m, int64_t p, int64_t nf) { return learned_carve(nullptr, m, p, nf, nullptr); }

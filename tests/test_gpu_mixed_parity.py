@@ -213,3 +213,4 @@ def test_mixed_rows_over_several_qr_chunks():
         assert np.abs(Uf.T @ Uf - np.eye(k)).max() < 1e-5
     true = np.array([np.linalg.norm(Xh64[:, :, f] - That[:, :, f]) for f in range(nf)])
     np.testing.assert_allclose(got["cert"], true, rtol=1e-9, atol=1e-14 * np.max(got["fro"]))
+
