@@ -601,14 +601,22 @@ tsvdm_status tsvdm_rank_features(const tsvdm_tensor *Xhat, const float *omega, u
 size_t tsvdm_truncate_learned_workspace_size(const tsvdm_tensor *Xhat);
 
 /* Mixed-precision truncation (as tsvdm_truncate with PREC_MIXED and the
- * energy rule) whose sketch width is chosen per face by the predictor w16:
- * features, prediction (k/32, l/48) -> width = the smallest of 16, 32, 40 not
- * below ceil(48 l) + 1; the faces of each width are truncated together (rank
- * caps 13, 26, 32); faces whose certified error then exceeds tau ||Xhat_f|| are
- * truncated again with width 40.  widths (nf, device) receives each face's
- * final width.  opts: ENERGY, tau, omega (p x 40), power_iters, max_sweeps.
- * out->kmax >= 32; cert and fro are required.  Synchronizes the stream twice
- * (bucket sizes), so it cannot be captured in a graph. */
+ * energy rule) whose rank cap and sketch width are chosen per face by the
+ * predictor w16 (the learned part of step 3 of Algorithm alg:strategy):
+ * features, prediction (k/32, l/48) -> kh = ceil(32 k) in 1..32, lw =
+ * ceil(48 l) + 1; the face takes the first bucket (width 16, 32, 40 with rank
+ * caps 13, 26, 32) whose width is at least lw and cap at least kh, and the
+ * energy rule's cap min(bucket cap, kh + 2).  The feature sketch
+ * Xhat_f omega[:, :32] is the first sketch of the width-16 and width-32
+ * buckets.  Faces whose certified error then exceeds tau ||Xhat_f|| (and did
+ * not already run at width 40 with cap 32) are truncated again there.  widths
+ * (nf, device) receives each face's final width.  opts: ENERGY, tau, omega
+ * (p x 40), power_iters, max_sweeps.  out->kmax >= 32; cert and fro are
+ * required.  Launches kernels only (bucket sizes stay on the device): it can be
+ * captured in a graph.  The three buckets run on three streams the library
+ * creates per device on first use and joins back to `stream` with events;
+ * learned truncations issued at once from several host threads on one device
+ * share those streams and must be serialized by the caller. */
 tsvdm_status tsvdm_truncate_learned(const tsvdm_tensor *Xhat, const tsvdm_truncate_opts *opts,
                                     const uint16_t *w16, tsvdm_factors *out, int32_t *widths,
                                     void *workspace, size_t workspace_bytes, void *stream);
