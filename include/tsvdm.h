@@ -614,9 +614,11 @@ size_t tsvdm_truncate_learned_workspace_size(const tsvdm_tensor *Xhat);
  * (p x 40), power_iters, max_sweeps.  out->kmax >= 32; cert and fro are
  * required.  Launches kernels only (bucket sizes stay on the device): it can be
  * captured in a graph.  The three buckets run on three streams the library
- * creates per device on first use and joins back to `stream` with events;
- * learned truncations issued at once from several host threads on one device
- * share those streams and must be serialized by the caller. */
+ * creates per device on first use (so the first call on a device must not be
+ * under stream capture; it returns an error if it is) and joins back to
+ * `stream` with events; learned truncations issued at once from several host
+ * threads on one device share those streams and must be serialized by the
+ * caller. */
 tsvdm_status tsvdm_truncate_learned(const tsvdm_tensor *Xhat, const tsvdm_truncate_opts *opts,
                                     const uint16_t *w16, tsvdm_factors *out, int32_t *widths,
                                     void *workspace, size_t workspace_bytes, void *stream);
