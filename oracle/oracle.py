@@ -415,8 +415,10 @@ def randomized_face(F: np.ndarray, Omega: np.ndarray, power_iters: int = 1,
 
 def randomized_tsvdm_faces(Xh: np.ndarray, Omega: np.ndarray, k: int, power_iters: int = 1,
                            mode: str = "fixed", tau: float = 0.0):
-    """Randomized facewise truncation of a real transform-domain tensor with
-    one shared Gaussian test matrix Omega (p x ell).
+    """Randomized facewise truncation of a transform-domain tensor (real, or
+    complex faces as the DFT gives) with one shared real Gaussian test matrix
+    Omega (p x ell); for complex faces the adjoint in the range finder is the
+    conjugate transpose and the norms are sums of |x|^2.
 
     Rank rule on the small SVD: fixed k, or the smallest k <= the cap k with
     ||F||^2 - sum_{j<=k} s_j^2 <= tau^2 ||F||^2 (the left side is the squared
@@ -425,18 +427,19 @@ def randomized_tsvdm_faces(Xh: np.ndarray, Omega: np.ndarray, k: int, power_iter
     the error ||F - T_f||_F of the kept approximation, formed explicitly."""
     m, p, nf = Xh.shape
     ell = Omega.shape[1]
-    U = np.zeros((m, ell, nf), order="F")
-    V = np.zeros((p, ell, nf), order="F")
+    dt = np.complex128 if np.iscomplexobj(Xh) else np.float64
+    U = np.zeros((m, ell, nf), dtype=dt, order="F")
+    V = np.zeros((p, ell, nf), dtype=dt, order="F")
     s = np.zeros((ell, nf), order="F")
     ranks = np.zeros(nf, dtype=np.int32)
     cert = np.zeros(nf)
-    That = np.zeros_like(Xh)
+    That = np.zeros_like(Xh, dtype=dt)
     for f in range(nf):
         F = Xh[:, :, f]
         Uf, sf, Vf, _ = randomized_face(F, Omega, power_iters)
         ns = sf.shape[0]
         U[:, :ns, f], s[:ns, f], V[:, :ns, f] = Uf, sf, Vf
-        fro2 = float(np.sum(F * F))
+        fro2 = float(np.sum(np.abs(F) ** 2))
         if mode == "fixed":
             kf = min(k, ns)
         else:
@@ -447,8 +450,8 @@ def randomized_tsvdm_faces(Xh: np.ndarray, Omega: np.ndarray, k: int, power_iter
                     kf = kk
                     break
         ranks[f] = kf
-        That[:, :, f] = (Uf[:, :kf] * sf[:kf]) @ Vf[:, :kf].T
-        cert[f] = np.sqrt(max(np.sum((F - That[:, :, f]) ** 2), 0.0))
+        That[:, :, f] = (Uf[:, :kf] * sf[:kf]) @ np.conj(Vf[:, :kf]).T
+        cert[f] = np.sqrt(max(np.sum(np.abs(F - That[:, :, f]) ** 2), 0.0))
     return dict(U=U, s=s, V=V, ranks=ranks, cert=cert, That=That)
 
 

@@ -536,3 +536,104 @@ def test_approx_from_factors_dct_full_rank_returns_input():
         U[:, :, f], S[:, f], V[:, :, f] = u, s, vh.T
     T = oracle.approx_from_factors(U, S, V, np.full(n, 4), oracle.dct2_matrix(n))
     assert np.max(np.abs(T - X)) < 1e-13
+
+
+# ------------------------------------------------------------ randomized, complex faces
+def _complex_faces_with_spectra(m, p, spectra, seed):
+    """Complex faces U_f diag(s_f) V_f^H with U_f, V_f the Q factors (numpy QR)
+    of complex Gaussian matrices: the singular values of face f are exactly
+    s_f, and the face is not the complexification of a real one."""
+    g = np.random.default_rng(seed)
+    Xh = np.zeros((m, p, len(spectra)), dtype=np.complex128, order="F")
+    for f, s in enumerate(spectra):
+        r = len(s)
+        Ua, _ = np.linalg.qr(g.standard_normal((m, r)) + 1j * g.standard_normal((m, r)))
+        Va, _ = np.linalg.qr(g.standard_normal((p, r)) + 1j * g.standard_normal((p, r)))
+        Xh[:, :, f] = (Ua * s) @ np.conj(Va).T
+    return Xh
+
+
+@pytest.mark.parametrize("shape", [(50, 36), (30, 44)])
+def test_randomized_complex_faces_exact_rank_and_eckart_young(shape):
+    """Complex faces of exact rank 9 with a real Gaussian Omega of width 14:
+    the range finder captures the range exactly (a real test matrix spans the
+    complex range of a generic complex face), so truncation at 9 returns the
+    face, the returned singular values are the constructed ones, and
+    truncation at 6 leaves the discarded singular values as the error
+    (Eckart-Young).  Dropping the conjugate of the adjoint anywhere in the
+    range finder or the reconstruction fails all three."""
+    m, p = shape
+    r = 9
+    spectra = [np.linspace(3.0, 0.5, r), 10.0 ** (-0.3 * np.arange(r))]
+    Xh = _complex_faces_with_spectra(m, p, spectra, 331)
+    Omega = _rand((p, r + 5), 332)
+    rr = oracle.randomized_tsvdm_faces(Xh, Omega, r, power_iters=1)
+    assert np.max(np.abs(rr["That"] - Xh)) < 1e-11 * np.abs(Xh).max()
+    assert np.all(rr["cert"] < 1e-11)
+    for f, s in enumerate(spectra):
+        np.testing.assert_allclose(rr["s"][:r, f], s, rtol=1e-12)
+        U, V = rr["U"][:, :r, f], rr["V"][:, :r, f]
+        assert np.max(np.abs(np.conj(U).T @ U - np.eye(r))) < 1e-12
+        assert np.max(np.abs(np.conj(V).T @ V - np.eye(r))) < 1e-12
+    rr6 = oracle.randomized_tsvdm_faces(Xh, Omega, 6, power_iters=0)
+    for f, s in enumerate(spectra):
+        assert rr6["cert"][f] == pytest.approx(np.sqrt(np.sum(s[6:] ** 2)), rel=1e-9)
+
+
+def test_randomized_complex_energy_rule_closed_form():
+    """The energy rule on complex faces of exact rank 12 (sketch width 16):
+    each rank is the closed-form crossing of its geometric spectrum, as for
+    real faces; the phases of the singular vectors do not enter."""
+    m, p, r, ell, tau = 60, 48, 12, 16, 1e-3
+    rhos = [0.25, 0.35, 0.45, 0.7, 0.9]
+    spectra = [10.0 ** (-rho * np.arange(1, r + 1)) for rho in rhos]
+    want = []
+    for rho in rhos:
+        k, x = _geometric_crossing(rho, tau, r)
+        assert min(x - np.floor(x), np.ceil(x) - x) >= 0.2 or k == r
+        want.append(min(k, r))
+    Xh = _complex_faces_with_spectra(m, p, spectra, 333)
+    Omega = _rand((p, ell), 334)
+    rr = oracle.randomized_tsvdm_faces(Xh, Omega, ell, power_iters=1, mode="energy", tau=tau)
+    assert list(rr["ranks"]) == want
+    for f, s in enumerate(spectra):
+        assert rr["cert"][f] == pytest.approx(np.sqrt(np.sum(s[want[f]:] ** 2)), rel=1e-6, abs=1e-13)
+
+
+def test_randomized_dft_half_spectrum_error_identity():
+    """Randomized truncation of the stored half spectrum of a real tensor's
+    unitary DFT, expanded to all faces by conjugation and transformed back:
+    the result is real and its error equals sqrt(sum_f w_f cert_f^2) with
+    w_f = 2 for the faces whose conjugate is not stored (unitarity of M and
+    Lemma lem:tenapprox)."""
+    m, p, n3, k = 24, 20, 6, 5
+    X = _rand((m, p, n3), 335)
+    M = oracle.dft_matrix(n3)
+    Xh = oracle.mode3(X, M)
+    half = n3 // 2 + 1
+    Omega = _rand((p, k + 4), 336)
+    rr = oracle.randomized_tsvdm_faces(np.asfortranarray(Xh[:, :, :half]), Omega, k, power_iters=1)
+    U, s, V, ranks = oracle.expand_hermitian(rr["U"], rr["s"], rr["V"], rr["ranks"], n3)
+    T = oracle.approx_from_factors(U, s, V, ranks, M)
+    assert np.max(np.abs(np.imag(T))) < 1e-12
+    w = np.array([1.0 if f in (0, n3 // 2) else 2.0 for f in range(half)])
+    err = np.linalg.norm((X - np.real(T)).ravel())
+    assert err == pytest.approx(np.sqrt(np.sum(w * rr["cert"] ** 2)), rel=1e-10)
+
+
+def test_randomized_complex_power_iteration_accuracy():
+    """Complex faces of rank 40 with s_j = 10^(-j/4) and a sketch of width 20:
+    one power iteration makes the leading ten Ritz values exact to ~1e-15
+    relative (the gap to s_21 enters to the sixth power, 10^(-16.5) for
+    j = 10), while a sketch without a correct power step is off by ~1e-5
+    (second power).  So the returned singular values pin the adjoint step
+    (the conjugate transpose) of the complex power iteration."""
+    m, p, r, ell = 70, 64, 40, 20
+    s = 10.0 ** (-0.25 * np.arange(1, r + 1))
+    Xh = _complex_faces_with_spectra(m, p, [s, s], 337)
+    Omega = _rand((p, ell), 338)
+    rr = oracle.randomized_tsvdm_faces(Xh, Omega, ell, power_iters=1)
+    for f in range(2):
+        np.testing.assert_allclose(rr["s"][:10, f], s[:10], rtol=1e-9)
+    r0 = oracle.randomized_tsvdm_faces(Xh, Omega, ell, power_iters=0)
+    assert np.max(np.abs(r0["s"][:10, 0] / s[:10] - 1.0)) > 1e-8  # the power step matters here
