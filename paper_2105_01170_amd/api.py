@@ -111,7 +111,10 @@ class Truncator:
             kmax = min(k if k > 0 else ns, ns)
             if precision != C.PREC_F64:
                 kmax = min(kmax, k + oversample)
-        fdt = torch.float32 if precision == C.PREC_MIXED else dtype
+        if precision == C.PREC_MIXED:  # FP32 factors, complex for complex faces
+            fdt = torch.complex64 if dtype == torch.complex64 else torch.float32
+        else:
+            fdt = dtype
         self.F = empty_factors(m, p, nf, max(kmax, 1), fdt, device)
 
     def __call__(self, xhat: torch.Tensor, stream=None) -> Factors:

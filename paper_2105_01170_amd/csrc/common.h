@@ -180,7 +180,7 @@ tsvdm_status launch_direct_batched(const DirectDesc *desc, const TransformGroup 
 size_t jacobi_workspace(int64_t m, int64_t p, int64_t nf, bool cplx);
 tsvdm_status launch_jacobi_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
                                     tsvdm_factors *F, void *ws, hipStream_t s);
-size_t mixed_workspace(int64_t m, int64_t p, int64_t nf, int ell);
+size_t mixed_workspace(int64_t m, int64_t p, int64_t nf, int ell, bool cplx = false);
 size_t f64rand_workspace(int64_t m, int64_t p, int64_t nf, int ell);
 tsvdm_status launch_f64rand_truncate(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
                                      void *ws, hipStream_t s);

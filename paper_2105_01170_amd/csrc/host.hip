@@ -306,14 +306,16 @@ static tsvdm_status check_truncate(const tsvdm_tensor *X, const tsvdm_truncate_o
     if (o->precision == TSVDM_PREC_F64) {
         if (!is_double(X->dtype)) FAIL(TSVDM_EINVAL, "PREC_F64 needs an F64 or C128 Xhat");
     } else if (o->precision == TSVDM_PREC_MIXED || o->precision == TSVDM_PREC_F64_RAND) {
-        if (o->precision == TSVDM_PREC_MIXED && X->dtype != TSVDM_F32)
-            FAIL(TSVDM_EUNSUPPORTED, "PREC_MIXED needs a real F32 Xhat");
+        if (o->precision == TSVDM_PREC_MIXED && X->dtype != TSVDM_F32 && X->dtype != TSVDM_C64)
+            FAIL(TSVDM_EUNSUPPORTED, "PREC_MIXED needs an F32 or C64 Xhat");
         if (o->precision == TSVDM_PREC_F64_RAND && X->dtype != TSVDM_F64)
             FAIL(TSVDM_EUNSUPPORTED, "PREC_F64_RAND needs a real F64 Xhat");
         if (o->oversample < 0) FAIL(TSVDM_EINVAL, "oversample must be >= 0");
         if (o->power_iters < 0 || o->power_iters > 1) FAIL(TSVDM_EUNSUPPORTED, "power_iters must be 0 or 1");
         int ell = o->k + o->oversample;
         if (ell < 1 || ell > 64) FAIL(TSVDM_EUNSUPPORTED, "sketch width k+oversample = %d not in 1..64", ell);
+        if (is_cplx(X->dtype) && ell > 48)
+            FAIL(TSVDM_EUNSUPPORTED, "sketch width k+oversample = %d not in 1..48 for complex faces", ell);
         if (ell > X->m || ell > X->p)
             FAIL(TSVDM_EINVAL, "sketch width %d exceeds min(m, p) = %lld", ell,
                  (long long)(X->m < X->p ? X->m : X->p));
@@ -328,7 +330,7 @@ size_t tsvdm_truncate_workspace_size(const tsvdm_tensor *X, const tsvdm_truncate
     if (check_truncate(X, o, false) != TSVDM_OK) return 0;
     if (o->precision == TSVDM_PREC_F64) return jacobi_workspace(X->m, X->p, X->n3, is_cplx(X->dtype));
     if (o->precision == TSVDM_PREC_F64_RAND) return f64rand_workspace(X->m, X->p, X->n3, o->k + o->oversample);
-    return mixed_workspace(X->m, X->p, X->n3, o->k + o->oversample);
+    return mixed_workspace(X->m, X->p, X->n3, o->k + o->oversample, is_cplx(X->dtype));
 }
 
 // the factors of a truncation of X with options o
@@ -346,7 +348,7 @@ static tsvdm_status check_truncate_out(const tsvdm_tensor *X, const tsvdm_trunca
     if (o->precision != TSVDM_PREC_F64 && need > o->k + o->oversample) need = o->k + o->oversample;
     if (F->kmax < need || F->kmax < 1)
         FAIL(TSVDM_EINVAL, "out->kmax (%lld) < largest possible rank (%lld)", (long long)F->kmax, (long long)need);
-    const int32_t want = o->precision == TSVDM_PREC_MIXED ? TSVDM_F32 : X->dtype;
+    const int32_t want = o->precision == TSVDM_PREC_MIXED ? (X->dtype == TSVDM_C64 ? TSVDM_C64 : TSVDM_F32) : X->dtype;
     if (F->dtype != want) FAIL(TSVDM_EINVAL, "factor dtype %d, expected %d", F->dtype, want);
     if (X->m * X->p * X->n3 > 0 && (!F->U || !F->S || !F->V || !F->ranks))
         FAIL(TSVDM_EINVAL, "factor pointers U, S, V, ranks must be set");
@@ -372,6 +374,7 @@ tsvdm_status tsvdm_truncate_noalloc(const tsvdm_tensor *X, const tsvdm_truncate_
     tsvdm_status st;
     if ((st = check_truncate(X, o)) != TSVDM_OK) return st;
     if (o->precision != TSVDM_PREC_MIXED) FAIL(TSVDM_EUNSUPPORTED, "tsvdm_truncate_noalloc: PREC_MIXED only");
+    if (X->dtype != TSVDM_F32) FAIL(TSVDM_EUNSUPPORTED, "tsvdm_truncate_noalloc: a real F32 Xhat only");
     if ((st = check_truncate_out(X, o, F)) != TSVDM_OK) return st;
     if (X->n3 == 0) return TSVDM_OK;
     return launch_mixed_truncate_noalloc(X, o, F, (hipStream_t)stream);

@@ -248,4 +248,223 @@ __device__ void jacobi_eig(double *G0, double *G1, double *E0, double *E1, doubl
 // Slot of the j-th real eigenpair (j < n) given the padding slot of jacobi_eig.
 __device__ __forceinline__ int jacobi_slot(int j, int dslot) { return dslot >= 0 && j >= dslot ? j + 1 : j; }
 
+// ---------------------------------------------------------------- Hermitian
+// Complex arithmetic on (re, im) pairs.
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+    return double2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// conj(a) * b
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {
+    return double2{a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x};
+}
+
+// Rotation of the Hermitian pair [[app, apq], [conj(apq), aqq]]: with
+// w = apq / |apq| the phase diag(1, conj(w)) turns the pair into the real
+// symmetric [[app, |apq|], [|apq|, aqq]], and the real rotation (c, s) of
+// jrot annihilates that; the unitary is U = diag(1, conj(w)) [[c, s], [-s, c]].
+// Same test as jneeds on |apq|, in squares.  Identity (c = 1, s = 0, w = 1)
+// when the pair need not rotate.  Branch free.
+__device__ __forceinline__ bool jrot_c(double app, double aqq, double2 apq, double atol, double &c, double &s,
+                                       double2 &w) {
+    const double a2 = apq.x * apq.x + apq.y * apq.y;
+    const bool go = a2 > 1e-30 * fabs(app * aqq) && a2 > atol * atol;
+    const double ih = rsqrt_nr(go ? a2 : 1.0);  // 1 / |apq|
+    const double h = a2 * ih;                   // |apq|
+    w = go ? double2{apq.x * ih, apq.y * ih} : double2{1.0, 0.0};
+    const double d = aqq - app, e = 2.0 * h;
+    const double y = rsqrt_nr(go ? fma(d, d, e * e) : 1.0);
+    const double c2 = fma(0.5 * fabs(d), y, 0.5);
+    const double z = rsqrt_nr(c2);
+    const double sa = 0.5 * e * y * z;
+    c = go ? c2 * z : 1.0;
+    s = go ? (d >= 0.0 ? sa : -sa) : 0.0;
+    return go;
+}
+
+// Pitch (complex entries) of the buffers of jacobi_eig_c.
+template <int LP>
+constexpr int jacobi_ldc() {
+    return LP + 1;
+}
+
+// Cyclic Jacobi eigensolver of the Hermitian n x n matrix in G0 (LDS, complex
+// entries, pitch jacobi_ldc<LP>(), upper triangle i <= j used, the diagonal
+// real), on the slot scheme of jacobi_eig: the same round-robin ordering,
+// the same two barriers per round and fixed addresses for every work item.
+// A pair's record is (c, s) in cs and the phase w in ph; block (P rows, Q
+// columns) becomes U_P^H B U_Q.  Because only the upper triangle is stored,
+// an entry whose destination slots (i, j) have i > j is stored conjugated at
+// (j, i); the lower entry of a diagonal block is the conjugate of its upper
+// one.  E0/E1 hold the eigenvectors transposed (E[c * LDC + r] = entry r of
+// the eigenvector in slot c), the identity on the first n slots of E0 on
+// entry; entries past ne of G0 and E0 zero.  Returns like jacobi_eig: Gout's
+// diagonal (real parts) the eigenvalues in slot order, Eout the eigenvectors,
+// dslot the padding slot for odd n.  Ends with a barrier.
+template <int LP, int NTH>
+__device__ void jacobi_eig_c(double2 *G0, double2 *G1, double2 *E0, double2 *E1, double2 *cs, double2 *ph,
+                             int *rflag, int n, double atol, int max_sweeps, int &conv, const double2 *&Gout,
+                             const double2 *&Eout, int &dslot) {
+    constexpr int LD = jacobi_ldc<LP>(), NPM = LP / 2;
+    constexpr int IPT = (NPM * (NPM + 1) / 2 + (LP / 4) * NPM + NTH - 1) / NTH;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int ne = n + (n & 1), h = ne / 2, n1 = ne - 1;
+    // destination of slot entry (i, j): its upper position, and whether the
+    // value goes there conjugated
+    auto up = [&](int i, int j, int &cj) -> int {
+        cj = i > j;
+        return i <= j ? i * LD + j : j * LD + i;
+    };
+    const int ng = h * (h + 1) / 2, nq = (ne + 3) / 4, nitems = ng + nq * h;
+    int ik[IPT], i1[IPT], i2[IPT], src[IPT], d0[IPT], d1[IPT], d2[IPT], d3[IPT], cjm[IPT];
+#pragma unroll
+    for (int u = 0; u < IPT; ++u) {
+        const int it = tid + u * NTH;
+        ik[u] = it < ng ? 0 : it < nitems ? 1 : 2;
+        i1[u] = i2[u] = src[u] = d0[u] = d1[u] = d2[u] = d3[u] = cjm[u] = 0;
+        if (ik[u] == 0) {
+            int pp = 0, rem = it;
+            while (rem >= h - pp) {
+                rem -= h - pp;
+                ++pp;
+            }
+            const int qq = pp + rem;
+            i1[u] = pp;
+            i2[u] = qq;
+            src[u] = 2 * pp * LD + 2 * qq;
+            const int a = rr_next(2 * pp, h), b = rr_next(2 * pp + 1, h);
+            const int c = rr_next(2 * qq, h), d = rr_next(2 * qq + 1, h);
+            int c0, c1, c2, c3;
+            d0[u] = up(a, c, c0);
+            d1[u] = up(a, d, c1);
+            d2[u] = up(b, c, c2);
+            d3[u] = up(b, d, c3);
+            cjm[u] = c0 | (c1 << 1) | (c2 << 2) | (c3 << 3);
+        } else if (ik[u] == 1) {
+            const int k = (it - ng) % h, r0 = 4 * ((it - ng) / h);
+            i1[u] = r0;
+            i2[u] = k;
+            src[u] = 2 * k * LD + r0;
+            d0[u] = rr_next(2 * k, h) * LD + r0;
+            d1[u] = rr_next(2 * k + 1, h) * LD + r0;
+        }
+    }
+    double2 *Gc = G0, *Gn = G1, *Ec = E0, *En = E1;
+    // eigenvector block item: E_p <- c E_p - s conj(w) E_q, E_q <- s E_p + c conj(w) E_q
+    auto e_item = [&](int u, int par) {
+        const double2 rt = cs[par * NPM + i2[u]], w = ph[par * NPM + i2[u]];
+        double2 x[4], y[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            x[v] = Ec[src[u] + v];
+            y[v] = Ec[src[u] + LD + v];
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const double2 wy = cmulc(w, y[v]);
+            En[d0[u] + v] = double2{rt.x * x[v].x - rt.y * wy.x, rt.x * x[v].y - rt.y * wy.y};
+            En[d1[u] + v] = double2{rt.y * x[v].x + rt.x * wy.x, rt.y * x[v].y + rt.x * wy.y};
+        }
+    };
+    auto put = [&](int d, int cj, double2 v) { Gn[d] = cj ? double2{v.x, -v.y} : v; };
+
+    int rr = 0;
+    conv = 0;
+    for (int sweep = 1;; ++sweep) {
+        const int fl = sweep % 3;
+        {
+            bool need = false;
+            for (int e = tid; e < ne * ne; e += NTH) {
+                const int i = e / ne, j = e - i * ne;
+                if (i < j) {
+                    const double2 g = Gc[i * LD + j];
+                    const double a2 = g.x * g.x + g.y * g.y, app = Gc[i * LD + i].x, aqq = Gc[j * LD + j].x;
+                    need |= a2 > 1e-30 * fabs(app * aqq) && a2 > atol * atol;
+                }
+            }
+            if (__any(need) && lane == 0) rflag[fl] = 1;
+            __syncthreads();
+            if (tid == 0) rflag[(sweep + 2) % 3] = 0;
+            if (rflag[fl] == 0) {
+                conv = 1;
+                break;
+            }
+        }
+        if (sweep > max_sweeps) break;
+        for (int r = 0; r < n1; ++r, ++rr) {
+            const int par = rr & 1;
+            if (tid < h) {
+                const double app = Gc[2 * tid * (LD + 1)].x, aqq = Gc[(2 * tid + 1) * (LD + 1)].x;
+                const double2 apq = Gc[2 * tid * (LD + 1) + 1];
+                double c, s;
+                double2 w;
+                jrot_c(app, aqq, apq, atol, c, s, w);
+                cs[par * NPM + tid] = double2{c, s};
+                ph[par * NPM + tid] = w;
+            }
+            if (rr > 0) {
+#pragma unroll
+                for (int u = 0; u < IPT; ++u)
+                    if (ik[u] == 1) e_item(u, par ^ 1);
+            }
+            __syncthreads();
+            if (rr > 0) {
+                double2 *t = Ec;
+                Ec = En;
+                En = t;
+            }
+#pragma unroll
+            for (int u = 0; u < IPT; ++u) {
+                if (ik[u] != 0) continue;
+                const bool dg = i1[u] == i2[u];
+                const double2 m00 = Gc[src[u]], m01 = Gc[src[u] + 1];
+                const double2 m10 = dg ? double2{m01.x, -m01.y} : Gc[src[u] + LD], m11 = Gc[src[u] + LD + 1];
+                const double2 rp = cs[par * NPM + i1[u]], rq = cs[par * NPM + i2[u]];
+                const double2 wp = ph[par * NPM + i1[u]], wq = ph[par * NPM + i2[u]];
+                const double cp = rp.x, sp = rp.y, cq = rq.x, sq = rq.y;
+                // rows: (r0, r1) <- (cp r0 - sp w_p r1, sp r0 + cp w_p r1)
+                const double2 u0 = cmul(wp, m10), u1 = cmul(wp, m11);
+                const double2 t00{cp * m00.x - sp * u0.x, cp * m00.y - sp * u0.y};
+                const double2 t01{cp * m01.x - sp * u1.x, cp * m01.y - sp * u1.y};
+                const double2 t10{sp * m00.x + cp * u0.x, sp * m00.y + cp * u0.y};
+                const double2 t11{sp * m01.x + cp * u1.x, sp * m01.y + cp * u1.y};
+                // columns: (k0, k1) <- (cq k0 - sq conj(w_q) k1, sq k0 + cq conj(w_q) k1)
+                const double2 v0 = cmulc(wq, t01), v1 = cmulc(wq, t11);
+                double2 b00{cq * t00.x - sq * v0.x, cq * t00.y - sq * v0.y};
+                const double2 b01{sq * t00.x + cq * v0.x, sq * t00.y + cq * v0.y};
+                const double2 b10{cq * t10.x - sq * v1.x, cq * t10.y - sq * v1.y};
+                double2 b11{sq * t10.x + cq * v1.x, sq * t10.y + cq * v1.y};
+                if (dg) {  // diagonal entries of a Hermitian matrix are real
+                    b00.y = 0.0;
+                    b11.y = 0.0;
+                }
+                const int cj = cjm[u];
+                put(d0[u], cj & 1, b00);
+                put(d1[u], (cj >> 1) & 1, b01);
+                if (!dg) put(d2[u], (cj >> 2) & 1, b10);
+                put(d3[u], (cj >> 3) & 1, b11);
+            }
+            __syncthreads();
+            double2 *t = Gc;
+            Gc = Gn;
+            Gn = t;
+        }
+    }
+    if (rr > 0) {
+#pragma unroll
+        for (int u = 0; u < IPT; ++u)
+            if (ik[u] == 1) e_item(u, (rr - 1) & 1);
+        __syncthreads();
+        Ec = En;
+    }
+    __syncthreads();
+    Gout = Gc;
+    Eout = Ec;
+    dslot = -1;
+    if (n & 1) {
+        int sl = ne - 1;
+        for (int k = 0, nr = n1 > 0 ? rr % n1 : 0; k < nr; ++k) sl = rr_next(sl, h);
+        dslot = sl;
+    }
+}
+
 }  // namespace tsvdm

@@ -1379,7 +1379,11 @@ __global__ __launch_bounds__(GT) void k_factors(const T *__restrict__ Q, const T
 // (independent accumulators); the FP64 output layout (row lane/16 + 4v,
 // column lane%16) picks the X values from LDS.
 // T: element type of X and the factors (FP32 mixed, FP64 randomized).
-template <int KP, bool VEC, typename T = float>
+// CPLX: complex faces and factors, X read as the real 2m x p matrix X' of its
+// interleaved storage (m is then 2m): (Uhat S Vhat^H)' = [Uhat' | (-i Uhat)']
+// times [S Re Vhat | S Im Vhat]^T, the two column sets interleaved (column 2r
+// and 2r+1 for triplet r), so the kernel runs unchanged on 2 ranks[f] columns.
+template <int KP, bool VEC, typename T = float, bool CPLX = false>
 __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_resid(const T *__restrict__ X, int m, int p, int nf,
                                               const T *__restrict__ U, const double *__restrict__ S,
                                               const T *__restrict__ V, int64_t kmax,
@@ -1398,10 +1402,11 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if (fd < 0) return;  // an unused slot of a face list sized on the device
     const int a0 = blk * 64;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int kf = ranks[fd] < KP ? ranks[fd] : KP, ns = (kf + 3) / 4;
+    const int rk = CPLX ? 2 * ranks[fd] : ranks[fd];
+    const int kf = rk < KP ? rk : KP, ns = (kf + 3) / 4;
     const T *Xf = X + (int64_t)fd * m * p;
     const T *Uf = U + (int64_t)fd * m * kmax;
-    const T *Vf = V + (int64_t)fd * p * kmax;
+    const T *Vf = V + (int64_t)fd * (CPLX ? 2 * p : p) * kmax;
     const double *Sf = S + (int64_t)fd * kmax;
     double ua[NS];  // A operands: Uhat[a0 + 16 wave + lane%16][4 s + lane/16]
     {
@@ -1409,11 +1414,21 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 #pragma unroll
         for (int st = 0; st < NS; ++st) {
             const int r = 4 * st + (lane >> 4);
-            ua[st] = row < m && r < kf ? (double)Uf[row + (int64_t)m * r] : 0.0;
+            if constexpr (CPLX) {  // row 2i + a of X'; column 2r' + b
+                const int rc = r >> 1, a = row & 1;
+                double v = 0.0;
+                if (row < m && r < kf) {
+                    if ((r & 1) == 0) v = (double)Uf[row + (int64_t)m * rc];
+                    else v = a == 0 ? (double)Uf[row + 1 + (int64_t)m * rc] : -(double)Uf[row - 1 + (int64_t)m * rc];
+                }
+                ua[st] = v;
+            } else {
+                ua[st] = row < m && r < kf ? (double)Uf[row + (int64_t)m * r] : 0.0;
+            }
         }
     }
     const int xq = tid & 15, xc = tid >> 4, vc = tid & 63, vr0 = tid >> 6;
-    if (tid < KP) ss[tid] = tid < kf ? Sf[tid] : 0.0;
+    if (tid < KP) ss[tid] = tid < kf ? Sf[CPLX ? tid >> 1 : tid] : 0.0;
     // chunk loads: X rows a0 + 4 (tid%16) .. +3 of columns b0 + tid/16 + 16 it;
     // V row b0 + tid%64 of ranks tid/64 + 4 q
     T xr[16], vr[VPT];
@@ -1449,7 +1464,8 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         for (int q = 0; q < VPT; ++q) {
             const int r = vr0 + 4 * q, b = b0 + vc;
             const bool ok = r < kf && b < p;
-            const T v = Vf[ok ? b + (int64_t)p * r : 0];
+            const int64_t vo = CPLX ? 2 * (int64_t)b + (r & 1) + 2 * (int64_t)p * (r >> 1) : b + (int64_t)p * r;
+            const T v = Vf[ok ? vo : 0];
             vr[q] = ok ? v : (T)0;
         }
     };
@@ -1502,6 +1518,491 @@ __global__ void k_cert(const double *__restrict__ res_part, int nparts, int nf, 
     cert[fmap ? fmap[f] : f] = sqrt(r);
 }
 
+// ---------------------------------------------------------------- complex faces
+// The mixed path on complex faces (the stored half spectrum of the DFT of a
+// real tensor) runs its passes over X with the real GEMM kernels above.  A
+// complex m x p face stored interleaved is the real 2m x p matrix X' whose
+// rows 2i and 2i+1 hold the real and imaginary parts of row i; for a complex
+// panel Q write Q' for the same view and (iQ)' for that of i Q.  Then
+//   X' Omega                 = (X Omega)'                  (Omega real)
+//   X'^T [Q' | (iQ)']        = [Re X^H Q | -Im X^H Q]
+//   X' [Re Z | Im Z]         = P,  X Z = (P[2i, :l] - P[2i+1, l:]) + i (P[2i+1, :l] + P[2i, l:])
+//   X'^T [Q' | (iQ)'] with the Gram partials and the residual of the
+//   projection gives B^H = X^H Q in that layout, the Gram of its 2l real
+//   columns and ||X' - [Q' | (iQ)'] [Re B^H | -Im B^H]^T||^2 = ||X - Q B||^2,
+// so every pass reads X once, at twice the real width.  The per-face kernels
+// below take and give panels in these layouts:
+//   CIN_IL   S = (X Omega)' (2 rows x LP)
+//   CIN_COMB S = P (2 rows x 2LP), combined as above
+//   CIN_PC   S = [Re Z | -Im Z] (rows x 2LP)
+//   COUT_RL  Q as [Q' | (iQ)'] (2 rows x 2LP), the operand of X'^T
+//   COUT_PL  Q as [Re Q | Im Q] (rows x 2LP), the operand of X'
+// Columns from ell to LP of each half are zero.
+enum { CIN_IL = 0, CIN_COMB = 1, CIN_PC = 2 };
+enum { COUT_RL = 0, COUT_PL = 1 };
+constexpr int CQT = 256;
+
+// Complex Cholesky-QR: G = Y^H Y (+ shift on the first pass) = R^H R, R upper
+// triangular with a real positive diagonal, Q = Y R^{-1}; `passes` = 2 repeats
+// the step on Q.  One workgroup per face, one row per thread in chunks of CQT
+// rows.  The Gram is formed here from the rows (staged in LDS as FP32
+// [Re | Im], FP64 MFMA over the 2LP x 2LP real Gram W^T W of W = [Re Y | Im Y]:
+// Y^H Y = W11 + W22 + i (W12 - W12^T)).  Shift, dropping rule and flag as in
+// k_cholqr; the triangular solve is in FP64 in registers, the result stored
+// as FP32 and its rounded rows are what the next pass's Gram sees.
+template <int LP, int IN, int OUT>
+__global__ __launch_bounds__(CQT) void k_cholqr_c(const float *__restrict__ Sin, int rows, int ell,
+                                                  float *__restrict__ Qout, int passes,
+                                                  int32_t *__restrict__ qr_info, int first) {
+    constexpr int L2 = 2 * LP, LDG = LP + 1, LDR = LP + 1, LDS_ = L2 + 1, HR = 128;
+    constexpr int NT = L2 / 16, NH = LP / 16, NTILE = NT * (NT + 1) / 2, TPW = (NTILE + 3) / 4;
+    __shared__ __align__(16) double2 G[LP * LDG];
+    __shared__ __align__(16) double2 Rt[LP * LDR];  // Rt[c * LDR + j] = R[j][c]
+    __shared__ double rinv[LP];
+    __shared__ float st[HR * LDS_];
+    __shared__ double trace_s;
+    __shared__ int bad;
+    const int f = blockIdx.x, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t R2 = 2 * (int64_t)rows;
+    const float *S = Sin + (int64_t)f * (IN == CIN_IL ? R2 * LP : IN == CIN_COMB ? R2 * L2 : (int64_t)rows * L2);
+    float *Q = Qout + (int64_t)f * (OUT == COUT_RL ? R2 * L2 : (int64_t)rows * L2);
+    if (tid == 0) bad = 0;
+    const int nch = (rows + CQT - 1) / CQT;
+    float xr[LP], xi[LP];
+    // row `row` of the input panel, or (own) of this kernel's output
+    auto load_row = [&](int row, bool own) {
+        const int rw = row < rows ? row : rows - 1;
+#pragma unroll
+        for (int c = 0; c < LP; ++c) {
+            float a, b;
+            if (own) {
+                if constexpr (OUT == COUT_RL) {
+                    const float2 v = *reinterpret_cast<const float2 *>(Q + 2 * (int64_t)rw + R2 * c);
+                    a = v.x;
+                    b = v.y;
+                } else {
+                    a = Q[rw + (int64_t)rows * c];
+                    b = Q[rw + (int64_t)rows * (LP + c)];
+                }
+            } else if constexpr (IN == CIN_IL) {
+                const float2 v = *reinterpret_cast<const float2 *>(S + 2 * (int64_t)rw + R2 * c);
+                a = v.x;
+                b = v.y;
+            } else if constexpr (IN == CIN_COMB) {
+                const float2 u = *reinterpret_cast<const float2 *>(S + 2 * (int64_t)rw + R2 * c);
+                const float2 v = *reinterpret_cast<const float2 *>(S + 2 * (int64_t)rw + R2 * (LP + c));
+                a = u.x - v.y;
+                b = u.y + v.x;
+            } else {
+                a = S[rw + (int64_t)rows * c];
+                b = -S[rw + (int64_t)rows * (LP + c)];
+            }
+            const bool ok = row < rows && c < ell;
+            xr[c] = ok ? a : 0.0f;
+            xi[c] = ok ? b : 0.0f;
+        }
+    };
+    // the rows of every thread through LDS into the 2LP x 2LP Gram tiles
+    auto accumulate = [&](f64x4(&g)[TPW]) {
+#pragma unroll
+        for (int hh = 0; hh < CQT / HR; ++hh) {
+            if (tid / HR == hh) {
+                const int r = tid % HR;
+#pragma unroll
+                for (int c = 0; c < LP; ++c) {
+                    st[r * LDS_ + c] = xr[c];
+                    st[r * LDS_ + LP + c] = xi[c];
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const int idx = wave + 4 * t;
+                if (idx >= NTILE) continue;
+                int ti, tj;
+                tile_ij<NT>(idx, ti, tj);
+#pragma unroll 4
+                for (int kk = 0; kk < HR / 4; ++kk) {
+                    const int r = 4 * kk + (lane >> 4);
+                    g[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)st[r * LDS_ + 16 * ti + (lane & 15)],
+                                                                (double)st[r * LDS_ + 16 * tj + (lane & 15)], g[t],
+                                                                0, 0, 0);
+                }
+            }
+            __syncthreads();
+        }
+    };
+    // Gram tiles -> complex G: Re from W11 and W22, Im from W12 (set, then
+    // its transpose subtracted); FP64 MFMA output row lane/16 + 4v
+    auto to_complex = [&](const f64x4(&g)[TPW]) {
+#pragma unroll
+        for (int ph = 0; ph < 2; ++ph) {
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const int idx = wave + 4 * t;
+                if (idx >= NTILE) continue;
+                int ti, tj;
+                tile_ij<NT>(idx, ti, tj);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 16 * ti + (lane >> 4) + 4 * v, j = 16 * tj + (lane & 15);
+                    const double x = g[t][v];
+                    if (tj < NH) {  // W11
+                        if (ph == 0 && (ti < tj || i <= j)) {
+                            G[i * LDG + j].x = x;
+                            G[j * LDG + i].x = x;
+                        }
+                    } else if (ti >= NH) {  // W22
+                        const int a = i - LP, b = j - LP;
+                        if (ph == 1 && (ti < tj || a <= b)) {
+                            G[a * LDG + b].x += x;
+                            if (a != b) G[b * LDG + a].x += x;
+                        }
+                    } else {  // W12
+                        if (ph == 0) G[i * LDG + (j - LP)].y = x;
+                        else G[(j - LP) * LDG + i].y -= x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    };
+
+    // ---- first Gram, from the input panel
+    {
+        f64x4 g[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) g[t] = f64x4{0, 0, 0, 0};
+        for (int ch = 0; ch < nch; ++ch) {
+            load_row(ch * CQT + tid, false);
+            accumulate(g);
+        }
+        to_complex(g);
+    }
+    for (int pass = 0; pass < passes; ++pass) {
+        if (wave == 0) {
+            double t = 0.0;
+            for (int c = lane; c < ell; c += 64) t += G[c * LDG + c].x;
+            t = wave_sum(t);
+            if (lane == 0) trace_s = t;
+        }
+        __syncthreads();
+        const double level = 11.0 * ((double)rows * ell + (double)ell * (ell + 1)) * 0x1p-53 * trace_s;
+        const double pfloor = pass == 0 ? 0.0 : level;
+        if (pass == 0) {
+            if (tid < ell) G[tid * LDG + tid].x += level;
+            __syncthreads();
+        }
+        // ---- right-looking Cholesky, upper entries numbered by decreasing row
+        // (see k_cholqr): G[i][c] -= conj(G[j][i]) G[j][c] / G[j][j]
+        {
+            constexpr int NU = LP * (LP + 1) / 2, UPT = (NU + CQT - 1) / CQT;
+            int ei[UPT], ec[UPT];
+#pragma unroll
+            for (int u = 0; u < UPT; ++u) {
+                int rem = tid + u * CQT, i = ell - 1;
+                while (i >= 0 && rem >= ell - i) {
+                    rem -= ell - i;
+                    --i;
+                }
+                ei[u] = i;
+                ec[u] = i >= 0 ? i + rem : 0;
+            }
+            for (int j = 0; j < ell; ++j) {
+                const int cnt = (ell - j - 1) * (ell - j) / 2;
+                const double piv = G[j * LDG + j].x;
+                const double ipv = piv > pfloor && isfinite(piv) ? recip(piv) : 0.0;
+#pragma unroll
+                for (int u = 0; u < UPT; ++u) {
+                    if (u * CQT + (tid & ~63) >= cnt) break;
+                    const bool act = tid + u * CQT < cnt;
+                    const int i = act ? ei[u] : j, c = act ? ec[u] : j;
+                    const double2 gji = G[j * LDG + i], gjc = G[j * LDG + c], gic = G[i * LDG + c];
+                    const double2 l = cmulc(gji, gjc);
+                    if (act) G[i * LDG + c] = double2{gic.x - l.x * ipv, gic.y - l.y * ipv};
+                }
+                __syncthreads();
+            }
+            for (int e = tid; e < ell * ell; e += CQT) {
+                const int j = e / ell, c = e % ell;
+                if (c < j) continue;
+                const double piv = G[j * LDG + j].x;
+                const bool fin = isfinite(piv), ok = fin && piv > pfloor, drop = fin && !ok && pass > 0;
+                const double d = ok ? sqrt(piv) : 1.0, id = 1.0 / d;
+                const double2 gjc = G[j * LDG + c];
+                Rt[c * LDR + j] = c == j ? double2{d, 0.0} : ok ? double2{gjc.x * id, gjc.y * id} : double2{0.0, 0.0};
+                if (c == j) {
+                    rinv[j] = drop ? 0.0 : id;
+                    if (!ok && !drop) bad = 1;
+                }
+            }
+            __syncthreads();
+        }
+        // ---- Q = Y R^{-1} row by row: q[c] = (y[c] - sum_{j<c} q[j] R[j][c]) / R[c][c]
+        const bool again = pass + 1 < passes;
+        f64x4 g[TPW];
+#pragma unroll
+        for (int t = 0; t < TPW; ++t) g[t] = f64x4{0, 0, 0, 0};
+        for (int ch = 0; ch < nch; ++ch) {
+            const int row = ch * CQT + tid;
+            load_row(row, pass > 0);
+            double2 q[LP];
+#pragma unroll
+            for (int c = 0; c < LP; ++c) {
+                if (c < ell) {
+                    double2 v0{(double)xr[c], (double)xi[c]}, v1{0.0, 0.0};
+                    const double2 *rc = Rt + c * LDR;
+#pragma unroll
+                    for (int j = 0; j + 1 < c; j += 2) {
+                        const double2 r0 = rc[j], r1 = rc[j + 1];
+                        const double2 p0 = cmul(q[j], r0), p1 = cmul(q[j + 1], r1);
+                        v0.x -= p0.x;
+                        v0.y -= p0.y;
+                        v1.x -= p1.x;
+                        v1.y -= p1.y;
+                    }
+                    if (c & 1) {
+                        const double2 p0 = cmul(q[c - 1], rc[c - 1]);
+                        v0.x -= p0.x;
+                        v0.y -= p0.y;
+                    }
+                    const double ri = rinv[c];
+                    q[c] = double2{(v0.x + v1.x) * ri, (v0.y + v1.y) * ri};
+                } else {
+                    q[c] = double2{0.0, 0.0};
+                }
+                xr[c] = (float)q[c].x;
+                xi[c] = (float)q[c].y;
+            }
+            if (row < rows) {
+#pragma unroll
+                for (int c = 0; c < LP; ++c) {
+                    if constexpr (OUT == COUT_RL) {
+                        *reinterpret_cast<float2 *>(Q + 2 * (int64_t)row + R2 * c) = float2{xr[c], xi[c]};
+                        *reinterpret_cast<float2 *>(Q + 2 * (int64_t)row + R2 * (LP + c)) = float2{-xi[c], xr[c]};
+                    } else {
+                        Q[row + (int64_t)rows * c] = xr[c];
+                        Q[row + (int64_t)rows * (LP + c)] = xi[c];
+                    }
+                }
+            }
+            if (again) accumulate(g);
+        }
+        if (again) to_complex(g);
+    }
+    if (tid == 0) {
+        if (first) qr_info[f] = bad ? 2 : 0;
+        else if (bad) qr_info[f] = 2;
+    }
+}
+
+// Complex core: H = B B^H = (B^H)^H B^H, formed from the Gram partials of the
+// projection's [Re B^H | -Im B^H] (width 2LP, staged in the eigenvector
+// buffers): H = W11 + W22 + i (W21 - W12); its eigenpairs by the Hermitian
+// Jacobi solver; sorting, rank rule, certificate and outputs as k_core (U_B
+// complex, column j at UB[f][j], LP entries).
+template <int LP>
+__global__ __launch_bounds__(QT) void k_core_c(const double *__restrict__ gpart, int nparts, int ell,
+                                               const double *__restrict__ fro_part, int nfro,
+                                               const double *__restrict__ res_part, int nres, int mode, int kfix,
+                                               double tau, int max_sweeps, double jtol, double2 *__restrict__ UB,
+                                               double *__restrict__ sig, int *__restrict__ perm_out,
+                                               int *__restrict__ kf_out, double *__restrict__ fro2_out,
+                                               double *__restrict__ cert, int32_t *__restrict__ jinfo) {
+    constexpr int L2 = 2 * LP, LD = jacobi_ldc<LP>(), NPM = LP / 2, LDW = L2 + 1;
+    __shared__ __align__(16) double2 Gb[2][LP * LD];
+    __shared__ __align__(16) double2 Eb[2][LP * LD];
+    __shared__ double2 cs[2][NPM], ph[2][NPM];
+    __shared__ double lam[LP];
+    __shared__ int perm[LP];
+    __shared__ double trace_s;
+    __shared__ int rflag[3];
+    static_assert(L2 * LDW * sizeof(double) <= sizeof(Eb), "the real Gram fits in the eigenvector buffers");
+    const int f = blockIdx.x, tid = threadIdx.x;
+    double *W = reinterpret_cast<double *>(&Eb[0][0]);
+    load_gram_partials<L2, QT>(gpart, f, nparts, W, LDW);
+    __syncthreads();
+    for (int e = tid; e < LP * LD; e += QT) {
+        const int a = e / LD, b = e % LD;
+        double2 v{0.0, 0.0};
+        if (b < LP) {
+            v.x = W[a * LDW + b] + W[(LP + a) * LDW + LP + b];
+            v.y = a == b ? 0.0 : W[(LP + a) * LDW + b] - W[a * LDW + LP + b];
+        }
+        Gb[0][e] = v;
+    }
+    __syncthreads();
+    for (int e = tid; e < LP * LD; e += QT) Eb[0][e] = Eb[1][e] = double2{0.0, 0.0};
+    __syncthreads();
+    if (tid < ell) Eb[0][tid * LD + tid] = double2{1.0, 0.0};
+    if (tid < 3) rflag[tid] = 0;
+    if (tid < 64) {
+        double t = 0.0;
+        for (int c = tid; c < ell; c += 64) t += Gb[0][c * LD + c].x;
+        t = wave_sum(t);
+        if (tid == 0) trace_s = t;
+    }
+    __syncthreads();
+    const double trace = trace_s;
+    int conv = 0, dslot;
+    const double2 *G, *E;
+    jacobi_eig_c<LP, QT>(Gb[0], Gb[1], Eb[0], Eb[1], &cs[0][0], &ph[0][0], rflag, ell, jtol * trace, max_sweeps,
+                         conv, G, E, dslot);
+    if (tid < ell) {
+        const int sl = jacobi_slot(tid, dslot);
+        lam[tid] = fmax(G[sl * LD + sl].x, 0.0);
+    }
+    __syncthreads();
+    if (tid < ell) {
+        int pos = 0;
+        double li = lam[tid];
+        for (int j = 0; j < ell; ++j) pos += (lam[j] > li) || (lam[j] == li && j < tid);
+        perm[pos] = tid;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double fro2 = 0.0, res = 0.0;
+        for (int i = 0; i < nfro; ++i) fro2 += fro_part[(int64_t)f * nfro + i];
+        for (int i = 0; i < nres; ++i) res += res_part[(int64_t)f * nres + i];
+        int kf, miss = 0;
+        if (mode == TSVDM_RANK_FIXED) {
+            kf = kfix < ell ? kfix : ell;
+        } else {
+            const int cap = kfix > 0 && kfix < ell ? kfix : ell;
+            double tail = res, bound = tau * tau * fro2;
+            for (int j = 0; j < ell; ++j) tail += lam[j];
+            kf = -1;
+            for (int k = 0; k <= cap; ++k) {
+                if (tail <= bound) {
+                    kf = k;
+                    break;
+                }
+                if (k < ell) tail -= lam[perm[k]];
+            }
+            if (kf < 0) {
+                kf = cap;
+                miss = 1;
+            }
+        }
+        double disc = 0.0;
+        for (int j = ell - 1; j >= kf; --j) disc += lam[perm[j]];
+        kf_out[f] = kf;
+        fro2_out[f] = fro2;
+        if (cert) cert[f] = nres != 0 ? sqrt(res + disc) : -1.0;
+        jinfo[f] = ((conv || ell <= 1) ? 0 : 1) | (miss ? 4 : 0);
+    }
+    for (int r = tid; r < LP; r += QT) {
+        int j = r < ell ? perm[r] : r;
+        sig[(int64_t)f * LP + r] = r < ell ? sqrt(lam[j]) : 0.0;
+        perm_out[(int64_t)f * LP + r] = j;
+    }
+    for (int e = tid; e < LP * LP; e += QT)
+        UB[(int64_t)f * LP * LP + e] =
+            e / LP < ell ? E[jacobi_slot(e / LP, dslot) * LD + e % LP] : double2{0.0, 0.0};
+}
+
+// Complex factors: Uhat = Q U_B[:, perm], Vhat = B^H U_B[:, perm] / s, from
+// the layouts above by FP32 MFMA 16x16x4 (the structure of k_factors):
+//   Uhat' = [Q' | (iQ)'] [Re U_B; Im U_B]                    (rows 2m)
+//   Re Vhat = [Re B^H | -Im B^H] [Re U_B; Im U_B] / s,
+//   Im Vhat = [Re B^H | -Im B^H] [Im U_B; -Re U_B] / s       (rows p)
+// Output columns r of Uhat; for Vhat, output column 2r + b is part b of
+// complex column r, stored interleaved.  Uo, Vo: C64 factors, face stride
+// m kmax and p kmax complex values.  Grid (ceil(2m/64) + ceil(p/64), nf).
+template <int LP>
+__global__ __launch_bounds__(GT) void k_factors_c(const float *__restrict__ Qr, const float *__restrict__ Btr, int m,
+                                                  int p, int ell, int64_t kmax, const double2 *__restrict__ UB,
+                                                  const double *__restrict__ sig, const int *__restrict__ perm,
+                                                  const int *__restrict__ kf_in, const double *__restrict__ fro2,
+                                                  const int32_t *__restrict__ qr_info,
+                                                  const int32_t *__restrict__ jinfo, float *__restrict__ Uo,
+                                                  double *__restrict__ So, float *__restrict__ Vo,
+                                                  int32_t *__restrict__ ranks, double *__restrict__ fro,
+                                                  int32_t *__restrict__ info) {
+    constexpr int L2 = 2 * LP, LU = L2 + 1, NT = L2 / 16;
+    __shared__ float ubs[L2 * LU];
+    const int f = blockIdx.y, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int kf = kf_in[f], m2 = 2 * m, nbu = (m2 + 63) / 64;
+    const bool isv = (int)blockIdx.x >= nbu;
+    const int blk = isv ? blockIdx.x - nbu : blockIdx.x, rows = isv ? p : m2;
+    const float *S = isv ? Btr + (int64_t)f * p * L2 : Qr + (int64_t)f * m2 * L2;
+    const int kc = kf < kmax ? kf : (int)kmax;
+    for (int e = tid; e < L2 * L2; e += GT) {
+        const int r = e / L2, c = e % L2, cc = c < LP ? c : c - LP, rk = isv ? r >> 1 : r;
+        float u = 0.0f;
+        if (rk < kc && cc < ell) {
+            const double2 v = UB[(int64_t)f * LP * LP + cc + (int64_t)LP * perm[(int64_t)f * LP + rk]];
+            if (!isv) {
+                u = (float)(c < LP ? v.x : v.y);
+            } else {
+                const double sv = sig[(int64_t)f * LP + rk], is = sv > 0.0 ? 1.0 / sv : 0.0;
+                const double val = (r & 1) == 0 ? (c < LP ? v.x : v.y) : (c < LP ? v.y : -v.x);
+                u = (float)(val * is);
+            }
+        }
+        ubs[r * LU + c] = u;
+    }
+    __syncthreads();
+    const int ncol = isv ? 2 * kc : kc, nt = (ncol + 15) / 16;
+    const int row0 = blk * 64 + 16 * wave, jr = row0 + (lane & 15), kl = lane >> 4;
+    const bool rok = jr < rows;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = f32x4{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < L2 / 4; ++kk) {
+        if ((4 * kk) % LP >= ell) continue;  // zero columns of both halves
+        const float x = S[rok ? jr + (int64_t)rows * (4 * kk + kl) : 0];
+        const float bq = rok ? x : 0.0f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            if (t >= nt) break;
+            const float a = ubs[(16 * t + (lane & 15)) * LU + 4 * kk + kl];
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bq, acc[t], 0, 0, 0);
+        }
+    }
+    float *Uf = Uo + (int64_t)f * m2 * kmax;
+    float *Vf = Vo + (int64_t)f * 2 * p * kmax;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        if (t >= nt) break;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int e = 16 * t + 4 * kl + v;
+            if (!rok) continue;
+            if (!isv) {
+                if (e < kmax) Uf[jr + (int64_t)m2 * e] = acc[t][v];
+            } else if ((e >> 1) < kmax) {
+                Vf[2 * (int64_t)jr + (e & 1) + 2 * (int64_t)p * (e >> 1)] = acc[t][v];
+            }
+        }
+    }
+    // zero the columns past the computed tiles
+    const int done = isv ? 8 * nt : 16 * nt;
+    const int64_t zc = kmax - done;
+    for (int64_t e = tid; e < 64 * zc; e += GT) {
+        const int row = blk * 64 + (int)(e % 64);
+        const int64_t col = done + e / 64;
+        if (row >= rows) continue;
+        if (!isv) Uf[row + (int64_t)m2 * col] = 0.0f;
+        else *reinterpret_cast<float2 *>(Vf + 2 * (int64_t)row + 2 * (int64_t)p * col) = float2{0.0f, 0.0f};
+    }
+    if (blockIdx.x == 0) {
+        for (int r = tid; r < kmax; r += GT) So[(int64_t)f * kmax + r] = r < kf ? sig[(int64_t)f * LP + r] : 0.0;
+        if (tid == 0) {
+            ranks[f] = kf;
+            if (fro) fro[f] = sqrt(fro2[f]);
+            if (info) {
+                int code = (jinfo[f] & 4) ? 4 : 0;
+                if (jinfo[f] & 1) code = 1;
+                if (qr_info[f]) code = 2;
+                if (!isfinite(fro2[f])) code = 3;
+                info[f] = code;
+            }
+        }
+    }
+}
+
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct MixedWs {
@@ -1511,8 +2012,10 @@ struct MixedWs {
     int32_t *qr_info, *jinfo;
 };
 
-// esz: bytes per element of the panels Y, Q, Z, Qz (4 mixed, 8 FP64 randomized)
-size_t carve(char *base, int64_t m, int64_t p, int64_t nf, int LP, MixedWs *w, int esz = 4) {
+// esz: bytes per element of the panels Y, Q, Z, Qz (4 mixed, 8 FP64 randomized);
+// gram_m: whether the passes over rows of X keep Gram partials (the complex
+// path forms those Grams in its Cholesky-QR instead)
+size_t carve(char *base, int64_t m, int64_t p, int64_t nf, int LP, MixedWs *w, int esz = 4, bool gram_m = true) {
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
         char *ptr = base ? base + off : nullptr;
@@ -1525,7 +2028,7 @@ size_t carve(char *base, int64_t m, int64_t p, int64_t nf, int LP, MixedWs *w, i
     t.Qm = (float *)take((size_t)esz * nf * m * LP);
     t.Z = (float *)take((size_t)esz * nf * p * LP);
     t.Qp = (float *)take((size_t)esz * nf * p * LP);
-    t.gram_m = (double *)take(sizeof(double) * nf * mparts * LP * LP);
+    t.gram_m = (double *)take(gram_m ? sizeof(double) * nf * mparts * LP * LP : 0);
     t.gram_p = (double *)take(sizeof(double) * nf * pparts * LP * LP);
     t.fro_part = (double *)take(sizeof(double) * nf * mparts);
     t.res_part = (double *)take(sizeof(double) * nf * pparts);
@@ -1846,6 +2349,112 @@ tsvdm_status run_mixed(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     return run_group<LP>(X, o, F, w, 0, (int)X->n3, s);
 }
 
+// ---------------------------------------------------------------- complex faces
+// PREC_MIXED on complex faces (C64 Xhat, C64 factors): the steps of run_group
+// with the layouts of the complex kernels above.  LP: the padded complex
+// width; the passes run at 2LP real columns over the 2m x p real view of each
+// face.
+template <int LP>
+tsvdm_status run_cplx(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F, void *wsp,
+                      hipStream_t s) {
+    constexpr int L2 = 2 * LP;
+    const int m = (int)X->m, p = (int)X->p, nf = (int)X->n3, ell = o->k + o->oversample, m2 = 2 * m;
+    const int mparts = (m2 + 63) / 64, pparts = (p + 63) / 64;
+    const int64_t kmax = F->kmax;
+    MixedWs w;
+    carve(reinterpret_cast<char *>(wsp), m2, p, nf, L2, &w, 4, false);
+    const float *Xd = reinterpret_cast<const float *>(X->data);
+    float *Uo = reinterpret_cast<float *>(F->U), *Vo = reinterpret_cast<float *>(F->V);
+    const dim3 gm((unsigned)(mparts * nf)), gp((unsigned)(pparts * nf));
+    const bool power = o->power_iters > 0;
+    const bool resid = o->rank_mode == TSVDM_RANK_ENERGY;
+    const bool exact = o->certify && F->cert;
+    const bool v4 = vec_loads_ok(Xd, m2, p);
+    // pass 1: (X Omega)' (BF16) and ||X||^2
+    if (v4 && reinterpret_cast<uintptr_t>(o->omega) % 16 == 0)
+        TSVDM_LAUNCH("c_sketch_xw_bf16", (k_xw<LP, PROD_BF16, false, true>), gm, dim3(GT), 0, s, Xd, m2, p, nf,
+                     o->omega, (int64_t)0, p, ell, w.Y, w.fro_part, (double *)nullptr, (const int32_t *)nullptr);
+    else
+        TSVDM_LAUNCH("c_sketch_xw_bf16", (k_xw<LP, PROD_BF16, false, false>), gm, dim3(GT), 0, s, Xd, m2, p, nf,
+                     o->omega, (int64_t)0, p, ell, w.Y, w.fro_part, (double *)nullptr, (const int32_t *)nullptr);
+    if (power) {
+        TSVDM_LAUNCH("c_cholqr_sketch", (k_cholqr_c<LP, CIN_IL, COUT_RL>), dim3(nf), dim3(CQT), 0, s,
+                     (const float *)w.Y, m, ell, w.Qm, 1, w.qr_info, 1);
+        // pass 2: [Re Z | -Im Z] = X'^T [Q' | (iQ)'] (BF16), Z = X^H Q
+        if (v4)
+            TSVDM_LAUNCH("c_power_xtw_bf16", (k_xtw<L2, PROD_BF16, false, false, true>), gp, dim3(GT), 0, s, Xd,
+                         m2, p, nf, (const float *)w.Qm, (int64_t)m2 * L2, m2, L2, w.Z, (double *)nullptr,
+                         (double *)nullptr, (const int32_t *)nullptr);
+        else
+            TSVDM_LAUNCH("c_power_xtw_bf16", (k_xtw<L2, PROD_BF16, false, false, false>), gp, dim3(GT), 0, s, Xd,
+                         m2, p, nf, (const float *)w.Qm, (int64_t)m2 * L2, m2, L2, w.Z, (double *)nullptr,
+                         (double *)nullptr, (const int32_t *)nullptr);
+        TSVDM_LAUNCH("c_cholqr_power_z", (k_cholqr_c<LP, CIN_PC, COUT_PL>), dim3(nf), dim3(CQT), 0, s,
+                     (const float *)w.Z, p, ell, w.Qp, 1, w.qr_info, 0);
+        // pass 3: P = X' [Re Qz | Im Qz] (split BF16); X Qz is combined from P
+        if (v4)
+            TSVDM_LAUNCH("c_power_xw_split", (k_xw<L2, PROD_SPLIT, false, true>), gm, dim3(GT), 0, s, Xd, m2, p,
+                         nf, (const float *)w.Qp, (int64_t)p * L2, p, L2, w.Y, (double *)nullptr, (double *)nullptr,
+                         (const int32_t *)nullptr);
+        else
+            TSVDM_LAUNCH("c_power_xw_split", (k_xw<L2, PROD_SPLIT, false, false>), gm, dim3(GT), 0, s, Xd, m2, p,
+                         nf, (const float *)w.Qp, (int64_t)p * L2, p, L2, w.Y, (double *)nullptr, (double *)nullptr,
+                         (const int32_t *)nullptr);
+        TSVDM_LAUNCH("c_cholqr_final", (k_cholqr_c<LP, CIN_COMB, COUT_RL>), dim3(nf), dim3(CQT), 0, s,
+                     (const float *)w.Y, m, ell, w.Qm, 2, w.qr_info, 0);
+    } else {
+        TSVDM_LAUNCH("c_cholqr_final", (k_cholqr_c<LP, CIN_IL, COUT_RL>), dim3(nf), dim3(CQT), 0, s,
+                     (const float *)w.Y, m, ell, w.Qm, 2, w.qr_info, 1);
+    }
+    // pass 4: [Re B^H | -Im B^H] = X'^T [Q' | (iQ)'] (split BF16), its Gram
+    // partials and, for the energy rule, ||X - Q B||^2 per 64-column block
+#define TSVDM_CPROJECT(NAME, RES, V, RP)                                                                   \
+    TSVDM_LAUNCH(NAME, (k_xtw<L2, PROD_SPLIT, true, RES, V>), gp, dim3(GT), 0, s, Xd, m2, p, nf,            \
+                 (const float *)w.Qm, (int64_t)m2 * L2, m2, L2, w.Z, w.gram_p, RP, (const int32_t *)nullptr)
+    if (resid) {
+        if (v4) TSVDM_CPROJECT("c_project_resid_split", true, true, w.res_part);
+        else TSVDM_CPROJECT("c_project_resid_split", true, false, w.res_part);
+    } else {
+        if (v4) TSVDM_CPROJECT("c_project_xtw_split", false, true, (double *)nullptr);
+        else TSVDM_CPROJECT("c_project_xtw_split", false, false, (double *)nullptr);
+    }
+#undef TSVDM_CPROJECT
+    const int msw = o->max_sweeps > 0 ? o->max_sweeps : 30;
+    double2 *UB = reinterpret_cast<double2 *>(w.UB);
+    TSVDM_LAUNCH("c_core_gram_eig", (k_core_c<LP>), dim3(nf), dim3(QT), 0, s, (const double *)w.gram_p, pparts,
+                 ell, (const double *)w.fro_part, mparts, (const double *)w.res_part, resid ? pparts : 0,
+                 o->rank_mode, o->k, o->tau, msw, kJacobiTolMixed, UB, w.sig, w.perm, w.kf, w.fro2,
+                 exact ? (double *)nullptr : F->cert, w.jinfo);
+    TSVDM_LAUNCH("c_factors", (k_factors_c<LP>), dim3((unsigned)((m2 + 63) / 64 + pparts), nf), dim3(GT), 0, s,
+                 (const float *)w.Qm, (const float *)w.Z, m, p, ell, kmax, (const double2 *)UB, (const double *)w.sig,
+                 (const int *)w.perm, (const int *)w.kf, (const double *)w.fro2, (const int32_t *)w.qr_info,
+                 (const int32_t *)w.jinfo, Uo, F->S, Vo, F->ranks, F->fro, F->info);
+    if (exact) {
+        // the certificate of the stored complex factors: 2 ranks[f] real columns
+        const int kcap = (int)(kmax < ell ? kmax : ell);
+        const bool xv = m2 % 4 == 0 && reinterpret_cast<uintptr_t>(Xd) % 16 == 0;
+#define TSVDM_CRESID(KP)                                                                                       \
+    do {                                                                                                      \
+        if (xv)                                                                                               \
+            TSVDM_LAUNCH("c_resid_factors", (k_resid<KP, true, float, true>), gm, dim3(GT), 0, s, Xd, m2, p, nf, \
+                         (const float *)Uo, (const double *)F->S, (const float *)Vo, kmax,                    \
+                         (const int32_t *)F->ranks, w.cert_part, (const int32_t *)nullptr);                   \
+        else                                                                                                  \
+            TSVDM_LAUNCH("c_resid_factors", (k_resid<KP, false, float, true>), gm, dim3(GT), 0, s, Xd, m2, p,    \
+                         nf, (const float *)Uo, (const double *)F->S, (const float *)Vo, kmax,                \
+                         (const int32_t *)F->ranks, w.cert_part, (const int32_t *)nullptr);                   \
+    } while (0)
+        if (kcap <= 16) TSVDM_CRESID(32);
+        else if (kcap <= 32) TSVDM_CRESID(64);
+        else TSVDM_CRESID(96);
+#undef TSVDM_CRESID
+        TSVDM_LAUNCH("c_cert", k_cert, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s,
+                     (const double *)w.cert_part, mparts, nf, F->cert, (const int32_t *)nullptr);
+    }
+    TSVDM_LAUNCH_CHECK("mixed truncate (complex)");
+    return TSVDM_OK;
+}
+
 // ---------------------------------------------------------------- FP64 randomized
 // PREC_F64_RAND: the randomized range finder of the mixed path with every
 // product in FP64 (FP64 MFMA) on an FP64 Xhat: Y = X Omega, Q = qr(Y),
@@ -1993,7 +2602,8 @@ namespace tsvdm {
 
 static int padded(int ell) { return ell <= 16 ? 16 : ell <= 32 ? 32 : ell <= 48 ? 48 : 64; }
 
-size_t mixed_workspace(int64_t m, int64_t p, int64_t nf, int ell) {
+size_t mixed_workspace(int64_t m, int64_t p, int64_t nf, int ell, bool cplx) {
+    if (cplx) return carve(nullptr, 2 * m, p, nf, 2 * padded(ell), nullptr, 4, false);
     return carve(nullptr, m, p, nf, padded(ell), nullptr);
 }
 
@@ -2002,6 +2612,17 @@ tsvdm_status launch_mixed_truncate(const tsvdm_tensor *X, const tsvdm_truncate_o
     if (X->m > 65536 || X->p > 65536 || X->n3 > 65535) {
         set_error("PREC_MIXED: face dims up to 65536 and up to 65535 faces");
         return TSVDM_EUNSUPPORTED;
+    }
+    if (X->dtype == TSVDM_C64) {
+        if (X->m > 32768) {
+            set_error("PREC_MIXED on complex faces: m up to 32768");
+            return TSVDM_EUNSUPPORTED;
+        }
+        switch (padded(o->k + o->oversample)) {
+            case 16: return run_cplx<16>(X, o, F, ws, s);
+            case 32: return run_cplx<32>(X, o, F, ws, s);
+            default: return run_cplx<48>(X, o, F, ws, s);
+        }
     }
     switch (padded(o->k + o->oversample)) {
         case 16: return run_mixed<16>(X, o, F, ws, s);

@@ -1,0 +1,279 @@
+"""GPU parity of the mixed-precision truncation on complex faces (the stored
+half spectrum of the unitary DFT of a real tensor) against the oracle's FP64
+randomized truncation with the same real Gaussian test matrix, its exact
+facewise truncation and, through the structured apply, its dense product."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_helpers import from_dev, reconstruct, relerr, to_dev
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from paper_2105_01170_amd import api  # noqa: E402
+from paper_2105_01170_amd import tsvdm as C  # noqa: E402
+
+
+def _factors(F, nf):
+    m, p, k = F.m, F.p, F.kmax
+    return dict(U=from_dev(F.U, (m, k, nf)).astype(np.complex128), S=from_dev(F.S, (k, nf)),
+                V=from_dev(F.V, (p, k, nf)).astype(np.complex128), ranks=from_dev(F.ranks, (nf,)),
+                cert=from_dev(F.cert, (nf,)), fro=from_dev(F.fro, (nf,)), info=from_dev(F.info, (nf,)))
+
+
+def _complex_faces(m, p, spectra, salt):
+    """Faces U_f diag(s_f) V_f^H with U_f, V_f the Q factors of complex
+    Gaussian matrices (input assembly), rounded to complex64."""
+    g = synth.rng(2, salt)
+    Xh = np.zeros((m, p, len(spectra)), dtype=np.complex128, order="F")
+    for f, s in enumerate(spectra):
+        r = len(s)
+        Ua, _ = np.linalg.qr(synth.gaussian(g, (m, r)) + 1j * synth.gaussian(g, (m, r)))
+        Va, _ = np.linalg.qr(synth.gaussian(g, (p, r)) + 1j * synth.gaussian(g, (p, r)))
+        Xh[:, :, f] = (Ua * s) @ np.conj(Va).T
+    return Xh.astype(np.complex64)
+
+
+def _truncator(m, p, nf, k, os_, Omega, **kw):
+    return api.Truncator(m, p, nf, torch.complex64, k=k, precision=C.PREC_MIXED, oversample=os_,
+                         omega=to_dev(Omega), **kw)
+
+
+def _check_against_oracle(got, Xh64, Omega, k, power, tol=1e-4):
+    nf = Xh64.shape[2]
+    rnd = oracle.randomized_tsvdm_faces(Xh64, Omega.astype(np.float64), k, power)
+    assert np.array_equal(rnd["ranks"], got["ranks"])
+    That = reconstruct(got["U"], got["S"], got["V"], got["ranks"])
+    assert relerr(That, rnd["That"]) < tol
+    fro = np.sqrt(np.sum(np.abs(Xh64) ** 2, axis=(0, 1)))
+    np.testing.assert_allclose(got["fro"], fro, rtol=1e-6)
+    for f in range(nf):
+        kf = got["ranks"][f]
+        # Weyl: singular values on the scale of ||Xhat_f||
+        np.testing.assert_allclose(got["S"][:kf, f], rnd["s"][:kf, f], rtol=0, atol=1e-6 * fro[f])
+        Uf = got["U"][:, :kf, f]
+        assert np.abs(np.conj(Uf).T @ Uf - np.eye(kf)).max() < 1e-5
+        # V = B^H U_B / s: its columns carry the FP32 error of B over s_j, so
+        # they are orthonormal where s_j is well above that level
+        kv = int(np.sum(got["S"][:kf, f] >= 1e-2 * fro[f]))
+        Vf = got["V"][:, :kv, f]
+        assert np.abs(np.conj(Vf).T @ Vf - np.eye(kv)).max() < 1e-4
+        assert not np.any(got["U"][:, kf:, f]) and not np.any(got["V"][:, kf:, f])
+    # the certificate: the error of the stored factors against the stored faces
+    true = np.array([np.linalg.norm(Xh64[:, :, f] - That[:, :, f]) for f in range(nf)])
+    np.testing.assert_allclose(got["cert"], true, rtol=1e-9, atol=1e-14 * np.max(got["fro"]))
+    return That
+
+
+@pytest.mark.parametrize("shape,k,os_", [((96, 80), 8, 8), ((70, 130), 20, 8), ((128, 112), 32, 8)])
+def test_complex_fixed_rank_matches_oracle(shape, k, os_):
+    """FIXED rank on five complex faces with decaying spectra, one power
+    iteration; sketch widths 16, 28 and 40 (padded complex widths 16, 32,
+    48, passes at 32, 64 and 96 real columns).  (70, 130): 140 real rows (not
+    a multiple of 64) and p not a multiple of 4 (the element-wise load path).
+    Ranks equal the oracle's, the truncation agrees with its FP64 randomized
+    result at 1e-4, singular values to 1e-6 of ||Xhat_f||, U and V have
+    orthonormal columns, and the certificate is the error of the returned
+    factors."""
+    m, p = shape
+    rhos = [1 / 8, 1 / 5, 1 / 3, 1 / 2, 1 / 12]
+    spectra = [10.0 ** (-rho * np.arange(1, min(m, p) // 2 + 1)) for rho in rhos]
+    Xh = _complex_faces(m, p, spectra, salt=m + p + k)
+    nf = Xh.shape[2]
+    Omega = synth.gaussian(synth.rng(2, 700 + k), (p, k + os_)).astype(np.float32)
+    tr = _truncator(m, p, nf, k, os_, Omega, power_iters=1)
+    got = _factors(tr(to_dev(Xh)), nf)
+    assert np.all(got["ranks"] == k) and np.all(got["info"] == 0)
+    _check_against_oracle(got, Xh.astype(np.complex128), Omega, k, 1)
+
+
+def test_complex_rows_over_chunks():
+    """m = 600 rows: three chunks of 256 rows in the complex Cholesky-QR (the
+    last ragged), its second pass re-reading its own output; p = 96, one
+    power iteration; parity with the oracle at 1e-4."""
+    m, p, k, os_ = 600, 96, 12, 6
+    rhos = [1 / 2, 1, 0.7]
+    spectra = [10.0 ** (-rho * np.arange(1, 61)) for rho in rhos]
+    Xh = _complex_faces(m, p, spectra, salt=61)
+    nf = Xh.shape[2]
+    Omega = synth.gaussian(synth.rng(2, 62), (p, k + os_)).astype(np.float32)
+    tr = _truncator(m, p, nf, k, os_, Omega, power_iters=1)
+    got = _factors(tr(to_dev(Xh)), nf)
+    assert np.all(got["ranks"] == k) and np.all(got["info"] == 0)
+    _check_against_oracle(got, Xh.astype(np.complex128), Omega, k, 1)
+
+
+def test_complex_no_power_iteration():
+    """No power iteration: the final basis comes from the BF16 sketch through
+    the two-pass Cholesky-QR, so the result carries the sketch's BF16 error
+    (about 2^-8 of the leading singular value) against the oracle's FP64
+    randomized truncation, while the certificate is still the exact error of
+    the returned factors."""
+    m, p, k, os_ = 200, 96, 12, 6
+    spectra = [10.0 ** (-rho * np.arange(1, 61)) for rho in (1 / 4, 1 / 2, 1 / 8)]
+    Xh = _complex_faces(m, p, spectra, salt=73)
+    nf = Xh.shape[2]
+    Omega = synth.gaussian(synth.rng(2, 74), (p, k + os_)).astype(np.float32)
+    tr = _truncator(m, p, nf, k, os_, Omega, power_iters=0)
+    got = _factors(tr(to_dev(Xh)), nf)
+    assert np.all(got["ranks"] == k) and np.all(got["info"] == 0)
+    Xh64 = Xh.astype(np.complex128)
+    rnd = oracle.randomized_tsvdm_faces(Xh64, Omega.astype(np.float64), k, 0)
+    That = reconstruct(got["U"], got["S"], got["V"], got["ranks"])
+    assert relerr(That, rnd["That"]) < 2e-2
+    true = np.array([np.linalg.norm(Xh64[:, :, f] - That[:, :, f]) for f in range(nf)])
+    np.testing.assert_allclose(got["cert"], true, rtol=1e-9, atol=1e-14 * np.max(got["fro"]))
+    for f in range(nf):
+        Uf = got["U"][:, :k, f]
+        assert np.abs(np.conj(Uf).T @ Uf - np.eye(k)).max() < 1e-5
+
+
+def _energy_margin_ok(spectra, tau, cap, rel_margin=1e-2):
+    for s in spectra:
+        fro2 = np.sum(s * s)
+        for k in range(min(cap, len(s)) + 1):
+            if abs(np.sum(s[k:] ** 2) - tau * tau * fro2) < rel_margin * tau * tau * fro2:
+                return False
+    return True
+
+
+def test_complex_energy_ranks_equal_oracle():
+    """ENERGY rule on complex faces: ranks equal, bit for bit, those of the
+    oracle's randomized truncation with the same Omega and of its exact
+    facewise truncation, on spectra whose discarded energy stays 1e-2 tau^2
+    ||X_f||^2 clear of the threshold; a face whose tolerance is out of reach
+    within the cap returns the cap with info 4."""
+    m, p, r, cap, os_ = 120, 104, 30, 24, 8
+    rhos = [1 / 16, 1 / 10, 1 / 6, 1 / 4, 1 / 3, 1 / 2, 0.7, 0.12]
+    spectra = [10.0 ** (-rho * np.arange(1, r + 1)) for rho in rhos]
+    Xh = _complex_faces(m, p, spectra, salt=63)
+    nf = Xh.shape[2]
+    Xh64 = Xh.astype(np.complex128)
+    Omega = synth.gaussian(synth.rng(2, 64), (p, cap + os_)).astype(np.float32)
+    taus = [t for t in [1e-2, 5e-3, 2e-3, 1e-3, 5e-4] if _energy_margin_ok(spectra, t, cap)]
+    assert len(taus) >= 2
+    for tau in taus:
+        tr = _truncator(m, p, nf, cap, os_, Omega, power_iters=1, rank_mode=C.RANK_ENERGY, tau=tau)
+        got = _factors(tr(to_dev(Xh)), nf)
+        rnd = oracle.randomized_tsvdm_faces(Xh64, Omega.astype(np.float64), cap, 1, mode="energy", tau=tau)
+        exact = oracle.tsvdm_truncate_faces(Xh64, "energy", cap, tau)
+        assert np.array_equal(got["ranks"], rnd["ranks"]), (tau, got["ranks"], rnd["ranks"])
+        assert np.array_equal(got["ranks"], exact["ranks"]), (tau, got["ranks"], exact["ranks"])
+        miss = np.array([np.sum(s[cap:] ** 2) > tau * tau * np.sum(s * s) for s in spectra])
+        assert np.all(got["info"][miss] == 4) and np.all(got["info"][~miss] == 0)
+        assert np.all(got["ranks"][miss] == cap)
+        ok = ~miss
+        assert np.all(got["cert"][ok] <= tau * got["fro"][ok])
+
+
+def test_complex_zero_and_nonfinite_faces():
+    """An all-zero face and a face holding a NaN between ordinary complex
+    faces: the zero face gets rank 0, ||X_f|| = 0, certificate 0, zero factors
+    and info 2 (the range finder's Cholesky breaks down on a zero sketch);
+    the NaN face info 3; the ordinary faces come out bit for bit as in a run
+    without the degenerate faces."""
+    m, p, cap, tau = 96, 80, 16, 1e-3
+    spectra = [10.0 ** (-rho * np.arange(1, 25)) for rho in (1 / 3, 1 / 2, 1 / 4, 0.4)]
+    Xh = _complex_faces(m, p, spectra, salt=65)
+    nf = Xh.shape[2]
+    bad = Xh.copy(order="F")
+    bad[:, :, 1] = 0.0
+    bad[5, 7, 2] = np.nan + 0j
+    Omega = synth.gaussian(synth.rng(2, 66), (p, cap + 8)).astype(np.float32)
+    tr = _truncator(m, p, nf, cap, 8, Omega, power_iters=1, rank_mode=C.RANK_ENERGY, tau=tau)
+    good = _factors(tr(to_dev(Xh)), nf)
+    got = _factors(tr(to_dev(bad)), nf)
+    assert np.all(good["info"] == 0)
+    for f in (0, 3):
+        for key in ("U", "S", "V", "ranks", "cert", "fro", "info"):
+            a, b = np.take(got[key], f, axis=-1), np.take(good[key], f, axis=-1)
+            assert np.array_equal(a, b), (f, key)
+    assert got["ranks"][1] == 0 and got["fro"][1] == 0.0 and got["cert"][1] == 0.0
+    assert not np.any(got["U"][:, :, 1]) and not np.any(got["S"][:, 1]) and not np.any(got["V"][:, :, 1])
+    assert got["info"][1] == 2
+    assert got["info"][2] == 3 and not np.isfinite(got["fro"][2])
+
+
+def _dft_known_rank_tensor(m, p, n3, k, rho, salt):
+    """A real tensor whose unitary DFT has M-rank k with s_j = 10^(-rho j) on
+    every face: the stored half spectrum is built (faces 0 and n3/2 real, the
+    others complex), the other faces are its conjugates, and the tensor is
+    the inverse transform (real up to rounding, the imaginary part dropped)."""
+    g = synth.rng(2, salt)
+    s = 10.0 ** (-rho * np.arange(1, k + 1))
+    half = n3 // 2 + 1
+    Xh = np.zeros((m, p, n3), dtype=np.complex128, order="F")
+    for f in range(half):
+        real = f == 0 or 2 * f == n3
+        A = synth.gaussian(g, (m, k)) + (0 if real else 1j * synth.gaussian(g, (m, k)))
+        B = synth.gaussian(g, (p, k)) + (0 if real else 1j * synth.gaussian(g, (p, k)))
+        Ua, _ = np.linalg.qr(A)
+        Va, _ = np.linalg.qr(B)
+        Xh[:, :, f] = (Ua * s) @ np.conj(Va).T
+        if 0 < f and 2 * f != n3:
+            Xh[:, :, n3 - f] = np.conj(Xh[:, :, f])
+    X = oracle.inverse_mode3(Xh, oracle.dft_matrix(n3))
+    return np.asfortranarray(np.real(X)).astype(np.float32)
+
+
+def test_complex_dft_headline_slab_512_k32_ell40():
+    """The headline face shape on the DFT: a real 512 x 512 x 16 tensor of
+    M-rank 32 (s_j = 10^(-j/8)) under the unitary DFT, transformed on the GPU
+    (9 stored complex faces), truncated with k = 32, oversampling 8 (complex
+    width 40, passes at 96 real columns over 1024 real rows), one power
+    iteration.  Against the oracle's randomized truncation with the same
+    Omega on the FP64 transform of the same FP32 tensor (all faces) and its
+    exact truncation (three faces), at 1e-4; the certificate equals the error
+    of the factors against the GPU's own transform."""
+    m, p, n3, k, os_ = 512, 512, 16, 32, 8
+    X = _dft_known_rank_tensor(m, p, n3, k, 1 / 8, salt=67)
+    half = n3 // 2 + 1
+    Omega = synth.gaussian(synth.rng(2, 68), (p, k + os_)).astype(np.float32)
+    xh = api.transform(to_dev(X), m, p, n3, C.M_DFT, +1)
+    tr = _truncator(m, p, half, k, os_, Omega, power_iters=1)
+    got = _factors(tr(xh), half)
+    assert np.all(got["ranks"] == k) and np.all(got["info"] == 0)
+    Xh64 = np.asfortranarray(oracle.mode3(X.astype(np.float64), oracle.dft_matrix(n3))[:, :, :half])
+    rnd = oracle.randomized_tsvdm_faces(Xh64, Omega.astype(np.float64), k, 1)
+    That = reconstruct(got["U"], got["S"], got["V"], got["ranks"])
+    assert np.array_equal(rnd["ranks"], got["ranks"])
+    assert relerr(That, rnd["That"]) < 1e-4
+    sample = [0, 3, 8]
+    ex = oracle.tsvdm_truncate_faces(np.asfortranarray(Xh64[:, :, sample]), "fixed", k)
+    assert relerr(That[:, :, sample], ex["That"]) < 1e-4
+    xg = from_dev(xh, (m, p, half)).astype(np.complex128)
+    true = np.array([np.linalg.norm(xg[:, :, f] - That[:, :, f]) for f in range(half)])
+    np.testing.assert_allclose(got["cert"], true, rtol=1e-9, atol=1e-14 * np.max(got["fro"]))
+    assert np.max(got["cert"] / got["fro"]) < 1e-5
+
+
+def test_complex_truncation_feeds_the_dft_apply():
+    """Truncate the DFT faces of a real tensor (block view ell = 8, q = 12)
+    with the mixed path, then apply the structured approximation to 7
+    vectors through the DFT apply: equal, to 1e-5, to the dense product of the
+    matrix the oracle forms from the same factors (Hermitian expansion,
+    inverse DFT, M_E), and within the certified error of the oracle's exact
+    rank-k approximation."""
+    ell, q, m, n3, k, os_ = 8, 12, 40, 10, 6, 6
+    p = ell * q
+    X = _dft_known_rank_tensor(m, p, n3, 12, 1 / 4, salt=69)
+    half = n3 // 2 + 1
+    Omega = synth.gaussian(synth.rng(2, 70), (p, k + os_)).astype(np.float32)
+    xh = api.transform(to_dev(X), m, p, n3, C.M_DFT, +1)
+    F = _truncator(m, p, half, k, os_, Omega, power_iters=1)(xh)
+    got = _factors(F, half)
+    x = synth.gaussian(synth.rng(2, 71), (q * n3, 7))
+    y = api.apply(F, C.M_DFT, n3, ell, q, to_dev(x.astype(np.float32)))
+    yg = from_dev(y, (ell * m, 7)).astype(np.float64)
+    U, S, V, R = oracle.expand_hermitian(got["U"], got["S"], got["V"], got["ranks"], n3)
+    T = np.real(oracle.approx_from_factors(U, S, V, R, oracle.dft_matrix(n3)))
+    A_hat = oracle.blockmat_from_tensor(T, ell, q)
+    y_ref = A_hat @ x
+    assert relerr(yg, y_ref) < 1e-5
+    # against the original matrix: the error is the truncation's
+    A = oracle.blockmat_from_tensor(X.astype(np.float64), ell, q)
+    w = np.array([1.0 if f in (0, n3 // 2) else 2.0 for f in range(half)])
+    err = np.linalg.norm(A - A_hat)
+    assert err == pytest.approx(np.sqrt(np.sum(w * got["cert"] ** 2)), rel=1e-4)
