@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--kernel-table", action="store_true", help="print the per-kernel table to stderr")
-    ap.add_argument("--workload", choices=["dense", "uneven", "learned", "apply"], default="dense",
+    ap.add_argument("--workload", choices=["dense", "dft", "uneven", "learned", "apply"], default="dense",
                     help="dense: the 512x512x256 tensor (default); uneven: the batch of 256 "
                          "Kronecker-sum matrices through the batched truncation; learned: the "
                          "predicted-width truncation against the fixed width 40; apply: "
@@ -99,6 +99,209 @@ def algorithmic_work(m, p, nf, ell, k, sweeps=5):
         # 5 sweeps with rotations on this workload (measured)
         "core_gram_eig": ("fp64", nf * sweeps * 9.0 * ell ** 3),
     }
+
+
+def algorithmic_work_dft(m, p, n3, ell, k, sweeps=5):
+    """As algorithmic_work for the complex path on the DFT's stored half
+    spectrum (nh = n3/2 + 1 complex faces, 8 bytes per value): the bytes the
+    method must move (the complex faces once per pass, the complex panels and
+    factors), not the real-view operands the kernels stage; FP64 flops of the
+    complex Cholesky-QR and core at four real flops per complex one."""
+    nh = n3 // 2 + 1
+    Xh = 8.0 * m * p * nh
+
+    def chol_qr(rows, passes):
+        return 4.0 * nh * (passes * (ell ** 3 / 3.0 + rows * ell * ell) + passes * rows * ell * (ell + 1))
+
+    return {
+        "transform_fft": ("hbm", 4.0 * m * p * n3 + Xh),                   # read X, write the half spectrum
+        "c_sketch_xw_bf16": ("hbm", Xh + 8.0 * m * ell * nh),
+        "c_power_xtw_bf16": ("hbm", Xh + 8.0 * (m + p) * ell * nh),
+        "c_power_xw_split": ("hbm", Xh + 8.0 * (m + p) * ell * nh),
+        "c_project_xtw_split": ("hbm", Xh + 8.0 * (m + p) * ell * nh),
+        "c_project_resid_split": ("hbm", Xh + 8.0 * (m + p) * ell * nh),
+        "c_factors": ("hbm", 8.0 * (m + p) * (ell + k) * nh),
+        "c_resid_factors": ("hbm", Xh + 8.0 * (m + p) * k * nh),
+        "c_cholqr_sketch": ("fp64", chol_qr(m, 1)),
+        "c_cholqr_power_z": ("fp64", chol_qr(p, 1)),
+        "c_cholqr_final": ("fp64", chol_qr(m, 2)),
+        "c_core_gram_eig": ("fp64", 4.0 * nh * sweeps * 9.0 * ell ** 3),
+    }
+
+
+def dft_main(args):
+    """The headline tensor shape under the unitary DFT: a real 512 x 512 x 256
+    FP32 tensor of M-rank 32 (sigma_j = 10^(-j/8) on every face), forward DFT
+    to its 129 stored complex faces, mixed-precision truncation of those
+    (k = 32, oversampling 8, one power iteration, certified).  value counts
+    the 256 faces of the tensor per second (the 129 stored faces determine
+    all of them)."""
+    import torch
+
+    from paper_2105_01170_amd import api
+    from paper_2105_01170_amd import tsvdm as C
+    import synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    m, p, n3, k, os_ = M_, P_, N3, K, OS
+    ell, nh = k + os_, n3 // 2 + 1
+    t_setup = time.time()
+    g = synth.rng(3, 2105)
+    sigma = 10.0 ** (-np.arange(1, k + 1) / 8.0)
+    # half-spectrum faces U_f diag(sigma) V_f^H (U_f, V_f orthonormal; faces 0
+    # and n3/2 real), the tensor is their inverse DFT (library, FP64), stored FP32
+    Uh = np.zeros((nh, k, m), dtype=np.complex128)
+    Vh = np.zeros((nh, p, k), dtype=np.complex128)
+    for f in range(nh):
+        real = f == 0 or 2 * f == n3
+        A = synth.gaussian(g, (m, k)) + (0 if real else 1j * synth.gaussian(g, (m, k)))
+        B = synth.gaussian(g, (p, k)) + (0 if real else 1j * synth.gaussian(g, (p, k)))
+        Uh[f] = np.linalg.qr(A)[0].T
+        Vh[f] = np.conj(np.linalg.qr(B)[0]) * sigma
+    xhat64 = torch.bmm(torch.from_numpy(Vh).to(dev), torch.from_numpy(Uh).to(dev)).reshape(-1)
+    del Uh, Vh
+    x64 = api.transform(xhat64, m, p, n3, C.M_DFT, -1)
+    del xhat64
+    X = x64.to(torch.float32)
+    del x64
+    Omega = synth.gaussian(g, (p, ell))
+    omega = torch.from_numpy(np.ascontiguousarray(Omega.astype(np.float32).ravel(order="F"))).to(dev)
+    xh = torch.empty(m * p * nh, dtype=torch.complex64, device=dev)
+    tr = api.Truncator(m, p, nh, torch.complex64, k=k, precision=C.PREC_MIXED, oversample=os_,
+                       power_iters=1, omega=omega, certify=1, device=dev)
+
+    def step():
+        api.transform(X, m, p, n3, C.M_DFT, +1, out=xh)
+        return tr(xh)
+
+    calib_copy(args, dev)
+    for _ in range(args.warmup):
+        F = step()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        step()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        F = step()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    setup_s = time.time() - t_setup
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        graph.replay()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = e0.elapsed_time(e1)
+    ms_step = ms_total / args.steps
+    faces_per_s = n3 * args.steps / (ms_total / 1e3)
+    C.tsvdm_timing_enable(True)
+    for _ in range(args.steps):
+        F = step()
+    torch.cuda.synchronize()
+    table = C.timing_table()
+    C.tsvdm_timing_enable(False)
+    cert = F.cert.cpu().numpy()
+    fro = F.fro.cpu().numpy()
+    info = F.info.cpu().numpy()
+    # the error of the tensor: faces 0 < f < n3/2 stand for themselves and their conjugates
+    w = np.array([1.0 if f in (0, n3 // 2) else 2.0 for f in range(nh)])
+    rel_err = float(np.sqrt(np.sum(w * cert ** 2)) / np.sqrt(np.sum(w * fro ** 2)))
+
+    work = algorithmic_work_dft(m, p, n3, ell, k)
+    kernels = {name: {"launches": n, "avg_us": 1e3 * ms / n} for name, (n, ms) in table.items()}
+    dom = max(table.items(), key=lambda kv: kv[1][1])[0]
+    n_dom, ms_dom = table[dom]
+    avg_s = ms_dom / n_dom / 1e3
+    bound, amount = work.get(dom, ("hbm", float("nan")))
+    amount = amount * args.steps / n_dom
+    if bound == "hbm":
+        roof = {"bound": "hbm", "achieved": amount / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        roof = {"bound": "alu", "achieved": amount / avg_s / 1e12, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s (fp64)"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = measured_traffic(dom, "tsvdm_dft_512x512x256_k32.md")
+    roof["kernel"] = dom
+    roof["avg_us"] = 1e6 * avg_s
+    passes = {}
+    for name, (n, ms) in table.items():
+        b, amt = work.get(name, (None, None))
+        if b == "hbm":
+            passes[name] = round(amt * args.steps / n / (ms / n / 1e3) / 1e9 / HBM_PEAK_GBS, 4)
+
+    cpu, oracle_err = None, None
+    if not args.no_cpu_baseline:
+        import oracle
+        Xhost = X.cpu().numpy().astype(np.float64).reshape((m, p, n3), order="F")
+        ns = min(args.cpu_faces, nh)
+        sel = np.linspace(0, nh - 1, ns).round().astype(int)
+        Msel = oracle.dft_matrix(n3)[sel, :]
+        c0 = time.time()
+        xs = oracle.mode3(Xhost, Msel)
+        rr = oracle.randomized_tsvdm_faces(xs, Omega, k, power_iters=1)
+        c1 = time.time()
+        cpu = {"value": ns / (c1 - c0) * n3 / nh, "unit": "faces/s", "cores": blas_threads(), "kind": "oracle",
+               "sample": f"{ns} of the {nh} stored complex faces of the same tensor: explicit DFT rows for "
+                         f"those faces, FP64 randomized truncation with the same Omega and the explicit "
+                         f"residual; {c1 - c0:.1f} s on the host, scaled by {n3}/{nh} tensor faces per "
+                         f"stored face like value"}
+        cpu.update(host_cpu())
+        kmax = F.kmax
+        Ug = F.U.cpu().numpy().reshape((m, kmax, nh), order="F")[:, :, sel].astype(np.complex128)
+        Vg = F.V.cpu().numpy().reshape((p, kmax, nh), order="F")[:, :, sel].astype(np.complex128)
+        Sg = F.S.cpu().numpy().reshape((kmax, nh), order="F")[:, sel]
+        rk = F.ranks.cpu().numpy()[sel]
+        Tg = np.zeros_like(xs)
+        for i in range(len(sel)):
+            Tg[:, :, i] = (Ug[:, :rk[i], i] * Sg[:rk[i], i]) @ np.conj(Vg[:, :rk[i], i]).T
+        nx = np.linalg.norm(xs)
+        oracle_err = {"faces": int(ns), "vs_oracle": float(np.linalg.norm(Tg - rr["That"]) / nx),
+                      "true_rel_err": float(np.linalg.norm(xs - Tg) / nx),
+                      "oracle_true_rel_err": float(np.linalg.norm(xs - rr["That"]) / nx),
+                      "ranks_equal": bool(np.array_equal(rk, rr["ranks"]))}
+    out = {
+        "metric": METRIC,
+        "value": faces_per_s,
+        "unit": "faces/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "precision": "BF16 and split-BF16 MFMA with FP32 accumulation on the real view of the complex faces; "
+                     "FP64 complex QR, Hermitian core, certificate",
+        "data": "synthetic",
+        "config": {"workload": "t-SVDM of a 512x512x256 FP32 tensor under the unitary DFT (129 stored complex "
+                               "faces), M-rank 32, sigma_j=10^(-j/8); randomized k=32, oversample 8, 1 power "
+                               "iteration, certified; value counts the 256 faces of the tensor",
+                   "m": m, "p": p, "n3": n3, "stored_faces": nh, "k": k, "oversample": os_, "power_iters": 1},
+        "stored_faces_per_s": nh * args.steps / (ms_total / 1e3),
+        "certified_rel_err": rel_err,
+        "oracle_rel_err": oracle_err,
+        "faces_flagged": int(np.sum(info != 0)),
+        "roofline": roof,
+        "hbm_pass_frac": passes,
+        "kernels_us": {kname: round(v["avg_us"], 2) for kname, v in kernels.items()},
+        "cpu_baseline": cpu,
+        "setup_s": round(setup_s, 2),
+    }
+    if args.kernel_table:
+        for kname, v in sorted(kernels.items(), key=lambda kv: -kv[1]["avg_us"] * kv[1]["launches"]):
+            print(f"{kname:24s} {v['launches']:5d} launches  {v['avg_us']:10.1f} us avg", file=sys.stderr)
+    print(json.dumps(out))
 
 
 def kernel_sources_sha256():
@@ -649,6 +852,10 @@ STEP_PATTERNS = {
                 ("f64_cholqr_final", "k_cholqr"), ("f64_project_xtw", "k_xtw64"),
                 ("f64_core_gram_eig", "k_core"), ("f64_factors", "k_factors"),
                 ("f64_resid_factors", "k_resid"), ("f64_cert", "k_cert")],
+    "dft": [("transform_fft", "k_fft_tubes"), ("c_sketch_xw_bf16", "k_xw"), ("c_cholqr_sketch", "k_cholqr_c"),
+            ("c_power_xtw_bf16", "k_xtw"), ("c_cholqr_power_z", "k_cholqr_c"), ("c_power_xw_split", "k_xw"),
+            ("c_cholqr_final", "k_cholqr_c"), ("c_project_xtw_split", "k_xtw"), ("c_core_gram_eig", "k_core_c"),
+            ("c_factors", "k_factors_c"), ("c_resid_factors", "k_resid"), ("c_cert", "k_cert")],
     "apply": [("transform_fft", "k_fft_tubes"), ("apply_v_relayout", "k_vrelayout"),
               ("apply_fused", "k_apply_lds")],
     "uneven": [("transform_direct_batched[0]", "k_direct_batched_dct"), ("batched_reset", "k_bzero"),
@@ -739,6 +946,8 @@ def profile_summary(args):
     alg = {}
     if args.pattern == "mixed":
         alg = {l: b for l, (kind, b) in algorithmic_work(M_, P_, N3, K + OS, K).items() if kind == "hbm"}
+    elif args.pattern == "dft":
+        alg = {l: b for l, (kind, b) in algorithmic_work_dft(M_, P_, N3, K + OS, K).items() if kind == "hbm"}
     elif args.pattern == "f64rand":
         X8 = 8.0 * M_ * P_ * N3
         pan = 8.0 * (M_ + P_) * (K + OS) * N3
@@ -826,6 +1035,8 @@ def main():
         return uneven_main(args)
     if args.workload == "apply":
         return apply_main(args)
+    if args.workload == "dft":
+        return dft_main(args)
     if args.workload == "learned":
         return learned_main(args)
     import torch

@@ -98,7 +98,8 @@ enum {
     TSVDM_PREC_F64 = 0,     /* plain: full facewise SVD by one-sided Jacobi in FP64     */
     TSVDM_PREC_MIXED = 1,   /* randomized range finder: BF16 sketch and first power
                                half-step, split-BF16 (FP32-accurate) final half-step
-                               and projection, FP64 orthogonalisation and core SVD    */
+                               and projection, FP64 orthogonalisation and core SVD;
+                               real (F32) or complex (C64) faces                      */
     TSVDM_PREC_F64_RAND = 2 /* the same randomized range finder with every product in
                                FP64 (FP64 MFMA) on an FP64 Xhat: FP64 accuracy of the
                                sketched truncation, for real M                        */
@@ -384,9 +385,15 @@ size_t tsvdm_truncate_workspace_size(const tsvdm_tensor *Xhat, const tsvdm_trunc
  *               with the caller's Gaussian omega, power iteration, FP64
  *               shifted Cholesky-QR, FP64 core SVD.  ENERGY decides each
  *               rank from the estimate ||Xhat_f - Q B||^2 + sum_{j>k} s_j(B)^2
- *               (Q the basis, B = Q^T Xhat_f; a residual pass with the
+ *               (Q the basis, B = Q^H Xhat_f; a residual pass with the
  *               projection).  With opts->certify, a pass after the factors
  *               computes cert from the stored factors (see tsvdm_factors).
+ *               Xhat C64 (the stored half spectrum of the DFT of a real
+ *               tensor, or any complex faces): factors C64, the same steps in
+ *               complex arithmetic with the real omega (adjoints are
+ *               conjugate transposes, the QR Hermitian, the core a Hermitian
+ *               eigensolver), sketch width k + oversample up to 48, m up to
+ *               32768.
  *   PREC_F64_RAND: Xhat FP64 (real M); factors F64; the PREC_MIXED steps
  *               with every product in FP64 (FP64 MFMA, FP64 panels), the
  *               residual ||Xhat_f - Q B||^2 taken as ||Xhat_f||^2 - ||B||^2;
@@ -400,13 +407,14 @@ tsvdm_status tsvdm_truncate(const tsvdm_tensor *Xhat, const tsvdm_truncate_opts 
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):
- * tsvdm_truncate with PREC_MIXED and no workspace argument.  Its scratch is a
- * static device array of tsvdm_noalloc_scratch_bytes() bytes (32 MiB), one
+ * tsvdm_truncate with PREC_MIXED on a real F32 Xhat and no workspace
+ * argument.  Its scratch is a static device array of tsvdm_noalloc_scratch_bytes() bytes (32 MiB), one
  * per GPU the library runs on, held until the process ends; the call itself
  * allocates nothing.  The faces are processed in consecutive groups whose
  * workspace fits the array (the results equal tsvdm_truncate's bit for bit).
  * Returns TSVDM_EWORKSPACE if a single face needs more scratch than the array
- * holds, TSVDM_EUNSUPPORTED for PREC_F64; other arguments as for
+ * holds, TSVDM_EUNSUPPORTED for other precisions and complex faces; other
+ * arguments as for
  * tsvdm_truncate.  Every call on one GPU uses that GPU's one array: calls
  * that overlap on the same GPU (other streams, other threads) race and give
  * wrong results; serialise them.  Nothing needs clearing between calls (every

@@ -367,3 +367,29 @@ def test_autotune_table_file_round_trip_and_rejection(tmp_path):
     C.tsvdm_autotune_clear()
     C.tsvdm_autotune_save(out)
     assert out.read_text() == "tsvdm-autotune 1\n"
+
+
+def test_truncate_complex_mixed_validation_and_workspace():
+    """PREC_MIXED on complex (C64) faces: a workspace of its own size, C64
+    factors required, sketch width at most 48, no allocation-free variant;
+    C128 faces are refused (FP64 data belongs to the FP64 paths)."""
+    X = _t(64, 48, 5, C.C64)
+    o = C.truncate_opts(C.RANK_FIXED, 8, 0.0, C.PREC_MIXED, 8, 1, 0, 1, 0x2000)
+    ws = C.tsvdm_truncate_workspace_size(X, o)
+    assert ws > C.tsvdm_truncate_workspace_size(_t(64, 48, 5, C.F32), o) > 0
+    F = C.factors(64, 48, 5, 8, C.C64, 0x3000, 0x4000, 0x5000, 0x6000)
+    with pytest.raises(C.TsvdmError) as e:
+        C.tsvdm_truncate(X, o, F, 0x7000, ws - 1, 0)
+    assert e.value.status == C.EWORKSPACE
+    with pytest.raises(C.TsvdmError):            # real factors for complex faces
+        C.tsvdm_truncate(X, o, C.factors(64, 48, 5, 8, C.F32, 1, 2, 3, 4), 0x7000, ws, 0)
+    wide = C.truncate_opts(C.RANK_FIXED, 41, 0.0, C.PREC_MIXED, 8, 1, 0, 1, 0x2000)  # ell 49
+    Xw = _t(64, 64, 5, C.C64)
+    assert C.tsvdm_truncate_workspace_size(Xw, wide) == 0
+    with pytest.raises(C.TsvdmError) as e:
+        C.tsvdm_truncate(Xw, wide, C.factors(64, 64, 5, 41, C.C64, 1, 2, 3, 4), 0x7000, 1 << 30, 0)
+    assert e.value.status == C.EUNSUPPORTED
+    assert C.tsvdm_truncate_workspace_size(_t(64, 48, 5, C.C128), o) == 0
+    with pytest.raises(C.TsvdmError) as e:
+        C.tsvdm_truncate_noalloc(X, o, F, 0)
+    assert e.value.status == C.EUNSUPPORTED
