@@ -32,6 +32,7 @@
 
 #include <math.h>
 
+#include <algorithm>
 #include <mutex>
 
 using namespace tsvdm;
@@ -1383,12 +1384,12 @@ __global__ __launch_bounds__(GT) void k_factors(const T *__restrict__ Q, const T
 // interleaved storage (m is then 2m): (Uhat S Vhat^H)' = [Uhat' | (-i Uhat)']
 // times [S Re Vhat | S Im Vhat]^T, the two column sets interleaved (column 2r
 // and 2r+1 for triplet r), so the kernel runs unchanged on 2 ranks[f] columns.
-template <int KP, bool VEC, typename T = float, bool CPLX = false>
-__global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_resid(const T *__restrict__ X, int m, int p, int nf,
-                                              const T *__restrict__ U, const double *__restrict__ S,
-                                              const T *__restrict__ V, int64_t kmax,
-                                              const int32_t *__restrict__ ranks, double *__restrict__ res_part,
-                                              const int32_t *__restrict__ fmap) {
+template <int KP, bool VEC, typename T, bool CPLX>
+__device__ __forceinline__ void resid_body(const T *__restrict__ X, int m, int p, int nf,
+                                           const T *__restrict__ U, const double *__restrict__ S,
+                                           const T *__restrict__ V, int64_t kmax,
+                                           const int32_t *__restrict__ ranks, double *__restrict__ res_part,
+                                           const int32_t *__restrict__ fmap) {
     constexpr int NS = KP / 4, XP = 66, VPT = KP / 4;  // V loads per thread per chunk
     __shared__ T xs[64 * XP];    // xs[c * XP + r] = X[a0 + r][b0 + c]
     constexpr int WP = 80;  // rows 4 apart fall 16 banks apart
@@ -1508,6 +1509,27 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if (tid == 0) res_part[(int64_t)f * nb + blk] = red[0] + red[1] + red[2] + red[3];
 }
 
+// Real faces: four wavefronts per SIMD (at most 128 registers).
+template <int KP, bool VEC, typename T = float>
+__global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_resid(
+    const T *__restrict__ X, int m, int p, int nf, const T *__restrict__ U, const double *__restrict__ S,
+    const T *__restrict__ V, int64_t kmax, const int32_t *__restrict__ ranks, double *__restrict__ res_part,
+    const int32_t *__restrict__ fmap) {
+    resid_body<KP, VEC, T, false>(X, m, p, nf, U, S, V, kmax, ranks, res_part, fmap);
+}
+
+// Complex faces (2 ranks[f] real columns).  The same register cap: at width
+// 64 it spills a few registers, and that costs less than the occupancy the
+// uncapped kernel loses (measured 256 against 342 us on the 129 stored faces
+// of the 512 x 512 x 256 DFT workload).
+template <int KP, bool VEC>
+__global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_resid_c(const float *__restrict__ X, int m, int p, int nf,
+                                                const float *__restrict__ U, const double *__restrict__ S,
+                                                const float *__restrict__ V, int64_t kmax,
+                                                const int32_t *__restrict__ ranks, double *__restrict__ res_part) {
+    resid_body<KP, VEC, float, true>(X, m, p, nf, U, S, V, kmax, ranks, res_part, nullptr);
+}
+
 // cert[f] = sqrt of the ordered sum of face f's residual partials
 __global__ void k_cert(const double *__restrict__ res_part, int nparts, int nf, double *__restrict__ cert,
                        const int32_t *__restrict__ fmap) {
@@ -1540,22 +1562,104 @@ __global__ void k_cert(const double *__restrict__ res_part, int nparts, int nf, 
 // Columns from ell to LP of each half are zero.
 enum { CIN_IL = 0, CIN_COMB = 1, CIN_PC = 2 };
 enum { COUT_RL = 0, COUT_PL = 1 };
-constexpr int CQT = 256;
+constexpr int CQT = 512;
+
+// Gram partials of a complex panel in one of the input layouts: rows
+// blk*CGR .. +CGR-1 of face f as the real rows [Re y | Im y] (2LP wide; the
+// combine of CIN_COMB and the sign of CIN_PC applied as they are staged),
+// their 2LP x 2LP real Gram by FP64 MFMA 16x16x4 (products of FP32 values are
+// exact), written as packed upper tiles (gram_tiles<2LP>) at
+// gpart[(f * nblk + blk) * 4 LP^2].  With W = [Re Y | Im Y] the complex Gram
+// is Y^H Y = W11 + W22 + i (W12 - W12^T).  Grid (ceil(rows/CGR), nf),
+// GT threads; spreads the first Gram of every Cholesky-QR over several
+// workgroups per face.
+constexpr int CGR = 128;
+template <int LP, int IN>
+__global__ __launch_bounds__(GT) void k_cgram(const float *__restrict__ Sin, int rows, int ell,
+                                              double *__restrict__ gpart) {
+    constexpr int L2 = 2 * LP, LDS_ = L2 + 1, NT = L2 / 16, NTILE = NT * (NT + 1) / 2, TPW = (NTILE + 3) / 4;
+    constexpr int PER = CGR * LP / GT;  // (row, column) pairs per thread
+    __shared__ float st[CGR * LDS_];
+    const int blk = blockIdx.x, f = blockIdx.y, nblk = gridDim.x, tid = threadIdx.x, wave = tid >> 6,
+              lane = tid & 63;
+    const int64_t R2 = 2 * (int64_t)rows;
+    const float *S = Sin + (int64_t)f * (IN == CIN_IL ? R2 * LP : IN == CIN_COMB ? R2 * L2 : (int64_t)rows * L2);
+    const int r0 = blk * CGR;
+    float re[PER], im[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {  // pair e: row e % CGR, column e / CGR (consecutive rows per lane)
+        const int e = tid + q * GT, r = e % CGR, c = e / CGR, row = r0 + r;
+        const int rw = row < rows ? row : rows - 1;
+        float a, b;
+        if constexpr (IN == CIN_IL) {
+            const float2 v = *reinterpret_cast<const float2 *>(S + 2 * (int64_t)rw + R2 * c);
+            a = v.x;
+            b = v.y;
+        } else if constexpr (IN == CIN_COMB) {
+            const float2 u = *reinterpret_cast<const float2 *>(S + 2 * (int64_t)rw + R2 * c);
+            const float2 v = *reinterpret_cast<const float2 *>(S + 2 * (int64_t)rw + R2 * (LP + c));
+            a = u.x - v.y;
+            b = u.y + v.x;
+        } else {
+            a = S[rw + (int64_t)rows * c];
+            b = -S[rw + (int64_t)rows * (LP + c)];
+        }
+        const bool ok = row < rows && c < ell;
+        re[q] = ok ? a : 0.0f;
+        im[q] = ok ? b : 0.0f;
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int e = tid + q * GT, r = e % CGR, c = e / CGR;
+        st[r * LDS_ + c] = re[q];
+        st[r * LDS_ + LP + c] = im[q];
+    }
+    __syncthreads();
+    f64x4 g[TPW];
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) g[t] = f64x4{0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int idx = wave + 4 * t;
+        if (idx >= NTILE) continue;
+        int ti, tj;
+        tile_ij<NT>(idx, ti, tj);
+#pragma unroll 4
+        for (int kk = 0; kk < CGR / 4; ++kk) {
+            const int r = 4 * kk + (lane >> 4);
+            g[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)st[r * LDS_ + 16 * ti + (lane & 15)],
+                                                        (double)st[r * LDS_ + 16 * tj + (lane & 15)], g[t], 0, 0, 0);
+        }
+    }
+    double *out = gpart + ((int64_t)f * nblk + blk) * L2 * L2;
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+        const int idx = wave + 4 * t;
+        if (idx >= NTILE) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) out[idx * 256 + 64 * v + lane] = g[t][v];
+    }
+}
 
 // Complex Cholesky-QR: G = Y^H Y (+ shift on the first pass) = R^H R, R upper
 // triangular with a real positive diagonal, Q = Y R^{-1}; `passes` = 2 repeats
 // the step on Q.  One workgroup per face, one row per thread in chunks of CQT
-// rows.  The Gram is formed here from the rows (staged in LDS as FP32
-// [Re | Im], FP64 MFMA over the 2LP x 2LP real Gram W^T W of W = [Re Y | Im Y]:
-// Y^H Y = W11 + W22 + i (W12 - W12^T)).  Shift, dropping rule and flag as in
-// k_cholqr; the triangular solve is in FP64 in registers, the result stored
-// as FP32 and its rounded rows are what the next pass's Gram sees.
+// rows.  The first Gram is the ordered sum of the nparts partials k_cgram
+// wrote; the second pass's is formed here from the solved rows (staged in LDS
+// as FP32 [Re | Im], FP64 MFMA over the 2LP x 2LP real Gram W^T W of
+// W = [Re Y | Im Y]); both become Y^H Y = W11 + W22 + i (W12 - W12^T).  Shift, dropping rule and flag as in
+// k_cholqr; the triangular solve is in FP64 in registers, in place in the
+// row's own array (the row value of column c is needed only when q[c] is
+// formed), the result stored as FP32 and its rounded rows are what the next
+// pass's Gram sees.
 template <int LP, int IN, int OUT>
 __global__ __launch_bounds__(CQT) void k_cholqr_c(const float *__restrict__ Sin, int rows, int ell,
                                                   float *__restrict__ Qout, int passes,
-                                                  int32_t *__restrict__ qr_info, int first) {
+                                                  int32_t *__restrict__ qr_info, int first,
+                                                  const double *__restrict__ gpart, int nparts) {
     constexpr int L2 = 2 * LP, LDG = LP + 1, LDR = LP + 1, LDS_ = L2 + 1, HR = 128;
-    constexpr int NT = L2 / 16, NH = LP / 16, NTILE = NT * (NT + 1) / 2, TPW = (NTILE + 3) / 4;
+    constexpr int NW = CQT / 64, NT = L2 / 16, NH = LP / 16, NTILE = NT * (NT + 1) / 2;
+    constexpr int TPW = (NTILE + NW - 1) / NW;
     __shared__ __align__(16) double2 G[LP * LDG];
     __shared__ __align__(16) double2 Rt[LP * LDR];  // Rt[c * LDR + j] = R[j][c]
     __shared__ double rinv[LP];
@@ -1568,7 +1672,7 @@ __global__ __launch_bounds__(CQT) void k_cholqr_c(const float *__restrict__ Sin,
     float *Q = Qout + (int64_t)f * (OUT == COUT_RL ? R2 * L2 : (int64_t)rows * L2);
     if (tid == 0) bad = 0;
     const int nch = (rows + CQT - 1) / CQT;
-    float xr[LP], xi[LP];
+    double2 q[LP];  // the thread's row: input values, then the solved row
     // row `row` of the input panel, or (own) of this kernel's output
     auto load_row = [&](int row, bool own) {
         const int rw = row < rows ? row : rows - 1;
@@ -1598,8 +1702,7 @@ __global__ __launch_bounds__(CQT) void k_cholqr_c(const float *__restrict__ Sin,
                 b = -S[rw + (int64_t)rows * (LP + c)];
             }
             const bool ok = row < rows && c < ell;
-            xr[c] = ok ? a : 0.0f;
-            xi[c] = ok ? b : 0.0f;
+            q[c] = double2{ok ? (double)a : 0.0, ok ? (double)b : 0.0};
         }
     };
     // the rows of every thread through LDS into the 2LP x 2LP Gram tiles
@@ -1610,14 +1713,14 @@ __global__ __launch_bounds__(CQT) void k_cholqr_c(const float *__restrict__ Sin,
                 const int r = tid % HR;
 #pragma unroll
                 for (int c = 0; c < LP; ++c) {
-                    st[r * LDS_ + c] = xr[c];
-                    st[r * LDS_ + LP + c] = xi[c];
+                    st[r * LDS_ + c] = (float)q[c].x;
+                    st[r * LDS_ + LP + c] = (float)q[c].y;
                 }
             }
             __syncthreads();
 #pragma unroll
             for (int t = 0; t < TPW; ++t) {
-                const int idx = wave + 4 * t;
+                const int idx = wave + NW * t;
                 if (idx >= NTILE) continue;
                 int ti, tj;
                 tile_ij<NT>(idx, ti, tj);
@@ -1639,7 +1742,7 @@ __global__ __launch_bounds__(CQT) void k_cholqr_c(const float *__restrict__ Sin,
         for (int ph = 0; ph < 2; ++ph) {
 #pragma unroll
             for (int t = 0; t < TPW; ++t) {
-                const int idx = wave + 4 * t;
+                const int idx = wave + NW * t;
                 if (idx >= NTILE) continue;
                 int ti, tj;
                 tile_ij<NT>(idx, ti, tj);
@@ -1668,16 +1771,64 @@ __global__ __launch_bounds__(CQT) void k_cholqr_c(const float *__restrict__ Sin,
         }
     };
 
-    // ---- first Gram, from the input panel
+    // ---- first Gram: ordered sum of the partials, then W11 and W12 set and
+    // W22 and -W12^T added (two phases, every entry has one writer in each)
     {
-        f64x4 g[TPW];
+        constexpr int NE2 = NTILE * 128, E2 = (NE2 + CQT - 1) / CQT, PB = 4;
+        const double2 *g2 = reinterpret_cast<const double2 *>(gpart + (int64_t)f * nparts * L2 * L2);
+        double2 acc[E2];
 #pragma unroll
-        for (int t = 0; t < TPW; ++t) g[t] = f64x4{0, 0, 0, 0};
-        for (int ch = 0; ch < nch; ++ch) {
-            load_row(ch * CQT + tid, false);
-            accumulate(g);
+        for (int u = 0; u < E2; ++u) acc[u] = double2{0.0, 0.0};
+        for (int p0 = 0; p0 < nparts; p0 += PB) {
+            double2 v[E2][PB];
+#pragma unroll
+            for (int u = 0; u < E2; ++u)
+#pragma unroll
+                for (int b = 0; b < PB; ++b) {
+                    const int e2 = tid + u * CQT, pp = p0 + b;
+                    const bool in = e2 < NE2 && pp < nparts;
+                    const double2 t = g2[(int64_t)(pp < nparts ? pp : nparts - 1) * (L2 * L2 / 2) + (e2 < NE2 ? e2 : 0)];
+                    v[u][b] = in ? t : double2{0.0, 0.0};
+                }
+#pragma unroll
+            for (int u = 0; u < E2; ++u)
+#pragma unroll
+                for (int b = 0; b < PB; ++b) {
+                    acc[u].x += v[u][b].x;
+                    acc[u].y += v[u][b].y;
+                }
         }
-        to_complex(g);
+#pragma unroll
+        for (int ph = 0; ph < 2; ++ph) {
+#pragma unroll
+            for (int u = 0; u < E2; ++u) {
+                const int e2 = tid + u * CQT;
+                if (e2 >= NE2) continue;
+                const int t = (2 * e2) >> 8, r = ((2 * e2) >> 4) & 15, c = (2 * e2) & 15;
+                int ti, tj;
+                tile_ij<NT>(t, ti, tj);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = 16 * ti + r, j = 16 * tj + c + h;
+                    const double x = h ? acc[u].y : acc[u].x;
+                    if (tj < NH) {  // W11 (the tile holds both triangles of a diagonal tile)
+                        if (ph == 0) {
+                            G[i * LDG + j].x = x;
+                            if (ti != tj) G[j * LDG + i].x = x;
+                        }
+                    } else if (ti >= NH) {  // W22
+                        if (ph == 1) {
+                            G[(i - LP) * LDG + (j - LP)].x += x;
+                            if (ti != tj) G[(j - LP) * LDG + (i - LP)].x += x;
+                        }
+                    } else {  // W12
+                        if (ph == 0) G[i * LDG + (j - LP)].y = x;
+                        else G[(j - LP) * LDG + i].y -= x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
     }
     for (int pass = 0; pass < passes; ++pass) {
         if (wave == 0) {
@@ -1746,11 +1897,10 @@ __global__ __launch_bounds__(CQT) void k_cholqr_c(const float *__restrict__ Sin,
         for (int ch = 0; ch < nch; ++ch) {
             const int row = ch * CQT + tid;
             load_row(row, pass > 0);
-            double2 q[LP];
 #pragma unroll
             for (int c = 0; c < LP; ++c) {
                 if (c < ell) {
-                    double2 v0{(double)xr[c], (double)xi[c]}, v1{0.0, 0.0};
+                    double2 v0 = q[c], v1{0.0, 0.0};
                     const double2 *rc = Rt + c * LDR;
 #pragma unroll
                     for (int j = 0; j + 1 < c; j += 2) {
@@ -1771,18 +1921,17 @@ __global__ __launch_bounds__(CQT) void k_cholqr_c(const float *__restrict__ Sin,
                 } else {
                     q[c] = double2{0.0, 0.0};
                 }
-                xr[c] = (float)q[c].x;
-                xi[c] = (float)q[c].y;
             }
             if (row < rows) {
 #pragma unroll
                 for (int c = 0; c < LP; ++c) {
+                    const float a = (float)q[c].x, b = (float)q[c].y;
                     if constexpr (OUT == COUT_RL) {
-                        *reinterpret_cast<float2 *>(Q + 2 * (int64_t)row + R2 * c) = float2{xr[c], xi[c]};
-                        *reinterpret_cast<float2 *>(Q + 2 * (int64_t)row + R2 * (LP + c)) = float2{-xi[c], xr[c]};
+                        *reinterpret_cast<float2 *>(Q + 2 * (int64_t)row + R2 * c) = float2{a, b};
+                        *reinterpret_cast<float2 *>(Q + 2 * (int64_t)row + R2 * (LP + c)) = float2{-b, a};
                     } else {
-                        Q[row + (int64_t)rows * c] = xr[c];
-                        Q[row + (int64_t)rows * (LP + c)] = xi[c];
+                        Q[row + (int64_t)rows * c] = a;
+                        Q[row + (int64_t)rows * (LP + c)] = b;
                     }
                 }
             }
@@ -2013,9 +2162,9 @@ struct MixedWs {
 };
 
 // esz: bytes per element of the panels Y, Q, Z, Qz (4 mixed, 8 FP64 randomized);
-// gram_m: whether the passes over rows of X keep Gram partials (the complex
-// path forms those Grams in its Cholesky-QR instead)
-size_t carve(char *base, int64_t m, int64_t p, int64_t nf, int LP, MixedWs *w, int esz = 4, bool gram_m = true) {
+// gm_parts: Gram partials per face in gram_m (-1: one per 64 rows of X, the
+// passes' partials; the complex path keeps the k_cgram partials there)
+size_t carve(char *base, int64_t m, int64_t p, int64_t nf, int LP, MixedWs *w, int esz = 4, int64_t gm_parts = -1) {
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
         char *ptr = base ? base + off : nullptr;
@@ -2028,7 +2177,7 @@ size_t carve(char *base, int64_t m, int64_t p, int64_t nf, int LP, MixedWs *w, i
     t.Qm = (float *)take((size_t)esz * nf * m * LP);
     t.Z = (float *)take((size_t)esz * nf * p * LP);
     t.Qp = (float *)take((size_t)esz * nf * p * LP);
-    t.gram_m = (double *)take(gram_m ? sizeof(double) * nf * mparts * LP * LP : 0);
+    t.gram_m = (double *)take(sizeof(double) * nf * (gm_parts < 0 ? mparts : gm_parts) * LP * LP);
     t.gram_p = (double *)take(sizeof(double) * nf * pparts * LP * LP);
     t.fro_part = (double *)take(sizeof(double) * nf * mparts);
     t.res_part = (double *)take(sizeof(double) * nf * pparts);
@@ -2362,7 +2511,8 @@ tsvdm_status run_cplx(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm
     const int mparts = (m2 + 63) / 64, pparts = (p + 63) / 64;
     const int64_t kmax = F->kmax;
     MixedWs w;
-    carve(reinterpret_cast<char *>(wsp), m2, p, nf, L2, &w, 4, false);
+    const int cg = (std::max(m, p) + CGR - 1) / CGR;  // Gram partials per face
+    carve(reinterpret_cast<char *>(wsp), m2, p, nf, L2, &w, 4, cg);
     const float *Xd = reinterpret_cast<const float *>(X->data);
     float *Uo = reinterpret_cast<float *>(F->U), *Vo = reinterpret_cast<float *>(F->V);
     const dim3 gm((unsigned)(mparts * nf)), gp((unsigned)(pparts * nf));
@@ -2378,8 +2528,11 @@ tsvdm_status run_cplx(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm
         TSVDM_LAUNCH("c_sketch_xw_bf16", (k_xw<LP, PROD_BF16, false, false>), gm, dim3(GT), 0, s, Xd, m2, p, nf,
                      o->omega, (int64_t)0, p, ell, w.Y, w.fro_part, (double *)nullptr, (const int32_t *)nullptr);
     if (power) {
+        TSVDM_LAUNCH("c_gram_sketch", (k_cgram<LP, CIN_IL>), dim3((m + CGR - 1) / CGR, nf), dim3(GT), 0, s,
+                     (const float *)w.Y, m, ell, w.gram_m);
         TSVDM_LAUNCH("c_cholqr_sketch", (k_cholqr_c<LP, CIN_IL, COUT_RL>), dim3(nf), dim3(CQT), 0, s,
-                     (const float *)w.Y, m, ell, w.Qm, 1, w.qr_info, 1);
+                     (const float *)w.Y, m, ell, w.Qm, 1, w.qr_info, 1, (const double *)w.gram_m,
+                     (m + CGR - 1) / CGR);
         // pass 2: [Re Z | -Im Z] = X'^T [Q' | (iQ)'] (BF16), Z = X^H Q
         if (v4)
             TSVDM_LAUNCH("c_power_xtw_bf16", (k_xtw<L2, PROD_BF16, false, false, true>), gp, dim3(GT), 0, s, Xd,
@@ -2389,8 +2542,11 @@ tsvdm_status run_cplx(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm
             TSVDM_LAUNCH("c_power_xtw_bf16", (k_xtw<L2, PROD_BF16, false, false, false>), gp, dim3(GT), 0, s, Xd,
                          m2, p, nf, (const float *)w.Qm, (int64_t)m2 * L2, m2, L2, w.Z, (double *)nullptr,
                          (double *)nullptr, (const int32_t *)nullptr);
+        TSVDM_LAUNCH("c_gram_power_z", (k_cgram<LP, CIN_PC>), dim3((p + CGR - 1) / CGR, nf), dim3(GT), 0, s,
+                     (const float *)w.Z, p, ell, w.gram_m);
         TSVDM_LAUNCH("c_cholqr_power_z", (k_cholqr_c<LP, CIN_PC, COUT_PL>), dim3(nf), dim3(CQT), 0, s,
-                     (const float *)w.Z, p, ell, w.Qp, 1, w.qr_info, 0);
+                     (const float *)w.Z, p, ell, w.Qp, 1, w.qr_info, 0, (const double *)w.gram_m,
+                     (p + CGR - 1) / CGR);
         // pass 3: P = X' [Re Qz | Im Qz] (split BF16); X Qz is combined from P
         if (v4)
             TSVDM_LAUNCH("c_power_xw_split", (k_xw<L2, PROD_SPLIT, false, true>), gm, dim3(GT), 0, s, Xd, m2, p,
@@ -2400,11 +2556,17 @@ tsvdm_status run_cplx(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm
             TSVDM_LAUNCH("c_power_xw_split", (k_xw<L2, PROD_SPLIT, false, false>), gm, dim3(GT), 0, s, Xd, m2, p,
                          nf, (const float *)w.Qp, (int64_t)p * L2, p, L2, w.Y, (double *)nullptr, (double *)nullptr,
                          (const int32_t *)nullptr);
+        TSVDM_LAUNCH("c_gram_final", (k_cgram<LP, CIN_COMB>), dim3((m + CGR - 1) / CGR, nf), dim3(GT), 0, s,
+                     (const float *)w.Y, m, ell, w.gram_m);
         TSVDM_LAUNCH("c_cholqr_final", (k_cholqr_c<LP, CIN_COMB, COUT_RL>), dim3(nf), dim3(CQT), 0, s,
-                     (const float *)w.Y, m, ell, w.Qm, 2, w.qr_info, 0);
+                     (const float *)w.Y, m, ell, w.Qm, 2, w.qr_info, 0, (const double *)w.gram_m,
+                     (m + CGR - 1) / CGR);
     } else {
+        TSVDM_LAUNCH("c_gram_final", (k_cgram<LP, CIN_IL>), dim3((m + CGR - 1) / CGR, nf), dim3(GT), 0, s,
+                     (const float *)w.Y, m, ell, w.gram_m);
         TSVDM_LAUNCH("c_cholqr_final", (k_cholqr_c<LP, CIN_IL, COUT_RL>), dim3(nf), dim3(CQT), 0, s,
-                     (const float *)w.Y, m, ell, w.Qm, 2, w.qr_info, 1);
+                     (const float *)w.Y, m, ell, w.Qm, 2, w.qr_info, 1, (const double *)w.gram_m,
+                     (m + CGR - 1) / CGR);
     }
     // pass 4: [Re B^H | -Im B^H] = X'^T [Q' | (iQ)'] (split BF16), its Gram
     // partials and, for the energy rule, ||X - Q B||^2 per 64-column block
@@ -2436,13 +2598,13 @@ tsvdm_status run_cplx(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm
 #define TSVDM_CRESID(KP)                                                                                       \
     do {                                                                                                      \
         if (xv)                                                                                               \
-            TSVDM_LAUNCH("c_resid_factors", (k_resid<KP, true, float, true>), gm, dim3(GT), 0, s, Xd, m2, p, nf, \
+            TSVDM_LAUNCH("c_resid_factors", (k_resid_c<KP, true>), gm, dim3(GT), 0, s, Xd, m2, p, nf,         \
                          (const float *)Uo, (const double *)F->S, (const float *)Vo, kmax,                    \
-                         (const int32_t *)F->ranks, w.cert_part, (const int32_t *)nullptr);                   \
+                         (const int32_t *)F->ranks, w.cert_part);                                             \
         else                                                                                                  \
-            TSVDM_LAUNCH("c_resid_factors", (k_resid<KP, false, float, true>), gm, dim3(GT), 0, s, Xd, m2, p,    \
-                         nf, (const float *)Uo, (const double *)F->S, (const float *)Vo, kmax,                \
-                         (const int32_t *)F->ranks, w.cert_part, (const int32_t *)nullptr);                   \
+            TSVDM_LAUNCH("c_resid_factors", (k_resid_c<KP, false>), gm, dim3(GT), 0, s, Xd, m2, p, nf,        \
+                         (const float *)Uo, (const double *)F->S, (const float *)Vo, kmax,                    \
+                         (const int32_t *)F->ranks, w.cert_part);                                             \
     } while (0)
         if (kcap <= 16) TSVDM_CRESID(32);
         else if (kcap <= 32) TSVDM_CRESID(64);
@@ -2603,7 +2765,7 @@ namespace tsvdm {
 static int padded(int ell) { return ell <= 16 ? 16 : ell <= 32 ? 32 : ell <= 48 ? 48 : 64; }
 
 size_t mixed_workspace(int64_t m, int64_t p, int64_t nf, int ell, bool cplx) {
-    if (cplx) return carve(nullptr, 2 * m, p, nf, 2 * padded(ell), nullptr, 4, false);
+    if (cplx) return carve(nullptr, 2 * m, p, nf, 2 * padded(ell), nullptr, 4, (std::max(m, p) + CGR - 1) / CGR);
     return carve(nullptr, m, p, nf, padded(ell), nullptr);
 }
 
