@@ -121,7 +121,12 @@ def algorithmic_work_dft(m, p, n3, ell, k, sweeps=5):
         "c_project_xtw_split": ("hbm", Xh + 8.0 * (m + p) * ell * nh),
         "c_project_resid_split": ("hbm", Xh + 8.0 * (m + p) * ell * nh),
         "c_factors": ("hbm", 8.0 * (m + p) * (ell + k) * nh),
-        "c_resid_factors": ("hbm", Xh + 8.0 * (m + p) * k * nh),
+        "c_gram_sketch": ("hbm", 8.0 * m * ell * nh),
+        "c_gram_power_z": ("hbm", 8.0 * p * ell * nh),
+        "c_gram_final": ("hbm", 8.0 * m * ell * nh),
+        # the certificate: 2 (2m) p (2k) FP64 matrix-core flops per face on the
+        # real view (four real products per complex one); bound by the FP64 MFMA
+        "c_resid_factors": ("mfma64", 8.0 * m * p * k * nh),
         "c_cholqr_sketch": ("fp64", chol_qr(m, 1)),
         "c_cholqr_power_z": ("fp64", chol_qr(p, 1)),
         "c_cholqr_final": ("fp64", chol_qr(m, 2)),
@@ -226,6 +231,9 @@ def dft_main(args):
     amount = amount * args.steps / n_dom
     if bound == "hbm":
         roof = {"bound": "hbm", "achieved": amount / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    elif bound == "mfma64":
+        roof = {"bound": "mfma", "achieved": amount / avg_s / 1e12, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s (fp64 MFMA)"}
     else:
         roof = {"bound": "alu", "achieved": amount / avg_s / 1e12, "peak": FP64_PEAK_TFLOPS,
                 "unit": "TFLOP/s (fp64)"}
@@ -852,10 +860,11 @@ STEP_PATTERNS = {
                 ("f64_cholqr_final", "k_cholqr"), ("f64_project_xtw", "k_xtw64"),
                 ("f64_core_gram_eig", "k_core"), ("f64_factors", "k_factors"),
                 ("f64_resid_factors", "k_resid"), ("f64_cert", "k_cert")],
-    "dft": [("transform_fft", "k_fft_tubes"), ("c_sketch_xw_bf16", "k_xw"), ("c_cholqr_sketch", "k_cholqr_c"),
-            ("c_power_xtw_bf16", "k_xtw"), ("c_cholqr_power_z", "k_cholqr_c"), ("c_power_xw_split", "k_xw"),
+    "dft": [("transform_fft", "k_fft_tubes"), ("c_sketch_xw_bf16", "k_xw"), ("c_gram_sketch", "k_cgram"),
+            ("c_cholqr_sketch", "k_cholqr_c"), ("c_power_xtw_bf16", "k_xtw"), ("c_gram_power_z", "k_cgram"),
+            ("c_cholqr_power_z", "k_cholqr_c"), ("c_power_xw_split", "k_xw"), ("c_gram_final", "k_cgram"),
             ("c_cholqr_final", "k_cholqr_c"), ("c_project_xtw_split", "k_xtw"), ("c_core_gram_eig", "k_core_c"),
-            ("c_factors", "k_factors_c"), ("c_resid_factors", "k_resid"), ("c_cert", "k_cert")],
+            ("c_factors", "k_factors_c"), ("c_resid_factors", "k_resid_c"), ("c_cert", "k_cert")],
     "apply": [("transform_fft", "k_fft_tubes"), ("apply_v_relayout", "k_vrelayout"),
               ("apply_fused", "k_apply_lds")],
     "uneven": [("transform_direct_batched[0]", "k_direct_batched_dct"), ("batched_reset", "k_bzero"),

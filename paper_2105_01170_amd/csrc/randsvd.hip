@@ -134,16 +134,15 @@ __device__ __forceinline__ void load_gram_partials(const double *__restrict__ gp
 // XCD L % 8, each with its own L2).  For a pass whose nb blocks of a face all
 // read the same per-face operand, give those blocks consecutive slots on one
 // XCD, so the operand is fetched into that L2 once instead of eight times.
+// The grid is nb times the face count rounded up to a multiple of 8
+// (xcd_grid); workgroups of the padding faces (f >= nf) exit at once.
 __device__ __forceinline__ void xcd_map(int L, int nb, int nf, int &b, int &f) {
-    if ((nf & 7) == 0) {
-        const int x = L & 7, s = L >> 3;
-        b = s % nb;
-        f = (s / nb) * 8 + x;
-    } else {
-        b = L % nb;
-        f = L / nb;
-    }
+    const int x = L & 7, s = L >> 3;
+    b = s % nb;
+    f = (s / nb) * 8 + x;
+    (void)nf;
 }
+inline unsigned xcd_grid(int nb, int nf) { return (unsigned)nb * (unsigned)((nf + 7) / 8 * 8); }
 
 // ---------------------------------------------------------------- staging
 // Rows r0..r0+RC-1 of the rows x LP column-major panel S into
@@ -310,6 +309,7 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
     const int nb = (m + 63) / 64;
     int blk, f;
     xcd_map(blockIdx.x, nb, nf, blk, f);
+    if (f >= nf) return;  // a padding face of the grid
     if (fmap && fmap[f] < 0) return;  // an unused slot of a face list sized on the device
     const int a0 = blk * 64;
     const float *Xf = X + (int64_t)(fmap ? fmap[f] : f) * m * p;
@@ -492,6 +492,7 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
     const int nb = (p + 63) / 64;
     int blk, f;
     xcd_map(blockIdx.x, nb, nf, blk, f);
+    if (f >= nf) return;  // a padding face of the grid
     if (fmap && fmap[f] < 0) return;  // an unused slot of a face list sized on the device
     const int b0 = blk * 64;
     const float *Xf = X + (int64_t)(fmap ? fmap[f] : f) * m * p;
@@ -777,6 +778,7 @@ __global__ __launch_bounds__(GT) void k_xw64(const double *__restrict__ X, int m
     const int nb = (m + 63) / 64;
     int blk, f;
     xcd_map(blockIdx.x, nb, nf, blk, f);
+    if (f >= nf) return;  // a padding face of the grid
     const int a0 = blk * 64, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const double *Xf = X + (int64_t)f * m * p;
     const TW *Wf = W + (int64_t)f * w_stride;
@@ -859,6 +861,7 @@ __global__ __launch_bounds__(GT) void k_xtw64(const double *__restrict__ X, int 
     const int nb = (p + 63) / 64;
     int blk, f;
     xcd_map(blockIdx.x, nb, nf, blk, f);
+    if (f >= nf) return;  // a padding face of the grid
     const int b0 = blk * 64, tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const double *Xf = X + (int64_t)f * m * p;
     const double *Wf = W + (int64_t)f * w_stride;
@@ -1399,6 +1402,7 @@ __device__ __forceinline__ void resid_body(const T *__restrict__ X, int m, int p
     const int nb = (m + 63) / 64;
     int blk, f;
     xcd_map(blockIdx.x, nb, nf, blk, f);
+    if (f >= nf) return;  // a padding face of the grid
     const int fd = fmap ? fmap[f] : f;
     if (fd < 0) return;  // an unused slot of a face list sized on the device
     const int a0 = blk * 64;
@@ -2384,7 +2388,7 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     double *fro = F->fro ? F->fro + f0 : nullptr;
     int32_t *info = F->info ? F->info + f0 : nullptr;
     const int nf = nfg;
-    const dim3 gm((unsigned)(mparts * nf)), gp((unsigned)(pparts * nf));
+    const dim3 gm(xcd_grid(mparts, nf)), gp(xcd_grid(pparts, nf));
     const bool power = o->power_iters > 0;
     // the energy rule needs the sketch residual ||X - Q B||^2 before the rank
     // is chosen (an estimate of the error, computed with the projection); the
@@ -2515,7 +2519,7 @@ tsvdm_status run_cplx(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm
     carve(reinterpret_cast<char *>(wsp), m2, p, nf, L2, &w, 4, cg);
     const float *Xd = reinterpret_cast<const float *>(X->data);
     float *Uo = reinterpret_cast<float *>(F->U), *Vo = reinterpret_cast<float *>(F->V);
-    const dim3 gm((unsigned)(mparts * nf)), gp((unsigned)(pparts * nf));
+    const dim3 gm(xcd_grid(mparts, nf)), gp(xcd_grid(pparts, nf));
     const bool power = o->power_iters > 0;
     const bool resid = o->rank_mode == TSVDM_RANK_ENERGY;
     const bool exact = o->certify && F->cert;
@@ -2637,7 +2641,7 @@ tsvdm_status run_f64rand(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, ts
     double *Z = reinterpret_cast<double *>(w.Z), *Qp = reinterpret_cast<double *>(w.Qp);
     const double *Xd = reinterpret_cast<const double *>(X->data);
     double *Uo = reinterpret_cast<double *>(F->U), *Vo = reinterpret_cast<double *>(F->V);
-    const dim3 gm((unsigned)(mparts * nf)), gp((unsigned)(pparts * nf));
+    const dim3 gm(xcd_grid(mparts, nf)), gp(xcd_grid(pparts, nf));
     const bool power = o->power_iters > 0;
     const bool exact = o->certify && F->cert;
     TSVDM_LAUNCH("f64_sketch_xw", (k_xw64<LP, float, true>), gm, dim3(GT), 0, s, Xd, m, p, nf, o->omega,
@@ -2843,7 +2847,7 @@ tsvdm_status launch_rank_features(const tsvdm_tensor *X, const float *omega, uin
     carve(reinterpret_cast<char *>(ws), m, p, nf, 32, &w);
     const int mparts = (m + 63) / 64;
     const float *Xd = reinterpret_cast<const float *>(X->data);
-    const dim3 gm((unsigned)(mparts * nf));
+    const dim3 gm(xcd_grid(mparts, nf));
     if (vec_loads_ok(Xd, m, p) && reinterpret_cast<uintptr_t>(omega) % 16 == 0)
         TSVDM_LAUNCH("features_sketch", (k_xw<32, PROD_BF16, true, true>), gm, dim3(GT), 0, s, Xd, m, p, nf,
                      omega, (int64_t)0, p, 32, w.Y, w.fro_part, w.gram_m, (const int32_t *)nullptr);

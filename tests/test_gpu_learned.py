@@ -191,3 +191,22 @@ def test_learned_truncation_graph_replays_match_eager():
         for a, b in zip(outs, ref):
             assert torch.equal(a, b), rep
         del junk
+
+
+def test_library_rank_labels_equal_the_closed_form():
+    """The rank labels the library produces for training (the width-40
+    truncation's energy rank, cap 32) equal, face by face, the exact energy
+    rank of the prescribed spectrum sigma_j = 10^(-rho j), j = 1..32 (the
+    oracle's rank_label, itself pinned to the closed form of the geometric
+    tail), on every face whose discarded energy stays 1e-2 tau^2 ||X_f||^2
+    clear of the threshold at every k (most of the 256 faces)."""
+    nf = 256
+    xh, sig = _faces(nf, salt=41)
+    rank, _ = learned.labels(xh, M, P, nf, _omega(), TAU)
+    rank = rank.cpu().numpy()
+    want = np.array([mlp.rank_label(s, TAU) for s in sig])
+    clear = np.array([all(abs(np.sum(s[k:] ** 2) - TAU * TAU * np.sum(s * s)) >= 1e-2 * TAU * TAU * np.sum(s * s)
+                          for k in range(33)) for s in sig])
+    assert clear.sum() >= 200
+    assert np.array_equal(rank[clear], want[clear]), np.nonzero(rank[clear] != want[clear])
+    assert len(np.unique(want[clear])) >= 10  # the labels span the range of ranks
