@@ -860,11 +860,14 @@ STEP_PATTERNS = {
                 ("f64_cholqr_final", "k_cholqr"), ("f64_project_xtw", "k_xtw64"),
                 ("f64_core_gram_eig", "k_core"), ("f64_factors", "k_factors"),
                 ("f64_resid_factors", "k_resid"), ("f64_cert", "k_cert")],
-    "dft": [("transform_fft", "k_fft_tubes"), ("c_sketch_xw_bf16", "k_xw"), ("c_gram_sketch", "k_cgram"),
-            ("c_cholqr_sketch", "k_cholqr_c"), ("c_power_xtw_bf16", "k_xtw"), ("c_gram_power_z", "k_cgram"),
-            ("c_cholqr_power_z", "k_cholqr_c"), ("c_power_xw_split", "k_xw"), ("c_gram_final", "k_cgram"),
-            ("c_cholqr_final", "k_cholqr_c"), ("c_project_xtw_split", "k_xtw"), ("c_core_gram_eig", "k_core_c"),
-            ("c_factors", "k_factors_c"), ("c_resid_factors", "k_resid_c"), ("c_cert", "k_cert")],
+    # two face groups (the second on a side stream), each the same launch sequence
+    "dft": [("transform_fft", "k_fft_tubes")] + [
+        (name + ("" if g == 0 else " (2nd group)"), kern) for g in range(2) for name, kern in (
+            ("c_sketch_xw_bf16", "k_xw"), ("c_gram_sketch", "k_cgram"), ("c_cholqr_sketch", "k_cholqr_c"),
+            ("c_power_xtw_bf16", "k_xtw"), ("c_gram_power_z", "k_cgram"), ("c_cholqr_power_z", "k_cholqr_c"),
+            ("c_power_xw_split", "k_xw"), ("c_gram_final", "k_cgram"), ("c_cholqr_final", "k_cholqr_c"),
+            ("c_project_xtw_split", "k_xtw"), ("c_core_gram_eig", "k_core_c"), ("c_factors", "k_factors_c"),
+            ("c_resid_factors", "k_resid_c"), ("c_cert", "k_cert"))],
     "apply": [("transform_fft", "k_fft_tubes"), ("apply_v_relayout", "k_vrelayout"),
               ("apply_fused", "k_apply_lds")],
     "uneven": [("transform_direct_batched[0]", "k_direct_batched_dct"), ("batched_reset", "k_bzero"),
@@ -891,14 +894,13 @@ def _find_csv(d, suffix):
 def _pmc_dispatches(d):
     """[(kernel name, {counter: value})] in dispatch order from a --pmc run."""
     rows = _read_csv(_find_csv(d, "_counter_collection.csv"))
-    order, by = [], {}
+    by = {}
     for r in rows:
         did = int(r["Dispatch_Id"])
         if did not in by:
             by[did] = (r["Kernel_Name"], {})
-            order.append(did)
         by[did][1][r["Counter_Name"]] = by[did][1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
-    return [by[i] for i in order]
+    return [by[i] for i in sorted(by)]  # dispatch (enqueue) order, whatever stream ran them
 
 
 def _match_steps(names, pattern):
@@ -923,6 +925,8 @@ def profile_summary(args):
     pat = STEP_PATTERNS[args.pattern]
     launches = [l for l, _ in pat]
     trace = _read_csv(_find_csv(args.trace_dir, "_kernel_trace.csv"))
+    if trace and "Dispatch_Id" in trace[0]:  # enqueue order, also for launches on several streams
+        trace.sort(key=lambda r: int(r["Dispatch_Id"]))
     tnames = [r["Kernel_Name"] for r in trace]
     starts = _match_steps(tnames, pat)
     if not starts:
@@ -956,7 +960,17 @@ def profile_summary(args):
     if args.pattern == "mixed":
         alg = {l: b for l, (kind, b) in algorithmic_work(M_, P_, N3, K + OS, K).items() if kind == "hbm"}
     elif args.pattern == "dft":
-        alg = {l: b for l, (kind, b) in algorithmic_work_dft(M_, P_, N3, K + OS, K).items() if kind == "hbm"}
+        # per launch: the transform covers the step, each group's launch its share of the 129 faces
+        nh = N3 // 2 + 1
+        share = ((nh + 1) // 2 / nh, (nh - (nh + 1) // 2) / nh)
+        alg = {}
+        for l, (kind, b) in algorithmic_work_dft(M_, P_, N3, K + OS, K).items():
+            if kind != "hbm":
+                continue
+            if l == "transform_fft":
+                alg[l] = b
+            else:
+                alg[l], alg[l + " (2nd group)"] = b * share[0], b * share[1]
     elif args.pattern == "f64rand":
         X8 = 8.0 * M_ * P_ * N3
         pan = 8.0 * (M_ + P_) * (K + OS) * N3

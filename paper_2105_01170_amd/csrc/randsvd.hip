@@ -2504,25 +2504,51 @@ tsvdm_status run_mixed(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
 
 // ---------------------------------------------------------------- complex faces
 // PREC_MIXED on complex faces (C64 Xhat, C64 factors): the steps of run_group
-// with the layouts of the complex kernels above.  LP: the padded complex
-// width; the passes run at 2LP real columns over the 2m x p real view of each
-// face.
+// with the layouts of the complex kernels above, for faces [f0, f0 + nfg) of
+// the workspace w0 carved for the whole tensor (every kernel works face by
+// face, so the pointers are offset to the group's first face; each panel by
+// its per-face stride in the carve, which is at least what every kernel
+// writes per face).  LP: the padded complex width; the passes run at 2LP real
+// columns over the 2m x p real view of each face.  mark: recorded on s after
+// the group's sketch pass (or null).
 template <int LP>
-tsvdm_status run_cplx(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F, void *wsp,
-                      hipStream_t s) {
+tsvdm_status run_cplx_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
+                            const MixedWs &w0, int f0, int nfg, hipStream_t s, hipEvent_t mark) {
     constexpr int L2 = 2 * LP;
-    const int m = (int)X->m, p = (int)X->p, nf = (int)X->n3, ell = o->k + o->oversample, m2 = 2 * m;
+    const int m = (int)X->m, p = (int)X->p, nf = nfg, ell = o->k + o->oversample, m2 = 2 * m;
     const int mparts = (m2 + 63) / 64, pparts = (p + 63) / 64;
     const int64_t kmax = F->kmax;
-    MixedWs w;
     const int cg = (std::max(m, p) + CGR - 1) / CGR;  // Gram partials per face
-    carve(reinterpret_cast<char *>(wsp), m2, p, nf, L2, &w, 4, cg);
-    const float *Xd = reinterpret_cast<const float *>(X->data);
-    float *Uo = reinterpret_cast<float *>(F->U), *Vo = reinterpret_cast<float *>(F->V);
+    MixedWs w = w0;
+    const int64_t g0 = f0;
+    w.Y += g0 * m2 * L2;
+    w.Qm += g0 * m2 * L2;
+    w.Z += g0 * p * L2;
+    w.Qp += g0 * p * L2;
+    w.gram_m += g0 * cg * L2 * L2;
+    w.gram_p += g0 * pparts * L2 * L2;
+    w.fro_part += g0 * mparts;
+    w.res_part += g0 * pparts;
+    w.cert_part += g0 * mparts;
+    w.UB += g0 * L2 * L2;
+    w.sig += g0 * L2;
+    w.fro2 += g0;
+    w.perm += g0 * L2;
+    w.kf += g0;
+    w.qr_info += g0;
+    w.jinfo += g0;
+    const float *Xd = reinterpret_cast<const float *>(X->data) + g0 * m2 * p;
+    float *Uo = reinterpret_cast<float *>(F->U) + g0 * m2 * kmax;
+    float *Vo = reinterpret_cast<float *>(F->V) + g0 * 2 * p * kmax;
+    double *So = F->S + g0 * kmax;
+    int32_t *ranks = F->ranks + g0;
+    double *cert = F->cert ? F->cert + g0 : nullptr;
+    double *fro = F->fro ? F->fro + g0 : nullptr;
+    int32_t *info = F->info ? F->info + g0 : nullptr;
     const dim3 gm(xcd_grid(mparts, nf)), gp(xcd_grid(pparts, nf));
     const bool power = o->power_iters > 0;
     const bool resid = o->rank_mode == TSVDM_RANK_ENERGY;
-    const bool exact = o->certify && F->cert;
+    const bool exact = o->certify && cert;
     const bool v4 = vec_loads_ok(Xd, m2, p);
     // pass 1: (X Omega)' (BF16) and ||X||^2
     if (v4 && reinterpret_cast<uintptr_t>(o->omega) % 16 == 0)
@@ -2531,6 +2557,10 @@ tsvdm_status run_cplx(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm
     else
         TSVDM_LAUNCH("c_sketch_xw_bf16", (k_xw<LP, PROD_BF16, false, false>), gm, dim3(GT), 0, s, Xd, m2, p, nf,
                      o->omega, (int64_t)0, p, ell, w.Y, w.fro_part, (double *)nullptr, (const int32_t *)nullptr);
+    if (mark) {
+        hipError_t e = hipEventRecord(mark, s);
+        if (e != hipSuccess) return hip_check(e, "complex truncate: mark");
+    }
     if (power) {
         TSVDM_LAUNCH("c_gram_sketch", (k_cgram<LP, CIN_IL>), dim3((m + CGR - 1) / CGR, nf), dim3(GT), 0, s,
                      (const float *)w.Y, m, ell, w.gram_m);
@@ -2590,11 +2620,11 @@ tsvdm_status run_cplx(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm
     TSVDM_LAUNCH("c_core_gram_eig", (k_core_c<LP>), dim3(nf), dim3(QT), 0, s, (const double *)w.gram_p, pparts,
                  ell, (const double *)w.fro_part, mparts, (const double *)w.res_part, resid ? pparts : 0,
                  o->rank_mode, o->k, o->tau, msw, kJacobiTolMixed, UB, w.sig, w.perm, w.kf, w.fro2,
-                 exact ? (double *)nullptr : F->cert, w.jinfo);
+                 exact ? (double *)nullptr : cert, w.jinfo);
     TSVDM_LAUNCH("c_factors", (k_factors_c<LP>), dim3((unsigned)((m2 + 63) / 64 + pparts), nf), dim3(GT), 0, s,
                  (const float *)w.Qm, (const float *)w.Z, m, p, ell, kmax, (const double2 *)UB, (const double *)w.sig,
                  (const int *)w.perm, (const int *)w.kf, (const double *)w.fro2, (const int32_t *)w.qr_info,
-                 (const int32_t *)w.jinfo, Uo, F->S, Vo, F->ranks, F->fro, F->info);
+                 (const int32_t *)w.jinfo, Uo, So, Vo, ranks, fro, info);
     if (exact) {
         // the certificate of the stored complex factors: 2 ranks[f] real columns
         const int kcap = (int)(kmax < ell ? kmax : ell);
@@ -2603,21 +2633,65 @@ tsvdm_status run_cplx(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm
     do {                                                                                                      \
         if (xv)                                                                                               \
             TSVDM_LAUNCH("c_resid_factors", (k_resid_c<KP, true>), gm, dim3(GT), 0, s, Xd, m2, p, nf,         \
-                         (const float *)Uo, (const double *)F->S, (const float *)Vo, kmax,                    \
-                         (const int32_t *)F->ranks, w.cert_part);                                             \
+                         (const float *)Uo, (const double *)So, (const float *)Vo, kmax,                      \
+                         (const int32_t *)ranks, w.cert_part);                                                \
         else                                                                                                  \
             TSVDM_LAUNCH("c_resid_factors", (k_resid_c<KP, false>), gm, dim3(GT), 0, s, Xd, m2, p, nf,        \
-                         (const float *)Uo, (const double *)F->S, (const float *)Vo, kmax,                    \
-                         (const int32_t *)F->ranks, w.cert_part);                                             \
+                         (const float *)Uo, (const double *)So, (const float *)Vo, kmax,                      \
+                         (const int32_t *)ranks, w.cert_part);                                                \
     } while (0)
         if (kcap <= 16) TSVDM_CRESID(32);
         else if (kcap <= 32) TSVDM_CRESID(64);
         else TSVDM_CRESID(96);
 #undef TSVDM_CRESID
         TSVDM_LAUNCH("c_cert", k_cert, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s,
-                     (const double *)w.cert_part, mparts, nf, F->cert, (const int32_t *)nullptr);
+                     (const double *)w.cert_part, mparts, nf, cert, (const int32_t *)nullptr);
     }
     TSVDM_LAUNCH_CHECK("mixed truncate (complex)");
+    return TSVDM_OK;
+}
+
+// The side streams of this device if they already exist (none are created:
+// the caller may be capturing a graph).
+bool side_streams_created(SideStreams **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return false;
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    *out = g_side[dev];
+    return *out != nullptr;
+}
+
+// Two face groups: with one workgroup per face, the per-face FP64 kernels of
+// a group leave most CUs idle, so the second group runs on a side stream,
+// started once the first group's sketch pass has finished, and its passes
+// over X fill those CUs (and the other way round); the caller's stream then
+// waits for it.  One group for a few faces, or when the side streams do not
+// exist yet and s is being captured (creating them would break the capture).
+// The results do not depend on the grouping: every kernel works face by face.
+template <int LP>
+tsvdm_status run_cplx(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F, void *wsp,
+                      hipStream_t s) {
+    const int m = (int)X->m, p = (int)X->p, nf = (int)X->n3;
+    MixedWs w;
+    carve(reinterpret_cast<char *>(wsp), 2 * m, p, nf, 2 * LP, &w, 4, (std::max(m, p) + CGR - 1) / CGR);
+    SideStreams *ss = nullptr;
+    bool split = nf >= 32;
+    if (split) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        hipError_t e = hipStreamIsCapturing(s, &cs);
+        if (e != hipSuccess) return hip_check(e, "complex truncate: capture status");
+        split = cs == hipStreamCaptureStatusNone ? side_streams(&ss) == TSVDM_OK : side_streams_created(&ss);
+    }
+    if (!split) return run_cplx_group<LP>(X, o, F, w, 0, nf, s, nullptr);
+    const int g0 = (nf + 1) / 2;
+    tsvdm_status st = run_cplx_group<LP>(X, o, F, w, 0, g0, s, ss->ev[0]);
+    if (st != TSVDM_OK) return st;
+    hipStream_t sb = ss->s[0];
+    hipError_t e = hipStreamWaitEvent(sb, ss->ev[0], 0);
+    if (e != hipSuccess) return hip_check(e, "complex truncate: fork");
+    if ((st = run_cplx_group<LP>(X, o, F, w, g0, nf - g0, sb, nullptr)) != TSVDM_OK) return st;
+    if ((e = hipEventRecord(ss->ev[1], sb)) != hipSuccess) return hip_check(e, "complex truncate: join");
+    if ((e = hipStreamWaitEvent(s, ss->ev[1], 0)) != hipSuccess) return hip_check(e, "complex truncate: join");
     return TSVDM_OK;
 }
 

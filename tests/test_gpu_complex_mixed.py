@@ -277,3 +277,92 @@ def test_complex_truncation_feeds_the_dft_apply():
     w = np.array([1.0 if f in (0, n3 // 2) else 2.0 for f in range(half)])
     err = np.linalg.norm(A - A_hat)
     assert err == pytest.approx(np.sqrt(np.sum(w * got["cert"] ** 2)), rel=1e-4)
+
+
+def test_complex_path_graph_replays_match_eager():
+    """The DFT transform and the complex truncation launch kernels only:
+    captured in a graph, every replay (outputs overwritten and eager work
+    with synchronization between replays) gives the eager result bit for
+    bit, including an odd face count (not a multiple of 8) and the
+    certificate pass."""
+    m, p, n3, k, os_ = 96, 88, 10, 12, 8
+    X = _dft_known_rank_tensor(m, p, n3, 16, 1 / 5, salt=81)
+    half = n3 // 2 + 1
+    Omega = synth.gaussian(synth.rng(2, 82), (p, k + os_)).astype(np.float32)
+    xd = to_dev(X)
+    xh = torch.empty(m * p * half, dtype=torch.complex64, device="cuda")
+    tr = _truncator(m, p, half, k, os_, Omega, power_iters=1)
+
+    def step():
+        api.transform(xd, m, p, n3, C.M_DFT, +1, out=xh)
+        return tr(xh)
+
+    F = step()
+    torch.cuda.synchronize()
+    outs = (F.U, F.S, F.V, F.ranks, F.cert, F.fro, F.info)
+    ref = [t.clone() for t in outs]
+    assert np.all(F.info.cpu().numpy() == 0) and np.all(F.ranks.cpu().numpy() == k)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for rep in range(3):
+        for t in outs:
+            t.fill_(-7)
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(outs, ref):
+            assert torch.equal(a, b), rep
+        del junk
+
+
+def test_complex_two_face_groups_equal_separate_calls():
+    """40 faces take the two-group schedule (the second group on a side
+    stream): every output equals, bit for bit, two separate calls on the
+    first and last 20 faces (one group each), in eager mode and in every
+    replay of a captured graph."""
+    m, p, k, os_, nf = 64, 56, 8, 8, 40
+    spectra = [10.0 ** (-(0.1 + 0.02 * f) * np.arange(1, 33)) for f in range(nf)]
+    Xh = _complex_faces(m, p, spectra, salt=83)
+    Omega = synth.gaussian(synth.rng(2, 84), (p, k + os_)).astype(np.float32)
+    xd = to_dev(Xh)
+    tr = _truncator(m, p, nf, k, os_, Omega, power_iters=1)
+    F = tr(xd)
+    torch.cuda.synchronize()
+    got = _factors(F, nf)
+    half = nf // 2
+    parts = []
+    for lo in (0, half):
+        t = _truncator(m, p, half, k, os_, Omega, power_iters=1)
+        parts.append(_factors(t(to_dev(np.asfortranarray(Xh[:, :, lo:lo + half]))), half))
+    for key in ("U", "S", "V", "ranks", "cert", "fro", "info"):
+        joined = np.concatenate([parts[0][key], parts[1][key]], axis=-1)
+        assert np.array_equal(got[key], joined), key
+    outs = (F.U, F.S, F.V, F.ranks, F.cert, F.fro, F.info)
+    ref = [t.clone() for t in outs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        tr(xd, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        tr(xd)
+    for rep in range(3):
+        for t in outs:
+            t.fill_(-7)
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(outs, ref):
+            assert torch.equal(a, b), rep
+        del junk
