@@ -393,7 +393,12 @@ size_t tsvdm_truncate_workspace_size(const tsvdm_tensor *Xhat, const tsvdm_trunc
  *               complex arithmetic with the real omega (adjoints are
  *               conjugate transposes, the QR Hermitian, the core a Hermitian
  *               eigensolver), sketch width k + oversample up to 48, m up to
- *               32768.
+ *               32768.  From 32 faces on, half of them run on a stream the
+ *               library creates per device (as tsvdm_truncate_learned's),
+ *               joined back to `stream` with events; under stream capture
+ *               that happens only if an earlier call created it (else one
+ *               stream, same results).  Complex truncations issued at once
+ *               from several host threads on one device must be serialized.
  *   PREC_F64_RAND: Xhat FP64 (real M); factors F64; the PREC_MIXED steps
  *               with every product in FP64 (FP64 MFMA, FP64 panels), the
  *               residual ||Xhat_f - Q B||^2 taken as ||Xhat_f||^2 - ||B||^2;
