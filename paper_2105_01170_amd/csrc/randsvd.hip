@@ -1452,7 +1452,8 @@ __device__ __forceinline__ void resid_body(const T *__restrict__ X, int m, int p
                     xr[4 * it + 2] = ok ? v1.x : 0.0;
                     xr[4 * it + 3] = ok ? v1.y : 0.0;
                 } else {
-                    const f32x4 v = *reinterpret_cast<const f32x4 *>(src);
+                    // the last read of Xhat in a truncation: non-temporal
+                    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(src));
 #pragma unroll
                     for (int u = 0; u < 4; ++u) xr[4 * it + u] = ok ? v[u] : 0.0f;
                 }

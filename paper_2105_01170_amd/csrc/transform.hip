@@ -60,7 +60,10 @@ __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, V
     typedef T vec_t __attribute__((ext_vector_type(VW)));
     // vector path, forward: the tile (at most 32 KiB, so at most 2048 vectors,
     // VMAX a thread) is loaded before the twiddles are computed, which then
-    // overlap the loads' latency
+    // overlap the loads' latency.  The input is read once: non-temporal loads
+    // leave the caches (and the MALL) to the transformed tensor the next pass
+    // reads (measured on 512 x 512 x 256: transform 124.6 -> 121.3 us, the
+    // following sketch pass 74.4 -> 70.4 us)
     constexpr int VMAX = 2048 / NT;
     const int lvpr = logtt - (VW == 4 ? 2 : 1), vpr = 1 << lvpr, vtotal = vpr * N;
     vec_t vfirst[VMAX];
@@ -70,7 +73,8 @@ __global__ __launch_bounds__(NT) void k_fft_tubes(const void *__restrict__ in, V
         for (int q = 0; q < VMAX; ++q) {
             const int w = tid + q * NT;
             const int u4 = w & (vpr - 1), t = w >> lvpr;
-            if (w < vtotal) vfirst[q] = *reinterpret_cast<const vec_t *>(X + u4 * VW + (int64_t)t * iv.s_t);
+            if (w < vtotal)
+                vfirst[q] = __builtin_nontemporal_load(reinterpret_cast<const vec_t *>(X + u4 * VW + (int64_t)t * iv.s_t));
         }
     }
 
