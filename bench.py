@@ -1051,7 +1051,7 @@ def main():
     if args.profile_summary:
         return profile_summary(args)
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 "
                           "(sharding over several GPUs is designed but not built)"}))
         sys.exit(2)
     if args.workload == "uneven":
