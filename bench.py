@@ -28,6 +28,7 @@ METRIC = "faces/sec truncated t-SVDM @1e-4 rel err, mixed vs FP64 GPU; % HBM/MFM
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 FP32_MFMA_PEAK_TFLOPS = 157.3
+FP32_VALU_PEAK_TFLOPS = 157.3
 M_, P_, N3, K, OS = 512, 512, 256, 32, 8
 
 
@@ -41,7 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--kernel-table", action="store_true", help="print the per-kernel table to stderr")
-    ap.add_argument("--workload", choices=["dense", "dft", "uneven", "learned", "apply"], default="dense",
+    ap.add_argument("--workload", choices=["dense", "dft", "uneven", "learned", "apply", "structured", "hosvd",
+                                           "mprod", "spsd"], default="dense",
                     help="dense: the 512x512x256 tensor (default); uneven: the batch of 256 "
                          "Kronecker-sum matrices through the batched truncation; learned: the "
                          "predicted-width truncation against the fixed width 40; apply: "
@@ -645,6 +647,338 @@ def apply_main(args):
     print(json.dumps(out))
 
 
+# ---------------------------------------------------------------- widened rows
+def _timed(step, steps, warmup, stream):
+    """(ms per step over `steps` eager steps bracketed by events on stream,
+    the library's per-launch timing table of 3 more steps)."""
+    import torch
+
+    from paper_2105_01170_amd import tsvdm as C
+    for _ in range(max(warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    C.tsvdm_timing_enable(True)
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    table = C.timing_table()
+    C.tsvdm_timing_enable(False)
+    return ms, table
+
+
+def _roof(table, work, reps=3):
+    """Roofline of the kernel with the largest summed time among those with a
+    work figure: work[name] = (bound, amount per step), bound "hbm" (bytes),
+    "mfma32"/"mfma64" (matrix-core flops) or "alu64" (FP64 vector flops)."""
+    dom = max(table.items(), key=lambda kv: kv[1][1])[0]
+    n, ms = table[dom]
+    avg_s = ms / n / 1e3
+    if dom not in work:  # no work figure for this launch: its time only
+        return {"bound": None, "achieved": None, "peak": None, "unit": None, "frac": None, "traffic": None,
+                "kernel": dom, "avg_us": 1e6 * avg_s}
+    bound, amount = work[dom]
+    per_launch = amount * reps / n
+    if bound == "hbm":
+        roof = {"bound": "hbm", "achieved": per_launch / avg_s / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    elif bound == "mfma32":
+        roof = {"bound": "mfma", "achieved": per_launch / avg_s / 1e12, "peak": FP32_MFMA_PEAK_TFLOPS,
+                "unit": "TFLOP/s (fp32 MFMA)"}
+    elif bound == "mfma64":
+        roof = {"bound": "mfma", "achieved": per_launch / avg_s / 1e12, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s (fp64 MFMA)"}
+    elif bound == "alu32":
+        roof = {"bound": "alu", "achieved": per_launch / avg_s / 1e12, "peak": FP32_VALU_PEAK_TFLOPS,
+                "unit": "TFLOP/s (fp32 vector)"}
+    else:
+        roof = {"bound": "alu", "achieved": per_launch / avg_s / 1e12, "peak": FP64_PEAK_TFLOPS,
+                "unit": "TFLOP/s (fp64)"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+    roof["kernel"] = dom
+    roof["avg_us"] = 1e6 * avg_s
+    return roof
+
+
+def _trunc_work(m, p, nf, ell, k):
+    """algorithmic_work for a mixed truncation of nf faces of m x p, the FP64
+    per-face kernels counted as FP64 vector work."""
+    w = dict(algorithmic_work(m, p, nf, ell, k))
+    w.update({nm: ("alu64", v) for nm, (b, v) in w.items() if b == "fp64"})
+    w["cert"] = ("hbm", 8.0 * nf * ((m + 63) // 64))
+    return w
+
+
+def next_main(args):
+    """The rows built after the hot path, each measured on one workload:
+    structured  NEXT-1: a 4096 x 4096 block-Toeplitz matrix (64 x 64 blocks, 127
+                distinct) compressed (T_E gather with sqrt(eta) weights, DCT-II,
+                mixed truncation at rank 8) and applied to 1024 vectors by the
+                structured apply; value: the step's dense-equivalent GFLOP/s.
+    hosvd       NEXT-2: the mode-3 HOSVD factor of a 512 x 512 x 64 tensor as the
+                transform (mode-3 Gram, Jacobi eigensolver), the dense transform
+                and the mixed truncation at rank 16; value: faces/s.
+    mprod       NEXT-3: the truncated t-SVDM of a 64 x 64 x 64 tensor under the DFT
+                as the M-product operator on 64 x 1024 x 64 (the block-circulant
+                reading of a 4096 x 4096 operator on 1024 vectors); value:
+                dense-equivalent GFLOP/s of the operator.
+    spsd        NEXT-4: the two-sided compression of a synthetic space-time
+                covariance (N = 1351 points, T = 30 times, rank 30): T_E from the
+                30 distinct blocks, the factor U from the mixed truncation of the
+                mode-1 unfolding, the FP64 core; value: steps/s, with the trace
+                error and storage ratio of Sec. 6.2."""
+    import torch
+
+    import oracle
+    from paper_2105_01170_amd import api
+    from paper_2105_01170_amd import tsvdm as C
+    import synth
+
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    wl = args.workload
+
+    def dev32(a):
+        return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float32).ravel(order="F"))).to(dev)
+
+    def dev64(a):
+        return torch.from_numpy(np.ascontiguousarray(np.asarray(a, dtype=np.float64).ravel(order="F"))).to(dev)
+
+    out = {"n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "data": "synthetic"}
+    if wl == "structured":
+        ell = q = m = n = 64
+        k, os_, nrhs = 8, 8, 1024
+        block_of, p = C.tsvdm_block_structure(C.PLACE_TOEPLITZ, ell, q, 0)
+        g = synth.rng(10, 1)
+        # 127 distinct blocks sum_r c[k, r] a_r w_r^T (8 terms, weights 10^(-r/4)) + 1e-6 relative noise
+        a, wv = g.standard_normal((m, 8)), g.standard_normal((n, 8))
+        c = g.standard_normal((p, 8)) * 10.0 ** (-np.arange(8) / 4.0)
+        blocks = np.einsum("kr,ar,tr->atk", c, a, wv)
+        blocks = synth.add_relative_noise(g, blocks, 1e-6)
+        A = np.zeros((ell * m, q * n), order="F")
+        for j in range(q):
+            for i in range(ell):
+                kb = block_of[i + ell * j]
+                if kb >= 0:
+                    A[i * m:(i + 1) * m, j * n:(j + 1) * n] = blocks[:, :, kb]
+        A32 = A.astype(np.float32)
+        x = g.standard_normal((q * n, nrhs))
+        Omega = g.standard_normal((p, k + os_))
+        pl = api.Placement(ell, q, block_of, p)
+        Ad, xd, od = dev32(A32), dev32(x), dev32(Omega)
+        tr = api.Truncator(m, p, n, torch.float32, k=k, precision=C.PREC_MIXED, oversample=os_, power_iters=1,
+                           omega=od, device=dev)
+        res = {}
+
+        def step():
+            xt = pl.tensor_from_blockmat(Ad, m, n)
+            F = tr(api.transform(xt, m, p, n, C.M_DCT2, +1))
+            res["y"] = pl.apply(F, C.M_DCT2, n, xd)
+
+        ms, table = _timed(step, args.steps, args.warmup, stream)
+        dense = 2.0 * (ell * m) * (q * n) * nrhs
+        work = _trunc_work(m, p, n, k + os_, k)
+        work.update({"apply_fused": ("mfma32", n * 2.0 * (ell * k * q * nrhs + ell * m * k * nrhs)),
+                     "tensor_from_blockmat_E": ("hbm", 4.0 * (m * p * n + m * p * n)),
+                     "transform_fft": ("hbm", 2 * 4.0 * (m * p * n + q * n * nrhs)),
+                     "apply_E_vgather": ("hbm", 4.0 * n * k * (p + ell * q)),
+                     "apply_v_relayout": ("hbm", 2 * 4.0 * n * k * ell * q)})
+        out.update({"metric": "structured (block-Toeplitz) compress + apply, dense-equivalent GFLOP/s",
+                    "value": dense / (ms / 1e3) / 1e9, "unit": "GFLOP/s", "ms_per_step": ms, "dtype": "f32",
+                    "config": {"workload": "4096 x 4096 block-Toeplitz matrix, 64 x 64 blocks (127 distinct, each "
+                                           "a sum of 8 rank-one terms + 1e-6 noise), T_E with sqrt(eta) weights, "
+                                           "DCT-II, mixed truncation k = 8 (+8), structured apply to 1024 vectors"}})
+        if not args.no_cpu_baseline:
+            E = []
+            for kb in range(p):
+                Ek = np.array([[1.0 if block_of[i + ell * j] == kb else 0.0 for j in range(q)] for i in range(ell)])
+                E.append(Ek / np.sqrt(Ek.sum()))
+            c0 = time.time()
+            X = oracle.tensor_from_blockmat_E(A32.astype(np.float64), E, m, n)
+            ref = oracle.tsvdm(X, oracle.dct2_matrix(n), "fixed", k)
+            Aref = oracle.blockmat_from_tensor_E(ref["T"], E)
+            y_ref = oracle.dense_apply(Aref, x.astype(np.float32).astype(np.float64))
+            c1 = time.time()
+            yg = res["y"].cpu().numpy().astype(np.float64).reshape((ell * m, nrhs), order="F")
+            out["oracle_rel_err"] = float(np.linalg.norm(yg - y_ref) / np.linalg.norm(y_ref))
+            out["cpu_baseline"] = dict(value=dense / (c1 - c0) / 1e9, unit="GFLOP/s", cores=blas_threads(),
+                                       kind="oracle", sample="the whole step: T_E, exact t-SVDM (Jacobi), the "
+                                       "dense matrix formed, its product with the 1024 vectors (FP64)")
+            out["cpu_baseline"].update(host_cpu())
+    elif wl == "hosvd":
+        m, p, n, k, os_ = 512, 512, 64, 16, 8
+        g = synth.rng(10, 2)
+        # a sum of 24 separable terms with decaying weights: the mode-3 spectrum decays
+        r = 24
+        Aa, Bb, Cc = g.standard_normal((m, r)), g.standard_normal((p, r)), g.standard_normal((n, r))
+        wts = 10.0 ** (-np.arange(r) / 6.0)
+        Xd = torch.einsum("r,ar,br,tr->tba", torch.tensor(wts), torch.tensor(Aa), torch.tensor(Bb),
+                          torch.tensor(Cc)).contiguous().reshape(-1).to(dev, torch.float32)
+        Omega = g.standard_normal((p, k + os_))
+        tr = api.Truncator(m, p, n, torch.float32, k=k, precision=C.PREC_MIXED, oversample=os_, power_iters=1,
+                           omega=dev32(Omega), device=dev)
+        res = {}
+
+        def step():
+            Md, sv = api.mode3_transform(Xd, m, p, n)
+            xh = api.transform(Xd, m, p, n, C.M_DENSE, +1, M=Md)
+            res["F"], res["M"], res["sv"] = tr(xh), Md, sv
+
+        ms, table = _timed(step, args.steps, args.warmup, stream)
+        work = _trunc_work(m, p, n, k + os_, k)
+        nparts = 512  # the Gram's persistent workgroups, one n x n FP64 partial each
+        work.update({"mode_gram": ("hbm", 4.0 * m * p * n), "transform_direct": ("hbm", 2 * 4.0 * m * p * n),
+                     "mode_gram_reduce": ("hbm", 8.0 * nparts * n * n),
+                     # cyclic Jacobi on the n x n Gram: 9 n^3 flops per sweep, 5 sweeps counted (as the core)
+                     "sym_eig": ("alu64", 5 * 9.0 * n ** 3), "sqrt_pos": ("hbm", 16.0 * n)})
+        out.update({"metric": "data-driven transform (mode-3 HOSVD) + mixed t-SVDM, faces/s",
+                    "value": n / (ms / 1e3), "unit": "faces/s", "ms_per_step": ms, "dtype": "bf16",
+                    "config": {"workload": "512 x 512 x 64 FP32 tensor, a sum of 24 separable terms with weights "
+                                           "10^(-r/6); M = the mode-3 HOSVD factor (mode-3 Gram, Jacobi); mixed "
+                                           "truncation k = 16 (+8)"}})
+        if not args.no_cpu_baseline:
+            X64 = Xd.cpu().numpy().astype(np.float64).reshape((m, p, n), order="F")
+            c0 = time.time()
+            Mo = oracle.mode3_transform_matrix(X64)
+            sel = [0, 1, 2, 7]
+            xs = oracle.mode3(X64, Mo[sel, :])
+            rr = oracle.randomized_tsvdm_faces(xs, Omega, k, power_iters=1)
+            c1 = time.time()
+            F = res["F"]
+            Mg = res["M"].cpu().numpy().reshape((n, n), order="F")
+            sv_o = np.linalg.svd(oracle.unfold(X64, 3), compute_uv=False)
+            km = F.kmax
+            U = F.U.cpu().numpy().reshape((m, km, n), order="F")[:, :, sel].astype(np.float64)
+            V = F.V.cpu().numpy().reshape((p, km, n), order="F")[:, :, sel].astype(np.float64)
+            S = F.S.cpu().numpy().reshape((km, n), order="F")[:, sel]
+            rk = F.ranks.cpu().numpy()[sel]
+            T = np.stack([(U[:, :rk[i], i] * S[:rk[i], i]) @ V[:, :rk[i], i].T for i in range(len(sel))], axis=2)
+            # rows of M for the leading mode-3 singular values, above 1e-3 of the
+            # largest (below, down to the FP32 rounding of X, the basis is that of
+            # a near-null space and any orthonormal one is as good)
+            nz = int(np.sum(sv_o > 1e-3 * sv_o[0]))
+            out["oracle_rel_err"] = {
+                "transform_M_leading_rows": float(np.abs(Mg[:nz] - Mo[:nz]).max()), "leading_rows": nz,
+                "mode3_singular_values": float(np.max(np.abs(res["sv"].cpu().numpy() - sv_o)) / sv_o[0]),
+                "truncation_vs_oracle": float(np.linalg.norm(T - rr["That"]) / np.linalg.norm(xs)),
+                "ranks_equal": bool(np.array_equal(rk, rr["ranks"]))}
+            out["cpu_baseline"] = dict(value=len(sel) / (c1 - c0), unit="faces/s", cores=blas_threads(), kind="oracle",
+                                       sample=f"the mode-3 HOSVD factor (SVD of the unfolding) and {len(sel)} of the "
+                                       f"{n} faces (explicit transform rows, FP64 randomized truncation); "
+                                       f"{c1 - c0:.1f} s")
+            out["cpu_baseline"].update(host_cpu())
+    elif wl == "mprod":
+        m = p = n = 64
+        k, os_, s = 16, 8, 1024
+        g = synth.rng(10, 3)
+        U0, V0 = g.standard_normal((m, k, n)), g.standard_normal((p, k, n))
+        sig = 10.0 ** (-np.arange(1, k + 1) / 8.0)
+        Mf = oracle.dft_matrix(n)
+        Uh, Vh = oracle.mode3(U0, Mf), oracle.mode3(V0, Mf)
+        Th = np.zeros((m, p, n), dtype=complex, order="F")
+        for f in range(n):
+            Th[:, :, f] = (Uh[:, :, f] * sig) @ np.conj(Vh[:, :, f]).T
+        Tt = np.real(oracle.inverse_mode3(Th, Mf)).astype(np.float32)
+        nf = n // 2 + 1
+        Omega = g.standard_normal((p, k + os_))
+        xh = api.transform(dev32(Tt), m, p, n, C.M_DFT, +1)
+        F = api.Truncator(m, p, nf, torch.complex64, k=k, precision=C.PREC_MIXED, oversample=os_, power_iters=1,
+                          omega=dev32(Omega), device=dev)(xh)
+        X = g.standard_normal((p, s, n))
+        xd = dev32(X)
+        res = {}
+
+        def step():
+            res["Y"] = api.mprod(F, C.M_DFT, n, xd, s)
+
+        ms, table = _timed(step, args.steps, args.warmup, stream)
+        kt = api.kron_terms(F, C.M_DFT, n, 8, 8)
+        torch.cuda.synchronize()
+        dense = 2.0 * (m * n) * (p * n) * s
+        # the facewise complex products (Z = V^H Xhat, Y = U S Z: 8 flops per complex
+        # multiply-add, FP32 vector units) and the two tube transforms
+        work = {"mprod_faces": ("alu32", nf * 8.0 * (k * p * s + m * k * s)),
+                "transform_fft": ("hbm", 4.0 * (p + m) * s * n + 8.0 * (p + m) * s * nf)}
+        out.update({"metric": "M-product operator Y = T *_M X, dense-equivalent GFLOP/s",
+                    "value": dense / (ms / 1e3) / 1e9, "unit": "GFLOP/s", "ms_per_step": ms, "dtype": "f32",
+                    "kron_terms": int(kt[2]),
+                    "config": {"workload": "T 64 x 64 x 64 of M-rank 16 (sigma_j = 10^(-j/8)) under the unitary DFT, "
+                                           "mixed truncation of its 33 stored complex faces (k = 16, +8), applied as "
+                                           "the M-product operator to X 64 x 1024 x 64 (the block-circulant 4096 x "
+                                           "4096 operator on 1024 vectors)"}})
+        if not args.no_cpu_baseline:
+            c0 = time.time()
+            ref = oracle.tsvdm(Tt.astype(np.float64), Mf, "fixed", k)
+            Yo = np.real(oracle.mprod(ref["T"], X.astype(np.float32).astype(np.float64), Mf))
+            c1 = time.time()
+            Yg = res["Y"].cpu().numpy().astype(np.float64).reshape((m, s, n), order="F")
+            out["oracle_rel_err"] = float(np.linalg.norm(Yg - Yo) / np.linalg.norm(Yo))
+            out["cpu_baseline"] = dict(value=dense / (c1 - c0) / 1e9, unit="GFLOP/s", cores=blas_threads(),
+                                       kind="oracle", sample="exact t-SVDM of T (Jacobi) and the M-product with the "
+                                       "whole X (explicit DFT matrix, facewise products), FP64")
+            out["cpu_baseline"].update(host_cpu())
+    else:  # spsd
+        N, T, r = 1351, 30, 30
+        blocks, _, _ = synth.spacetime_covariance(N, T)
+        pl = api.Placement.structure(C.PLACE_TOEPLITZ_SYM, T, T)
+        b64, b32 = dev64(blocks), dev32(blocks)
+        g = synth.rng(10, 4)
+        Omega = g.standard_normal((T * N, r + 8))
+        tr = api.Truncator(N, T * N, 1, torch.float32, k=r, precision=C.PREC_MIXED, oversample=8, power_iters=1,
+                           omega=dev32(Omega), device=dev)
+        res = {}
+
+        def step():
+            X64 = pl.tensor_from_blocks(b64, N, N)
+            X32 = pl.tensor_from_blocks(b32, N, N)
+            U = tr(X32).U[:N * r]
+            res["G"], res["U"], res["X64"] = api.two_sided(X64, N, T, U, r), U, X64
+
+        ms, table = _timed(step, args.steps, args.warmup, stream)
+        # the core reads the FP64 tensor once; T_E writes it in FP64 and FP32 from the small blocks
+        work = _trunc_work(N, T * N, 1, r + 8, r)
+        # G_b = U^T S_b U: 2 N^2 r + 2 N r^2 FP64 flops per slice (FP64 vector units)
+        work.update({"two_sided": ("alu64", T * (2.0 * N * N * r + 2.0 * N * r * r)),
+                     "two_sided_reduce": ("hbm", 8.0 * T * ((N + 63) // 64) * r * r),
+                     "tensor_from_blocks_E": ("hbm", 12.0 * N * T * N)})
+        Uh = res["U"].cpu().numpy().astype(np.float64).reshape((N, r), order="F")
+        trc = float(N * T)
+        out.update({"metric": "SPSD two-sided compression of a space-time covariance, steps/s",
+                    "value": 1e3 / ms, "unit": "steps/s", "ms_per_step": ms, "dtype": "bf16",
+                    "trace_rel_err": abs(trc - T * float(np.trace(Uh.T @ blocks[:, :, 0] @ Uh))) / trc,
+                    "storage_ratio": (r * r * T + N * r) / (N * N * T),
+                    "config": {"workload": "N = 1351 random points on a longitude/latitude box, T = 30 times, "
+                                           "phi(r, tau) = exp(-((r/90)^2 + (tau/0.5)^2)), symmetric block-Toeplitz "
+                                           "placement, U from the mixed truncation of the 1351 x 40530 mode-1 "
+                                           "unfolding (k = 30, +8), FP64 core G = X x1 U^T x3 U^T"}})
+        if not args.no_cpu_baseline:
+            Xh = res["X64"].cpu().numpy().reshape((N, T, N), order="F")
+            c0 = time.time()
+            rr = oracle.randomized_face(oracle.unfold(Xh, 1), Omega, 1)
+            Go, _ = oracle.spsd_two_sided(Xh, Uh)
+            c1 = time.time()
+            Gg = res["G"].cpu().numpy().reshape((r, T, r), order="F")
+            Uo = rr[0][:, :r]
+            out["oracle_rel_err"] = {"core_G": float(np.linalg.norm(Gg - Go) / np.linalg.norm(Go)),
+                                     "range_of_U": float(np.linalg.norm(Uh - Uo @ (Uo.T @ Uh)) / np.sqrt(r))}
+            out["cpu_baseline"] = dict(value=1.0 / (c1 - c0), unit="steps/s", cores=blas_threads(), kind="oracle",
+                                       sample="FP64 randomized factor of the mode-1 unfolding (same Omega) and the "
+                                       "two-sided core, from the same tensor")
+            out["cpu_baseline"].update(host_cpu())
+    out["roofline"] = _roof(table, work)
+    out["kernels_us_per_step"] = {nm: round(1e3 * t / 3, 2) for nm, (nl, t) in table.items()}
+    print(json.dumps(out))
+
+
 def host_cpu():
     """The host CPU's model name and the number of logical CPUs this process may use."""
     model = "unknown"
@@ -1060,6 +1394,8 @@ def main():
         return apply_main(args)
     if args.workload == "dft":
         return dft_main(args)
+    if args.workload in ("structured", "hosvd", "mprod", "spsd"):
+        return next_main(args)
     if args.workload == "learned":
         return learned_main(args)
     import torch

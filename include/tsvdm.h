@@ -262,7 +262,10 @@ tsvdm_status tsvdm_sym_eig(const double *G, int64_t N, double *lam, double *W, v
  * vectors of X_(3) (eigenvectors of the mode-3 Gram, sign-fixed as above), M =
  * W^T (n3 x n3, device, column major, FP64) for TSVDM_M_DENSE, so that face f
  * of X x_3 M carries the energy sv[f]^2 of the unfolding; sv (n3, device, may
- * be NULL): the singular values of X_(3), decreasing.  n3 <= 64. */
+ * be NULL): the singular values of X_(3), decreasing.  n3 <= 64.  The Jacobi
+ * solver stops rotating pairs below 1e-15 of the Gram's trace: eigenvalues
+ * are exact to that absolute level, and rows of M for eigenvalues within it
+ * of each other or of zero are some orthonormal basis of their subspace. */
 size_t tsvdm_mode3_transform_workspace_size(const tsvdm_tensor *X);
 tsvdm_status tsvdm_mode3_transform(const tsvdm_tensor *X, double *M, double *sv, void *workspace,
                                    size_t workspace_bytes, void *stream);

@@ -32,7 +32,7 @@ namespace {
 inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int GT = 256, CH = 64;  // threads; elements per chunk
-constexpr int GRAM_WG = 512;      // workgroups of the Gram kernel (fixed: partials summed in order)
+constexpr int GRAM_WG = 512;      // workgroups of the Gram kernel (fixed, so the partials are summed in a fixed order)
 
 // element e of row j of the mode-`mode` unfolding of a dense m x p x n3 tensor
 struct UnfoldView {
@@ -104,20 +104,41 @@ __global__ __launch_bounds__(GT) void k_mode_gram(const T *__restrict__ X, Unfol
     }
 }
 
-// G (N x N, column major) = ordered sum of the partials' upper blocks, mirrored
+// G (N x N, column major) = sum of the partials' upper blocks, mirrored.
+// Workgroup: 16 entries, each summed by 16 threads over the partials
+// q, q + 16, .. (independent loads in flight), then the 16 sums of an entry
+// added in a fixed order: the result is the same on every run.
+constexpr int RE = 16, RQ = 16;
 template <int NP>
-__global__ void k_gram_reduce(const double *__restrict__ part, int nparts, int N, double *__restrict__ G) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= N * N) return;
-    int i = e % N, j = e / N;
-    if (i / 4 > j / 4) {  // lower block: the mirror of an upper one
-        const int t = i;
-        i = j;
-        j = t;
-    }
+__global__ __launch_bounds__(RE * RQ) void k_gram_reduce(const double *__restrict__ part, int nparts, int N,
+                                                         double *__restrict__ G) {
+    __shared__ double red[RQ][RE];
+    const int el = threadIdx.x % RE, q = threadIdx.x / RE;
+    const int e = blockIdx.x * RE + el;
     double s = 0.0;
-    for (int w = 0; w < nparts; ++w) s += part[(int64_t)w * NP * NP + i * NP + j];
-    G[e] = s;
+    if (e < N * N) {
+        int i = e % N, j = e / N;
+        if (i / 4 > j / 4) {  // lower block: the mirror of an upper one
+            const int t = i;
+            i = j;
+            j = t;
+        }
+        const double *src = part + i * NP + j;
+        int w = q;
+        for (; w + 3 * RQ < nparts; w += 4 * RQ) {
+            const double a = src[(int64_t)w * NP * NP], b = src[(int64_t)(w + RQ) * NP * NP];
+            const double c = src[(int64_t)(w + 2 * RQ) * NP * NP], d = src[(int64_t)(w + 3 * RQ) * NP * NP];
+            s += (a + b) + (c + d);
+        }
+        for (; w < nparts; w += RQ) s += src[(int64_t)w * NP * NP];
+    }
+    red[q][el] = s;
+    __syncthreads();
+    if (q == 0 && e < N * N) {
+        double t = 0.0;
+        for (int u = 0; u < RQ; ++u) t += red[u][el];
+        G[e] = t;
+    }
 }
 
 constexpr int ET = 512;
@@ -125,7 +146,7 @@ constexpr int ET = 512;
 // lam[j] decreasing, W[:, j] the eigenvectors (largest-magnitude entry
 // positive), and, when Mt is set, Mt = W^T (column major).
 template <int LP>
-__global__ __launch_bounds__(ET) void k_sym_eig(const double *__restrict__ G, int N, int max_sweeps,
+__global__ __launch_bounds__(ET) void k_sym_eig(const double *__restrict__ G, int N, int max_sweeps, double jtol,
                                                 double *__restrict__ lam, double *__restrict__ W,
                                                 double *__restrict__ Mt, int32_t *__restrict__ info) {
     constexpr int LD = jacobi_ld<LP>(), LDE = jacobi_ld<LP>(), NPM = LP / 2;
@@ -147,9 +168,23 @@ __global__ __launch_bounds__(ET) void k_sym_eig(const double *__restrict__ G, in
     if (tid < N) Eb[0][tid * LDE + tid] = 1.0;
     if (tid < 3) rflag[tid] = 0;
     __syncthreads();
+    // absolute rotation threshold jtol times the trace (0: the relative test
+    // alone, every eigenpair to full relative accuracy).  For a transform
+    // basis of a positive semidefinite Gram, 1e-15 leaves the eigenvectors of
+    // eigenvalues at the rounding level of the largest unresolved, which on
+    // low-rank data took most of the sweeps
+    if (tid < 64) {
+        double t = 0.0;
+        for (int c = tid; c < N; c += 64) t += fabs(Gb[0][c * LD + c]);
+        t = wave_sum(t);
+        if (tid == 0) lv[0] = t;
+    }
+    __syncthreads();
+    const double atol = jtol * lv[0];
+    __syncthreads();
     int conv = 0, dslot;
     const double *Gf, *Ef;
-    jacobi_eig<LP, ET>(Gb[0], Gb[1], Eb[0], Eb[1], &cs[0][0], rflag, N, 0.0, max_sweeps, conv, Gf, Ef, dslot);
+    jacobi_eig<LP, ET>(Gb[0], Gb[1], Eb[0], Eb[1], &cs[0][0], rflag, N, atol, max_sweeps, conv, Gf, Ef, dslot);
     if (tid < N) {
         const int sl = jacobi_slot(tid, dslot);
         lv[tid] = Gf[sl * LD + sl];
@@ -257,8 +292,8 @@ tsvdm_status launch_gram(const tsvdm_tensor *X, int mode, double *G, void *ws, h
         else                                                                                                \
             TSVDM_LAUNCH("mode_gram", (k_mode_gram<NPV, float>), dim3(GRAM_WG), dim3(GT), 0, s,             \
                          reinterpret_cast<const float *>(X->data), v, part);                                \
-        TSVDM_LAUNCH("mode_gram_reduce", (k_gram_reduce<NPV>), dim3((unsigned)((N * N + 255) / 256)), dim3(256), \
-                     0, s, (const double *)part, GRAM_WG, (int)N, G);                                       \
+        TSVDM_LAUNCH("mode_gram_reduce", (k_gram_reduce<NPV>), dim3((unsigned)((N * N + RE - 1) / RE)),           \
+                     dim3(RE * RQ), 0, s, (const double *)part, GRAM_WG, (int)N, G);                        \
     } while (0)
     switch (NP) {
         case 16: TSVDM_GRAM(16); break;
@@ -271,9 +306,10 @@ tsvdm_status launch_gram(const tsvdm_tensor *X, int mode, double *G, void *ws, h
     return TSVDM_OK;
 }
 
-tsvdm_status launch_eig(const double *G, int64_t N, double *lam, double *W, double *Mt, hipStream_t s) {
+tsvdm_status launch_eig(const double *G, int64_t N, double *lam, double *W, double *Mt, double jtol, hipStream_t s) {
 #define TSVDM_EIG(LPV)                                                                                         \
-    TSVDM_LAUNCH("sym_eig", (k_sym_eig<LPV>), dim3(1), dim3(ET), 0, s, G, (int)N, 60, lam, W, Mt, (int32_t *)nullptr)
+    TSVDM_LAUNCH("sym_eig", (k_sym_eig<LPV>), dim3(1), dim3(ET), 0, s, G, (int)N, 60, jtol, lam, W, Mt,         \
+                 (int32_t *)nullptr)
     switch (padded(N)) {
         case 16: TSVDM_EIG(16); break;
         case 32: TSVDM_EIG(32); break;
@@ -312,7 +348,7 @@ tsvdm_status tsvdm_mode_gram(const tsvdm_tensor *X, int32_t mode, double *G, voi
 tsvdm_status tsvdm_sym_eig(const double *G, int64_t N, double *lam, double *W, void *stream) {
     if (!G || !lam || !W) FAILH(TSVDM_EINVAL, "G, lam and W are required");
     if (N < 1 || N > 64) FAILH(TSVDM_EUNSUPPORTED, "order %lld: 1..64", (long long)N);
-    return launch_eig(G, N, lam, W, nullptr, (hipStream_t)stream);
+    return launch_eig(G, N, lam, W, nullptr, 0.0, (hipStream_t)stream);
 }
 
 size_t tsvdm_mode3_transform_workspace_size(const tsvdm_tensor *X) {
@@ -337,7 +373,7 @@ tsvdm_status tsvdm_mode3_transform(const tsvdm_tensor *X, double *M, double *sv,
     double *lam = W + al256(sizeof(double) * (size_t)(N * N)) / sizeof(double);
     tsvdm_status st = launch_gram(X, 3, G, workspace, s);
     if (st != TSVDM_OK) return st;
-    st = launch_eig(G, N, lam, W, M, s);
+    st = launch_eig(G, N, lam, W, M, 1e-15, s);
     if (st != TSVDM_OK) return st;
     if (sv) {
         TSVDM_LAUNCH("sqrt_pos", k_sqrt_pos, dim3(1), dim3(64), 0, s, (const double *)lam, (int)N, sv);
