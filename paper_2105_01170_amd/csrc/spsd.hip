@@ -26,19 +26,27 @@ inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int ST = 256;
 
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
+// Workgroup (column chunk t0 of 64, slice b): W = U^T S[:, t0 .. t0+63] (r x 64,
+// S = sq(X(:, b, :))) by FP64 MFMA 16x16x4 over 64-row LDS chunks of U and S
+// (wavefront w: column tile w, every row tile of U^T), then the partial
+// W U[t0 .. t0+63, :] (r x r) on the vector units.  Rows past m are staged as
+// zeros, so the tail chunk needs no special case.
 template <typename TX, typename TU>
 __global__ __launch_bounds__(ST) void k_two_sided_fwd(const TX *__restrict__ X, int64_t m, int64_t p,
                                                       const TU *__restrict__ U, int r, double *__restrict__ part) {
     __shared__ double us[64 * 65];  // us[a * 65 + i] = U(a0 + a, i); later U(t0 + c, j)
     __shared__ double xs[64 * 65];  // xs[a * 65 + c] = S(a0 + a, t0 + c)
     __shared__ double ws[64 * 65];  // ws[i * 65 + c] = W(i, c)
-    const int tid = threadIdx.x, cl = tid & 63, g = tid >> 6;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t b = blockIdx.y, t0 = (int64_t)blockIdx.x * 64;
     const int64_t lds = m * p;  // leading dimension of S = sq(X(:, b, :))
     const TX *S = X + m * b;
-    double w[16];
+    const int nti = (r + 15) / 16;
+    f64x4_t acc[4];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) w[u] = 0.0;
+    for (int u = 0; u < 4; ++u) acc[u] = f64x4_t{0, 0, 0, 0};
     for (int64_t a0 = 0; a0 < m; a0 += 64) {
         __syncthreads();
         for (int e = tid; e < 64 * 64; e += ST) {
@@ -48,16 +56,24 @@ __global__ __launch_bounds__(ST) void k_two_sided_fwd(const TX *__restrict__ X, 
             us[aa * 65 + cc] = oka && cc < r ? (double)U[(a0 + aa) + m * cc] : 0.0;
         }
         __syncthreads();
-        const int na = (int)(m - a0 < 64 ? m - a0 : 64);
-        for (int aa = 0; aa < na; ++aa) {
-            const double x = xs[aa * 65 + cl];
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+            const int a = 4 * kk + (lane >> 4);
+            const double bv = xs[a * 65 + 16 * wave + (lane & 15)];  // B[k][c] = S(a, c)
 #pragma unroll
-            for (int u = 0; u < 16; ++u) w[u] = fma(us[aa * 65 + g + 4 * u], x, w[u]);
+            for (int ti = 0; ti < 4; ++ti)
+                if (ti < nti)  // A[i][k] = U(a, i)
+                    acc[ti] = __builtin_amdgcn_mfma_f64_16x16x4f64(us[a * 65 + 16 * ti + (lane & 15)], bv, acc[ti],
+                                                                   0, 0, 0);
         }
     }
     __syncthreads();
+    // FP64 16x16x4 output: row lane/16 + 4v, column lane%16 of the tile
 #pragma unroll
-    for (int u = 0; u < 16; ++u) ws[(g + 4 * u) * 65 + cl] = w[u];
+    for (int ti = 0; ti < 4; ++ti)
+        if (ti < nti)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) ws[(16 * ti + (lane >> 4) + 4 * v) * 65 + 16 * wave + (lane & 15)] = acc[ti][v];
     for (int e = tid; e < 64 * 64; e += ST) {  // U rows t0 .. t0+63
         const int cc = e % 64, j = e / 64;
         us[cc * 65 + j] = t0 + cc < m && j < r ? (double)U[(t0 + cc) + m * j] : 0.0;
