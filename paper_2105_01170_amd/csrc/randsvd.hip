@@ -1387,24 +1387,31 @@ __global__ __launch_bounds__(GT) void k_factors(const T *__restrict__ Q, const T
 // interleaved storage (m is then 2m): (Uhat S Vhat^H)' = [Uhat' | (-i Uhat)']
 // times [S Re Vhat | S Im Vhat]^T, the two column sets interleaved (column 2r
 // and 2r+1 for triplet r), so the kernel runs unchanged on 2 ranks[f] columns.
+// nsplit: the face's columns split into that many ranges, one workgroup per
+// (64-row block, range), partial r = blk * nsplit + range (in that order, so
+// the ordered sum of a face's partials is fixed); more than one only where the
+// faces times row blocks leave most CUs idle (resid_splits).
 template <int KP, bool VEC, typename T, bool CPLX>
 __device__ __forceinline__ void resid_body(const T *__restrict__ X, int m, int p, int nf,
                                            const T *__restrict__ U, const double *__restrict__ S,
                                            const T *__restrict__ V, int64_t kmax,
                                            const int32_t *__restrict__ ranks, double *__restrict__ res_part,
-                                           const int32_t *__restrict__ fmap) {
+                                           const int32_t *__restrict__ fmap, int nsplit) {
     constexpr int NS = KP / 4, XP = 66, VPT = KP / 4;  // V loads per thread per chunk
     __shared__ T xs[64 * XP];    // xs[c * XP + r] = X[a0 + r][b0 + c]
     constexpr int WP = 80;  // rows 4 apart fall 16 banks apart
     __shared__ T ws[KP * WP];    // ws[r * WP + c] = V[b0 + c][r]
     __shared__ double ss[KP];        // S_r
     __shared__ double red[GT / 64];
-    const int nb = (m + 63) / 64;
-    int blk, f;
-    xcd_map(blockIdx.x, nb, nf, blk, f);
+    const int nb = ((m + 63) / 64) * nsplit;
+    int blkx, f;
+    xcd_map(blockIdx.x, nb, nf, blkx, f);
     if (f >= nf) return;  // a padding face of the grid
     const int fd = fmap ? fmap[f] : f;
     if (fd < 0) return;  // an unused slot of a face list sized on the device
+    const int blk = blkx / nsplit, sp = blkx % nsplit;
+    const int cps = ((p + 63) / 64 + nsplit - 1) / nsplit;  // 64-column chunks per range
+    const int c0 = sp * cps * 64, c1 = (sp + 1) * cps * 64 < p ? (sp + 1) * cps * 64 : p;
     const int a0 = blk * 64;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int rk = CPLX ? 2 * ranks[fd] : ranks[fd];
@@ -1476,8 +1483,8 @@ __device__ __forceinline__ void resid_body(const T *__restrict__ X, int m, int p
         }
     };
     double racc = 0.0;
-    load(0);
-    for (int b0 = 0; b0 < p; b0 += 64) {
+    if (c0 < c1) load(c0);
+    for (int b0 = c0; b0 < c1; b0 += 64) {
 #pragma unroll
         for (int it = 0; it < 4; ++it)
 #pragma unroll
@@ -1485,7 +1492,7 @@ __device__ __forceinline__ void resid_body(const T *__restrict__ X, int m, int p
 #pragma unroll
         for (int q = 0; q < VPT; ++q) ws[(vr0 + 4 * q) * WP + vc] = vr[q];
         __syncthreads();
-        if (b0 + 64 < p) load(b0 + 64);  // next chunk in flight during the products
+        if (b0 + 64 < c1) load(b0 + 64);  // next chunk in flight during the products
         f64x4 acc[4];
 #pragma unroll
         for (int t = 0; t < 4; ++t) acc[t] = f64x4{0, 0, 0, 0};
@@ -1511,7 +1518,7 @@ __device__ __forceinline__ void resid_body(const T *__restrict__ X, int m, int p
     racc = wave_sum(racc);
     if (lane == 0) red[wave] = racc;
     __syncthreads();
-    if (tid == 0) res_part[(int64_t)f * nb + blk] = red[0] + red[1] + red[2] + red[3];
+    if (tid == 0) res_part[(int64_t)f * nb + blkx] = red[0] + red[1] + red[2] + red[3];
 }
 
 // Real faces: four wavefronts per SIMD (at most 128 registers).
@@ -1519,8 +1526,8 @@ template <int KP, bool VEC, typename T = float>
 __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_resid(
     const T *__restrict__ X, int m, int p, int nf, const T *__restrict__ U, const double *__restrict__ S,
     const T *__restrict__ V, int64_t kmax, const int32_t *__restrict__ ranks, double *__restrict__ res_part,
-    const int32_t *__restrict__ fmap) {
-    resid_body<KP, VEC, T, false>(X, m, p, nf, U, S, V, kmax, ranks, res_part, fmap);
+    const int32_t *__restrict__ fmap, int nsplit) {
+    resid_body<KP, VEC, T, false>(X, m, p, nf, U, S, V, kmax, ranks, res_part, fmap, nsplit);
 }
 
 // Complex faces (2 ranks[f] real columns).  The same register cap: at width
@@ -1532,7 +1539,7 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                                                 const float *__restrict__ U, const double *__restrict__ S,
                                                 const float *__restrict__ V, int64_t kmax,
                                                 const int32_t *__restrict__ ranks, double *__restrict__ res_part) {
-    resid_body<KP, VEC, float, true>(X, m, p, nf, U, S, V, kmax, ranks, res_part, nullptr);
+    resid_body<KP, VEC, float, true>(X, m, p, nf, U, S, V, kmax, ranks, res_part, nullptr, 1);
 }
 
 // cert[f] = sqrt of the ordered sum of face f's residual partials
@@ -2166,6 +2173,19 @@ struct MixedWs {
     int32_t *qr_info, *jinfo;
 };
 
+// Column ranges of the certificate pass per face (resid_body): more than one
+// only when the faces' 64-row blocks alone would leave most of the 256 CUs
+// idle (a few wide faces); then about 512 workgroups in all.
+constexpr int kResidSplitMax = 32;
+inline int resid_splits(int64_t nf, int64_t mparts, int64_t p) {
+    const int64_t chunks = (p + 63) / 64, blocks = nf * mparts;
+    if (blocks >= 256 || blocks < 1) return 1;
+    int64_t sp = (512 + blocks - 1) / blocks;
+    if (sp > kResidSplitMax) sp = kResidSplitMax;
+    if (sp > chunks) sp = chunks;
+    return sp < 1 ? 1 : (int)sp;
+}
+
 // esz: bytes per element of the panels Y, Q, Z, Qz (4 mixed, 8 FP64 randomized);
 // gm_parts: Gram partials per face in gram_m (-1: one per 64 rows of X, the
 // passes' partials; the complex path keeps the k_cgram partials there)
@@ -2186,7 +2206,7 @@ size_t carve(char *base, int64_t m, int64_t p, int64_t nf, int LP, MixedWs *w, i
     t.gram_p = (double *)take(sizeof(double) * nf * pparts * LP * LP);
     t.fro_part = (double *)take(sizeof(double) * nf * mparts);
     t.res_part = (double *)take(sizeof(double) * nf * pparts);
-    t.cert_part = (double *)take(sizeof(double) * nf * mparts);
+    t.cert_part = (double *)take(sizeof(double) * nf * mparts * kResidSplitMax);
     t.UB = (double *)take(sizeof(double) * nf * LP * LP);
     t.sig = (double *)take(sizeof(double) * nf * LP);
     t.fro2 = (double *)take(sizeof(double) * nf);
@@ -2372,7 +2392,7 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     w.gram_p += g0 * pparts * LP * LP;
     w.fro_part += g0 * mparts;
     w.res_part += g0 * pparts;
-    w.cert_part += g0 * mparts;
+    w.cert_part += g0 * mparts * kResidSplitMax;
     w.UB += g0 * LP * LP;
     w.sig += g0 * LP;
     w.fro2 += g0;
@@ -2472,16 +2492,21 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
         // ranks are at most min(kmax, ell): the W staging is sized for that
         const int kcap = (int)(kmax < ell ? kmax : ell);
         const bool xv = m % 4 == 0 && reinterpret_cast<uintptr_t>(Xd) % 16 == 0;
+        // from the whole tensor's face count, so that face groups (the
+        // allocation-free entry point, the learned buckets) sum every face's
+        // partials in the same order as one call on all faces
+        const int nsp = resid_splits(X->n3, mparts, p);
+        const dim3 gr(xcd_grid(mparts * nsp, nf));
 #define TSVDM_RESID(KP)                                                                                        \
     do {                                                                                                      \
         if (xv)                                                                                               \
-            TSVDM_LAUNCH("resid_factors", (k_resid<KP, true>), gm, dim3(GT), 0, s, Xd, m, p, nf,              \
+            TSVDM_LAUNCH("resid_factors", (k_resid<KP, true>), gr, dim3(GT), 0, s, Xd, m, p, nf,              \
                          (const float *)Uo, (const double *)So, (const float *)Vo, kmax, (const int32_t *)ranks, \
-                         w.cert_part, fmap);                                                                  \
+                         w.cert_part, fmap, nsp);                                                             \
         else                                                                                                  \
-            TSVDM_LAUNCH("resid_factors", (k_resid<KP, false>), gm, dim3(GT), 0, s, Xd, m, p, nf,             \
+            TSVDM_LAUNCH("resid_factors", (k_resid<KP, false>), gr, dim3(GT), 0, s, Xd, m, p, nf,             \
                          (const float *)Uo, (const double *)So, (const float *)Vo, kmax, (const int32_t *)ranks, \
-                         w.cert_part, fmap);                                                                  \
+                         w.cert_part, fmap, nsp);                                                             \
     } while (0)
         if (kcap <= 16) TSVDM_RESID(16);
         else if (kcap <= 32) TSVDM_RESID(32);
@@ -2489,7 +2514,7 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
         else TSVDM_RESID(64);
 #undef TSVDM_RESID
         TSVDM_LAUNCH("cert", k_cert, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s,
-                     (const double *)w.cert_part, mparts, nf, cert, fmap);
+                     (const double *)w.cert_part, mparts * nsp, nf, cert, fmap);
     }
     TSVDM_LAUNCH_CHECK("mixed truncate");
     return TSVDM_OK;
@@ -2530,7 +2555,7 @@ tsvdm_status run_cplx_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o,
     w.gram_p += g0 * pparts * L2 * L2;
     w.fro_part += g0 * mparts;
     w.res_part += g0 * pparts;
-    w.cert_part += g0 * mparts;
+    w.cert_part += g0 * mparts * kResidSplitMax;
     w.UB += g0 * L2 * L2;
     w.sig += g0 * L2;
     w.fro2 += g0;
@@ -2755,11 +2780,11 @@ tsvdm_status run_f64rand(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, ts
         if (xv)                                                                                                 \
             TSVDM_LAUNCH("f64_resid_factors", (k_resid<KP, true, double>), gm, dim3(GT), 0, s, Xd, m, p, nf,    \
                          (const double *)Uo, (const double *)F->S, (const double *)Vo, kmax,                   \
-                         (const int32_t *)F->ranks, w.cert_part, (const int32_t *)nullptr);                    \
+                         (const int32_t *)F->ranks, w.cert_part, (const int32_t *)nullptr, 1);                 \
         else                                                                                                    \
             TSVDM_LAUNCH("f64_resid_factors", (k_resid<KP, false, double>), gm, dim3(GT), 0, s, Xd, m, p, nf,   \
                          (const double *)Uo, (const double *)F->S, (const double *)Vo, kmax,                   \
-                         (const int32_t *)F->ranks, w.cert_part, (const int32_t *)nullptr);                    \
+                         (const int32_t *)F->ranks, w.cert_part, (const int32_t *)nullptr, 1);                 \
     } while (0)
         if (kcap <= 16) TSVDM_RESID64(16);
         else if (kcap <= 32) TSVDM_RESID64(32);

@@ -214,3 +214,25 @@ def test_mixed_rows_over_several_qr_chunks():
     true = np.array([np.linalg.norm(Xh64[:, :, f] - That[:, :, f]) for f in range(nf)])
     np.testing.assert_allclose(got["cert"], true, rtol=1e-9, atol=1e-14 * np.max(got["fro"]))
 
+
+
+def test_certificate_of_few_wide_faces_split_over_columns():
+    """Two 130 x 9000 faces: 6 row blocks in all, so the certificate pass
+    splits each face's columns over 32 ranges (a workgroup each) and sums
+    the partials in order.  The certificate still equals the error of the
+    returned factors against the faces (FP64 on the host), and the
+    truncation agrees with the oracle's randomized one at 1e-4."""
+    m, p, k, os_ = 130, 9000, 12, 8
+    Xh32, _ = _decaying_faces(m, p, [1 / 4, 1 / 6], 40, salt=95)
+    nf = Xh32.shape[2]
+    Omega = synth.gaussian(synth.rng(1, 96), (p, k + os_)).astype(np.float32)
+    tr = api.Truncator(m, p, nf, torch.float32, k=k, precision=C.PREC_MIXED, oversample=os_, power_iters=1,
+                       omega=to_dev(Omega))
+    got = _factors(tr(to_dev(Xh32)), nf)
+    assert np.all(got["ranks"] == k) and np.all(got["info"] == 0)
+    Xh64 = Xh32.astype(np.float64)
+    That = reconstruct(got["U"], got["S"], got["V"], got["ranks"])
+    true = np.array([np.linalg.norm(Xh64[:, :, f] - That[:, :, f]) for f in range(nf)])
+    np.testing.assert_allclose(got["cert"], true, rtol=1e-9, atol=1e-14 * np.max(got["fro"]))
+    rnd = oracle.randomized_tsvdm_faces(Xh64, Omega.astype(np.float64), k, 1)
+    assert relerr(That, rnd["That"]) < 1e-4
