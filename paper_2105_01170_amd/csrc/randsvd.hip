@@ -2374,11 +2374,13 @@ tsvdm_status side_streams(SideStreams **out) {
 // X Omega[:, :32] with its width-32 Gram partials, taken once for all faces
 // (indexed by face); a group of width 16 or 32 then starts from its first
 // columns instead of a sketch pass.  kcap_face: per-face energy-rule caps.
+// mark: recorded on s once the group's first pass over X (the sketch) has been
+// enqueued (the start of a second group on another stream).
 template <int LP>
 tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
                        const MixedWs &w0, int f0, int nfg, hipStream_t s,
                        const int32_t *fmap = nullptr, int wf0 = -1, const MixedWs *src = nullptr,
-                       const int32_t *kcap_face = nullptr) {
+                       const int32_t *kcap_face = nullptr, hipEvent_t mark = nullptr) {
     const int m = (int)X->m, p = (int)X->p, ell = o->k + o->oversample;
     const int mparts = (m + 63) / 64, pparts = (p + 63) / 64;
     const int64_t kmax = F->kmax;
@@ -2427,15 +2429,24 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
             TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true, false>), gm, dim3(GT), 0, s, Xd, m, p,    \
                          nf, o->omega, (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m, fmap);                 \
     } while (0)
+#define TSVDM_MARK()                                                                                        \
+    do {                                                                                                    \
+        if (mark) {                                                                                         \
+            hipError_t e_ = hipEventRecord(mark, s);                                                        \
+            if (e_ != hipSuccess) return hip_check(e_, "mixed truncate: group mark");                       \
+        }                                                                                                   \
+    } while (0)
     const bool reuse = power && src && LP <= 32 && ell <= 32;
     if (power) {
         if (reuse) {
             // the sketch's first ell columns were taken once for all faces
             TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)src->Y, m, ell,
                          w.Qm, 1, (const double *)src->gram_m, mparts, w.qr_info, 1, fmap, 1, 32);
+            TSVDM_MARK();
         } else {
             // pass 1: sketch Y = X Omega (BF16), ||X||^2, Gram partials of Y
             TSVDM_SKETCH();
+            TSVDM_MARK();
             // basis of the sketch: one shifted Cholesky-QR step (its span is what
             // the power step needs)
             TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell,
@@ -2461,7 +2472,9 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
                          (const float *)w.Qp, (int64_t)p * LP, p, ell, w.Y, fp3, w.gram_m, fmap);
     } else {
         TSVDM_SKETCH();
+        TSVDM_MARK();
     }
+#undef TSVDM_MARK
 #undef TSVDM_SKETCH
     // final basis: FP64 shifted Cholesky-QR2 (first Gram from the partials)
     TSVDM_LAUNCH("cholqr_final", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell, w.Qm,
@@ -2520,12 +2533,41 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     return TSVDM_OK;
 }
 
+bool side_streams_created(SideStreams **out);
+
+// Two face groups, as for complex faces (run_cplx): the second half of the
+// faces runs on a side stream, started once the first half's sketch pass has
+// finished, so that each group's latency-bound per-face FP64 kernels (one
+// workgroup per face) run beside the other group's passes over X; the
+// caller's stream then waits for the side stream.  One group for fewer than
+// 32 faces, or when s is being captured and the side streams do not exist
+// yet.  The workspace is carved for the whole tensor and every group uses its
+// faces' part of it; the results do not depend on the grouping.
 template <int LP>
 tsvdm_status run_mixed(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
                        void *wsp, hipStream_t s) {
     MixedWs w;
     carve(reinterpret_cast<char *>(wsp), X->m, X->p, X->n3, LP, &w);
-    return run_group<LP>(X, o, F, w, 0, (int)X->n3, s);
+    const int nf = (int)X->n3;
+    SideStreams *ss = nullptr;
+    bool split = nf >= 32;
+    if (split) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        hipError_t e = hipStreamIsCapturing(s, &cs);
+        if (e != hipSuccess) return hip_check(e, "mixed truncate: capture status");
+        split = cs == hipStreamCaptureStatusNone ? side_streams(&ss) == TSVDM_OK : side_streams_created(&ss);
+    }
+    if (!split) return run_group<LP>(X, o, F, w, 0, nf, s);
+    const int g0 = (nf + 1) / 2;
+    tsvdm_status st = run_group<LP>(X, o, F, w, 0, g0, s, nullptr, -1, nullptr, nullptr, ss->ev[2]);
+    if (st != TSVDM_OK) return st;
+    hipStream_t sb = ss->s[0];
+    hipError_t e = hipStreamWaitEvent(sb, ss->ev[2], 0);
+    if (e != hipSuccess) return hip_check(e, "mixed truncate: fork");
+    if ((st = run_group<LP>(X, o, F, w, g0, nf - g0, sb)) != TSVDM_OK) return st;
+    if ((e = hipEventRecord(ss->ev[3], sb)) != hipSuccess) return hip_check(e, "mixed truncate: join");
+    if ((e = hipStreamWaitEvent(s, ss->ev[3], 0)) != hipSuccess) return hip_check(e, "mixed truncate: join");
+    return TSVDM_OK;
 }
 
 // ---------------------------------------------------------------- complex faces

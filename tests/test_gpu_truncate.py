@@ -154,6 +154,66 @@ def test_mixed_truncation_below_rank():
     np.testing.assert_allclose(cert, true, rtol=1e-9, atol=1e-14 * np.max(fro))
 
 
+@pytest.mark.parametrize("mode", ["fixed", "energy"])
+def test_mixed_two_face_groups_equal_separate_calls(mode):
+    """40 faces take the two-group schedule (the second half of the faces on a
+    side stream, started after the first half's sketch): every output equals,
+    bit for bit, two separate calls on the first and last 20 faces (one group
+    each), eagerly and in every replay of a captured graph."""
+    m, p, k, os_, nf = 72, 56, 12, 8, 40
+    g = synth.rng(5, 77)
+    faces = []
+    for f in range(nf):  # face f: sigma_j = 10^(-r_f j), r_f from 0.2 to 1.3
+        U, _ = np.linalg.qr(synth.gaussian(g, (m, p)))
+        V, _ = np.linalg.qr(synth.gaussian(g, (p, p)))
+        faces.append((U * 10.0 ** (-(0.2 + 1.1 * f / (nf - 1)) * np.arange(p))) @ V.T)
+    Xh = np.asfortranarray(np.stack(faces, axis=2).astype(np.float32))
+    Omega = synth.gaussian(synth.rng(5, 78), (p, k + os_)).astype(np.float32)
+    omega = to_dev(Omega, np.float32)
+    kw = dict(rank_mode=C.RANK_FIXED, k=k) if mode == "fixed" else dict(rank_mode=C.RANK_ENERGY, k=k, tau=1e-2)
+
+    def truncator(n):
+        return api.Truncator(m, p, n, torch.float32, precision=C.PREC_MIXED, oversample=os_,
+                             power_iters=1, omega=omega, **kw)
+
+    xd = to_dev(Xh, np.float32)
+    tr = truncator(nf)
+    F = tr(xd)
+    torch.cuda.synchronize()
+    got = _gpu_factors(F, nf)
+    half = nf // 2
+    parts = []
+    for lo in (0, half):
+        t = truncator(half)
+        parts.append(_gpu_factors(t(to_dev(np.asfortranarray(Xh[:, :, lo:lo + half]), np.float32)), half))
+    for i, key in enumerate(("U", "S", "V", "ranks", "cert", "fro", "info")):
+        joined = np.concatenate([parts[0][i], parts[1][i]], axis=-1)
+        assert np.array_equal(got[i], joined), key
+    if mode == "energy":
+        assert len(np.unique(got[3])) > 1  # the faces' ranks differ
+    outs = (F.U, F.S, F.V, F.ranks, F.cert, F.fro, F.info)
+    ref = [t.clone() for t in outs]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        tr(xd, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        tr(xd)
+    for rep in range(3):
+        for t in outs:
+            t.fill_(-7)
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(outs, ref):
+            assert torch.equal(a, b), rep
+        del junk
+
+
 def test_mixed_step_graph_replays_match_eager():
     """The transform and the mixed truncation (launches only: no host
     synchronisation, allocation or memset) captured in a graph give, on every
