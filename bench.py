@@ -1185,15 +1185,19 @@ def mlp_widths(y):
 # Launch sequence of one step of each profiled workload: (launch name as the
 # library's timing table names it, kernel name in a rocprofv3 -T trace).
 STEP_PATTERNS = {
-    "mixed": [("transform_fft", "k_fft_tubes"), ("sketch_xw_bf16", "k_xw"), ("cholqr_sketch", "k_cholqr"),
-              ("power_xtw_bf16", "k_xtw"), ("cholqr_power_z", "k_cholqr"), ("power_xw_split", "k_xw"),
-              ("cholqr_final", "k_cholqr"), ("project_xtw_split", "k_xtw"), ("core_gram_eig", "k_core"),
-              ("factors", "k_factors"), ("resid_factors", "k_resid"), ("cert", "k_cert")],
-    "f64rand": [("transform_fft", "k_fft_tubes"), ("f64_sketch_xw", "k_xw64"), ("f64_cholqr_sketch", "k_cholqr"),
-                ("f64_power_xtw", "k_xtw64"), ("f64_cholqr_power_z", "k_cholqr"), ("f64_power_xw", "k_xw64"),
-                ("f64_cholqr_final", "k_cholqr"), ("f64_project_xtw", "k_xtw64"),
-                ("f64_core_gram_eig", "k_core"), ("f64_factors", "k_factors"),
-                ("f64_resid_factors", "k_resid"), ("f64_cert", "k_cert")],
+    # two face groups (the second on a side stream), each the same launch sequence
+    "mixed": [("transform_fft", "k_fft_tubes")] + [
+        (name + ("" if g == 0 else " (2nd group)"), kern) for g in range(2) for name, kern in (
+            ("sketch_xw_bf16", "k_xw"), ("cholqr_sketch", "k_cholqr"), ("power_xtw_bf16", "k_xtw"),
+            ("cholqr_power_z", "k_cholqr"), ("power_xw_split", "k_xw"), ("cholqr_final", "k_cholqr"),
+            ("project_xtw_split", "k_xtw"), ("core_gram_eig", "k_core"), ("factors", "k_factors"),
+            ("resid_factors", "k_resid"), ("cert", "k_cert"))],
+    "f64rand": [("transform_fft", "k_fft_tubes")] + [
+        (name + ("" if g == 0 else " (2nd group)"), kern) for g in range(2) for name, kern in (
+            ("f64_sketch_xw", "k_xw64"), ("f64_cholqr_sketch", "k_cholqr"), ("f64_power_xtw", "k_xtw64"),
+            ("f64_cholqr_power_z", "k_cholqr"), ("f64_power_xw", "k_xw64"), ("f64_cholqr_final", "k_cholqr"),
+            ("f64_project_xtw", "k_xtw64"), ("f64_core_gram_eig", "k_core"), ("f64_factors", "k_factors"),
+            ("f64_resid_factors", "k_resid"), ("f64_cert", "k_cert"))],
     # two face groups (the second on a side stream), each the same launch sequence
     "dft": [("transform_fft", "k_fft_tubes")] + [
         (name + ("" if g == 0 else " (2nd group)"), kern) for g in range(2) for name, kern in (
@@ -1292,7 +1296,15 @@ def profile_summary(args):
     tbytes = {l: 1024.0 * (fetch[l] * sf + write[l] * sw) for l in launches}
     alg = {}
     if args.pattern == "mixed":
-        alg = {l: b for l, (kind, b) in algorithmic_work(M_, P_, N3, K + OS, K).items() if kind == "hbm"}
+        # per launch: the transform covers the step, each group's launch its half of the faces
+        share = ((N3 + 1) // 2 / N3, (N3 - (N3 + 1) // 2) / N3)
+        for l, (kind, b) in algorithmic_work(M_, P_, N3, K + OS, K).items():
+            if kind != "hbm":
+                continue
+            if l == "transform_fft":
+                alg[l] = b
+            else:
+                alg[l], alg[l + " (2nd group)"] = b * share[0], b * share[1]
     elif args.pattern == "dft":
         # per launch: the transform covers the step, each group's launch its share of the 129 faces
         nh = N3 // 2 + 1
@@ -1308,9 +1320,14 @@ def profile_summary(args):
     elif args.pattern == "f64rand":
         X8 = 8.0 * M_ * P_ * N3
         pan = 8.0 * (M_ + P_) * (K + OS) * N3
-        alg = {"transform_fft": 2 * 4.0 * M_ * P_ * N3 * 2, "f64_sketch_xw": X8 + 8.0 * M_ * (K + OS) * N3,
-               "f64_power_xtw": X8 + pan, "f64_power_xw": X8 + pan, "f64_project_xtw": X8 + pan,
-               "f64_factors": 8.0 * (M_ + P_) * (2 * K + OS) * N3, "f64_resid_factors": X8 + 8.0 * (M_ + P_) * K * N3}
+        per_step = {"f64_sketch_xw": X8 + 8.0 * M_ * (K + OS) * N3, "f64_power_xtw": X8 + pan,
+                    "f64_power_xw": X8 + pan, "f64_project_xtw": X8 + pan,
+                    "f64_factors": 8.0 * (M_ + P_) * (2 * K + OS) * N3, "f64_resid_factors": X8 + 8.0 * (M_ + P_) * K * N3}
+        # per launch: each group's launch its half of the faces
+        share = ((N3 + 1) // 2 / N3, (N3 - (N3 + 1) // 2) / N3)
+        alg = {"transform_fft": 2 * 4.0 * M_ * P_ * N3 * 2}
+        for l, b in per_step.items():
+            alg[l], alg[l + " (2nd group)"] = b * share[0], b * share[1]
     mfma = None
     if args.mfma_dir:
         disp = _pmc_dispatches(args.mfma_dir)
@@ -1566,10 +1583,14 @@ def main():
         # the FP64 passes: 2 m p l flops on FP64 MFMA per face, X read once (8 m p bytes)
         fl = 2.0 * m * p * ell * n3
         by = 8.0 * m * p * n3
-        passes64 = {nm: {"fp64_mfma_frac": round(fl / (us * 1e-6) / 1e12 / FP64_PEAK_TFLOPS, 4),
-                         "hbm_frac": round(by / (us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
-                    for nm, us in k64.items() if nm in ("f64_sketch_xw", "f64_power_xtw", "f64_power_xw",
-                                                        "f64_project_xtw")}
+        # (a step's work is split over its launches, one per face group)
+        passes64 = {}
+        for nm, (nl, ms) in t64.items():
+            if nm in ("f64_sketch_xw", "f64_power_xtw", "f64_power_xw", "f64_project_xtw"):
+                sec = ms / nl / 1e3
+                share = nrep / nl
+                passes64[nm] = {"fp64_mfma_frac": round(fl * share / sec / 1e12 / FP64_PEAK_TFLOPS, 4),
+                                "hbm_frac": round(by * share / sec / 1e9 / HBM_PEAK_GBS, 4)}
         fp64r = {"value": n3 / (msr / 1e3), "unit": "faces/s", "ms_per_step": msr,
                  "what": "FP64 randomized t-SVDM of the FP64 input (PREC_F64_RAND): same Omega, k, "
                          "oversampling and power iteration, FP64 MFMA products, FP64 Cholesky-QR2 at every "

@@ -2771,23 +2771,44 @@ tsvdm_status run_cplx(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm
 // stored factors as in the mixed path (or, without certify, the estimate
 // sqrt(||X||^2 - sum_{j<=k} lambda_j)).
 constexpr double kJacobiTolF64 = 1e-15;
+// The faces f0 .. f0+nfg-1 (the workspace w0 carved for the whole tensor);
+// mark as in run_group.
 template <int LP>
-tsvdm_status run_f64rand(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F, void *wsp,
-                         hipStream_t s) {
-    const int m = (int)X->m, p = (int)X->p, nf = (int)X->n3, ell = o->k + o->oversample;
+tsvdm_status run_f64rand_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F,
+                               const MixedWs &w0, int f0, int nfg, hipStream_t s, hipEvent_t mark) {
+    const int m = (int)X->m, p = (int)X->p, nf = nfg, ell = o->k + o->oversample;
     const int mparts = (m + 63) / 64, pparts = (p + 63) / 64;
-    const int64_t kmax = F->kmax;
-    MixedWs w;
-    carve(reinterpret_cast<char *>(wsp), m, p, nf, LP, &w, 8);
-    double *Y = reinterpret_cast<double *>(w.Y), *Qm = reinterpret_cast<double *>(w.Qm);
-    double *Z = reinterpret_cast<double *>(w.Z), *Qp = reinterpret_cast<double *>(w.Qp);
-    const double *Xd = reinterpret_cast<const double *>(X->data);
-    double *Uo = reinterpret_cast<double *>(F->U), *Vo = reinterpret_cast<double *>(F->V);
+    const int64_t kmax = F->kmax, g0 = f0;
+    MixedWs w = w0;
+    double *Y = reinterpret_cast<double *>(w.Y) + g0 * m * LP, *Qm = reinterpret_cast<double *>(w.Qm) + g0 * m * LP;
+    double *Z = reinterpret_cast<double *>(w.Z) + g0 * p * LP, *Qp = reinterpret_cast<double *>(w.Qp) + g0 * p * LP;
+    w.gram_m += g0 * mparts * LP * LP;
+    w.gram_p += g0 * pparts * LP * LP;
+    w.fro_part += g0 * mparts;
+    w.cert_part += g0 * mparts * kResidSplitMax;
+    w.UB += g0 * LP * LP;
+    w.sig += g0 * LP;
+    w.fro2 += g0;
+    w.perm += g0 * LP;
+    w.kf += g0;
+    w.qr_info += g0;
+    w.jinfo += g0;
+    const double *Xd = reinterpret_cast<const double *>(X->data) + g0 * m * p;
+    double *Uo = reinterpret_cast<double *>(F->U) + g0 * m * kmax, *Vo = reinterpret_cast<double *>(F->V) + g0 * p * kmax;
+    double *So = F->S + g0 * kmax;
+    int32_t *ranks = F->ranks + g0;
+    double *cert = F->cert ? F->cert + g0 : nullptr;
+    double *fro = F->fro ? F->fro + g0 : nullptr;
+    int32_t *info = F->info ? F->info + g0 : nullptr;
     const dim3 gm(xcd_grid(mparts, nf)), gp(xcd_grid(pparts, nf));
     const bool power = o->power_iters > 0;
-    const bool exact = o->certify && F->cert;
+    const bool exact = o->certify && cert;
     TSVDM_LAUNCH("f64_sketch_xw", (k_xw64<LP, float, true>), gm, dim3(GT), 0, s, Xd, m, p, nf, o->omega,
                  (int64_t)0, p, ell, Y, w.fro_part, w.gram_m);
+    if (mark) {
+        hipError_t e = hipEventRecord(mark, s);
+        if (e != hipSuccess) return hip_check(e, "FP64 randomized truncate: group mark");
+    }
     if (power) {
         // both intermediate bases are made orthonormal (two passes): a single
         // shifted pass leaves columns of norm ~sqrt(shift) along directions
@@ -2809,11 +2830,11 @@ tsvdm_status run_f64rand(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, ts
     const int msw = o->max_sweeps > 0 ? o->max_sweeps : 30;
     TSVDM_LAUNCH("f64_core_gram_eig", (k_core<LP>), dim3(nf), dim3(QT), 0, s, (const double *)w.gram_p, pparts,
                  ell, (const double *)w.fro_part, mparts, (const double *)nullptr, -1, o->rank_mode, o->k, o->tau,
-                 msw, kJacobiTolF64, w.UB, w.sig, w.perm, w.kf, w.fro2, exact ? (double *)nullptr : F->cert,
+                 msw, kJacobiTolF64, w.UB, w.sig, w.perm, w.kf, w.fro2, exact ? (double *)nullptr : cert,
                  w.jinfo, (const int32_t *)nullptr);
     TSVDM_LAUNCH("f64_factors", (k_factors<LP, double>), dim3((unsigned)(mparts + pparts), nf), dim3(GT), 0, s,
                  (const double *)Qm, (const double *)Z, m, p, ell, kmax, w.UB, w.sig, w.perm, w.kf, w.fro2,
-                 w.qr_info, w.jinfo, Uo, F->S, Vo, F->ranks, F->fro, F->info, (const int32_t *)nullptr);
+                 w.qr_info, w.jinfo, Uo, So, Vo, ranks, fro, info, (const int32_t *)nullptr);
     if (exact) {
         const int kcap = (int)(kmax < ell ? kmax : ell);
         const bool xv = m % 4 == 0 && reinterpret_cast<uintptr_t>(Xd) % 16 == 0;
@@ -2821,12 +2842,12 @@ tsvdm_status run_f64rand(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, ts
     do {                                                                                                        \
         if (xv)                                                                                                 \
             TSVDM_LAUNCH("f64_resid_factors", (k_resid<KP, true, double>), gm, dim3(GT), 0, s, Xd, m, p, nf,    \
-                         (const double *)Uo, (const double *)F->S, (const double *)Vo, kmax,                   \
-                         (const int32_t *)F->ranks, w.cert_part, (const int32_t *)nullptr, 1);                 \
+                         (const double *)Uo, (const double *)So, (const double *)Vo, kmax,                      \
+                         (const int32_t *)ranks, w.cert_part, (const int32_t *)nullptr, 1);                    \
         else                                                                                                    \
             TSVDM_LAUNCH("f64_resid_factors", (k_resid<KP, false, double>), gm, dim3(GT), 0, s, Xd, m, p, nf,   \
-                         (const double *)Uo, (const double *)F->S, (const double *)Vo, kmax,                   \
-                         (const int32_t *)F->ranks, w.cert_part, (const int32_t *)nullptr, 1);                 \
+                         (const double *)Uo, (const double *)So, (const double *)Vo, kmax,                      \
+                         (const int32_t *)ranks, w.cert_part, (const int32_t *)nullptr, 1);                    \
     } while (0)
         if (kcap <= 16) TSVDM_RESID64(16);
         else if (kcap <= 32) TSVDM_RESID64(32);
@@ -2834,9 +2855,37 @@ tsvdm_status run_f64rand(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, ts
         else TSVDM_RESID64(64);
 #undef TSVDM_RESID64
         TSVDM_LAUNCH("f64_cert", k_cert, dim3((unsigned)((nf + 255) / 256)), dim3(256), 0, s,
-                     (const double *)w.cert_part, mparts, nf, F->cert, (const int32_t *)nullptr);
+                     (const double *)w.cert_part, mparts, nf, cert, (const int32_t *)nullptr);
     }
     TSVDM_LAUNCH_CHECK("FP64 randomized truncate");
+    return TSVDM_OK;
+}
+
+// Two face groups on two streams, as in run_mixed (the same conditions).
+template <int LP>
+tsvdm_status run_f64rand(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm_factors *F, void *wsp,
+                         hipStream_t s) {
+    MixedWs w;
+    carve(reinterpret_cast<char *>(wsp), X->m, X->p, X->n3, LP, &w, 8);
+    const int nf = (int)X->n3;
+    SideStreams *ss = nullptr;
+    bool split = nf >= 32;
+    if (split) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        hipError_t e = hipStreamIsCapturing(s, &cs);
+        if (e != hipSuccess) return hip_check(e, "FP64 randomized truncate: capture status");
+        split = cs == hipStreamCaptureStatusNone ? side_streams(&ss) == TSVDM_OK : side_streams_created(&ss);
+    }
+    if (!split) return run_f64rand_group<LP>(X, o, F, w, 0, nf, s, nullptr);
+    const int g0 = (nf + 1) / 2;
+    tsvdm_status st = run_f64rand_group<LP>(X, o, F, w, 0, g0, s, ss->ev[2]);
+    if (st != TSVDM_OK) return st;
+    hipStream_t sb = ss->s[0];
+    hipError_t e = hipStreamWaitEvent(sb, ss->ev[2], 0);
+    if (e != hipSuccess) return hip_check(e, "FP64 randomized truncate: fork");
+    if ((st = run_f64rand_group<LP>(X, o, F, w, g0, nf - g0, sb, nullptr)) != TSVDM_OK) return st;
+    if ((e = hipEventRecord(ss->ev[3], sb)) != hipSuccess) return hip_check(e, "FP64 randomized truncate: join");
+    if ((e = hipStreamWaitEvent(s, ss->ev[3], 0)) != hipSuccess) return hip_check(e, "FP64 randomized truncate: join");
     return TSVDM_OK;
 }
 

@@ -167,3 +167,23 @@ def test_f64rand_headline_tensor_against_exact_truncation():
     ex = oracle.tsvdm_truncate_faces(np.asfortranarray(Xh[:, :, sample]), "fixed", k)
     assert relerr(That[:, :, sample], ex["That"]) < 1e-10
     assert np.max(got["cert"] / got["fro"]) < 1e-12
+
+
+@pytest.mark.parametrize("mode", [C.RANK_FIXED, C.RANK_ENERGY])
+def test_f64rand_two_face_groups_equal_separate_calls(mode):
+    """40 faces take the two-group schedule (the second half on a side
+    stream): every output equals, bit for bit, two separate calls on the
+    first and last 20 faces (one group each)."""
+    nf = 40
+    rhos = [0.05 + 0.01 * f for f in range(nf)]
+    Xh = _faces(72, 56, rhos, 40, salt=91, noise=1e-9)
+    tau = 1e-3 if mode == C.RANK_ENERGY else 0.0
+    got, _ = _run(Xh, 12, 8, 1, mode=mode, tau=tau, salt=92)
+    half = nf // 2
+    parts = [_run(np.asfortranarray(Xh[:, :, lo:lo + half]), 12, 8, 1, mode=mode, tau=tau, salt=92)[0]
+             for lo in (0, half)]
+    for key in ("U", "S", "V", "ranks", "cert", "fro", "info"):
+        joined = np.concatenate([parts[0][key], parts[1][key]], axis=-1)
+        assert np.array_equal(got[key], joined), key
+    if mode == C.RANK_ENERGY:
+        assert len(np.unique(got["ranks"])) > 1
