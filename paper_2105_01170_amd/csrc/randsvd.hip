@@ -2535,12 +2535,20 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
 
 bool side_streams_created(SideStreams **out);
 
+// Whether a randomized truncation runs its faces in two groups (below): at
+// least 32 faces and 128 MiB of face data.  The second group starts one
+// sketch pass late, and the split pays only when the passes over X it hides
+// under the other group's per-face FP64 kernels are long: 256 faces of 512^2
+// FP32 (256 MiB) ran 4-5% faster in two groups, 64 such faces 2% slower and
+// 127 faces of 64^2 6% slower.
+inline bool split_pays(int64_t nf, int64_t bytes) { return nf >= 32 && bytes >= ((int64_t)128 << 20); }
+
 // Two face groups, as for complex faces (run_cplx): the second half of the
 // faces runs on a side stream, started once the first half's sketch pass has
 // finished, so that each group's latency-bound per-face FP64 kernels (one
 // workgroup per face) run beside the other group's passes over X; the
-// caller's stream then waits for the side stream.  One group for fewer than
-// 32 faces, or when s is being captured and the side streams do not exist
+// caller's stream then waits for the side stream.  One group unless
+// split_pays, or when s is being captured and the side streams do not exist
 // yet.  The workspace is carved for the whole tensor and every group uses its
 // faces' part of it; the results do not depend on the grouping.
 template <int LP>
@@ -2550,7 +2558,7 @@ tsvdm_status run_mixed(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     carve(reinterpret_cast<char *>(wsp), X->m, X->p, X->n3, LP, &w);
     const int nf = (int)X->n3;
     SideStreams *ss = nullptr;
-    bool split = nf >= 32;
+    bool split = split_pays(nf, 4 * X->m * X->p * X->n3);
     if (split) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         hipError_t e = hipStreamIsCapturing(s, &cs);
@@ -2733,7 +2741,7 @@ bool side_streams_created(SideStreams **out) {
 // a group leave most CUs idle, so the second group runs on a side stream,
 // started once the first group's sketch pass has finished, and its passes
 // over X fill those CUs (and the other way round); the caller's stream then
-// waits for it.  One group for a few faces, or when the side streams do not
+// waits for it.  One group unless split_pays, or when the side streams do not
 // exist yet and s is being captured (creating them would break the capture).
 // The results do not depend on the grouping: every kernel works face by face.
 template <int LP>
@@ -2743,7 +2751,7 @@ tsvdm_status run_cplx(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvdm
     MixedWs w;
     carve(reinterpret_cast<char *>(wsp), 2 * m, p, nf, 2 * LP, &w, 4, (std::max(m, p) + CGR - 1) / CGR);
     SideStreams *ss = nullptr;
-    bool split = nf >= 32;
+    bool split = split_pays(nf, 8 * X->m * X->p * X->n3);
     if (split) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         hipError_t e = hipStreamIsCapturing(s, &cs);
@@ -2869,7 +2877,7 @@ tsvdm_status run_f64rand(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, ts
     carve(reinterpret_cast<char *>(wsp), X->m, X->p, X->n3, LP, &w, 8);
     const int nf = (int)X->n3;
     SideStreams *ss = nullptr;
-    bool split = nf >= 32;
+    bool split = split_pays(nf, 8 * X->m * X->p * X->n3);
     if (split) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
         hipError_t e = hipStreamIsCapturing(s, &cs);

@@ -324,11 +324,12 @@ def test_complex_path_graph_replays_match_eager():
 
 
 def test_complex_two_face_groups_equal_separate_calls():
-    """40 faces take the two-group schedule (the second group on a side
-    stream): every output equals, bit for bit, two separate calls on the
-    first and last 20 faces (one group each), in eager mode and in every
-    replay of a captured graph."""
-    m, p, k, os_, nf = 64, 56, 8, 8, 40
+    """40 complex faces of 768 x 560 (137.6 MB, past the 128 MiB from which
+    the faces run in two groups, the second on a side stream): every output
+    equals, bit for bit, two separate calls on the first and last 20 faces
+    (one group each), in eager mode and in every replay of a captured graph."""
+    m, p, k, os_, nf = 768, 560, 8, 8, 40
+    assert 8 * m * p * nf >= 128 << 20 > 8 * m * p * (nf // 2)
     spectra = [10.0 ** (-(0.1 + 0.02 * f) * np.arange(1, 33)) for f in range(nf)]
     Xh = _complex_faces(m, p, spectra, salt=83)
     Omega = synth.gaussian(synth.rng(2, 84), (p, k + os_)).astype(np.float32)

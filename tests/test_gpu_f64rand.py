@@ -171,12 +171,14 @@ def test_f64rand_headline_tensor_against_exact_truncation():
 
 @pytest.mark.parametrize("mode", [C.RANK_FIXED, C.RANK_ENERGY])
 def test_f64rand_two_face_groups_equal_separate_calls(mode):
-    """40 faces take the two-group schedule (the second half on a side
-    stream): every output equals, bit for bit, two separate calls on the
-    first and last 20 faces (one group each)."""
-    nf = 40
+    """40 FP64 faces of 512 x 840 (137.6 MB, past the 128 MiB from which the
+    faces run in two groups, the second half on a side stream): every output
+    equals, bit for bit, two separate calls on the first and last 20 faces
+    (one group each)."""
+    nf, m, p = 40, 512, 840
+    assert 8 * m * p * nf >= 128 << 20 > 8 * m * p * (nf // 2)
     rhos = [0.05 + 0.01 * f for f in range(nf)]
-    Xh = _faces(72, 56, rhos, 40, salt=91, noise=1e-9)
+    Xh = _faces(m, p, rhos, 40, salt=91, noise=1e-9)
     tau = 1e-3 if mode == C.RANK_ENERGY else 0.0
     got, _ = _run(Xh, 12, 8, 1, mode=mode, tau=tau, salt=92)
     half = nf // 2

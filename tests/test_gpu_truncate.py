@@ -156,18 +156,19 @@ def test_mixed_truncation_below_rank():
 
 @pytest.mark.parametrize("mode", ["fixed", "energy"])
 def test_mixed_two_face_groups_equal_separate_calls(mode):
-    """40 faces take the two-group schedule (the second half of the faces on a
-    side stream, started after the first half's sketch): every output equals,
-    bit for bit, two separate calls on the first and last 20 faces (one group
-    each), eagerly and in every replay of a captured graph."""
-    m, p, k, os_, nf = 72, 56, 12, 8, 40
+    """40 faces of 1024 x 840 (137.6 MB, past the 128 MiB from which the
+    faces run in two groups: the second half on a side stream, started after
+    the first half's sketch): every output equals, bit for bit, two separate
+    calls on the first and last 20 faces (68.8 MB each, one group), eagerly
+    and in every replay of a captured graph."""
+    m, p, k, os_, nf, r = 1024, 840, 12, 8, 40, 56
+    assert 4 * m * p * nf >= 128 << 20 > 4 * m * p * (nf // 2)
     g = synth.rng(5, 77)
-    faces = []
-    for f in range(nf):  # face f: sigma_j = 10^(-r_f j), r_f from 0.2 to 1.3
-        U, _ = np.linalg.qr(synth.gaussian(g, (m, p)))
-        V, _ = np.linalg.qr(synth.gaussian(g, (p, p)))
-        faces.append((U * 10.0 ** (-(0.2 + 1.1 * f / (nf - 1)) * np.arange(p))) @ V.T)
-    Xh = np.asfortranarray(np.stack(faces, axis=2).astype(np.float32))
+    Xh = np.empty((m, p, nf), dtype=np.float32, order="F")
+    for f in range(nf):  # face f: sigma_j = 10^(-r_f j), r_f from 0.2 to 1.3, rank 56
+        U, _ = np.linalg.qr(synth.gaussian(g, (m, r)))
+        V, _ = np.linalg.qr(synth.gaussian(g, (p, r)))
+        Xh[:, :, f] = (U * 10.0 ** (-(0.2 + 1.1 * f / (nf - 1)) * np.arange(r))) @ V.T
     Omega = synth.gaussian(synth.rng(5, 78), (p, k + os_)).astype(np.float32)
     omega = to_dev(Omega, np.float32)
     kw = dict(rank_mode=C.RANK_FIXED, k=k) if mode == "fixed" else dict(rank_mode=C.RANK_ENERGY, k=k, tau=1e-2)
