@@ -934,7 +934,19 @@ __global__ __launch_bounds__(GT) void k_xtw64(const double *__restrict__ X, int 
 //  * the Gram of the first pass's Q, for the second pass, comes from those FP32
 //    rows staged in LDS (FP64 MFMA), so the second pass reads nothing from HBM
 //    when the panel fits in one chunk of QT rows.
+// With one pass the rows are independent once R is known: gridDim.y
+// workgroups per face (cholqr_row_groups) each form the same R and solve the
+// chunks blockIdx.y, blockIdx.y + gridDim.y, ..  (a few tall panels on many
+// CUs; every row as with one workgroup).  Two passes need gridDim.y = 1.
 constexpr int QT = 512;
+
+// Workgroups per face for a one-pass Cholesky-QR of nf panels of `rows` rows:
+// about 256 in all, at most one per chunk of QT rows.
+inline unsigned cholqr_row_groups(int64_t rows, int64_t nf) {
+    const int64_t nch = (rows + QT - 1) / QT, want = nf > 0 ? 256 / nf : 1;
+    const int64_t g = want < nch ? want : nch;
+    return g < 1 ? 1u : (unsigned)g;
+}
 
 // T: the panel's element type (FP32 in the mixed path, FP64 in the FP64
 // randomized path, which stages fewer rows per LDS pass).
@@ -1054,7 +1066,7 @@ __global__ __launch_bounds__(QT) void k_cholqr(const T *__restrict__ Sin, int ro
         f64x4 gacc[TPW];
 #pragma unroll
         for (int t = 0; t < TPW; ++t) gacc[t] = f64x4{0, 0, 0, 0};
-        for (int ch = 0; ch < nch; ++ch) {
+        for (int ch = blockIdx.y; ch < nch; ch += gridDim.y) {
             const int row = ch * QT + tid;
             if (pass == 0 || nch > 1) {
                 const T *src = (pass == 0 ? S : Q) + (row < rows ? row : rows - 1);
@@ -1132,7 +1144,7 @@ __global__ __launch_bounds__(QT) void k_cholqr(const T *__restrict__ Sin, int ro
         }
     }
     // the first Cholesky-QR of a truncation sets the flag, later ones raise it
-    if (tid == 0) {
+    if (tid == 0 && blockIdx.y == 0) {
         if (first) qr_info[f] = bad ? 2 : 0;
         else if (bad) qr_info[f] = 2;
     }
@@ -2440,8 +2452,9 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     if (power) {
         if (reuse) {
             // the sketch's first ell columns were taken once for all faces
-            TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)src->Y, m, ell,
-                         w.Qm, 1, (const double *)src->gram_m, mparts, w.qr_info, 1, fmap, 1, 32);
+            TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf, cholqr_row_groups(m, nf)), dim3(QT), 0, s,
+                         (const float *)src->Y, m, ell, w.Qm, 1, (const double *)src->gram_m, mparts, w.qr_info, 1,
+                         fmap, 1, 32);
             TSVDM_MARK();
         } else {
             // pass 1: sketch Y = X Omega (BF16), ||X||^2, Gram partials of Y
@@ -2449,8 +2462,8 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
             TSVDM_MARK();
             // basis of the sketch: one shifted Cholesky-QR step (its span is what
             // the power step needs)
-            TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell,
-                         w.Qm, 1, gm_c, mparts, w.qr_info, 1, fmap);
+            TSVDM_LAUNCH("cholqr_sketch", (k_cholqr<LP>), dim3(nf, cholqr_row_groups(m, nf)), dim3(QT), 0, s,
+                         (const float *)w.Y, m, ell, w.Qm, 1, gm_c, mparts, w.qr_info, 1, fmap);
         }
         // pass 2: Z = X^T Q (BF16) and its Gram partials; basis of Z
         if (v4)
@@ -2459,8 +2472,8 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
         else
             TSVDM_LAUNCH("power_xtw_bf16", (k_xtw<LP, PROD_BF16, true, false, false>), gp, dim3(GT), 0, s, Xd, m,
                          p, nf, (const float *)w.Qm, (int64_t)m * LP, m, ell, w.Z, w.gram_p, (double *)nullptr, fmap);
-        TSVDM_LAUNCH("cholqr_power_z", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Z, p, ell,
-                     w.Qp, 1, gp_c, pparts, w.qr_info, 0, fmap);
+        TSVDM_LAUNCH("cholqr_power_z", (k_cholqr<LP>), dim3(nf, cholqr_row_groups(p, nf)), dim3(QT), 0, s,
+                     (const float *)w.Z, p, ell, w.Qp, 1, gp_c, pparts, w.qr_info, 0, fmap);
         // pass 3: Y' = X Qz, FP32-accurate (split BF16), and its Gram partials
         // (and ||X||^2 when the sketch pass was skipped)
         double *fp3 = reuse ? w.fro_part : (double *)nullptr;
