@@ -327,23 +327,27 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
     auto load = [&](int b0) {
         xm = 0;
         wm = 0;
+        if constexpr (VEC) {  // arow < m implies arow + 3 < m
 #pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int b = b0 + 4 * cg + it;
-            if constexpr (VEC) {  // arow < m implies arow + 3 < m
+            for (int it = 0; it < 4; ++it) {
+                const int b = b0 + 4 * cg + it;
                 const bool ok = b < p && arow < m;
                 const uint32_t off = ok ? 4u * ((uint32_t)arow + (uint32_t)m * (uint32_t)b) : 0u;
                 const f32x4 x = *reinterpret_cast<const f32x4 *>(Xb + off);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) xr[4 * it + v] = x[v];
                 xm |= ok ? 0xFu << (4 * it) : 0u;
-            } else {
+            }
+        } else {
+            // one row per lane, 16 columns per wavefront: every load is 64
+            // consecutive rows of one column
+            const int a = a0 + lane;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const bool ok = b < p && arow + v < m;
-                    xr[4 * it + v] = Xf[ok ? arow + v + (int64_t)m * b : 0];
-                    xm |= (uint32_t)ok << (4 * it + v);
-                }
+            for (int i = 0; i < 16; ++i) {
+                const int b = b0 + 16 * wave + i;
+                const bool ok = b < p && a < m;
+                xr[i] = Xf[ok ? a + (int64_t)m * b : 0];
+                xm |= (uint32_t)ok << i;
             }
         }
         if constexpr (VEC) {  // four consecutive rows of W (p, ldw multiples of 4)
@@ -370,18 +374,22 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
     load(0);
     for (int b0 = 0; b0 < p; b0 += KC) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {  // row 4rq + v, columns 4cg .. 4cg+3
+        for (int v = 0; v < 4; ++v) {
+            // VEC: row 4rq + v, columns 4cg .. 4cg+3; else row lane, columns
+            // 16 wave + 4v .. 16 wave + 4v + 3
             float x[4];
 #pragma unroll
             for (int it = 0; it < 4; ++it) {
-                x[it] = (xm >> (4 * it + v)) & 1u ? xr[4 * it + v] : 0.0f;
+                const int q = VEC ? 4 * it + v : 4 * v + it;
+                x[it] = (xm >> q) & 1u ? xr[q] : 0.0f;
                 fro += (double)x[it] * (double)x[it];
             }
             uint2 h, l;
             split2(x[0], x[1], h.x, l.x);
             split2(x[2], x[3], h.y, l.y);
-            *reinterpret_cast<uint2 *>(&xh[(4 * rq + v) * LDK + 4 * cg]) = h;
-            if (SPL) *reinterpret_cast<uint2 *>(&xl[(4 * rq + v) * LDK + 4 * cg]) = l;
+            const int at = VEC ? (4 * rq + v) * LDK + 4 * cg : lane * LDK + 16 * wave + 4 * v;
+            *reinterpret_cast<uint2 *>(&xh[at]) = h;
+            if (SPL) *reinterpret_cast<uint2 *>(&xl[at]) = l;
         }
         if constexpr (VEC) {
 #pragma unroll
@@ -506,26 +514,30 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
     float xr[16], wr[WPT];
     uint32_t xm = 0, wm = 0;
     auto load = [&](int a0) {
-        const int a = a0 + 4 * q4;
         xm = 0;
         wm = 0;
+        if constexpr (VEC) {  // a < m implies a + 3 < m
+            const int a = a0 + 4 * q4;
 #pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int b = b0 + cj0 + 16 * it;
-            if constexpr (VEC) {  // a < m implies a + 3 < m
+            for (int it = 0; it < 4; ++it) {
+                const int b = b0 + cj0 + 16 * it;
                 const bool ok = b < p && a < m;
                 const uint32_t off = ok ? 4u * ((uint32_t)a + (uint32_t)m * (uint32_t)b) : 0u;
                 const f32x4 x = *reinterpret_cast<const f32x4 *>(Xb + off);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) xr[4 * it + v] = x[v];
                 xm |= ok ? 0xFu << (4 * it) : 0u;
-            } else {
+            }
+        } else {
+            // one row per lane, 16 columns per wavefront: every load is 64
+            // consecutive rows of one column
+            const int a = a0 + lane;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const bool ok = b < p && a + v < m;
-                    xr[4 * it + v] = Xf[ok ? a + v + (int64_t)m * b : 0];
-                    xm |= (uint32_t)ok << (4 * it + v);
-                }
+            for (int i = 0; i < 16; ++i) {
+                const int b = b0 + 16 * wave + i;
+                const bool ok = b < p && a < m;
+                xr[i] = Xf[ok ? a + (int64_t)m * b : 0];
+                xm |= (uint32_t)ok << i;
             }
         }
         if constexpr (VEC) {  // four consecutive rows of W (m, ldw multiples of 4)
@@ -551,17 +563,32 @@ __global__ __launch_bounds__(GT) void k_xtw(const float *__restrict__ X, int m, 
     };
     load(0);
     for (int a0 = 0; a0 < m; a0 += KC) {
+        if constexpr (VEC) {
 #pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int cj = cj0 + 16 * it;
-            float x[4];
+            for (int it = 0; it < 4; ++it) {
+                const int cj = cj0 + 16 * it;
+                float x[4];
 #pragma unroll
-            for (int v = 0; v < 4; ++v) x[v] = (xm >> (4 * it + v)) & 1u ? xr[4 * it + v] : 0.0f;
-            uint2 ph, pl;
-            split2(x[0], x[1], ph.x, pl.x);
-            split2(x[2], x[3], ph.y, pl.y);
-            *reinterpret_cast<uint2 *>(&xh[cj * LDK + 4 * q4]) = ph;
-            if (SPL) *reinterpret_cast<uint2 *>(&xl[cj * LDK + 4 * q4]) = pl;
+                for (int v = 0; v < 4; ++v) x[v] = (xm >> (4 * it + v)) & 1u ? xr[4 * it + v] : 0.0f;
+                uint2 ph, pl;
+                split2(x[0], x[1], ph.x, pl.x);
+                split2(x[2], x[3], ph.y, pl.y);
+                *reinterpret_cast<uint2 *>(&xh[cj * LDK + 4 * q4]) = ph;
+                if (SPL) *reinterpret_cast<uint2 *>(&xl[cj * LDK + 4 * q4]) = pl;
+            }
+        } else {  // row a0 + lane of columns 16 wave + i
+#pragma unroll
+            for (int i = 0; i < 16; i += 2) {
+                uint32_t hh, ll;
+                split2((xm >> i) & 1u ? xr[i] : 0.0f, (xm >> (i + 1)) & 1u ? xr[i + 1] : 0.0f, hh, ll);
+                const int cj = 16 * wave + i;
+                xh[cj * LDK + lane] = (uint16_t)hh;
+                xh[(cj + 1) * LDK + lane] = (uint16_t)(hh >> 16);
+                if (SPL) {
+                    xl[cj * LDK + lane] = (uint16_t)ll;
+                    xl[(cj + 1) * LDK + lane] = (uint16_t)(ll >> 16);
+                }
+            }
         }
         if constexpr (VEC) {
 #pragma unroll
