@@ -48,6 +48,9 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int GT = 256;  // threads per workgroup
 enum { PROD_BF16 = 0, PROD_SPLIT = 1 };
+// most column ranges per 64-row block (the certificate pass, the X W passes);
+// the certificate partials hold that many per block
+constexpr int kResidSplitMax = 32;
 
 // (x0, x1) -> packed BF16 pairs hi = RNE(x), lo = RNE(x - hi) (x - hi is
 // exact in FP32), element 0 in the low half; the hardware packed conversion
@@ -294,7 +297,8 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
                                            int nw, float *__restrict__ Y,
                                            double *__restrict__ fro_part,
                                            double *__restrict__ gram_part,
-    const int32_t *__restrict__ fmap) {
+    const int32_t *__restrict__ fmap, int ksplit = 1, float *__restrict__ ypart = nullptr,
+    double *__restrict__ frop = nullptr) {
     constexpr int KC = 64, LDK = KC + 8;  // LDS row pitch (bf16 elements)
     constexpr int NB = LP / 16, WPT = KC * LP / GT;
     constexpr bool SPL = PROD == PROD_SPLIT;
@@ -307,11 +311,15 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
     __shared__ __align__(16) float ys[GRAM ? YS : 1];
     __shared__ double red[GT / 64];
     const int nb = (m + 63) / 64;
-    int blk, f;
-    xcd_map(blockIdx.x, nb, nf, blk, f);
+    int bx, f;
+    xcd_map(blockIdx.x, nb * ksplit, nf, bx, f);
     if (f >= nf) return;  // a padding face of the grid
     if (fmap && fmap[f] < 0) return;  // an unused slot of a face list sized on the device
+    const int blk = bx / ksplit, sp = bx - blk * ksplit;
     const int a0 = blk * 64;
+    // the workgroup's columns c0 .. pe-1: range sp of ksplit over the chunks
+    const int cps = ((p + KC - 1) / KC + ksplit - 1) / ksplit;
+    const int c0 = min(p, sp * cps * KC), pe = min(p, (sp + 1) * cps * KC);
     const float *Xf = X + (int64_t)(fmap ? fmap[f] : f) * m * p;
     const float *Wf = W + (int64_t)f * w_stride;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -331,7 +339,7 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
 #pragma unroll
             for (int it = 0; it < 4; ++it) {
                 const int b = b0 + 4 * cg + it;
-                const bool ok = b < p && arow < m;
+                const bool ok = b < pe && arow < m;
                 const uint32_t off = ok ? 4u * ((uint32_t)arow + (uint32_t)m * (uint32_t)b) : 0u;
                 const f32x4 x = *reinterpret_cast<const f32x4 *>(Xb + off);
 #pragma unroll
@@ -345,7 +353,7 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int b = b0 + 16 * wave + i;
-                const bool ok = b < p && a < m;
+                const bool ok = b < pe && a < m;
                 xr[i] = Xf[ok ? a + (int64_t)m * b : 0];
                 xm |= (uint32_t)ok << i;
             }
@@ -354,7 +362,7 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
 #pragma unroll
             for (int q = 0; q < WPT / 4; ++q) {
                 const int e = tid + q * GT, k4 = e % (KC / 4), c = e / (KC / 4), b = b0 + 4 * k4;
-                const bool ok = c < nw && b < p;
+                const bool ok = c < nw && b < pe;
                 const f32x4 x = *reinterpret_cast<const f32x4 *>(
                     Wb + (ok ? 4u * ((uint32_t)b + (uint32_t)ldw * (uint32_t)c) : 0u));
 #pragma unroll
@@ -365,14 +373,14 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
 #pragma unroll
             for (int q = 0; q < WPT; ++q) {
                 const int e = tid + q * GT, k = e % KC, c = e / KC, b = b0 + k;
-                const bool ok = c < nw && b < p;
+                const bool ok = c < nw && b < pe;
                 wr[q] = *reinterpret_cast<const float *>(Wb + (ok ? 4u * ((uint32_t)b + (uint32_t)ldw * (uint32_t)c) : 0u));
                 wm |= (uint32_t)ok << q;
             }
         }
     };
-    load(0);
-    for (int b0 = 0; b0 < p; b0 += KC) {
+    load(c0);
+    for (int b0 = c0; b0 < pe; b0 += KC) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             // VEC: row 4rq + v, columns 4cg .. 4cg+3; else row lane, columns
@@ -419,7 +427,7 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
             }
         }
         __syncthreads();
-        if (b0 + KC < p) load(b0 + KC);  // next chunk in flight during the MFMAs
+        if (b0 + KC < pe) load(b0 + KC);  // next chunk in flight during the MFMAs
         const int ar = 16 * wave + (lane & 15);
 #pragma unroll
         for (int kk = 0; kk < KC / 32; ++kk) {
@@ -441,6 +449,29 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
         }
         __syncthreads();
     }
+    if (ksplit > 1) {
+        // a partial product: into panel sp of the face's ypart (stride p LP
+        // per face, ksplit m <= p), ||X||^2 of the columns into frop; k_ysum
+        // sums them and forms the Gram partials
+        float *Pf = ypart + (int64_t)f * p * LP + (int64_t)sp * m * LP;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+            const int c = 16 * j + (lane & 15);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int r = a0 + 16 * wave + 4 * (lane >> 4) + v;
+                if (r < m) Pf[r + (int64_t)m * c] = acc[j][v];
+            }
+        }
+        if (fro_part) {
+            fro = wave_sum(fro);
+            if (lane == 0) red[wave] = fro;
+            __syncthreads();
+            if (tid == 0)
+                frop[(int64_t)f * nb * kResidSplitMax + blk * ksplit + sp] = red[0] + red[1] + red[2] + red[3];
+        }
+        return;
+    }
     float *Yf = Y + (int64_t)f * m * LP;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
@@ -457,6 +488,48 @@ __global__ __launch_bounds__(GT) void k_xw(const float *__restrict__ X, int m, i
         if (lane == 0) red[wave] = fro;
         __syncthreads();
         if (tid == 0) fro_part[(int64_t)f * nb + blk] = red[0] + red[1] + red[2] + red[3];
+    }
+}
+
+// The ksplit partial products of k_xw summed in order (grid (ceil(m/64), nf),
+// XCD-aware): Y, the FP64 Gram partials of its 64-row blocks and, with
+// fro_part, ||X||^2 per block from the partial sums in frop.
+template <int LP>
+__global__ __launch_bounds__(GT) void k_ysum(const float *__restrict__ ypart, int m, int p, int nf, int ksplit,
+                                             float *__restrict__ Y, double *__restrict__ gram_part,
+                                             const double *__restrict__ frop, double *__restrict__ fro_part,
+                                             const int32_t *__restrict__ fmap) {
+    constexpr int NB = LP / 16;
+    constexpr int YS = 64 * (LP + 1) > 512 * gram_tiles<LP>() ? 64 * (LP + 1) : 512 * gram_tiles<LP>();
+    __shared__ __align__(16) float ys[YS];
+    const int nb = (m + 63) / 64;
+    int blk, f;
+    xcd_map(blockIdx.x, nb, nf, blk, f);
+    if (f >= nf) return;  // a padding face of the grid
+    if (fmap && fmap[f] < 0) return;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, a0 = blk * 64;
+    const float *Pf = ypart + (int64_t)f * p * LP;
+    float *Yf = Y + (int64_t)f * m * LP;
+    f32x4 acc[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int c = 16 * j + (lane & 15);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int r = a0 + 16 * wave + 4 * (lane >> 4) + v;
+            float t = 0.0f;
+            if (r < m) {
+                for (int q = 0; q < ksplit; ++q) t += Pf[(int64_t)q * m * LP + r + (int64_t)m * c];
+                Yf[r + (int64_t)m * c] = t;
+            }
+            acc[j][v] = t;
+        }
+    }
+    block_gram_f64<LP>(acc, gram_part + ((int64_t)f * nb + blk) * LP * LP, ys, reinterpret_cast<double *>(ys));
+    if (fro_part && tid == 0) {
+        double t = 0.0;
+        for (int q = 0; q < ksplit; ++q) t += frop[(int64_t)f * nb * kResidSplitMax + blk * ksplit + q];
+        fro_part[(int64_t)f * nb + blk] = t;
     }
 }
 
@@ -2215,13 +2288,23 @@ struct MixedWs {
 // Column ranges of the certificate pass per face (resid_body): more than one
 // only when the faces' 64-row blocks alone would leave most of the 256 CUs
 // idle (a few wide faces); then about 512 workgroups in all.
-constexpr int kResidSplitMax = 32;
 inline int resid_splits(int64_t nf, int64_t mparts, int64_t p) {
     const int64_t chunks = (p + 63) / 64, blocks = nf * mparts;
     if (blocks >= 256 || blocks < 1) return 1;
     int64_t sp = (512 + blocks - 1) / blocks;
     if (sp > kResidSplitMax) sp = kResidSplitMax;
     if (sp > chunks) sp = chunks;
+    return sp < 1 ? 1 : (int)sp;
+}
+
+// Column ranges of the X W passes (k_xw, ksplit) for the same reason, with
+// the partial products kept in the face's Z panel (p x LP, idle during those
+// passes), so at most p / m of them; from the whole tensor's face count, so
+// that face groups give the same bits.
+inline int xw_splits(int64_t nf, int64_t mparts, int64_t m, int64_t p) {
+    int64_t sp = resid_splits(nf, mparts, p);
+    const int64_t cap = m > 0 ? p / m : 1;
+    if (sp > cap) sp = cap;
     return sp < 1 ? 1 : (int)sp;
 }
 
@@ -2459,14 +2542,28 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     const bool exact = o->certify && cert;
     const bool v4 = vec_loads_ok(Xd, m, p) && reinterpret_cast<uintptr_t>(w.Y) % 16 == 0;
     const double *gm_c = w.gram_m, *gp_c = w.gram_p;
+    // the X W passes of a few wide faces: xsp column ranges per 64-row block,
+    // partial products in Z and the partial ||X||^2 in cert_part (both idle
+    // then), summed by k_ysum
+    const int xsp = xw_splits(X->n3, mparts, m, p);
+    const dim3 gx(xcd_grid(mparts * xsp, nf));
+    float *xyp = xsp > 1 ? w.Z : nullptr;
+    double *xfp = xsp > 1 ? w.cert_part : nullptr;
+#define TSVDM_YSUM(NAME, FRO)                                                                               \
+    do {                                                                                                    \
+        if (xsp > 1)                                                                                        \
+            TSVDM_LAUNCH(NAME, (k_ysum<LP>), gm, dim3(GT), 0, s, (const float *)w.Z, m, p, nf, xsp, w.Y,      \
+                         w.gram_m, (const double *)w.cert_part, FRO, fmap);                                 \
+    } while (0)
 #define TSVDM_SKETCH()                                                                                      \
     do {                                                                                                    \
         if (v4 && reinterpret_cast<uintptr_t>(o->omega) % 16 == 0)                                          \
-            TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true, true>), gm, dim3(GT), 0, s, Xd, m, p, nf, \
-                         o->omega, (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m, fmap);                     \
+            TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true, true>), gx, dim3(GT), 0, s, Xd, m, p, nf, \
+                         o->omega, (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m, fmap, xsp, xyp, xfp);      \
         else                                                                                                \
-            TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true, false>), gm, dim3(GT), 0, s, Xd, m, p,    \
-                         nf, o->omega, (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m, fmap);                 \
+            TSVDM_LAUNCH("sketch_xw_bf16", (k_xw<LP, PROD_BF16, true, false>), gx, dim3(GT), 0, s, Xd, m, p,    \
+                         nf, o->omega, (int64_t)0, p, ell, w.Y, w.fro_part, w.gram_m, fmap, xsp, xyp, xfp);  \
+        TSVDM_YSUM("sketch_reduce", w.fro_part);                                                            \
     } while (0)
 #define TSVDM_MARK()                                                                                        \
     do {                                                                                                    \
@@ -2505,17 +2602,19 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
         // (and ||X||^2 when the sketch pass was skipped)
         double *fp3 = reuse ? w.fro_part : (double *)nullptr;
         if (v4)
-            TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true, true>), gm, dim3(GT), 0, s, Xd, m, p, nf,
-                         (const float *)w.Qp, (int64_t)p * LP, p, ell, w.Y, fp3, w.gram_m, fmap);
+            TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true, true>), gx, dim3(GT), 0, s, Xd, m, p, nf,
+                         (const float *)w.Qp, (int64_t)p * LP, p, ell, w.Y, fp3, w.gram_m, fmap, xsp, xyp, xfp);
         else
-            TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true, false>), gm, dim3(GT), 0, s, Xd, m, p, nf,
-                         (const float *)w.Qp, (int64_t)p * LP, p, ell, w.Y, fp3, w.gram_m, fmap);
+            TSVDM_LAUNCH("power_xw_split", (k_xw<LP, PROD_SPLIT, true, false>), gx, dim3(GT), 0, s, Xd, m, p, nf,
+                         (const float *)w.Qp, (int64_t)p * LP, p, ell, w.Y, fp3, w.gram_m, fmap, xsp, xyp, xfp);
+        TSVDM_YSUM("power_xw_reduce", fp3);
     } else {
         TSVDM_SKETCH();
         TSVDM_MARK();
     }
 #undef TSVDM_MARK
 #undef TSVDM_SKETCH
+#undef TSVDM_YSUM
     // final basis: FP64 shifted Cholesky-QR2 (first Gram from the partials)
     TSVDM_LAUNCH("cholqr_final", (k_cholqr<LP>), dim3(nf), dim3(QT), 0, s, (const float *)w.Y, m, ell, w.Qm,
                  2, gm_c, mparts, w.qr_info, power ? 0 : 1, fmap);
