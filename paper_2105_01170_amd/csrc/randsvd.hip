@@ -137,15 +137,24 @@ __device__ __forceinline__ void load_gram_partials(const double *__restrict__ gp
 // XCD L % 8, each with its own L2).  For a pass whose nb blocks of a face all
 // read the same per-face operand, give those blocks consecutive slots on one
 // XCD, so the operand is fetched into that L2 once instead of eight times.
-// The grid is nb times the face count rounded up to a multiple of 8
-// (xcd_grid); workgroups of the padding faces (f >= nf) exit at once.
+// With fewer than 8 faces a face's blocks are cut into g = ceil(8 / nf)
+// consecutive runs, each on its own XCD (else a single face would run on one
+// XCD of eight).  The grid is ceil(nb / g) times nf g rounded up to a
+// multiple of 8 (xcd_grid); workgroups past the faces or past a face's last
+// block get f = nf and exit at once.
+__host__ __device__ __forceinline__ int xcd_runs(int nf) { return nf >= 8 || nf < 1 ? 1 : (nf + 7) / nf; }
 __device__ __forceinline__ void xcd_map(int L, int nb, int nf, int &b, int &f) {
+    const int g = xcd_runs(nf), nbv = (nb + g - 1) / g;
     const int x = L & 7, s = L >> 3;
-    b = s % nb;
-    f = (s / nb) * 8 + x;
-    (void)nf;
+    const int vf = (s / nbv) * 8 + x;  // run vf % g of face vf / g
+    b = (vf % g) * nbv + s % nbv;
+    f = vf / g;
+    if (b >= nb) f = nf;
 }
-inline unsigned xcd_grid(int nb, int nf) { return (unsigned)nb * (unsigned)((nf + 7) / 8 * 8); }
+inline unsigned xcd_grid(int nb, int nf) {
+    const int g = xcd_runs(nf), nbv = (nb + g - 1) / g;
+    return (unsigned)nbv * (unsigned)((nf * g + 7) / 8 * 8);
+}
 
 // ---------------------------------------------------------------- staging
 // Rows r0..r0+RC-1 of the rows x LP column-major panel S into
@@ -1553,10 +1562,21 @@ __device__ __forceinline__ void resid_body(const T *__restrict__ X, int m, int p
     }
     const int xq = tid & 15, xc = tid >> 4, vc = tid & 63, vr0 = tid >> 6;
     if (tid < KP) ss[tid] = tid < kf ? Sf[CPLX ? tid >> 1 : tid] : 0.0;
-    // chunk loads: X rows a0 + 4 (tid%16) .. +3 of columns b0 + tid/16 + 16 it;
-    // V row b0 + tid%64 of ranks tid/64 + 4 q
+    // chunk loads: X rows a0 + 4 (tid%16) .. +3 of columns b0 + tid/16 + 16 it
+    // (VEC), else row a0 + lane of columns b0 + 16 wave .. +15 (every load 64
+    // consecutive rows of a column); V row b0 + tid%64 of ranks tid/64 + 4 q
     T xr[16], vr[VPT];
     auto load = [&](int b0) {
+        if constexpr (!VEC) {
+            const int a = a0 + lane;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int b = b0 + 16 * wave + i;
+                const bool ok = b < p && a < m;
+                const T v = Xf[ok ? a + (int64_t)m * b : 0];
+                xr[i] = ok ? v : (T)0;
+            }
+        }
 #pragma unroll
         for (int it = 0; it < 4; ++it) {
             const int b = b0 + xc + 16 * it, a = a0 + 4 * xq;
@@ -1576,13 +1596,6 @@ __device__ __forceinline__ void resid_body(const T *__restrict__ X, int m, int p
 #pragma unroll
                     for (int u = 0; u < 4; ++u) xr[4 * it + u] = ok ? v[u] : 0.0f;
                 }
-            } else {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const bool ok = b < p && a + u < m;
-                    const T v = Xf[ok ? a + u + (int64_t)m * b : 0];
-                    xr[4 * it + u] = ok ? v : (T)0;
-                }
             }
         }
 #pragma unroll
@@ -1597,10 +1610,15 @@ __device__ __forceinline__ void resid_body(const T *__restrict__ X, int m, int p
     double racc = 0.0;
     if (c0 < c1) load(c0);
     for (int b0 = c0; b0 < c1; b0 += 64) {
+        if constexpr (VEC) {
 #pragma unroll
-        for (int it = 0; it < 4; ++it)
+            for (int it = 0; it < 4; ++it)
 #pragma unroll
-            for (int u = 0; u < 4; ++u) xs[(xc + 16 * it) * XP + 4 * xq + u] = xr[4 * it + u];
+                for (int u = 0; u < 4; ++u) xs[(xc + 16 * it) * XP + 4 * xq + u] = xr[4 * it + u];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) xs[(16 * wave + i) * XP + lane] = xr[i];
+        }
 #pragma unroll
         for (int q = 0; q < VPT; ++q) ws[(vr0 + 4 * q) * WP + vc] = vr[q];
         __syncthreads();
