@@ -236,3 +236,28 @@ def test_certificate_of_few_wide_faces_split_over_columns():
     np.testing.assert_allclose(got["cert"], true, rtol=1e-9, atol=1e-14 * np.max(got["fro"]))
     rnd = oracle.randomized_tsvdm_faces(Xh64, Omega.astype(np.float64), k, 1)
     assert relerr(That, rnd["That"]) < 1e-4
+
+
+def test_few_wide_faces_split_passes_with_vector_loads():
+    """Three 128 x 6000 faces (m a multiple of 4: 16-byte loads): 6 row
+    blocks in all, so the X W passes split every block's columns over
+    workgroups (partial products summed by the reduction kernel), each face's
+    blocks run on three XCDs, and the one-pass Cholesky-QR of the 6000-row Z
+    spreads its chunks over workgroups.  The certificate equals the error of
+    the returned factors and the truncation agrees with the oracle's
+    randomized one (same Omega) at 1e-4."""
+    m, p, k, os_ = 128, 6000, 10, 6
+    Xh32, _ = _decaying_faces(m, p, [1 / 4, 1 / 5, 1 / 7], 40, salt=97)
+    nf = Xh32.shape[2]
+    Omega = synth.gaussian(synth.rng(1, 98), (p, k + os_)).astype(np.float32)
+    tr = api.Truncator(m, p, nf, torch.float32, k=k, precision=C.PREC_MIXED, oversample=os_, power_iters=1,
+                       omega=to_dev(Omega))
+    got = _factors(tr(to_dev(Xh32)), nf)
+    assert np.all(got["ranks"] == k) and np.all(got["info"] == 0)
+    Xh64 = Xh32.astype(np.float64)
+    np.testing.assert_allclose(got["fro"], [np.linalg.norm(Xh64[:, :, f]) for f in range(nf)], rtol=1e-6)
+    That = reconstruct(got["U"], got["S"], got["V"], got["ranks"])
+    true = np.array([np.linalg.norm(Xh64[:, :, f] - That[:, :, f]) for f in range(nf)])
+    np.testing.assert_allclose(got["cert"], true, rtol=1e-9, atol=1e-14 * np.max(got["fro"]))
+    rnd = oracle.randomized_tsvdm_faces(Xh64, Omega.astype(np.float64), k, 1)
+    assert relerr(That, rnd["That"]) < 1e-4
