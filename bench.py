@@ -944,12 +944,13 @@ def next_main(args):
             res["G"], res["U"], res["X64"] = api.two_sided(X64, N, T, U, r), U, X64
 
         ms, table = _timed(step, args.steps, args.warmup, stream)
-        # the core reads the FP64 tensor once; T_E writes it in FP64 and FP32 from the small blocks
+        # the core reads the FP64 tensor once; T_E writes it in FP64 and FP32, reading as many
+        # bytes of blocks (the T distinct N x N blocks are as large as the tensor)
         work = _trunc_work(N, T * N, 1, r + 8, r)
         # G_b = U^T S_b U: 2 N^2 r + 2 N r^2 FP64 flops per slice (FP64 vector units)
         work.update({"two_sided": ("alu64", T * (2.0 * N * N * r + 2.0 * N * r * r)),
                      "two_sided_reduce": ("hbm", 8.0 * T * ((N + 63) // 64) * r * r),
-                     "tensor_from_blocks_E": ("hbm", 12.0 * N * T * N)})
+                     "tensor_from_blocks_E": ("hbm", 24.0 * N * T * N)})
         Uh = res["U"].cpu().numpy().astype(np.float64).reshape((N, r), order="F")
         trc = float(N * T)
         out.update({"metric": "SPSD two-sided compression of a space-time covariance, steps/s",

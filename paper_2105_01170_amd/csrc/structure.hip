@@ -347,16 +347,23 @@ void placement_tables(const tsvdm_placement *pl, int64_t *ell, int64_t *q, int64
 }  // namespace tsvdm
 
 namespace {
-// X(a, k, t) = sqrt(eta_k) B(a, t, k) from the distinct blocks stacked m x n x p
+// X(a, k, t) = sqrt(eta_k) B(a, t, k) from the distinct blocks stacked m x n x p:
+// a workgroup copies whole columns kt = k + p t of X (one division per column,
+// contiguous loads and stores), grid-stride over the p n columns
 template <typename T>
-__global__ void k_tensor_from_blocks_E(const T *__restrict__ B, int64_t m, int64_t n, int64_t p,
-                                       const double *__restrict__ w, T *__restrict__ X) {
-    const int64_t tot = m * p * n;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t a = e % m, kt = e / m, k = kt % p, t = kt / p;
-        X[e] = (T)(w[k] * (double)B[a + m * t + m * n * k]);
+__global__ __launch_bounds__(256) void k_tensor_from_blocks_E(const T *__restrict__ B, int64_t m, int64_t n,
+                                                              int64_t p, const double *__restrict__ w,
+                                                              T *__restrict__ X) {
+    const int64_t ncol = p * n;
+    for (int64_t kt = blockIdx.x; kt < ncol; kt += gridDim.x) {
+        const int64_t k = kt % p, t = kt / p;
+        const double wk = w[k];
+        const T *src = B + m * t + m * n * k;
+        T *dst = X + m * kt;
+        for (int64_t a = threadIdx.x; a < m; a += 256) dst[a] = (T)(wk * (double)src[a]);
     }
 }
+inline unsigned columns_grid(int64_t ncol) { return (unsigned)(ncol < 1 ? 1 : ncol < (1 << 20) ? ncol : (1 << 20)); }
 }  // namespace
 
 extern "C" tsvdm_status tsvdm_tensor_from_blocks_E(const tsvdm_placement *pl, const void *blocks, int32_t dtype,
@@ -365,13 +372,12 @@ extern "C" tsvdm_status tsvdm_tensor_from_blocks_E(const tsvdm_placement *pl, co
     if (m < 1 || n < 1) FAILS(TSVDM_EINVAL, "block size %lld x %lld", (long long)m, (long long)n);
     if (dtype != TSVDM_F32 && dtype != TSVDM_F64) FAILS(TSVDM_EINVAL, "dtype must be F32 or F64");
     hipStream_t s = (hipStream_t)stream;
-    const int64_t tot = m * pl->p * n;
     if (dtype == TSVDM_F64)
-        TSVDM_LAUNCH("tensor_from_blocks_E", k_tensor_from_blocks_E<double>, dim3(grid_of(tot)), dim3(256), 0, s,
+        TSVDM_LAUNCH("tensor_from_blocks_E", k_tensor_from_blocks_E<double>, dim3(columns_grid(pl->p * n)), dim3(256), 0, s,
                      reinterpret_cast<const double *>(blocks), m, n, pl->p, (const double *)pl->w,
                      reinterpret_cast<double *>(X));
     else
-        TSVDM_LAUNCH("tensor_from_blocks_E", k_tensor_from_blocks_E<float>, dim3(grid_of(tot)), dim3(256), 0, s,
+        TSVDM_LAUNCH("tensor_from_blocks_E", k_tensor_from_blocks_E<float>, dim3(columns_grid(pl->p * n)), dim3(256), 0, s,
                      reinterpret_cast<const float *>(blocks), m, n, pl->p, (const double *)pl->w,
                      reinterpret_cast<float *>(X));
     TSVDM_LAUNCH_CHECK("tensor_from_blocks_E");
