@@ -519,21 +519,52 @@ __global__ __launch_bounds__(GT) void k_ysum(const float *__restrict__ ypart, in
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, a0 = blk * 64;
     const float *Pf = ypart + (int64_t)f * p * LP;
     float *Yf = Y + (int64_t)f * m * LP;
+    // the sums in row order (a lane per row: every load 64 consecutive rows
+    // of a column), staged in LDS as ys[r * (LP+1) + c]
+    // (four partials of all of a thread's columns in flight at once; every
+    // sum in the order of the partials)
+    constexpr int PER = 64 * LP / GT;
+    const int r = a0 + lane;
+    const bool rok = r < m;
+    const float *src = Pf + (rok ? r : 0);
+    const int64_t pst = (int64_t)m * LP;
+    float t[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) t[u] = 0.0f;
+    int q = 0;
+    for (; q + 4 <= ksplit; q += 4) {
+        float v[4][PER];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int u = 0; u < PER; ++u) v[i][u] = src[(q + i) * pst + (int64_t)m * (wave + 4 * u)];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int u = 0; u < PER; ++u) t[u] += v[i][u];
+    }
+    for (; q < ksplit; ++q) {
+        float v[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) v[u] = src[q * pst + (int64_t)m * (wave + 4 * u)];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) t[u] += v[u];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int c = wave + 4 * u;
+        if (rok) Yf[r + (int64_t)m * c] = t[u];
+        ys[lane * (LP + 1) + c] = rok ? t[u] : 0.0f;
+    }
+    __syncthreads();
+    // the MFMA output layout block_gram_f64 takes: row 16 wave + 4 (lane/16) + v,
+    // column 16 j + lane % 16
     f32x4 acc[NB];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const int c = 16 * j + (lane & 15);
+    for (int j = 0; j < NB; ++j)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = a0 + 16 * wave + 4 * (lane >> 4) + v;
-            float t = 0.0f;
-            if (r < m) {
-                for (int q = 0; q < ksplit; ++q) t += Pf[(int64_t)q * m * LP + r + (int64_t)m * c];
-                Yf[r + (int64_t)m * c] = t;
-            }
-            acc[j][v] = t;
-        }
-    }
+        for (int v = 0; v < 4; ++v) acc[j][v] = ys[(16 * wave + 4 * (lane >> 4) + v) * (LP + 1) + 16 * j + (lane & 15)];
+    __syncthreads();
     block_gram_f64<LP>(acc, gram_part + ((int64_t)f * nb + blk) * LP * LP, ys, reinterpret_cast<double *>(ys));
     if (fro_part && tid == 0) {
         double t = 0.0;
