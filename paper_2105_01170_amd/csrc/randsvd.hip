@@ -80,15 +80,19 @@ constexpr int gram_tiles() {
 // face f, both triangles.  All loads of a block of 8 partials are issued
 // before any is summed (clamped addresses, zero-selected, no branches).
 // lps: the width the partials were written for (LP, or 32 when LP = 16: the
-// 16 x 16 Gram is the first packed tile of a width-32 partial).
+// 16 x 16 Gram is the first packed tile of a width-32 partial).  pstride,
+// fparts: the nparts summed are every pstride-th of the face's fparts
+// partials (group sums of k_gram_group), fparts < 0 meaning nparts.
 template <int LP, int NTH>
 __device__ __forceinline__ void load_gram_partials(const double *__restrict__ gpart, int f, int nparts,
-                                                   double *G, int ldg, int lps = LP) {
+                                                   double *G, int ldg, int lps = LP, int pstride = 1,
+                                                   int fparts = -1) {
     constexpr int NT = LP / 16, NE2 = gram_tiles<LP>() * 128;
     constexpr int E2 = (NE2 + NTH - 1) / NTH, PB = 8;
     const int S2 = lps * lps / 2;
     const int tid = threadIdx.x;
-    const double2 *g2 = reinterpret_cast<const double2 *>(gpart + (int64_t)f * nparts * lps * lps);
+    const double2 *g2 =
+        reinterpret_cast<const double2 *>(gpart + (int64_t)f * (fparts < 0 ? nparts : fparts) * lps * lps);
     double2 acc[E2];
 #pragma unroll
     for (int q = 0; q < E2; ++q) acc[q] = double2{0.0, 0.0};
@@ -100,7 +104,7 @@ __device__ __forceinline__ void load_gram_partials(const double *__restrict__ gp
             for (int u = 0; u < PB; ++u) {
                 const int e2 = tid + q * NTH, pp = p0 + u;
                 const bool in = e2 < NE2 && pp < nparts;
-                const double2 t = g2[(int64_t)(pp < nparts ? pp : nparts - 1) * S2 + (e2 < NE2 ? e2 : 0)];
+                const double2 t = g2[(int64_t)(pp < nparts ? pp : nparts - 1) * pstride * S2 + (e2 < NE2 ? e2 : 0)];
                 v[q][u] = in ? t : double2{0.0, 0.0};
             }
 #pragma unroll
@@ -1060,6 +1064,45 @@ __global__ __launch_bounds__(GT) void k_xtw64(const double *__restrict__ X, int 
     if (GRAM) block_gram_f64d<LP>(acc, gram_part + ((int64_t)f * nb + blk) * LP * LP, ys, ys);
 }
 
+// ---------------------------------------------------------------- Gram groups
+// In place: partial g*grp of face f becomes the ordered sum of that face's
+// partials g*grp .. g*grp+grp-1 (grid (groups x element blocks, nf); a
+// thread per packed element and group, eight loads in flight), so a
+// Cholesky-QR whose rows are spread over many workgroups (cholqr_row_groups)
+// sums a few group sums in each of them instead of every partial.
+template <int LP>
+__global__ __launch_bounds__(256) void k_gram_group(double *__restrict__ gpart, int nparts, int grp,
+                                                    const int32_t *__restrict__ fmap) {
+    constexpr int NE2 = gram_tiles<LP>() * 128, NBK = (NE2 + 255) / 256, S2 = LP * LP / 2;
+    const int f = blockIdx.y;
+    if (fmap && fmap[f] < 0) return;
+    const int g = blockIdx.x / NBK, e2 = (blockIdx.x % NBK) * 256 + threadIdx.x;
+    const int p0 = g * grp, p1 = p0 + grp < nparts ? p0 + grp : nparts;
+    if (e2 >= NE2 || p0 >= nparts) return;
+    double2 *g2 = reinterpret_cast<double2 *>(gpart + (int64_t)f * nparts * LP * LP);
+    double2 acc = double2{0.0, 0.0};
+    for (int pp = p0; pp < p1; pp += 8) {
+        double2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int q = pp + u < p1 ? pp + u : p1 - 1;
+            const double2 t = g2[(int64_t)q * S2 + e2];
+            v[u] = pp + u < p1 ? t : double2{0.0, 0.0};
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            acc.x += v[u].x;
+            acc.y += v[u].y;
+        }
+    }
+    g2[(int64_t)p0 * S2 + e2] = acc;
+}
+template <int LP>
+inline unsigned gram_group_blocks(int nparts, int grp) {
+    constexpr int NE2 = gram_tiles<LP>() * 128;
+    return (unsigned)(((nparts + grp - 1) / grp) * ((NE2 + 255) / 256));
+}
+
 // ---------------------------------------------------------------- Cholesky-QR
 // Orthonormal basis Q (rows x LP, FP32, columns >= ell zero) of the rows x ell
 // panel S by shifted Cholesky-QR (Fukaya et al. 2020): G = S^T S (+ shift on
@@ -1100,7 +1143,7 @@ __global__ __launch_bounds__(QT) void k_cholqr(const T *__restrict__ Sin, int ro
                                                const double *__restrict__ gpart, int nparts,
                                                int32_t *__restrict__ qr_info, int first,
                                                const int32_t *__restrict__ fmap = nullptr, int src_global = 0,
-                                               int src_lp = LP) {
+                                               int src_lp = LP, int pgroup = 1) {
     constexpr bool D = sizeof(T) == 8;
     constexpr int LDG = LP + 1, LDR = LP + 2, LDS_ = LP + 1;
     // rows staged per LDS round for the second pass's Gram: a quarter of the
@@ -1121,8 +1164,9 @@ __global__ __launch_bounds__(QT) void k_cholqr(const T *__restrict__ Sin, int ro
     T *Q = Qout + (int64_t)f * rows * LP;
     if (tid == 0) bad = 0;
 
-    // ---- first Gram: ordered sum of the partials
-    load_gram_partials<LP, QT>(gpart, fs, nparts, G, LDG, slp);
+    // ---- first Gram: ordered sum of the partials (of their group sums, pgroup > 1)
+    if (pgroup > 1) load_gram_partials<LP, QT>(gpart, fs, (nparts + pgroup - 1) / pgroup, G, LDG, slp, pgroup, nparts);
+    else load_gram_partials<LP, QT>(gpart, fs, nparts, G, LDG, slp);
     __syncthreads();
 
     const int nch = (rows + QT - 1) / QT;
@@ -2645,8 +2689,14 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
         else
             TSVDM_LAUNCH("power_xtw_bf16", (k_xtw<LP, PROD_BF16, true, false, false>), gp, dim3(GT), 0, s, Xd, m,
                          p, nf, (const float *)w.Qm, (int64_t)m * LP, m, ell, w.Z, w.gram_p, (double *)nullptr, fmap);
-        TSVDM_LAUNCH("cholqr_power_z", (k_cholqr<LP>), dim3(nf, cholqr_row_groups(p, nf)), dim3(QT), 0, s,
-                     (const float *)w.Z, p, ell, w.Qp, 1, gp_c, pparts, w.qr_info, 0, fmap);
+        // many partials and rows spread over workgroups: group sums first
+        const unsigned zrg = cholqr_row_groups(p, nf);
+        const int zgp = zrg > 1 && pparts > 64 ? 32 : 1;
+        if (zgp > 1)
+            TSVDM_LAUNCH("gram_group_z", (k_gram_group<LP>), dim3(gram_group_blocks<LP>(pparts, zgp), nf), dim3(256),
+                         0, s, w.gram_p, pparts, zgp, fmap);
+        TSVDM_LAUNCH("cholqr_power_z", (k_cholqr<LP>), dim3(nf, zrg), dim3(QT), 0, s, (const float *)w.Z, p, ell,
+                     w.Qp, 1, gp_c, pparts, w.qr_info, 0, fmap, 0, LP, zgp);
         // pass 3: Y' = X Qz, FP32-accurate (split BF16), and its Gram partials
         // (and ||X||^2 when the sketch pass was skipped)
         double *fp3 = reuse ? w.fro_part : (double *)nullptr;
