@@ -1359,7 +1359,7 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
                                              int *__restrict__ perm_out, int *__restrict__ kf_out,
                                              double *__restrict__ fro2_out, double *__restrict__ cert,
                                              int32_t *__restrict__ jinfo,
-    const int32_t *__restrict__ fmap, const int32_t *__restrict__ kcap_face = nullptr) {
+    const int32_t *__restrict__ fmap, const int32_t *__restrict__ kcap_face = nullptr, int pgroup = 1) {
     constexpr int LD = jacobi_ld<LP>(), LDE = jacobi_ld<LP>(), NPM = LP / 2;
     __shared__ __align__(16) double Gb[2][LP * LD];
     __shared__ __align__(16) double Eb[2][LP * LDE];  // eigenvectors transposed: E[c * LDE + r]
@@ -1375,7 +1375,9 @@ __global__ __launch_bounds__(QT) void k_core(const double *__restrict__ gpart, i
     __syncthreads();
     // Gram into the leading block (the padded rows and columns of the
     // partials are zero), identity eigenvectors
-    load_gram_partials<LP, QT>(gpart, f, nparts, Gb[0], LD);
+    // (of their group sums, pgroup > 1: k_gram_group)
+    if (pgroup > 1) load_gram_partials<LP, QT>(gpart, f, (nparts + pgroup - 1) / pgroup, Gb[0], LD, LP, pgroup, nparts);
+    else load_gram_partials<LP, QT>(gpart, f, nparts, Gb[0], LD);
     if (tid < ell) Eb[0][tid * LDE + tid] = 1.0;
     if (tid < 3) rflag[tid] = 0;
     __syncthreads();
@@ -2731,10 +2733,15 @@ tsvdm_status run_group(const tsvdm_tensor *X, const tsvdm_truncate_opts *o, tsvd
     }
 #undef TSVDM_PROJECT
     const int msw = o->max_sweeps > 0 ? o->max_sweeps : 30;
+    // a face of many column blocks: group sums of its Gram partials first
+    const int cgp = pparts > 64 ? 32 : 1;
+    if (cgp > 1)
+        TSVDM_LAUNCH("gram_group_b", (k_gram_group<LP>), dim3(gram_group_blocks<LP>(pparts, cgp), nf), dim3(256), 0,
+                     s, w.gram_p, pparts, cgp, fmap);
     TSVDM_LAUNCH("core_gram_eig", (k_core<LP>), dim3(nf), dim3(QT), 0, s, gp_c, pparts, ell,
                  (const double *)w.fro_part, mparts, (const double *)w.res_part, resid ? pparts : 0,
                  o->rank_mode, o->k, o->tau, msw, kJacobiTolMixed, w.UB, w.sig, w.perm, w.kf, w.fro2,
-                 exact ? (double *)nullptr : cert, w.jinfo, fmap, kcap_face);
+                 exact ? (double *)nullptr : cert, w.jinfo, fmap, kcap_face, cgp);
     TSVDM_LAUNCH("factors", (k_factors<LP>), dim3((unsigned)(mparts + pparts), nf), dim3(GT), 0, s,
                  (const float *)w.Qm, (const float *)w.Z, m, p, ell, kmax, w.UB, w.sig, w.perm, w.kf,
                  w.fro2, w.qr_info, w.jinfo, Uo, So, Vo, ranks, fro, info, fmap);
