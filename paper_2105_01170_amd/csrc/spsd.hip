@@ -49,11 +49,33 @@ __global__ __launch_bounds__(ST) void k_two_sided_fwd(const TX *__restrict__ X, 
     for (int u = 0; u < 4; ++u) acc[u] = f64x4_t{0, 0, 0, 0};
     for (int64_t a0 = 0; a0 < m; a0 += 64) {
         __syncthreads();
-        for (int e = tid; e < 64 * 64; e += ST) {
-            const int aa = e % 64, cc = e / 64;
+        {
+            // element tid + q ST of the chunk: row tid % 64, column tid / 64 + 4 q.
+            // Every load is issued before any is used (the fence keeps the
+            // conversions after them; without it each load waited for the
+            // last); loading the next chunk during the products was slower
+            constexpr int PER = 64 * 64 / ST;
+            TX xr[PER];
+            TU ur[PER];
+            const int aa = tid & 63;
             const bool oka = a0 + aa < m;
-            xs[aa * 65 + cc] = oka && t0 + cc < m ? (double)S[(a0 + aa) + lds * (t0 + cc)] : 0.0;
-            us[aa * 65 + cc] = oka && cc < r ? (double)U[(a0 + aa) + m * cc] : 0.0;
+            const TX *sp = S + (oka ? a0 + aa : 0);
+            const TU *up = U + (oka ? a0 + aa : 0);
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int cc = (tid >> 6) + 4 * q;
+                const bool okx = oka && t0 + cc < m, oku = oka && cc < r;
+                xr[q] = sp[lds * (okx ? t0 + cc : 0)];
+                ur[q] = up[(int64_t)m * (oku ? cc : 0)];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int q = 0; q < PER; ++q) {
+                const int cc = (tid >> 6) + 4 * q;
+                const bool okx = oka && t0 + cc < m, oku = oka && cc < r;
+                xs[aa * 65 + cc] = okx ? (double)xr[q] : 0.0;
+                us[aa * 65 + cc] = oku ? (double)ur[q] : 0.0;
+            }
         }
         __syncthreads();
 #pragma unroll 4
