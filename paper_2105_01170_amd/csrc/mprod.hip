@@ -116,16 +116,36 @@ __global__ __launch_bounds__(256) void k_mprod_faces(const T *__restrict__ U, co
     Acc<T> z[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) z[u] = Acc<T>{T(0), T(0)};
+    // staging: element tid + 256 i of a chunk is row tid % BC, column tid / BC
+    // + 8 i; all of a thread's loads are issued before any is used (the fence
+    // keeps the selects and LDS stores after them)
+    constexpr int PER = BC * 64 / 256;
+    const int sb = tid % BC, sc = tid / BC;
     for (int64_t b0 = 0; b0 < p; b0 += BC) {
         __syncthreads();
-        for (int e = tid; e < BC * 64; e += 256) {
-            const int bb = e % BC, cc = e / BC;
-            const int64_t b = b0 + bb;
-            const bool okv = b < p && cc < kc, okx = b < p && c0 + cc < s;
+        {
+            T vv[PER * E], xv[PER * E];
+            const int64_t b = b0 + sb;
 #pragma unroll
-            for (int q = 0; q < E; ++q) {
-                vs[(bb * 65 + cc) * E + q] = okv ? Vf[E * (b + p * cc) + q] : T(0);
-                xs[(bb * 65 + cc) * E + q] = okx ? Xf[E * (b + p * (c0 + cc)) + q] : T(0);
+            for (int i = 0; i < PER; ++i) {
+                const int cc = sc + 8 * i;
+                const bool okv = b < p && cc < kc, okx = b < p && c0 + cc < s;
+#pragma unroll
+                for (int q = 0; q < E; ++q) {
+                    vv[i * E + q] = Vf[okv ? E * (b + p * cc) + q : 0];
+                    xv[i * E + q] = Xf[okx ? E * (b + p * (c0 + cc)) + q : 0];
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int cc = sc + 8 * i;
+                const bool okv = b < p && cc < kc, okx = b < p && c0 + cc < s;
+#pragma unroll
+                for (int q = 0; q < E; ++q) {
+                    vs[(sb * 65 + cc) * E + q] = okv ? vv[i * E + q] : T(0);
+                    xs[(sb * 65 + cc) * E + q] = okx ? xv[i * E + q] : T(0);
+                }
             }
         }
         __syncthreads();
@@ -155,11 +175,23 @@ __global__ __launch_bounds__(256) void k_mprod_faces(const T *__restrict__ U, co
     }
     for (int64_t a0 = 0; a0 < m; a0 += BC) {
         __syncthreads();
-        for (int e = tid; e < BC * 64; e += 256) {
-            const int aa = e % BC, rr = e / BC;
-            const bool ok = a0 + aa < m && rr < kc;
+        {
+            T uv[PER * E];
 #pragma unroll
-            for (int q = 0; q < E; ++q) vs[(aa * 65 + rr) * E + q] = ok ? Uf[E * (a0 + aa + m * rr) + q] : T(0);
+            for (int i = 0; i < PER; ++i) {
+                const int rr = sc + 8 * i;
+                const bool ok = a0 + sb < m && rr < kc;
+#pragma unroll
+                for (int q = 0; q < E; ++q) uv[i * E + q] = Uf[ok ? E * (a0 + sb + m * rr) + q : 0];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < PER; ++i) {
+                const int rr = sc + 8 * i;
+                const bool ok = a0 + sb < m && rr < kc;
+#pragma unroll
+                for (int q = 0; q < E; ++q) vs[(sb * 65 + rr) * E + q] = ok ? uv[i * E + q] : T(0);
+            }
         }
         __syncthreads();
         // thread: column cl, rows a0 + g + 4 i
