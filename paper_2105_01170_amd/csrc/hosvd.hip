@@ -73,10 +73,22 @@ __global__ __launch_bounds__(GT) void k_mode_gram(const T *__restrict__ X, Unfol
     for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
         const int64_t e = c * CH + el;
         __syncthreads();
+        {
+            // all of the thread's loads issued before any is stored (the fence
+            // keeps the conversions and LDS stores after them)
+            constexpr int PJ = NP * CH / GT;
+            T xv[PJ];
 #pragma unroll
-        for (int j = j0; j < NP; j += GT / CH) {
-            const bool ok = j < N && e < E;
-            xs[j * LDX + el] = ok ? (double)X[v.addr(j, e)] : 0.0;
+            for (int i = 0; i < PJ; ++i) {
+                const int j = j0 + i * (GT / CH);
+                xv[i] = X[j < N && e < E ? v.addr(j, e) : 0];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < PJ; ++i) {
+                const int j = j0 + i * (GT / CH);
+                xs[j * LDX + el] = j < N && e < E ? (double)xv[i] : 0.0;
+            }
         }
         __syncthreads();
         if (own) {
