@@ -1620,21 +1620,29 @@ __device__ __forceinline__ void resid_body(const T *__restrict__ X, int m, int p
     const double *Sf = S + (int64_t)fd * kmax;
     double ua[NS];  // A operands: Uhat[a0 + 16 wave + lane%16][4 s + lane/16]
     {
+        // all loads first, then (after the fence) their conversions
         const int row = a0 + 16 * wave + (lane & 15);
+        T uraw[NS];
 #pragma unroll
         for (int st = 0; st < NS; ++st) {
             const int r = 4 * st + (lane >> 4);
+            const bool ok = row < m && r < kf;
+            int64_t idx;
             if constexpr (CPLX) {  // row 2i + a of X'; column 2r' + b
                 const int rc = r >> 1, a = row & 1;
-                double v = 0.0;
-                if (row < m && r < kf) {
-                    if ((r & 1) == 0) v = (double)Uf[row + (int64_t)m * rc];
-                    else v = a == 0 ? (double)Uf[row + 1 + (int64_t)m * rc] : -(double)Uf[row - 1 + (int64_t)m * rc];
-                }
-                ua[st] = v;
+                idx = (r & 1) == 0 ? row + (int64_t)m * rc : a == 0 ? row + 1 + (int64_t)m * rc : row - 1 + (int64_t)m * rc;
             } else {
-                ua[st] = row < m && r < kf ? (double)Uf[row + (int64_t)m * r] : 0.0;
+                idx = row + (int64_t)m * r;
             }
+            uraw[st] = Uf[ok ? idx : 0];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int st = 0; st < NS; ++st) {
+            const int r = 4 * st + (lane >> 4);
+            const bool ok = row < m && r < kf;
+            const bool neg = CPLX && (r & 1) == 1 && (row & 1) == 1;
+            ua[st] = ok ? (neg ? -(double)uraw[st] : (double)uraw[st]) : 0.0;
         }
     }
     const int xq = tid & 15, xc = tid >> 4, vc = tid & 63, vr0 = tid >> 6;
