@@ -1901,35 +1901,47 @@ __global__ __launch_bounds__(CQT) void k_cholqr_c(const float *__restrict__ Sin,
     const int nch = (rows + CQT - 1) / CQT;
     double2 q[LP];  // the thread's row: input values, then the solved row
     // row `row` of the input panel, or (own) of this kernel's output
+    // Eight columns at a time, their raw values all loaded before any is
+    // converted (the fence keeps the conversions after the loads; converted as
+    // loaded, each load waited for the last).  The input and this kernel's
+    // output share a layout up to the sign of CIN_PC and the second operand
+    // of CIN_COMB (loaded from the input and ignored for the own rows).
+    static_assert((IN == CIN_PC) == (OUT == COUT_PL), "layouts");
     auto load_row = [&](int row, bool own) {
         const int rw = row < rows ? row : rows - 1;
+        const float *base = own ? Q : S;
+        constexpr int CB = 8;
+        static_assert(LP % CB == 0, "column groups");
 #pragma unroll
-        for (int c = 0; c < LP; ++c) {
-            float a, b;
-            if (own) {
-                if constexpr (OUT == COUT_RL) {
-                    const float2 v = *reinterpret_cast<const float2 *>(Q + 2 * (int64_t)rw + R2 * c);
-                    a = v.x;
-                    b = v.y;
+        for (int c0 = 0; c0 < LP; c0 += CB) {
+            float2 u[CB], v[CB];
+#pragma unroll
+            for (int i = 0; i < CB; ++i) {
+                const int c = c0 + i;
+                if constexpr (IN == CIN_PC) {
+                    u[i] = float2{base[rw + (int64_t)rows * c], base[rw + (int64_t)rows * (LP + c)]};
                 } else {
-                    a = Q[rw + (int64_t)rows * c];
-                    b = Q[rw + (int64_t)rows * (LP + c)];
+                    u[i] = *reinterpret_cast<const float2 *>(base + 2 * (int64_t)rw + R2 * c);
+                    if constexpr (IN == CIN_COMB)
+                        v[i] = *reinterpret_cast<const float2 *>(S + 2 * (int64_t)rw + R2 * (LP + c));
                 }
-            } else if constexpr (IN == CIN_IL) {
-                const float2 v = *reinterpret_cast<const float2 *>(S + 2 * (int64_t)rw + R2 * c);
-                a = v.x;
-                b = v.y;
-            } else if constexpr (IN == CIN_COMB) {
-                const float2 u = *reinterpret_cast<const float2 *>(S + 2 * (int64_t)rw + R2 * c);
-                const float2 v = *reinterpret_cast<const float2 *>(S + 2 * (int64_t)rw + R2 * (LP + c));
-                a = u.x - v.y;
-                b = u.y + v.x;
-            } else {
-                a = S[rw + (int64_t)rows * c];
-                b = -S[rw + (int64_t)rows * (LP + c)];
             }
-            const bool ok = row < rows && c < ell;
-            q[c] = double2{ok ? (double)a : 0.0, ok ? (double)b : 0.0};
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int i = 0; i < CB; ++i) {
+                const int c = c0 + i;
+                float a = u[i].x, b = u[i].y;
+                if constexpr (IN == CIN_PC) {
+                    if (!own) b = -b;
+                } else if constexpr (IN == CIN_COMB) {
+                    if (!own) {
+                        a = u[i].x - v[i].y;
+                        b = u[i].y + v[i].x;
+                    }
+                }
+                const bool ok = row < rows && c < ell;
+                q[c] = double2{ok ? (double)a : 0.0, ok ? (double)b : 0.0};
+            }
         }
     };
     // the rows of every thread through LDS into the 2LP x 2LP Gram tiles
