@@ -153,7 +153,7 @@ __global__ __launch_bounds__(RE * RQ) void k_gram_reduce(const double *__restric
     }
 }
 
-constexpr int ET = 512;
+constexpr int ET = 1024;
 // Eigendecomposition of the symmetric N x N matrix G (column major, FP64):
 // lam[j] decreasing, W[:, j] the eigenvectors (largest-magnitude entry
 // positive), and, when Mt is set, Mt = W^T (column major).
